@@ -1,0 +1,203 @@
+"""Textbook solvers on the undecomposed problem, used to pin the oracle.
+
+TEST INFRASTRUCTURE ONLY (imported by the tests, never by the product path).
+
+Nothing here calls the C oracle: these are independent global-array
+formulations written from the textbook definitions, so that a mistake in the
+oracle's decomposition (a dropped term, a wrong sign or index, a transposed
+copy) shows up as a disagreement.
+
+  * the forward differences D of eq. (FFD) and the discrete divergence
+    div = -D^T (Chambolle's convention), which by Prop. equiv is the RT0
+    divergence of Sec. 2.3;
+  * projected FISTA (Beck & Teboulle 2009) on the full dual ROF problem;
+  * the accelerated primal-dual method (Chambolle & Pock 2011, Alg. 2) on the
+    full saddle problem eq. (model_pd);
+  * exact references on tiny images: the dual ROF problem as a box-constrained
+    least-squares problem (solved by BVLS, certified by the KKT conditions), and
+    TV-L1 (with or without inpainting mask) as a linear program.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def fd_grad(u):
+    """Forward differences, eq. (FFD): returns (D1 [(H-1) x W], D2 [H x (W-1)])
+    holding only the differences that are not identically zero."""
+    u = np.asarray(u, dtype=np.float64)
+    return u[1:, :] - u[:-1, :], u[:, 1:] - u[:, :-1]
+
+
+def fd_div(q1, q2, H, W):
+    """div = -D^T for FD-indexed fields q1 [(H-1) x W], q2 [H x (W-1)]."""
+    d = np.zeros((H, W))
+    d[:-1, :] += q1
+    d[1:, :] -= q1
+    d[:, :-1] += q2
+    d[:, 1:] -= q2
+    return d
+
+
+def fd_to_edges(q1, q2, H, W):
+    """FD-indexed field -> global edge arrays g1 [(H+1) x W], g2 [H x (W+1)]
+    (boundary rows / columns are the zero dofs of H_0(div))."""
+    g1 = np.zeros((H + 1, W))
+    g2 = np.zeros((H, W + 1))
+    g1[1:H, :] = q1
+    g2[:, 1:W] = q2
+    return g1, g2
+
+
+def tv_aniso(u):
+    d1, d2 = fd_grad(u)
+    return float(np.abs(d1).sum() + np.abs(d2).sum())
+
+
+def fista_dual_rof(f, alpha, n_iter, q=None):
+    """Projected FISTA on min_{|q|<=1} (1/(2 alpha))|div q + alpha f|^2 with step
+    1/L, L = 8/alpha, starting from q (default 0).  Returns (q1, q2, u) with
+    u = f + div q / alpha."""
+    f = np.asarray(f, dtype=np.float64)
+    H, W = f.shape
+    L = 8.0 / alpha
+    if q is None:
+        x1, x2 = np.zeros((H - 1, W)), np.zeros((H, W - 1))
+    else:
+        x1, x2 = (np.array(a, dtype=np.float64) for a in q)
+    y1, y2 = x1.copy(), x2.copy()
+    t = 1.0
+    for _ in range(n_iter):
+        v = f + fd_div(y1, y2, H, W) / alpha
+        d1, d2 = fd_grad(v)          # the gradient of the dual energy is -D v
+        z1 = np.clip(y1 - (-d1) / L, -1.0, 1.0)
+        z2 = np.clip(y2 - (-d2) / L, -1.0, 1.0)
+        tn = 0.5 * (1.0 + np.sqrt(1.0 + 4.0 * t * t))
+        b = (t - 1.0) / tn
+        y1, y2 = z1 + b * (z1 - x1), z2 + b * (z2 - x2)
+        x1, x2 = z1, z2
+        t = tn
+    return x1, x2, f + fd_div(x1, x2, H, W) / alpha
+
+
+def _prox(fidelity, z, f, m, a):
+    if fidelity == "L2":
+        out = (z + a * f) / (1.0 + a)
+    else:
+        d = z - f
+        out = f + np.sign(d) * np.maximum(np.abs(d) - a, 0.0)
+    return np.where(m, out, z)
+
+
+def cp2_full(f, alpha, n_iter, tau0, sigma0, gamma, fidelity="L2", mask=None, q=None, u=None):
+    """Chambolle-Pock Alg. 2 on min_q max_u <div q, u> + chi_C(q) - alpha F(u)
+    (the saddle form of Sec. 5 without the proximal term): u is the ascent
+    variable, q the accelerated one."""
+    f = np.asarray(f, dtype=np.float64)
+    H, W = f.shape
+    m = np.ones((H, W), bool) if mask is None else np.asarray(mask).astype(bool)
+    if q is None:
+        x1, x2 = np.zeros((H - 1, W)), np.zeros((H, W - 1))
+    else:
+        x1, x2 = (np.array(a, dtype=np.float64) for a in q)
+    y = f.copy() if u is None else np.array(u, dtype=np.float64)
+    xb1, xb2 = x1.copy(), x2.copy()
+    tk, sk = tau0, sigma0
+    for _ in range(n_iter):
+        y = _prox(fidelity, y + sk * fd_div(xb1, xb2, H, W), f, m, sk * alpha)
+        d1, d2 = fd_grad(y)          # div^* y = -D y
+        z1 = np.clip(x1 - tk * (-d1), -1.0, 1.0)
+        z2 = np.clip(x2 - tk * (-d2), -1.0, 1.0)
+        th = 1.0 / np.sqrt(1.0 + 2.0 * gamma * tk)
+        tk, sk = th * tk, sk / th
+        xb1, xb2 = z1 + th * (z1 - x1), z2 + th * (z2 - x2)
+        x1, x2 = z1, z2
+    return x1, x2, y
+
+
+def _div_matrix(H, W):
+    """Dense matrix of div acting on the stacked FD-indexed dual dofs."""
+    n1, n2 = (H - 1) * W, H * (W - 1)
+    A = np.zeros((H * W, n1 + n2))
+    for k in range(n1 + n2):
+        e = np.zeros(n1 + n2)
+        e[k] = 1.0
+        A[:, k] = fd_div(e[:n1].reshape(H - 1, W), e[n1:].reshape(H, W - 1), H, W).ravel()
+    return A
+
+
+def rof_exact(f, alpha):
+    """Exact ROF solution on a tiny image: the dual min_{|q|<=1} |A q + alpha f|^2
+    (A = div) solved by bounded-variable least squares, u = f + A q / alpha.
+    Returns (u, kkt_residual); the residual certifies the optimality of u:
+    alpha (u - f) = div q with q in [-1, 1] and q_e = sign((Du)_e) where
+    (Du)_e != 0 (the sign of the saddle form eq. (model_pd), whose optimality
+    conditions are eq. (pd_relation))."""
+    from scipy.optimize import lsq_linear
+
+    f = np.asarray(f, dtype=np.float64)
+    H, W = f.shape
+    A = _div_matrix(H, W)
+    res = lsq_linear(A, -alpha * f.ravel(), bounds=(-1.0, 1.0), method="bvls", tol=1e-15,
+                     lsmr_tol=None, max_iter=10000)
+    q = res.x
+    u = f + (A @ q).reshape(H, W) / alpha
+    d = np.concatenate([a.ravel() for a in fd_grad(u)])
+    big = np.abs(d) > 1e-9
+    kkt = max(float(np.abs(alpha * (u - f) - (A @ q).reshape(H, W)).max()),
+              float(np.abs(q[big] - np.sign(d[big])).max()) if big.any() else 0.0,
+              float(max(np.abs(q).max() - 1.0, 0.0)))
+    return u, kkt
+
+
+def tvl1_exact_energy(f, alpha, mask=None):
+    """Exact minimum of alpha sum_m |u - f| + TV(u) (TV-L1, optionally with an
+    inpainting mask, Sec. 3) on a tiny image, as a linear program over
+    (u, s, t) with |u - f| <= s on observed pixels and |Du| <= t."""
+    from scipy.optimize import linprog
+
+    f = np.asarray(f, dtype=np.float64)
+    H, W = f.shape
+    n = H * W
+    m = np.ones(n, bool) if mask is None else np.asarray(mask).astype(bool).ravel()
+    # difference matrix rows
+    rows = []
+    for i in range(H - 1):
+        for j in range(W):
+            r = np.zeros(n); r[(i + 1) * W + j] = 1; r[i * W + j] = -1; rows.append(r)
+    for i in range(H):
+        for j in range(W - 1):
+            r = np.zeros(n); r[i * W + j + 1] = 1; r[i * W + j] = -1; rows.append(r)
+    Dm = np.array(rows).reshape(-1, n)
+    ne = Dm.shape[0]
+    # variables: u (n), s (n), t (ne)
+    c = np.concatenate([np.zeros(n), alpha * m.astype(float), np.ones(ne)])
+    I = np.eye(n)
+    A_ub = np.block([
+        [I, -I, np.zeros((n, ne))],
+        [-I, -I, np.zeros((n, ne))],
+        [Dm, np.zeros((ne, n)), -np.eye(ne)],
+        [-Dm, np.zeros((ne, n)), -np.eye(ne)],
+    ])
+    fv = f.ravel()
+    b_ub = np.concatenate([fv, -fv, np.zeros(ne), np.zeros(ne)])
+    bounds = [(None, None)] * n + [(0, None)] * (n + ne)
+    res = linprog(c, A_ub=A_ub, b_ub=b_ub, bounds=bounds, method="highs-ds",
+                  options={"primal_feasibility_tolerance": 1e-10, "dual_feasibility_tolerance": 1e-10})
+    if res.status != 0:
+        raise RuntimeError(res.message)
+    u = res.x[:n].reshape(H, W)
+    return float(res.fun), u
+
+
+def div_norm_sq(apply_div, apply_divT, n_in, iters=2000, seed=0):
+    """Largest eigenvalue of div^* div by power iteration."""
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal(n_in)
+    x /= np.linalg.norm(x)
+    lam = 0.0
+    for _ in range(iters):
+        y = apply_divT(apply_div(x))
+        lam = float(np.linalg.norm(y))
+        x = y / lam
+    return lam
