@@ -1,0 +1,192 @@
+/*
+ * dtvdd.h -- C-ABI of libdtvdd.so, the MI355X (gfx950) solver for the
+ * primal-dual nonoverlapping domain decomposition of dual total-variation
+ * problems (C.-O. Lee and J. Park, arXiv 1901.00682).
+ *
+ * The problem (Sec. 3, eq. model): min_u  alpha F(u) + TV(u) on an H x W image,
+ * TV the anisotropic discrete total variation of the lowest-order
+ * Raviart-Thomas dual (Sec. 2.3, eq. dTV), F one of
+ *     L2:  F(u) = 1/2 sum_m (u - f)^2     (ROF denoising / L2 inpainting)
+ *     L1:  F(u) = sum_m |u - f|           (TV-L1 denoising / L1 inpainting)
+ * where the optional mask m (1 = observed pixel, 0 = pixel of the inpainting
+ * set D) removes pixels from the fidelity term (Sec. 3, inpainting models).
+ *
+ * The method is Algorithm 1 (Sec. 4): the dual problem is torn along the
+ * interfaces of an ny x nx grid of rectangular subdomains (Sec. 2.4), the
+ * continuity of the normal flux is enforced with Lagrange multipliers lambda
+ * (eq. DD), and the saddle problem is solved by an outer Chambolle-Pock
+ * iteration whose primal step is a set of independent local problems, one
+ * per subdomain (eq. DD_local), each solved approximately by n_inner steps of
+ *     FISTA on the local dual (ROF without mask), or
+ *     the accelerated primal-dual method of Chambolle-Pock (Sec. 5, any F).
+ *
+ * Data (all device buffers are owned by the caller; the library never
+ * allocates or frees them):
+ *   f, u, mask:  H x W row-major per image, images concatenated (px_off).
+ *   p1, p2:      the torn dual variable p~ in the "torn layout":
+ *       P1 has H+ny rows of p1_pitch floats (W used).  Subdomain row r,
+ *          covering pixel rows [a, b), stores its horizontal edges
+ *          (edge above pixel row a .. edge below pixel row b-1) in P1 rows
+ *          a+r .. b+r.  Entry = normal flux in the +row direction.
+ *       P2 has H rows of p2_pitch floats (W+nx used).  Subdomain column c,
+ *          covering pixel columns [a, b), stores its vertical edges in P2
+ *          columns a+c .. b+c.  Entry = normal flux in the +column direction.
+ *       Interface edges thus appear twice (one copy per side); edges on the
+ *       image boundary (P1 rows 0 and H+ny-1, P2 columns 0 and W+nx-1) are
+ *       not unknowns (H_0(div)) and hold 0.
+ *   lambda:      per image 3*n_lam floats: the multipliers lambda
+ *       [n_lam_h horizontal-interface dofs, (r-1)*W + j for the interface
+ *        between subdomain rows r-1 and r;  then n_lam_v vertical, (c-1)*H + i],
+ *       then the side-s copies and the side-t copies of p~ at the previous
+ *       outer step (same ordering), which Algorithm 1 needs for its
+ *       extrapolation 2 p~^n - p~^(n-1).  Side s is the upper / left
+ *       subdomain (lower row-major index); (B p~)_e = p~_s,e - p~_t,e.
+ *
+ * Error convention: every call returns DTV_OK (0) or a negative code; the
+ * message of the last failing call on the calling thread is returned by
+ * dtv_last_error().  Arguments are validated before anything is enqueued,
+ * so a failing call leaves every output untouched.  Calls are stream-ordered
+ * on the given stream (a hipStream_t, NULL = default stream); the host only
+ * waits when diagnostics are requested (h_stats, gap_tol).  A plan is not
+ * thread-safe; distinct plans are independent.
+ */
+#ifndef DTVDD_H
+#define DTVDD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define DTV_OK 0
+#define DTV_EINVAL (-1)      /* bad shape, cuts, alpha, step sizes, null pointer, unsupported combination */
+#define DTV_ENOWS (-2)       /* no workspace bound, or the bound one is too small */
+#define DTV_EHIP (-3)        /* a HIP runtime call failed (its message is in dtv_last_error) */
+#define DTV_ESTATE (-4)      /* backward without a forward that saved its checkpoints */
+#define DTV_ENONFINITE (-5)  /* the FP64 diagnostics saw NaN or Inf (outputs are still written) */
+
+/* fidelity (Sec. 3) */
+#define DTV_L2 0
+#define DTV_L1 1
+
+/* local solver */
+#define DTV_INNER_FISTA 0    /* projected FISTA on the local dual; L2 without mask only */
+#define DTV_INNER_CP2 1      /* accelerated primal-dual (Sec. 5); any fidelity, mask allowed */
+
+/* kernel schedule of the local solves (numerically identical results) */
+#define DTV_SCHED_AUTO 0     /* pick by measurement (autotuner), cached per shape */
+#define DTV_SCHED_STREAM 1   /* one launch per inner step over all subdomains */
+#define DTV_SCHED_FUSED 2    /* one workgroup per subdomain runs all inner steps on chip
+                                (FISTA, subdomains up to 128 x 128) */
+
+typedef struct dtv_dd_plan dtv_dd_plan; /* opaque, owned by the library */
+
+/* One image and its subdomain grid (Sec. 2.4; cuts need not be equal, any
+   strictly increasing cut vector is accepted). */
+typedef struct {
+    int32_t H, W;              /* rows, columns; >= 1 */
+    int32_t ny, nx;            /* subdomain rows / columns; 1 <= ny <= H, 1 <= nx <= W */
+    const int32_t *row_cuts;   /* host array of ny+1 strictly increasing values, [0] = 0,
+                                  [ny] = H; NULL: floor(k H / ny) */
+    const int32_t *col_cuts;   /* host array of nx+1 values likewise; NULL: floor(k W / nx) */
+    double alpha;              /* fidelity weight, > 0 (eq. model) */
+} dtv_image_desc;
+
+/* Solver settings.  Outer step sizes of Algorithm 1 and the local-solver
+   parameters of Sec. 5 (defaults used by the paper: tau = 50, tau sigma = 1/2,
+   tau0 = 10, tau0 sigma0 = 1/8, gamma = 1/(8 tau)). */
+typedef struct {
+    int32_t fidelity;          /* DTV_L2 or DTV_L1 */
+    int32_t inner;             /* DTV_INNER_FISTA or DTV_INNER_CP2 */
+    int32_t has_mask;          /* 1: d_mask is given */
+    double tau, sigma;         /* > 0, tau * sigma <= 1/2 (|B|^2 = 2, Prop. B_norm) */
+    double tau0, sigma0;       /* CP2: > 0, 8 tau0 sigma0 <= 1 (|div_s|^2 <= 8) */
+    double gamma;              /* CP2: 0 <= gamma <= 1/tau (G_s^* is 1/tau-uniformly convex) */
+    int32_t n_outer, n_inner;  /* iteration counts; n_outer >= 0, n_inner >= 1 */
+    int32_t diag_every;        /* 0: none; k > 0: FP64 diagnostics every k outer steps and after the last */
+    double gap_tol;            /* > 0 (single L2 image without mask, diag_every > 0): stop at the
+                                  first diagnostic step with gap <= gap_tol * |J| */
+    int32_t warm_start;        /* 0: start from p~ = 0, lambda = 0, u = f; 1: continue from the
+                                  state held in d_p1, d_p2, d_lambda (and d_u for CP2) */
+    int32_t save_for_backward; /* 1: keep outer-step checkpoints for dtv_dd_backward (FISTA only) */
+    int32_t ckpt_every;        /* outer steps between checkpoints, >= 1 */
+    int32_t schedule;          /* DTV_SCHED_* */
+    int32_t time_kernels;      /* 1: time every launch of the inner-step kernel with HIP events
+                                  (read back with dtv_dd_kernel_time) */
+} dtv_dd_params;
+
+/* Where image `image` lives in the concatenated buffers (element offsets). */
+typedef struct {
+    int64_t px_off;            /* f, u, mask, grad_f, grad_u: H*W block at this offset */
+    int64_t p1_off;            /* P1 block at this offset in d_p1 */
+    int64_t p2_off;            /* P2 block at this offset in d_p2 */
+    int64_t lam_off;           /* 3*n_lam lambda-state block at this offset in d_lambda */
+    int32_t H, W, ny, nx;
+    int32_t p1_rows, p1_pitch; /* H+ny rows, row pitch in floats (>= W) */
+    int32_t p2_cols, p2_pitch; /* W+nx used columns, row pitch in floats */
+    int32_t n_lam_h, n_lam_v;  /* (ny-1)*W and (nx-1)*H */
+} dtv_layout;
+
+/* Validate the problem and build a plan.  imgs: n_images >= 1 descriptors.
+   Batched solves (n_images > 1) require inner = FISTA and no mask. */
+int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const dtv_dd_params *prm, dtv_dd_plan **out);
+
+/* Layout of one image (image in [0, n_images)); image = -1 reports totals:
+   px_off = total pixels, p1_off / p2_off = floats of d_p1 / d_p2,
+   lam_off = floats of d_lambda. */
+int dtv_dd_layout(const dtv_dd_plan *plan, int32_t image, dtv_layout *out);
+
+/* Device workspace the solver needs (bytes), and binding of a caller-owned
+   allocation of at least that size (256-byte aligned).  Binding uploads the
+   plan's metadata with a synchronous copy. */
+int dtv_dd_workspace_bytes(const dtv_dd_plan *plan, size_t *bytes);
+int dtv_dd_bind_workspace(dtv_dd_plan *plan, void *d_ws, size_t bytes);
+
+/* Run n_outer steps of Algorithm 1 (Sec. 4):
+     lambda <- lambda + sigma B(2 p~^n - p~^(n-1));  phat = p~^n - tau B^* lambda;
+     every subdomain: n_inner local steps on eq. (DD_local), warm-started;
+     u assembled from the local primal variables (for FISTA u = f + div p~ / alpha).
+   d_f: input image(s); d_mask: NULL unless has_mask; d_u, d_p1, d_p2,
+   d_lambda: outputs (and inputs when warm_start = 1).
+   h_stats: NULL, or host room for n_images * (n_outer / diag_every + 1) rows of
+   5 doubles [outer step, J(u), D(p_avg), gap = J - D, |B p~|_2], image-major;
+   *n_rows (may be NULL) receives the number of rows per image.  D and gap are
+   NaN unless the fidelity is L2 without mask.  Returns DTV_ENONFINITE if a
+   diagnostic is not finite. */
+int dtv_dd_solve(dtv_dd_plan *plan, const float *d_f, const uint8_t *d_mask, float *d_u, float *d_p1,
+                 float *d_p2, float *d_lambda, double *h_stats, int32_t *n_rows, void *stream);
+
+/* FP64 diagnostics of a given state (same quantities as a row of h_stats,
+   without the step count): h_out receives 4 doubles per image. */
+int dtv_dd_diagnostics(dtv_dd_plan *plan, const float *d_f, const uint8_t *d_mask, const float *d_u,
+                       const float *d_p1, const float *d_p2, double *h_out, void *stream);
+
+/* Reverse mode of the unrolled solve (FISTA, save_for_backward = 1): given
+   dl/du, writes dl/df (H*W per image) and dl/dalpha (one float per image).
+   The last dtv_dd_solve of this plan must have saved its checkpoints; d_f
+   must hold the same data as in that solve. */
+int dtv_dd_backward(dtv_dd_plan *plan, const float *d_f, const float *d_grad_u, float *d_grad_f,
+                    float *d_grad_alpha, void *stream);
+
+/* Average duration (ms) of the inner-step kernel launches timed in the last
+   solve with time_kernels = 1, their count, the kernel's name and its
+   algorithmic HBM bytes per launch (the bytes model of the chosen schedule). */
+int dtv_dd_kernel_time(const dtv_dd_plan *plan, double *avg_ms, int64_t *launches, const char **name,
+                       double *bytes_per_launch);
+
+/* The schedule the plan will use (DTV_SCHED_STREAM or DTV_SCHED_FUSED). */
+int dtv_dd_schedule(const dtv_dd_plan *plan, int32_t *schedule);
+
+void dtv_dd_destroy(dtv_dd_plan *plan);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *dtv_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DTVDD_H */

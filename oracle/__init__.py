@@ -91,6 +91,7 @@ def load(path: str = LIB_PATH):
     lib.orc_prox.argtypes = [ctypes.c_int, ctypes.c_long, _D, _D, _U8, ctypes.c_double, _D]
     lib.orc_n_done.restype = ctypes.c_int
     lib.orc_n_done.argtypes = [vp]
+    lib.orc_threads.restype = ctypes.c_int
     if hasattr(lib, "orc_backward"):
         lib.orc_backward.restype = ctypes.c_int
         lib.orc_backward.argtypes = [vp, ctypes.c_int, _D, _D, _U8, _D, _D, _D]
@@ -274,6 +275,11 @@ def prox(fidelity: str, z, f, a: float, mask=None):
     load().orc_prox(FIDELITY[fidelity], z.size, _dp(z), _dp(f), None if m is None else m.ctypes.data_as(_U8),
                     float(a), _dp(out))
     return out
+
+
+def threads() -> int:
+    """Threads used by the oracle's parallel loop over subdomains."""
+    return int(load().orc_threads())
 
 
 def tv(u) -> float:

@@ -788,3 +788,16 @@ void orc_prox(int fidelity, long n, const double *z, const double *f, const unsi
 }
 
 int orc_n_done(const orc_state *st) { return st->n_done; }
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+/* number of threads the parallel loops of the oracle use */
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

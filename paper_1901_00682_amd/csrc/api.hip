@@ -1,0 +1,566 @@
+// Host runtime and C-ABI of libdtvdd.so: plan building and validation, the
+// torn HBM layout, workspace binding, and the outer loop of Algorithm 1
+// (Lee & Park, arXiv 1901.00682, Sec. 4) driving the HIP kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "dtvdd.h"
+#include "dtvdd_internal.h"
+
+using namespace dtv;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return DTV_EHIP;
+}
+
+#define HIP_TRY(call, what)                        \
+    do {                                           \
+        hipError_t e_ = (call);                    \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+int pitch_of(int n) { return (int)align_up((size_t)n, 64); }
+
+struct ImgHost {
+    int H, W, ny, nx;
+    double alpha;
+    std::vector<int> rcut, ccut;
+    dtv_layout L;
+};
+
+}  // namespace
+
+struct dtv_dd_plan {
+    dtv_dd_params prm;
+    std::vector<ImgHost> imgs;
+    int n = 0;
+    int maxH = 0, maxW = 0, max_nlam = 0;
+    int64_t tot_px = 0, tot_p1 = 0, tot_p2 = 0, tot_lam = 0;
+    int schedule = DTV_SCHED_STREAM;
+    int rows = 16;  // rows per wave strip of the streaming kernels
+
+    // metadata uploaded to the workspace at bind time
+    std::vector<ImgDev> h_imgs;
+    std::vector<int> h_info;
+    std::vector<StreamTile> h_tiles;
+    std::vector<SubTile> h_subs;
+
+    // workspace layout (byte offsets)
+    size_t off_imgs = 0, off_info = 0, off_tiles = 0, off_subs = 0, off_buf[3] = {0, 0, 0}, off_u2 = 0,
+           off_part = 0, off_dout = 0, ws_bytes = 0;
+    int diag_nblk = 0;
+    char *ws = nullptr;
+    double *h_diag = nullptr;  // pinned host mirror of the diagnostics sums
+
+    // timing of the inner-step kernel
+    std::vector<hipEvent_t> events;
+    double t_ms = 0.0;
+    int64_t t_count = 0;
+
+    ~dtv_dd_plan()
+    {
+        for (hipEvent_t e : events) (void)hipEventDestroy(e);
+        if (h_diag) (void)hipHostFree(h_diag);
+    }
+
+    const ImgDev *d_imgs() const { return (const ImgDev *)(ws + off_imgs); }
+    const int *d_info() const { return (const int *)(ws + off_info); }
+    const StreamTile *d_tiles() const { return (const StreamTile *)(ws + off_tiles); }
+    float *buf1(int k) const { return (float *)(ws + off_buf[k]); }
+    float *buf2(int k) const { return (float *)(ws + off_buf[k]) + tot_p1; }
+    float *u2() const { return (float *)(ws + off_u2); }
+    double *partials() const { return (double *)(ws + off_part); }
+    double *dout() const { return (double *)(ws + off_dout); }
+};
+
+// ---------------------------------------------------------------------------
+// validation and plan building
+
+static int check_cuts(const int32_t *given, int parts, int n, std::vector<int> &out, const char *what)
+{
+    out.resize(parts + 1);
+    if (!given) {
+        for (int k = 0; k <= parts; ++k) out[k] = (int)(((int64_t)k * n) / parts);
+    } else {
+        for (int k = 0; k <= parts; ++k) out[k] = given[k];
+    }
+    if (out[0] != 0 || out[parts] != n) return fail(DTV_EINVAL, std::string(what) + " cuts must start at 0 and end at the size");
+    for (int k = 0; k < parts; ++k)
+        if (out[k + 1] <= out[k]) return fail(DTV_EINVAL, std::string(what) + " cuts must be strictly increasing");
+    return DTV_OK;
+}
+
+static bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const dtv_dd_params *prm,
+                            dtv_dd_plan **out)
+{
+    if (!imgs || !prm || !out) return fail(DTV_EINVAL, "null argument");
+    if (n_images < 1) return fail(DTV_EINVAL, "n_images must be >= 1");
+    const dtv_dd_params &p = *prm;
+    if (p.fidelity != DTV_L2 && p.fidelity != DTV_L1) return fail(DTV_EINVAL, "fidelity must be DTV_L2 or DTV_L1");
+    if (p.inner != DTV_INNER_FISTA && p.inner != DTV_INNER_CP2) return fail(DTV_EINVAL, "unknown inner solver");
+    if (p.inner == DTV_INNER_FISTA && (p.fidelity != DTV_L2 || p.has_mask))
+        return fail(DTV_EINVAL, "FISTA local solver needs the L2 fidelity without mask (use CP2)");
+    if (!finite_pos(p.tau) || !finite_pos(p.sigma)) return fail(DTV_EINVAL, "tau and sigma must be positive");
+    if (p.tau * p.sigma > 0.5 * (1.0 + 1e-12)) return fail(DTV_EINVAL, "tau * sigma must be <= 1/2");
+    if (p.inner == DTV_INNER_CP2) {
+        if (!finite_pos(p.tau0) || !finite_pos(p.sigma0)) return fail(DTV_EINVAL, "tau0 and sigma0 must be positive");
+        if (8.0 * p.tau0 * p.sigma0 > 1.0 + 1e-12) return fail(DTV_EINVAL, "8 tau0 sigma0 must be <= 1");
+        if (!(p.gamma >= 0.0) || p.gamma > 1.0 / p.tau * (1.0 + 1e-12))
+            return fail(DTV_EINVAL, "gamma must lie in [0, 1/tau]");
+    }
+    if (p.n_outer < 0 || p.n_inner < 1) return fail(DTV_EINVAL, "n_outer must be >= 0 and n_inner >= 1");
+    if (p.diag_every < 0) return fail(DTV_EINVAL, "diag_every must be >= 0");
+    if (p.gap_tol < 0.0 || !std::isfinite(p.gap_tol)) return fail(DTV_EINVAL, "gap_tol must be finite and >= 0");
+    if (p.gap_tol > 0.0 && (n_images != 1 || p.fidelity != DTV_L2 || p.has_mask || p.diag_every <= 0))
+        return fail(DTV_EINVAL, "gap_tol needs one L2 image without mask and diag_every > 0");
+    if (p.save_for_backward && (p.inner != DTV_INNER_FISTA || p.ckpt_every < 1))
+        return fail(DTV_EINVAL, "save_for_backward needs FISTA and ckpt_every >= 1");
+    if (p.schedule < DTV_SCHED_AUTO || p.schedule > DTV_SCHED_FUSED) return fail(DTV_EINVAL, "unknown schedule");
+    if (p.schedule == DTV_SCHED_FUSED) return fail(DTV_EINVAL, "the fused schedule is not available in this build");
+
+    dtv_dd_plan *pl = new dtv_dd_plan();
+    pl->prm = p;
+    pl->n = n_images;
+    pl->imgs.resize(n_images);
+    int64_t px = 0, o1 = 0, o2 = 0, ol = 0;
+    for (int b = 0; b < n_images; ++b) {
+        const dtv_image_desc &d = imgs[b];
+        ImgHost &h = pl->imgs[b];
+        if (d.H < 1 || d.W < 1) { delete pl; return fail(DTV_EINVAL, "image sizes must be >= 1"); }
+        if (d.ny < 1 || d.ny > d.H || d.nx < 1 || d.nx > d.W) {
+            delete pl;
+            return fail(DTV_EINVAL, "subdomain grid must satisfy 1 <= ny <= H and 1 <= nx <= W");
+        }
+        if (!finite_pos(d.alpha)) { delete pl; return fail(DTV_EINVAL, "alpha must be positive"); }
+        if ((int64_t)(d.H + d.ny) * pitch_of(d.W) >= (1LL << 40)) { delete pl; return fail(DTV_EINVAL, "image too large"); }
+        int rc = check_cuts(d.row_cuts, d.ny, d.H, h.rcut, "row");
+        if (rc == DTV_OK) rc = check_cuts(d.col_cuts, d.nx, d.W, h.ccut, "column");
+        if (rc != DTV_OK) { delete pl; return rc; }
+        h.H = d.H; h.W = d.W; h.ny = d.ny; h.nx = d.nx; h.alpha = d.alpha;
+        dtv_layout &L = h.L;
+        L.H = d.H; L.W = d.W; L.ny = d.ny; L.nx = d.nx;
+        L.p1_rows = d.H + d.ny;
+        L.p1_pitch = pitch_of(d.W);
+        L.p2_cols = d.W + d.nx;
+        L.p2_pitch = pitch_of(d.W + d.nx);
+        L.n_lam_h = (d.ny - 1) * d.W;
+        L.n_lam_v = (d.nx - 1) * d.H;
+        L.px_off = px;
+        L.p1_off = o1;
+        L.p2_off = o2;
+        L.lam_off = ol;
+        px += (int64_t)d.H * d.W;
+        o1 += align_up((size_t)L.p1_rows * L.p1_pitch, 64);
+        o2 += align_up((size_t)d.H * L.p2_pitch, 64);
+        ol += align_up((size_t)3 * (L.n_lam_h + L.n_lam_v), 64);
+        pl->maxH = std::max(pl->maxH, d.H);
+        pl->maxW = std::max(pl->maxW, d.W);
+        pl->max_nlam = std::max(pl->max_nlam, L.n_lam_h + L.n_lam_v);
+    }
+    pl->tot_px = px;
+    pl->tot_p1 = o1;
+    pl->tot_p2 = o2;
+    pl->tot_lam = ol;
+
+    // device metadata: image descriptors, info words, cuts, work lists
+    const double tau = p.tau;
+    for (int b = 0; b < n_images; ++b) {
+        const ImgHost &h = pl->imgs[b];
+        ImgDev g{};
+        g.H = h.H; g.W = h.W; g.ny = h.ny; g.nx = h.nx;
+        g.px = h.L.px_off; g.p1 = h.L.p1_off; g.p2 = h.L.p2_off;
+        g.pitch1 = h.L.p1_pitch; g.pitch2 = h.L.p2_pitch;
+        g.lam = h.L.lam_off;
+        g.nlh = h.L.n_lam_h; g.nlam = h.L.n_lam_h + h.L.n_lam_v;
+        g.rinfo = (long long)pl->h_info.size();
+        for (int r = 0; r < h.ny; ++r)
+            for (int i = h.rcut[r]; i < h.rcut[r + 1]; ++i)
+                pl->h_info.push_back((r << 2) | (i == h.rcut[r] ? 1 : 0) | (i == h.rcut[r + 1] - 1 ? 2 : 0));
+        g.cinfo = (long long)pl->h_info.size();
+        for (int c = 0; c < h.nx; ++c)
+            for (int j = h.ccut[c]; j < h.ccut[c + 1]; ++j)
+                pl->h_info.push_back((c << 2) | (j == h.ccut[c] ? 1 : 0) | (j == h.ccut[c + 1] - 1 ? 2 : 0));
+        g.rcut = (long long)pl->h_info.size();
+        for (int v : h.rcut) pl->h_info.push_back(v);
+        g.ccut = (long long)pl->h_info.size();
+        for (int v : h.ccut) pl->h_info.push_back(v);
+        const double L = 8.0 / h.alpha + 1.0 / tau;
+        g.alpha = (float)h.alpha;
+        g.inv_alpha = (float)(1.0 / h.alpha);
+        g.invL = (float)(1.0 / L);
+        g.a_keep = (float)(1.0 - 1.0 / (L * tau));
+        pl->h_imgs.push_back(g);
+        for (int i0 = 0; i0 < h.H; i0 += pl->rows)
+            for (int j0 = 0; j0 < h.W; j0 += kStreamCols) pl->h_tiles.push_back(StreamTile{b, i0, j0, 0});
+    }
+
+    // workspace layout
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + std::max<size_t>(bytes, 1), 256);
+        return o;
+    };
+    pl->off_imgs = take(sizeof(ImgDev) * pl->h_imgs.size());
+    pl->off_info = take(sizeof(int) * pl->h_info.size());
+    pl->off_tiles = take(sizeof(StreamTile) * pl->h_tiles.size());
+    for (int k = 0; k < 3; ++k) pl->off_buf[k] = take(sizeof(float) * (size_t)(pl->tot_p1 + pl->tot_p2));
+    pl->off_u2 = take(p.inner == DTV_INNER_CP2 ? sizeof(float) * (size_t)pl->tot_px : 0);
+    pl->diag_nblk = diag_blocks_per_image(pl->maxH, pl->maxW);
+    pl->off_part = take(sizeof(double) * 6 * (size_t)pl->diag_nblk * n_images);
+    pl->off_dout = take(sizeof(double) * 6 * (size_t)n_images);
+    pl->ws_bytes = off;
+    pl->schedule = DTV_SCHED_STREAM;
+    *out = pl;
+    g_err.clear();
+    return DTV_OK;
+}
+
+extern "C" int dtv_dd_layout(const dtv_dd_plan *pl, int32_t image, dtv_layout *out)
+{
+    if (!pl || !out) return fail(DTV_EINVAL, "null argument");
+    if (image == -1) {
+        dtv_layout L{};
+        L.px_off = pl->tot_px;
+        L.p1_off = pl->tot_p1;
+        L.p2_off = pl->tot_p2;
+        L.lam_off = pl->tot_lam;
+        *out = L;
+        return DTV_OK;
+    }
+    if (image < 0 || image >= pl->n) return fail(DTV_EINVAL, "image index out of range");
+    *out = pl->imgs[image].L;
+    return DTV_OK;
+}
+
+extern "C" int dtv_dd_workspace_bytes(const dtv_dd_plan *pl, size_t *bytes)
+{
+    if (!pl || !bytes) return fail(DTV_EINVAL, "null argument");
+    *bytes = pl->ws_bytes;
+    return DTV_OK;
+}
+
+extern "C" int dtv_dd_bind_workspace(dtv_dd_plan *pl, void *d_ws, size_t bytes)
+{
+    if (!pl || !d_ws) return fail(DTV_EINVAL, "null argument");
+    if (bytes < pl->ws_bytes) return fail(DTV_ENOWS, "workspace too small");
+    if (((uintptr_t)d_ws & 255) != 0) return fail(DTV_EINVAL, "workspace must be 256-byte aligned");
+    char *ws = (char *)d_ws;
+    HIP_TRY(hipMemcpy(ws + pl->off_imgs, pl->h_imgs.data(), sizeof(ImgDev) * pl->h_imgs.size(), hipMemcpyHostToDevice),
+            "upload image descriptors");
+    HIP_TRY(hipMemcpy(ws + pl->off_info, pl->h_info.data(), sizeof(int) * pl->h_info.size(), hipMemcpyHostToDevice),
+            "upload info words");
+    HIP_TRY(hipMemcpy(ws + pl->off_tiles, pl->h_tiles.data(), sizeof(StreamTile) * pl->h_tiles.size(),
+                      hipMemcpyHostToDevice),
+            "upload work list");
+    // rotation buffers start at zero so that their boundary (non-dof) edges are 0
+    for (int k = 0; k < 3; ++k)
+        HIP_TRY(hipMemset(ws + pl->off_buf[k], 0, sizeof(float) * (size_t)(pl->tot_p1 + pl->tot_p2)), "clear buffers");
+    if (!pl->h_diag) HIP_TRY(hipHostMalloc((void **)&pl->h_diag, sizeof(double) * 6 * pl->n), "pinned diag buffer");
+    pl->ws = ws;
+    return DTV_OK;
+}
+
+extern "C" int dtv_dd_schedule(const dtv_dd_plan *pl, int32_t *schedule)
+{
+    if (!pl || !schedule) return fail(DTV_EINVAL, "null argument");
+    *schedule = pl->schedule;
+    return DTV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// diagnostics
+
+static int run_diag(dtv_dd_plan *pl, const float *f, const uint8_t *mask, const float *u, const float *p1,
+                    const float *p2, hipStream_t s, double *rows /* n x 4 */, bool *nonfinite)
+{
+    HIP_TRY(launch_diag(pl->d_imgs(), pl->n, pl->maxH, pl->maxW, pl->d_info(), p1, p2, f, u, mask,
+                        pl->prm.fidelity, pl->partials(), pl->diag_nblk, pl->dout(), s),
+            "diagnostics kernels");
+    HIP_TRY(hipMemcpyAsync(pl->h_diag, pl->dout(), sizeof(double) * 6 * pl->n, hipMemcpyDeviceToHost, s),
+            "diagnostics copy");
+    HIP_TRY(hipStreamSynchronize(s), "diagnostics sync");
+    const bool dual_ok = pl->prm.fidelity == DTV_L2 && !pl->prm.has_mask;
+    *nonfinite = false;
+    for (int b = 0; b < pl->n; ++b) {
+        const double *q = pl->h_diag + 6 * b;
+        const double alpha = pl->imgs[b].alpha;
+        const double J = alpha * q[0] + q[1];
+        const double D = dual_ok ? -q[2] - q[3] / (2.0 * alpha) : NAN;
+        rows[4 * b + 0] = J;
+        rows[4 * b + 1] = D;
+        rows[4 * b + 2] = J - D;
+        rows[4 * b + 3] = std::sqrt(q[4]);
+        if (q[5] != 0.0 || !std::isfinite(J) || !std::isfinite(q[4])) *nonfinite = true;
+    }
+    return DTV_OK;
+}
+
+extern "C" int dtv_dd_diagnostics(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_mask, const float *d_u,
+                                  const float *d_p1, const float *d_p2, double *h_out, void *stream)
+{
+    if (!pl || !d_f || !d_u || !d_p1 || !d_p2 || !h_out) return fail(DTV_EINVAL, "null argument");
+    if (pl->prm.has_mask && !d_mask) return fail(DTV_EINVAL, "mask expected");
+    if (!pl->ws) return fail(DTV_ENOWS, "no workspace bound");
+    bool nf = false;
+    int rc = run_diag(pl, d_f, pl->prm.has_mask ? d_mask : nullptr, d_u, d_p1, d_p2, (hipStream_t)stream, h_out, &nf);
+    if (rc != DTV_OK) return rc;
+    return nf ? fail(DTV_ENONFINITE, "non-finite value in the diagnostics") : DTV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// solve
+
+namespace {
+
+struct EdgeBuf {
+    float *p1, *p2;
+};
+
+// inner-step timing: events around each launch of the step kernel
+struct Timer {
+    dtv_dd_plan *pl;
+    hipStream_t s;
+    size_t used = 0;
+    bool on;
+    int begin()
+    {
+        if (!on) return DTV_OK;
+        while (pl->events.size() < used + 2) {
+            hipEvent_t e;
+            HIP_TRY(hipEventCreate(&e), "event create");
+            pl->events.push_back(e);
+        }
+        HIP_TRY(hipEventRecord(pl->events[used], s), "event record");
+        return DTV_OK;
+    }
+    int end()
+    {
+        if (!on) return DTV_OK;
+        HIP_TRY(hipEventRecord(pl->events[used + 1], s), "event record");
+        used += 2;
+        return DTV_OK;
+    }
+    int collect()
+    {
+        if (!on) return DTV_OK;
+        HIP_TRY(hipStreamSynchronize(s), "timing sync");
+        double tot = 0.0;
+        for (size_t k = 0; k < used; k += 2) {
+            float ms = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&ms, pl->events[k], pl->events[k + 1]), "event elapsed");
+            tot += ms;
+        }
+        pl->t_ms = used ? tot / (double)(used / 2) : 0.0;
+        pl->t_count = (int64_t)(used / 2);
+        return DTV_OK;
+    }
+};
+
+}  // namespace
+
+extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_mask, float *d_u, float *d_p1,
+                            float *d_p2, float *d_lambda, double *h_stats, int32_t *n_rows, void *stream)
+{
+    if (!pl || !d_f || !d_u || !d_p1 || !d_p2 || !d_lambda) return fail(DTV_EINVAL, "null argument");
+    const dtv_dd_params &P = pl->prm;
+    if (P.has_mask && !d_mask) return fail(DTV_EINVAL, "mask expected (has_mask = 1)");
+    if (!pl->ws) return fail(DTV_ENOWS, "no workspace bound");
+    hipStream_t s = (hipStream_t)stream;
+    const uint8_t *mask = P.has_mask ? d_mask : nullptr;
+    const bool cp2 = P.inner == DTV_INNER_CP2;
+    const int K = P.n_inner;
+
+    if (!P.warm_start) {
+        HIP_TRY(hipMemsetAsync(d_p1, 0, sizeof(float) * (size_t)pl->tot_p1, s), "clear p1");
+        HIP_TRY(hipMemsetAsync(d_p2, 0, sizeof(float) * (size_t)pl->tot_p2, s), "clear p2");
+        HIP_TRY(hipMemsetAsync(d_lambda, 0, sizeof(float) * (size_t)pl->tot_lam, s), "clear lambda");
+        if (cp2) HIP_TRY(hipMemcpyAsync(d_u, d_f, sizeof(float) * (size_t)pl->tot_px, hipMemcpyDeviceToDevice, s), "u = f");
+    }
+    HIP_TRY(launch_zero_boundary(pl->d_imgs(), pl->n, pl->maxH, pl->maxW, d_p1, d_p2, s), "zero boundary");
+
+    // step parameters, computed in double precision on the host
+    std::vector<float> beta(K + 1, 0.0f);  // FISTA momentum of step k (1-based)
+    {
+        std::vector<double> t(K + 2, 1.0);
+        for (int m = 1; m <= K; ++m) t[m + 1] = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t[m] * t[m]));
+        for (int k = 2; k <= K; ++k) beta[k] = (float)((t[k - 1] - 1.0) / t[k]);
+    }
+    std::vector<double> tk(K + 1), sk(K + 1), th(K + 1);
+    {
+        double a = P.tau0, b = P.sigma0;
+        for (int it = 0; it < K; ++it) {
+            tk[it] = a;
+            sk[it] = b;
+            th[it] = 1.0 / std::sqrt(1.0 + 2.0 * P.gamma * a);
+            a *= th[it];
+            b /= th[it];
+        }
+    }
+
+    EdgeBuf bufs[4] = {{d_p1, d_p2}, {pl->buf1(0), pl->buf2(0)}, {pl->buf1(1), pl->buf2(1)}, {pl->buf1(2), pl->buf2(2)}};
+    int base = 0;
+    float *u_cur = d_u;  // CP2: current u buffer (d_u or the workspace copy)
+    Timer tm{pl, s, 0, P.time_kernels != 0};
+    const int rows_cap = P.diag_every > 0 ? P.n_outer / P.diag_every + 1 : 0;
+    int nrow = 0;
+    bool nonfinite = false;
+    std::vector<double> drow(4 * pl->n);
+
+    auto emit_stats = [&](int step, const float *u, const EdgeBuf &b) -> int {
+        bool nf = false;
+        int rc = run_diag(pl, d_f, mask, u, b.p1, b.p2, s, drow.data(), &nf);
+        if (rc != DTV_OK) return rc;
+        nonfinite = nonfinite || nf;
+        if (h_stats && nrow < rows_cap)
+            for (int img = 0; img < pl->n; ++img) {
+                double *r = h_stats + 5 * ((size_t)img * rows_cap + nrow);
+                r[0] = step;
+                for (int q = 0; q < 4; ++q) r[1 + q] = drow[4 * img + q];
+            }
+        nrow++;
+        return DTV_OK;
+    };
+
+    for (int n = 0; n < P.n_outer; ++n) {
+        // (a1) multipliers from the extrapolated interface jump
+        HIP_TRY(launch_lambda(pl->d_imgs(), pl->n, pl->max_nlam, pl->d_info(), bufs[base].p1, bufs[base].p2, d_lambda,
+                              (float)P.sigma, s),
+                "lambda update");
+        int sc[3], q = 0;
+        for (int k = 0; k < 4; ++k)
+            if (k != base) sc[q++] = k;
+        // (a2)+(a3) local solves; the anchor phat is formed on the fly from bufs[base] and lambda
+        for (int k = 1; k <= K; ++k) {
+            const int ia = k == 1 ? base : sc[(k - 2) % 3];
+            const int ib = k >= 3 ? sc[(k - 3) % 3] : base;
+            const int io = sc[(k - 1) % 3];
+            int rc = tm.begin();
+            if (rc != DTV_OK) return rc;
+            if (!cp2) {
+                FistaStepArgs a{};
+                a.imgs = pl->d_imgs(); a.tiles = pl->d_tiles(); a.ntiles = (int)pl->h_tiles.size(); a.info = pl->d_info();
+                a.xa1 = bufs[ia].p1; a.xa2 = bufs[ia].p2; a.xb1 = bufs[ib].p1; a.xb2 = bufs[ib].p2;
+                a.base1 = bufs[base].p1; a.base2 = bufs[base].p2; a.lam = d_lambda; a.f = d_f;
+                a.out1 = bufs[io].p1; a.out2 = bufs[io].p2;
+                a.beta = beta[k]; a.tau = (float)P.tau; a.inv_tau = (float)(1.0 / P.tau);
+                HIP_TRY(launch_fista_step(a, k >= 3, pl->rows, s), "FISTA step");
+            } else {
+                const int it = k - 1;
+                Cp2StepArgs a{};
+                a.imgs = pl->d_imgs(); a.tiles = pl->d_tiles(); a.ntiles = (int)pl->h_tiles.size(); a.info = pl->d_info();
+                a.xa1 = bufs[ia].p1; a.xa2 = bufs[ia].p2; a.xb1 = bufs[ib].p1; a.xb2 = bufs[ib].p2;
+                a.base1 = bufs[base].p1; a.base2 = bufs[base].p2; a.lam = d_lambda; a.f = d_f; a.mask = mask;
+                float *u_next = u_cur == d_u ? pl->u2() : d_u;
+                a.u_in = u_cur; a.u_out = u_next;
+                a.out1 = bufs[io].p1; a.out2 = bufs[io].p2;
+                a.theta_prev = it >= 1 ? (float)th[it - 1] : 0.0f;
+                a.sk = (float)sk[it]; a.tk = (float)tk[it]; a.tau = (float)P.tau;
+                a.c_keep = (float)(P.tau / (P.tau + tk[it]));
+                a.c_anchor = (float)(tk[it] / (P.tau + tk[it]));
+                a.fidelity = P.fidelity;
+                HIP_TRY(launch_cp2_step(a, it >= 1, pl->rows, s), "CP2 step");
+                u_cur = u_next;
+            }
+            rc = tm.end();
+            if (rc != DTV_OK) return rc;
+        }
+        base = sc[(K - 1) % 3];
+        const bool last = n == P.n_outer - 1;
+        if (P.diag_every > 0 && ((n + 1) % P.diag_every == 0 || last)) {
+            const float *u = u_cur;
+            if (!cp2) {
+                HIP_TRY(launch_u_from_p(pl->d_imgs(), pl->n, pl->maxH, pl->maxW, pl->d_info(), bufs[base].p1,
+                                        bufs[base].p2, d_f, d_u, s),
+                        "u recovery");
+                u = d_u;
+            }
+            int rc = emit_stats(n + 1, u, bufs[base]);
+            if (rc != DTV_OK) return rc;
+            if (P.gap_tol > 0.0 && drow[2] <= P.gap_tol * std::fabs(drow[0])) break;
+        }
+    }
+    if (base != 0) {
+        HIP_TRY(hipMemcpyAsync(d_p1, bufs[base].p1, sizeof(float) * (size_t)pl->tot_p1, hipMemcpyDeviceToDevice, s), "copy p1");
+        HIP_TRY(hipMemcpyAsync(d_p2, bufs[base].p2, sizeof(float) * (size_t)pl->tot_p2, hipMemcpyDeviceToDevice, s), "copy p2");
+    }
+    if (cp2) {
+        if (u_cur != d_u)
+            HIP_TRY(hipMemcpyAsync(d_u, u_cur, sizeof(float) * (size_t)pl->tot_px, hipMemcpyDeviceToDevice, s), "copy u");
+    } else {
+        HIP_TRY(launch_u_from_p(pl->d_imgs(), pl->n, pl->maxH, pl->maxW, pl->d_info(), d_p1, d_p2, d_f, d_u, s),
+                "u recovery");
+    }
+    int rc = tm.collect();
+    if (rc != DTV_OK) return rc;
+    if (n_rows) *n_rows = nrow;
+    if (nonfinite) return fail(DTV_ENONFINITE, "non-finite value in the diagnostics");
+    return DTV_OK;
+}
+
+extern "C" int dtv_dd_backward(dtv_dd_plan *pl, const float *d_f, const float *d_grad_u, float *d_grad_f,
+                               float *d_grad_alpha, void *stream)
+{
+    (void)d_f; (void)d_grad_u; (void)d_grad_f; (void)d_grad_alpha; (void)stream;
+    if (!pl) return fail(DTV_EINVAL, "null argument");
+    return fail(DTV_ESTATE, "no saved forward: backward is not available in this build");
+}
+
+extern "C" int dtv_dd_kernel_time(const dtv_dd_plan *pl, double *avg_ms, int64_t *launches, const char **name,
+                                  double *bytes_per_launch)
+{
+    if (!pl) return fail(DTV_EINVAL, "null argument");
+    if (avg_ms) *avg_ms = pl->t_ms;
+    if (launches) *launches = pl->t_count;
+    const bool cp2 = pl->prm.inner == DTV_INNER_CP2;
+    if (name) *name = cp2 ? "k_cp2_step" : "k_fista_step";
+    if (bytes_per_launch) {
+        // Algorithmic HBM bytes of one inner-step launch, averaged over the n_inner
+        // launches of an outer step.  E = edge dofs (torn), N = pixels.
+        //   FISTA step 1: read x_0 (= anchor base) and f, write x_1            4 (2E + N)
+        //   FISTA step 2: read x_1, base, f, write x_2 (no momentum yet)       4 (3E + N)
+        //   FISTA step k >= 3: read x_{k-1}, x_{k-2}, base, f, write x_k      4 (4E + N)
+        //   CP2 step 1: read x_0, u, f (+ mask), write x_1, u                  4 (2E + 3N) + mask
+        //   CP2 step k >= 2: read x_{k-1}, x_{k-2}, base, u, f (+ mask), write 4 (4E + 3N) + mask
+        double E = 0.0, N = 0.0;
+        for (const ImgHost &h : pl->imgs) {
+            E += (double)(h.H + h.ny) * h.W + (double)h.H * (h.W + h.nx);
+            N += (double)h.H * h.W;
+        }
+        const int K = pl->prm.n_inner;
+        const double mb = pl->prm.has_mask ? N : 0.0;
+        double tot = 0.0;
+        for (int k = 1; k <= K; ++k) {
+            if (cp2) tot += (k == 1 ? 4.0 * (2 * E + 3 * N) : 4.0 * (4 * E + 3 * N)) + mb;
+            else tot += k == 1 ? 4.0 * (2 * E + N) : (k == 2 ? 4.0 * (3 * E + N) : 4.0 * (4 * E + N));
+        }
+        *bytes_per_launch = tot / K;
+    }
+    return DTV_OK;
+}
+
+extern "C" void dtv_dd_destroy(dtv_dd_plan *pl) { delete pl; }
+
+extern "C" const char *dtv_last_error(void) { return g_err.c_str(); }

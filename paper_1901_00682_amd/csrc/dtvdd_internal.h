@@ -1,0 +1,106 @@
+// Internal declarations shared by the host runtime and the HIP kernels of
+// libdtvdd.so.  Layout conventions are those documented in include/dtvdd.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dtv {
+
+// Per-image descriptor as the kernels see it (lives in the workspace).
+struct ImgDev {
+    int H, W, ny, nx;
+    long long px;        // offset of the H*W pixel block (f, u, mask, grads)
+    long long p1, p2;    // offsets of P1 / P2 in the edge arrays
+    int pitch1, pitch2;  // row pitches (floats) of P1 / P2
+    long long lam;       // offset of the 3*n_lam lambda-state block
+    int nlh, nlam;       // horizontal-interface dofs, all interface dofs
+    long long rinfo;     // offset of H row-info words in the info array
+    long long cinfo;     // offset of W column-info words
+    long long rcut;      // offset of ny+1 row cuts in the info array
+    long long ccut;      // offset of nx+1 column cuts
+    float alpha, inv_alpha;
+    float invL;          // FISTA step 1/L, L = 8/alpha + 1/tau
+    float a_keep;        // FISTA: 1 - 1/(L tau)  (coefficient of y in the fused update)
+    float pad0, pad1;
+};
+
+// Row / column info word: subdomain index << 2 | first << 0 | last << 1.
+__host__ __device__ inline int info_sub(int w) { return w >> 2; }
+__host__ __device__ inline bool info_first(int w) { return (w & 1) != 0; }
+__host__ __device__ inline bool info_last(int w) { return (w & 2) != 0; }
+
+// Work item of the streaming kernels: one wave handles columns
+// [j0 - 1, j0 + 62] (lane 0 is a halo column) and rows [i0, i0 + R).
+struct StreamTile {
+    int img, i0, j0, pad;
+};
+
+// Work item of the fused kernels: one subdomain.
+struct SubTile {
+    int img, r, c;       // image, subdomain row / column
+    int ra, ca, h, w;    // pixel origin and extent
+    int pad;
+};
+
+constexpr int kStreamCols = 63;   // output columns per wave
+constexpr int kFusedMax = 128;    // largest subdomain side handled by the fused kernel
+
+struct FistaStepArgs {
+    const ImgDev *imgs;
+    const StreamTile *tiles;
+    int ntiles;
+    const int *info;
+    const float *xa1, *xa2;   // x_{k-1}
+    const float *xb1, *xb2;   // x_{k-2} (momentum steps only)
+    const float *base1, *base2; // p~^n (anchor base)
+    const float *lam;         // lambda state
+    const float *f;
+    float *out1, *out2;       // x_k
+    float beta;               // momentum coefficient of this step
+    float tau;                // outer tau (anchor p~ -/+ tau lambda)
+    float inv_tau;
+};
+
+struct Cp2StepArgs {
+    const ImgDev *imgs;
+    const StreamTile *tiles;
+    int ntiles;
+    const int *info;
+    const float *xa1, *xa2;   // x_{k-1} (the current p)
+    const float *xb1, *xb2;   // x_{k-2} (for the extrapolation; theta_prev = 0 on the first step)
+    const float *base1, *base2;
+    const float *lam;
+    const float *f;
+    const uint8_t *mask;      // NULL: all observed
+    const float *u_in;
+    float *u_out;
+    float *out1, *out2;
+    float theta_prev;         // extrapolation weight of xbar = x + theta_prev (x - x_prev)
+    float sk;                 // sigma_k
+    float tk;                 // tau_k
+    float tau;                // outer tau
+    float c_keep, c_anchor;   // tau/(tau+tau_k), tau_k/(tau+tau_k)
+    int fidelity;
+};
+
+// Kernel launchers (kernels.hip).
+hipError_t launch_lambda(const ImgDev *imgs, int nimg, int max_nlam, const int *info, const float *p1,
+                         const float *p2, float *lam, float sigma, hipStream_t s);
+hipError_t launch_fista_step(const FistaStepArgs &a, bool momentum, int rows, hipStream_t s);
+hipError_t launch_cp2_step(const Cp2StepArgs &a, bool extrapolate, int rows, hipStream_t s);
+hipError_t launch_u_from_p(const ImgDev *imgs, int nimg, int maxH, int maxW, const int *info, const float *p1,
+                           const float *p2, const float *f, float *u, hipStream_t s);
+hipError_t launch_zero_boundary(const ImgDev *imgs, int nimg, int maxH, int maxW, float *p1, float *p2,
+                                hipStream_t s);
+// FP64 diagnostics: per image 6 partial sums reduced into out[img*6 + q]:
+// q = 0 fidelity sum, 1 TV, 2 <f, div p_avg>, 3 |div p_avg|^2, 4 |B p|^2, 5 non-finite count.
+hipError_t launch_diag(const ImgDev *imgs, int nimg, int maxH, int maxW, const int *info, const float *p1,
+                       const float *p2, const float *f, const float *u, const uint8_t *mask, int fidelity,
+                       double *partials, int nblk_per_img, double *out, hipStream_t s);
+int diag_blocks_per_image(int maxH, int maxW);
+hipError_t launch_fused_fista(const ImgDev *imgs, const SubTile *subs, int nsub, const float *base1,
+                              const float *base2, const float *lam, const float *f, float *out1, float *out2,
+                              const float *betas, int n_inner, float tau, float inv_tau, hipStream_t s);
+
+}  // namespace dtv

@@ -1,0 +1,517 @@
+// HIP kernels of libdtvdd.so for gfx950: the streaming schedule of
+// Algorithm 1 (Lee & Park, arXiv 1901.00682, Sec. 4) -- one launch per inner
+// step over every subdomain of every image -- plus the multiplier update,
+// the primal recovery and the FP64 diagnostics.
+//
+// Work decomposition of the step kernels: one 64-lane wave owns a strip of
+// R pixel rows and 64 consecutive columns; lane 0 is a halo column whose
+// values are only used by lane 1, so each wave writes 63 columns and all
+// loads and stores of a row are coalesced.  Rows are swept top to bottom so
+// the edge shared by two vertically adjacent pixels of the same subdomain is
+// loaded once and the value of the pixel above stays in a register; the
+// value of the left neighbour comes from the lane to the left by a shuffle.
+// Subdomain membership comes from per-row / per-column info words, so tiles
+// of any size (ragged ones included) need no special cases.
+//
+// Arithmetic is FP32 with explicit fmaf where a fused multiply-add is meant
+// (the library is built with -ffp-contract=off so that the streaming and
+// fused schedules round identically).
+#include "dtvdd_internal.h"
+
+namespace dtv {
+
+// Workgroup ids are dealt to the 8 XCDs round-robin; remap them so that
+// consecutive work items (which share halo rows in L2) run on one XCD.
+__device__ __forceinline__ int xcd_remap(int b, int n)
+{
+    const int xcd = b & 7, idx = b >> 3;
+    const int per = n >> 3, rem = n & 7;
+    return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+}
+
+__device__ __forceinline__ float clamp1(float z) { return __builtin_amdgcn_fmed3f(z, -1.0f, 1.0f); }
+
+// ---------------------------------------------------------------------------
+// (a1) multiplier update, one thread per interface dof:
+//   lambda_e += sigma ((2 p_s - prev_s) - (2 p_t - prev_t)),  prev <- p.
+__global__ __launch_bounds__(256) void k_lambda(const ImgDev *imgs, const int *info, const float *p1,
+                                                const float *p2, float *lam, float sigma)
+{
+    const ImgDev im = imgs[blockIdx.y];
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= im.nlam) return;
+    float ps, pt;
+    if (e < im.nlh) {
+        const int r = e / im.W + 1, j = e - (r - 1) * im.W;
+        const int cut = info[im.rcut + r];
+        // side s: bottom copy of subdomain row r-1 at P1 row cut + r - 1; side t: row cut + r
+        ps = p1[im.p1 + (long long)(cut + r - 1) * im.pitch1 + j];
+        pt = p1[im.p1 + (long long)(cut + r) * im.pitch1 + j];
+    } else {
+        const int q = e - im.nlh;
+        const int c = q / im.H + 1, i = q - (c - 1) * im.H;
+        const int cut = info[im.ccut + c];
+        ps = p2[im.p2 + (long long)i * im.pitch2 + cut + c - 1];
+        pt = p2[im.p2 + (long long)i * im.pitch2 + cut + c];
+    }
+    float *L = lam + im.lam;
+    const float prev_s = L[im.nlam + e], prev_t = L[2 * im.nlam + e];
+    L[e] = L[e] + sigma * ((2.0f * ps - prev_s) - (2.0f * pt - prev_t));
+    L[im.nlam + e] = ps;
+    L[2 * im.nlam + e] = pt;
+}
+
+hipError_t launch_lambda(const ImgDev *imgs, int nimg, int max_nlam, const int *info, const float *p1,
+                         const float *p2, float *lam, float sigma, hipStream_t s)
+{
+    if (max_nlam <= 0) return hipSuccess;
+    dim3 grid((max_nlam + 255) / 256, nimg);
+    hipLaunchKernelGGL(k_lambda, grid, dim3(256), 0, s, imgs, info, p1, p2, lam, sigma);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// (a3) one projected-FISTA step on every local dual problem (ROF):
+//   y = x_{k-1} + beta (x_{k-1} - x_{k-2})
+//   v = f + div_s y / alpha                       (per pixel)
+//   g = div_s^* v + (y - phat) / tau              (per dof edge; one-sided on
+//                                                  interface copies)
+//   x_k = clamp(y - g / L, -1, 1)
+// with phat = p~^n -/+ tau lambda on the s / t copies of interface edges
+// (Algorithm 1, phat = p~ - tau B^* lambda) and p~^n elsewhere.
+template <int R, bool MOM>
+__global__ __launch_bounds__(64) void k_fista_step(FistaStepArgs a)
+{
+    const int t = xcd_remap(blockIdx.x, gridDim.x);
+    const StreamTile tile = a.tiles[t];
+    const ImgDev im = a.imgs[tile.img];
+    const int lane = threadIdx.x;
+    const int H = im.H, W = im.W;
+    const int j = tile.j0 - 1 + lane;
+    const bool colok = (j >= 0) && (j < W);
+    const int cw = colok ? a.info[im.cinfo + j] : 0;
+    const int cs = info_sub(cw);
+    const bool cfirst = info_first(cw), clast = info_last(cw);
+    const int left = j + cs;
+    const bool outlane = colok && lane >= 1;
+    const long long P1 = im.pitch1, P2 = im.pitch2;
+
+    const float *xa1 = a.xa1 + im.p1, *xa2 = a.xa2 + im.p2;
+    const float *xb1 = MOM ? a.xb1 + im.p1 : nullptr, *xb2 = MOM ? a.xb2 + im.p2 : nullptr;
+    const float *b1 = a.base1 + im.p1, *b2 = a.base2 + im.p2;
+    const float *lam = a.lam + im.lam;
+    const float *f = a.f + im.px;
+    float *o1 = a.out1 + im.p1, *o2 = a.out2 + im.p2;
+    const float beta = a.beta, ia = im.inv_alpha, invL = im.invL, tau = a.tau, itau = a.inv_tau;
+
+    auto y1 = [&](long long idx) -> float {
+        const float x = xa1[idx];
+        if constexpr (MOM) return fmaf(beta, x - xb1[idx], x);
+        return x;
+    };
+    auto y2 = [&](long long idx) -> float {
+        const float x = xa2[idx];
+        if constexpr (MOM) return fmaf(beta, x - xb2[idx], x);
+        return x;
+    };
+
+    const int i0 = tile.i0;
+    const int iend = min(i0 + R, H);
+    float v_up = 0.0f, y_carry = 0.0f;
+    bool have = false;
+    if (i0 > 0 && !info_first(a.info[im.rinfo + i0])) {
+        // halo row: v of the pixel above the strip, same subdomain
+        const int i = i0 - 1;
+        const int top = i + info_sub(a.info[im.rinfo + i]);
+        if (colok) {
+            const float yt = y1(top * P1 + j), yb = y1((top + 1) * P1 + j);
+            const float yl = y2(i * P2 + left), yr = y2(i * P2 + left + 1);
+            v_up = fmaf((yb - yt) + (yr - yl), ia, f[(long long)i * W + j]);
+            y_carry = yb;
+        }
+        have = true;
+    }
+    for (int i = i0; i < iend; ++i) {
+        const int rw = a.info[im.rinfo + i];
+        const int rs = info_sub(rw);
+        const bool rfirst = info_first(rw), rlast = info_last(rw);
+        const long long top = i + rs;
+        if (rfirst) {
+            have = false;
+            v_up = 0.0f;
+        }
+        float v = 0.0f, yt = 0.0f, yb = 0.0f, yl = 0.0f, yr = 0.0f;
+        if (colok) {
+            yt = have ? y_carry : y1(top * P1 + j);
+            yb = y1((top + 1) * P1 + j);
+            yl = y2(i * P2 + left);
+            yr = y2(i * P2 + left + 1);
+            v = fmaf((yb - yt) + (yr - yl), ia, f[(long long)i * W + j]);
+        }
+        float v_left = __shfl_up(v, 1, 64);
+        if (cfirst) v_left = 0.0f;
+        if (outlane) {
+            if (i > 0) {  // edge above the pixel (interior, or t copy of an interface)
+                float anchor = b1[top * P1 + j];
+                if (rfirst) anchor = fmaf(tau, lam[(long long)(rs - 1) * W + j], anchor);
+                const float g = fmaf(yt - anchor, itau, v_up - v);
+                o1[top * P1 + j] = clamp1(fmaf(-g, invL, yt));
+            }
+            if (j > 0) {  // edge left of the pixel
+                float anchor = b2[i * P2 + left];
+                if (cfirst) anchor = fmaf(tau, lam[im.nlh + (long long)(cs - 1) * H + i], anchor);
+                const float g = fmaf(yl - anchor, itau, v_left - v);
+                o2[i * P2 + left] = clamp1(fmaf(-g, invL, yl));
+            }
+            if (rlast && i < H - 1) {  // s copy below the last row of the subdomain
+                const float anchor = fmaf(-tau, lam[(long long)rs * W + j], b1[(top + 1) * P1 + j]);
+                const float g = fmaf(yb - anchor, itau, v);
+                o1[(top + 1) * P1 + j] = clamp1(fmaf(-g, invL, yb));
+            }
+            if (clast && j < W - 1) {  // s copy right of the last column
+                const float anchor = fmaf(-tau, lam[im.nlh + (long long)cs * H + i], b2[i * P2 + left + 1]);
+                const float g = fmaf(yr - anchor, itau, v);
+                o2[i * P2 + left + 1] = clamp1(fmaf(-g, invL, yr));
+            }
+        }
+        v_up = v;
+        y_carry = yb;
+        have = true;
+    }
+}
+
+template <int R>
+static hipError_t fista_rows(const FistaStepArgs &a, bool momentum, hipStream_t s)
+{
+    if (momentum)
+        hipLaunchKernelGGL((k_fista_step<R, true>), dim3(a.ntiles), dim3(64), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_fista_step<R, false>), dim3(a.ntiles), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fista_step(const FistaStepArgs &a, bool momentum, int rows, hipStream_t s)
+{
+    if (a.ntiles <= 0) return hipSuccess;
+    switch (rows) {
+    case 8: return fista_rows<8>(a, momentum, s);
+    case 16: return fista_rows<16>(a, momentum, s);
+    case 32: return fista_rows<32>(a, momentum, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// (a3) one step of the accelerated primal-dual method (Chambolle-Pock 2011,
+// Alg. 2) on every local saddle problem eq. (local) of Sec. 5:
+//   xbar = x_{k-1} + theta_prev (x_{k-1} - x_{k-2})
+//   u_k  = prox_{sigma_k alpha F}(u_{k-1} + sigma_k div_s xbar)   (per pixel)
+//   x_k  = clamp((tau (x_{k-1} - tau_k div_s^* u_k) + tau_k phat) / (tau + tau_k))
+__device__ __forceinline__ float prox_fid(int fidelity, float z, float fv, bool observed, float a)
+{
+    if (!observed) return z;
+    if (fidelity == 0) return (z + a * fv) / (1.0f + a);
+    const float d = z - fv;
+    const float mag = fmaxf(fabsf(d) - a, 0.0f);
+    return d > 0.0f ? fv + mag : (d < 0.0f ? fv - mag : fv);
+}
+
+template <int R, bool EXT>
+__global__ __launch_bounds__(64) void k_cp2_step(Cp2StepArgs a)
+{
+    const int t = xcd_remap(blockIdx.x, gridDim.x);
+    const StreamTile tile = a.tiles[t];
+    const ImgDev im = a.imgs[tile.img];
+    const int lane = threadIdx.x;
+    const int H = im.H, W = im.W;
+    const int j = tile.j0 - 1 + lane;
+    const bool colok = (j >= 0) && (j < W);
+    const int cw = colok ? a.info[im.cinfo + j] : 0;
+    const int cs = info_sub(cw);
+    const bool cfirst = info_first(cw), clast = info_last(cw);
+    const int left = j + cs;
+    const bool outlane = colok && lane >= 1;
+    const long long P1 = im.pitch1, P2 = im.pitch2;
+
+    const float *xa1 = a.xa1 + im.p1, *xa2 = a.xa2 + im.p2;
+    const float *xb1 = EXT ? a.xb1 + im.p1 : nullptr, *xb2 = EXT ? a.xb2 + im.p2 : nullptr;
+    const float *b1 = a.base1 + im.p1, *b2 = a.base2 + im.p2;
+    const float *lam = a.lam + im.lam;
+    const float *f = a.f + im.px;
+    const uint8_t *mk = a.mask ? a.mask + im.px : nullptr;
+    const float *uin = a.u_in + im.px;
+    float *uout = a.u_out + im.px;
+    float *o1 = a.out1 + im.p1, *o2 = a.out2 + im.p2;
+    const float th = a.theta_prev, sk = a.sk, tk = a.tk, tau = a.tau;
+    const float ck = a.c_keep, ca = a.c_anchor, sa = a.sk * im.alpha;
+    const int fid = a.fidelity;
+
+    auto xbar1 = [&](long long idx, float &x) -> float {
+        x = xa1[idx];
+        if constexpr (EXT) return fmaf(th, x - xb1[idx], x);
+        return x;
+    };
+    auto xbar2 = [&](long long idx, float &x) -> float {
+        x = xa2[idx];
+        if constexpr (EXT) return fmaf(th, x - xb2[idx], x);
+        return x;
+    };
+    auto unew = [&](int i, float xt, float xb, float xl, float xr) -> float {
+        const long long px = (long long)i * W + j;
+        const float d = (xb - xt) + (xr - xl);
+        return prox_fid(fid, fmaf(sk, d, uin[px]), f[px], mk ? mk[px] != 0 : true, sa);
+    };
+    auto pupdate = [&](float x, float du, float anchor) -> float {
+        const float pbar = fmaf(-tk, du, x);  // x - tau_k div^* u
+        return clamp1(fmaf(ck, pbar, ca * anchor));
+    };
+
+    const int i0 = tile.i0;
+    const int iend = min(i0 + R, H);
+    float u_up = 0.0f, xbar_carry = 0.0f, x_carry = 0.0f;
+    bool have = false;
+    if (i0 > 0 && !info_first(a.info[im.rinfo + i0])) {
+        const int i = i0 - 1;
+        const int top = i + info_sub(a.info[im.rinfo + i]);
+        if (colok) {
+            float x;
+            const float xt = xbar1(top * P1 + j, x);
+            const float xb = xbar1((top + 1) * P1 + j, x_carry);
+            const float xl = xbar2(i * P2 + left, x), xr = xbar2(i * P2 + left + 1, x);
+            u_up = unew(i, xt, xb, xl, xr);
+            xbar_carry = xb;
+        }
+        have = true;
+    }
+    for (int i = i0; i < iend; ++i) {
+        const int rw = a.info[im.rinfo + i];
+        const int rs = info_sub(rw);
+        const bool rfirst = info_first(rw), rlast = info_last(rw);
+        const long long top = i + rs;
+        if (rfirst) {
+            have = false;
+            u_up = 0.0f;
+        }
+        float u = 0.0f, xt = 0.0f, xb = 0.0f, xl = 0.0f, xr = 0.0f;
+        float pt = 0.0f, pb = 0.0f, pl = 0.0f, pr = 0.0f;  // current x on the four edges
+        if (colok) {
+            if (have) {
+                xt = xbar_carry;
+                pt = x_carry;
+            } else {
+                xt = xbar1(top * P1 + j, pt);
+            }
+            xb = xbar1((top + 1) * P1 + j, pb);
+            xl = xbar2(i * P2 + left, pl);
+            xr = xbar2(i * P2 + left + 1, pr);
+            u = unew(i, xt, xb, xl, xr);
+        }
+        float u_left = __shfl_up(u, 1, 64);
+        if (cfirst) u_left = 0.0f;
+        if (outlane) {
+            uout[(long long)i * W + j] = u;
+            if (i > 0) {
+                float anchor = b1[top * P1 + j];
+                if (rfirst) anchor = fmaf(tau, lam[(long long)(rs - 1) * W + j], anchor);
+                o1[top * P1 + j] = pupdate(pt, u_up - u, anchor);
+            }
+            if (j > 0) {
+                float anchor = b2[i * P2 + left];
+                if (cfirst) anchor = fmaf(tau, lam[im.nlh + (long long)(cs - 1) * H + i], anchor);
+                o2[i * P2 + left] = pupdate(pl, u_left - u, anchor);
+            }
+            if (rlast && i < H - 1) {
+                const float anchor = fmaf(-tau, lam[(long long)rs * W + j], b1[(top + 1) * P1 + j]);
+                o1[(top + 1) * P1 + j] = pupdate(pb, u, anchor);
+            }
+            if (clast && j < W - 1) {
+                const float anchor = fmaf(-tau, lam[im.nlh + (long long)cs * H + i], b2[i * P2 + left + 1]);
+                o2[i * P2 + left + 1] = pupdate(pr, u, anchor);
+            }
+        }
+        u_up = u;
+        xbar_carry = xb;
+        x_carry = pb;
+        have = true;
+    }
+}
+
+template <int R>
+static hipError_t cp2_rows(const Cp2StepArgs &a, bool ext, hipStream_t s)
+{
+    if (ext)
+        hipLaunchKernelGGL((k_cp2_step<R, true>), dim3(a.ntiles), dim3(64), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_cp2_step<R, false>), dim3(a.ntiles), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_cp2_step(const Cp2StepArgs &a, bool extrapolate, int rows, hipStream_t s)
+{
+    if (a.ntiles <= 0) return hipSuccess;
+    switch (rows) {
+    case 8: return cp2_rows<8>(a, extrapolate, s);
+    case 16: return cp2_rows<16>(a, extrapolate, s);
+    case 32: return cp2_rows<32>(a, extrapolate, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// (a4) primal recovery for ROF: u = f + div_s p~ / alpha on every pixel.
+__global__ __launch_bounds__(256) void k_u_from_p(const ImgDev *imgs, const int *info, const float *p1,
+                                                  const float *p2, const float *f, float *u)
+{
+    const ImgDev im = imgs[blockIdx.z];
+    const int j = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (i >= im.H || j >= im.W) return;
+    const long long top = i + info_sub(info[im.rinfo + i]);
+    const long long left = j + info_sub(info[im.cinfo + j]);
+    const float *q1 = p1 + im.p1, *q2 = p2 + im.p2;
+    const float yt = q1[top * im.pitch1 + j], yb = q1[(top + 1) * im.pitch1 + j];
+    const float yl = q2[i * (long long)im.pitch2 + left], yr = q2[i * (long long)im.pitch2 + left + 1];
+    const long long px = im.px + (long long)i * im.W + j;
+    u[px] = fmaf((yb - yt) + (yr - yl), im.inv_alpha, f[px]);
+}
+
+hipError_t launch_u_from_p(const ImgDev *imgs, int nimg, int maxH, int maxW, const int *info, const float *p1,
+                           const float *p2, const float *f, float *u, hipStream_t s)
+{
+    dim3 grid((maxW + 63) / 64, (maxH + 3) / 4, nimg);
+    hipLaunchKernelGGL(k_u_from_p, grid, dim3(256), 0, s, imgs, info, p1, p2, f, u);
+    return hipGetLastError();
+}
+
+// Boundary edges of the image carry no dof: keep them at zero.
+__global__ __launch_bounds__(256) void k_zero_boundary(const ImgDev *imgs, float *p1, float *p2)
+{
+    const ImgDev im = imgs[blockIdx.y];
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < im.W) {
+        p1[im.p1 + k] = 0.0f;
+        p1[im.p1 + (long long)(im.H + im.ny - 1) * im.pitch1 + k] = 0.0f;
+    }
+    if (k < im.H) {
+        p2[im.p2 + (long long)k * im.pitch2] = 0.0f;
+        p2[im.p2 + (long long)k * im.pitch2 + im.W + im.nx - 1] = 0.0f;
+    }
+}
+
+hipError_t launch_zero_boundary(const ImgDev *imgs, int nimg, int maxH, int maxW, float *p1, float *p2,
+                                hipStream_t s)
+{
+    const int n = maxH > maxW ? maxH : maxW;
+    hipLaunchKernelGGL(k_zero_boundary, dim3((n + 255) / 256, nimg), dim3(256), 0, s, imgs, p1, p2);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// (a5) FP64 diagnostics.  Per pixel, in double precision:
+//   fidelity term, TV terms |u(i+1,j) - u(i,j)| + |u(i,j+1) - u(i,j)|,
+//   d = div p_avg (interface dofs averaged over their two copies),
+//   f d and d^2, and |p_s - p_t|^2 for the interface edges below / right of
+//   the pixel.  Fixed-order reductions (wave shuffles, then a fixed tree), so
+//   results are bitwise reproducible.
+constexpr int kDiagRows = 32;  // rows per diagnostics block (4 rows per pass, 8 passes)
+
+int diag_blocks_per_image(int maxH, int maxW) { return ((maxW + 63) / 64) * ((maxH + kDiagRows - 1) / kDiagRows); }
+
+__device__ __forceinline__ double wave_sum(double x)
+{
+    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+__global__ __launch_bounds__(256) void k_diag(const ImgDev *imgs, const int *info, const float *p1,
+                                              const float *p2, const float *f, const float *u,
+                                              const uint8_t *mask, int fidelity, double *partials)
+{
+    const ImgDev im = imgs[blockIdx.z];
+    const int j = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int H = im.H, W = im.W;
+    const float *q1 = p1 + im.p1, *q2 = p2 + im.p2;
+    const long long P1 = im.pitch1, P2 = im.pitch2;
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int pass = 0; pass < kDiagRows / 4; ++pass) {
+        const int i = blockIdx.y * kDiagRows + pass * 4 + (threadIdx.x >> 6);
+        if (i >= H || j >= W) continue;
+        const int rw = info[im.rinfo + i], cw = info[im.cinfo + j];
+        const long long top = i + info_sub(rw), left = j + info_sub(cw);
+        const long long px = im.px + (long long)i * W + j;
+        const double uv = u[px], fv = f[px];
+        const bool obs = mask ? mask[px] != 0 : true;
+        if (obs) {
+            const double d = uv - fv;
+            acc[0] += fidelity == 0 ? 0.5 * d * d : fabs(d);
+        }
+        if (i + 1 < H) acc[1] += fabs((double)u[px + W] - uv);
+        if (j + 1 < W) acc[1] += fabs((double)u[px + 1] - uv);
+        // conforming average on the four edges of the pixel
+        double et = q1[top * P1 + j], eb = q1[(top + 1) * P1 + j];
+        double el = q2[i * P2 + left], er = q2[i * P2 + left + 1];
+        if (info_first(rw) && i > 0) et = 0.5 * (et + (double)q1[(top - 1) * P1 + j]);
+        if (info_last(rw) && i < H - 1) {
+            const double t = q1[(top + 2) * P1 + j];
+            acc[4] += (eb - t) * (eb - t);
+            eb = 0.5 * (eb + t);
+        }
+        if (info_first(cw) && j > 0) el = 0.5 * (el + (double)q2[i * P2 + left - 1]);
+        if (info_last(cw) && j < W - 1) {
+            const double t = q2[i * P2 + left + 2];
+            acc[4] += (er - t) * (er - t);
+            er = 0.5 * (er + t);
+        }
+        const double d = (eb - et) + (er - el);
+        acc[2] += fv * d;
+        acc[3] += d * d;
+        if (!isfinite(uv) || !isfinite(et) || !isfinite(el) || !isfinite(eb) || !isfinite(er)) acc[5] += 1.0;
+    }
+    __shared__ double red[4][6];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int q = 0; q < 6; ++q) {
+        const double s = wave_sum(acc[q]);
+        if (lane == 0) red[wave][q] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int q = threadIdx.x;
+        const double s = (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
+        const long long blk = (long long)blockIdx.z * gridDim.x * gridDim.y + blockIdx.y * gridDim.x + blockIdx.x;
+        partials[blk * 6 + q] = s;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_diag_final(const double *partials, int nblk, double *out)
+{
+    const int img = blockIdx.x;
+    const double *P = partials + (long long)img * nblk * 6;
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nblk; b += 256)
+        for (int q = 0; q < 6; ++q) acc[q] += P[(long long)b * 6 + q];
+    __shared__ double red[4][6];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int q = 0; q < 6; ++q) {
+        const double s = wave_sum(acc[q]);
+        if (lane == 0) red[wave][q] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int q = threadIdx.x;
+        out[img * 6 + q] = (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
+    }
+}
+
+hipError_t launch_diag(const ImgDev *imgs, int nimg, int maxH, int maxW, const int *info, const float *p1,
+                       const float *p2, const float *f, const float *u, const uint8_t *mask, int fidelity,
+                       double *partials, int nblk_per_img, double *out, hipStream_t s)
+{
+    dim3 grid((maxW + 63) / 64, (maxH + kDiagRows - 1) / kDiagRows, nimg);
+    hipLaunchKernelGGL(k_diag, grid, dim3(256), 0, s, imgs, info, p1, p2, f, u, mask, fidelity, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_diag_final, dim3(nimg), dim3(256), 0, s, partials, nblk_per_img, out);
+    return hipGetLastError();
+}
+
+}  // namespace dtv

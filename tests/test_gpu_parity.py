@@ -1,0 +1,193 @@
+"""GPU path (through the C-ABI) against the FP64 oracle at matched iteration
+counts: relative L2 <= 1e-5 on u and on the torn p (all dofs), FP64
+diagnostics within 1e-6 relative.  Inputs are the seeded synthetic workloads
+(paper_1901_00682_amd.synth); the oracle gets the same FP32 data widened."""
+import sys
+import zlib
+
+import numpy as np
+import pytest
+
+from paper_1901_00682_amd import synth
+from tests.helpers import compare, gpu_image_state, oracle_for, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1901_00682_amd import dtvdd
+    dtvdd.lib()
+
+
+def run_gpu(f32, alpha, rc, cc, mask=None, **kw):
+    from paper_1901_00682_amd import dtvdd
+    H, W = f32.shape
+    plan = dtvdd.Plan([dtvdd.Image(H, W, rc, cc, alpha)], has_mask=mask is not None, **kw)
+    f = torch.from_numpy(np.ascontiguousarray(f32, dtype=np.float32).ravel()).cuda()
+    m = None if mask is None else torch.from_numpy(np.ascontiguousarray(mask, dtype=np.uint8).ravel()).cuda()
+    state, stats = plan.solve(f, m)
+    torch.cuda.synchronize()
+    return plan, state, stats, f, m
+
+
+CASES = {
+    # name: (H, W, row_cuts, col_cuts, alpha, fidelity, inner, masked, n_outer, n_inner)
+    "rof_ragged": (70, 150, [0, 20, 41, 70], [0, 1, 63, 64, 100, 150], 6.0, "L2", "FISTA", False, 30, 7),
+    "rof_1x1": (40, 33, [0, 40], [0, 33], 10.0, "L2", "FISTA", False, 20, 10),
+    "rof_row": (1, 200, [0, 1], [0, 70, 130, 200], 8.0, "L2", "FISTA", False, 40, 5),
+    "rof_col": (130, 1, [0, 64, 65, 130], [0, 1], 8.0, "L2", "FISTA", False, 40, 5),
+    "cp2_l2": (70, 150, [0, 20, 41, 70], [0, 1, 63, 64, 100, 150], 6.0, "L2", "CP2", False, 25, 6),
+    "cp2_l1_mask": (90, 140, [0, 31, 60, 90], [0, 35, 70, 105, 140], 1.5, "L1", "CP2", True, 30, 5),
+    "cp2_l2_mask": (64, 80, [0, 32, 64], [0, 27, 54, 80], 10.0, "L2", "CP2", True, 30, 5),
+    "cp2_l1": (48, 48, [0, 16, 48], [0, 30, 48], 1.0, "L1", "CP2", False, 30, 5),
+}
+
+
+def _input(name, H, W, masked, fidelity):
+    rng = np.random.default_rng(zlib.crc32(name.encode()))
+    clean = synth.shapes(H, W, rng)
+    if fidelity == "L1":
+        f = synth.salt_and_pepper(clean, 0.3, rng)
+    else:
+        f = clean + synth.gaussian((H, W), 0.05, rng)
+    mask = None
+    if masked:
+        mask = synth.stroke_mask(H, W, 0.1, rng)
+        f = np.where(mask == 1, f, 0.0)
+    return f.astype(np.float32), mask
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_parity_small(name):
+    H, W, rc, cc, alpha, fid, inner, masked, n_outer, n_inner = CASES[name]
+    _say(f"[parity] {name} {H}x{W} {fid}/{inner} mask={masked} {n_outer}x{n_inner}")
+    f, mask = _input(name, H, W, masked, fid)
+    plan, state, stats, _, _ = run_gpu(f, alpha, np.array(rc), np.array(cc), mask=mask, fidelity=fid, inner=inner,
+                                       n_outer=n_outer, n_inner=n_inner, schedule="stream")
+    o = oracle_for(f, alpha, rc, cc, fidelity=fid, inner=inner, mask=mask, n_inner=n_inner)
+    o.run(n_outer)
+    errs = compare(gpu_image_state(plan, state), o)
+    _say(f"  errors {errs}")
+
+
+def test_parity_config1_with_diagnostics():
+    c = synth.config1()
+    _say("[parity] config1 64x64 2x2 100x10 with diagnostics")
+    plan, state, stats, _, _ = run_gpu(c.f, c.alpha, c.row_cuts, c.col_cuts, n_outer=c.n_outer, n_inner=c.n_inner,
+                                       diag_every=10, schedule="stream")
+    o = oracle_for(c.f, c.alpha, c.row_cuts, c.col_cuts, n_inner=c.n_inner)
+    ost = o.run(c.n_outer, diag_every=10)
+    errs = compare(gpu_image_state(plan, state), o)
+    _say(f"  errors {errs}")
+    assert stats.shape == (1, 10, 5)
+    g = stats[0]
+    assert np.array_equal(g[:, 0], ost[:, 0])
+    # J, D to 1e-6 relative; the gap and |Bp| relative to the energy scale
+    for q in (1, 2):
+        assert np.max(np.abs(g[:, q] - ost[:, q]) / np.abs(ost[:, q])) <= 1e-6
+    assert np.max(np.abs(g[:, 3] - ost[:, 3])) <= 1e-6 * np.abs(ost[:, 1]).max()
+    assert np.max(np.abs(g[:, 4] - ost[:, 4]) / np.maximum(ost[:, 4], 1e-3)) <= 1e-4
+    assert (g[:, 3] >= -1e-6 * np.abs(g[:, 1])).all()
+
+
+def test_parity_config2_full():
+    """2048 x 2048, 16 x 16 subdomains of 128 x 128, alpha 8, 500 outer x 5 FISTA."""
+    c = synth.config2()
+    _say("[parity] config2 2048^2 16x16 500x5 (GPU)")
+    plan, state, _, _, _ = run_gpu(c.f, c.alpha, c.row_cuts, c.col_cuts, n_outer=c.n_outer, n_inner=c.n_inner)
+    g = gpu_image_state(plan, state)
+    _say("[parity] config2 oracle (CPU)")
+    o = oracle_for(c.f, c.alpha, c.row_cuts, c.col_cuts, n_inner=c.n_inner)
+    o.run(c.n_outer)
+    errs = compare(g, o)
+    _say(f"  errors {errs}")
+
+
+def test_parity_config3_reduced():
+    """TV-L1 + inpainting mask, 2000 x 3000 (H x W), 13 x 20 uneven subdomains, CP2,
+    200 of the 1000 outer steps."""
+    c = synth.config3(n_outer=200)
+    _say("[parity] config3 2000x3000 13x20 TV-L1+mask 200x5 (GPU)")
+    plan, state, _, _, _ = run_gpu(c.f, c.alpha, c.row_cuts, c.col_cuts, mask=c.mask, fidelity="L1", inner="CP2",
+                                   n_outer=c.n_outer, n_inner=c.n_inner)
+    g = gpu_image_state(plan, state)
+    _say("[parity] config3 oracle (CPU)")
+    o = oracle_for(c.f, c.alpha, c.row_cuts, c.col_cuts, fidelity="L1", inner="CP2", mask=c.mask, n_inner=c.n_inner)
+    o.run(c.n_outer)
+    errs = compare(g, o)
+    _say(f"  errors {errs}")
+
+
+def test_deterministic_and_resume_bitwise():
+    c = synth.config1()
+    kw = dict(n_inner=c.n_inner, schedule="stream")
+    p1, s1, _, f, _ = run_gpu(c.f, c.alpha, c.row_cuts, c.col_cuts, n_outer=40, **kw)
+    p2, s2, _, _, _ = run_gpu(c.f, c.alpha, c.row_cuts, c.col_cuts, n_outer=40, **kw)
+    for k in ("u", "p1", "p2", "lam"):
+        assert torch.equal(s1[k], s2[k])
+    # 15 steps, then 25 more from the returned state, equals 40 in one go
+    from paper_1901_00682_amd import dtvdd
+    H, W = c.f.shape
+    pa = dtvdd.Plan([dtvdd.Image(H, W, c.row_cuts, c.col_cuts, c.alpha)], n_outer=15, **kw)
+    st, _ = pa.solve(f)
+    pb = dtvdd.Plan([dtvdd.Image(H, W, c.row_cuts, c.col_cuts, c.alpha)], n_outer=25, warm_start=True, **kw)
+    st, _ = pb.solve(f, state=st)
+    torch.cuda.synchronize()
+    for k in ("u", "p1", "p2", "lam"):
+        assert torch.equal(s1[k], st[k]), k
+
+
+@pytest.mark.parametrize("inner", ["FISTA", "CP2"])
+def test_batched_equals_single(inner):
+    """Several images of different sizes in one plan give bitwise the same result
+    as each image alone (the kernels are per-pixel identical)."""
+    from paper_1901_00682_amd import dtvdd
+    rng = np.random.default_rng(3)
+    shapes = [(40, 70), (97, 33), (64, 64)]
+    imgs, fs = [], []
+    for k, (H, W) in enumerate(shapes):
+        f = (synth.shapes(H, W, rng) + synth.gaussian((H, W), 0.1, rng)).astype(np.float32)
+        fs.append(f)
+        imgs.append(dtvdd.Image(H, W, synth.tile_cuts(H, 32), synth.tile_cuts(W, 32), 4.0 + 3 * k))
+    kw = dict(n_outer=20, n_inner=5, inner=inner, schedule="stream")
+    plan = dtvdd.Plan(imgs, **kw)
+    fcat = torch.from_numpy(np.concatenate([f.ravel() for f in fs])).cuda()
+    st, _ = plan.solve(fcat)
+    torch.cuda.synchronize()
+    for k, im in enumerate(imgs):
+        single = dtvdd.Plan([im], **kw)
+        s1, _ = single.solve(torch.from_numpy(fs[k].ravel()).cuda())
+        torch.cuda.synchronize()
+        a, b = gpu_image_state(plan, st, k), gpu_image_state(single, s1, 0)
+        for q in a:
+            assert np.array_equal(a[q], b[q]), (k, q)
+        o = oracle_for(fs[k], im.alpha, im.row_cuts, im.col_cuts, inner=inner, n_inner=5)
+        o.run(20)
+        compare(a, o)
+
+
+def test_nonfinite_input_is_reported():
+    from paper_1901_00682_amd import dtvdd
+    f = np.random.default_rng(0).uniform(size=(32, 32)).astype(np.float32)
+    f[5, 7] = np.nan
+    with pytest.raises(dtvdd.DtvError) as ei:
+        run_gpu(f, 8.0, np.array([0, 16, 32]), np.array([0, 16, 32]), n_outer=3, n_inner=2, diag_every=1)
+    assert ei.value.code == dtvdd.DTV_ENONFINITE
+
+
+def test_kernel_timing_reports_launches():
+    c = synth.config1()
+    plan, state, _, _, _ = run_gpu(c.f, c.alpha, c.row_cuts, c.col_cuts, n_outer=5, n_inner=4, time_kernels=True,
+                                   schedule="stream")
+    kt = plan.kernel_time()
+    assert kt["launches"] == 20 and kt["avg_ms"] > 0 and kt["bytes_per_launch"] > 0
