@@ -64,6 +64,7 @@ struct dtv_dd_plan {
     std::vector<int> h_info;
     std::vector<StreamTile> h_tiles;
     std::vector<SubTile> h_subs;
+    bool fused_ok = false;  // every subdomain fits the fused kernel
 
     // workspace layout (byte offsets)
     size_t off_imgs = 0, off_info = 0, off_tiles = 0, off_subs = 0, off_buf[3] = {0, 0, 0}, off_u2 = 0,
@@ -84,6 +85,7 @@ struct dtv_dd_plan {
     }
 
     const ImgDev *d_imgs() const { return (const ImgDev *)(ws + off_imgs); }
+    const SubTile *d_subs() const { return (const SubTile *)(ws + off_subs); }
     const int *d_info() const { return (const int *)(ws + off_info); }
     const StreamTile *d_tiles() const { return (const StreamTile *)(ws + off_tiles); }
     float *buf1(int k) const { return (float *)(ws + off_buf[k]); }
@@ -138,7 +140,6 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
     if (p.save_for_backward && (p.inner != DTV_INNER_FISTA || p.ckpt_every < 1))
         return fail(DTV_EINVAL, "save_for_backward needs FISTA and ckpt_every >= 1");
     if (p.schedule < DTV_SCHED_AUTO || p.schedule > DTV_SCHED_FUSED) return fail(DTV_EINVAL, "unknown schedule");
-    if (p.schedule == DTV_SCHED_FUSED) return fail(DTV_EINVAL, "the fused schedule is not available in this build");
 
     dtv_dd_plan *pl = new dtv_dd_plan();
     pl->prm = p;
@@ -211,9 +212,21 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
         g.inv_alpha = (float)(1.0 / h.alpha);
         g.invL = (float)(1.0 / L);
         g.a_keep = (float)(1.0 - 1.0 / (L * tau));
+        g.kL = (float)(1.0 / (h.alpha * L));
         pl->h_imgs.push_back(g);
         for (int i0 = 0; i0 < h.H; i0 += pl->rows)
             for (int j0 = 0; j0 < h.W; j0 += kStreamCols) pl->h_tiles.push_back(StreamTile{b, i0, j0, 0});
+        for (int r = 0; r < h.ny; ++r)
+            for (int c = 0; c < h.nx; ++c)
+                pl->h_subs.push_back(SubTile{b, r, c, h.rcut[r], h.ccut[c], h.rcut[r + 1] - h.rcut[r],
+                                             h.ccut[c + 1] - h.ccut[c], 0});
+    }
+    pl->fused_ok = p.inner == DTV_INNER_FISTA && p.n_inner <= kMaxFusedInner;
+    for (const SubTile &st : pl->h_subs)
+        if (st.h > kFusedMax || st.w > kFusedMax) pl->fused_ok = false;
+    if (p.schedule == DTV_SCHED_FUSED && !pl->fused_ok) {
+        delete pl;
+        return fail(DTV_EINVAL, "the fused schedule needs FISTA, n_inner <= 64 and subdomains of at most 128 x 128");
     }
 
     // workspace layout
@@ -226,13 +239,15 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
     pl->off_imgs = take(sizeof(ImgDev) * pl->h_imgs.size());
     pl->off_info = take(sizeof(int) * pl->h_info.size());
     pl->off_tiles = take(sizeof(StreamTile) * pl->h_tiles.size());
+    pl->off_subs = take(sizeof(SubTile) * pl->h_subs.size());
     for (int k = 0; k < 3; ++k) pl->off_buf[k] = take(sizeof(float) * (size_t)(pl->tot_p1 + pl->tot_p2));
     pl->off_u2 = take(p.inner == DTV_INNER_CP2 ? sizeof(float) * (size_t)pl->tot_px : 0);
     pl->diag_nblk = diag_blocks_per_image(pl->maxH, pl->maxW);
     pl->off_part = take(sizeof(double) * 6 * (size_t)pl->diag_nblk * n_images);
     pl->off_dout = take(sizeof(double) * 6 * (size_t)n_images);
     pl->ws_bytes = off;
-    pl->schedule = DTV_SCHED_STREAM;
+    pl->schedule = p.schedule == DTV_SCHED_STREAM ? DTV_SCHED_STREAM
+                 : (p.schedule == DTV_SCHED_FUSED || pl->fused_ok) ? DTV_SCHED_FUSED : DTV_SCHED_STREAM;
     *out = pl;
     g_err.clear();
     return DTV_OK;
@@ -275,6 +290,8 @@ extern "C" int dtv_dd_bind_workspace(dtv_dd_plan *pl, void *d_ws, size_t bytes)
     HIP_TRY(hipMemcpy(ws + pl->off_tiles, pl->h_tiles.data(), sizeof(StreamTile) * pl->h_tiles.size(),
                       hipMemcpyHostToDevice),
             "upload work list");
+    HIP_TRY(hipMemcpy(ws + pl->off_subs, pl->h_subs.data(), sizeof(SubTile) * pl->h_subs.size(), hipMemcpyHostToDevice),
+            "upload subdomain list");
     // rotation buffers start at zero so that their boundary (non-dof) edges are 0
     for (int k = 0; k < 3; ++k)
         HIP_TRY(hipMemset(ws + pl->off_buf[k], 0, sizeof(float) * (size_t)(pl->tot_p1 + pl->tot_p2)), "clear buffers");
@@ -384,25 +401,27 @@ struct Timer {
 extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_mask, float *d_u, float *d_p1,
                             float *d_p2, float *d_lambda, double *h_stats, int32_t *n_rows, void *stream)
 {
-    if (!pl || !d_f || !d_u || !d_p1 || !d_p2 || !d_lambda) return fail(DTV_EINVAL, "null argument");
+    if (!pl || !d_f || !d_u || !d_p1 || !d_p2) return fail(DTV_EINVAL, "null argument");
+    if (!d_lambda && pl->tot_lam > 0) return fail(DTV_EINVAL, "null argument (lambda)");
     const dtv_dd_params &P = pl->prm;
     if (P.has_mask && !d_mask) return fail(DTV_EINVAL, "mask expected (has_mask = 1)");
     if (!pl->ws) return fail(DTV_ENOWS, "no workspace bound");
     hipStream_t s = (hipStream_t)stream;
     const uint8_t *mask = P.has_mask ? d_mask : nullptr;
     const bool cp2 = P.inner == DTV_INNER_CP2;
+    const bool fused = pl->schedule == DTV_SCHED_FUSED;
     const int K = P.n_inner;
 
     if (!P.warm_start) {
         HIP_TRY(hipMemsetAsync(d_p1, 0, sizeof(float) * (size_t)pl->tot_p1, s), "clear p1");
         HIP_TRY(hipMemsetAsync(d_p2, 0, sizeof(float) * (size_t)pl->tot_p2, s), "clear p2");
-        HIP_TRY(hipMemsetAsync(d_lambda, 0, sizeof(float) * (size_t)pl->tot_lam, s), "clear lambda");
+        if (pl->tot_lam > 0) HIP_TRY(hipMemsetAsync(d_lambda, 0, sizeof(float) * (size_t)pl->tot_lam, s), "clear lambda");
         if (cp2) HIP_TRY(hipMemcpyAsync(d_u, d_f, sizeof(float) * (size_t)pl->tot_px, hipMemcpyDeviceToDevice, s), "u = f");
     }
     HIP_TRY(launch_zero_boundary(pl->d_imgs(), pl->n, pl->maxH, pl->maxW, d_p1, d_p2, s), "zero boundary");
 
     // step parameters, computed in double precision on the host
-    std::vector<float> beta(K + 1, 0.0f);  // FISTA momentum of step k (1-based)
+    std::vector<float> beta(K + 1, 0.0f);  // FISTA momentum of step k (1-based); 0 for k = 1, 2
     {
         std::vector<double> t(K + 2, 1.0);
         for (int m = 1; m <= K; ++m) t[m + 1] = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t[m] * t[m]));
@@ -420,6 +439,7 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
         }
     }
 
+    // edge buffers: 0 = the caller's p~, 1..3 = workspace
     EdgeBuf bufs[4] = {{d_p1, d_p2}, {pl->buf1(0), pl->buf2(0)}, {pl->buf1(1), pl->buf2(1)}, {pl->buf1(2), pl->buf2(2)}};
     int base = 0;
     float *u_cur = d_u;  // CP2: current u buffer (d_u or the workspace copy)
@@ -428,6 +448,18 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
     int nrow = 0;
     bool nonfinite = false;
     std::vector<double> drow(4 * pl->n);
+
+    FusedArgs fa{};
+    if (fused) {
+        fa.imgs = pl->d_imgs();
+        fa.subs = pl->d_subs();
+        fa.lam = d_lambda;
+        fa.f = d_f;
+        fa.tau = (float)P.tau;
+        fa.inv_tau = (float)(1.0 / P.tau);
+        fa.n_inner = K;
+        for (int k = 1; k <= K; ++k) fa.beta[k] = beta[k];
+    }
 
     auto emit_stats = [&](int step, const float *u, const EdgeBuf &b) -> int {
         bool nf = false;
@@ -449,25 +481,47 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
         HIP_TRY(launch_lambda(pl->d_imgs(), pl->n, pl->max_nlam, pl->d_info(), bufs[base].p1, bufs[base].p2, d_lambda,
                               (float)P.sigma, s),
                 "lambda update");
-        int sc[3], q = 0;
-        for (int k = 0; k < 4; ++k)
-            if (k != base) sc[q++] = k;
-        // (a2)+(a3) local solves; the anchor phat is formed on the fly from bufs[base] and lambda
-        for (int k = 1; k <= K; ++k) {
-            const int ia = k == 1 ? base : sc[(k - 2) % 3];
-            const int ib = k >= 3 ? sc[(k - 3) % 3] : base;
-            const int io = sc[(k - 1) % 3];
+        // (a2)+(a3) local solves; the anchor phat is formed on the fly from p~^n and lambda
+        if (fused) {
+            const int out = base == 0 ? 1 : 0;
+            fa.base1 = bufs[base].p1; fa.base2 = bufs[base].p2;
+            fa.out1 = bufs[out].p1; fa.out2 = bufs[out].p2;
             int rc = tm.begin();
             if (rc != DTV_OK) return rc;
-            if (!cp2) {
+            HIP_TRY(launch_fused_fista(fa, (int)pl->h_subs.size(), s), "fused FISTA");
+            rc = tm.end();
+            if (rc != DTV_OK) return rc;
+            base = out;
+        } else if (!cp2) {
+            // x_k lives in rot[k % 3]; c' in workspace buffer 3
+            int rot[3] = {base, 0, 0}, q = 1;
+            for (int k = 0; k < 3; ++k)
+                if (k != base) rot[q++] = k;
+            for (int k = 1; k <= K; ++k) {
+                const int ia = rot[(k - 1) % 3], ib = rot[(k + 1) % 3], io = rot[k % 3];
                 FistaStepArgs a{};
                 a.imgs = pl->d_imgs(); a.tiles = pl->d_tiles(); a.ntiles = (int)pl->h_tiles.size(); a.info = pl->d_info();
                 a.xa1 = bufs[ia].p1; a.xa2 = bufs[ia].p2; a.xb1 = bufs[ib].p1; a.xb2 = bufs[ib].p2;
-                a.base1 = bufs[base].p1; a.base2 = bufs[base].p2; a.lam = d_lambda; a.f = d_f;
+                a.lam = d_lambda; a.f = d_f;
+                a.c1 = bufs[3].p1; a.c2 = bufs[3].p2;
                 a.out1 = bufs[io].p1; a.out2 = bufs[io].p2;
                 a.beta = beta[k]; a.tau = (float)P.tau; a.inv_tau = (float)(1.0 / P.tau);
-                HIP_TRY(launch_fista_step(a, k >= 3, pl->rows, s), "FISTA step");
-            } else {
+                const int mode = k == 1 ? kFistaFirst : (k == 2 ? kFistaPlain : kFistaMomentum);
+                int rc = tm.begin();
+                if (rc != DTV_OK) return rc;
+                HIP_TRY(launch_fista_step(a, mode, pl->rows, s), "FISTA step");
+                rc = tm.end();
+                if (rc != DTV_OK) return rc;
+            }
+            base = rot[K % 3];
+        } else {
+            int sc[3], q = 0;
+            for (int k = 0; k < 4; ++k)
+                if (k != base) sc[q++] = k;
+            for (int k = 1; k <= K; ++k) {
+                const int ia = k == 1 ? base : sc[(k - 2) % 3];
+                const int ib = k >= 3 ? sc[(k - 3) % 3] : base;
+                const int io = sc[(k - 1) % 3];
                 const int it = k - 1;
                 Cp2StepArgs a{};
                 a.imgs = pl->d_imgs(); a.tiles = pl->d_tiles(); a.ntiles = (int)pl->h_tiles.size(); a.info = pl->d_info();
@@ -481,13 +535,15 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
                 a.c_keep = (float)(P.tau / (P.tau + tk[it]));
                 a.c_anchor = (float)(tk[it] / (P.tau + tk[it]));
                 a.fidelity = P.fidelity;
+                int rc = tm.begin();
+                if (rc != DTV_OK) return rc;
                 HIP_TRY(launch_cp2_step(a, it >= 1, pl->rows, s), "CP2 step");
+                rc = tm.end();
+                if (rc != DTV_OK) return rc;
                 u_cur = u_next;
             }
-            rc = tm.end();
-            if (rc != DTV_OK) return rc;
+            base = sc[(K - 1) % 3];
         }
-        base = sc[(K - 1) % 3];
         const bool last = n == P.n_outer - 1;
         if (P.diag_every > 0 && ((n + 1) % P.diag_every == 0 || last)) {
             const float *u = u_cur;
@@ -535,15 +591,17 @@ extern "C" int dtv_dd_kernel_time(const dtv_dd_plan *pl, double *avg_ms, int64_t
     if (avg_ms) *avg_ms = pl->t_ms;
     if (launches) *launches = pl->t_count;
     const bool cp2 = pl->prm.inner == DTV_INNER_CP2;
-    if (name) *name = cp2 ? "k_cp2_step" : "k_fista_step";
+    const bool fused = pl->schedule == DTV_SCHED_FUSED;
+    if (name) *name = fused ? "k_fused_fista" : (cp2 ? "k_cp2_step" : "k_fista_step");
     if (bytes_per_launch) {
-        // Algorithmic HBM bytes of one inner-step launch, averaged over the n_inner
-        // launches of an outer step.  E = edge dofs (torn), N = pixels.
-        //   FISTA step 1: read x_0 (= anchor base) and f, write x_1            4 (2E + N)
-        //   FISTA step 2: read x_1, base, f, write x_2 (no momentum yet)       4 (3E + N)
-        //   FISTA step k >= 3: read x_{k-1}, x_{k-2}, base, f, write x_k      4 (4E + N)
-        //   CP2 step 1: read x_0, u, f (+ mask), write x_1, u                  4 (2E + 3N) + mask
-        //   CP2 step k >= 2: read x_{k-1}, x_{k-2}, base, u, f (+ mask), write 4 (4E + 3N) + mask
+        // Algorithmic HBM bytes of one timed launch (E = edge dofs of the torn
+        // p~, N = pixels, 4 bytes each), averaged over the launches of an outer step.
+        //   fused: read p~^n and f, write p~^(n+1)                                 4 (2E + N)
+        //   streaming FISTA step 1: read x_0 and f, write c' and x_1                4 (3E + N)
+        //   streaming FISTA step 2: read x_1 and c', write x_2                      4 (3E)
+        //   streaming FISTA step k >= 3: read x_{k-1}, x_{k-2}, c', write x_k       4 (4E)
+        //   CP2 step 1: read x_0, u, f (+ mask bytes), write x_1, u                 4 (2E + 3N) + mask
+        //   CP2 step k >= 2: read x_{k-1}, x_{k-2}, anchor base, u, f (+ mask), write 4 (4E + 3N) + mask
         double E = 0.0, N = 0.0;
         for (const ImgHost &h : pl->imgs) {
             E += (double)(h.H + h.ny) * h.W + (double)h.H * (h.W + h.nx);
@@ -552,11 +610,15 @@ extern "C" int dtv_dd_kernel_time(const dtv_dd_plan *pl, double *avg_ms, int64_t
         const int K = pl->prm.n_inner;
         const double mb = pl->prm.has_mask ? N : 0.0;
         double tot = 0.0;
-        for (int k = 1; k <= K; ++k) {
-            if (cp2) tot += (k == 1 ? 4.0 * (2 * E + 3 * N) : 4.0 * (4 * E + 3 * N)) + mb;
-            else tot += k == 1 ? 4.0 * (2 * E + N) : (k == 2 ? 4.0 * (3 * E + N) : 4.0 * (4 * E + N));
+        if (fused) {
+            *bytes_per_launch = 4.0 * (2 * E + N);
+        } else {
+            for (int k = 1; k <= K; ++k) {
+                if (cp2) tot += (k == 1 ? 4.0 * (2 * E + 3 * N) : 4.0 * (4 * E + 3 * N)) + mb;
+                else tot += k == 1 ? 4.0 * (3 * E + N) : (k == 2 ? 4.0 * (3 * E) : 4.0 * (4 * E));
+            }
+            *bytes_per_launch = tot / K;
         }
-        *bytes_per_launch = tot / K;
     }
     return DTV_OK;
 }

@@ -21,8 +21,9 @@ struct ImgDev {
     long long ccut;      // offset of nx+1 column cuts
     float alpha, inv_alpha;
     float invL;          // FISTA step 1/L, L = 8/alpha + 1/tau
-    float a_keep;        // FISTA: 1 - 1/(L tau)  (coefficient of y in the fused update)
-    float pad0, pad1;
+    float a_keep;        // FISTA: 1 - 1/(L tau), the weight of y in the update
+    float kL;            // FISTA: 1/(alpha L), the weight of the divergence difference
+    float pad0;
 };
 
 // Row / column info word: subdomain index << 2 | first << 0 | last << 1.
@@ -45,21 +46,43 @@ struct SubTile {
 
 constexpr int kStreamCols = 63;   // output columns per wave
 constexpr int kFusedMax = 128;    // largest subdomain side handled by the fused kernel
+constexpr int kMaxFusedInner = 64;  // largest n_inner of the fused kernel
+
+// FISTA step of the streaming schedule.  The local gradient step
+//   z = y - (1/L) [div_s^*(f + div_s y / alpha) + (y - phat)/tau]
+// is evaluated as  z = a_keep y + c' - kL (d_before - d_after)  with
+// d = div_s y per pixel and the per-edge constant
+//   c' = (phat / tau - (f_before - f_after)) / L,
+// which the first step of every outer iteration computes (from p~^n, lambda
+// and f) and stores; later steps read it.  Same formulas as the fused kernel.
+enum FistaMode { kFistaFirst = 0, kFistaPlain = 1, kFistaMomentum = 2 };
 
 struct FistaStepArgs {
     const ImgDev *imgs;
     const StreamTile *tiles;
     int ntiles;
     const int *info;
-    const float *xa1, *xa2;   // x_{k-1}
+    const float *xa1, *xa2;   // x_{k-1} (first step: x_0 = p~^n)
     const float *xb1, *xb2;   // x_{k-2} (momentum steps only)
-    const float *base1, *base2; // p~^n (anchor base)
-    const float *lam;         // lambda state
-    const float *f;
+    const float *lam;         // lambda state (first step)
+    const float *f;           // image (first step)
+    float *c1, *c2;           // c' (written by the first step, read by the others)
     float *out1, *out2;       // x_k
     float beta;               // momentum coefficient of this step
     float tau;                // outer tau (anchor p~ -/+ tau lambda)
     float inv_tau;
+};
+
+struct FusedArgs {
+    const ImgDev *imgs;
+    const SubTile *subs;
+    const float *base1, *base2;  // p~^n
+    const float *lam;
+    const float *f;
+    float *out1, *out2;          // p~^(n+1)
+    float tau, inv_tau;
+    int n_inner;
+    float beta[kMaxFusedInner + 1];  // beta[k], k = 1..n_inner
 };
 
 struct Cp2StepArgs {
@@ -87,7 +110,7 @@ struct Cp2StepArgs {
 // Kernel launchers (kernels.hip).
 hipError_t launch_lambda(const ImgDev *imgs, int nimg, int max_nlam, const int *info, const float *p1,
                          const float *p2, float *lam, float sigma, hipStream_t s);
-hipError_t launch_fista_step(const FistaStepArgs &a, bool momentum, int rows, hipStream_t s);
+hipError_t launch_fista_step(const FistaStepArgs &a, int mode, int rows, hipStream_t s);
 hipError_t launch_cp2_step(const Cp2StepArgs &a, bool extrapolate, int rows, hipStream_t s);
 hipError_t launch_u_from_p(const ImgDev *imgs, int nimg, int maxH, int maxW, const int *info, const float *p1,
                            const float *p2, const float *f, float *u, hipStream_t s);
@@ -99,8 +122,6 @@ hipError_t launch_diag(const ImgDev *imgs, int nimg, int maxH, int maxW, const i
                        const float *p2, const float *f, const float *u, const uint8_t *mask, int fidelity,
                        double *partials, int nblk_per_img, double *out, hipStream_t s);
 int diag_blocks_per_image(int maxH, int maxW);
-hipError_t launch_fused_fista(const ImgDev *imgs, const SubTile *subs, int nsub, const float *base1,
-                              const float *base2, const float *lam, const float *f, float *out1, float *out2,
-                              const float *betas, int n_inner, float tau, float inv_tau, hipStream_t s);
+hipError_t launch_fused_fista(const FusedArgs &a, int nsub, hipStream_t s);
 
 }  // namespace dtv

@@ -17,19 +17,9 @@
 // (the library is built with -ffp-contract=off so that the streaming and
 // fused schedules round identically).
 #include "dtvdd_internal.h"
+#include "fista_ops.h"
 
 namespace dtv {
-
-// Workgroup ids are dealt to the 8 XCDs round-robin; remap them so that
-// consecutive work items (which share halo rows in L2) run on one XCD.
-__device__ __forceinline__ int xcd_remap(int b, int n)
-{
-    const int xcd = b & 7, idx = b >> 3;
-    const int per = n >> 3, rem = n & 7;
-    return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
-}
-
-__device__ __forceinline__ float clamp1(float z) { return __builtin_amdgcn_fmed3f(z, -1.0f, 1.0f); }
 
 // ---------------------------------------------------------------------------
 // (a1) multiplier update, one thread per interface dof:
@@ -71,17 +61,15 @@ hipError_t launch_lambda(const ImgDev *imgs, int nimg, int max_nlam, const int *
 }
 
 // ---------------------------------------------------------------------------
-// (a3) one projected-FISTA step on every local dual problem (ROF):
-//   y = x_{k-1} + beta (x_{k-1} - x_{k-2})
-//   v = f + div_s y / alpha                       (per pixel)
-//   g = div_s^* v + (y - phat) / tau              (per dof edge; one-sided on
-//                                                  interface copies)
-//   x_k = clamp(y - g / L, -1, 1)
-// with phat = p~^n -/+ tau lambda on the s / t copies of interface edges
-// (Algorithm 1, phat = p~ - tau B^* lambda) and p~^n elsewhere.
-template <int R, bool MOM>
+// (a3) one projected-FISTA step on every local dual problem (ROF), in the
+// form of fista_ops.h.  The first step of an outer iteration (MODE first)
+// starts from y = x_0 = p~^n and also builds c' from the anchor
+// phat = p~^n -/+ tau lambda on the s / t copies of interface edges
+// (Algorithm 1: phat = p~ - tau B^* lambda) and from f; later steps read c'.
+template <int R, int MODE>
 __global__ __launch_bounds__(64) void k_fista_step(FistaStepArgs a)
 {
+    constexpr bool FIRST = MODE == kFistaFirst, MOM = MODE == kFistaMomentum;
     const int t = xcd_remap(blockIdx.x, gridDim.x);
     const StreamTile tile = a.tiles[t];
     const ImgDev im = a.imgs[tile.img];
@@ -98,36 +86,35 @@ __global__ __launch_bounds__(64) void k_fista_step(FistaStepArgs a)
 
     const float *xa1 = a.xa1 + im.p1, *xa2 = a.xa2 + im.p2;
     const float *xb1 = MOM ? a.xb1 + im.p1 : nullptr, *xb2 = MOM ? a.xb2 + im.p2 : nullptr;
-    const float *b1 = a.base1 + im.p1, *b2 = a.base2 + im.p2;
+    float *c1 = a.c1 + im.p1, *c2 = a.c2 + im.p2;
     const float *lam = a.lam + im.lam;
     const float *f = a.f + im.px;
     float *o1 = a.out1 + im.p1, *o2 = a.out2 + im.p2;
-    const float beta = a.beta, ia = im.inv_alpha, invL = im.invL, tau = a.tau, itau = a.inv_tau;
+    const float beta = a.beta, tau = a.tau, itau = a.inv_tau;
+    const float invL = im.invL, ak = im.a_keep, kL = im.kL;
 
     auto y1 = [&](long long idx) -> float {
-        const float x = xa1[idx];
-        if constexpr (MOM) return fmaf(beta, x - xb1[idx], x);
-        return x;
+        if constexpr (MOM) return fista_y(xa1[idx], xb1[idx], beta);
+        return xa1[idx];
     };
     auto y2 = [&](long long idx) -> float {
-        const float x = xa2[idx];
-        if constexpr (MOM) return fmaf(beta, x - xb2[idx], x);
-        return x;
+        if constexpr (MOM) return fista_y(xa2[idx], xb2[idx], beta);
+        return xa2[idx];
     };
 
     const int i0 = tile.i0;
     const int iend = min(i0 + R, H);
-    float v_up = 0.0f, y_carry = 0.0f;
+    float d_up = 0.0f, y_carry = 0.0f, f_up = 0.0f;
     bool have = false;
     if (i0 > 0 && !info_first(a.info[im.rinfo + i0])) {
-        // halo row: v of the pixel above the strip, same subdomain
+        // halo row: divergence of the pixel above the strip, same subdomain
         const int i = i0 - 1;
         const int top = i + info_sub(a.info[im.rinfo + i]);
         if (colok) {
             const float yt = y1(top * P1 + j), yb = y1((top + 1) * P1 + j);
-            const float yl = y2(i * P2 + left), yr = y2(i * P2 + left + 1);
-            v_up = fmaf((yb - yt) + (yr - yl), ia, f[(long long)i * W + j]);
+            d_up = div4(yt, yb, y2(i * P2 + left), y2(i * P2 + left + 1));
             y_carry = yb;
+            if constexpr (FIRST) f_up = f[(long long)i * W + j];
         }
         have = true;
     }
@@ -138,65 +125,97 @@ __global__ __launch_bounds__(64) void k_fista_step(FistaStepArgs a)
         const long long top = i + rs;
         if (rfirst) {
             have = false;
-            v_up = 0.0f;
+            d_up = 0.0f;
+            f_up = 0.0f;
         }
-        float v = 0.0f, yt = 0.0f, yb = 0.0f, yl = 0.0f, yr = 0.0f;
+        float d = 0.0f, yt = 0.0f, yb = 0.0f, yl = 0.0f, yr = 0.0f, fv = 0.0f;
         if (colok) {
             yt = have ? y_carry : y1(top * P1 + j);
             yb = y1((top + 1) * P1 + j);
             yl = y2(i * P2 + left);
             yr = y2(i * P2 + left + 1);
-            v = fmaf((yb - yt) + (yr - yl), ia, f[(long long)i * W + j]);
+            d = div4(yt, yb, yl, yr);
+            if constexpr (FIRST) fv = f[(long long)i * W + j];
         }
-        float v_left = __shfl_up(v, 1, 64);
-        if (cfirst) v_left = 0.0f;
+        float d_left = __shfl_up(d, 1, 64);
+        float f_left = 0.0f;
+        if constexpr (FIRST) f_left = __shfl_up(fv, 1, 64);
+        if (cfirst) {
+            d_left = 0.0f;
+            f_left = 0.0f;
+        }
         if (outlane) {
             if (i > 0) {  // edge above the pixel (interior, or t copy of an interface)
-                float anchor = b1[top * P1 + j];
-                if (rfirst) anchor = fmaf(tau, lam[(long long)(rs - 1) * W + j], anchor);
-                const float g = fmaf(yt - anchor, itau, v_up - v);
-                o1[top * P1 + j] = clamp1(fmaf(-g, invL, yt));
+                float c;
+                if constexpr (FIRST) {
+                    float anchor = yt;
+                    if (rfirst) anchor = fmaf(tau, lam[(long long)(rs - 1) * W + j], anchor);
+                    c = fista_cprime(anchor, f_up, fv, itau, invL);
+                    c1[top * P1 + j] = c;
+                } else {
+                    c = c1[top * P1 + j];
+                }
+                o1[top * P1 + j] = fista_edge(yt, d_up, d, c, ak, kL);
             }
             if (j > 0) {  // edge left of the pixel
-                float anchor = b2[i * P2 + left];
-                if (cfirst) anchor = fmaf(tau, lam[im.nlh + (long long)(cs - 1) * H + i], anchor);
-                const float g = fmaf(yl - anchor, itau, v_left - v);
-                o2[i * P2 + left] = clamp1(fmaf(-g, invL, yl));
+                float c;
+                if constexpr (FIRST) {
+                    float anchor = yl;
+                    if (cfirst) anchor = fmaf(tau, lam[im.nlh + (long long)(cs - 1) * H + i], anchor);
+                    c = fista_cprime(anchor, f_left, fv, itau, invL);
+                    c2[i * P2 + left] = c;
+                } else {
+                    c = c2[i * P2 + left];
+                }
+                o2[i * P2 + left] = fista_edge(yl, d_left, d, c, ak, kL);
             }
             if (rlast && i < H - 1) {  // s copy below the last row of the subdomain
-                const float anchor = fmaf(-tau, lam[(long long)rs * W + j], b1[(top + 1) * P1 + j]);
-                const float g = fmaf(yb - anchor, itau, v);
-                o1[(top + 1) * P1 + j] = clamp1(fmaf(-g, invL, yb));
+                float c;
+                if constexpr (FIRST) {
+                    c = fista_cprime(fmaf(-tau, lam[(long long)rs * W + j], yb), fv, 0.0f, itau, invL);
+                    c1[(top + 1) * P1 + j] = c;
+                } else {
+                    c = c1[(top + 1) * P1 + j];
+                }
+                o1[(top + 1) * P1 + j] = fista_edge(yb, d, 0.0f, c, ak, kL);
             }
             if (clast && j < W - 1) {  // s copy right of the last column
-                const float anchor = fmaf(-tau, lam[im.nlh + (long long)cs * H + i], b2[i * P2 + left + 1]);
-                const float g = fmaf(yr - anchor, itau, v);
-                o2[i * P2 + left + 1] = clamp1(fmaf(-g, invL, yr));
+                float c;
+                if constexpr (FIRST) {
+                    c = fista_cprime(fmaf(-tau, lam[im.nlh + (long long)cs * H + i], yr), fv, 0.0f, itau, invL);
+                    c2[i * P2 + left + 1] = c;
+                } else {
+                    c = c2[i * P2 + left + 1];
+                }
+                o2[i * P2 + left + 1] = fista_edge(yr, d, 0.0f, c, ak, kL);
             }
         }
-        v_up = v;
+        d_up = d;
         y_carry = yb;
+        f_up = fv;
         have = true;
     }
 }
 
 template <int R>
-static hipError_t fista_rows(const FistaStepArgs &a, bool momentum, hipStream_t s)
+static hipError_t fista_rows(const FistaStepArgs &a, int mode, hipStream_t s)
 {
-    if (momentum)
-        hipLaunchKernelGGL((k_fista_step<R, true>), dim3(a.ntiles), dim3(64), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_fista_step<R, false>), dim3(a.ntiles), dim3(64), 0, s, a);
+    switch (mode) {
+    case kFistaFirst: hipLaunchKernelGGL((k_fista_step<R, kFistaFirst>), dim3(a.ntiles), dim3(64), 0, s, a); break;
+    case kFistaPlain: hipLaunchKernelGGL((k_fista_step<R, kFistaPlain>), dim3(a.ntiles), dim3(64), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_fista_step<R, kFistaMomentum>), dim3(a.ntiles), dim3(64), 0, s, a); break;
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_fista_step(const FistaStepArgs &a, bool momentum, int rows, hipStream_t s)
+hipError_t launch_fista_step(const FistaStepArgs &a, int mode, int rows, hipStream_t s)
 {
     if (a.ntiles <= 0) return hipSuccess;
     switch (rows) {
-    case 8: return fista_rows<8>(a, momentum, s);
-    case 16: return fista_rows<16>(a, momentum, s);
-    case 32: return fista_rows<32>(a, momentum, s);
+    case 4: return fista_rows<4>(a, mode, s);
+    case 8: return fista_rows<8>(a, mode, s);
+    case 16: return fista_rows<16>(a, mode, s);
+    case 32: return fista_rows<32>(a, mode, s);
     default: return hipErrorInvalidValue;
     }
 }

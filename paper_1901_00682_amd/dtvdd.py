@@ -182,7 +182,7 @@ class Plan:
         import torch
 
         T = self.layout(-1)
-        z = lambda n: torch.zeros(int(n), dtype=torch.float32, device=self.device)
+        z = lambda n: torch.zeros(max(int(n), 1), dtype=torch.float32, device=self.device)
         return {"u": z(T.px_off), "p1": z(T.p1_off), "p2": z(T.p2_off), "lam": z(T.lam_off)}
 
     def _stream(self, stream):

@@ -72,12 +72,41 @@ def test_parity_small(name):
     H, W, rc, cc, alpha, fid, inner, masked, n_outer, n_inner = CASES[name]
     _say(f"[parity] {name} {H}x{W} {fid}/{inner} mask={masked} {n_outer}x{n_inner}")
     f, mask = _input(name, H, W, masked, fid)
-    plan, state, stats, _, _ = run_gpu(f, alpha, np.array(rc), np.array(cc), mask=mask, fidelity=fid, inner=inner,
-                                       n_outer=n_outer, n_inner=n_inner, schedule="stream")
+    scheds = ["stream", "fused"] if inner == "FISTA" else ["stream"]
     o = oracle_for(f, alpha, rc, cc, fidelity=fid, inner=inner, mask=mask, n_inner=n_inner)
     o.run(n_outer)
-    errs = compare(gpu_image_state(plan, state), o)
-    _say(f"  errors {errs}")
+    got = {}
+    for sch in scheds:
+        plan, state, stats, _, _ = run_gpu(f, alpha, np.array(rc), np.array(cc), mask=mask, fidelity=fid,
+                                           inner=inner, n_outer=n_outer, n_inner=n_inner, schedule=sch)
+        got[sch] = gpu_image_state(plan, state)
+        errs = compare(got[sch], o)
+        _say(f"  {sch}: errors {errs}")
+    if len(got) == 2:
+        for q in got["stream"]:
+            assert np.array_equal(got["stream"][q], got["fused"][q]), q
+
+
+@pytest.mark.parametrize("K", [1, 2, 3, 4, 5, 7])
+def test_fused_equals_stream_bitwise(K):
+    """The two schedules of the FISTA local solves round identically: full
+    128 x 128 subdomains with interfaces on every side, ragged ones, and every
+    parity of the inner count."""
+    rng = np.random.default_rng(100 + K)
+    H, W = 300, 357
+    rc, cc = np.array([0, 128, 256, 300]), np.array([0, 101, 229, 357])
+    f = (synth.shapes(H, W, rng) + synth.gaussian((H, W), 0.1, rng)).astype(np.float32)
+    _say(f"[fused==stream] {H}x{W} K={K}")
+    res = {}
+    for sch in ("stream", "fused"):
+        plan, state, _, _, _ = run_gpu(f, 8.0, rc, cc, n_outer=6, n_inner=K, schedule=sch)
+        assert plan.schedule() == sch
+        res[sch] = gpu_image_state(plan, state)
+    for q in res["stream"]:
+        assert np.array_equal(res["stream"][q], res["fused"][q]), q
+    o = oracle_for(f, 8.0, rc, cc, n_inner=K)
+    o.run(6)
+    compare(res["fused"], o)
 
 
 def test_parity_config1_with_diagnostics():
@@ -105,6 +134,7 @@ def test_parity_config2_full():
     c = synth.config2()
     _say("[parity] config2 2048^2 16x16 500x5 (GPU)")
     plan, state, _, _, _ = run_gpu(c.f, c.alpha, c.row_cuts, c.col_cuts, n_outer=c.n_outer, n_inner=c.n_inner)
+    assert plan.schedule() == "fused"
     g = gpu_image_state(plan, state)
     _say("[parity] config2 oracle (CPU)")
     o = oracle_for(c.f, c.alpha, c.row_cuts, c.col_cuts, n_inner=c.n_inner)
