@@ -37,7 +37,9 @@ struct FusedLds {
     float cb[kFusedMax];             // c' of the bottom boundary edges (per column)
     float cr[kFusedMax];             // c' of the right boundary edges (per row)
     float rx[2][kFusedMax];          // right boundary edges: the two iterate slots (per row)
-    float yt[kWaves][kFusedMax];     // y on the top edges of each strip's first row
+    float yt[2][kWaves][kFusedMax];  // y on the top edges of each strip's first row, one buffer per
+                                     // step parity: a strip may start the next step while the strip
+                                     // above still reads the current row
     float dl[kWaves][kFusedMax];     // d of each strip's last row
 };
 
@@ -64,6 +66,7 @@ struct Slot {
 
 struct Ctx {
     int s, lane, ja, jb, il0, h, w;
+    int par;  // exchange-buffer parity of the current step
     bool acta, actb, lastcol_a, lastcol_b, top_bnd, bot_bnd, left_bnd, right_bnd, has_bottom;
     int rb;
     float ak, kL;
@@ -81,8 +84,8 @@ __device__ __forceinline__ void edge_below(const Ctx &c, const FusedLds &S, cons
         yb = Y.e1b[r + 1];
     } else {
         const int sn = c.s < kWaves - 1 ? c.s + 1 : c.s;
-        ya = S.yt[sn][c.ja];
-        yb = S.yt[sn][c.jb];
+        ya = S.yt[c.par][sn][c.ja];
+        yb = S.yt[c.par][sn][c.jb];
     }
 }
 
@@ -103,9 +106,24 @@ __device__ __forceinline__ void row_div(const Ctx &c, const Slot &Y, const float
 // One projected-FISTA step.  On entry X holds x_{k-1} and Y holds x_{k-2};
 // on exit Y holds x_k.  sx selects the LDS slot of the right boundary edges
 // that plays the role of X.
-__device__ __forceinline__ void fused_step(const Ctx &c, FusedLds &S, const Slot &X, Slot &Y, int sx, float beta,
-                                          bool mom)
+__device__ __forceinline__ void copy_slot(Slot &dst, const Slot &src)
 {
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+        dst.e1a[r] = src.e1a[r];
+        dst.e1b[r] = src.e1b[r];
+        dst.e2a[r] = src.e2a[r];
+        dst.e2b[r] = src.e2b[r];
+    }
+    dst.ba = src.ba;
+    dst.bb = src.bb;
+}
+
+template <bool mom>
+__device__ __forceinline__ void fused_step(const Ctx &c0, FusedLds &S, const Slot &X, Slot &Y, int sx, float beta)
+{
+    Ctx c = c0;
+    c.par = sx;
     const float *RX = S.rx[sx];
     float *RY = S.rx[sx ^ 1];
     const bool lastcol = c.lastcol_a || c.lastcol_b;
@@ -122,8 +140,8 @@ __device__ __forceinline__ void fused_step(const Ctx &c, FusedLds &S, const Slot
     Y.ba = mom ? fista_y(X.ba, Y.ba, beta) : X.ba;
     Y.bb = mom ? fista_y(X.bb, Y.bb, beta) : X.bb;
     if (c.s > 0 && c.il0 < c.h) {
-        S.yt[c.s][c.ja] = Y.e1a[0];
-        S.yt[c.s][c.jb] = Y.e1b[0];
+        S.yt[sx][c.s][c.ja] = Y.e1a[0];
+        S.yt[sx][c.s][c.jb] = Y.e1b[0];
     }
     __syncthreads();
 
@@ -178,7 +196,7 @@ __global__ __launch_bounds__(1024) void k_fused_fista(FusedArgs a)
     const SubTile tl = a.subs[t];
     const ImgDev im = a.imgs[tl.img];
     Ctx c;
-    c.s = threadIdx.x >> 6;
+    c.s = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform strip index
     c.lane = threadIdx.x & 63;
     c.ja = 2 * c.lane;
     c.jb = c.ja + 1;
@@ -200,7 +218,6 @@ __global__ __launch_bounds__(1024) void k_fused_fista(FusedArgs a)
     c.kL = im.kL;
     const int h = c.h, w = c.w, il0 = c.il0, ja = c.ja, jb = c.jb;
     const long long P1 = im.pitch1, P2 = im.pitch2;
-    const long long gja = tl.ca + ja;
     const long long row1 = (long long)tl.ra + tl.r;  // P1 row of the tile's edge row 0
     const long long col2 = (long long)tl.ca + tl.c;  // P2 column of the tile's edge column 0
     const float *b1 = a.base1 + im.p1, *b2 = a.base2 + im.p2;
@@ -213,88 +230,144 @@ __global__ __launch_bounds__(1024) void k_fused_fista(FusedArgs a)
     A.ba = A.bb = 0.0f;
 
     // ---- load p~^n and build c' (anchor phat = p~^n -/+ tau lambda on interface copies).
-    // One pixel (il, jl): returns its top and left edge values (and the bottom
-    // boundary edge below it), writes c' and the right boundary slots to LDS.
-    auto load_px = [&](int il, int jl, float &x1, float &x2, float &xbot) {
-        const long long gi = tl.ra + il;
-        const long long gj = tl.ca + jl;
-        const float *f_row = f + gi * W;
-        x1 = b1[(row1 + il) * P1 + gj];
-        x2 = b2[gi * P2 + col2 + jl];
-        const float fv = f_row[gj];
-        const float fu = il > 0 ? f_row[gj - W] : 0.0f;
-        const float fl = jl > 0 ? f_row[gj - 1] : 0.0f;
-        float at = x1;
-        if (il == 0 && tl.r > 0) at = fmaf(tau, lam[(long long)(tl.r - 1) * W + gj], at);
-        S.c1[il][jl] = fista_cprime(at, fu, fv, itau, invL);
-        float al = x2;
-        if (jl == 0 && tl.c > 0) al = fmaf(tau, lam[im.nlh + (long long)(tl.c - 1) * H + gi], al);
-        S.c2[il][jl] = fista_cprime(al, fl, fv, itau, invL);
-        if (il == h - 1) {
-            const float xb = b1[(row1 + h) * P1 + gj];
-            xbot = xb;
-            const float ab = c.bot_bnd ? xb : fmaf(-tau, lam[(long long)tl.r * W + gj], xb);
-            S.cb[jl] = fista_cprime(ab, fv, 0.0f, itau, invL);
-        }
-        if (jl == w - 1) {
-            const float xr = b2[gi * P2 + col2 + w];
-            S.rx[0][il] = xr;
-            S.rx[1][il] = xr;
-            const float ar = c.right_bnd ? xr : fmaf(-tau, lam[im.nlh + (long long)tl.c * H + gi], xr);
-            S.cr[il] = fista_cprime(ar, fv, 0.0f, itau, invL);
-        }
+    // Each lane reads its two adjacent columns with 8-byte accesses; f of the
+    // row above is carried down the strip and f of the column to the left comes
+    // from the neighbouring lane.
+    auto ld2 = [](const float *p, float &x, float &y) {
+        float2 v;
+        __builtin_memcpy(&v, p, 8);
+        x = v.x;
+        y = v.y;
     };
+    float fua = 0.0f, fub = 0.0f;  // f of the row above (0 above the tile)
+    // uniform (per wave) row pointers; lanes index them with their column ja
+    const float *f_tile = f + (long long)tl.ra * W + tl.ca;                 // pixel (0, 0) of the tile
+    const float *p1_tile = b1 + row1 * P1 + tl.ca;                          // edge above pixel (0, 0)
+    const float *p2_tile = b2 + (long long)tl.ra * P2 + col2;               // edge left of pixel (0, 0)
+    if (il0 > 0 && il0 < h) {
+        const float *fr = f_tile + (long long)(il0 - 1) * W;
+        if (c.actb) ld2(fr + ja, fua, fub);
+        else if (c.acta) fua = fr[ja];
+    }
 #pragma unroll
     for (int r = 0; r < kR; ++r) {
         const int il = il0 + r;
-        float x1a = 0.0f, x2a = 0.0f, x1b = 0.0f, x2b = 0.0f;
-        if (il < h && c.acta) load_px(il, ja, x1a, x2a, A.ba);
-        if (il < h && c.actb) load_px(il, jb, x1b, x2b, A.bb);
+        float x1a = 0.0f, x1b = 0.0f, x2a = 0.0f, x2b = 0.0f, fva = 0.0f, fvb = 0.0f;
+        const float *p1r = p1_tile + (long long)il * P1;
+        const float *p2r = p2_tile + (long long)il * P2;
+        const float *fr = f_tile + (long long)il * W;
+        if (il < h) {
+            if (c.actb) {
+                ld2(p1r + ja, x1a, x1b);
+                ld2(p2r + ja, x2a, x2b);
+                ld2(fr + ja, fva, fvb);
+            } else if (c.acta) {
+                x1a = p1r[ja];
+                x2a = p2r[ja];
+                fva = fr[ja];
+            }
+        }
+        const float fla = from_left(fvb);  // f of column a - 1 (lane 0: left of the tile, 0)
+        if (il < h) {
+            const long long gi = tl.ra + il;
+            // top edges (t copies of an interface on the tile's first row)
+            float ata = x1a, atb = x1b;
+            if (il == 0 && tl.r > 0) {
+                const float *lr = lam + (long long)(tl.r - 1) * W + tl.ca;
+                if (c.acta) ata = fmaf(tau, lr[ja], ata);
+                if (c.actb) atb = fmaf(tau, lr[jb], atb);
+            }
+            // left edge (t copy of an interface on the tile's first column)
+            float ala = x2a;
+            if (ja == 0 && tl.c > 0) ala = fmaf(tau, lam[im.nlh + (long long)(tl.c - 1) * H + gi], ala);
+            if (c.acta) {
+                S.c1[il][ja] = fista_cprime(ata, fua, fva, itau, invL);
+                S.c2[il][ja] = fista_cprime(ala, ja > 0 ? fla : 0.0f, fva, itau, invL);
+            }
+            if (c.actb) {
+                S.c1[il][jb] = fista_cprime(atb, fub, fvb, itau, invL);
+                S.c2[il][jb] = fista_cprime(x2b, fva, fvb, itau, invL);
+            }
+            if (il == h - 1) {  // bottom boundary edges (s copies unless on the image boundary)
+                const float *pb = p1_tile + (long long)h * P1;
+                const float *lb = lam + (long long)tl.r * W + tl.ca;
+                if (c.acta) {
+                    const float xb = pb[ja];
+                    A.ba = xb;
+                    const float ab = c.bot_bnd ? xb : fmaf(-tau, lb[ja], xb);
+                    S.cb[ja] = fista_cprime(ab, fva, 0.0f, itau, invL);
+                }
+                if (c.actb) {
+                    const float xb = pb[jb];
+                    A.bb = xb;
+                    const float ab = c.bot_bnd ? xb : fmaf(-tau, lb[jb], xb);
+                    S.cb[jb] = fista_cprime(ab, fvb, 0.0f, itau, invL);
+                }
+            }
+            if (c.lastcol_a || c.lastcol_b) {  // right boundary edge of this row
+                const float xr = p2r[w];
+                S.rx[0][il] = xr;
+                S.rx[1][il] = xr;
+                const float ar = c.right_bnd ? xr : fmaf(-tau, lam[im.nlh + (long long)tl.c * H + gi], xr);
+                S.cr[il] = fista_cprime(ar, c.lastcol_a ? fva : fvb, 0.0f, itau, invL);
+            }
+        }
         A.e1a[r] = x1a; A.e2a[r] = x2a; A.e1b[r] = x1b; A.e2b[r] = x2b;
+        fua = fva;
+        fub = fvb;
     }
     B = A;
     __syncthreads();
 
+    // steps 1 and 2 have no momentum (beta = 0); x_K ends in slot A
     const int K = a.n_inner;
-    int k = 1;
-    for (; k + 1 <= K; k += 2) {
-        fused_step(c, S, A, B, 0, a.beta[k], k >= 3);
-        fused_step(c, S, B, A, 1, a.beta[k + 1], k + 1 >= 3);
-    }
-    const bool odd = (K & 1) != 0;
-    if (odd) {
-        fused_step(c, S, A, B, 0, a.beta[K], K >= 3);
-#pragma unroll
-        for (int r = 0; r < kR; ++r) {
-            A.e1a[r] = B.e1a[r];
-            A.e1b[r] = B.e1b[r];
-            A.e2a[r] = B.e2a[r];
-            A.e2b[r] = B.e2b[r];
+    int rx_slot = 0;  // LDS slot of the right boundary edges holding x_K
+    if (K == 1) {
+        fused_step<false>(c, S, A, B, 0, 0.0f);
+        copy_slot(A, B);
+        rx_slot = 1;
+    } else {
+        fused_step<false>(c, S, A, B, 0, 0.0f);
+        fused_step<false>(c, S, B, A, 1, 0.0f);
+        int k = 3;
+        for (; k + 1 <= K; k += 2) {
+            fused_step<true>(c, S, A, B, 0, a.beta[k]);
+            fused_step<true>(c, S, B, A, 1, a.beta[k + 1]);
         }
-        A.ba = B.ba;
-        A.bb = B.bb;
+        if (k == K) {
+            fused_step<true>(c, S, A, B, 0, a.beta[K]);
+            copy_slot(A, B);
+            rx_slot = 1;
+        }
     }
 
     // ---- store x_K (now in slot A) as p~^(n+1)
+    auto st2 = [](float *p, float x, float y) {
+        const float2 v = make_float2(x, y);
+        __builtin_memcpy(p, &v, 8);
+    };
+    float *q1_tile = o1 + row1 * P1 + tl.ca;
+    float *q2_tile = o2 + (long long)tl.ra * P2 + col2;
 #pragma unroll
     for (int r = 0; r < kR; ++r) {
         const int il = il0 + r;
         if (il < h) {
-            const long long gi = tl.ra + il;
-            if (c.acta) {
-                o1[(row1 + il) * P1 + gja] = A.e1a[r];
-                o2[gi * P2 + col2 + ja] = A.e2a[r];
-            }
+            float *q1 = q1_tile + (long long)il * P1;
+            float *q2 = q2_tile + (long long)il * P2;
             if (c.actb) {
-                o1[(row1 + il) * P1 + gja + 1] = A.e1b[r];
-                o2[gi * P2 + col2 + jb] = A.e2b[r];
+                st2(q1 + ja, A.e1a[r], A.e1b[r]);
+                st2(q2 + ja, A.e2a[r], A.e2b[r]);
+            } else if (c.acta) {
+                q1[ja] = A.e1a[r];
+                q2[ja] = A.e2a[r];
             }
-            if (c.lastcol_a || c.lastcol_b) o2[gi * P2 + col2 + w] = S.rx[odd ? 1 : 0][il];
+            if (c.lastcol_a || c.lastcol_b) q2[w] = S.rx[rx_slot][il];
         }
     }
     if (c.has_bottom) {
-        if (c.acta) o1[(row1 + h) * P1 + gja] = A.ba;
-        if (c.actb) o1[(row1 + h) * P1 + gja + 1] = A.bb;
+        float *qb = q1_tile + (long long)h * P1;
+        if (c.actb) st2(qb + ja, A.ba, A.bb);
+        else if (c.acta) qb[ja] = A.ba;
     }
 }
 
