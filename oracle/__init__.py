@@ -94,7 +94,7 @@ def load(path: str = LIB_PATH):
     lib.orc_threads.restype = ctypes.c_int
     if hasattr(lib, "orc_backward"):
         lib.orc_backward.restype = ctypes.c_int
-        lib.orc_backward.argtypes = [vp, ctypes.c_int, _D, _D, _U8, _D, _D, _D]
+        lib.orc_backward.argtypes = [vp, ctypes.c_int, _D, _U8, _D, _D, _D]
     if path == LIB_PATH:
         _lib = lib
     return lib
@@ -196,6 +196,21 @@ class Oracle:
     def import_state(self, st: dict) -> None:
         self.lib.orc_import(self.h, _dp(_f64(st["u"])), _dp(_f64(st["p"])), _dp(_f64(st["lam"])),
                             _dp(_f64(st["prev"])), int(st["n_done"]))
+
+    def backward(self, n_outer: int, ubar) -> tuple:
+        """Reverse mode of n_outer steps of Algorithm 1 from the initial state
+        (FISTA local solver, L2, no mask): returns (dl/df, dl/dalpha) for the
+        loss gradient ubar = dl/du of the final u = f + div~ p / alpha.  Runs
+        the forward itself; the oracle must not have been stepped before."""
+        if not hasattr(self.lib, "orc_backward"):
+            raise RuntimeError("oracle built without the reverse pass")
+        ub = _f64(ubar).reshape(self.H, self.W)
+        fbar = np.zeros((self.H, self.W))
+        abar = np.zeros(1)
+        rc = self.lib.orc_backward(self.h, int(n_outer), _dp(self.f), self._mp, _dp(ub), _dp(fbar), _dp(abar))
+        if rc != 0:
+            raise ValueError("reverse pass not available for this problem (needs FISTA, L2, no mask, fresh state)")
+        return fbar, float(abar[0])
 
     def diagnostics(self) -> np.ndarray:
         out = np.zeros(4)

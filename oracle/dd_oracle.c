@@ -801,3 +801,305 @@ int orc_threads(void)
     return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------ */
+/* reverse mode of the unrolled solve (FISTA local solver, L2, no mask)  */
+/*
+ * The forward map is Algorithm 1 exactly as outer_step() runs it with
+ * local_fista(); the final image is u = f + div~ p^N / alpha.  Given
+ * ubar = dl/du this computes dl/df and dl/dalpha by reverse accumulation:
+ *   - outer steps are reversed one at a time from stored snapshots
+ *     (p^n, lambda^n, prev^n) and their inner iterates recomputed;
+ *   - x_k = proj(z_k): zbar = xbar * 1{|z_k| < 1} (0 on non-dof edges);
+ *   - z_k = y - (1/L)[div*(f + div y / alpha) + (y - phat)/tau] is affine in
+ *     (y, phat, f) with L = 8/alpha + 1/tau, so
+ *       ybar += zbar - (1/L)[div*(div zbar)/alpha + zbar/tau],
+ *       phatbar += zbar / (L tau),  fbar -= div zbar / L,
+ *       alphabar += <zbar, dz/dalpha>,
+ *     dz/dalpha = -a'[div* f + (y - phat)/tau] - b' div* div y with
+ *     a = 1/L, b = 1/(alpha L), a' = 8/(alpha L)^2, b' = -1/(tau (alpha L)^2);
+ *   - y_k = x_k + beta_k (x_k - x_{k-1}) with constant beta_k;
+ *   - phat = p - tau B^* lambda^{n+1};
+ *   - lambda^{n+1} = lambda^n + sigma B(2 p^n - prev^n), prev^{n+1} = p^n|_Gamma.
+ * Returns 0, or -1 for unsupported settings.
+ */
+
+typedef struct {
+    double *x;     /* x_0 .. x_K, each n1 + n2 (p1 block then p2 block) */
+    double *y;     /* y_0 .. y_{K-1} */
+    double *z;     /* z_1 .. z_K */
+    double *zb, *yb, *xb;  /* adjoint work, n1 + n2 each; xb holds x_0 .. x_K adjoints */
+    double *v;     /* pixel work */
+    double *w;     /* pixel work */
+} rev_work;
+
+/* apply div_s to a concatenated (p1, p2) block */
+static void div_blk(const orc_sub *S, const double *p, double *out)
+{
+    div_local(S, p, p + (size_t)(S->h + 1) * S->w, out);
+}
+
+static void divT_blk(const orc_state *st, const orc_sub *S, const double *v, double *q)
+{
+    divT_local(st, S, v, q, q + (size_t)(S->h + 1) * S->w);
+}
+
+/* forward FISTA of one subdomain from x_0 = p with anchor phat (h1, h2),
+   storing every iterate; the arithmetic is that of local_fista() */
+static void fista_record(const orc_state *st, const orc_sub *S, const double *x0, const double *hat, rev_work *W)
+{
+    const orc_params *P = &st->prm;
+    int h = S->h, w = S->w;
+    size_t n = (size_t)(h + 1) * w + (size_t)h * (w + 1);
+    double inv_tau = 1.0 / P->tau, L = 8.0 / P->alpha + inv_tau;
+    double *q = W->yb; /* scratch */
+    memcpy(W->x, x0, sizeof(double) * n);
+    memcpy(W->y, x0, sizeof(double) * n);
+    double t = 1.0;
+    for (int k = 1; k <= P->n_inner; k++) {
+        const double *y = W->y + (size_t)(k - 1) * n;
+        double *z = W->z + (size_t)(k - 1) * n;
+        double *xk = W->x + (size_t)k * n;
+        const double *xm = W->x + (size_t)(k - 1) * n;
+        div_blk(S, y, W->v);
+        for (int i = 0; i < h * w; i++) W->v[i] = S->f[i] + W->v[i] / P->alpha;
+        divT_blk(st, S, W->v, q);
+        for (size_t e = 0; e < n; e++) {
+            double g = q[e] + (y[e] - hat[e]) * inv_tau;
+            z[e] = y[e] - g / L;
+        }
+        /* non-dof edges: z is 0 there (q, y, phat all 0) */
+        for (size_t e = 0; e < n; e++) xk[e] = proj_box(z[e]);
+        double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
+        double beta = (t - 1.0) / tn;
+        if (k < P->n_inner) {
+            double *yn = W->y + (size_t)k * n;
+            for (size_t e = 0; e < n; e++) yn[e] = xk[e] + beta * (xk[e] - xm[e]);
+        }
+        t = tn;
+    }
+}
+
+/* reverse of fista_record: xbar_K in W->xb + K n on entry; on exit
+   W->xb holds xbar_0 (first block), hatbar accumulated, fbar_s and abar
+   accumulated */
+static void fista_reverse(const orc_state *st, const orc_sub *S, const double *hat, rev_work *W, double *hatbar,
+                          double *fbar_s, double *abar)
+{
+    const orc_params *P = &st->prm;
+    int h = S->h, w = S->w, K = P->n_inner;
+    size_t n = (size_t)(h + 1) * w + (size_t)h * (w + 1);
+    double tau = P->tau, alpha = P->alpha;
+    double L = 8.0 / alpha + 1.0 / tau;
+    double a = 1.0 / L;
+    double da = 8.0 / (alpha * L * alpha * L);
+    double db = -1.0 / (tau * (alpha * L) * (alpha * L));
+    /* momentum coefficients beta_k, k = 1..K-1 (y_k = x_k + beta_k (x_k - x_{k-1})) */
+    double *beta = (double *)calloc((size_t)K + 1, sizeof(double));
+    double t = 1.0;
+    for (int k = 1; k <= K; k++) {
+        double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
+        beta[k] = (t - 1.0) / tn;
+        t = tn;
+    }
+    double *q = (double *)malloc(sizeof(double) * n);
+    double *dfz = (double *)malloc(sizeof(double) * (size_t)h * w); /* div zbar */
+    double *dy = (double *)malloc(sizeof(double) * (size_t)h * w);  /* div y */
+    /* xbar_k, k = 0..K-1 start at 0 */
+    memset(W->xb, 0, sizeof(double) * n * (size_t)K);
+    for (int k = K; k >= 1; k--) {
+        const double *y = W->y + (size_t)(k - 1) * n;
+        const double *z = W->z + (size_t)(k - 1) * n;
+        const double *xbk = W->xb + (size_t)k * n;
+        /* projection: derivative 1 where |z| < 1, 0 where the box is active */
+        for (size_t e = 0; e < n; e++) W->zb[e] = fabs(z[e]) < 1.0 ? xbk[e] : 0.0;
+        /* zero the non-dof edges */
+        {
+            double *z1 = W->zb, *z2 = W->zb + (size_t)(h + 1) * w;
+            for (int x = 0; x < w; x++) {
+                if (!dof1(st, S, 0)) z1[x] = 0.0;
+                if (!dof1(st, S, h)) z1[(size_t)h * w + x] = 0.0;
+            }
+            for (int yy = 0; yy < h; yy++) {
+                if (!dof2(st, S, 0)) z2[(size_t)yy * (w + 1)] = 0.0;
+                if (!dof2(st, S, w)) z2[(size_t)yy * (w + 1) + w] = 0.0;
+            }
+        }
+        /* linear part */
+        div_blk(S, W->zb, dfz);
+        for (int i = 0; i < h * w; i++) W->v[i] = dfz[i] / alpha;
+        divT_blk(st, S, W->v, q);
+        for (size_t e = 0; e < n; e++) W->yb[e] = W->zb[e] - a * (q[e] + W->zb[e] / tau);
+        for (size_t e = 0; e < n; e++) hatbar[e] += a / tau * W->zb[e];
+        for (int i = 0; i < h * w; i++) fbar_s[i] -= a * dfz[i];
+        /* dz/dalpha */
+        div_blk(S, y, dy);
+        double s_f = 0.0, s_y = 0.0, s_dd = 0.0;
+        for (int i = 0; i < h * w; i++) {
+            s_f += dfz[i] * S->f[i];
+            s_dd += dfz[i] * dy[i];
+        }
+        for (size_t e = 0; e < n; e++) s_y += W->zb[e] * (y[e] - hat[e]);
+        *abar += -da * (s_f + s_y / tau) - db * s_dd;
+        /* y_{k-1} = x_{k-1} + beta_{k-1} (x_{k-1} - x_{k-2}); y_0 = x_0 */
+        double *xb1 = W->xb + (size_t)(k - 1) * n;
+        if (k - 1 >= 1) {
+            double bk = beta[k - 1];
+            double *xb2 = W->xb + (size_t)(k - 2) * n;
+            for (size_t e = 0; e < n; e++) {
+                xb1[e] += (1.0 + bk) * W->yb[e];
+                xb2[e] -= bk * W->yb[e];
+            }
+        } else {
+            for (size_t e = 0; e < n; e++) xb1[e] += W->yb[e];
+        }
+    }
+    free(beta); free(q); free(dfz); free(dy);
+}
+
+/* Positions of the two copies of every interface dof in the concatenated
+   p (p1_s then p2_s per subdomain): is[e] on side s, it[e] on side t, for the
+   multiplier ordering lam_h then lam_v. */
+static void interface_maps(const orc_state *st, long *is, long *it)
+{
+    int H = st->prm.H, W = st->prm.W, ny = st->prm.ny, nx = st->prm.nx;
+    long *off = (long *)malloc(sizeof(long) * (size_t)(st->nsub + 1));
+    off[0] = 0;
+    for (int s = 0; s < st->nsub; s++) {
+        const orc_sub *S = &st->sub[s];
+        off[s + 1] = off[s] + (long)(S->h + 1) * S->w + (long)S->h * (S->w + 1);
+    }
+    size_t nh = (size_t)(ny - 1) * W;
+    for (int r = 1; r < ny; r++)
+        for (int j = 0; j < W; j++) {
+            int c = sub_col_of(st, j);
+            int si = (r - 1) * nx + c, ti = r * nx + c;
+            const orc_sub *S = &st->sub[si], *T = &st->sub[ti];
+            size_t e = (size_t)(r - 1) * W + j;
+            is[e] = off[si] + (long)S->h * S->w + (j - S->ca);
+            it[e] = off[ti] + (j - T->ca);
+        }
+    for (int c = 1; c < nx; c++)
+        for (int i = 0; i < H; i++) {
+            int r = sub_row_of(st, i);
+            int si = r * nx + c - 1, ti = r * nx + c;
+            const orc_sub *S = &st->sub[si], *T = &st->sub[ti];
+            size_t e = nh + (size_t)(c - 1) * H + i;
+            is[e] = off[si] + (long)(S->h + 1) * S->w + (long)(i - S->ra) * (S->w + 1) + S->w;
+            it[e] = off[ti] + (long)(T->h + 1) * T->w + (long)(i - T->ra) * (T->w + 1);
+        }
+    free(off);
+}
+
+int orc_backward(orc_state *st, int n_outer, const double *f_global, const unsigned char *mask, const double *ubar,
+                 double *fbar, double *abar_out)
+{
+    const orc_params *P = &st->prm;
+    (void)f_global;
+    if (P->inner != ORC_FISTA || P->fidelity != ORC_L2 || P->no_prox_term || st->n_done != 0 || mask) return -1;
+    int H = P->H, W = P->W, ny = P->ny, nx = P->nx, K = P->n_inner;
+    long sz[3];
+    orc_sizes(st, sz);
+    size_t np = (size_t)sz[0], nl = (size_t)sz[1];
+    size_t nh = (size_t)(ny - 1) * W, nv = (size_t)(nx - 1) * H;
+    size_t nl1 = nl ? nl : 1;
+    long *is = (long *)malloc(sizeof(long) * nl1), *it = (long *)malloc(sizeof(long) * nl1);
+    interface_maps(st, is, it);
+
+    /* forward with snapshots of (p, lambda, prev) before every outer step */
+    double *sp = (double *)malloc(sizeof(double) * np * (size_t)(n_outer + 1));
+    double *sl = (double *)malloc(sizeof(double) * nl1 * (size_t)(n_outer + 1));
+    double *sv = (double *)malloc(sizeof(double) * 2 * nl1 * (size_t)(n_outer + 1));
+    for (int n = 0; n <= n_outer; n++) {
+        orc_export(st, NULL, sp + np * n, sl + nl1 * n, sv + 2 * nl1 * n, NULL);
+        if (n < n_outer) outer_step(st, NULL);
+    }
+
+    /* u = f + div~ p^N / alpha */
+    double abar = 0.0;
+    double *dv = (double *)malloc(sizeof(double) * (size_t)H * W);
+    orc_apply_div(st, sp + np * n_outer, dv);
+    for (size_t i = 0; i < (size_t)H * W; i++) {
+        fbar[i] = ubar[i];
+        abar += -ubar[i] * dv[i] / (P->alpha * P->alpha);
+        dv[i] = ubar[i] / P->alpha;
+    }
+    double *Pb = (double *)calloc(np, sizeof(double));   /* adjoint of p^{n+1} */
+    orc_apply_divT(st, dv, Pb);
+    double *lamb = (double *)calloc(nl1, sizeof(double)); /* adjoint of lambda^{n+1} from later steps */
+    double *pvs = (double *)calloc(nl1, sizeof(double));  /* adjoint of prev_s^{n+1} */
+    double *pvt = (double *)calloc(nl1, sizeof(double));  /* adjoint of prev_t^{n+1} */
+    double *Pn = (double *)malloc(sizeof(double) * np), *hat = (double *)malloc(sizeof(double) * np);
+    double *hatb = (double *)malloc(sizeof(double) * np), *Pb0 = (double *)malloc(sizeof(double) * np);
+    double *lam1 = (double *)malloc(sizeof(double) * nl1);
+
+    size_t nmax = 0, pmax = 0;
+    for (int s = 0; s < st->nsub; s++) {
+        const orc_sub *S = &st->sub[s];
+        size_t n = (size_t)(S->h + 1) * S->w + (size_t)S->h * (S->w + 1);
+        if (n > nmax) nmax = n;
+        if ((size_t)S->h * S->w > pmax) pmax = (size_t)S->h * S->w;
+    }
+    rev_work Wk;
+    Wk.x = (double *)malloc(sizeof(double) * nmax * (size_t)(K + 1));
+    Wk.y = (double *)malloc(sizeof(double) * nmax * (size_t)(K + 1));
+    Wk.z = (double *)malloc(sizeof(double) * nmax * (size_t)(K + 1));
+    Wk.xb = (double *)malloc(sizeof(double) * nmax * (size_t)(K + 1));
+    Wk.zb = (double *)malloc(sizeof(double) * nmax);
+    Wk.yb = (double *)malloc(sizeof(double) * nmax);
+    Wk.v = (double *)malloc(sizeof(double) * pmax);
+    Wk.w = (double *)malloc(sizeof(double) * pmax);
+    double *fbar_s = (double *)malloc(sizeof(double) * pmax);
+
+    for (int n = n_outer - 1; n >= 0; n--) {
+        const double *lam = sl + nl1 * n, *pv = sv + 2 * nl1 * n;
+        memcpy(Pn, sp + np * n, sizeof(double) * np);
+        /* redo the multiplier update and the anchor of step n exactly as outer_step does */
+        for (size_t e = 0; e < nl; e++) {
+            double prev_s = e < nh ? pv[e] : pv[2 * nh + (e - nh)];
+            double prev_t = e < nh ? pv[nh + e] : pv[2 * nh + nv + (e - nh)];
+            lam1[e] = lam[e] + P->sigma * ((2.0 * Pn[is[e]] - prev_s) - (2.0 * Pn[it[e]] - prev_t));
+        }
+        memcpy(hat, Pn, sizeof(double) * np);
+        for (size_t e = 0; e < nl; e++) {
+            hat[is[e]] -= P->tau * lam1[e];
+            hat[it[e]] += P->tau * lam1[e];
+        }
+        /* local solves in reverse */
+        memset(hatb, 0, sizeof(double) * np);
+        size_t o = 0;
+        for (int s = 0; s < st->nsub; s++) {
+            orc_sub *S = &st->sub[s];
+            size_t nn = (size_t)(S->h + 1) * S->w + (size_t)S->h * (S->w + 1);
+            fista_record(st, S, Pn + o, hat + o, &Wk);
+            memcpy(Wk.xb + (size_t)K * nn, Pb + o, sizeof(double) * nn);
+            memset(fbar_s, 0, sizeof(double) * (size_t)S->h * S->w);
+            fista_reverse(st, S, hat + o, &Wk, hatb + o, fbar_s, &abar);
+            memcpy(Pb0 + o, Wk.xb, sizeof(double) * nn);
+            for (int y = 0; y < S->h; y++)
+                for (int x = 0; x < S->w; x++) fbar[(size_t)(S->ra + y) * W + S->ca + x] += fbar_s[y * S->w + x];
+            o += nn;
+        }
+        /* phat = p^n - tau B^* lambda^{n+1} */
+        for (size_t e = 0; e < np; e++) Pb0[e] += hatb[e];
+        for (size_t e = 0; e < nl; e++) {
+            double lt = lamb[e] - P->tau * (hatb[is[e]] - hatb[it[e]]); /* total adjoint of lambda^{n+1} */
+            /* prev^{n+1} = p^n on the interface copies */
+            Pb0[is[e]] += pvs[e];
+            Pb0[it[e]] += pvt[e];
+            /* lambda^{n+1} = lambda^n + sigma ((2 p_s - prev_s) - (2 p_t - prev_t)) */
+            Pb0[is[e]] += 2.0 * P->sigma * lt;
+            Pb0[it[e]] -= 2.0 * P->sigma * lt;
+            pvs[e] = -P->sigma * lt;
+            pvt[e] = P->sigma * lt;
+            lamb[e] = lt;
+        }
+        memcpy(Pb, Pb0, sizeof(double) * np);
+    }
+    /* p^0, lambda^0, prev^0 are constants: nothing flows further */
+    *abar_out = abar;
+    free(is); free(it); free(sp); free(sl); free(sv); free(dv); free(Pb); free(lamb); free(pvs); free(pvt);
+    free(Pn); free(hat); free(hatb); free(Pb0); free(lam1);
+    free(Wk.x); free(Wk.y); free(Wk.z); free(Wk.xb); free(Wk.zb); free(Wk.yb); free(Wk.v); free(Wk.w); free(fbar_s);
+    return 0;
+}
