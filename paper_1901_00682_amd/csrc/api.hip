@@ -73,6 +73,14 @@ struct dtv_dd_plan {
     char *ws = nullptr;
     double *h_diag = nullptr;  // pinned host mirror of the diagnostics sums
 
+    // reverse mode: outer-step checkpoints and the work buffers of the adjoint
+    int nseg = 0;             // checkpoint slots ckpt(0..nseg-1) hold the state before steps 0, C, 2C, ...
+    size_t state_floats = 0;  // one state: P1, P2, then the lambda state
+    size_t off_ckpt = 0, off_seg = 0, off_xrec = 0, off_zrec = 0, off_lam1 = 0, off_xb = 0, off_hb = 0, off_pb = 0,
+           off_lb = 0, off_galpha = 0;
+    bool saved = false;       // the last solve saved its checkpoints
+    int saved_outer = 0;      // outer steps of that solve
+
     // timing of the inner-step kernel
     std::vector<hipEvent_t> events;
     double t_ms = 0.0;
@@ -92,6 +100,17 @@ struct dtv_dd_plan {
     float *buf2(int k) const { return (float *)(ws + off_buf[k]) + tot_p1; }
     float *u2() const { return (float *)(ws + off_u2); }
     double *partials() const { return (double *)(ws + off_part); }
+    size_t edges() const { return (size_t)(tot_p1 + tot_p2); }
+    float *ckpt(int k) const { return (float *)(ws + off_ckpt) + (size_t)k * state_floats; }
+    float *seg(int k) const { return (float *)(ws + off_seg) + (size_t)k * state_floats; }
+    float *xrec(int k) const { return (float *)(ws + off_xrec) + (size_t)k * edges(); }
+    float *zrec(int k) const { return (float *)(ws + off_zrec) + (size_t)k * edges(); }
+    float *lam1() const { return (float *)(ws + off_lam1); }
+    float *xb(int k) const { return (float *)(ws + off_xb) + (size_t)k * edges(); }
+    float *hb() const { return (float *)(ws + off_hb); }
+    float *pb() const { return (float *)(ws + off_pb); }
+    float *lb() const { return (float *)(ws + off_lb); }
+    double *galpha() const { return (double *)(ws + off_galpha); }
     double *dout() const { return (double *)(ws + off_dout); }
 };
 
@@ -139,6 +158,7 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
         return fail(DTV_EINVAL, "gap_tol needs one L2 image without mask and diag_every > 0");
     if (p.save_for_backward && (p.inner != DTV_INNER_FISTA || p.ckpt_every < 1))
         return fail(DTV_EINVAL, "save_for_backward needs FISTA and ckpt_every >= 1");
+    if (p.save_for_backward && p.gap_tol > 0.0) return fail(DTV_EINVAL, "save_for_backward needs fixed iteration counts");
     if (p.schedule < DTV_SCHED_AUTO || p.schedule > DTV_SCHED_FUSED) return fail(DTV_EINVAL, "unknown schedule");
 
     dtv_dd_plan *pl = new dtv_dd_plan();
@@ -213,6 +233,8 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
         g.invL = (float)(1.0 / L);
         g.a_keep = (float)(1.0 - 1.0 / (L * tau));
         g.kL = (float)(1.0 / (h.alpha * L));
+        g.dA = 8.0 / ((h.alpha * L) * (h.alpha * L));
+        g.dB = -1.0 / (tau * (h.alpha * L) * (h.alpha * L));
         pl->h_imgs.push_back(g);
         for (int i0 = 0; i0 < h.H; i0 += pl->rows)
             for (int j0 = 0; j0 < h.W; j0 += kStreamCols) pl->h_tiles.push_back(StreamTile{b, i0, j0, 0});
@@ -245,6 +267,23 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
     pl->diag_nblk = diag_blocks_per_image(pl->maxH, pl->maxW);
     pl->off_part = take(sizeof(double) * 6 * (size_t)pl->diag_nblk * n_images);
     pl->off_dout = take(sizeof(double) * 6 * (size_t)n_images);
+    if (p.save_for_backward) {
+        const size_t E = (size_t)(pl->tot_p1 + pl->tot_p2);
+        pl->state_floats = E + (size_t)pl->tot_lam;
+        const int C = p.ckpt_every;
+        pl->nseg = (p.n_outer + C - 1) / C;
+        const int segmax = std::min(C, std::max(p.n_outer, 1));
+        pl->off_ckpt = take(sizeof(float) * pl->state_floats * (size_t)(pl->nseg + 1));
+        pl->off_seg = take(sizeof(float) * pl->state_floats * (size_t)segmax);
+        pl->off_xrec = take(sizeof(float) * E * (size_t)p.n_inner);
+        pl->off_zrec = take(sizeof(float) * E * (size_t)p.n_inner);
+        pl->off_lam1 = take(sizeof(float) * (size_t)pl->tot_lam);
+        pl->off_xb = take(sizeof(float) * E * 3);
+        pl->off_hb = take(sizeof(float) * E);
+        pl->off_pb = take(sizeof(float) * E);
+        pl->off_lb = take(sizeof(float) * (size_t)pl->tot_lam);
+        pl->off_galpha = take(sizeof(double) * pl->h_tiles.size());
+    }
     pl->ws_bytes = off;
     pl->schedule = p.schedule == DTV_SCHED_STREAM ? DTV_SCHED_STREAM
                  : (p.schedule == DTV_SCHED_FUSED || pl->fused_ok) ? DTV_SCHED_FUSED : DTV_SCHED_STREAM;
@@ -295,6 +334,10 @@ extern "C" int dtv_dd_bind_workspace(dtv_dd_plan *pl, void *d_ws, size_t bytes)
     // rotation buffers start at zero so that their boundary (non-dof) edges are 0
     for (int k = 0; k < 3; ++k)
         HIP_TRY(hipMemset(ws + pl->off_buf[k], 0, sizeof(float) * (size_t)(pl->tot_p1 + pl->tot_p2)), "clear buffers");
+    // reverse-mode buffers: the step kernels write dof edges only, so the
+    // boundary entries of every edge buffer must start (and stay) at zero
+    if (pl->prm.save_for_backward)
+        HIP_TRY(hipMemset(ws + pl->off_ckpt, 0, pl->ws_bytes - pl->off_ckpt), "clear reverse-mode buffers");
     if (!pl->h_diag) HIP_TRY(hipHostMalloc((void **)&pl->h_diag, sizeof(double) * 6 * pl->n), "pinned diag buffer");
     pl->ws = ws;
     return DTV_OK;
@@ -476,7 +519,24 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
         return DTV_OK;
     };
 
+    auto save_state = [&](int slot, const EdgeBuf &b) -> int {
+        float *dst = pl->ckpt(slot);
+        HIP_TRY(hipMemcpyAsync(dst, b.p1, sizeof(float) * (size_t)pl->tot_p1, hipMemcpyDeviceToDevice, s), "checkpoint");
+        HIP_TRY(hipMemcpyAsync(dst + pl->tot_p1, b.p2, sizeof(float) * (size_t)pl->tot_p2, hipMemcpyDeviceToDevice, s),
+                "checkpoint");
+        if (pl->tot_lam > 0)
+            HIP_TRY(hipMemcpyAsync(dst + pl->edges(), d_lambda, sizeof(float) * (size_t)pl->tot_lam,
+                                   hipMemcpyDeviceToDevice, s),
+                    "checkpoint");
+        return DTV_OK;
+    };
+    pl->saved = false;
+
     for (int n = 0; n < P.n_outer; ++n) {
+        if (P.save_for_backward && n % P.ckpt_every == 0) {
+            int rc = save_state(n / P.ckpt_every, bufs[base]);
+            if (rc != DTV_OK) return rc;
+        }
         // (a1) multipliers from the extrapolated interface jump
         HIP_TRY(launch_lambda(pl->d_imgs(), pl->n, pl->max_nlam, pl->d_info(), bufs[base].p1, bufs[base].p2, d_lambda,
                               (float)P.sigma, s),
@@ -558,6 +618,12 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
             if (P.gap_tol > 0.0 && drow[2] <= P.gap_tol * std::fabs(drow[0])) break;
         }
     }
+    if (P.save_for_backward) {
+        int rc = save_state(pl->nseg, bufs[base]);
+        if (rc != DTV_OK) return rc;
+        pl->saved = true;
+        pl->saved_outer = P.n_outer;
+    }
     if (base != 0) {
         HIP_TRY(hipMemcpyAsync(d_p1, bufs[base].p1, sizeof(float) * (size_t)pl->tot_p1, hipMemcpyDeviceToDevice, s), "copy p1");
         HIP_TRY(hipMemcpyAsync(d_p2, bufs[base].p2, sizeof(float) * (size_t)pl->tot_p2, hipMemcpyDeviceToDevice, s), "copy p2");
@@ -576,12 +642,128 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
     return DTV_OK;
 }
 
+// FISTA momentum coefficients beta[k] of step k (0 for k = 1, 2)
+static std::vector<float> fista_betas(int K)
+{
+    std::vector<float> beta(K + 1, 0.0f);
+    std::vector<double> t(K + 2, 1.0);
+    for (int m = 1; m <= K; ++m) t[m + 1] = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t[m] * t[m]));
+    for (int k = 2; k <= K; ++k) beta[k] = (float)((t[k - 1] - 1.0) / t[k]);
+    return beta;
+}
+
+// One outer step from a stored state (P1, P2, lambda state) with the
+// streaming kernels: the multiplier update into lam1 and the n_inner FISTA
+// steps into xrec(0..K-1), recording z_k into zrec when asked.
+static int rec_outer(dtv_dd_plan *pl, const float *state, const float *d_f, bool record, const std::vector<float> &beta,
+                     hipStream_t s)
+{
+    const dtv_dd_params &P = pl->prm;
+    const float *p1 = state, *p2 = state + pl->tot_p1, *lam = state + pl->edges();
+    const int K = P.n_inner;
+    if (pl->tot_lam > 0)
+        HIP_TRY(hipMemcpyAsync(pl->lam1(), lam, sizeof(float) * (size_t)pl->tot_lam, hipMemcpyDeviceToDevice, s),
+                "lambda copy");
+    HIP_TRY(launch_lambda(pl->d_imgs(), pl->n, pl->max_nlam, pl->d_info(), p1, p2, pl->lam1(), (float)P.sigma, s),
+            "lambda update");
+    for (int k = 1; k <= K; ++k) {
+        FistaStepArgs a{};
+        a.imgs = pl->d_imgs(); a.tiles = pl->d_tiles(); a.ntiles = (int)pl->h_tiles.size(); a.info = pl->d_info();
+        const float *xa = k == 1 ? state : pl->xrec(k - 2);
+        const float *xbp = k >= 3 ? pl->xrec(k - 3) : state;
+        a.xa1 = xa; a.xa2 = xa + pl->tot_p1;
+        a.xb1 = xbp; a.xb2 = xbp + pl->tot_p1;
+        a.lam = pl->lam1(); a.f = d_f;
+        a.c1 = pl->buf1(2); a.c2 = pl->buf2(2);
+        a.out1 = pl->xrec(k - 1); a.out2 = pl->xrec(k - 1) + pl->tot_p1;
+        if (record) {
+            a.z1 = pl->zrec(k - 1);
+            a.z2 = pl->zrec(k - 1) + pl->tot_p1;
+        }
+        a.beta = beta[k]; a.tau = (float)P.tau; a.inv_tau = (float)(1.0 / P.tau);
+        const int mode = k == 1 ? kFistaFirst : (k == 2 ? kFistaPlain : kFistaMomentum);
+        HIP_TRY(launch_fista_step(a, mode, pl->rows, s), "FISTA step (recompute)");
+    }
+    return DTV_OK;
+}
+
 extern "C" int dtv_dd_backward(dtv_dd_plan *pl, const float *d_f, const float *d_grad_u, float *d_grad_f,
                                float *d_grad_alpha, void *stream)
 {
-    (void)d_f; (void)d_grad_u; (void)d_grad_f; (void)d_grad_alpha; (void)stream;
-    if (!pl) return fail(DTV_EINVAL, "null argument");
-    return fail(DTV_ESTATE, "no saved forward: backward is not available in this build");
+    if (!pl || !d_f || !d_grad_u || !d_grad_f || !d_grad_alpha) return fail(DTV_EINVAL, "null argument");
+    if (!pl->prm.save_for_backward || !pl->saved) return fail(DTV_ESTATE, "no forward solve with saved checkpoints");
+    if (!pl->ws) return fail(DTV_ENOWS, "no workspace bound");
+    hipStream_t s = (hipStream_t)stream;
+    const dtv_dd_params &P = pl->prm;
+    const int K = P.n_inner, N = pl->saved_outer, C = P.ckpt_every;
+    const size_t E = pl->edges();
+    const std::vector<float> beta = fista_betas(K);
+    const int ntiles = (int)pl->h_tiles.size();
+
+    HIP_TRY(hipMemsetAsync(pl->galpha(), 0, sizeof(double) * (size_t)ntiles, s), "clear");
+    HIP_TRY(hipMemsetAsync(pl->pb(), 0, sizeof(float) * E, s), "clear");
+    if (pl->tot_lam > 0) HIP_TRY(hipMemsetAsync(pl->lb(), 0, sizeof(float) * (size_t)pl->tot_lam, s), "clear");
+    // u = f + div p^N / alpha
+    const float *pN = pl->ckpt(pl->nseg);
+    HIP_TRY(launch_bwd_final_u(pl->d_imgs(), pl->d_tiles(), ntiles, pl->rows, pl->d_info(), pN, pN + pl->tot_p1,
+                               d_grad_u, d_grad_f, pl->pb(), pl->pb() + pl->tot_p1, pl->galpha(), s),
+            "final u reverse");
+
+    for (int sg = pl->nseg - 1; sg >= 0; --sg) {
+        const int n0 = sg * C, n1 = std::min(N, n0 + C), m = n1 - n0;
+        HIP_TRY(hipMemcpyAsync(pl->seg(0), pl->ckpt(sg), sizeof(float) * pl->state_floats, hipMemcpyDeviceToDevice, s),
+                "restore checkpoint");
+        // recompute the states of the segment
+        for (int q = 0; q + 1 < m; ++q) {
+            int rc = rec_outer(pl, pl->seg(q), d_f, false, beta, s);
+            if (rc != DTV_OK) return rc;
+            HIP_TRY(hipMemcpyAsync(pl->seg(q + 1), pl->xrec(K - 1), sizeof(float) * E, hipMemcpyDeviceToDevice, s),
+                    "segment state");
+            if (pl->tot_lam > 0)
+                HIP_TRY(hipMemcpyAsync(pl->seg(q + 1) + E, pl->lam1(), sizeof(float) * (size_t)pl->tot_lam,
+                                       hipMemcpyDeviceToDevice, s),
+                        "segment state");
+        }
+        // reverse the outer steps of the segment
+        for (int q = m - 1; q >= 0; --q) {
+            const float *st = pl->seg(q);
+            int rc = rec_outer(pl, st, d_f, true, beta, s);
+            if (rc != DTV_OK) return rc;
+            // xbar_K = pbar; xbar_{K-1}, xbar_{K-2} start at 0 (buffers indexed by k mod 3)
+            HIP_TRY(hipMemcpyAsync(pl->xb(K % 3), pl->pb(), sizeof(float) * E, hipMemcpyDeviceToDevice, s), "xbar");
+            HIP_TRY(hipMemsetAsync(pl->xb((K + 2) % 3), 0, sizeof(float) * E, s), "clear");
+            if (K >= 2) HIP_TRY(hipMemsetAsync(pl->xb((K + 1) % 3), 0, sizeof(float) * E, s), "clear");
+            HIP_TRY(hipMemsetAsync(pl->hb(), 0, sizeof(float) * E, s), "clear");
+            for (int k = K; k >= 1; --k) {
+                FistaBwdArgs a{};
+                a.imgs = pl->d_imgs(); a.tiles = pl->d_tiles(); a.ntiles = ntiles; a.info = pl->d_info();
+                a.z1 = pl->zrec(k - 1); a.z2 = pl->zrec(k - 1) + pl->tot_p1;
+                const float *xa = k == 1 ? st : pl->xrec(k - 2);
+                const float *xbp = k >= 3 ? pl->xrec(k - 3) : st;
+                a.xa1 = xa; a.xa2 = xa + pl->tot_p1;
+                a.xb1 = xbp; a.xb2 = xbp + pl->tot_p1;
+                a.base1 = st; a.base2 = st + pl->tot_p1;
+                a.lam = pl->lam1(); a.f = d_f;
+                a.gx1 = pl->xb(k % 3); a.gx2 = pl->xb(k % 3) + pl->tot_p1;
+                a.ga1 = pl->xb((k + 2) % 3); a.ga2 = pl->xb((k + 2) % 3) + pl->tot_p1;
+                a.gb1 = pl->xb((k + 1) % 3); a.gb2 = pl->xb((k + 1) % 3) + pl->tot_p1;
+                a.gh1 = pl->hb(); a.gh2 = pl->hb() + pl->tot_p1;
+                a.gf = d_grad_f; a.galpha = pl->galpha();
+                a.beta = beta[k]; a.tau = (float)P.tau; a.inv_tau = (float)(1.0 / P.tau);
+                HIP_TRY(launch_fista_bwd_step(a, k >= 3, pl->rows, s), "FISTA reverse step");
+                // xbar_k is consumed; its buffer becomes xbar_{k-3}
+                if (k >= 3) HIP_TRY(hipMemsetAsync(pl->xb(k % 3), 0, sizeof(float) * E, s), "clear");
+            }
+            // pbar^n = xbar_0 + phatbar, then the interface terms
+            HIP_TRY(launch_axpy_edges(pl->xb(0), pl->hb(), pl->pb(), (long long)E, s), "pbar");
+            HIP_TRY(launch_bwd_interface(pl->d_imgs(), pl->n, pl->max_nlam, pl->d_info(), pl->hb(),
+                                         pl->hb() + pl->tot_p1, pl->pb(), pl->pb() + pl->tot_p1, pl->lb(),
+                                         (float)P.tau, (float)P.sigma, s),
+                    "interface reverse");
+        }
+    }
+    HIP_TRY(launch_alpha_reduce(pl->d_tiles(), ntiles, pl->n, pl->galpha(), d_grad_alpha, s), "alpha reduce");
+    return DTV_OK;
 }
 
 extern "C" int dtv_dd_kernel_time(const dtv_dd_plan *pl, double *avg_ms, int64_t *launches, const char **name,

@@ -24,6 +24,7 @@ struct ImgDev {
     float a_keep;        // FISTA: 1 - 1/(L tau), the weight of y in the update
     float kL;            // FISTA: 1/(alpha L), the weight of the divergence difference
     float pad0;
+    double dA, dB;       // adjoint: d(1/L)/dalpha = 8/(alpha L)^2, d(1/(alpha L))/dalpha = -1/(tau (alpha L)^2)
 };
 
 // Row / column info word: subdomain index << 2 | first << 0 | last << 1.
@@ -68,9 +69,38 @@ struct FistaStepArgs {
     const float *f;           // image (first step)
     float *c1, *c2;           // c' (written by the first step, read by the others)
     float *out1, *out2;       // x_k
+    float *z1, *z2;           // optional: z_k before the projection (recorded for the reverse pass)
     float beta;               // momentum coefficient of this step
     float tau;                // outer tau (anchor p~ -/+ tau lambda)
     float inv_tau;
+};
+
+// Reverse of one FISTA step over every subdomain (reverse mode of the
+// unrolled solve).  With zbar = xbar_k * 1{|z_k| < 1}:
+//   ybar = a_keep zbar - kL div_s^*(div_s zbar)   (the linear part of the step
+//          is self-adjoint, so this is the forward stencil applied to zbar),
+//   xbar_{k-1} += (1 + beta) ybar,  xbar_{k-2} -= beta ybar,
+//   phatbar += zbar / (L tau),  fbar -= div_s zbar / L,
+//   alphabar += -dA (<div zbar, f> + <zbar, y - phat>/tau) - dB <div zbar, div y>.
+struct FistaBwdArgs {
+    const ImgDev *imgs;
+    const StreamTile *tiles;
+    int ntiles;
+    const int *info;
+    const float *z1, *z2;      // z_k
+    const float *xa1, *xa2;    // x_{k-1}
+    const float *xb1, *xb2;    // x_{k-2} (momentum steps)
+    const float *base1, *base2;  // p~^n
+    const float *lam;          // lambda state holding lambda^{n+1}
+    const float *f;
+    const float *gx1, *gx2;    // xbar_k
+    float *ga1, *ga2;          // xbar_{k-1} (accumulated)
+    float *gb1, *gb2;          // xbar_{k-2} (accumulated, momentum steps)
+    float *gh1, *gh2;          // phatbar (accumulated)
+    float *gf;                 // fbar (accumulated)
+    double *galpha;            // per-tile partial sums of alphabar (accumulated)
+    float beta;                // beta_{k-1}
+    float tau, inv_tau;
 };
 
 struct FusedArgs {
@@ -123,5 +153,24 @@ hipError_t launch_diag(const ImgDev *imgs, int nimg, int maxH, int maxW, const i
                        double *partials, int nblk_per_img, double *out, hipStream_t s);
 int diag_blocks_per_image(int maxH, int maxW);
 hipError_t launch_fused_fista(const FusedArgs &a, int nsub, hipStream_t s);
+
+// reverse-mode kernels (kernels_bwd.hip)
+hipError_t launch_fista_bwd_step(const FistaBwdArgs &a, bool momentum, int rows, hipStream_t s);
+// u = f + div p / alpha reversed: fbar = ubar, pbar = div^*(ubar / alpha),
+// galpha[tile] += -<ubar, div p> / alpha^2
+hipError_t launch_bwd_final_u(const ImgDev *imgs, const StreamTile *tiles, int ntiles, int rows, const int *info,
+                              const float *p1, const float *p2, const float *ubar, float *fbar, float *pb1,
+                              float *pb2, double *galpha, hipStream_t s);
+// pbar = xbar_0 + phatbar (all edges)
+hipError_t launch_axpy_edges(const float *x, const float *y, float *out, long long n, hipStream_t s);
+// per interface dof: lt = lamb - tau (hb_s - hb_t); pbar_s += prevb_s + 2 sigma lt;
+// pbar_t += prevb_t - 2 sigma lt; prevb_s = -sigma lt; prevb_t = sigma lt; lamb = lt
+hipError_t launch_bwd_interface(const ImgDev *imgs, int nimg, int max_nlam, const int *info, const float *hb1,
+                                const float *hb2, float *pb1, float *pb2, float *lamb, float tau, float sigma,
+                                hipStream_t s);
+// dl/dalpha per image from the per-tile partial sums (fixed order)
+hipError_t launch_alpha_reduce(const StreamTile *tiles, int ntiles, int nimg, const double *galpha, float *out,
+                               hipStream_t s);
+
 
 }  // namespace dtv

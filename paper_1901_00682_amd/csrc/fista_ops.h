@@ -36,10 +36,16 @@ __device__ __forceinline__ float fista_cprime(float anchor, float f_b, float f_a
 // extrapolated point y = x + beta (x - x_prev)
 __device__ __forceinline__ float fista_y(float x, float x_prev, float beta) { return fmaf(beta, x - x_prev, x); }
 
+// gradient step on one edge before the projection
+__device__ __forceinline__ float fista_z(float y, float d_b, float d_a, float c, float a_keep, float kL)
+{
+    return fmaf(-kL, d_b - d_a, fmaf(a_keep, y, c));
+}
+
 // projected step on one edge
 __device__ __forceinline__ float fista_edge(float y, float d_b, float d_a, float c, float a_keep, float kL)
 {
-    return clamp1(fmaf(-kL, d_b - d_a, fmaf(a_keep, y, c)));
+    return clamp1(fista_z(y, d_b, d_a, c, a_keep, kL));
 }
 
 // unscaled divergence of a pixel from its four edge values

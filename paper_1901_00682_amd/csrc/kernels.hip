@@ -90,6 +90,8 @@ __global__ __launch_bounds__(64) void k_fista_step(FistaStepArgs a)
     const float *lam = a.lam + im.lam;
     const float *f = a.f + im.px;
     float *o1 = a.out1 + im.p1, *o2 = a.out2 + im.p2;
+    const bool rec = a.z1 != nullptr;
+    float *zr1 = rec ? a.z1 + im.p1 : nullptr, *zr2 = rec ? a.z2 + im.p2 : nullptr;
     const float beta = a.beta, tau = a.tau, itau = a.inv_tau;
     const float invL = im.invL, ak = im.a_keep, kL = im.kL;
 
@@ -155,7 +157,9 @@ __global__ __launch_bounds__(64) void k_fista_step(FistaStepArgs a)
                 } else {
                     c = c1[top * P1 + j];
                 }
-                o1[top * P1 + j] = fista_edge(yt, d_up, d, c, ak, kL);
+                const float z = fista_z(yt, d_up, d, c, ak, kL);
+                o1[top * P1 + j] = clamp1(z);
+                if (rec) zr1[top * P1 + j] = z;
             }
             if (j > 0) {  // edge left of the pixel
                 float c;
@@ -167,7 +171,9 @@ __global__ __launch_bounds__(64) void k_fista_step(FistaStepArgs a)
                 } else {
                     c = c2[i * P2 + left];
                 }
-                o2[i * P2 + left] = fista_edge(yl, d_left, d, c, ak, kL);
+                const float z = fista_z(yl, d_left, d, c, ak, kL);
+                o2[i * P2 + left] = clamp1(z);
+                if (rec) zr2[i * P2 + left] = z;
             }
             if (rlast && i < H - 1) {  // s copy below the last row of the subdomain
                 float c;
@@ -177,7 +183,9 @@ __global__ __launch_bounds__(64) void k_fista_step(FistaStepArgs a)
                 } else {
                     c = c1[(top + 1) * P1 + j];
                 }
-                o1[(top + 1) * P1 + j] = fista_edge(yb, d, 0.0f, c, ak, kL);
+                const float z = fista_z(yb, d, 0.0f, c, ak, kL);
+                o1[(top + 1) * P1 + j] = clamp1(z);
+                if (rec) zr1[(top + 1) * P1 + j] = z;
             }
             if (clast && j < W - 1) {  // s copy right of the last column
                 float c;
@@ -187,7 +195,9 @@ __global__ __launch_bounds__(64) void k_fista_step(FistaStepArgs a)
                 } else {
                     c = c2[i * P2 + left + 1];
                 }
-                o2[i * P2 + left + 1] = fista_edge(yr, d, 0.0f, c, ak, kL);
+                const float z = fista_z(yr, d, 0.0f, c, ak, kL);
+                o2[i * P2 + left + 1] = clamp1(z);
+                if (rec) zr2[i * P2 + left + 1] = z;
             }
         }
         d_up = d;

@@ -222,6 +222,18 @@ class Plan:
                                         self._stream(stream)))
         return out.reshape(self.n_images, 4)
 
+    def backward(self, f, grad_u, stream=None):
+        """Reverse mode of the last solve (which must have run with
+        save_for_backward): returns (dl/df, dl/dalpha per image)."""
+        import torch
+
+        assert f.dtype == torch.float32 and grad_u.dtype == torch.float32
+        grad_f = torch.empty_like(f)
+        grad_alpha = torch.zeros(self.n_images, dtype=torch.float32, device=self.device)
+        _check(lib().dtv_dd_backward(self.h, _ptr(f), _ptr(grad_u.contiguous()), _ptr(grad_f), _ptr(grad_alpha),
+                                     self._stream(stream)))
+        return grad_f, grad_alpha
+
     def kernel_time(self):
         ms, n, nm, b = ctypes.c_double(), ctypes.c_int64(), ctypes.c_char_p(), ctypes.c_double()
         _check(lib().dtv_dd_kernel_time(self.h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(nm), ctypes.byref(b)))
@@ -265,3 +277,55 @@ def solve(f, alpha, *, mask=None, grid=(2, 2), row_cuts=None, col_cuts=None, fid
     lam, _, _ = plan.lam_view(state)
     return {"u": plan.u_view(state), "p1": p1, "p2": p2, "lam": lam, "stats": None if stats is None else stats[0],
             "plan": plan, "state": state}
+
+
+def _torch_function():
+    import torch
+
+    class DTVDD(torch.autograd.Function):
+        """u = solve(f, alpha) with the unrolled Algorithm 1 (FISTA local
+        steps); differentiable in f and alpha through the library's reverse
+        mode with outer-step checkpoints.  f: [H, W] or [B, H, W] float32 on the
+        GPU; alpha: a scalar or [B] tensor (one weight per image)."""
+
+        @staticmethod
+        def forward(ctx, f, alpha, grid=(4, 4), n_outer=200, n_inner=5, ckpt_every=20, tau=50.0, sigma=0.01,
+                    schedule="auto"):
+            batched = f.dim() == 3
+            fb = f if batched else f.unsqueeze(0)
+            B, H, W = fb.shape
+            al = alpha.detach().reshape(-1).to("cpu", torch.float64)
+            if al.numel() == 1 and B > 1:
+                al = al.expand(B)
+            rc, cc = floor_cuts(H, grid[0]), floor_cuts(W, grid[1])
+            plan = Plan([Image(H, W, rc, cc, float(al[b])) for b in range(B)], n_outer=n_outer, n_inner=n_inner,
+                        save_for_backward=True, ckpt_every=ckpt_every, tau=tau, sigma=sigma, schedule=schedule,
+                        device=f.device)
+            fl = fb.detach().contiguous().reshape(-1).to(torch.float32)
+            state, _ = plan.solve(fl, want_stats=False)
+            u = state["u"][: B * H * W].view(B, H, W).clone()
+            ctx.plan = plan
+            ctx.batched = batched
+            ctx.alpha_shape = alpha.shape
+            ctx.alpha_device = alpha.device
+            ctx.save_for_backward(fl)
+            return u if batched else u[0]
+
+        @staticmethod
+        def backward(ctx, grad_u):
+            (fl,) = ctx.saved_tensors
+            g = grad_u.contiguous().reshape(-1).to(torch.float32)
+            gf, ga = ctx.plan.backward(fl, g)
+            gf = gf.view(grad_u.shape)
+            if ga.numel() != max(1, int(np.prod(ctx.alpha_shape))):
+                ga = ga.sum()   # one alpha shared by the whole batch
+            ga = ga.reshape(ctx.alpha_shape).to(ctx.alpha_device)
+            return gf, ga, None, None, None, None, None, None, None
+
+    return DTVDD
+
+
+def __getattr__(name):
+    if name == "DTVDD":
+        return _torch_function()
+    raise AttributeError(name)
