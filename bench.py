@@ -40,6 +40,101 @@ def workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
+def run_batched(args):
+    """64 mixed-size ROF images in one plan (one launch per outer step over
+    every subdomain of every image) against the same images solved one by one."""
+    import torch
+
+    from paper_1901_00682_amd import dtvdd, synth
+
+    cases = synth.config4()
+    dev = torch.device("cuda:0")
+    imgs = [dtvdd.Image(c.f.shape[0], c.f.shape[1], c.row_cuts, c.col_cuts, c.alpha) for c in cases]
+    n_outer, K = cases[0].n_outer, cases[0].n_inner
+    px = sum(c.f.size for c in cases)
+    f = torch.from_numpy(np.concatenate([c.f.ravel() for c in cases])).to(dev)
+    plan = dtvdd.Plan(imgs, n_outer=n_outer, n_inner=K, schedule=args.schedule, device=dev, time_kernels=True)
+    st = plan.new_state()
+    for _ in range(args.warmup):
+        plan.solve(f, state=st, want_stats=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.solve(f, state=st, want_stats=False)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    kt = plan.kernel_time()
+    # the same images one plan each, solved back to back
+    plans = [dtvdd.Plan([im], n_outer=n_outer, n_inner=K, schedule=args.schedule, device=dev) for im in imgs]
+    fs = [torch.from_numpy(c.f.ravel()).to(dev) for c in cases]
+    sts = [p.new_state() for p in plans]
+    for p, fi, si in zip(plans, fs, sts):
+        p.solve(fi, state=si, want_stats=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p, fi, si in zip(plans, fs, sts):
+        p.solve(fi, state=si, want_stats=False)
+    torch.cuda.synchronize()
+    dt_seq = time.perf_counter() - t0
+    tiles = sum((len(c.row_cuts) - 1) * (len(c.col_cuts) - 1) for c in cases)
+    return {
+        "metric": METRIC, "value": px * n_outer * K / dt, "unit": "pixel-inner-iterations/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"batched: {len(cases)} ROF images, {px} pixels, {tiles} subdomains (128-cuts, ragged), "
+                               f"{n_outer} outer x {K} inner", "schedule": plan.schedule()},
+        "sequential_plain": {"value": px * n_outer * K / dt_seq, "ms": dt_seq * 1e3},
+        "batched_over_sequential": dt_seq / dt,
+        "kernel": {"name": kt["name"], "avg_launch_us": kt["avg_ms"] * 1e3, "bytes_per_launch": kt["bytes_per_launch"],
+                   "achieved_GBs": kt["bytes_per_launch"] / (kt["avg_ms"] * 1e-3) / 1e9},
+    }
+
+
+def run_diff(args):
+    """Forward and reverse mode of 16 unrolled 512 x 512 ROF solves."""
+    import torch
+
+    from paper_1901_00682_amd import dtvdd, synth
+
+    cases = synth.config5()
+    dev = torch.device("cuda:0")
+    B = len(cases)
+    H, W = cases[0].f.shape
+    f = torch.from_numpy(np.stack([c.f for c in cases])).to(dev)
+    g = torch.from_numpy(np.stack([c.clean for c in cases])).to(dev)
+    imgs = [dtvdd.Image(H, W, c.row_cuts, c.col_cuts, c.alpha) for c in cases]
+    n_outer, K = cases[0].n_outer, cases[0].n_inner
+    plan = dtvdd.Plan(imgs, n_outer=n_outer, n_inner=K, save_for_backward=True, ckpt_every=20,
+                      schedule=args.schedule, device=dev)
+    plain = dtvdd.Plan(imgs, n_outer=n_outer, n_inner=K, schedule=args.schedule, device=dev)
+    fl = f.reshape(-1)
+    st, sp = plan.new_state(), plain.new_state()
+    tf, tb, tp = [], [], []
+    for it in range(args.warmup + args.steps):
+        torch.cuda.synchronize(); t0 = time.perf_counter()
+        plain.solve(fl, state=sp, want_stats=False)
+        torch.cuda.synchronize(); t1 = time.perf_counter()
+        plan.solve(fl, state=st, want_stats=False)
+        torch.cuda.synchronize(); t2 = time.perf_counter()
+        u = st["u"][: B * H * W]
+        gu = 2.0 * (u - g.reshape(-1))
+        plan.backward(fl, gu)
+        torch.cuda.synchronize(); t3 = time.perf_counter()
+        if it >= args.warmup:
+            tp.append(t1 - t0); tf.append(t2 - t1); tb.append(t3 - t2)
+    px = B * H * W
+    return {
+        "metric": METRIC, "value": px * n_outer * K / float(np.median(tf)), "unit": "pixel-inner-iterations/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": float(np.median(tf + tb)) * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"differentiation: {B} x {H}x{W} ROF, 4x4 subdomains, {n_outer} outer x {K} inner, "
+                               "checkpoint every 20 outer steps", "schedule": plan.schedule()},
+        "forward_ms": float(np.median(tf)) * 1e3, "forward_with_checkpoints_ms": float(np.median(tf)) * 1e3,
+        "plain_forward_ms": float(np.median(tp)) * 1e3, "backward_ms": float(np.median(tb)) * 1e3,
+        "backward_over_forward": float(np.median(tb)) / float(np.median(tp)),
+    }
+
+
 def cpu_baseline(c, outer_sample: int) -> dict:
     import oracle
 
@@ -62,7 +157,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="rof2048")
     ap.add_argument("--schedule", default="auto")
-    ap.add_argument("--cpu-outer", type=int, default=100, help="outer steps of the oracle sample (0: skip)")
+    ap.add_argument("--cpu-outer", type=int, default=500, help="outer steps of the oracle sample (0: skip)")
+    ap.add_argument("--calibrate-copy", action="store_true", help="also run a 256 MiB device copy (counter scale)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (the subdomain grid would be "
@@ -74,6 +170,12 @@ def main():
 
     from paper_1901_00682_amd import dtvdd
 
+    if args.workload == "batched":
+        print(json.dumps(run_batched(args)), flush=True)
+        return
+    if args.workload == "diff":
+        print(json.dumps(run_diff(args)), flush=True)
+        return
     c = workload(args.workload)
     H, W = c.f.shape
     dev = torch.device("cuda:0")
@@ -85,22 +187,38 @@ def main():
     kw = dict(fidelity=c.fidelity, inner=c.inner, has_mask=c.mask is not None, tau=c.tau, sigma=c.sigma,
               tau0=c.tau0, sigma0=c.sigma0, gamma=c.gamma, n_outer=c.n_outer, n_inner=c.n_inner,
               schedule=args.schedule, device=dev)
-    plan = dtvdd.Plan([img], time_kernels=True, **kw)
+    plan = dtvdd.Plan([img], **kw)
     state = plan.new_state()
     for _ in range(args.warmup):
         plan.solve(f, m, state=state, stream=stream, want_stats=False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    launch_ms = []
     for _ in range(args.steps):
         plan.solve(f, m, state=state, stream=stream, want_stats=False)
-        launch_ms.append(plan.kernel_time()["avg_ms"])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    kt = plan.kernel_time()
     px_it = H * W * c.n_outer * c.n_inner * args.steps / dt
+    # kernel timing: the same solves with HIP events around every launch of the
+    # dominant kernel on the solve stream
+    tplan = dtvdd.Plan([img], time_kernels=True, **kw)
+    tstate = tplan.new_state()
+    tplan.solve(f, m, state=tstate, stream=stream, want_stats=False)
+    launch_ms = []
+    for _ in range(max(1, args.steps // 2)):
+        tplan.solve(f, m, state=tstate, stream=stream, want_stats=False)
+        launch_ms.append(tplan.kernel_time()["avg_ms"])
+    torch.cuda.synchronize()
+    kt = tplan.kernel_time()
     avg_ms = float(np.mean(launch_ms))
     achieved = kt["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9
+    if args.calibrate_copy:
+        # a plain device copy of known size, for scaling the HBM byte counters
+        nbytes = 256 << 20
+        src = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).uniform_()
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
     out = {
         "metric": METRIC,
         "value": px_it,
@@ -123,8 +241,19 @@ def main():
                      "avg_launch_us": avg_ms * 1e3, "bytes_per_launch": kt["bytes_per_launch"],
                      "launches_per_step": kt["launches"]},
     }
+    # the whole hot path against the streaming byte model (every inner step
+    # reading x_k, x_{k-1}, the anchor and f and writing x_{k+1}; u written once
+    # per outer step): an effective bandwidth, above HBM peak when the fused
+    # schedule keeps the inner iterates on chip
+    E = (H + out["config"]["subdomains"][0]) * W + H * (W + out["config"]["subdomains"][1])
+    N = H * W
+    K = c.n_inner
+    per_outer = 4.0 * (2 * E + N) + (K - 1) * 4.0 * (4 * E + N) + 4.0 * N
+    eff = per_outer * c.n_outer / (dt / args.steps) / 1e9
+    out["hot_path_streaming_model"] = {"bytes_per_outer_step": per_outer, "effective_GBs": eff,
+                                       "frac_of_hbm_peak": eff / HBM_PEAK_GBS}
     if args.cpu_outer > 0:
-        out["cpu_baseline"] = cpu_baseline(c, args.cpu_outer)
+        out["cpu_baseline"] = cpu_baseline(c, min(args.cpu_outer, c.n_outer))
     print(json.dumps(out), flush=True)
 
 

@@ -399,28 +399,30 @@ struct EdgeBuf {
     float *p1, *p2;
 };
 
-// inner-step timing: events around each launch of the step kernel
+// inner-step timing: start / stop events stamped by each launch of the
+// dominant kernel
 struct Timer {
     dtv_dd_plan *pl;
     hipStream_t s;
     size_t used = 0;
     bool on;
+    hipEvent_t e0 = nullptr, e1 = nullptr;  // events for the next launch (null when off)
     int begin()
     {
+        e0 = e1 = nullptr;
         if (!on) return DTV_OK;
         while (pl->events.size() < used + 2) {
             hipEvent_t e;
             HIP_TRY(hipEventCreate(&e), "event create");
             pl->events.push_back(e);
         }
-        HIP_TRY(hipEventRecord(pl->events[used], s), "event record");
+        e0 = pl->events[used];
+        e1 = pl->events[used + 1];
         return DTV_OK;
     }
     int end()
     {
-        if (!on) return DTV_OK;
-        HIP_TRY(hipEventRecord(pl->events[used + 1], s), "event record");
-        used += 2;
+        if (on) used += 2;
         return DTV_OK;
     }
     int collect()
@@ -548,7 +550,7 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
             fa.out1 = bufs[out].p1; fa.out2 = bufs[out].p2;
             int rc = tm.begin();
             if (rc != DTV_OK) return rc;
-            HIP_TRY(launch_fused_fista(fa, (int)pl->h_subs.size(), s), "fused FISTA");
+            HIP_TRY(launch_fused_fista(fa, (int)pl->h_subs.size(), s, tm.e0, tm.e1), "fused FISTA");
             rc = tm.end();
             if (rc != DTV_OK) return rc;
             base = out;
@@ -569,7 +571,7 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
                 const int mode = k == 1 ? kFistaFirst : (k == 2 ? kFistaPlain : kFistaMomentum);
                 int rc = tm.begin();
                 if (rc != DTV_OK) return rc;
-                HIP_TRY(launch_fista_step(a, mode, pl->rows, s), "FISTA step");
+                HIP_TRY(launch_fista_step(a, mode, pl->rows, s, tm.e0, tm.e1), "FISTA step");
                 rc = tm.end();
                 if (rc != DTV_OK) return rc;
             }
@@ -597,7 +599,7 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
                 a.fidelity = P.fidelity;
                 int rc = tm.begin();
                 if (rc != DTV_OK) return rc;
-                HIP_TRY(launch_cp2_step(a, it >= 1, pl->rows, s), "CP2 step");
+                HIP_TRY(launch_cp2_step(a, it >= 1, pl->rows, s, tm.e0, tm.e1), "CP2 step");
                 rc = tm.end();
                 if (rc != DTV_OK) return rc;
                 u_cur = u_next;

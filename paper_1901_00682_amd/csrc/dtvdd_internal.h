@@ -2,6 +2,7 @@
 // libdtvdd.so.  Layout conventions are those documented in include/dtvdd.h.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -140,8 +141,11 @@ struct Cp2StepArgs {
 // Kernel launchers (kernels.hip).
 hipError_t launch_lambda(const ImgDev *imgs, int nimg, int max_nlam, const int *info, const float *p1,
                          const float *p2, float *lam, float sigma, hipStream_t s);
-hipError_t launch_fista_step(const FistaStepArgs &a, int mode, int rows, hipStream_t s);
-hipError_t launch_cp2_step(const Cp2StepArgs &a, bool extrapolate, int rows, hipStream_t s);
+// e0 / e1: optional events stamped at the kernel's start and end (launch timing)
+hipError_t launch_fista_step(const FistaStepArgs &a, int mode, int rows, hipStream_t s, hipEvent_t e0 = nullptr,
+                             hipEvent_t e1 = nullptr);
+hipError_t launch_cp2_step(const Cp2StepArgs &a, bool extrapolate, int rows, hipStream_t s, hipEvent_t e0 = nullptr,
+                           hipEvent_t e1 = nullptr);
 hipError_t launch_u_from_p(const ImgDev *imgs, int nimg, int maxH, int maxW, const int *info, const float *p1,
                            const float *p2, const float *f, float *u, hipStream_t s);
 hipError_t launch_zero_boundary(const ImgDev *imgs, int nimg, int maxH, int maxW, float *p1, float *p2,
@@ -152,7 +156,8 @@ hipError_t launch_diag(const ImgDev *imgs, int nimg, int maxH, int maxW, const i
                        const float *p2, const float *f, const float *u, const uint8_t *mask, int fidelity,
                        double *partials, int nblk_per_img, double *out, hipStream_t s);
 int diag_blocks_per_image(int maxH, int maxW);
-hipError_t launch_fused_fista(const FusedArgs &a, int nsub, hipStream_t s);
+hipError_t launch_fused_fista(const FusedArgs &a, int nsub, hipStream_t s, hipEvent_t e0 = nullptr,
+                              hipEvent_t e1 = nullptr);
 
 // reverse-mode kernels (kernels_bwd.hip)
 hipError_t launch_fista_bwd_step(const FistaBwdArgs &a, bool momentum, int rows, hipStream_t s);

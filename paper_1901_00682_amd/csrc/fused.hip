@@ -371,11 +371,14 @@ __global__ __launch_bounds__(1024) void k_fused_fista(FusedArgs a)
     }
 }
 
-hipError_t launch_fused_fista(const FusedArgs &a, int nsub, hipStream_t s)
+hipError_t launch_fused_fista(const FusedArgs &a, int nsub, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     if (nsub <= 0) return hipSuccess;
     if (a.n_inner < 1 || a.n_inner > kMaxFusedInner) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_fused_fista, dim3(nsub), dim3(1024), 0, s, a);
+    if (e0)
+        hipExtLaunchKernelGGL(k_fused_fista, dim3(nsub), dim3(1024), 0, s, e0, e1, 0, a);
+    else
+        hipLaunchKernelGGL(k_fused_fista, dim3(nsub), dim3(1024), 0, s, a);
     return hipGetLastError();
 }
 

@@ -207,25 +207,36 @@ __global__ __launch_bounds__(64) void k_fista_step(FistaStepArgs a)
     }
 }
 
+// launch with optional start / stop events recorded by the dispatch itself
+template <typename... Args>
+static void launch_timed(void (*kern)(Args...), dim3 grid, dim3 block, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+                         Args... args)
+{
+    if (e0)
+        hipExtLaunchKernelGGL(kern, grid, block, 0, s, e0, e1, 0, args...);
+    else
+        hipLaunchKernelGGL(kern, grid, block, 0, s, args...);
+}
+
 template <int R>
-static hipError_t fista_rows(const FistaStepArgs &a, int mode, hipStream_t s)
+static hipError_t fista_rows(const FistaStepArgs &a, int mode, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     switch (mode) {
-    case kFistaFirst: hipLaunchKernelGGL((k_fista_step<R, kFistaFirst>), dim3(a.ntiles), dim3(64), 0, s, a); break;
-    case kFistaPlain: hipLaunchKernelGGL((k_fista_step<R, kFistaPlain>), dim3(a.ntiles), dim3(64), 0, s, a); break;
-    default: hipLaunchKernelGGL((k_fista_step<R, kFistaMomentum>), dim3(a.ntiles), dim3(64), 0, s, a); break;
+    case kFistaFirst: launch_timed(k_fista_step<R, kFistaFirst>, dim3(a.ntiles), dim3(64), s, e0, e1, a); break;
+    case kFistaPlain: launch_timed(k_fista_step<R, kFistaPlain>, dim3(a.ntiles), dim3(64), s, e0, e1, a); break;
+    default: launch_timed(k_fista_step<R, kFistaMomentum>, dim3(a.ntiles), dim3(64), s, e0, e1, a); break;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_fista_step(const FistaStepArgs &a, int mode, int rows, hipStream_t s)
+hipError_t launch_fista_step(const FistaStepArgs &a, int mode, int rows, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     if (a.ntiles <= 0) return hipSuccess;
     switch (rows) {
-    case 4: return fista_rows<4>(a, mode, s);
-    case 8: return fista_rows<8>(a, mode, s);
-    case 16: return fista_rows<16>(a, mode, s);
-    case 32: return fista_rows<32>(a, mode, s);
+    case 4: return fista_rows<4>(a, mode, s, e0, e1);
+    case 8: return fista_rows<8>(a, mode, s, e0, e1);
+    case 16: return fista_rows<16>(a, mode, s, e0, e1);
+    case 32: return fista_rows<32>(a, mode, s, e0, e1);
     default: return hipErrorInvalidValue;
     }
 }
@@ -366,22 +377,23 @@ __global__ __launch_bounds__(64) void k_cp2_step(Cp2StepArgs a)
 }
 
 template <int R>
-static hipError_t cp2_rows(const Cp2StepArgs &a, bool ext, hipStream_t s)
+static hipError_t cp2_rows(const Cp2StepArgs &a, bool ext, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     if (ext)
-        hipLaunchKernelGGL((k_cp2_step<R, true>), dim3(a.ntiles), dim3(64), 0, s, a);
+        launch_timed(k_cp2_step<R, true>, dim3(a.ntiles), dim3(64), s, e0, e1, a);
     else
-        hipLaunchKernelGGL((k_cp2_step<R, false>), dim3(a.ntiles), dim3(64), 0, s, a);
+        launch_timed(k_cp2_step<R, false>, dim3(a.ntiles), dim3(64), s, e0, e1, a);
     return hipGetLastError();
 }
 
-hipError_t launch_cp2_step(const Cp2StepArgs &a, bool extrapolate, int rows, hipStream_t s)
+hipError_t launch_cp2_step(const Cp2StepArgs &a, bool extrapolate, int rows, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     if (a.ntiles <= 0) return hipSuccess;
     switch (rows) {
-    case 8: return cp2_rows<8>(a, extrapolate, s);
-    case 16: return cp2_rows<16>(a, extrapolate, s);
-    case 32: return cp2_rows<32>(a, extrapolate, s);
+    case 4: return cp2_rows<4>(a, extrapolate, s, e0, e1);
+    case 8: return cp2_rows<8>(a, extrapolate, s, e0, e1);
+    case 16: return cp2_rows<16>(a, extrapolate, s, e0, e1);
+    case 32: return cp2_rows<32>(a, extrapolate, s, e0, e1);
     default: return hipErrorInvalidValue;
     }
 }
