@@ -64,6 +64,7 @@ struct dtv_dd_plan {
     std::vector<int> h_info;
     std::vector<StreamTile> h_tiles;
     std::vector<SubTile> h_subs;
+    int n_full = 0;         // h_subs[0, n_full) are 128 x 128
     bool fused_ok = false;  // every subdomain fits the fused kernel
 
     // workspace layout (byte offsets)
@@ -243,6 +244,10 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
                 pl->h_subs.push_back(SubTile{b, r, c, h.rcut[r], h.ccut[c], h.rcut[r + 1] - h.rcut[r],
                                              h.ccut[c + 1] - h.ccut[c], 0});
     }
+    // full 128 x 128 subdomains first: the fused schedule runs them with a specialised kernel
+    std::stable_partition(pl->h_subs.begin(), pl->h_subs.end(),
+                          [](const SubTile &st) { return st.h == kFusedMax && st.w == kFusedMax; });
+    for (const SubTile &st : pl->h_subs) pl->n_full += st.h == kFusedMax && st.w == kFusedMax;
     pl->fused_ok = p.inner == DTV_INNER_FISTA && p.n_inner <= kMaxFusedInner;
     for (const SubTile &st : pl->h_subs)
         if (st.h > kFusedMax || st.w > kFusedMax) pl->fused_ok = false;
@@ -550,7 +555,7 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
             fa.out1 = bufs[out].p1; fa.out2 = bufs[out].p2;
             int rc = tm.begin();
             if (rc != DTV_OK) return rc;
-            HIP_TRY(launch_fused_fista(fa, (int)pl->h_subs.size(), s, tm.e0, tm.e1), "fused FISTA");
+            HIP_TRY(launch_fused_fista(fa, (int)pl->h_subs.size(), pl->n_full, s, tm.e0, tm.e1), "fused FISTA");
             rc = tm.end();
             if (rc != DTV_OK) return rc;
             base = out;

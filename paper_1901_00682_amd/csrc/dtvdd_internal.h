@@ -156,7 +156,8 @@ hipError_t launch_diag(const ImgDev *imgs, int nimg, int maxH, int maxW, const i
                        const float *p2, const float *f, const float *u, const uint8_t *mask, int fidelity,
                        double *partials, int nblk_per_img, double *out, hipStream_t s);
 int diag_blocks_per_image(int maxH, int maxW);
-hipError_t launch_fused_fista(const FusedArgs &a, int nsub, hipStream_t s, hipEvent_t e0 = nullptr,
+// subs[0, nfull) are 128 x 128 tiles (specialised kernel), subs[nfull, nsub) the others
+hipError_t launch_fused_fista(const FusedArgs &a, int nsub, int nfull, hipStream_t s, hipEvent_t e0 = nullptr,
                               hipEvent_t e1 = nullptr);
 
 // reverse-mode kernels (kernels_bwd.hip)

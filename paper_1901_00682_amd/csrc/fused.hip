@@ -21,178 +21,67 @@
 //
 // The arithmetic per edge is that of the streaming kernel (fista_ops.h), so
 // both schedules give bitwise identical results.
-#include "dtvdd_internal.h"
-#include "fista_ops.h"
+#include "fused_common.h"
 
 namespace dtv {
 
+using namespace fused;
+
 namespace {
 
-constexpr int kR = 8;         // rows per wave
-constexpr int kWaves = 16;    // 128 / kR
-
-struct FusedLds {
-    float c1[kFusedMax][kFusedMax];  // c' of the edge above pixel (il, jl)
-    float c2[kFusedMax][kFusedMax];  // c' of the edge left of pixel (il, jl)
-    float cb[kFusedMax];             // c' of the bottom boundary edges (per column)
-    float cr[kFusedMax];             // c' of the right boundary edges (per row)
-    float rx[2][kFusedMax];          // right boundary edges: the two iterate slots (per row)
-    float yt[2][kWaves][kFusedMax];  // y on the top edges of each strip's first row, one buffer per
-                                     // step parity: a strip may start the next step while the strip
-                                     // above still reads the current row
-    float dl[kWaves][kFusedMax];     // d of each strip's last row
+struct GenericStep {
+    template <bool mom>
+    __device__ __forceinline__ static void step(const Ctx &c, FusedLds &S, const Slot &X, Slot &Y, int sx, float beta)
+    {
+        fused_step<mom>(c, S, X, Y, sx, beta);
+    }
 };
 
-// lane i receives lane i - 1 (lane 0 receives 0)
-__device__ __forceinline__ float from_left(float x)
-{
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x138, 0xF, 0xF, false));
-}
+struct FullStep {
+    template <bool mom>
+    __device__ __forceinline__ static void step(const FullCtx &c, FusedLds &S, const Slot &X, Slot &Y, int sx,
+                                                float beta)
+    {
+        full_step<mom>(c, S, X, Y, sx, beta);
+    }
+};
 
-// lane i receives lane i + 1 (lane 63 receives 0)
-__device__ __forceinline__ float from_right(float x)
+// K projected-FISTA steps from x_0 in A (B holds a copy); x_K ends in A.
+// Steps 1 and 2 have no momentum (beta = 0).  Returns the LDS slot of the
+// right boundary edges that holds x_K.
+template <class Step, class C>
+__device__ __forceinline__ int run_steps(const C &c, FusedLds &S, Slot &A, Slot &B, int K, const float *beta)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x130, 0xF, 0xF, false));
+    if (K == 1) {
+        Step::template step<false>(c, S, A, B, 0, 0.0f);
+        copy_slot(A, B);
+        return 1;
+    }
+    Step::template step<false>(c, S, A, B, 0, 0.0f);
+    Step::template step<false>(c, S, B, A, 1, 0.0f);
+    int k = 3;
+    for (; k + 1 <= K; k += 2) {
+        Step::template step<true>(c, S, A, B, 0, beta[k]);
+        Step::template step<true>(c, S, B, A, 1, beta[k + 1]);
+    }
+    if (k == K) {
+        Step::template step<true>(c, S, A, B, 0, beta[K]);
+        copy_slot(A, B);
+        return 1;
+    }
+    return 0;
 }
 
 }  // namespace
 
-// iterate slot of one thread: its top (1) and left (2) edges in columns a and
-// b of its kR rows, and the bottom boundary edges of the tile (last strip)
-struct Slot {
-    float e1a[kR], e1b[kR], e2a[kR], e2b[kR];
-    float ba, bb;
-};
 
-struct Ctx {
-    int s, lane, ja, jb, il0, h, w;
-    int par;  // exchange-buffer parity of the current step
-    bool acta, actb, lastcol_a, lastcol_b, top_bnd, bot_bnd, left_bnd, right_bnd, has_bottom;
-    int rb;
-    float ak, kL;
-};
-
-// y on the edge below row r of columns a and b
-__device__ __forceinline__ void edge_below(const Ctx &c, const FusedLds &S, const Slot &Y, int r, float &ya, float &yb)
-{
-    const int il = c.il0 + r;
-    if (il == c.h - 1) {
-        ya = Y.ba;
-        yb = Y.bb;
-    } else if (r < kR - 1) {
-        ya = Y.e1a[r + 1];
-        yb = Y.e1b[r + 1];
-    } else {
-        const int sn = c.s < kWaves - 1 ? c.s + 1 : c.s;
-        ya = S.yt[c.par][sn][c.ja];
-        yb = S.yt[c.par][sn][c.jb];
-    }
-}
-
-// unscaled divergence of the two pixels of row r
-__device__ __forceinline__ void row_div(const Ctx &c, const Slot &Y, const float *RY, int r, float ya_below,
-                                        float yb_below, float &da, float &db)
-{
-    const int il = c.il0 + r;
-    float yra = Y.e2b[r];                // right edge of column a = left edge of column b
-    float yrb = from_right(Y.e2a[r]);    // right edge of column b = left edge of the next lane's column a
-    if (c.lastcol_a) yra = RY[il];
-    if (c.lastcol_b) yrb = RY[il];
-    const bool on = il < c.h;
-    da = (on && c.acta) ? div4(Y.e1a[r], ya_below, Y.e2a[r], yra) : 0.0f;
-    db = (on && c.actb) ? div4(Y.e1b[r], yb_below, Y.e2b[r], yrb) : 0.0f;
-}
-
-// One projected-FISTA step.  On entry X holds x_{k-1} and Y holds x_{k-2};
-// on exit Y holds x_k.  sx selects the LDS slot of the right boundary edges
-// that plays the role of X.
-__device__ __forceinline__ void copy_slot(Slot &dst, const Slot &src)
-{
-#pragma unroll
-    for (int r = 0; r < kR; ++r) {
-        dst.e1a[r] = src.e1a[r];
-        dst.e1b[r] = src.e1b[r];
-        dst.e2a[r] = src.e2a[r];
-        dst.e2b[r] = src.e2b[r];
-    }
-    dst.ba = src.ba;
-    dst.bb = src.bb;
-}
-
-template <bool mom>
-__device__ __forceinline__ void fused_step(const Ctx &c0, FusedLds &S, const Slot &X, Slot &Y, int sx, float beta)
-{
-    Ctx c = c0;
-    c.par = sx;
-    const float *RX = S.rx[sx];
-    float *RY = S.rx[sx ^ 1];
-    const bool lastcol = c.lastcol_a || c.lastcol_b;
-    // (1) y on every owned edge
-#pragma unroll
-    for (int r = 0; r < kR; ++r) {
-        Y.e1a[r] = mom ? fista_y(X.e1a[r], Y.e1a[r], beta) : X.e1a[r];
-        Y.e1b[r] = mom ? fista_y(X.e1b[r], Y.e1b[r], beta) : X.e1b[r];
-        Y.e2a[r] = mom ? fista_y(X.e2a[r], Y.e2a[r], beta) : X.e2a[r];
-        Y.e2b[r] = mom ? fista_y(X.e2b[r], Y.e2b[r], beta) : X.e2b[r];
-        const int il = c.il0 + r;
-        if (lastcol && il < c.h) RY[il] = mom ? fista_y(RX[il], RY[il], beta) : RX[il];
-    }
-    Y.ba = mom ? fista_y(X.ba, Y.ba, beta) : X.ba;
-    Y.bb = mom ? fista_y(X.bb, Y.bb, beta) : X.bb;
-    if (c.s > 0 && c.il0 < c.h) {
-        S.yt[sx][c.s][c.ja] = Y.e1a[0];
-        S.yt[sx][c.s][c.jb] = Y.e1b[0];
-    }
-    __syncthreads();
-
-    // (2) publish d of the strip's last row
-    {
-        float ya, yb, da, db;
-        edge_below(c, S, Y, kR - 1, ya, yb);
-        row_div(c, Y, RY, kR - 1, ya, yb, da, db);
-        S.dl[c.s][c.ja] = da;
-        S.dl[c.s][c.jb] = db;
-    }
-    __syncthreads();
-
-    // (3) sweep the rows: d of the row, then the projected step on its edges
-    float dua = 0.0f, dub = 0.0f;  // d of the row above (0 above the tile: one-sided copy)
-    if (c.s > 0) {
-        dua = S.dl[c.s - 1][c.ja];
-        dub = S.dl[c.s - 1][c.jb];
-    }
-#pragma unroll
-    for (int r = 0; r < kR; ++r) {
-        const int il = c.il0 + r;
-        float ya, yb, da, db;
-        edge_below(c, S, Y, r, ya, yb);
-        row_div(c, Y, RY, r, ya, yb, da, db);
-        const float dlb = from_left(db);  // d of column a - 1 (lane 0: left of the tile, 0)
-        if (il < c.h) {
-            if (!(il == 0 && c.top_bnd)) {
-                if (c.acta) Y.e1a[r] = fista_edge(Y.e1a[r], dua, da, S.c1[il][c.ja], c.ak, c.kL);
-                if (c.actb) Y.e1b[r] = fista_edge(Y.e1b[r], dub, db, S.c1[il][c.jb], c.ak, c.kL);
-            }
-            if (c.acta && !(c.ja == 0 && c.left_bnd)) Y.e2a[r] = fista_edge(Y.e2a[r], dlb, da, S.c2[il][c.ja], c.ak, c.kL);
-            if (c.actb) Y.e2b[r] = fista_edge(Y.e2b[r], da, db, S.c2[il][c.jb], c.ak, c.kL);
-            if (c.has_bottom && r == c.rb && !c.bot_bnd) {
-                if (c.acta) Y.ba = fista_edge(Y.ba, da, 0.0f, S.cb[c.ja], c.ak, c.kL);
-                if (c.actb) Y.bb = fista_edge(Y.bb, db, 0.0f, S.cb[c.jb], c.ak, c.kL);
-            }
-            if (!c.right_bnd) {
-                if (c.lastcol_a) RY[il] = fista_edge(RY[il], da, 0.0f, S.cr[il], c.ak, c.kL);
-                if (c.lastcol_b) RY[il] = fista_edge(RY[il], db, 0.0f, S.cr[il], c.ak, c.kL);
-            }
-        }
-        dua = da;
-        dub = db;
-    }
-}
-
-__global__ __launch_bounds__(1024) void k_fused_fista(FusedArgs a)
+// kFull: every tile of the launch is 128 x 128 (the list holds the full
+// tiles first; the full launch takes that prefix, the other launch the rest)
+template <bool kFull>
+__global__ __launch_bounds__(1024) void k_fused_fista(FusedArgs a, int first)
 {
     __shared__ FusedLds S;
-    const int t = xcd_remap(blockIdx.x, gridDim.x);
+    const int t = first + xcd_remap(blockIdx.x, gridDim.x);
     const SubTile tl = a.subs[t];
     const ImgDev im = a.imgs[tl.img];
     Ctx c;
@@ -201,8 +90,8 @@ __global__ __launch_bounds__(1024) void k_fused_fista(FusedArgs a)
     c.ja = 2 * c.lane;
     c.jb = c.ja + 1;
     c.il0 = kR * c.s;
-    c.h = tl.h;
-    c.w = tl.w;
+    c.h = kFull ? kFusedMax : tl.h;
+    c.w = kFull ? kFusedMax : tl.w;
     c.acta = c.ja < c.w;
     c.actb = c.jb < c.w;
     c.lastcol_a = c.ja == c.w - 1;
@@ -322,23 +211,29 @@ __global__ __launch_bounds__(1024) void k_fused_fista(FusedArgs a)
     // steps 1 and 2 have no momentum (beta = 0); x_K ends in slot A
     const int K = a.n_inner;
     int rx_slot = 0;  // LDS slot of the right boundary edges holding x_K
-    if (K == 1) {
-        fused_step<false>(c, S, A, B, 0, 0.0f);
-        copy_slot(A, B);
-        rx_slot = 1;
+    if constexpr (kFull) {
+        FullCtx fc;
+        fc.s = c.s;
+        fc.lane = c.lane;
+        fc.ja = ja;
+        fc.il0 = il0;
+        fc.oc = il0 * kFusedMax + ja;
+        fc.oy = c.s * kFusedMax + ja;
+        fc.olr = il0 + c.lane;
+        fc.last = c.s == kWaves - 1;
+        fc.right_bnd = c.right_bnd;
+        const bool tb = c.top_bnd && c.s == 0, lb = c.left_bnd && c.lane == 0;
+        fc.lo1 = tb ? 0.0f : -1.0f;
+        fc.hi1 = tb ? 0.0f : 1.0f;
+        fc.lo2a = lb ? 0.0f : -1.0f;
+        fc.hi2a = lb ? 0.0f : 1.0f;
+        fc.lob = c.bot_bnd ? 0.0f : -1.0f;
+        fc.hib = c.bot_bnd ? 0.0f : 1.0f;
+        fc.ak = c.ak;
+        fc.kL = c.kL;
+        rx_slot = run_steps<FullStep>(fc, S, A, B, K, a.beta);
     } else {
-        fused_step<false>(c, S, A, B, 0, 0.0f);
-        fused_step<false>(c, S, B, A, 1, 0.0f);
-        int k = 3;
-        for (; k + 1 <= K; k += 2) {
-            fused_step<true>(c, S, A, B, 0, a.beta[k]);
-            fused_step<true>(c, S, B, A, 1, a.beta[k + 1]);
-        }
-        if (k == K) {
-            fused_step<true>(c, S, A, B, 0, a.beta[K]);
-            copy_slot(A, B);
-            rx_slot = 1;
-        }
+        rx_slot = run_steps<GenericStep>(c, S, A, B, K, a.beta);
     }
 
     // ---- store x_K (now in slot A) as p~^(n+1)
@@ -371,14 +266,26 @@ __global__ __launch_bounds__(1024) void k_fused_fista(FusedArgs a)
     }
 }
 
-hipError_t launch_fused_fista(const FusedArgs &a, int nsub, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
+hipError_t launch_fused_fista(const FusedArgs &a, int nsub, int nfull, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     if (nsub <= 0) return hipSuccess;
-    if (a.n_inner < 1 || a.n_inner > kMaxFusedInner) return hipErrorInvalidValue;
-    if (e0)
-        hipExtLaunchKernelGGL(k_fused_fista, dim3(nsub), dim3(1024), 0, s, e0, e1, 0, a);
-    else
-        hipLaunchKernelGGL(k_fused_fista, dim3(nsub), dim3(1024), 0, s, a);
+    if (a.n_inner < 1 || a.n_inner > kMaxFusedInner || nfull < 0 || nfull > nsub) return hipErrorInvalidValue;
+    const int npart = nsub - nfull;
+    // the timing events bracket both launches
+    if (nfull > 0) {
+        hipEvent_t stop = npart > 0 ? nullptr : e1;
+        if (e0)
+            hipExtLaunchKernelGGL(k_fused_fista<true>, dim3(nfull), dim3(1024), 0, s, e0, stop, 0, a, 0);
+        else
+            hipLaunchKernelGGL(k_fused_fista<true>, dim3(nfull), dim3(1024), 0, s, a, 0);
+    }
+    if (npart > 0) {
+        hipEvent_t start = nfull > 0 ? nullptr : e0;
+        if (e0)
+            hipExtLaunchKernelGGL(k_fused_fista<false>, dim3(npart), dim3(1024), 0, s, start, e1, 0, a, nfull);
+        else
+            hipLaunchKernelGGL(k_fused_fista<false>, dim3(npart), dim3(1024), 0, s, a, nfull);
+    }
     return hipGetLastError();
 }
 

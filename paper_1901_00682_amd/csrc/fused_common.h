@@ -1,0 +1,327 @@
+// Device code shared by the fused and the persistent FISTA kernels: the
+// on-chip layout of one subdomain tile (LDS and register slots) and one
+// projected-FISTA step over the tile.  See fused.hip for the layout.
+#pragma once
+
+#include "dtvdd_internal.h"
+#include "fista_ops.h"
+
+namespace dtv {
+namespace fused {
+
+constexpr int kR = 8;         // rows per wave
+constexpr int kWaves = 16;    // 128 / kR
+
+struct FusedLds {
+    // the small arrays first, so that their offsets fit the 16-bit immediate of LDS instructions
+    float cb[kFusedMax];             // c' of the bottom boundary edges (per column)
+    float cr[kFusedMax];             // c' of the right boundary edges (per row)
+    float rx[2][kFusedMax];          // right boundary edges: the two iterate slots (per row)
+    float yt[2][kWaves][kFusedMax];  // y on the top edges of each strip's first row, one buffer per
+                                     // step parity: a strip may start the next step while the strip
+                                     // above still reads the current row
+    float dl[kWaves][kFusedMax];     // d of each strip's last row
+    float c1[kFusedMax][kFusedMax];  // c' of the edge above pixel (il, jl)
+    float c2[kFusedMax][kFusedMax];  // c' of the edge left of pixel (il, jl)
+};
+
+// lane i receives lane i - 1 (lane 0 receives 0)
+__device__ __forceinline__ float from_left(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x138, 0xF, 0xF, false));
+}
+
+// lane i receives lane i + 1 (lane 63 receives 0)
+__device__ __forceinline__ float from_right(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x130, 0xF, 0xF, false));
+}
+
+// iterate slot of one thread: its top (1) and left (2) edges in columns a and
+// b of its kR rows, and the bottom boundary edges of the tile (last strip)
+struct Slot {
+    float e1a[kR], e1b[kR], e2a[kR], e2b[kR];
+    float ba, bb;
+};
+
+struct Ctx {
+    int s, lane, ja, jb, il0, h, w;
+    int par;  // exchange-buffer parity of the current step
+    bool acta, actb, lastcol_a, lastcol_b, top_bnd, bot_bnd, left_bnd, right_bnd, has_bottom;
+    int rb;
+    float ak, kL;
+};
+
+// y on the edge below row r of columns a and b
+__device__ __forceinline__ void edge_below(const Ctx &c, const FusedLds &S, const Slot &Y, int r, float &ya, float &yb)
+{
+    const int il = c.il0 + r;
+    if (il == c.h - 1) {
+        ya = Y.ba;
+        yb = Y.bb;
+    } else if (r < kR - 1) {
+        ya = Y.e1a[r + 1];
+        yb = Y.e1b[r + 1];
+    } else {
+        const int sn = c.s < kWaves - 1 ? c.s + 1 : c.s;
+        ya = S.yt[c.par][sn][c.ja];
+        yb = S.yt[c.par][sn][c.jb];
+    }
+}
+
+// unscaled divergence of the two pixels of row r
+__device__ __forceinline__ void row_div(const Ctx &c, const Slot &Y, const float *RY, int r, float ya_below,
+                                        float yb_below, float &da, float &db)
+{
+    const int il = c.il0 + r;
+    float yra = Y.e2b[r];                // right edge of column a = left edge of column b
+    float yrb = from_right(Y.e2a[r]);    // right edge of column b = left edge of the next lane's column a
+    if (c.lastcol_a) yra = RY[il];
+    if (c.lastcol_b) yrb = RY[il];
+    const bool on = il < c.h;
+    da = (on && c.acta) ? div4(Y.e1a[r], ya_below, Y.e2a[r], yra) : 0.0f;
+    db = (on && c.actb) ? div4(Y.e1b[r], yb_below, Y.e2b[r], yrb) : 0.0f;
+}
+
+// One projected-FISTA step.  On entry X holds x_{k-1} and Y holds x_{k-2};
+// on exit Y holds x_k.  sx selects the LDS slot of the right boundary edges
+// that plays the role of X.
+__device__ __forceinline__ void copy_slot(Slot &dst, const Slot &src)
+{
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+        dst.e1a[r] = src.e1a[r];
+        dst.e1b[r] = src.e1b[r];
+        dst.e2a[r] = src.e2a[r];
+        dst.e2b[r] = src.e2b[r];
+    }
+    dst.ba = src.ba;
+    dst.bb = src.bb;
+}
+
+template <bool mom>
+__device__ __forceinline__ void fused_step(const Ctx &c0, FusedLds &S, const Slot &X, Slot &Y, int sx, float beta)
+{
+    Ctx c = c0;
+    c.par = sx;
+    const float *RX = S.rx[sx];
+    float *RY = S.rx[sx ^ 1];
+    const bool lastcol = c.lastcol_a || c.lastcol_b;
+    // (1) y on every owned edge
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+        Y.e1a[r] = mom ? fista_y(X.e1a[r], Y.e1a[r], beta) : X.e1a[r];
+        Y.e1b[r] = mom ? fista_y(X.e1b[r], Y.e1b[r], beta) : X.e1b[r];
+        Y.e2a[r] = mom ? fista_y(X.e2a[r], Y.e2a[r], beta) : X.e2a[r];
+        Y.e2b[r] = mom ? fista_y(X.e2b[r], Y.e2b[r], beta) : X.e2b[r];
+        const int il = c.il0 + r;
+        if (lastcol && il < c.h) RY[il] = mom ? fista_y(RX[il], RY[il], beta) : RX[il];
+    }
+    Y.ba = mom ? fista_y(X.ba, Y.ba, beta) : X.ba;
+    Y.bb = mom ? fista_y(X.bb, Y.bb, beta) : X.bb;
+    if (c.s > 0 && c.il0 < c.h) {
+        S.yt[sx][c.s][c.ja] = Y.e1a[0];
+        S.yt[sx][c.s][c.jb] = Y.e1b[0];
+    }
+    __syncthreads();
+
+    // (2) publish d of the strip's last row
+    {
+        float ya, yb, da, db;
+        edge_below(c, S, Y, kR - 1, ya, yb);
+        row_div(c, Y, RY, kR - 1, ya, yb, da, db);
+        S.dl[c.s][c.ja] = da;
+        S.dl[c.s][c.jb] = db;
+    }
+    __syncthreads();
+
+    // (3) sweep the rows: d of the row, then the projected step on its edges
+    float dua = 0.0f, dub = 0.0f;  // d of the row above (0 above the tile: one-sided copy)
+    if (c.s > 0) {
+        dua = S.dl[c.s - 1][c.ja];
+        dub = S.dl[c.s - 1][c.jb];
+    }
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+        const int il = c.il0 + r;
+        float ya, yb, da, db;
+        edge_below(c, S, Y, r, ya, yb);
+        row_div(c, Y, RY, r, ya, yb, da, db);
+        const float dlb = from_left(db);  // d of column a - 1 (lane 0: left of the tile, 0)
+        if (il < c.h) {
+            if (!(il == 0 && c.top_bnd)) {
+                if (c.acta) Y.e1a[r] = fista_edge(Y.e1a[r], dua, da, S.c1[il][c.ja], c.ak, c.kL);
+                if (c.actb) Y.e1b[r] = fista_edge(Y.e1b[r], dub, db, S.c1[il][c.jb], c.ak, c.kL);
+            }
+            if (c.acta && !(c.ja == 0 && c.left_bnd)) Y.e2a[r] = fista_edge(Y.e2a[r], dlb, da, S.c2[il][c.ja], c.ak, c.kL);
+            if (c.actb) Y.e2b[r] = fista_edge(Y.e2b[r], da, db, S.c2[il][c.jb], c.ak, c.kL);
+            if (c.has_bottom && r == c.rb && !c.bot_bnd) {
+                if (c.acta) Y.ba = fista_edge(Y.ba, da, 0.0f, S.cb[c.ja], c.ak, c.kL);
+                if (c.actb) Y.bb = fista_edge(Y.bb, db, 0.0f, S.cb[c.jb], c.ak, c.kL);
+            }
+            if (!c.right_bnd) {
+                if (c.lastcol_a) RY[il] = fista_edge(RY[il], da, 0.0f, S.cr[il], c.ak, c.kL);
+                if (c.lastcol_b) RY[il] = fista_edge(RY[il], db, 0.0f, S.cr[il], c.ak, c.kL);
+            }
+        }
+        dua = da;
+        dub = db;
+    }
+}
+
+// ---- full tiles (h = w = 128) ----------------------------------------------
+// Every thread owns two columns inside the tile and eight rows inside it, so
+// the per-element guards of fused_step drop out and the few special edges are
+// handled without divergent branches: the tile's top row (strip 0) and bottom
+// row (strip 15) by wave-uniform branches, the left edges of column 0 by
+// clamp bounds that collapse to 0 on the image boundary, and the right
+// boundary column by lanes 0..7 of each strip after the row sweep (lane r
+// updates row 8 s + r from the last column's d, gathered with lane moves).
+
+struct FullCtx {
+    int s, lane, ja, il0;
+    // LDS element offsets il0 * 128 + ja, s * 128 + ja and il0 + lane.  full_step
+    // passes them through opaque() once per step, so that each LDS access is a
+    // base register plus an immediate offset computed inside the step, rather
+    // than an address register hoisted out of the step loop and kept live.
+    int oc, oy, olr;
+    bool last;       // strip 15: owns the tile's bottom boundary edges
+    bool right_bnd;  // the tile's right boundary edges lie on the image boundary
+    // clamp bounds, (-1, 1) or (0, 0) for edges on the image boundary: the
+    // top edges of the strip's first row, the left edge of column a, the
+    // tile's bottom edges
+    float lo1, hi1, lo2a, hi2a, lob, hib;
+    float ak, kL;
+};
+
+__device__ __forceinline__ int opaque(int x)
+{
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
+// Marks four values as used here: their computation cannot sink below this
+// point (the compiler otherwise moves every row update next to its use in the
+// following step and keeps all rows' temporaries alive at once).
+__device__ __forceinline__ void pin4(float &a, float &b, float &c, float &d)
+{
+    asm volatile("" : "+v"(a), "+v"(b), "+v"(c), "+v"(d));
+}
+
+// 8-byte LDS access; p is 8-byte aligned (an even column of a row)
+__device__ __forceinline__ void lds_ld2(const float *p, float &x, float &y)
+{
+    const float2 v = *reinterpret_cast<const float2 *>(__builtin_assume_aligned(p, 8));
+    x = v.x;
+    y = v.y;
+}
+
+__device__ __forceinline__ void lds_st2(float *p, float x, float y)
+{
+    *reinterpret_cast<float2 *>(__builtin_assume_aligned(p, 8)) = make_float2(x, y);
+}
+
+// lane i receives lane i + 1; lane 63 receives edge
+__device__ __forceinline__ float from_right_or(float x, float edge)
+{
+    return __int_as_float(
+        __builtin_amdgcn_update_dpp(__float_as_int(edge), __float_as_int(x), 0x130, 0xF, 0xF, false));
+}
+
+// unscaled divergence of the two pixels of row r of a full tile; RYr points
+// at the right boundary edge of the strip's first row
+__device__ __forceinline__ void full_row_div(const Slot &Y, const float *RYr, int r, float ya_below, float yb_below,
+                                             float &da, float &db)
+{
+    const float yrb = from_right_or(Y.e2a[r], RYr[r]);
+    da = div4(Y.e1a[r], ya_below, Y.e2a[r], Y.e2b[r]);
+    db = div4(Y.e1b[r], yb_below, Y.e2b[r], yrb);
+}
+
+// fused_step on a full tile; same arithmetic per edge, hence the same result
+template <bool mom>
+__device__ __forceinline__ void full_step(const FullCtx &c, FusedLds &S, const Slot &X, Slot &Y, int sx, float beta)
+{
+    // The phases are written without branches wherever a select does the job:
+    // a branch splits the step into blocks and the compiler then sinks the row
+    // updates towards their next use, keeping every row's temporaries alive.
+    const int oc = opaque(c.oc), oy = opaque(c.oy), olr = opaque(c.olr), orow = opaque(c.il0);
+    const float *RX = S.rx[sx];
+    float *RY = S.rx[sx ^ 1];
+    const float ak = c.ak, kL = c.kL;
+    // (1) y on every owned edge; lanes 0..7 take the right boundary edges of the strip's rows
+    if (c.lane < kR) RY[olr] = mom ? fista_y(RX[olr], RY[olr], beta) : RX[olr];
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+        Y.e1a[r] = mom ? fista_y(X.e1a[r], Y.e1a[r], beta) : X.e1a[r];
+        Y.e1b[r] = mom ? fista_y(X.e1b[r], Y.e1b[r], beta) : X.e1b[r];
+        Y.e2a[r] = mom ? fista_y(X.e2a[r], Y.e2a[r], beta) : X.e2a[r];
+        Y.e2b[r] = mom ? fista_y(X.e2b[r], Y.e2b[r], beta) : X.e2b[r];
+        pin4(Y.e1a[r], Y.e1b[r], Y.e2a[r], Y.e2b[r]);
+    }
+    Y.ba = mom ? fista_y(X.ba, Y.ba, beta) : X.ba;  // meaningful in strip 15 only
+    Y.bb = mom ? fista_y(X.bb, Y.bb, beta) : X.bb;
+    float *yt = &S.yt[sx][0][0] + oy;  // this strip's row of the exchange buffer (strip 0's is unused)
+    lds_st2(yt, Y.e1a[0], Y.e1b[0]);
+    __syncthreads();
+
+    // (2) d of the strip's last row, published for the strip below
+    const float *RYr = RY + orow;
+    float ya7, yb7;  // y on the edges below the last row
+    lds_ld2(yt + kFusedMax, ya7, yb7);  // strip 15 reads a neighbouring array here and discards it
+    ya7 = c.last ? Y.ba : ya7;
+    yb7 = c.last ? Y.bb : yb7;
+    float *dl = &S.dl[0][0] + oy;
+    {
+        float da7, db7;
+        full_row_div(Y, RYr, kR - 1, ya7, yb7, da7, db7);
+        lds_st2(dl, da7, db7);
+    }
+    __syncthreads();
+
+    // (3) row sweep
+    float dua, dub;  // d of the row above (0 above the tile)
+    lds_ld2(dl - kFusedMax, dua, dub);  // strip 0 reads a neighbouring array here and discards it
+    dua = c.s > 0 ? dua : 0.0f;
+    dub = c.s > 0 ? dub : 0.0f;
+    const float *c1 = &S.c1[0][0] + oc, *c2 = &S.c2[0][0] + oc;
+    float dR = 0.0f;  // lane r: d of the last column in row r
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+        __builtin_amdgcn_sched_barrier(0);  // one row at a time: bounds the registers in flight
+        float da, db;
+        if (r < kR - 1) full_row_div(Y, RYr, r, Y.e1a[r + 1], Y.e1b[r + 1], da, db);
+        else full_row_div(Y, RYr, r, ya7, yb7, da, db);
+        const float dlb = from_left(db);
+        float c1a, c1b, c2a, c2b;
+        lds_ld2(c1 + r * kFusedMax, c1a, c1b);
+        lds_ld2(c2 + r * kFusedMax, c2a, c2b);
+        if (r == 0) {  // the top edges of the tile collapse to 0 on the image boundary
+            Y.e1a[r] = __builtin_amdgcn_fmed3f(fista_z(Y.e1a[r], dua, da, c1a, ak, kL), c.lo1, c.hi1);
+            Y.e1b[r] = __builtin_amdgcn_fmed3f(fista_z(Y.e1b[r], dub, db, c1b, ak, kL), c.lo1, c.hi1);
+        } else {
+            Y.e1a[r] = fista_edge(Y.e1a[r], dua, da, c1a, ak, kL);
+            Y.e1b[r] = fista_edge(Y.e1b[r], dub, db, c1b, ak, kL);
+        }
+        Y.e2a[r] = __builtin_amdgcn_fmed3f(fista_z(Y.e2a[r], dlb, da, c2a, ak, kL), c.lo2a, c.hi2a);
+        Y.e2b[r] = fista_edge(Y.e2b[r], da, db, c2b, ak, kL);
+        if (r == kR - 1) {  // bottom boundary edges of the tile (strip 15, unless on the image boundary)
+            float cba, cbb;
+            lds_ld2(S.cb + (oy - c.s * kFusedMax), cba, cbb);
+            // only strip 15 uses them; they collapse to 0 on the image boundary
+            Y.ba = __builtin_amdgcn_fmed3f(fista_z(Y.ba, da, 0.0f, cba, ak, kL), c.lob, c.hib);
+            Y.bb = __builtin_amdgcn_fmed3f(fista_z(Y.bb, db, 0.0f, cbb, ak, kL), c.lob, c.hib);
+        }
+        {
+            const float dlast = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(db), 63));
+            dR = c.lane == r ? dlast : dR;
+        }
+        pin4(Y.e1a[r], Y.e1b[r], Y.e2a[r], Y.e2b[r]);
+        dua = da;
+        dub = db;
+    }
+    if (!c.right_bnd && c.lane < kR) RY[olr] = fista_edge(RY[olr], dR, 0.0f, S.cr[olr], ak, kL);
+}
+
+}  // namespace fused
+}  // namespace dtv

@@ -149,6 +149,7 @@ class Plan:
         h = ctypes.c_void_p()
         _check(L.dtv_dd_setup(descs, len(self.images), ctypes.byref(self.params), ctypes.byref(h)))
         self.h = h
+        self._L = L
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         self.ws = None
         if bind:
@@ -159,8 +160,9 @@ class Plan:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h is not None and h.value:
-            lib().dtv_dd_destroy(h)
+        L = getattr(self, "_L", None)  # held by the plan: module globals may be gone at interpreter exit
+        if h is not None and h.value and L is not None:
+            L.dtv_dd_destroy(h)
             self.h = None
 
     @property

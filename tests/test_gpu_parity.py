@@ -87,16 +87,28 @@ def test_parity_small(name):
             assert np.array_equal(got["stream"][q], got["fused"][q]), q
 
 
-@pytest.mark.parametrize("K", [1, 2, 3, 4, 5, 7])
-def test_fused_equals_stream_bitwise(K):
+FUSED_GEOMS = {
+    # ragged tiles beside full 128 x 128 ones (interfaces on all four sides of one)
+    "mixed": (300, 357, [0, 128, 256, 300], [0, 101, 229, 357]),
+    # 3 x 3 full tiles: every combination of image-boundary sides, and an interior tile
+    "full3x3": (384, 384, [0, 128, 256, 384], [0, 128, 256, 384]),
+    # one full tile bounded by the image on all sides
+    "full1x1": (128, 128, [0, 128], [0, 128]),
+}
+
+
+@pytest.mark.parametrize("geom,K", [("mixed", k) for k in (1, 2, 3, 4, 5, 7)]
+                         + [("full3x3", k) for k in (1, 2, 5, 6)] + [("full1x1", 3)])
+def test_fused_equals_stream_bitwise(geom, K):
     """The two schedules of the FISTA local solves round identically: full
-    128 x 128 subdomains with interfaces on every side, ragged ones, and every
-    parity of the inner count."""
-    rng = np.random.default_rng(100 + K)
-    H, W = 300, 357
-    rc, cc = np.array([0, 128, 256, 300]), np.array([0, 101, 229, 357])
+    128 x 128 subdomains (the specialised kernel) with image boundaries and
+    interfaces on every combination of sides, ragged ones, and every parity of
+    the inner count."""
+    rng = np.random.default_rng(100 + K + 1000 * list(FUSED_GEOMS).index(geom))
+    H, W, rc, cc = FUSED_GEOMS[geom]
+    rc, cc = np.array(rc), np.array(cc)
     f = (synth.shapes(H, W, rng) + synth.gaussian((H, W), 0.1, rng)).astype(np.float32)
-    _say(f"[fused==stream] {H}x{W} K={K}")
+    _say(f"[fused==stream] {geom} {H}x{W} K={K}")
     res = {}
     for sch in ("stream", "fused"):
         plan, state, _, _, _ = run_gpu(f, 8.0, rc, cc, n_outer=6, n_inner=K, schedule=sch)
