@@ -81,6 +81,10 @@ extern "C" {
 #define DTV_SCHED_STREAM 1   /* one launch per inner step over all subdomains */
 #define DTV_SCHED_FUSED 2    /* one workgroup per subdomain runs all inner steps on chip
                                 (FISTA, subdomains up to 128 x 128) */
+#define DTV_SCHED_PERSIST 3  /* one cooperative launch runs every outer step; the iterates stay
+                                on chip between outer steps (FISTA, every subdomain exactly
+                                128 x 128, all of them resident on the device at once, no
+                                diagnostics, no save_for_backward) */
 
 typedef struct dtv_dd_plan dtv_dd_plan; /* opaque, owned by the library */
 
@@ -177,7 +181,7 @@ int dtv_dd_backward(dtv_dd_plan *plan, const float *d_f, const float *d_grad_u, 
 int dtv_dd_kernel_time(const dtv_dd_plan *plan, double *avg_ms, int64_t *launches, const char **name,
                        double *bytes_per_launch);
 
-/* The schedule the plan will use (DTV_SCHED_STREAM or DTV_SCHED_FUSED). */
+/* The schedule the plan will use (DTV_SCHED_STREAM, DTV_SCHED_FUSED or DTV_SCHED_PERSIST). */
 int dtv_dd_schedule(const dtv_dd_plan *plan, int32_t *schedule);
 
 void dtv_dd_destroy(dtv_dd_plan *plan);

@@ -66,10 +66,11 @@ struct dtv_dd_plan {
     std::vector<SubTile> h_subs;
     int n_full = 0;         // h_subs[0, n_full) are 128 x 128
     bool fused_ok = false;  // every subdomain fits the fused kernel
+    bool persist_ok = false;  // the persistent schedule applies (full tiles, all resident, no per-step host work)
 
     // workspace layout (byte offsets)
     size_t off_imgs = 0, off_info = 0, off_tiles = 0, off_subs = 0, off_buf[3] = {0, 0, 0}, off_u2 = 0,
-           off_part = 0, off_dout = 0, ws_bytes = 0;
+           off_part = 0, off_dout = 0, off_xch = 0, off_sync = 0, ws_bytes = 0;
     int diag_nblk = 0;
     char *ws = nullptr;
     double *h_diag = nullptr;  // pinned host mirror of the diagnostics sums
@@ -113,6 +114,8 @@ struct dtv_dd_plan {
     float *lb() const { return (float *)(ws + off_lb); }
     double *galpha() const { return (double *)(ws + off_galpha); }
     double *dout() const { return (double *)(ws + off_dout); }
+    unsigned long long *xch() const { return (unsigned long long *)(ws + off_xch); }
+    unsigned *sync_words() const { return (unsigned *)(ws + off_sync); }  // error flag of the persistent kernel
 };
 
 // ---------------------------------------------------------------------------
@@ -160,7 +163,7 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
     if (p.save_for_backward && (p.inner != DTV_INNER_FISTA || p.ckpt_every < 1))
         return fail(DTV_EINVAL, "save_for_backward needs FISTA and ckpt_every >= 1");
     if (p.save_for_backward && p.gap_tol > 0.0) return fail(DTV_EINVAL, "save_for_backward needs fixed iteration counts");
-    if (p.schedule < DTV_SCHED_AUTO || p.schedule > DTV_SCHED_FUSED) return fail(DTV_EINVAL, "unknown schedule");
+    if (p.schedule < DTV_SCHED_AUTO || p.schedule > DTV_SCHED_PERSIST) return fail(DTV_EINVAL, "unknown schedule");
 
     dtv_dd_plan *pl = new dtv_dd_plan();
     pl->prm = p;
@@ -255,6 +258,20 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
         delete pl;
         return fail(DTV_EINVAL, "the fused schedule needs FISTA, n_inner <= 64 and subdomains of at most 128 x 128");
     }
+    {
+        const int nsub = (int)pl->h_subs.size();
+        pl->persist_ok = pl->fused_ok && nsub > 0 && pl->n_full == nsub && p.diag_every == 0 && !p.save_for_backward;
+        int dev = 0;
+        if (pl->persist_ok && hipGetDevice(&dev) == hipSuccess)
+            pl->persist_ok = persist_supported(dev) && nsub <= persist_capacity(dev);
+        else
+            pl->persist_ok = false;
+    }
+    if (p.schedule == DTV_SCHED_PERSIST && !pl->persist_ok) {
+        delete pl;
+        return fail(DTV_EINVAL, "the persistent schedule needs FISTA, n_inner <= 64, every subdomain 128 x 128, all "
+                                "subdomains resident on the device at once, diag_every = 0 and no save_for_backward");
+    }
 
     // workspace layout
     size_t off = 0;
@@ -272,6 +289,8 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
     pl->diag_nblk = diag_blocks_per_image(pl->maxH, pl->maxW);
     pl->off_part = take(sizeof(double) * 6 * (size_t)pl->diag_nblk * n_images);
     pl->off_dout = take(sizeof(double) * 6 * (size_t)n_images);
+    pl->off_xch = take(pl->persist_ok ? sizeof(unsigned long long) * 2 * (size_t)pl->tot_lam : 0);
+    pl->off_sync = take(2 * sizeof(unsigned));
     if (p.save_for_backward) {
         const size_t E = (size_t)(pl->tot_p1 + pl->tot_p2);
         pl->state_floats = E + (size_t)pl->tot_lam;
@@ -290,8 +309,10 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
         pl->off_galpha = take(sizeof(double) * pl->h_tiles.size());
     }
     pl->ws_bytes = off;
-    pl->schedule = p.schedule == DTV_SCHED_STREAM ? DTV_SCHED_STREAM
-                 : (p.schedule == DTV_SCHED_FUSED || pl->fused_ok) ? DTV_SCHED_FUSED : DTV_SCHED_STREAM;
+    if (p.schedule != DTV_SCHED_AUTO)
+        pl->schedule = p.schedule;
+    else
+        pl->schedule = pl->persist_ok ? DTV_SCHED_PERSIST : pl->fused_ok ? DTV_SCHED_FUSED : DTV_SCHED_STREAM;
     *out = pl;
     g_err.clear();
     return DTV_OK;
@@ -459,7 +480,8 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
     hipStream_t s = (hipStream_t)stream;
     const uint8_t *mask = P.has_mask ? d_mask : nullptr;
     const bool cp2 = P.inner == DTV_INNER_CP2;
-    const bool fused = pl->schedule == DTV_SCHED_FUSED;
+    const bool fused = pl->schedule == DTV_SCHED_FUSED || pl->schedule == DTV_SCHED_PERSIST;
+    const bool persist = pl->schedule == DTV_SCHED_PERSIST;
     const int K = P.n_inner;
 
     if (!P.warm_start) {
@@ -539,7 +561,35 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
     };
     pl->saved = false;
 
-    for (int n = 0; n < P.n_outer; ++n) {
+    if (persist && P.n_outer > 0) {
+        // every outer step in one cooperative launch; p~ and lambda updated in place
+        unsigned *sync = pl->sync_words();
+        HIP_TRY(hipMemsetAsync(sync, 0, 2 * sizeof(unsigned), s), "clear error flag");
+        HIP_TRY(hipMemsetAsync(pl->xch(), 0, sizeof(unsigned long long) * 2 * (size_t)pl->tot_lam, s), "clear exchange");
+        PersistArgs pa{};
+        pa.fa = fa;
+        pa.fa.base1 = pa.fa.out1 = d_p1;
+        pa.fa.base2 = pa.fa.out2 = d_p2;
+        pa.lam_out = d_lambda;
+        pa.xch = pl->xch();
+        pa.xch_stride = pl->tot_lam;
+        pa.err = (int *)sync;
+        pa.n_outer = P.n_outer;
+        pa.sigma = (float)P.sigma;
+        int rc = tm.begin();
+        if (rc != DTV_OK) return rc;
+        if (tm.e0) HIP_TRY(hipEventRecord(tm.e0, s), "event");
+        HIP_TRY(launch_persist_fista(pa, (int)pl->h_subs.size(), s), "persistent FISTA");
+        if (tm.e1) HIP_TRY(hipEventRecord(tm.e1, s), "event");
+        rc = tm.end();
+        if (rc != DTV_OK) return rc;
+        int err = 0;
+        HIP_TRY(hipMemcpyAsync(&err, sync, sizeof(int), hipMemcpyDeviceToHost, s), "exchange status");
+        HIP_TRY(hipStreamSynchronize(s), "exchange status");
+        if (err) return fail(DTV_EHIP, "persistent FISTA: a wait for a neighbouring subdomain timed out");
+    }
+
+    for (int n = 0; n < (persist ? 0 : P.n_outer); ++n) {
         if (P.save_for_backward && n % P.ckpt_every == 0) {
             int rc = save_state(n / P.ckpt_every, bufs[base]);
             if (rc != DTV_OK) return rc;
@@ -781,7 +831,8 @@ extern "C" int dtv_dd_kernel_time(const dtv_dd_plan *pl, double *avg_ms, int64_t
     if (launches) *launches = pl->t_count;
     const bool cp2 = pl->prm.inner == DTV_INNER_CP2;
     const bool fused = pl->schedule == DTV_SCHED_FUSED;
-    if (name) *name = fused ? "k_fused_fista" : (cp2 ? "k_cp2_step" : "k_fista_step");
+    const bool persist = pl->schedule == DTV_SCHED_PERSIST;
+    if (name) *name = persist ? "k_persist_fista" : fused ? "k_fused_fista" : (cp2 ? "k_cp2_step" : "k_fista_step");
     if (bytes_per_launch) {
         // Algorithmic HBM bytes of one timed launch (E = edge dofs of the torn
         // p~, N = pixels, 4 bytes each), averaged over the launches of an outer step.
@@ -799,7 +850,13 @@ extern "C" int dtv_dd_kernel_time(const dtv_dd_plan *pl, double *avg_ms, int64_t
         const int K = pl->prm.n_inner;
         const double mb = pl->prm.has_mask ? N : 0.0;
         double tot = 0.0;
-        if (fused) {
+        double lam = 0.0;  // multipliers
+        for (const ImgHost &h : pl->imgs) lam += (double)(h.ny - 1) * h.W + (double)(h.nx - 1) * h.H;
+        if (persist) {
+            // one launch for the whole solve: read p~^0, f and the lambda state, write p~^N and the
+            // lambda state, and per outer step publish and read back two extrapolated copies per multiplier
+            *bytes_per_launch = 4.0 * (2 * E + N + 6 * lam + 4 * lam * pl->prm.n_outer);
+        } else if (fused) {
             *bytes_per_launch = 4.0 * (2 * E + N);
         } else {
             for (int k = 1; k <= K; ++k) {

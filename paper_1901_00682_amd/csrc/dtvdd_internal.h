@@ -156,6 +156,21 @@ hipError_t launch_diag(const ImgDev *imgs, int nimg, int maxH, int maxW, const i
                        const float *p2, const float *f, const float *u, const uint8_t *mask, int fidelity,
                        double *partials, int nblk_per_img, double *out, hipStream_t s);
 int diag_blocks_per_image(int maxH, int maxW);
+// Persistent schedule: every outer step in one cooperative launch (persist.hip).
+// All subdomains are full 128 x 128 tiles and the grid fits on the device at once.
+struct PersistArgs {
+    FusedArgs fa;          // base = p~^0 (read), out = p~^N (written; may alias base), lam = lambda state in
+    float *lam_out;        // lambda state out (may alias fa.lam)
+    unsigned long long *xch;  // exchange words of the extrapolated copies: 2 slots of xch_stride, zero at launch
+    long long xch_stride;     // >= length of the lambda state
+    int *err;                 // set to 1 when a wait for a neighbour times out, 0 at launch
+    int n_outer;
+    float sigma;
+};
+bool persist_supported(int device);
+int persist_capacity(int device);  // workgroups of the persistent kernel resident at once
+hipError_t launch_persist_fista(const PersistArgs &a, int nsub, hipStream_t s);
+
 // subs[0, nfull) are 128 x 128 tiles (specialised kernel), subs[nfull, nsub) the others
 hipError_t launch_fused_fista(const FusedArgs &a, int nsub, int nfull, hipStream_t s, hipEvent_t e0 = nullptr,
                               hipEvent_t e1 = nullptr);

@@ -27,52 +27,6 @@ namespace dtv {
 
 using namespace fused;
 
-namespace {
-
-struct GenericStep {
-    template <bool mom>
-    __device__ __forceinline__ static void step(const Ctx &c, FusedLds &S, const Slot &X, Slot &Y, int sx, float beta)
-    {
-        fused_step<mom>(c, S, X, Y, sx, beta);
-    }
-};
-
-struct FullStep {
-    template <bool mom>
-    __device__ __forceinline__ static void step(const FullCtx &c, FusedLds &S, const Slot &X, Slot &Y, int sx,
-                                                float beta)
-    {
-        full_step<mom>(c, S, X, Y, sx, beta);
-    }
-};
-
-// K projected-FISTA steps from x_0 in A (B holds a copy); x_K ends in A.
-// Steps 1 and 2 have no momentum (beta = 0).  Returns the LDS slot of the
-// right boundary edges that holds x_K.
-template <class Step, class C>
-__device__ __forceinline__ int run_steps(const C &c, FusedLds &S, Slot &A, Slot &B, int K, const float *beta)
-{
-    if (K == 1) {
-        Step::template step<false>(c, S, A, B, 0, 0.0f);
-        copy_slot(A, B);
-        return 1;
-    }
-    Step::template step<false>(c, S, A, B, 0, 0.0f);
-    Step::template step<false>(c, S, B, A, 1, 0.0f);
-    int k = 3;
-    for (; k + 1 <= K; k += 2) {
-        Step::template step<true>(c, S, A, B, 0, beta[k]);
-        Step::template step<true>(c, S, B, A, 1, beta[k + 1]);
-    }
-    if (k == K) {
-        Step::template step<true>(c, S, A, B, 0, beta[K]);
-        copy_slot(A, B);
-        return 1;
-    }
-    return 0;
-}
-
-}  // namespace
 
 
 // kFull: every tile of the launch is 128 x 128 (the list holds the full

@@ -323,5 +323,64 @@ __device__ __forceinline__ void full_step(const FullCtx &c, FusedLds &S, const S
     if (!c.right_bnd && c.lane < kR) RY[olr] = fista_edge(RY[olr], dR, 0.0f, S.cr[olr], ak, kL);
 }
 
+struct GenericStep {
+    template <bool mom>
+    __device__ __forceinline__ static void step(const Ctx &c, FusedLds &S, const Slot &X, Slot &Y, int sx, float beta)
+    {
+        fused_step<mom>(c, S, X, Y, sx, beta);
+    }
+};
+
+struct FullStep {
+    template <bool mom>
+    __device__ __forceinline__ static void step(const FullCtx &c, FusedLds &S, const Slot &X, Slot &Y, int sx,
+                                                float beta)
+    {
+        full_step<mom>(c, S, X, Y, sx, beta);
+    }
+};
+
+// K projected-FISTA steps from x_0 in A (B holds a copy); x_K ends in A.
+// Steps 1 and 2 have no momentum (beta = 0).  Returns the LDS slot of the
+// right boundary edges that holds x_K.
+template <class Step, class C>
+__device__ __forceinline__ int run_steps(const C &c, FusedLds &S, Slot &A, Slot &B, int K, const float *beta)
+{
+    if (K == 1) {
+        Step::template step<false>(c, S, A, B, 0, 0.0f);
+        copy_slot(A, B);
+        return 1;
+    }
+    Step::template step<false>(c, S, A, B, 0, 0.0f);
+    Step::template step<false>(c, S, B, A, 1, 0.0f);
+    int k = 3;
+    for (; k + 1 <= K; k += 2) {
+        Step::template step<true>(c, S, A, B, 0, beta[k]);
+        Step::template step<true>(c, S, B, A, 1, beta[k + 1]);
+    }
+    if (k == K) {
+        Step::template step<true>(c, S, A, B, 0, beta[K]);
+        copy_slot(A, B);
+        return 1;
+    }
+    return 0;
+}
+
+// The same K steps on a full tile with K known at compile time: fully
+// unrolled, so the two slots never swap roles across a loop back-edge (which
+// costs register copies, and spills where the caller keeps more state live).
+// x_K ends in A when K is even and in B when K is odd; returns the LDS slot of
+// the right boundary column holding it (K & 1).
+template <int K, int k = 1>
+__device__ __forceinline__ int full_steps_fixed(const FullCtx &c, FusedLds &S, Slot &X, Slot &Y, const float *beta)
+{
+    if constexpr (k <= K) {
+        full_step<(k >= 3)>(c, S, X, Y, (k - 1) & 1, k >= 3 ? beta[k] : 0.0f);
+        return full_steps_fixed<K, k + 1>(c, S, Y, X, beta);
+    } else {
+        return K & 1;
+    }
+}
+
 }  // namespace fused
 }  // namespace dtv

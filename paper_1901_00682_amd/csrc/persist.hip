@@ -1,0 +1,333 @@
+// Persistent schedule of Algorithm 1 (Lee & Park, arXiv 1901.00682) for ROF
+// with FISTA local solves: one cooperative launch runs every outer step.
+//
+// Each workgroup owns one full 128 x 128 subdomain for the whole solve; its
+// iterate stays in VGPRs (the slots of the fused kernel) from the first outer
+// step to the last, so p~ crosses HBM twice per solve instead of twice per
+// outer step.  Per outer step n:
+//   (1) each tile forms q = 2 p^n - p^(n-1) on its own interface copies (the
+//       extrapolated copies of the multiplier update) and publishes them;
+//   (2) it waits for the copies its neighbours publish on the same edges;
+//   (3) both tiles of an interface edge compute lambda^(n+1) = lambda^n +
+//       sigma (q_s - q_t) from the two copies, with the operations of the
+//       multiplier-update kernel, so both hold the same value;
+//   (4) c' of every edge is rebuilt from the anchor phat = p^n -/+ tau lambda
+//       (fista_ops.h) and f;
+//   (5) the n_inner FISTA steps of the fused kernel (full_step).
+// lambda^n and the tile's own previous copies live in LDS.
+//
+// Synchronisation is point to point, between the two tiles of an interface:
+// every copy travels in a 64-bit word that also holds n + 1, written and
+// polled with relaxed agent-scope atomics, so a word is valid exactly when its
+// step number matches and no fence or grid-wide barrier is needed (an
+// agent-scope fence writes back and invalidates a whole L2).  The words
+// alternate between two slots by step parity; a tile overwrites slot n % 2 at
+// step n + 2 only after it has read its neighbour's step n + 1 copy, which
+// the neighbour publishes only after reading the step n word.  The
+// cooperative launch keeps every tile resident, so every wait can end.
+//
+// The arithmetic per edge and per multiplier is that of the fused and
+// streaming schedules, so all three give bitwise identical results.
+#include "fused_common.h"
+
+namespace dtv {
+
+using namespace fused;
+
+namespace {
+
+constexpr int kSides = 4;                // 0 top (t copies), 1 bottom (s), 2 left (t), 3 right (s)
+constexpr unsigned kSpinLimit = 1u << 21;  // polls of one exchange word before a tile gives up (~0.1 s)
+
+struct PersistLds {
+    FusedLds f;
+    float lam[kSides][kFusedMax];  // lambda on the tile's interface edges
+    float prv[kSides][kFusedMax];  // the tile's own copies on those edges at the previous outer step
+    int ok;                        // every wait of the current step completed
+};
+
+// exchange word: the copy in the low half, its outer step + 1 in the high half
+__device__ __forceinline__ void publish(unsigned long long *w, float q, int n)
+{
+    const unsigned long long v = ((unsigned long long)(unsigned)(n + 1) << 32) | __float_as_uint(q);
+    __hip_atomic_store(w, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// waits for the step-n word; false after kSpinLimit polls
+__device__ __forceinline__ bool fetch(const unsigned long long *w, int n, float &q)
+{
+    for (unsigned spins = 0; spins < kSpinLimit; ++spins) {
+        const unsigned long long v = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((unsigned)(v >> 32) == (unsigned)(n + 1)) {
+            q = __uint_as_float((unsigned)v);
+            return true;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    return false;
+}
+
+// lambda index of edge i of side `side` of tile (r, c) (interface edges only)
+__device__ __forceinline__ long long side_edge(const ImgDev &im, const SubTile &tl, int side, int i)
+{
+    switch (side) {
+    case 0: return (long long)(tl.r - 1) * im.W + tl.ca + i;
+    case 1: return (long long)tl.r * im.W + tl.ca + i;
+    case 2: return im.nlh + (long long)(tl.c - 1) * im.H + tl.ra + i;
+    default: return im.nlh + (long long)tl.c * im.H + tl.ra + i;
+    }
+}
+
+__device__ __forceinline__ bool side_exists(const ImgDev &im, const SubTile &tl, int side)
+{
+    switch (side) {
+    case 0: return tl.r > 0;
+    case 1: return tl.r < im.ny - 1;
+    case 2: return tl.c > 0;
+    default: return tl.c < im.nx - 1;
+    }
+}
+
+__device__ __forceinline__ void ld2g(const float *p, float &x, float &y)
+{
+    float2 v;
+    __builtin_memcpy(&v, p, 8);
+    x = v.x;
+    y = v.y;
+}
+
+__device__ __forceinline__ void st2g(float *p, float x, float y)
+{
+    const float2 v = make_float2(x, y);
+    __builtin_memcpy(p, &v, 8);
+}
+
+}  // namespace
+
+// KF > 0: the kernel for n_inner = KF (steps unrolled); KF = 0: any n_inner
+template <int KF>
+__global__ __launch_bounds__(1024) void k_persist_fista(PersistArgs a)
+{
+    __shared__ PersistLds L;
+    FusedLds &S = L.f;
+    const int t = xcd_remap(blockIdx.x, gridDim.x);
+    const SubTile tl = a.fa.subs[t];
+    const ImgDev im = a.fa.imgs[tl.img];
+    const int s = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // strip (wave) index
+    const int lane = threadIdx.x & 63;
+    const int ja = 2 * lane, jb = ja + 1, il0 = kR * s;
+    const int H = im.H, W = im.W;
+    const bool top_bnd = tl.ra == 0, bot_bnd = tl.ra + kFusedMax == H;
+    const bool left_bnd = tl.ca == 0, right_bnd = tl.ca + kFusedMax == W;
+    const long long P1 = im.pitch1, P2 = im.pitch2;
+    const long long row1 = (long long)tl.ra + tl.r;  // P1 row of the tile's edge row 0
+    const long long col2 = (long long)tl.ca + tl.c;  // P2 column of the tile's edge column 0
+    const float tau = a.fa.tau, itau = a.fa.inv_tau, invL = im.invL;
+    const float *f_tile = a.fa.f + im.px + (long long)tl.ra * W + tl.ca;
+    const long long nlam = im.nlam;
+
+    FullCtx fc;
+    fc.s = s;
+    fc.lane = lane;
+    fc.ja = ja;
+    fc.il0 = il0;
+    fc.oc = il0 * kFusedMax + ja;
+    fc.oy = s * kFusedMax + ja;
+    fc.olr = il0 + lane;
+    fc.last = s == kWaves - 1;
+    fc.right_bnd = right_bnd;
+    {
+        const bool tb = top_bnd && s == 0, lb = left_bnd && lane == 0;
+        fc.lo1 = tb ? 0.0f : -1.0f;
+        fc.hi1 = tb ? 0.0f : 1.0f;
+        fc.lo2a = lb ? 0.0f : -1.0f;
+        fc.hi2a = lb ? 0.0f : 1.0f;
+        fc.lob = bot_bnd ? 0.0f : -1.0f;
+        fc.hib = bot_bnd ? 0.0f : 1.0f;
+    }
+    fc.ak = im.a_keep;
+    fc.kL = im.kL;
+
+    // side work (multiplier update): waves 0..7, side = wave / 2 (wave-uniform), edge
+    // si = 64 (wave % 2) + lane; the lambda index is side_base + si
+    const int side = s >> 1;
+    const bool side_wave = s < 2 * kSides && side_exists(im, tl, side);
+    const bool side_s = side == 1 || side == 3;  // s copies: bottom and right sides
+    const long long side_base = side_wave ? side_edge(im, tl, side, 0) : 0;
+
+    // ---- load p~^0 (slot A, right boundary column in LDS) and the lambda state
+    Slot A, B;
+    A.ba = A.bb = 0.0f;
+    {
+        const float *p1_tile = a.fa.base1 + im.p1 + row1 * P1 + tl.ca;
+        const float *p2_tile = a.fa.base2 + im.p2 + (long long)tl.ra * P2 + col2;
+#pragma unroll
+        for (int r = 0; r < kR; ++r) {
+            const int il = il0 + r;
+            ld2g(p1_tile + (long long)il * P1 + ja, A.e1a[r], A.e1b[r]);
+            ld2g(p2_tile + (long long)il * P2 + ja, A.e2a[r], A.e2b[r]);
+        }
+        if (fc.last) ld2g(p1_tile + (long long)kFusedMax * P1 + ja, A.ba, A.bb);
+        if (lane < kR) S.rx[0][il0 + lane] = p2_tile[(long long)(il0 + lane) * P2 + kFusedMax];
+    }
+    if (side_wave) {
+        const int si = (s & 1) * 64 + lane;
+        const float *ls = a.fa.lam + im.lam + side_base;
+        L.lam[side][si] = ls[si];
+        L.prv[side][si] = ls[(side_s ? nlam : 2 * nlam) + si];
+    }
+    int rx_slot = 0;  // LDS slot of the right boundary column holding the current iterate
+    bool ok = true;
+
+    for (int n = 0; n < a.n_outer; ++n) {
+        // ---- (1) stage the current iterate on the four sides (dl is free between local solves)
+        __syncthreads();
+        if (s == 0) lds_st2(&S.dl[0][ja], A.e1a[0], A.e1b[0]);
+        if (fc.last) lds_st2(&S.dl[1][ja], A.ba, A.bb);
+        if (lane == 0) {
+#pragma unroll
+            for (int r = 0; r < kR; ++r) S.dl[2][il0 + r] = A.e2a[r];
+        }
+        if (threadIdx.x == 0) L.ok = 1;
+        __syncthreads();
+        if (side_wave) {
+            const int si = (s & 1) * 64 + opaque(lane);
+            unsigned long long *xch = a.xch + (long long)(n & 1) * a.xch_stride + im.lam + side_base + si;
+            const float x = side == 3 ? S.rx[rx_slot][si] : S.dl[side][si];
+            const float q_own = 2.0f * x - L.prv[side][si];
+            L.prv[side][si] = x;
+            publish(xch + (side_s ? 0 : nlam), q_own, n);
+            // ---- (2) the neighbour's copy of the same edge, then (3) lambda^(n+1)
+            float q_oth = 0.0f;
+            if (fetch(xch + (side_s ? nlam : 0), n, q_oth)) {
+                const float qs = side_s ? q_own : q_oth, qt = side_s ? q_oth : q_own;
+                L.lam[side][si] = L.lam[side][si] + a.sigma * (qs - qt);
+            } else {
+                L.ok = 0;
+                atomicOr(a.err, 1);
+            }
+        }
+        // the right boundary column of the iterate goes to slot 0 (the first step reads it there)
+        if (rx_slot == 1 && lane < kR) S.rx[0][il0 + lane] = S.rx[1][il0 + lane];
+        __syncthreads();
+        ok = L.ok != 0;
+        if (!ok) break;  // a neighbour stopped publishing: leave (the host reports the error)
+
+        // ---- (4) c' from phat = p^n -/+ tau lambda^(n+1) and f (as in the fused kernel's prologue)
+        {
+            // per outer step, so that the row addresses are formed here and not hoisted out of the loop
+            const int jo = opaque(ja);
+            float fua = 0.0f, fub = 0.0f;  // f of the row above (0 above the tile)
+            if (il0 > 0) ld2g(f_tile + (long long)(il0 - 1) * W + jo, fua, fub);
+#pragma unroll
+            for (int r = 0; r < kR; ++r) {
+                const int il = il0 + r;
+                float fva, fvb;
+                ld2g(f_tile + (long long)il * W + jo, fva, fvb);
+                const float fla = from_left(fvb);  // f of column a - 1 (lane 0: left of the tile, 0)
+                float ata = A.e1a[r], atb = A.e1b[r];
+                if (il == 0 && tl.r > 0) {  // t copies of the interface above
+                    ata = fmaf(tau, L.lam[0][ja], ata);
+                    atb = fmaf(tau, L.lam[0][jb], atb);
+                }
+                float ala = A.e2a[r];
+                if (ja == 0 && tl.c > 0) ala = fmaf(tau, L.lam[2][il], ala);  // t copy of the interface on the left
+                lds_st2(&S.c1[il][ja], fista_cprime(ata, fua, fva, itau, invL), fista_cprime(atb, fub, fvb, itau, invL));
+                lds_st2(&S.c2[il][ja], fista_cprime(ala, ja > 0 ? fla : 0.0f, fva, itau, invL),
+                        fista_cprime(A.e2b[r], fva, fvb, itau, invL));
+                if (il == kFusedMax - 1) {  // bottom boundary edges (s copies unless on the image boundary)
+                    const float aba = bot_bnd ? A.ba : fmaf(-tau, L.lam[1][ja], A.ba);
+                    const float abb = bot_bnd ? A.bb : fmaf(-tau, L.lam[1][jb], A.bb);
+                    lds_st2(&S.cb[ja], fista_cprime(aba, fva, 0.0f, itau, invL),
+                            fista_cprime(abb, fvb, 0.0f, itau, invL));
+                }
+                if (lane == 63) {  // right boundary edge of this row (s copy unless on the image boundary)
+                    const float xr = S.rx[0][il];
+                    const float ar = right_bnd ? xr : fmaf(-tau, L.lam[3][il], xr);
+                    S.cr[il] = fista_cprime(ar, fvb, 0.0f, itau, invL);
+                }
+                fua = fva;
+                fub = fvb;
+            }
+        }
+        __syncthreads();
+
+        // ---- (5) the local FISTA solves
+        if constexpr (KF > 0) {
+            rx_slot = full_steps_fixed<KF>(fc, S, A, B, a.fa.beta);
+            if constexpr (KF & 1) copy_slot(A, B);
+        } else {
+            rx_slot = run_steps<FullStep>(fc, S, A, B, a.fa.n_inner, a.fa.beta);
+        }
+    }
+
+    // ---- store p~^N and the lambda state (lambda^N and the copies of the last multiplier update)
+    __syncthreads();
+    {
+        float *q1_tile = a.fa.out1 + im.p1 + row1 * P1 + tl.ca;
+        float *q2_tile = a.fa.out2 + im.p2 + (long long)tl.ra * P2 + col2;
+#pragma unroll
+        for (int r = 0; r < kR; ++r) {
+            const int il = il0 + r;
+            st2g(q1_tile + (long long)il * P1 + ja, A.e1a[r], A.e1b[r]);
+            st2g(q2_tile + (long long)il * P2 + ja, A.e2a[r], A.e2b[r]);
+        }
+        if (fc.last) st2g(q1_tile + (long long)kFusedMax * P1 + ja, A.ba, A.bb);
+        if (lane < kR) q2_tile[(long long)(il0 + lane) * P2 + kFusedMax] = S.rx[rx_slot][il0 + lane];
+    }
+    if (side_wave && ok) {
+        const int si = (s & 1) * 64 + lane;
+        float *ls = a.lam_out + im.lam + side_base;
+        if (side_s) {
+            ls[si] = L.lam[side][si];
+            ls[nlam + si] = L.prv[side][si];
+        } else {
+            ls[2 * nlam + si] = L.prv[side][si];
+        }
+    }
+}
+
+bool persist_supported(int device)
+{
+    int coop = 0;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device) != hipSuccess) return false;
+    return coop != 0;
+}
+
+namespace {
+
+using PersistKernel = void (*)(PersistArgs);
+
+// kernels with the inner step count unrolled, for the common counts
+template <int... Ks>
+struct PersistTable {
+    static PersistKernel get(int K)
+    {
+        PersistKernel k = nullptr;
+        ((K == Ks ? (k = k_persist_fista<Ks>, 0) : 0), ...);
+        return k ? k : k_persist_fista<0>;
+    }
+};
+using Persist = PersistTable<1, 2, 3, 4, 5, 6, 7, 8, 10>;
+
+}  // namespace
+
+int persist_capacity(int device)
+{
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persist_fista<0>, 1024, 0) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
+    return per_cu * cus;
+}
+
+hipError_t launch_persist_fista(const PersistArgs &a, int nsub, hipStream_t s)
+{
+    if (nsub <= 0 || a.n_outer <= 0) return hipSuccess;
+    if (a.fa.n_inner < 1 || a.fa.n_inner > kMaxFusedInner) return hipErrorInvalidValue;
+    PersistArgs arg = a;
+    void *args[] = {&arg};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(Persist::get(a.fa.n_inner)), dim3(nsub),
+                                      dim3(1024), args, 0, s);
+}
+
+}  // namespace dtv

@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(HERE, "_build", "libdtvdd.so")
 DTV_OK, DTV_EINVAL, DTV_ENOWS, DTV_EHIP, DTV_ESTATE, DTV_ENONFINITE = 0, -1, -2, -3, -4, -5
 FIDELITY = {"L2": 0, "L1": 1}
 INNER = {"FISTA": 0, "CP2": 1}
-SCHEDULE = {"auto": 0, "stream": 1, "fused": 2}
+SCHEDULE = {"auto": 0, "stream": 1, "fused": 2, "persistent": 3}
 SCHEDULE_NAME = {v: k for k, v in SCHEDULE.items()}
 
 # every entry point declared in include/dtvdd.h
