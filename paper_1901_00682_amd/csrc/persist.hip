@@ -7,12 +7,13 @@
 // outer step.  Per outer step n:
 //   (1) each tile forms q = 2 p^n - p^(n-1) on its own interface copies (the
 //       extrapolated copies of the multiplier update) and publishes them;
+//   (4a) meanwhile it rebuilds c' of every edge from the anchor p^n and f
+//       (fista_ops.h);
 //   (2) it waits for the copies its neighbours publish on the same edges;
 //   (3) both tiles of an interface edge compute lambda^(n+1) = lambda^n +
 //       sigma (q_s - q_t) from the two copies, with the operations of the
 //       multiplier-update kernel, so both hold the same value;
-//   (4) c' of every edge is rebuilt from the anchor phat = p^n -/+ tau lambda
-//       (fista_ops.h) and f;
+//   (4b) c' of the interface copies is redone from phat = p^n -/+ tau lambda;
 //   (5) the n_inner FISTA steps of the fused kernel (full_step).
 // lambda^n and the tile's own previous copies live in LDS.
 //
@@ -115,7 +116,7 @@ __global__ __launch_bounds__(1024) void k_persist_fista(PersistArgs a)
     const ImgDev im = a.fa.imgs[tl.img];
     const int s = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // strip (wave) index
     const int lane = threadIdx.x & 63;
-    const int ja = 2 * lane, jb = ja + 1, il0 = kR * s;
+    const int ja = 2 * lane, il0 = kR * s;
     const int H = im.H, W = im.W;
     const bool top_bnd = tl.ra == 0, bot_bnd = tl.ra + kFusedMax == H;
     const bool left_bnd = tl.ca == 0, right_bnd = tl.ca + kFusedMax == W;
@@ -190,30 +191,21 @@ __global__ __launch_bounds__(1024) void k_persist_fista(PersistArgs a)
         }
         if (threadIdx.x == 0) L.ok = 1;
         __syncthreads();
+        // ---- (1b) publish q = 2 p^n - p^(n-1) on the tile's interface copies
+        const int si = (s & 1) * 64 + opaque(lane);
+        unsigned long long *xch = a.xch + (long long)(n & 1) * a.xch_stride + im.lam + side_base + si;
+        float x_side = 0.0f, q_own = 0.0f;
         if (side_wave) {
-            const int si = (s & 1) * 64 + opaque(lane);
-            unsigned long long *xch = a.xch + (long long)(n & 1) * a.xch_stride + im.lam + side_base + si;
-            const float x = side == 3 ? S.rx[rx_slot][si] : S.dl[side][si];
-            const float q_own = 2.0f * x - L.prv[side][si];
-            L.prv[side][si] = x;
+            x_side = side == 3 ? S.rx[rx_slot][si] : S.dl[side][si];
+            q_own = 2.0f * x_side - L.prv[side][si];
+            L.prv[side][si] = x_side;
             publish(xch + (side_s ? 0 : nlam), q_own, n);
-            // ---- (2) the neighbour's copy of the same edge, then (3) lambda^(n+1)
-            float q_oth = 0.0f;
-            if (fetch(xch + (side_s ? nlam : 0), n, q_oth)) {
-                const float qs = side_s ? q_own : q_oth, qt = side_s ? q_oth : q_own;
-                L.lam[side][si] = L.lam[side][si] + a.sigma * (qs - qt);
-            } else {
-                L.ok = 0;
-                atomicOr(a.err, 1);
-            }
         }
         // the right boundary column of the iterate goes to slot 0 (the first step reads it there)
         if (rx_slot == 1 && lane < kR) S.rx[0][il0 + lane] = S.rx[1][il0 + lane];
-        __syncthreads();
-        ok = L.ok != 0;
-        if (!ok) break;  // a neighbour stopped publishing: leave (the host reports the error)
 
-        // ---- (4) c' from phat = p^n -/+ tau lambda^(n+1) and f (as in the fused kernel's prologue)
+        // ---- (4a) while the neighbours' copies travel: c' of every edge from the anchor p^n (the
+        // interface copies get their multiplier term in (4b)) and f, as in the fused kernel's prologue
         {
             // per outer step, so that the row addresses are formed here and not hoisted out of the loop
             const int jo = opaque(ja);
@@ -225,32 +217,44 @@ __global__ __launch_bounds__(1024) void k_persist_fista(PersistArgs a)
                 float fva, fvb;
                 ld2g(f_tile + (long long)il * W + jo, fva, fvb);
                 const float fla = from_left(fvb);  // f of column a - 1 (lane 0: left of the tile, 0)
-                float ata = A.e1a[r], atb = A.e1b[r];
-                if (il == 0 && tl.r > 0) {  // t copies of the interface above
-                    ata = fmaf(tau, L.lam[0][ja], ata);
-                    atb = fmaf(tau, L.lam[0][jb], atb);
-                }
-                float ala = A.e2a[r];
-                if (ja == 0 && tl.c > 0) ala = fmaf(tau, L.lam[2][il], ala);  // t copy of the interface on the left
-                lds_st2(&S.c1[il][ja], fista_cprime(ata, fua, fva, itau, invL), fista_cprime(atb, fub, fvb, itau, invL));
-                lds_st2(&S.c2[il][ja], fista_cprime(ala, ja > 0 ? fla : 0.0f, fva, itau, invL),
+                lds_st2(&S.c1[il][ja], fista_cprime(A.e1a[r], fua, fva, itau, invL),
+                        fista_cprime(A.e1b[r], fub, fvb, itau, invL));
+                lds_st2(&S.c2[il][ja], fista_cprime(A.e2a[r], ja > 0 ? fla : 0.0f, fva, itau, invL),
                         fista_cprime(A.e2b[r], fva, fvb, itau, invL));
-                if (il == kFusedMax - 1) {  // bottom boundary edges (s copies unless on the image boundary)
-                    const float aba = bot_bnd ? A.ba : fmaf(-tau, L.lam[1][ja], A.ba);
-                    const float abb = bot_bnd ? A.bb : fmaf(-tau, L.lam[1][jb], A.bb);
-                    lds_st2(&S.cb[ja], fista_cprime(aba, fva, 0.0f, itau, invL),
-                            fista_cprime(abb, fvb, 0.0f, itau, invL));
-                }
-                if (lane == 63) {  // right boundary edge of this row (s copy unless on the image boundary)
-                    const float xr = S.rx[0][il];
-                    const float ar = right_bnd ? xr : fmaf(-tau, L.lam[3][il], xr);
-                    S.cr[il] = fista_cprime(ar, fvb, 0.0f, itau, invL);
-                }
+                if (il == kFusedMax - 1)  // bottom boundary edges
+                    lds_st2(&S.cb[ja], fista_cprime(A.ba, fva, 0.0f, itau, invL),
+                            fista_cprime(A.bb, fvb, 0.0f, itau, invL));
+                if (lane == 63) S.cr[il] = fista_cprime(S.rx[0][il], fvb, 0.0f, itau, invL);  // right boundary edge
                 fua = fva;
                 fub = fvb;
             }
         }
         __syncthreads();
+
+        // ---- (2) the neighbour's copy of each interface edge, (3) lambda^(n+1), (4b) c' of the
+        // interface copies from phat = p^n -/+ tau lambda^(n+1) (t copies +, s copies -)
+        if (side_wave) {
+            // the pixel of the tile next to the edge (its f enters the edge's c')
+            const int pi = side == 0 ? 0 : side == 1 ? kFusedMax - 1 : si;
+            const int pj = side == 2 ? 0 : side == 3 ? kFusedMax - 1 : si;
+            const float fp = f_tile[(long long)pi * W + pj];
+            float q_oth = 0.0f;
+            if (fetch(xch + (side_s ? nlam : 0), n, q_oth)) {
+                const float qs = side_s ? q_own : q_oth, qt = side_s ? q_oth : q_own;
+                const float lam = L.lam[side][si] + a.sigma * (qs - qt);
+                L.lam[side][si] = lam;
+                if (side == 0) S.c1[0][si] = fista_cprime(fmaf(tau, lam, x_side), 0.0f, fp, itau, invL);
+                else if (side == 2) S.c2[si][0] = fista_cprime(fmaf(tau, lam, x_side), 0.0f, fp, itau, invL);
+                else if (side == 1) S.cb[si] = fista_cprime(fmaf(-tau, lam, x_side), fp, 0.0f, itau, invL);
+                else S.cr[si] = fista_cprime(fmaf(-tau, lam, x_side), fp, 0.0f, itau, invL);
+            } else {
+                L.ok = 0;
+                atomicOr(a.err, 1);
+            }
+        }
+        __syncthreads();
+        ok = L.ok != 0;
+        if (!ok) break;  // a neighbour stopped publishing: leave (the host reports the error)
 
         // ---- (5) the local FISTA solves
         if constexpr (KF > 0) {
