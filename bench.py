@@ -29,6 +29,36 @@ HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3  # MI355X vector FP32 (256 CUs x 128 lanes x 2 flops x 2.4 GHz)
 
 
+# source files of each timed kernel (the counters in profiles/traffic.txt are keyed by their hash)
+KERNEL_SOURCES = {
+    "k_persist_fista": ["persist.hip", "fused_common.h", "fista_ops.h", "dtvdd_internal.h"],
+    "k_fused_fista": ["fused.hip", "fused_common.h", "fista_ops.h", "dtvdd_internal.h"],
+    "k_fista_step": ["kernels.hip", "fista_ops.h", "dtvdd_internal.h"],
+    "k_cp2_step": ["kernels.hip", "fista_ops.h", "dtvdd_internal.h"],
+}
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per dispatch from the committed counter passes, or None when
+    there are none for this kernel and workload or the kernel changed since."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "traffic.txt")
+    if kernel not in KERNEL_SOURCES or not os.path.exists(path):
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, "paper_1901_00682_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    digest = h.hexdigest()[:16]
+    with open(path) as fh:
+        for line in fh:
+            w = line.split()
+            if len(w) == 7 and not line.startswith("#") and w[0] == kernel and w[1] == workload and w[2] == digest:
+                return (float(w[3]) * float(w[5]) + float(w[4]) * float(w[6])) * 1024.0
+    return None
+
+
 def fista_flops_per_pixel(K: int) -> float:
     """Algorithmic FP32 operations per pixel of one outer step with K FISTA
     steps (an FMA counts 2): per edge, the extrapolation y = x + beta (x - x_prev)
@@ -227,13 +257,15 @@ def main():
         flops = fista_flops_per_pixel(c.n_inner) * H * W * c.n_outer
         tflops = flops / (avg_ms * 1e-3) / 1e12
         roofline = {"bound": "alu", "kernel": kt["name"], "achieved": tflops, "peak": FP32_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": tflops / FP32_PEAK_TFLOPS, "traffic": None,
+                    "unit": "TFLOP/s", "frac": tflops / FP32_PEAK_TFLOPS,
+                    "traffic": measured_traffic(kt["name"], args.workload),
                     "avg_launch_us": avg_ms * 1e3, "flops_per_launch": flops,
                     "bytes_per_launch": kt["bytes_per_launch"], "hbm_GBs": achieved,
                     "launches_per_step": kt["launches"]}
     else:
         roofline = {"bound": "hbm", "kernel": kt["name"], "achieved": achieved, "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                    "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                    "traffic": measured_traffic(kt["name"], args.workload),
                     "avg_launch_us": avg_ms * 1e3, "bytes_per_launch": kt["bytes_per_launch"],
                     "launches_per_step": kt["launches"]}
     if args.calibrate_copy:

@@ -854,8 +854,8 @@ extern "C" int dtv_dd_kernel_time(const dtv_dd_plan *pl, double *avg_ms, int64_t
         for (const ImgHost &h : pl->imgs) lam += (double)(h.ny - 1) * h.W + (double)(h.nx - 1) * h.H;
         if (persist) {
             // one launch for the whole solve: read p~^0, f and the lambda state, write p~^N and the
-            // lambda state, and per outer step publish and read back two extrapolated copies per multiplier
-            *bytes_per_launch = 4.0 * (2 * E + N + 6 * lam + 4 * lam * pl->prm.n_outer);
+            // lambda state, and per outer step write and read two 8-byte exchange words per multiplier
+            *bytes_per_launch = 4.0 * (2 * E + N + 6 * lam) + 32.0 * lam * pl->prm.n_outer;
         } else if (fused) {
             *bytes_per_launch = 4.0 * (2 * E + N);
         } else {
