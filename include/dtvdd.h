@@ -77,7 +77,13 @@ extern "C" {
 #define DTV_INNER_CP2 1      /* accelerated primal-dual (Sec. 5); any fidelity, mask allowed */
 
 /* kernel schedule of the local solves (numerically identical results) */
-#define DTV_SCHED_AUTO 0     /* pick by measurement (autotuner), cached per shape */
+#define DTV_SCHED_AUTO 0     /* pick by measurement: the first solve of a plan whose shape the
+                                process has not seen runs its first outer steps in short timed
+                                chunks, one per candidate (schedule x streaming rows), keeps the
+                                fastest for the remaining steps and caches it per shape (the
+                                schedules round identically, so the result does not depend on
+                                the choice); with too few outer steps, or with time_kernels, a
+                                fixed rule picks: persistent, else fused, else streaming */
 #define DTV_SCHED_STREAM 1   /* one launch per inner step over all subdomains */
 #define DTV_SCHED_FUSED 2    /* one workgroup per subdomain runs all inner steps on chip
                                 (FISTA, subdomains up to 128 x 128) */
@@ -120,6 +126,12 @@ typedef struct {
     int32_t schedule;          /* DTV_SCHED_* */
     int32_t time_kernels;      /* 1: time every launch of the inner-step kernel with HIP events
                                   (read back with dtv_dd_kernel_time) */
+    int32_t rows;              /* rows per wave strip of the streaming kernels: 4, 8, 16 or 32;
+                                  0: chosen by the autotuner (16 until measured) */
+    int32_t no_graphs;         /* 1: enqueue every outer step eagerly; 0: replay the outer steps of
+                                  the per-step schedules from a captured hipGraph (when no
+                                  per-step host work is asked for: diagnostics, checkpoints,
+                                  kernel timing) */
 } dtv_dd_params;
 
 /* Where image `image` lives in the concatenated buffers (element offsets). */
@@ -183,6 +195,12 @@ int dtv_dd_kernel_time(const dtv_dd_plan *plan, double *avg_ms, int64_t *launche
 
 /* The schedule the plan will use (DTV_SCHED_STREAM, DTV_SCHED_FUSED or DTV_SCHED_PERSIST). */
 int dtv_dd_schedule(const dtv_dd_plan *plan, int32_t *schedule);
+
+/* The schedule and streaming rows the plan uses and where they came from:
+   source 0 = the fixed rule (nothing measured yet), 1 = measured by this
+   plan's first solve, 2 = taken from the process-wide cache of an earlier
+   plan with the same shape, 3 = set explicitly in dtv_dd_params. */
+int dtv_dd_choice(const dtv_dd_plan *plan, int32_t *schedule, int32_t *rows, int32_t *source);
 
 void dtv_dd_destroy(dtv_dd_plan *plan);
 

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -50,6 +52,33 @@ struct ImgHost {
 
 }  // namespace
 
+namespace {
+
+// a schedule and the rows per strip of the streaming kernels
+struct Choice {
+    int schedule, rows;
+};
+
+// what a captured hipGraph of outer steps was recorded with
+struct GraphKey {
+    int schedule = -1, rows = 0, base = 0;
+    bool u_alt = false;
+    int period = 0;
+    const void *f = nullptr, *mask = nullptr, *u = nullptr, *p1 = nullptr, *p2 = nullptr, *lam = nullptr,
+               *ws = nullptr;
+    bool operator==(const GraphKey &o) const
+    {
+        return schedule == o.schedule && rows == o.rows && base == o.base && u_alt == o.u_alt && period == o.period &&
+               f == o.f && mask == o.mask && u == o.u && p1 == o.p1 && p2 == o.p2 && lam == o.lam && ws == o.ws;
+    }
+};
+
+// autotuner results of this process, by shape key
+std::mutex g_tune_mu;
+std::map<std::string, Choice> g_tune_cache;
+
+}  // namespace
+
 struct dtv_dd_plan {
     dtv_dd_params prm;
     std::vector<ImgHost> imgs;
@@ -62,14 +91,23 @@ struct dtv_dd_plan {
     // metadata uploaded to the workspace at bind time
     std::vector<ImgDev> h_imgs;
     std::vector<int> h_info;
-    std::vector<StreamTile> h_tiles;
+    std::vector<StreamTile> h_tiles[kRowChoices];  // streaming work lists, strips of 4 << ri rows
     std::vector<SubTile> h_subs;
     int n_full = 0;         // h_subs[0, n_full) are 128 x 128
+    // schedule choice: the fixed rule until measured (or cached, or explicit)
+    bool tuned = false;
+    int choice_source = 0;  // 0 rule, 1 measured, 2 cached, 3 explicit
+    std::string key;        // shape key of the autotuner cache
+    // hipGraph of one cycle of outer steps of a per-step schedule
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    GraphKey gkey;
     bool fused_ok = false;  // every subdomain fits the fused kernel
     bool persist_ok = false;  // the persistent schedule applies (full tiles, all resident, no per-step host work)
 
     // workspace layout (byte offsets)
-    size_t off_imgs = 0, off_info = 0, off_tiles = 0, off_subs = 0, off_buf[3] = {0, 0, 0}, off_u2 = 0,
+    size_t off_imgs = 0, off_info = 0, off_tiles[kRowChoices] = {0, 0, 0, 0}, off_subs = 0, off_buf[3] = {0, 0, 0},
+           off_u2 = 0,
            off_part = 0, off_dout = 0, off_xch = 0, off_sync = 0, ws_bytes = 0;
     int diag_nblk = 0;
     char *ws = nullptr;
@@ -90,6 +128,8 @@ struct dtv_dd_plan {
 
     ~dtv_dd_plan()
     {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
         if (h_diag) (void)hipHostFree(h_diag);
     }
@@ -97,7 +137,8 @@ struct dtv_dd_plan {
     const ImgDev *d_imgs() const { return (const ImgDev *)(ws + off_imgs); }
     const SubTile *d_subs() const { return (const SubTile *)(ws + off_subs); }
     const int *d_info() const { return (const int *)(ws + off_info); }
-    const StreamTile *d_tiles() const { return (const StreamTile *)(ws + off_tiles); }
+    const StreamTile *d_tiles(int R) const { return (const StreamTile *)(ws + off_tiles[row_index(R)]); }
+    int ntiles(int R) const { return (int)h_tiles[row_index(R)].size(); }
     float *buf1(int k) const { return (float *)(ws + off_buf[k]); }
     float *buf2(int k) const { return (float *)(ws + off_buf[k]) + tot_p1; }
     float *u2() const { return (float *)(ws + off_u2); }
@@ -137,6 +178,43 @@ static int check_cuts(const int32_t *given, int parts, int n, std::vector<int> &
 
 static bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
+// The autotuner's candidates: the schedules the plan admits (persistent, fused,
+// streaming) times the streaming rows (4, 8, 16, 32), restricted by explicit
+// choices in the parameters.
+static std::vector<Choice> candidates(const dtv_dd_plan *pl)
+{
+    const dtv_dd_params &p = pl->prm;
+    std::vector<Choice> c;
+    const bool any = p.schedule == DTV_SCHED_AUTO;
+    if ((any || p.schedule == DTV_SCHED_PERSIST) && pl->persist_ok) c.push_back({DTV_SCHED_PERSIST, pl->rows});
+    if ((any || p.schedule == DTV_SCHED_FUSED) && pl->fused_ok) c.push_back({DTV_SCHED_FUSED, pl->rows});
+    if (any || p.schedule == DTV_SCHED_STREAM) {
+        if (p.rows)
+            c.push_back({DTV_SCHED_STREAM, p.rows});
+        else
+            for (int R : {4, 8, 16, 32}) c.push_back({DTV_SCHED_STREAM, R});
+    }
+    return c;
+}
+
+// key of the autotuner cache: device, solver, inner count and every image's sizes and cuts
+static std::string shape_key(const dtv_dd_plan *pl)
+{
+    const dtv_dd_params &p = pl->prm;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::string k = "dev" + std::to_string(dev) + ":" + std::to_string(p.inner) + ":" + std::to_string(p.fidelity) +
+                    ":" + std::to_string(p.has_mask) + ":" + std::to_string(p.n_inner) + ":" +
+                    std::to_string(p.schedule) + ":" + std::to_string(p.rows);
+    for (const ImgHost &h : pl->imgs) {
+        k += "|" + std::to_string(h.H) + "x" + std::to_string(h.W) + ":";
+        for (int v : h.rcut) k += std::to_string(v) + ",";
+        k += ":";
+        for (int v : h.ccut) k += std::to_string(v) + ",";
+    }
+    return k;
+}
+
 extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const dtv_dd_params *prm,
                             dtv_dd_plan **out)
 {
@@ -164,6 +242,9 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
         return fail(DTV_EINVAL, "save_for_backward needs FISTA and ckpt_every >= 1");
     if (p.save_for_backward && p.gap_tol > 0.0) return fail(DTV_EINVAL, "save_for_backward needs fixed iteration counts");
     if (p.schedule < DTV_SCHED_AUTO || p.schedule > DTV_SCHED_PERSIST) return fail(DTV_EINVAL, "unknown schedule");
+    if (p.rows != 0 && p.rows != 4 && p.rows != 8 && p.rows != 16 && p.rows != 32)
+        return fail(DTV_EINVAL, "rows must be 0, 4, 8, 16 or 32");
+    if (p.no_graphs != 0 && p.no_graphs != 1) return fail(DTV_EINVAL, "no_graphs must be 0 or 1");
 
     dtv_dd_plan *pl = new dtv_dd_plan();
     pl->prm = p;
@@ -240,8 +321,9 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
         g.dA = 8.0 / ((h.alpha * L) * (h.alpha * L));
         g.dB = -1.0 / (tau * (h.alpha * L) * (h.alpha * L));
         pl->h_imgs.push_back(g);
-        for (int i0 = 0; i0 < h.H; i0 += pl->rows)
-            for (int j0 = 0; j0 < h.W; j0 += kStreamCols) pl->h_tiles.push_back(StreamTile{b, i0, j0, 0});
+        for (int ri = 0; ri < kRowChoices; ++ri)
+            for (int i0 = 0; i0 < h.H; i0 += 4 << ri)
+                for (int j0 = 0; j0 < h.W; j0 += kStreamCols) pl->h_tiles[ri].push_back(StreamTile{b, i0, j0, 0});
         for (int r = 0; r < h.ny; ++r)
             for (int c = 0; c < h.nx; ++c)
                 pl->h_subs.push_back(SubTile{b, r, c, h.rcut[r], h.ccut[c], h.rcut[r + 1] - h.rcut[r],
@@ -282,7 +364,7 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
     };
     pl->off_imgs = take(sizeof(ImgDev) * pl->h_imgs.size());
     pl->off_info = take(sizeof(int) * pl->h_info.size());
-    pl->off_tiles = take(sizeof(StreamTile) * pl->h_tiles.size());
+    for (int ri = 0; ri < kRowChoices; ++ri) pl->off_tiles[ri] = take(sizeof(StreamTile) * pl->h_tiles[ri].size());
     pl->off_subs = take(sizeof(SubTile) * pl->h_subs.size());
     for (int k = 0; k < 3; ++k) pl->off_buf[k] = take(sizeof(float) * (size_t)(pl->tot_p1 + pl->tot_p2));
     pl->off_u2 = take(p.inner == DTV_INNER_CP2 ? sizeof(float) * (size_t)pl->tot_px : 0);
@@ -306,13 +388,29 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
         pl->off_hb = take(sizeof(float) * E);
         pl->off_pb = take(sizeof(float) * E);
         pl->off_lb = take(sizeof(float) * (size_t)pl->tot_lam);
-        pl->off_galpha = take(sizeof(double) * pl->h_tiles.size());
+        pl->off_galpha = take(sizeof(double) * pl->h_tiles[0].size());  // the longest list (4-row strips)
     }
     pl->ws_bytes = off;
     if (p.schedule != DTV_SCHED_AUTO)
         pl->schedule = p.schedule;
     else
         pl->schedule = pl->persist_ok ? DTV_SCHED_PERSIST : pl->fused_ok ? DTV_SCHED_FUSED : DTV_SCHED_STREAM;
+    pl->rows = p.rows ? p.rows : 16;
+    // explicit choices are final; otherwise an earlier plan of the same shape may have measured one
+    if (candidates(pl).size() <= 1) {
+        pl->tuned = true;
+        pl->choice_source = p.schedule != DTV_SCHED_AUTO || p.rows != 0 ? 3 : 0;
+    } else {
+        pl->key = shape_key(pl);
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(pl->key);
+        if (it != g_tune_cache.end()) {
+            pl->schedule = it->second.schedule;
+            pl->rows = it->second.rows;
+            pl->tuned = true;
+            pl->choice_source = 2;
+        }
+    }
     *out = pl;
     g_err.clear();
     return DTV_OK;
@@ -352,9 +450,10 @@ extern "C" int dtv_dd_bind_workspace(dtv_dd_plan *pl, void *d_ws, size_t bytes)
             "upload image descriptors");
     HIP_TRY(hipMemcpy(ws + pl->off_info, pl->h_info.data(), sizeof(int) * pl->h_info.size(), hipMemcpyHostToDevice),
             "upload info words");
-    HIP_TRY(hipMemcpy(ws + pl->off_tiles, pl->h_tiles.data(), sizeof(StreamTile) * pl->h_tiles.size(),
-                      hipMemcpyHostToDevice),
-            "upload work list");
+    for (int ri = 0; ri < kRowChoices; ++ri)
+        HIP_TRY(hipMemcpy(ws + pl->off_tiles[ri], pl->h_tiles[ri].data(), sizeof(StreamTile) * pl->h_tiles[ri].size(),
+                          hipMemcpyHostToDevice),
+                "upload work list");
     HIP_TRY(hipMemcpy(ws + pl->off_subs, pl->h_subs.data(), sizeof(SubTile) * pl->h_subs.size(), hipMemcpyHostToDevice),
             "upload subdomain list");
     // rotation buffers start at zero so that their boundary (non-dof) edges are 0
@@ -469,6 +568,25 @@ struct Timer {
 
 }  // namespace
 
+static std::vector<float> fista_betas(int K);
+
+// next rotation state of the edge buffers after one outer step (see outer_step)
+static int next_base(int sched, bool cp2, int K, int base)
+{
+    if (sched == DTV_SCHED_PERSIST) return base;
+    if (sched == DTV_SCHED_FUSED) return base == 0 ? 1 : 0;
+    if (!cp2) {
+        int rot[3] = {base, 0, 0}, q = 1;
+        for (int k = 0; k < 3; ++k)
+            if (k != base) rot[q++] = k;
+        return rot[K % 3];
+    }
+    int sc[3], q = 0;
+    for (int k = 0; k < 4; ++k)
+        if (k != base) sc[q++] = k;
+    return sc[(K - 1) % 3];
+}
+
 extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_mask, float *d_u, float *d_p1,
                             float *d_p2, float *d_lambda, double *h_stats, int32_t *n_rows, void *stream)
 {
@@ -480,8 +598,6 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
     hipStream_t s = (hipStream_t)stream;
     const uint8_t *mask = P.has_mask ? d_mask : nullptr;
     const bool cp2 = P.inner == DTV_INNER_CP2;
-    const bool fused = pl->schedule == DTV_SCHED_FUSED || pl->schedule == DTV_SCHED_PERSIST;
-    const bool persist = pl->schedule == DTV_SCHED_PERSIST;
     const int K = P.n_inner;
 
     if (!P.warm_start) {
@@ -493,12 +609,7 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
     HIP_TRY(launch_zero_boundary(pl->d_imgs(), pl->n, pl->maxH, pl->maxW, d_p1, d_p2, s), "zero boundary");
 
     // step parameters, computed in double precision on the host
-    std::vector<float> beta(K + 1, 0.0f);  // FISTA momentum of step k (1-based); 0 for k = 1, 2
-    {
-        std::vector<double> t(K + 2, 1.0);
-        for (int m = 1; m <= K; ++m) t[m + 1] = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t[m] * t[m]));
-        for (int k = 2; k <= K; ++k) beta[k] = (float)((t[k - 1] - 1.0) / t[k]);
-    }
+    const std::vector<float> beta = fista_betas(K);  // FISTA momentum of step k (1-based); 0 for k = 1, 2
     std::vector<double> tk(K + 1), sk(K + 1), th(K + 1);
     {
         double a = P.tau0, b = P.sigma0;
@@ -518,20 +629,18 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
     Timer tm{pl, s, 0, P.time_kernels != 0};
     const int rows_cap = P.diag_every > 0 ? P.n_outer / P.diag_every + 1 : 0;
     int nrow = 0;
-    bool nonfinite = false;
+    bool nonfinite = false, stop = false;
     std::vector<double> drow(4 * pl->n);
 
     FusedArgs fa{};
-    if (fused) {
-        fa.imgs = pl->d_imgs();
-        fa.subs = pl->d_subs();
-        fa.lam = d_lambda;
-        fa.f = d_f;
-        fa.tau = (float)P.tau;
-        fa.inv_tau = (float)(1.0 / P.tau);
-        fa.n_inner = K;
-        for (int k = 1; k <= K; ++k) fa.beta[k] = beta[k];
-    }
+    fa.imgs = pl->d_imgs();
+    fa.subs = pl->d_subs();
+    fa.lam = d_lambda;
+    fa.f = d_f;
+    fa.tau = (float)P.tau;
+    fa.inv_tau = (float)(1.0 / P.tau);
+    fa.n_inner = std::min(K, kMaxFusedInner);
+    for (int k = 1; k <= fa.n_inner; ++k) fa.beta[k] = beta[k];
 
     auto emit_stats = [&](int step, const float *u, const EdgeBuf &b) -> int {
         bool nf = false;
@@ -560,21 +669,116 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
         return DTV_OK;
     };
     pl->saved = false;
+    const bool host_work = P.diag_every > 0 || P.save_for_backward || P.time_kernels;
 
-    if (persist && P.n_outer > 0) {
-        // every outer step in one cooperative launch; p~ and lambda updated in place
+    // One outer step n (a1 + a2 + a3) of a per-step schedule, enqueued on q.
+    // With host work: the checkpoint before it, the diagnostics after it.
+    auto outer_step = [&](int n, int sched, int rows, hipStream_t q, bool with_host) -> int {
+        if (with_host && P.save_for_backward && n % P.ckpt_every == 0) {
+            int rc = save_state(n / P.ckpt_every, bufs[base]);
+            if (rc != DTV_OK) return rc;
+        }
+        // (a1) multipliers from the extrapolated interface jump
+        HIP_TRY(launch_lambda(pl->d_imgs(), pl->n, pl->max_nlam, pl->d_info(), bufs[base].p1, bufs[base].p2, d_lambda,
+                              (float)P.sigma, q),
+                "lambda update");
+        // (a2)+(a3) local solves; the anchor phat is formed on the fly from p~^n and lambda
+        if (sched == DTV_SCHED_FUSED) {
+            const int out = next_base(sched, cp2, K, base);
+            fa.base1 = bufs[base].p1; fa.base2 = bufs[base].p2;
+            fa.out1 = bufs[out].p1; fa.out2 = bufs[out].p2;
+            int rc = with_host ? tm.begin() : DTV_OK;
+            if (rc != DTV_OK) return rc;
+            HIP_TRY(launch_fused_fista(fa, (int)pl->h_subs.size(), pl->n_full, q, with_host ? tm.e0 : nullptr,
+                                       with_host ? tm.e1 : nullptr),
+                    "fused FISTA");
+            rc = with_host ? tm.end() : DTV_OK;
+            if (rc != DTV_OK) return rc;
+            base = out;
+        } else if (!cp2) {
+            // x_k lives in rot[k % 3]; c' in workspace buffer 3
+            int rot[3] = {base, 0, 0}, r = 1;
+            for (int k = 0; k < 3; ++k)
+                if (k != base) rot[r++] = k;
+            for (int k = 1; k <= K; ++k) {
+                const int ia = rot[(k - 1) % 3], ib = rot[(k + 1) % 3], io = rot[k % 3];
+                FistaStepArgs a{};
+                a.imgs = pl->d_imgs(); a.tiles = pl->d_tiles(rows); a.ntiles = pl->ntiles(rows); a.info = pl->d_info();
+                a.xa1 = bufs[ia].p1; a.xa2 = bufs[ia].p2; a.xb1 = bufs[ib].p1; a.xb2 = bufs[ib].p2;
+                a.lam = d_lambda; a.f = d_f;
+                a.c1 = bufs[3].p1; a.c2 = bufs[3].p2;
+                a.out1 = bufs[io].p1; a.out2 = bufs[io].p2;
+                a.beta = beta[k]; a.tau = (float)P.tau; a.inv_tau = (float)(1.0 / P.tau);
+                const int mode = k == 1 ? kFistaFirst : (k == 2 ? kFistaPlain : kFistaMomentum);
+                int rc = with_host ? tm.begin() : DTV_OK;
+                if (rc != DTV_OK) return rc;
+                HIP_TRY(launch_fista_step(a, mode, rows, q, with_host ? tm.e0 : nullptr, with_host ? tm.e1 : nullptr),
+                        "FISTA step");
+                rc = with_host ? tm.end() : DTV_OK;
+                if (rc != DTV_OK) return rc;
+            }
+            base = rot[K % 3];
+        } else {
+            int sc[3], r = 0;
+            for (int k = 0; k < 4; ++k)
+                if (k != base) sc[r++] = k;
+            for (int k = 1; k <= K; ++k) {
+                const int ia = k == 1 ? base : sc[(k - 2) % 3];
+                const int ib = k >= 3 ? sc[(k - 3) % 3] : base;
+                const int io = sc[(k - 1) % 3];
+                const int it = k - 1;
+                Cp2StepArgs a{};
+                a.imgs = pl->d_imgs(); a.tiles = pl->d_tiles(rows); a.ntiles = pl->ntiles(rows); a.info = pl->d_info();
+                a.xa1 = bufs[ia].p1; a.xa2 = bufs[ia].p2; a.xb1 = bufs[ib].p1; a.xb2 = bufs[ib].p2;
+                a.base1 = bufs[base].p1; a.base2 = bufs[base].p2; a.lam = d_lambda; a.f = d_f; a.mask = mask;
+                float *u_next = u_cur == d_u ? pl->u2() : d_u;
+                a.u_in = u_cur; a.u_out = u_next;
+                a.out1 = bufs[io].p1; a.out2 = bufs[io].p2;
+                a.theta_prev = it >= 1 ? (float)th[it - 1] : 0.0f;
+                a.sk = (float)sk[it]; a.tk = (float)tk[it]; a.tau = (float)P.tau;
+                a.c_keep = (float)(P.tau / (P.tau + tk[it]));
+                a.c_anchor = (float)(tk[it] / (P.tau + tk[it]));
+                a.fidelity = P.fidelity;
+                int rc = with_host ? tm.begin() : DTV_OK;
+                if (rc != DTV_OK) return rc;
+                HIP_TRY(launch_cp2_step(a, it >= 1, rows, q, with_host ? tm.e0 : nullptr, with_host ? tm.e1 : nullptr),
+                        "CP2 step");
+                rc = with_host ? tm.end() : DTV_OK;
+                if (rc != DTV_OK) return rc;
+                u_cur = u_next;
+            }
+            base = sc[(K - 1) % 3];
+        }
+        const bool last = n == P.n_outer - 1;
+        if (with_host && P.diag_every > 0 && ((n + 1) % P.diag_every == 0 || last)) {
+            const float *u = u_cur;
+            if (!cp2) {
+                HIP_TRY(launch_u_from_p(pl->d_imgs(), pl->n, pl->maxH, pl->maxW, pl->d_info(), bufs[base].p1,
+                                        bufs[base].p2, d_f, d_u, s),
+                        "u recovery");
+                u = d_u;
+            }
+            int rc = emit_stats(n + 1, u, bufs[base]);
+            if (rc != DTV_OK) return rc;
+            if (P.gap_tol > 0.0 && drow[2] <= P.gap_tol * std::fabs(drow[0])) stop = true;
+        }
+        return DTV_OK;
+    };
+
+    // outer steps [n0, n0 + count) in one persistent launch; p~ and lambda updated in place
+    auto run_persist = [&](int count) -> int {
         unsigned *sync = pl->sync_words();
         HIP_TRY(hipMemsetAsync(sync, 0, 2 * sizeof(unsigned), s), "clear error flag");
         HIP_TRY(hipMemsetAsync(pl->xch(), 0, sizeof(unsigned long long) * 2 * (size_t)pl->tot_lam, s), "clear exchange");
         PersistArgs pa{};
         pa.fa = fa;
-        pa.fa.base1 = pa.fa.out1 = d_p1;
-        pa.fa.base2 = pa.fa.out2 = d_p2;
+        pa.fa.base1 = pa.fa.out1 = bufs[base].p1;
+        pa.fa.base2 = pa.fa.out2 = bufs[base].p2;
         pa.lam_out = d_lambda;
         pa.xch = pl->xch();
         pa.xch_stride = pl->tot_lam;
         pa.err = (int *)sync;
-        pa.n_outer = P.n_outer;
+        pa.n_outer = count;
         pa.sigma = (float)P.sigma;
         int rc = tm.begin();
         if (rc != DTV_OK) return rc;
@@ -587,94 +791,123 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
         HIP_TRY(hipMemcpyAsync(&err, sync, sizeof(int), hipMemcpyDeviceToHost, s), "exchange status");
         HIP_TRY(hipStreamSynchronize(s), "exchange status");
         if (err) return fail(DTV_EHIP, "persistent FISTA: a wait for a neighbouring subdomain timed out");
+        return DTV_OK;
+    };
+
+    // Outer steps [n0, n1) with one schedule.  The per-step schedules replay a
+    // captured cycle of outer steps (the rotation of the edge buffers returns
+    // to its start after 1, 2 or 3 steps) when there is no host work per step.
+    auto run_range = [&](int n0, int n1, int sched, int rows, bool graphs) -> int {
+        if (n1 <= n0) return DTV_OK;
+        if (sched == DTV_SCHED_PERSIST) return run_persist(n1 - n0);
+        int n = n0;
+        if (graphs && !host_work && !P.no_graphs && n1 - n0 >= 4) {
+            // the buffer state (base, which u buffer is current) after each step
+            auto state = [&](int b, bool uf) { return b * 2 + (uf ? 1 : 0); };
+            std::vector<int> seq;
+            int b = base;
+            bool uf = u_cur != d_u;
+            for (int i = 0; i < 8; ++i) {
+                seq.push_back(state(b, uf));
+                b = next_base(sched, cp2, K, b);
+                if (cp2 && (K & 1)) uf = !uf;
+            }
+            int start = -1, period = 0;
+            for (int i = 0; i < 4 && start < 0; ++i)
+                for (int j = i + 1; j < 8; ++j)
+                    if (seq[j] == seq[i]) {
+                        start = i;
+                        period = j - i;
+                        break;
+                    }
+            if (start >= 0 && n1 - n0 - start >= 2 * period) {
+                for (int i = 0; i < start; ++i, ++n) {
+                    int rc = outer_step(n, sched, rows, s, false);
+                    if (rc != DTV_OK) return rc;
+                }
+                const GraphKey key{sched, rows, base, u_cur != d_u, period, d_f, mask, d_u, d_p1, d_p2, d_lambda, pl->ws};
+                if (!pl->gexec || !(pl->gkey == key)) {
+                    if (pl->gexec) {
+                        (void)hipGraphExecDestroy(pl->gexec);
+                        pl->gexec = nullptr;
+                    }
+                    if (!pl->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking), "stream");
+                    const int base0 = base;
+                    float *u0 = u_cur;
+                    HIP_TRY(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal), "graph capture");
+                    int rc = DTV_OK;
+                    for (int i = 0; i < period && rc == DTV_OK; ++i) rc = outer_step(n + i, sched, rows, pl->cap_stream, false);
+                    hipGraph_t g = nullptr;
+                    const hipError_t ge = hipStreamEndCapture(pl->cap_stream, &g);
+                    base = base0;  // the captured cycle returns to the same buffers
+                    u_cur = u0;
+                    if (rc != DTV_OK) {
+                        if (g) (void)hipGraphDestroy(g);
+                        return rc;
+                    }
+                    HIP_TRY(ge, "graph capture");
+                    const hipError_t ie = hipGraphInstantiate(&pl->gexec, g, nullptr, nullptr, 0);
+                    (void)hipGraphDestroy(g);
+                    HIP_TRY(ie, "graph instantiate");
+                    pl->gkey = key;
+                }
+                const int reps = (n1 - n) / period;
+                for (int r = 0; r < reps; ++r) HIP_TRY(hipGraphLaunch(pl->gexec, s), "graph launch");
+                n += reps * period;
+            }
+        }
+        for (; n < n1 && !stop; ++n) {
+            int rc = outer_step(n, sched, rows, s, host_work);
+            if (rc != DTV_OK) return rc;
+        }
+        return DTV_OK;
+    };
+
+    int n = 0;
+    // ---- autotuner: the first solve of an untuned plan runs its first outer steps in timed chunks
+    if (!pl->tuned && !host_work && P.n_outer > 0) {
+        const std::vector<Choice> cands = candidates(pl);
+        const int nc = (int)cands.size();
+        const int chunk = std::min(16, P.n_outer / (2 * std::max(nc, 1)) - 1);
+        if (nc > 1 && chunk >= 2) {
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            HIP_TRY(hipEventCreate(&e0), "event create");
+            HIP_TRY(hipEventCreate(&e1), "event create");
+            double best = 0.0;
+            int bi = -1, rc = DTV_OK;
+            for (int c = 0; c < nc && rc == DTV_OK; ++c) {  // one untimed step each (first use of each kernel)
+                rc = run_range(n, n + 1, cands[c].schedule, cands[c].rows, false);
+                n += 1;
+            }
+            for (int c = 0; c < nc && rc == DTV_OK; ++c) {
+                if (hipEventRecord(e0, s) != hipSuccess) rc = fail(DTV_EHIP, "event record");
+                if (rc == DTV_OK) rc = run_range(n, n + chunk, cands[c].schedule, cands[c].rows, false);
+                if (rc == DTV_OK && hipEventRecord(e1, s) != hipSuccess) rc = fail(DTV_EHIP, "event record");
+                float ms = 0.0f;
+                if (rc == DTV_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                    rc = fail(DTV_EHIP, "autotune timing");
+                n += chunk;
+                if (rc == DTV_OK && (bi < 0 || ms < best)) {
+                    best = ms;
+                    bi = c;
+                }
+            }
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            if (rc != DTV_OK) return rc;
+            pl->schedule = cands[bi].schedule;
+            pl->rows = cands[bi].rows;
+            pl->tuned = true;
+            pl->choice_source = 1;
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            g_tune_cache[pl->key] = cands[bi];
+        }
+    }
+    {
+        int rc = run_range(n, P.n_outer, pl->schedule, pl->rows, true);
+        if (rc != DTV_OK) return rc;
     }
 
-    for (int n = 0; n < (persist ? 0 : P.n_outer); ++n) {
-        if (P.save_for_backward && n % P.ckpt_every == 0) {
-            int rc = save_state(n / P.ckpt_every, bufs[base]);
-            if (rc != DTV_OK) return rc;
-        }
-        // (a1) multipliers from the extrapolated interface jump
-        HIP_TRY(launch_lambda(pl->d_imgs(), pl->n, pl->max_nlam, pl->d_info(), bufs[base].p1, bufs[base].p2, d_lambda,
-                              (float)P.sigma, s),
-                "lambda update");
-        // (a2)+(a3) local solves; the anchor phat is formed on the fly from p~^n and lambda
-        if (fused) {
-            const int out = base == 0 ? 1 : 0;
-            fa.base1 = bufs[base].p1; fa.base2 = bufs[base].p2;
-            fa.out1 = bufs[out].p1; fa.out2 = bufs[out].p2;
-            int rc = tm.begin();
-            if (rc != DTV_OK) return rc;
-            HIP_TRY(launch_fused_fista(fa, (int)pl->h_subs.size(), pl->n_full, s, tm.e0, tm.e1), "fused FISTA");
-            rc = tm.end();
-            if (rc != DTV_OK) return rc;
-            base = out;
-        } else if (!cp2) {
-            // x_k lives in rot[k % 3]; c' in workspace buffer 3
-            int rot[3] = {base, 0, 0}, q = 1;
-            for (int k = 0; k < 3; ++k)
-                if (k != base) rot[q++] = k;
-            for (int k = 1; k <= K; ++k) {
-                const int ia = rot[(k - 1) % 3], ib = rot[(k + 1) % 3], io = rot[k % 3];
-                FistaStepArgs a{};
-                a.imgs = pl->d_imgs(); a.tiles = pl->d_tiles(); a.ntiles = (int)pl->h_tiles.size(); a.info = pl->d_info();
-                a.xa1 = bufs[ia].p1; a.xa2 = bufs[ia].p2; a.xb1 = bufs[ib].p1; a.xb2 = bufs[ib].p2;
-                a.lam = d_lambda; a.f = d_f;
-                a.c1 = bufs[3].p1; a.c2 = bufs[3].p2;
-                a.out1 = bufs[io].p1; a.out2 = bufs[io].p2;
-                a.beta = beta[k]; a.tau = (float)P.tau; a.inv_tau = (float)(1.0 / P.tau);
-                const int mode = k == 1 ? kFistaFirst : (k == 2 ? kFistaPlain : kFistaMomentum);
-                int rc = tm.begin();
-                if (rc != DTV_OK) return rc;
-                HIP_TRY(launch_fista_step(a, mode, pl->rows, s, tm.e0, tm.e1), "FISTA step");
-                rc = tm.end();
-                if (rc != DTV_OK) return rc;
-            }
-            base = rot[K % 3];
-        } else {
-            int sc[3], q = 0;
-            for (int k = 0; k < 4; ++k)
-                if (k != base) sc[q++] = k;
-            for (int k = 1; k <= K; ++k) {
-                const int ia = k == 1 ? base : sc[(k - 2) % 3];
-                const int ib = k >= 3 ? sc[(k - 3) % 3] : base;
-                const int io = sc[(k - 1) % 3];
-                const int it = k - 1;
-                Cp2StepArgs a{};
-                a.imgs = pl->d_imgs(); a.tiles = pl->d_tiles(); a.ntiles = (int)pl->h_tiles.size(); a.info = pl->d_info();
-                a.xa1 = bufs[ia].p1; a.xa2 = bufs[ia].p2; a.xb1 = bufs[ib].p1; a.xb2 = bufs[ib].p2;
-                a.base1 = bufs[base].p1; a.base2 = bufs[base].p2; a.lam = d_lambda; a.f = d_f; a.mask = mask;
-                float *u_next = u_cur == d_u ? pl->u2() : d_u;
-                a.u_in = u_cur; a.u_out = u_next;
-                a.out1 = bufs[io].p1; a.out2 = bufs[io].p2;
-                a.theta_prev = it >= 1 ? (float)th[it - 1] : 0.0f;
-                a.sk = (float)sk[it]; a.tk = (float)tk[it]; a.tau = (float)P.tau;
-                a.c_keep = (float)(P.tau / (P.tau + tk[it]));
-                a.c_anchor = (float)(tk[it] / (P.tau + tk[it]));
-                a.fidelity = P.fidelity;
-                int rc = tm.begin();
-                if (rc != DTV_OK) return rc;
-                HIP_TRY(launch_cp2_step(a, it >= 1, pl->rows, s, tm.e0, tm.e1), "CP2 step");
-                rc = tm.end();
-                if (rc != DTV_OK) return rc;
-                u_cur = u_next;
-            }
-            base = sc[(K - 1) % 3];
-        }
-        const bool last = n == P.n_outer - 1;
-        if (P.diag_every > 0 && ((n + 1) % P.diag_every == 0 || last)) {
-            const float *u = u_cur;
-            if (!cp2) {
-                HIP_TRY(launch_u_from_p(pl->d_imgs(), pl->n, pl->maxH, pl->maxW, pl->d_info(), bufs[base].p1,
-                                        bufs[base].p2, d_f, d_u, s),
-                        "u recovery");
-                u = d_u;
-            }
-            int rc = emit_stats(n + 1, u, bufs[base]);
-            if (rc != DTV_OK) return rc;
-            if (P.gap_tol > 0.0 && drow[2] <= P.gap_tol * std::fabs(drow[0])) break;
-        }
-    }
     if (P.save_for_backward) {
         int rc = save_state(pl->nseg, bufs[base]);
         if (rc != DTV_OK) return rc;
@@ -717,7 +950,7 @@ static int rec_outer(dtv_dd_plan *pl, const float *state, const float *d_f, bool
 {
     const dtv_dd_params &P = pl->prm;
     const float *p1 = state, *p2 = state + pl->tot_p1, *lam = state + pl->edges();
-    const int K = P.n_inner;
+    const int K = P.n_inner, rows = pl->rows;
     if (pl->tot_lam > 0)
         HIP_TRY(hipMemcpyAsync(pl->lam1(), lam, sizeof(float) * (size_t)pl->tot_lam, hipMemcpyDeviceToDevice, s),
                 "lambda copy");
@@ -725,7 +958,7 @@ static int rec_outer(dtv_dd_plan *pl, const float *state, const float *d_f, bool
             "lambda update");
     for (int k = 1; k <= K; ++k) {
         FistaStepArgs a{};
-        a.imgs = pl->d_imgs(); a.tiles = pl->d_tiles(); a.ntiles = (int)pl->h_tiles.size(); a.info = pl->d_info();
+        a.imgs = pl->d_imgs(); a.tiles = pl->d_tiles(rows); a.ntiles = pl->ntiles(rows); a.info = pl->d_info();
         const float *xa = k == 1 ? state : pl->xrec(k - 2);
         const float *xbp = k >= 3 ? pl->xrec(k - 3) : state;
         a.xa1 = xa; a.xa2 = xa + pl->tot_p1;
@@ -739,7 +972,7 @@ static int rec_outer(dtv_dd_plan *pl, const float *state, const float *d_f, bool
         }
         a.beta = beta[k]; a.tau = (float)P.tau; a.inv_tau = (float)(1.0 / P.tau);
         const int mode = k == 1 ? kFistaFirst : (k == 2 ? kFistaPlain : kFistaMomentum);
-        HIP_TRY(launch_fista_step(a, mode, pl->rows, s), "FISTA step (recompute)");
+        HIP_TRY(launch_fista_step(a, mode, rows, s), "FISTA step (recompute)");
     }
     return DTV_OK;
 }
@@ -755,14 +988,14 @@ extern "C" int dtv_dd_backward(dtv_dd_plan *pl, const float *d_f, const float *d
     const int K = P.n_inner, N = pl->saved_outer, C = P.ckpt_every;
     const size_t E = pl->edges();
     const std::vector<float> beta = fista_betas(K);
-    const int ntiles = (int)pl->h_tiles.size();
+    const int rows = pl->rows, ntiles = pl->ntiles(rows);
 
     HIP_TRY(hipMemsetAsync(pl->galpha(), 0, sizeof(double) * (size_t)ntiles, s), "clear");
     HIP_TRY(hipMemsetAsync(pl->pb(), 0, sizeof(float) * E, s), "clear");
     if (pl->tot_lam > 0) HIP_TRY(hipMemsetAsync(pl->lb(), 0, sizeof(float) * (size_t)pl->tot_lam, s), "clear");
     // u = f + div p^N / alpha
     const float *pN = pl->ckpt(pl->nseg);
-    HIP_TRY(launch_bwd_final_u(pl->d_imgs(), pl->d_tiles(), ntiles, pl->rows, pl->d_info(), pN, pN + pl->tot_p1,
+    HIP_TRY(launch_bwd_final_u(pl->d_imgs(), pl->d_tiles(rows), ntiles, rows, pl->d_info(), pN, pN + pl->tot_p1,
                                d_grad_u, d_grad_f, pl->pb(), pl->pb() + pl->tot_p1, pl->galpha(), s),
             "final u reverse");
 
@@ -793,7 +1026,7 @@ extern "C" int dtv_dd_backward(dtv_dd_plan *pl, const float *d_f, const float *d
             HIP_TRY(hipMemsetAsync(pl->hb(), 0, sizeof(float) * E, s), "clear");
             for (int k = K; k >= 1; --k) {
                 FistaBwdArgs a{};
-                a.imgs = pl->d_imgs(); a.tiles = pl->d_tiles(); a.ntiles = ntiles; a.info = pl->d_info();
+                a.imgs = pl->d_imgs(); a.tiles = pl->d_tiles(rows); a.ntiles = ntiles; a.info = pl->d_info();
                 a.z1 = pl->zrec(k - 1); a.z2 = pl->zrec(k - 1) + pl->tot_p1;
                 const float *xa = k == 1 ? st : pl->xrec(k - 2);
                 const float *xbp = k >= 3 ? pl->xrec(k - 3) : st;
@@ -807,7 +1040,7 @@ extern "C" int dtv_dd_backward(dtv_dd_plan *pl, const float *d_f, const float *d
                 a.gh1 = pl->hb(); a.gh2 = pl->hb() + pl->tot_p1;
                 a.gf = d_grad_f; a.galpha = pl->galpha();
                 a.beta = beta[k]; a.tau = (float)P.tau; a.inv_tau = (float)(1.0 / P.tau);
-                HIP_TRY(launch_fista_bwd_step(a, k >= 3, pl->rows, s), "FISTA reverse step");
+                HIP_TRY(launch_fista_bwd_step(a, k >= 3, rows, s), "FISTA reverse step");
                 // xbar_k is consumed; its buffer becomes xbar_{k-3}
                 if (k >= 3) HIP_TRY(hipMemsetAsync(pl->xb(k % 3), 0, sizeof(float) * E, s), "clear");
             }
@@ -819,7 +1052,7 @@ extern "C" int dtv_dd_backward(dtv_dd_plan *pl, const float *d_f, const float *d
                     "interface reverse");
         }
     }
-    HIP_TRY(launch_alpha_reduce(pl->d_tiles(), ntiles, pl->n, pl->galpha(), d_grad_alpha, s), "alpha reduce");
+    HIP_TRY(launch_alpha_reduce(pl->d_tiles(rows), ntiles, pl->n, pl->galpha(), d_grad_alpha, s), "alpha reduce");
     return DTV_OK;
 }
 
@@ -866,6 +1099,15 @@ extern "C" int dtv_dd_kernel_time(const dtv_dd_plan *pl, double *avg_ms, int64_t
             *bytes_per_launch = tot / K;
         }
     }
+    return DTV_OK;
+}
+
+extern "C" int dtv_dd_choice(const dtv_dd_plan *pl, int32_t *schedule, int32_t *rows, int32_t *source)
+{
+    if (!pl) return fail(DTV_EINVAL, "null argument");
+    if (schedule) *schedule = pl->schedule;
+    if (rows) *rows = pl->rows;
+    if (source) *source = pl->choice_source;
     return DTV_OK;
 }
 

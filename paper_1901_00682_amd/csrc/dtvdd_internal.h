@@ -47,6 +47,8 @@ struct SubTile {
 };
 
 constexpr int kStreamCols = 63;   // output columns per wave
+constexpr int kRowChoices = 4;    // rows per strip of the streaming kernels: 4, 8, 16 or 32
+inline int row_index(int R) { return R <= 4 ? 0 : R <= 8 ? 1 : R <= 16 ? 2 : 3; }
 constexpr int kFusedMax = 128;    // largest subdomain side handled by the fused kernel
 constexpr int kMaxFusedInner = 64;  // largest n_inner of the fused kernel
 

@@ -26,7 +26,7 @@ SCHEDULE_NAME = {v: k for k, v in SCHEDULE.items()}
 
 # every entry point declared in include/dtvdd.h
 EXPORTS = ("dtv_dd_setup", "dtv_dd_layout", "dtv_dd_workspace_bytes", "dtv_dd_bind_workspace", "dtv_dd_solve",
-           "dtv_dd_diagnostics", "dtv_dd_backward", "dtv_dd_kernel_time", "dtv_dd_schedule", "dtv_dd_destroy",
+           "dtv_dd_diagnostics", "dtv_dd_backward", "dtv_dd_kernel_time", "dtv_dd_schedule", "dtv_dd_choice", "dtv_dd_destroy",
            "dtv_last_error")
 
 
@@ -49,7 +49,8 @@ class Params(ctypes.Structure):
                 ("n_outer", ctypes.c_int32), ("n_inner", ctypes.c_int32), ("diag_every", ctypes.c_int32),
                 ("gap_tol", ctypes.c_double), ("warm_start", ctypes.c_int32),
                 ("save_for_backward", ctypes.c_int32), ("ckpt_every", ctypes.c_int32),
-                ("schedule", ctypes.c_int32), ("time_kernels", ctypes.c_int32)]
+                ("schedule", ctypes.c_int32), ("time_kernels", ctypes.c_int32), ("rows", ctypes.c_int32),
+                ("no_graphs", ctypes.c_int32)]
 
 
 class Layout(ctypes.Structure):
@@ -83,6 +84,7 @@ def lib(path: str = LIB_PATH):
     L.dtv_dd_kernel_time.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_char_p),
                                      ctypes.POINTER(dbl)]
     L.dtv_dd_schedule.argtypes = [vp, ctypes.POINTER(i32)]
+    L.dtv_dd_choice.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.dtv_dd_destroy.argtypes = [vp]
     L.dtv_dd_destroy.restype = None
     L.dtv_last_error.restype = ctypes.c_char_p
@@ -123,7 +125,7 @@ class Plan:
     def __init__(self, images, *, fidelity="L2", inner=None, has_mask=False, tau=50.0, sigma=0.01, tau0=10.0,
                  sigma0=1.0 / 80.0, gamma=None, n_outer=100, n_inner=10, diag_every=0, gap_tol=0.0,
                  warm_start=False, save_for_backward=False, ckpt_every=20, schedule="auto",
-                 time_kernels=False, device=None, bind=True):
+                 time_kernels=False, rows=0, graphs=True, device=None, bind=True):
         import torch
 
         L = lib()
@@ -145,7 +147,8 @@ class Plan:
         self.params = Params(FIDELITY[fidelity], INNER[inner], int(has_mask), float(tau), float(sigma),
                              float(tau0), float(sigma0), float(gamma), int(n_outer), int(n_inner),
                              int(diag_every), float(gap_tol), int(warm_start), int(save_for_backward),
-                             int(ckpt_every), SCHEDULE[schedule], int(time_kernels))
+                             int(ckpt_every), SCHEDULE[schedule], int(time_kernels), int(rows),
+                             int(not graphs))
         h = ctypes.c_void_p()
         _check(L.dtv_dd_setup(descs, len(self.images), ctypes.byref(self.params), ctypes.byref(h)))
         self.h = h
@@ -173,6 +176,13 @@ class Plan:
         out = Layout()
         _check(lib().dtv_dd_layout(self.h, int(image), ctypes.byref(out)))
         return out
+
+    def choice(self) -> dict:
+        """Schedule, streaming rows and their source (rule, measured, cached, explicit)."""
+        sc, r, src = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().dtv_dd_choice(self.h, ctypes.byref(sc), ctypes.byref(r), ctypes.byref(src)))
+        return {"schedule": SCHEDULE_NAME[sc.value], "rows": r.value,
+                "source": ("rule", "measured", "cached", "explicit")[src.value]}
 
     def schedule(self) -> str:
         s = ctypes.c_int32()

@@ -39,7 +39,7 @@ def _setup(H=64, W=64, rc=(0, 32, 64), cc=(0, 32, 64), alpha=10.0, n_images=1, *
                                    cc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), alpha)
     base = dict(fidelity=0, inner=0, has_mask=0, tau=50.0, sigma=0.01, tau0=10.0, sigma0=1 / 80, gamma=1 / 400,
                 n_outer=10, n_inner=5, diag_every=0, gap_tol=0.0, warm_start=0, save_for_backward=0, ckpt_every=20,
-                schedule=0, time_kernels=0)
+                schedule=0, time_kernels=0, rows=0, no_graphs=0)
     base.update(kw)
     prm = dtvdd.Params(**base)
     h = ctypes.c_void_p()
@@ -83,6 +83,9 @@ def test_valid_setup_and_layout():
     (dict(H=0), "sizes"),
     (dict(fidelity=7), "fidelity"),
     (dict(schedule=9), "schedule"),
+    (dict(rows=5), "rows"),
+    (dict(no_graphs=2), "no_graphs"),
+    (dict(schedule=3), "persistent"),
 ])
 def test_validation_errors(kw, msg):
     code, h = _setup(**kw)
@@ -115,3 +118,21 @@ def test_default_cuts_are_floor():
     L.dtv_dd_layout(h, 0, ctypes.byref(lay))
     assert lay.n_lam_h == 12 * 3000 and lay.n_lam_v == 19 * 2000
     L.dtv_dd_destroy(h)
+
+
+def test_schedule_choice_reporting():
+    """Before any solve the choice comes from the fixed rule; explicit
+    parameters are reported as explicit (no GPU needed)."""
+    L = dtvdd.lib()
+    sc, r, src = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    code, h = _setup()
+    assert code == 0
+    assert L.dtv_dd_choice(h, ctypes.byref(sc), ctypes.byref(r), ctypes.byref(src)) == 0
+    assert (r.value, src.value) == (16, 0)
+    L.dtv_dd_destroy(h)
+    code, h = _setup(schedule=1, rows=8)
+    assert code == 0
+    assert L.dtv_dd_choice(h, ctypes.byref(sc), ctypes.byref(r), ctypes.byref(src)) == 0
+    assert (sc.value, r.value, src.value) == (1, 8, 3)
+    L.dtv_dd_destroy(h)
+    assert L.dtv_dd_choice(None, None, None, None) == dtvdd.DTV_EINVAL
