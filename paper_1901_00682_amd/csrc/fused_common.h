@@ -21,14 +21,16 @@ struct FusedLds {
                                      // step parity: a strip may start the next step while the strip
                                      // above still reads the current row
     float dl[kWaves][kFusedMax];     // d of each strip's last row
+    float dR[kFusedMax];             // full tiles: d of the last column, per row
     float c1[kFusedMax][kFusedMax];  // c' of the edge above pixel (il, jl)
     float c2[kFusedMax][kFusedMax];  // c' of the edge left of pixel (il, jl)
 };
 
-// lane i receives lane i - 1 (lane 0 receives 0)
+// lane i receives lane i - 1 (lane 0 receives 0); the zero comes from the
+// bound control, so the move can fold into the instruction that consumes it
 __device__ __forceinline__ float from_left(float x)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x138, 0xF, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x138, 0xF, 0xF, true));
 }
 
 // lane i receives lane i + 1 (lane 63 receives 0)
@@ -176,7 +178,7 @@ __device__ __forceinline__ void fused_step(const Ctx &c0, FusedLds &S, const Slo
 // row (strip 15) by wave-uniform branches, the left edges of column 0 by
 // clamp bounds that collapse to 0 on the image boundary, and the right
 // boundary column by lanes 0..7 of each strip after the row sweep (lane r
-// updates row 8 s + r from the last column's d, gathered with lane moves).
+// updates row 8 s + r from the last column's d, passed through LDS).
 
 struct FullCtx {
     int s, lane, ja, il0;
@@ -272,11 +274,9 @@ __device__ __forceinline__ void full_step(const FullCtx &c, FusedLds &S, const S
     ya7 = c.last ? Y.ba : ya7;
     yb7 = c.last ? Y.bb : yb7;
     float *dl = &S.dl[0][0] + oy;
-    {
-        float da7, db7;
-        full_row_div(Y, RYr, kR - 1, ya7, yb7, da7, db7);
-        lds_st2(dl, da7, db7);
-    }
+    float da7, db7;  // d of the last row (the row sweep reuses it)
+    full_row_div(Y, RYr, kR - 1, ya7, yb7, da7, db7);
+    lds_st2(dl, da7, db7);
     __syncthreads();
 
     // (3) row sweep
@@ -285,13 +285,11 @@ __device__ __forceinline__ void full_step(const FullCtx &c, FusedLds &S, const S
     dua = c.s > 0 ? dua : 0.0f;
     dub = c.s > 0 ? dub : 0.0f;
     const float *c1 = &S.c1[0][0] + oc, *c2 = &S.c2[0][0] + oc;
-    float dR = 0.0f;  // lane r: d of the last column in row r
 #pragma unroll
     for (int r = 0; r < kR; ++r) {
         __builtin_amdgcn_sched_barrier(0);  // one row at a time: bounds the registers in flight
-        float da, db;
+        float da = da7, db = db7;
         if (r < kR - 1) full_row_div(Y, RYr, r, Y.e1a[r + 1], Y.e1b[r + 1], da, db);
-        else full_row_div(Y, RYr, r, ya7, yb7, da, db);
         const float dlb = from_left(db);
         float c1a, c1b, c2a, c2b;
         lds_ld2(c1 + r * kFusedMax, c1a, c1b);
@@ -312,15 +310,12 @@ __device__ __forceinline__ void full_step(const FullCtx &c, FusedLds &S, const S
             Y.ba = __builtin_amdgcn_fmed3f(fista_z(Y.ba, da, 0.0f, cba, ak, kL), c.lob, c.hib);
             Y.bb = __builtin_amdgcn_fmed3f(fista_z(Y.bb, db, 0.0f, cbb, ak, kL), c.lob, c.hib);
         }
-        {
-            const float dlast = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(db), 63));
-            dR = c.lane == r ? dlast : dR;
-        }
+        if (c.lane == 63) S.dR[orow + r] = db;  // the last column's d, for the right boundary edges
         pin4(Y.e1a[r], Y.e1b[r], Y.e2a[r], Y.e2b[r]);
         dua = da;
         dub = db;
     }
-    if (!c.right_bnd && c.lane < kR) RY[olr] = fista_edge(RY[olr], dR, 0.0f, S.cr[olr], ak, kL);
+    if (!c.right_bnd && c.lane < kR) RY[olr] = fista_edge(RY[olr], S.dR[olr], 0.0f, S.cr[olr], ak, kL);
 }
 
 struct GenericStep {

@@ -209,13 +209,16 @@ __global__ __launch_bounds__(1024) void k_persist_fista(PersistArgs a)
         {
             // per outer step, so that the row addresses are formed here and not hoisted out of the loop
             const int jo = opaque(ja);
+            // all rows' loads first, then the conditional one (its wait covers them all)
+            float fra[kR], frb[kR];
+#pragma unroll
+            for (int r = 0; r < kR; ++r) ld2g(f_tile + (long long)(il0 + r) * W + jo, fra[r], frb[r]);
             float fua = 0.0f, fub = 0.0f;  // f of the row above (0 above the tile)
             if (il0 > 0) ld2g(f_tile + (long long)(il0 - 1) * W + jo, fua, fub);
 #pragma unroll
             for (int r = 0; r < kR; ++r) {
                 const int il = il0 + r;
-                float fva, fvb;
-                ld2g(f_tile + (long long)il * W + jo, fva, fvb);
+                const float fva = fra[r], fvb = frb[r];
                 const float fla = from_left(fvb);  // f of column a - 1 (lane 0: left of the tile, 0)
                 lds_st2(&S.c1[il][ja], fista_cprime(A.e1a[r], fua, fva, itau, invL),
                         fista_cprime(A.e1b[r], fub, fvb, itau, invL));
