@@ -108,7 +108,7 @@ struct dtv_dd_plan {
     // workspace layout (byte offsets)
     size_t off_imgs = 0, off_info = 0, off_tiles[kRowChoices] = {0, 0, 0, 0}, off_subs = 0, off_buf[3] = {0, 0, 0},
            off_u2 = 0,
-           off_part = 0, off_dout = 0, off_xch = 0, off_sync = 0, ws_bytes = 0;
+           off_part = 0, off_dout = 0, off_xch = 0, off_sync = 0, off_lamw = 0, ws_bytes = 0;
     int diag_nblk = 0;
     char *ws = nullptr;
     double *h_diag = nullptr;  // pinned host mirror of the diagnostics sums
@@ -156,6 +156,7 @@ struct dtv_dd_plan {
     double *galpha() const { return (double *)(ws + off_galpha); }
     double *dout() const { return (double *)(ws + off_dout); }
     unsigned long long *xch() const { return (unsigned long long *)(ws + off_xch); }
+    float *lamw() const { return (float *)(ws + off_lamw); }  // second lambda state (fused schedule)
     unsigned *sync_words() const { return (unsigned *)(ws + off_sync); }  // error flag of the persistent kernel
 };
 
@@ -373,6 +374,7 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
     pl->off_dout = take(sizeof(double) * 6 * (size_t)n_images);
     pl->off_xch = take(pl->persist_ok ? sizeof(unsigned long long) * 2 * (size_t)pl->tot_lam : 0);
     pl->off_sync = take(2 * sizeof(unsigned));
+    pl->off_lamw = take(sizeof(float) * (size_t)pl->tot_lam);
     if (p.save_for_backward) {
         const size_t E = (size_t)(pl->tot_p1 + pl->tot_p2);
         pl->state_floats = E + (size_t)pl->tot_lam;
@@ -625,7 +627,9 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
     // edge buffers: 0 = the caller's p~, 1..3 = workspace
     EdgeBuf bufs[4] = {{d_p1, d_p2}, {pl->buf1(0), pl->buf2(0)}, {pl->buf1(1), pl->buf2(1)}, {pl->buf1(2), pl->buf2(2)}};
     int base = 0;
-    float *u_cur = d_u;  // CP2: current u buffer (d_u or the workspace copy)
+    float *u_cur = d_u;       // CP2: current u buffer (d_u or the workspace copy)
+    float *lam_cur = d_lambda;  // current lambda state (the fused schedule alternates with the workspace copy)
+    auto lam_other = [&]() { return lam_cur == d_lambda ? pl->lamw() : d_lambda; };
     Timer tm{pl, s, 0, P.time_kernels != 0};
     const int rows_cap = P.diag_every > 0 ? P.n_outer / P.diag_every + 1 : 0;
     int nrow = 0;
@@ -635,8 +639,8 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
     FusedArgs fa{};
     fa.imgs = pl->d_imgs();
     fa.subs = pl->d_subs();
-    fa.lam = d_lambda;
     fa.f = d_f;
+    fa.sigma = (float)P.sigma;
     fa.tau = (float)P.tau;
     fa.inv_tau = (float)(1.0 / P.tau);
     fa.n_inner = std::min(K, kMaxFusedInner);
@@ -663,7 +667,7 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
         HIP_TRY(hipMemcpyAsync(dst + pl->tot_p1, b.p2, sizeof(float) * (size_t)pl->tot_p2, hipMemcpyDeviceToDevice, s),
                 "checkpoint");
         if (pl->tot_lam > 0)
-            HIP_TRY(hipMemcpyAsync(dst + pl->edges(), d_lambda, sizeof(float) * (size_t)pl->tot_lam,
+            HIP_TRY(hipMemcpyAsync(dst + pl->edges(), lam_cur, sizeof(float) * (size_t)pl->tot_lam,
                                    hipMemcpyDeviceToDevice, s),
                     "checkpoint");
         return DTV_OK;
@@ -678,15 +682,18 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
             int rc = save_state(n / P.ckpt_every, bufs[base]);
             if (rc != DTV_OK) return rc;
         }
-        // (a1) multipliers from the extrapolated interface jump
-        HIP_TRY(launch_lambda(pl->d_imgs(), pl->n, pl->max_nlam, pl->d_info(), bufs[base].p1, bufs[base].p2, d_lambda,
-                              (float)P.sigma, q),
-                "lambda update");
+        // (a1) multipliers from the extrapolated interface jump: inside the fused kernel, else a launch
+        if (sched != DTV_SCHED_FUSED)
+            HIP_TRY(launch_lambda(pl->d_imgs(), pl->n, pl->max_nlam, pl->d_info(), bufs[base].p1, bufs[base].p2,
+                                  lam_cur, (float)P.sigma, q),
+                    "lambda update");
         // (a2)+(a3) local solves; the anchor phat is formed on the fly from p~^n and lambda
         if (sched == DTV_SCHED_FUSED) {
             const int out = next_base(sched, cp2, K, base);
             fa.base1 = bufs[base].p1; fa.base2 = bufs[base].p2;
             fa.out1 = bufs[out].p1; fa.out2 = bufs[out].p2;
+            fa.lam = lam_cur;
+            fa.lam_out = lam_other();
             int rc = with_host ? tm.begin() : DTV_OK;
             if (rc != DTV_OK) return rc;
             HIP_TRY(launch_fused_fista(fa, (int)pl->h_subs.size(), pl->n_full, q, with_host ? tm.e0 : nullptr,
@@ -695,6 +702,7 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
             rc = with_host ? tm.end() : DTV_OK;
             if (rc != DTV_OK) return rc;
             base = out;
+            lam_cur = lam_other();
         } else if (!cp2) {
             // x_k lives in rot[k % 3]; c' in workspace buffer 3
             int rot[3] = {base, 0, 0}, r = 1;
@@ -705,7 +713,7 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
                 FistaStepArgs a{};
                 a.imgs = pl->d_imgs(); a.tiles = pl->d_tiles(rows); a.ntiles = pl->ntiles(rows); a.info = pl->d_info();
                 a.xa1 = bufs[ia].p1; a.xa2 = bufs[ia].p2; a.xb1 = bufs[ib].p1; a.xb2 = bufs[ib].p2;
-                a.lam = d_lambda; a.f = d_f;
+                a.lam = lam_cur; a.f = d_f;
                 a.c1 = bufs[3].p1; a.c2 = bufs[3].p2;
                 a.out1 = bufs[io].p1; a.out2 = bufs[io].p2;
                 a.beta = beta[k]; a.tau = (float)P.tau; a.inv_tau = (float)(1.0 / P.tau);
@@ -730,7 +738,7 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
                 Cp2StepArgs a{};
                 a.imgs = pl->d_imgs(); a.tiles = pl->d_tiles(rows); a.ntiles = pl->ntiles(rows); a.info = pl->d_info();
                 a.xa1 = bufs[ia].p1; a.xa2 = bufs[ia].p2; a.xb1 = bufs[ib].p1; a.xb2 = bufs[ib].p2;
-                a.base1 = bufs[base].p1; a.base2 = bufs[base].p2; a.lam = d_lambda; a.f = d_f; a.mask = mask;
+                a.base1 = bufs[base].p1; a.base2 = bufs[base].p2; a.lam = lam_cur; a.f = d_f; a.mask = mask;
                 float *u_next = u_cur == d_u ? pl->u2() : d_u;
                 a.u_in = u_cur; a.u_out = u_next;
                 a.out1 = bufs[io].p1; a.out2 = bufs[io].p2;
@@ -774,7 +782,8 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
         pa.fa = fa;
         pa.fa.base1 = pa.fa.out1 = bufs[base].p1;
         pa.fa.base2 = pa.fa.out2 = bufs[base].p2;
-        pa.lam_out = d_lambda;
+        pa.fa.lam = lam_cur;
+        pa.lam_out = lam_cur;
         pa.xch = pl->xch();
         pa.xch_stride = pl->tot_lam;
         pa.err = (int *)sync;
@@ -803,14 +812,15 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
         int n = n0;
         if (graphs && !host_work && !P.no_graphs && n1 - n0 >= 4) {
             // the buffer state (base, which u buffer is current) after each step
-            auto state = [&](int b, bool uf) { return b * 2 + (uf ? 1 : 0); };
+            auto state = [&](int b, bool uf, bool lp) { return b * 4 + (uf ? 2 : 0) + (lp ? 1 : 0); };
             std::vector<int> seq;
             int b = base;
-            bool uf = u_cur != d_u;
+            bool uf = u_cur != d_u, lp = lam_cur != d_lambda;
             for (int i = 0; i < 8; ++i) {
-                seq.push_back(state(b, uf));
+                seq.push_back(state(b, uf, lp));
                 b = next_base(sched, cp2, K, b);
                 if (cp2 && (K & 1)) uf = !uf;
+                if (sched == DTV_SCHED_FUSED) lp = !lp;
             }
             int start = -1, period = 0;
             for (int i = 0; i < 4 && start < 0; ++i)
@@ -825,7 +835,7 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
                     int rc = outer_step(n, sched, rows, s, false);
                     if (rc != DTV_OK) return rc;
                 }
-                const GraphKey key{sched, rows, base, u_cur != d_u, period, d_f, mask, d_u, d_p1, d_p2, d_lambda, pl->ws};
+                const GraphKey key{sched, rows, base, u_cur != d_u, period, d_f, mask, d_u, d_p1, d_p2, lam_cur, pl->ws};
                 if (!pl->gexec || !(pl->gkey == key)) {
                     if (pl->gexec) {
                         (void)hipGraphExecDestroy(pl->gexec);
@@ -833,7 +843,7 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
                     }
                     if (!pl->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking), "stream");
                     const int base0 = base;
-                    float *u0 = u_cur;
+                    float *u0 = u_cur, *l0 = lam_cur;
                     HIP_TRY(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal), "graph capture");
                     int rc = DTV_OK;
                     for (int i = 0; i < period && rc == DTV_OK; ++i) rc = outer_step(n + i, sched, rows, pl->cap_stream, false);
@@ -841,6 +851,7 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
                     const hipError_t ge = hipStreamEndCapture(pl->cap_stream, &g);
                     base = base0;  // the captured cycle returns to the same buffers
                     u_cur = u0;
+                    lam_cur = l0;
                     if (rc != DTV_OK) {
                         if (g) (void)hipGraphDestroy(g);
                         return rc;
@@ -914,6 +925,9 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
         pl->saved = true;
         pl->saved_outer = P.n_outer;
     }
+    if (lam_cur != d_lambda && pl->tot_lam > 0)
+        HIP_TRY(hipMemcpyAsync(d_lambda, lam_cur, sizeof(float) * (size_t)pl->tot_lam, hipMemcpyDeviceToDevice, s),
+                "copy lambda");
     if (base != 0) {
         HIP_TRY(hipMemcpyAsync(d_p1, bufs[base].p1, sizeof(float) * (size_t)pl->tot_p1, hipMemcpyDeviceToDevice, s), "copy p1");
         HIP_TRY(hipMemcpyAsync(d_p2, bufs[base].p2, sizeof(float) * (size_t)pl->tot_p2, hipMemcpyDeviceToDevice, s), "copy p2");

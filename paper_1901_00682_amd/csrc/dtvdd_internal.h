@@ -110,7 +110,9 @@ struct FusedArgs {
     const ImgDev *imgs;
     const SubTile *subs;
     const float *base1, *base2;  // p~^n
-    const float *lam;
+    const float *lam;            // lambda state of step n (lambda^n, p_s^(n-1), p_t^(n-1))
+    float *lam_out;              // fused kernel: lambda state of step n + 1 (not aliasing lam)
+    float sigma;
     const float *f;
     float *out1, *out2;          // p~^(n+1)
     float tau, inv_tau;

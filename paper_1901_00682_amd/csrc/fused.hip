@@ -36,6 +36,7 @@ template <bool kFull, int KF>
 __global__ __launch_bounds__(1024) void k_fused_fista(FusedArgs a, int first)
 {
     __shared__ FusedLds S;
+    __shared__ float LS[4][kFusedMax];  // lambda^(n+1) on the top, bottom, left and right sides
     const int t = first + xcd_remap(blockIdx.x, gridDim.x);
     const SubTile tl = a.subs[t];
     const ImgDev im = a.imgs[tl.img];
@@ -66,7 +67,6 @@ __global__ __launch_bounds__(1024) void k_fused_fista(FusedArgs a, int first)
     const long long col2 = (long long)tl.ca + tl.c;  // P2 column of the tile's edge column 0
     const float *b1 = a.base1 + im.p1, *b2 = a.base2 + im.p2;
     float *o1 = a.out1 + im.p1, *o2 = a.out2 + im.p2;
-    const float *lam = a.lam + im.lam;
     const float *f = a.f + im.px;
     const float tau = a.tau, itau = a.inv_tau, invL = im.invL;
 
@@ -92,15 +92,13 @@ __global__ __launch_bounds__(1024) void k_fused_fista(FusedArgs a, int first)
     const bool lastcol = c.lastcol_a || c.lastcol_b;
     float fva[kR], fvb[kR];  // f of the strip's rows at columns a and b
     float xr[kR];            // right boundary edges of the rows (last-column lane)
-    float lam_l[kR], lam_r[kR];  // lambda of the left / right interface edges of the rows
     float fua = 0.0f, fub = 0.0f;  // f of the row above (0 above the tile)
-    float lta = 0.0f, ltb = 0.0f, lba = 0.0f, lbb = 0.0f;  // lambda of the top / bottom interface edges
     // the rows' edges and image values first (unconditional on full tiles) ...
 #pragma unroll
     for (int r = 0; r < kR; ++r) {
         const int il = il0 + r;
         float x1a = 0.0f, x1b = 0.0f, x2a = 0.0f, x2b = 0.0f;
-        fva[r] = fvb[r] = xr[r] = lam_l[r] = lam_r[r] = 0.0f;
+        fva[r] = fvb[r] = xr[r] = 0.0f;
         if (kFull || il < h) {  // (always on full tiles)
             const float *p1r = p1_tile + (long long)il * P1;
             const float *p2r = p2_tile + (long long)il * P2;
@@ -123,35 +121,72 @@ __global__ __launch_bounds__(1024) void k_fused_fista(FusedArgs a, int first)
         if (c.actb) ld2(fr + ja, fua, fub);
         else if (c.acta) fua = fr[ja];
     }
-    if (il0 == 0 && tl.r > 0) {  // t copies of the interface above
-        const float *lr = lam + (long long)(tl.r - 1) * W + tl.ca;
-        if (c.acta) lta = lr[ja];
-        if (c.actb) ltb = lr[jb];
-    }
     if (c.has_bottom) {  // bottom boundary edges
         const float *pb = p1_tile + (long long)h * P1;
-        const float *lb = lam + (long long)tl.r * W + tl.ca;
-        if (c.acta) {
-            A.ba = pb[ja];
-            if (!c.bot_bnd) lba = lb[ja];
-        }
-        if (c.actb) {
-            A.bb = pb[jb];
-            if (!c.bot_bnd) lbb = lb[jb];
-        }
+        if (c.acta) A.ba = pb[ja];
+        if (c.actb) A.bb = pb[jb];
     }
 #pragma unroll
     for (int r = 0; r < kR; ++r) {
         const int il = il0 + r;
-        if (kFull || il < h) {  // (always on full tiles)
-            const long long gi = tl.ra + il;
-            if (ja == 0 && tl.c > 0) lam_l[r] = lam[im.nlh + (long long)(tl.c - 1) * H + gi];
-            if (lastcol) {  // right boundary edge of this row
-                xr[r] = p2_tile[(long long)il * P2 + w];
-                if (!c.right_bnd) lam_r[r] = lam[im.nlh + (long long)tl.c * H + gi];
+        if ((kFull || il < h) && lastcol) xr[r] = p2_tile[(long long)il * P2 + w];  // right boundary edge of the row
+    }
+
+    // ---- (a1) lambda^(n+1) = lambda^n + sigma [(2 p_s^n - p_s^(n-1)) - (2 p_t^n - p_t^(n-1))] on the
+    // tile's interface edges, with the operations of the multiplier kernel (the two tiles of an
+    // interface compute the same value).  Waves 0..7 take the top, bottom, left and right sides
+    // (two waves each).  The new lambda state goes to lam_out: lambda^(n+1) and p_s^n by the s
+    // side (bottom, right), p_t^n by the t side (top, left).
+    {
+        const int side = c.s >> 1, si = (c.s & 1) * 64 + c.lane;
+        bool has = false;
+        long long e = 0, ips = 0, ipt = 0;  // lambda index; P1 or P2 offsets of the s and t copies
+        if (c.s < 2 * 4 && si < (side < 2 ? w : h)) {
+            const long long rs = (long long)(tl.ra + si) * P2;  // P2 row of a left / right edge
+            switch (side) {
+            case 0:  // top: the tile above holds the s copy
+                has = tl.r > 0;
+                e = (long long)(tl.r - 1) * W + tl.ca + si;
+                ips = (row1 - 1) * P1 + tl.ca + si;
+                ipt = row1 * P1 + tl.ca + si;
+                break;
+            case 1:  // bottom: the tile below holds the t copy
+                has = tl.r < im.ny - 1;
+                e = (long long)tl.r * W + tl.ca + si;
+                ips = (row1 + h) * P1 + tl.ca + si;
+                ipt = (row1 + h + 1) * P1 + tl.ca + si;
+                break;
+            case 2:  // left: the tile on the left holds the s copy
+                has = tl.c > 0;
+                e = im.nlh + (long long)(tl.c - 1) * H + tl.ra + si;
+                ips = rs + col2 - 1;
+                ipt = rs + col2;
+                break;
+            default:  // right: the tile on the right holds the t copy
+                has = tl.c < im.nx - 1;
+                e = im.nlh + (long long)tl.c * H + tl.ra + si;
+                ips = rs + col2 + w;
+                ipt = rs + col2 + w + 1;
+                break;
+            }
+        }
+        if (has) {
+            const float *pp = side < 2 ? b1 : b2;
+            const float ps = pp[ips], pt = pp[ipt];
+            const float *Li = a.lam + im.lam;
+            float *Lo = a.lam_out + im.lam;
+            const long long nl = im.nlam;
+            const float l1 = Li[e] + a.sigma * ((2.0f * ps - Li[nl + e]) - (2.0f * pt - Li[2 * nl + e]));
+            LS[side][si] = l1;
+            if (side == 1 || side == 3) {
+                Lo[e] = l1;
+                Lo[nl + e] = ps;
+            } else {
+                Lo[2 * nl + e] = pt;
             }
         }
     }
+    __syncthreads();
 #pragma unroll
     for (int r = 0; r < kR; ++r) {
         const int il = il0 + r;
@@ -160,12 +195,12 @@ __global__ __launch_bounds__(1024) void k_fused_fista(FusedArgs a, int first)
             // top edges (t copies of an interface on the tile's first row)
             float ata = A.e1a[r], atb = A.e1b[r];
             if (il == 0 && tl.r > 0) {
-                if (c.acta) ata = fmaf(tau, lta, ata);
-                if (c.actb) atb = fmaf(tau, ltb, atb);
+                if (c.acta) ata = fmaf(tau, LS[0][ja], ata);
+                if (c.actb) atb = fmaf(tau, LS[0][jb], atb);
             }
             // left edge (t copy of an interface on the tile's first column)
             float ala = A.e2a[r];
-            if (ja == 0 && tl.c > 0) ala = fmaf(tau, lam_l[r], ala);
+            if (ja == 0 && tl.c > 0) ala = fmaf(tau, LS[2][il], ala);
             if (c.acta) {
                 S.c1[il][ja] = fista_cprime(ata, fua, fva[r], itau, invL);
                 S.c2[il][ja] = fista_cprime(ala, ja > 0 ? fla : 0.0f, fva[r], itau, invL);
@@ -176,18 +211,18 @@ __global__ __launch_bounds__(1024) void k_fused_fista(FusedArgs a, int first)
             }
             if (il == h - 1) {  // bottom boundary edges (s copies unless on the image boundary)
                 if (c.acta) {
-                    const float ab = c.bot_bnd ? A.ba : fmaf(-tau, lba, A.ba);
+                    const float ab = c.bot_bnd ? A.ba : fmaf(-tau, LS[1][ja], A.ba);
                     S.cb[ja] = fista_cprime(ab, fva[r], 0.0f, itau, invL);
                 }
                 if (c.actb) {
-                    const float ab = c.bot_bnd ? A.bb : fmaf(-tau, lbb, A.bb);
+                    const float ab = c.bot_bnd ? A.bb : fmaf(-tau, LS[1][jb], A.bb);
                     S.cb[jb] = fista_cprime(ab, fvb[r], 0.0f, itau, invL);
                 }
             }
             if (lastcol) {  // right boundary edge of this row
                 S.rx[0][il] = xr[r];
                 S.rx[1][il] = xr[r];
-                const float ar = c.right_bnd ? xr[r] : fmaf(-tau, lam_r[r], xr[r]);
+                const float ar = c.right_bnd ? xr[r] : fmaf(-tau, LS[3][il], xr[r]);
                 S.cr[il] = fista_cprime(ar, c.lastcol_a ? fva[r] : fvb[r], 0.0f, itau, invL);
             }
         }
