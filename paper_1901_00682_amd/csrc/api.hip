@@ -117,7 +117,8 @@ struct dtv_dd_plan {
     int nseg = 0;             // checkpoint slots ckpt(0..nseg-1) hold the state before steps 0, C, 2C, ...
     size_t state_floats = 0;  // one state: P1, P2, then the lambda state
     size_t off_ckpt = 0, off_seg = 0, off_xrec = 0, off_zrec = 0, off_lam1 = 0, off_xb = 0, off_hb = 0, off_pb = 0,
-           off_lb = 0, off_galpha = 0;
+           off_lb = 0, off_galpha = 0, off_frec = 0, off_gsub = 0;
+    bool fbwd = false;        // reverse mode with the fused kernels (every subdomain 128 x 128)
     bool saved = false;       // the last solve saved its checkpoints
     int saved_outer = 0;      // outer steps of that solve
 
@@ -154,6 +155,8 @@ struct dtv_dd_plan {
     float *pb() const { return (float *)(ws + off_pb); }
     float *lb() const { return (float *)(ws + off_lb); }
     double *galpha() const { return (double *)(ws + off_galpha); }
+    float *frec() const { return (float *)(ws + off_frec); }       // step records of the fused forward
+    double *gsub() const { return (double *)(ws + off_gsub); }     // per-subdomain alpha partial sums
     double *dout() const { return (double *)(ws + off_dout); }
     unsigned long long *xch() const { return (unsigned long long *)(ws + off_xch); }
     float *lamw() const { return (float *)(ws + off_lamw); }  // second lambda state (fused schedule)
@@ -383,8 +386,16 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
         const int segmax = std::min(C, std::max(p.n_outer, 1));
         pl->off_ckpt = take(sizeof(float) * pl->state_floats * (size_t)(pl->nseg + 1));
         pl->off_seg = take(sizeof(float) * pl->state_floats * (size_t)segmax);
-        pl->off_xrec = take(sizeof(float) * E * (size_t)p.n_inner);
-        pl->off_zrec = take(sizeof(float) * E * (size_t)p.n_inner);
+        const size_t nsub = pl->h_subs.size();
+        pl->fbwd = pl->fused_ok && pl->n_full == (int)nsub && fused_record_supported(p.n_inner) &&
+                   fused_bwd_supported(p.n_inner);
+        if (pl->fbwd) {
+            pl->off_frec = take(sizeof(float) * (size_t)p.n_inner * nsub * kRecWords * kRecThreads);
+            pl->off_gsub = take(sizeof(double) * nsub);
+        } else {
+            pl->off_xrec = take(sizeof(float) * E * (size_t)p.n_inner);
+            pl->off_zrec = take(sizeof(float) * E * (size_t)p.n_inner);
+        }
         pl->off_lam1 = take(sizeof(float) * (size_t)pl->tot_lam);
         pl->off_xb = take(sizeof(float) * E * 3);
         pl->off_hb = take(sizeof(float) * E);
@@ -991,6 +1002,82 @@ static int rec_outer(dtv_dd_plan *pl, const float *state, const float *d_f, bool
     return DTV_OK;
 }
 
+// Reverse mode with the fused kernels (every subdomain 128 x 128): per outer
+// step one recording forward launch and one on-chip reverse launch (the n_inner
+// reverse steps), then the interface transpose.  pbar holds the adjoint of the
+// final p~ (from the u recovery) on entry.
+static int backward_fused(dtv_dd_plan *pl, const float *d_f, float *d_grad_f, float *d_grad_alpha,
+                          const std::vector<float> &beta, hipStream_t s)
+{
+    const dtv_dd_params &P = pl->prm;
+    const int K = P.n_inner, N = pl->saved_outer, C = P.ckpt_every, nsub = (int)pl->h_subs.size();
+    const size_t E = pl->edges();
+    HIP_TRY(hipMemsetAsync(pl->gsub(), 0, sizeof(double) * (size_t)nsub, s), "clear");
+    FusedArgs fa{};
+    fa.imgs = pl->d_imgs();
+    fa.subs = pl->d_subs();
+    fa.f = d_f;
+    fa.sigma = (float)P.sigma;
+    fa.tau = (float)P.tau;
+    fa.inv_tau = (float)(1.0 / P.tau);
+    fa.n_inner = K;
+    for (int k = 1; k <= K; ++k) fa.beta[k] = beta[k];
+    FusedBwdArgs ba{};
+    ba.imgs = pl->d_imgs();
+    ba.subs = pl->d_subs();
+    ba.rec = pl->frec();
+    ba.lam = pl->lam1();
+    ba.f = d_f;
+    ba.pb1 = pl->pb();
+    ba.pb2 = pl->pb() + pl->tot_p1;
+    ba.hb1 = pl->hb();
+    ba.hb2 = pl->hb() + pl->tot_p1;
+    ba.gf = d_grad_f;
+    ba.galpha = pl->gsub();
+    ba.tau = (float)P.tau;
+    ba.inv_tau = (float)(1.0 / P.tau);
+    ba.n_inner = K;
+    for (int k = 1; k <= K; ++k) ba.beta[k] = beta[k];
+    // one outer step of the fused forward from a state (p~, lambda state) to p~ out, lambda state out
+    auto forward = [&](const float *st, float *p_out, float *lam_out, float *rec) -> int {
+        fa.base1 = st;
+        fa.base2 = st + pl->tot_p1;
+        fa.lam = st + E;
+        fa.out1 = p_out;
+        fa.out2 = p_out + pl->tot_p1;
+        fa.lam_out = lam_out;
+        fa.rec = rec;
+        HIP_TRY(launch_fused_fista(fa, nsub, pl->n_full, s), rec ? "fused FISTA (recording)" : "fused FISTA");
+        return DTV_OK;
+    };
+    for (int sg = pl->nseg - 1; sg >= 0; --sg) {
+        const int n0 = sg * C, n1 = std::min(N, n0 + C), m = n1 - n0;
+        HIP_TRY(hipMemcpyAsync(pl->seg(0), pl->ckpt(sg), sizeof(float) * pl->state_floats, hipMemcpyDeviceToDevice, s),
+                "restore checkpoint");
+        for (int q = 0; q + 1 < m; ++q) {  // the segment's states
+            int rc = forward(pl->seg(q), pl->seg(q + 1), pl->seg(q + 1) + E, nullptr);
+            if (rc != DTV_OK) return rc;
+        }
+        for (int q = m - 1; q >= 0; --q) {  // its outer steps in reverse
+            const float *st = pl->seg(q);
+            int rc = forward(st, pl->buf1(0), pl->lam1(), pl->frec());
+            if (rc != DTV_OK) return rc;
+            ba.x0_1 = st;
+            ba.x0_2 = st + pl->tot_p1;
+            HIP_TRY(launch_fused_bwd(ba, nsub, s), "fused reverse steps");
+            HIP_TRY(launch_bwd_interface(pl->d_imgs(), pl->n, pl->max_nlam, pl->d_info(), pl->hb(),
+                                         pl->hb() + pl->tot_p1, pl->pb(), pl->pb() + pl->tot_p1, pl->lb(),
+                                         (float)P.tau, (float)P.sigma, s),
+                    "interface reverse");
+        }
+    }
+    const int rows = pl->rows;
+    HIP_TRY(launch_alpha_reduce2(pl->d_tiles(rows), pl->ntiles(rows), pl->galpha(), pl->d_subs(), nsub, pl->gsub(),
+                                 pl->n, d_grad_alpha, s),
+            "alpha reduce");
+    return DTV_OK;
+}
+
 extern "C" int dtv_dd_backward(dtv_dd_plan *pl, const float *d_f, const float *d_grad_u, float *d_grad_f,
                                float *d_grad_alpha, void *stream)
 {
@@ -1012,6 +1099,7 @@ extern "C" int dtv_dd_backward(dtv_dd_plan *pl, const float *d_f, const float *d
     HIP_TRY(launch_bwd_final_u(pl->d_imgs(), pl->d_tiles(rows), ntiles, rows, pl->d_info(), pN, pN + pl->tot_p1,
                                d_grad_u, d_grad_f, pl->pb(), pl->pb() + pl->tot_p1, pl->galpha(), s),
             "final u reverse");
+    if (pl->fbwd) return backward_fused(pl, d_f, d_grad_f, d_grad_alpha, beta, s);
 
     for (int sg = pl->nseg - 1; sg >= 0; --sg) {
         const int n0 = sg * C, n1 = std::min(N, n0 + C), m = n1 - n0;

@@ -48,6 +48,8 @@ struct SubTile {
 
 constexpr int kStreamCols = 63;   // output columns per wave
 constexpr int kRowChoices = 4;    // rows per strip of the streaming kernels: 4, 8, 16 or 32
+constexpr int kRecWords = 53;     // words per thread in a step record of the fused kernel (fused_common.h)
+constexpr int kRecThreads = 1024; // threads of a fused workgroup
 inline int row_index(int R) { return R <= 4 ? 0 : R <= 8 ? 1 : R <= 16 ? 2 : 3; }
 constexpr int kFusedMax = 128;    // largest subdomain side handled by the fused kernel
 constexpr int kMaxFusedInner = 64;  // largest n_inner of the fused kernel
@@ -113,6 +115,7 @@ struct FusedArgs {
     const float *lam;            // lambda state of step n (lambda^n, p_s^(n-1), p_t^(n-1))
     float *lam_out;              // fused kernel: lambda state of step n + 1 (not aliasing lam)
     float sigma;
+    float *rec;                  // reverse mode: the step records of full tiles (fused_common.h), or null
     const float *f;
     float *out1, *out2;          // p~^(n+1)
     float tau, inv_tau;
@@ -175,6 +178,28 @@ bool persist_supported(int device);
 int persist_capacity(int device);  // workgroups of the persistent kernel resident at once
 hipError_t launch_persist_fista(const PersistArgs &a, int nsub, hipStream_t s);
 
+// Reverse mode of one outer step on full 128 x 128 subdomains (fused_bwd.hip),
+// from the step records of the fused kernel.
+struct FusedBwdArgs {
+    const ImgDev *imgs;
+    const SubTile *subs;
+    const float *rec;            // the forward's step records (all subdomains, all steps)
+    const float *x0_1, *x0_2;    // p~^n
+    const float *lam;            // lambda state holding lambda^(n+1)
+    const float *f;
+    float *pb1, *pb2;            // in: pbar^(n+1); out: xbar_0 + phatbar (0 on the image boundary)
+    float *hb1, *hb2;            // out: phatbar
+    float *gf;                   // fbar (accumulated)
+    double *galpha;              // per-subdomain partial sums of alphabar (accumulated)
+    float tau, inv_tau;
+    int n_inner;
+    float beta[kMaxFusedInner + 1];
+};
+bool fused_bwd_supported(int K);
+hipError_t launch_fused_bwd(const FusedBwdArgs &a, int nsub, hipStream_t s);
+
+// whether the fused kernel can record its steps for this inner count (full tiles only)
+bool fused_record_supported(int K);
 // subs[0, nfull) are 128 x 128 tiles (specialised kernel), subs[nfull, nsub) the others
 hipError_t launch_fused_fista(const FusedArgs &a, int nsub, int nfull, hipStream_t s, hipEvent_t e0 = nullptr,
                               hipEvent_t e1 = nullptr);
@@ -194,6 +219,8 @@ hipError_t launch_bwd_interface(const ImgDev *imgs, int nimg, int max_nlam, cons
                                 const float *hb2, float *pb1, float *pb2, float *lamb, float tau, float sigma,
                                 hipStream_t s);
 // dl/dalpha per image from the per-tile partial sums (fixed order)
+hipError_t launch_alpha_reduce2(const StreamTile *tiles, int ntiles, const double *galpha, const SubTile *subs,
+                                int nsub, const double *gsub, int nimg, float *out, hipStream_t s);
 hipError_t launch_alpha_reduce(const StreamTile *tiles, int ntiles, int nimg, const double *galpha, float *out,
                                hipStream_t s);
 

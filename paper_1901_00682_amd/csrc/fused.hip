@@ -32,7 +32,8 @@ using namespace fused;
 // kFull: every tile of the launch is 128 x 128 (the list holds the full
 // tiles first; the full launch takes that prefix, the other launch the rest).
 // KF > 0: full tiles with n_inner = KF (steps unrolled); KF = 0: any n_inner.
-template <bool kFull, int KF>
+// REC: also record every step for reverse mode (full tiles, KF > 0; a.rec).
+template <bool kFull, int KF, bool REC = false>
 __global__ __launch_bounds__(1024) void k_fused_fista(FusedArgs a, int first)
 {
     __shared__ FusedLds S;
@@ -256,7 +257,13 @@ __global__ __launch_bounds__(1024) void k_fused_fista(FusedArgs a, int first)
         fc.ak = c.ak;
         fc.kL = c.kL;
         if constexpr (KF > 0) {
-            rx_slot = full_steps_fixed<KF>(fc, S, A, B, a.beta);
+            if constexpr (REC) {
+                const long long rec_step = (long long)gridDim.x * kRecWords * kRecThreads;
+                float *rec = a.rec + (long long)t * kRecWords * kRecThreads + threadIdx.x;
+                rx_slot = full_steps_fixed<KF, true>(fc, S, A, B, a.beta, rec, rec_step);
+            } else {
+                rx_slot = full_steps_fixed<KF>(fc, S, A, B, a.beta);
+            }
             if constexpr (KF & 1) copy_slot(A, B);
         } else {
             rx_slot = run_steps<FullStep>(fc, S, A, B, K, a.beta);
@@ -299,17 +306,24 @@ namespace {
 
 using FusedKernel = void (*)(FusedArgs, int);
 
-// full-tile kernels with the inner step count unrolled, for the common counts
+// full-tile kernels with the inner step count unrolled, for the common counts;
+// the recording ones exist only there
 template <int... Ks>
 struct FullTable {
-    static FusedKernel get(int K)
+    static FusedKernel get(int K, bool rec)
     {
         FusedKernel k = nullptr;
-        ((K == Ks ? (k = k_fused_fista<true, Ks>, 0) : 0), ...);
-        return k ? k : k_fused_fista<true, 0>;
+        ((K == Ks ? (k = rec ? k_fused_fista<true, Ks, true> : k_fused_fista<true, Ks>, 0) : 0), ...);
+        return k ? k : rec ? nullptr : k_fused_fista<true, 0>;
     }
 };
 using Full = FullTable<1, 2, 3, 4, 5, 6, 7, 8, 10>;
+
+}  // namespace
+
+bool fused_record_supported(int K) { return Full::get(K, true) != nullptr; }
+
+namespace {
 
 }  // namespace
 
@@ -318,9 +332,10 @@ hipError_t launch_fused_fista(const FusedArgs &a, int nsub, int nfull, hipStream
     if (nsub <= 0) return hipSuccess;
     if (a.n_inner < 1 || a.n_inner > kMaxFusedInner || nfull < 0 || nfull > nsub) return hipErrorInvalidValue;
     const int npart = nsub - nfull;
+    if (a.rec && (npart > 0 || !Full::get(a.n_inner, true))) return hipErrorInvalidValue;
     // the timing events bracket both launches
     if (nfull > 0) {
-        const FusedKernel kf = Full::get(a.n_inner);
+        const FusedKernel kf = Full::get(a.n_inner, a.rec != nullptr);
         hipEvent_t stop = npart > 0 ? nullptr : e1;
         if (e0)
             hipExtLaunchKernelGGL(kf, dim3(nfull), dim3(1024), 0, s, e0, stop, 0, a, 0);

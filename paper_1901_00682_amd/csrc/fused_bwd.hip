@@ -1,0 +1,398 @@
+// Reverse mode of one outer step of Algorithm 1 (Lee & Park, arXiv 1901.00682,
+// Sec. 4) with FISTA local steps, on full 128 x 128 subdomains: one 1024-thread
+// workgroup per subdomain runs the n_inner reverse steps on chip.
+//
+// The forward step is x_k = P(z_k), z_k = a y_k + c' - kL div_s^*(div_s y_k)
+// (fista_ops.h).  Its reverse, from xbar_k:
+//   zbar = xbar_k * 1{-1 < z_k < 1}                 (mask recorded by the forward)
+//   ybar = a zbar - kL div_s^*(div_s zbar)            (the linear part is self-adjoint)
+//   xbar_{k-1} += (1 + beta_k) ybar,  xbar_{k-2} += -beta_k ybar   (steps k >= 3; else xbar_{k-1} += ybar)
+// c' = (phat / tau - (f_b - f_a)) / L sends zbar / (L tau) to phat and
+// -div_s zbar / L to f; summed over the steps these need only S = sum_k zbar_k,
+// kept per edge in LDS.  The alpha derivative of z_k,
+//   dA ((phat - y_k) / tau - (f_b - f_a)) - dB div_s^*(div_s y_k),
+// with dA = 8 / (alpha L)^2 and dB = -1 / (tau (alpha L)^2), is collected as
+//   -dB sum_k <div zbar_k, div y_k> - dA/tau sum_k <zbar_k, y_k>
+//   + dA/tau <phat, S> - dA <f, div S>
+// with y_k and div y_k from the forward's record.
+//
+// The layout on chip is the forward's: wave s holds rows 8 s .. 8 s + 7, lane
+// l columns 2 l and 2 l + 1, the two adjoint slots in VGPRs, the right
+// boundary column in LDS, one exchange row per strip for zbar and one for
+// div zbar; each step has two workgroup barriers.
+#include "fused_common.h"
+
+namespace dtv {
+
+using namespace fused;
+
+namespace {
+
+struct BwdLds {
+    float Sb[kFusedMax];             // S on the bottom boundary edges
+    float Sr[kFusedMax];             // S on the right boundary edges
+    float rx[2][kFusedMax];          // right boundary edges: the two adjoint slots
+    float zt[2][kWaves][kFusedMax];  // zbar on each strip's first-row top edges, by step parity
+    float dl[kWaves][kFusedMax];     // div zbar of each strip's last row
+    float dR[kFusedMax];             // div zbar of the last column, per row
+    double red[kWaves];              // per-wave partial sums of the alpha derivative
+    float S1[kFusedMax][kFusedMax];  // S on the edge above pixel (il, jl)
+    float S2[kFusedMax][kFusedMax];  // S on the edge left of pixel (il, jl)
+};
+
+struct BwdCtx {
+    int s, lane, ja, il0;
+    bool last;                 // strip 15: owns the tile's bottom boundary edges
+    bool top_var, left_var;    // the strip's first-row top edges / lane's column-0 left edge are variables
+    bool bot_var, right_var;   // the tile's bottom / right boundary edges are variables
+    float ak, kL;
+};
+
+__device__ __forceinline__ void ld2(const float *p, float &x, float &y)
+{
+    float2 v;
+    __builtin_memcpy(&v, p, 8);
+    x = v.x;
+    y = v.y;
+}
+
+__device__ __forceinline__ void st2(float *p, float x, float y)
+{
+    const float2 v = make_float2(x, y);
+    __builtin_memcpy(p, &v, 8);
+}
+
+__device__ __forceinline__ double wave_sum_d(double x)
+{
+    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+// word w of this thread in a step record: rec is the subdomain's record of
+// the step (uniform), tid the thread; the word base stays in scalar registers
+__device__ __forceinline__ float rw(const float *rec, int w, int tid) { return (rec + w * kRecThreads)[tid]; }
+
+// One reverse step.  On entry Z holds xbar_k (complete) and P xbar_{k-1}
+// (partial); on exit P holds xbar_{k-1} (complete) and Z xbar_{k-2} (partial).
+// sx: LDS slot of the right boundary column of Z.  rec: the subdomain's record
+// of the step.
+template <bool mom>
+__device__ __forceinline__ void bwd_step(const BwdCtx &c, BwdLds &L, Slot &Z, Slot &P, int sx, float beta,
+                                         const float *rec, double &acc_zy, double &acc_dd)
+{
+    float *RZ = L.rx[sx];
+    float *RP = L.rx[sx ^ 1];
+    const float ak = c.ak, kL = c.kL;
+    // per step, so that addresses are formed here and not hoisted out of the step sequence
+    const int tid = opaque(c.s * 64 + c.lane), oc = opaque(c.il0 * kFusedMax + c.ja);
+    const int row = c.il0 + c.lane;  // lanes 0..7: right boundary edge of this row
+    float *S1 = &L.S1[0][0] + oc, *S2 = &L.S2[0][0] + oc;
+    // (1) zbar on every owned edge, S += zbar, <zbar, y>
+    const unsigned m0 = __float_as_uint(rw(rec, 51, tid));
+    const unsigned m1 = __float_as_uint(rw(rec, 52, tid));
+    // the step's dot products are summed in FP32 over the thread's 35 edges / 16 pixels and
+    // then added to the FP64 accumulators
+    float zy = 0.0f;
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+        Z.e1a[r] = (m0 >> (4 * r + 0)) & 1u ? Z.e1a[r] : 0.0f;
+        Z.e1b[r] = (m0 >> (4 * r + 1)) & 1u ? Z.e1b[r] : 0.0f;
+        Z.e2a[r] = (m0 >> (4 * r + 2)) & 1u ? Z.e2a[r] : 0.0f;
+        Z.e2b[r] = (m0 >> (4 * r + 3)) & 1u ? Z.e2b[r] : 0.0f;
+        zy = fmaf(Z.e1a[r], rw(rec, 4 * r + 0, tid), zy);
+        zy = fmaf(Z.e1b[r], rw(rec, 4 * r + 1, tid), zy);
+        zy = fmaf(Z.e2a[r], rw(rec, 4 * r + 2, tid), zy);
+        zy = fmaf(Z.e2b[r], rw(rec, 4 * r + 3, tid), zy);
+        float s1a, s1b, s2a, s2b;
+        lds_ld2(S1 + r * kFusedMax, s1a, s1b);
+        lds_ld2(S2 + r * kFusedMax, s2a, s2b);
+        lds_st2(S1 + r * kFusedMax, s1a + Z.e1a[r], s1b + Z.e1b[r]);
+        lds_st2(S2 + r * kFusedMax, s2a + Z.e2a[r], s2b + Z.e2b[r]);
+        pin4(Z.e1a[r], Z.e1b[r], Z.e2a[r], zy);
+    }
+    // bottom boundary edges: strip 15 only
+    Z.ba = c.last && (m1 & 1u) ? Z.ba : 0.0f;
+    Z.bb = c.last && (m1 & 2u) ? Z.bb : 0.0f;
+    if (c.last) {
+        zy = fmaf(Z.ba, rw(rec, 32, tid), fmaf(Z.bb, rw(rec, 33, tid), zy));
+        float sa, sb;
+        lds_ld2(&L.Sb[c.ja], sa, sb);
+        lds_st2(&L.Sb[c.ja], sa + Z.ba, sb + Z.bb);
+    }
+    if (c.lane < kR) {
+        const float zr = (m1 & 4u) ? RZ[row] : 0.0f;
+        RZ[row] = zr;
+        zy = fmaf(zr, rw(rec, 34, tid), zy);
+        L.Sr[row] += zr;
+    }
+    acc_zy += (double)zy;
+    lds_st2(&L.zt[sx][c.s][c.ja], Z.e1a[0], Z.e1b[0]);
+    __syncthreads();
+
+    // (2) div zbar of the strip's last row, published for the strip below
+    const float *RZr = RZ + c.il0;
+    float za7, zb7;  // zbar on the edges below the last row
+    lds_ld2(&L.zt[sx][c.s < kWaves - 1 ? c.s + 1 : c.s][c.ja], za7, zb7);
+    za7 = c.last ? Z.ba : za7;
+    zb7 = c.last ? Z.bb : zb7;
+    float da7, db7;
+    full_row_div(Z, RZr, kR - 1, za7, zb7, da7, db7);
+    lds_st2(&L.dl[c.s][c.ja], da7, db7);
+    __syncthreads();
+
+    // (3) row sweep: div zbar, <div zbar, div y>, ybar and the adjoint updates
+    float dua = 0.0f, dub = 0.0f;  // div zbar of the row above (0 above the tile)
+    if (c.s > 0) lds_ld2(&L.dl[c.s - 1][c.ja], dua, dub);
+    float dd = 0.0f;
+    const float bk = 1.0f + beta;
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+        __builtin_amdgcn_sched_barrier(0);  // one row at a time: bounds the registers in flight
+        float da = da7, db = db7;
+        if (r < kR - 1) full_row_div(Z, RZr, r, Z.e1a[r + 1], Z.e1b[r + 1], da, db);
+        dd = fmaf(da, rw(rec, 35 + 2 * r, tid), fmaf(db, rw(rec, 36 + 2 * r, tid), dd));
+        const float dlb = from_left(db);  // div zbar of column a - 1 (0 left of the tile)
+        float y1a = fmaf(-kL, dua - da, ak * Z.e1a[r]);
+        float y1b = fmaf(-kL, dub - db, ak * Z.e1b[r]);
+        float y2a = fmaf(-kL, dlb - da, ak * Z.e2a[r]);
+        const float y2b = fmaf(-kL, da - db, ak * Z.e2b[r]);
+        if (r == 0 && !c.top_var) y1a = y1b = 0.0f;  // image boundary: not variables
+        if (!c.left_var) y2a = 0.0f;
+        if (mom) {
+            P.e1a[r] = fmaf(bk, y1a, P.e1a[r]);
+            P.e1b[r] = fmaf(bk, y1b, P.e1b[r]);
+            P.e2a[r] = fmaf(bk, y2a, P.e2a[r]);
+            P.e2b[r] = fmaf(bk, y2b, P.e2b[r]);
+            Z.e1a[r] = -beta * y1a;
+            Z.e1b[r] = -beta * y1b;
+            Z.e2a[r] = -beta * y2a;
+            Z.e2b[r] = -beta * y2b;
+        } else {
+            P.e1a[r] += y1a;
+            P.e1b[r] += y1b;
+            P.e2a[r] += y2a;
+            P.e2b[r] += y2b;
+            Z.e1a[r] = Z.e1b[r] = Z.e2a[r] = Z.e2b[r] = 0.0f;
+        }
+        if (r == kR - 1) {  // bottom boundary edges (strip 15)
+            const bool v = c.last && c.bot_var;
+            const float yba = v ? fmaf(-kL, da, ak * Z.ba) : 0.0f;
+            const float ybb = v ? fmaf(-kL, db, ak * Z.bb) : 0.0f;
+            if (mom) {
+                P.ba = fmaf(bk, yba, P.ba);
+                P.bb = fmaf(bk, ybb, P.bb);
+                Z.ba = -beta * yba;
+                Z.bb = -beta * ybb;
+            } else {
+                P.ba += yba;
+                P.bb += ybb;
+                Z.ba = Z.bb = 0.0f;
+            }
+        }
+        if (c.lane == 63) L.dR[c.il0 + r] = db;  // div zbar of the last column
+        pin4(P.e1a[r], P.e1b[r], P.e2a[r], P.e2b[r]);
+        pin4(Z.e1a[r], Z.e1b[r], Z.e2a[r], dd);
+        dua = da;
+        dub = db;
+    }
+    acc_dd += (double)dd;
+    if (c.lane < kR) {  // right boundary edges
+        const float yr = c.right_var ? fmaf(-kL, L.dR[row], ak * RZ[row]) : 0.0f;
+        if (mom) {
+            RP[row] = fmaf(bk, yr, RP[row]);
+            RZ[row] = -beta * yr;
+        } else {
+            RP[row] += yr;
+            RZ[row] = 0.0f;
+        }
+    }
+}
+
+// reverse steps k = K .. 1 (the slots swap roles every step)
+template <int K, int k = K>
+__device__ __forceinline__ void bwd_steps(const BwdCtx &c, BwdLds &L, Slot &Z, Slot &P, const float *beta,
+                                          const float *rec, long long rec_step, double &acc_zy, double &acc_dd)
+{
+    if constexpr (k >= 1) {
+        bwd_step<(k >= 3)>(c, L, Z, P, (K - k) & 1, k >= 3 ? beta[k] : 0.0f, rec + (k - 1) * rec_step, acc_zy,
+                           acc_dd);
+        bwd_steps<K, k - 1>(c, L, P, Z, beta, rec, rec_step, acc_zy, acc_dd);
+    }
+}
+
+}  // namespace
+
+template <int KF>
+__global__ __launch_bounds__(1024) void k_fused_bwd(FusedBwdArgs a)
+{
+    __shared__ BwdLds L;
+    const int t = xcd_remap(blockIdx.x, gridDim.x);
+    const SubTile tl = a.subs[t];
+    const ImgDev im = a.imgs[tl.img];
+    BwdCtx c;
+    c.s = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    c.lane = threadIdx.x & 63;
+    c.ja = 2 * c.lane;
+    c.il0 = kR * c.s;
+    c.last = c.s == kWaves - 1;
+    const int H = im.H, W = im.W, s = c.s, lane = c.lane, ja = c.ja, il0 = c.il0;
+    const bool top_bnd = tl.ra == 0, bot_bnd = tl.ra + kFusedMax == H;
+    const bool left_bnd = tl.ca == 0, right_bnd = tl.ca + kFusedMax == W;
+    c.top_var = !(top_bnd && s == 0);
+    c.left_var = !(left_bnd && lane == 0);
+    c.bot_var = !bot_bnd;
+    c.right_var = !right_bnd;
+    c.ak = im.a_keep;
+    c.kL = im.kL;
+    const long long P1 = im.pitch1, P2 = im.pitch2;
+    const long long row1 = (long long)tl.ra + tl.r;
+    const long long col2 = (long long)tl.ca + tl.c;
+    float *pb1 = a.pb1 + im.p1 + row1 * P1 + tl.ca, *pb2 = a.pb2 + im.p2 + (long long)tl.ra * P2 + col2;
+    float *hb1 = a.hb1 + im.p1 + row1 * P1 + tl.ca, *hb2 = a.hb2 + im.p2 + (long long)tl.ra * P2 + col2;
+    const float *x1 = a.x0_1 + im.p1 + row1 * P1 + tl.ca, *x2 = a.x0_2 + im.p2 + (long long)tl.ra * P2 + col2;
+    const float *f_tile = a.f + im.px + (long long)tl.ra * W + tl.ca;
+    float *gf_tile = a.gf + im.px + (long long)tl.ra * W + tl.ca;
+    const float tau = a.tau, itau = a.inv_tau, invL = im.invL, hL = invL * itau;
+
+    // ---- xbar_K = pbar^(n+1) into slot A (right column in LDS), S = 0, slot B = 0
+    Slot A, B;
+    A.ba = A.bb = 0.0f;
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+        const int il = il0 + r;
+        ld2(pb1 + (long long)il * P1 + ja, A.e1a[r], A.e1b[r]);
+        ld2(pb2 + (long long)il * P2 + ja, A.e2a[r], A.e2b[r]);
+        lds_st2(&L.S1[il][ja], 0.0f, 0.0f);
+        lds_st2(&L.S2[il][ja], 0.0f, 0.0f);
+        B.e1a[r] = B.e1b[r] = B.e2a[r] = B.e2b[r] = 0.0f;
+    }
+    B.ba = B.bb = 0.0f;
+    if (c.last) ld2(pb1 + (long long)kFusedMax * P1 + ja, A.ba, A.bb);
+    if (s == 0) lds_st2(&L.Sb[ja], 0.0f, 0.0f);
+    if (lane < kR) {
+        L.rx[0][il0 + lane] = pb2[(long long)(il0 + lane) * P2 + kFusedMax];
+        L.rx[1][il0 + lane] = 0.0f;
+        L.Sr[il0 + lane] = 0.0f;
+    }
+    __syncthreads();
+
+    // ---- the K reverse steps; xbar_0 ends in A (right column in rx[K & 1])
+    double acc_zy = 0.0, acc_dd = 0.0;
+    const long long rec_step = (long long)gridDim.x * kRecWords * kRecThreads;
+    const float *rec = a.rec + (long long)t * kRecWords * kRecThreads;  // uniform: this subdomain's record
+    bwd_steps<KF>(c, L, A, B, a.beta, rec, rec_step, acc_zy, acc_dd);
+    if constexpr (KF & 1) copy_slot(A, B);
+    const int rxs = KF & 1;
+    __syncthreads();
+
+    // ---- outputs: pbar^n = xbar_0 + phatbar, phatbar = S / (L tau) (0 on the image boundary),
+    // fbar += -div S / L, and the alpha derivative
+    const double dA = im.dA, dB = im.dB;
+    double acc = -dB * acc_dd - dA * (double)itau * acc_zy;
+    const float *lam = a.lam + im.lam;
+    double sp = 0.0, fs = 0.0;  // <phat, S>, <f, div S>
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+        const int il = il0 + r;
+        const long long gi = tl.ra + il;
+        float s1a, s1b, s2a, s2b;
+        lds_ld2(&L.S1[il][ja], s1a, s1b);
+        lds_ld2(&L.S2[il][ja], s2a, s2b);
+        // anchors phat of the owned edges (t copies +tau lambda)
+        float x1a, x1b, x2a, x2b;
+        ld2(x1 + (long long)il * P1 + ja, x1a, x1b);
+        ld2(x2 + (long long)il * P2 + ja, x2a, x2b);
+        if (il == 0 && tl.r > 0) {
+            const float *lr = lam + (long long)(tl.r - 1) * W + tl.ca;
+            x1a = fmaf(tau, lr[ja], x1a);
+            x1b = fmaf(tau, lr[ja + 1], x1b);
+        }
+        if (ja == 0 && tl.c > 0) x2a = fmaf(tau, lam[im.nlh + (long long)(tl.c - 1) * H + gi], x2a);
+        sp += (double)x1a * s1a + (double)x1b * s1b + (double)x2a * s2a + (double)x2b * s2b;
+        // the row's edges
+        const bool tv = !(il == 0 && top_bnd);
+        const float h1a = tv ? hL * s1a : 0.0f, h1b = tv ? hL * s1b : 0.0f;
+        const float h2a = c.left_var ? hL * s2a : 0.0f, h2b = hL * s2b;
+        st2(hb1 + (long long)il * P1 + ja, h1a, h1b);
+        st2(hb2 + (long long)il * P2 + ja, h2a, h2b);
+        st2(pb1 + (long long)il * P1 + ja, tv ? A.e1a[r] + h1a : 0.0f, tv ? A.e1b[r] + h1b : 0.0f);
+        st2(pb2 + (long long)il * P2 + ja, c.left_var ? A.e2a[r] + h2a : 0.0f, A.e2b[r] + h2b);
+        // div S of the row's pixels (bottom edge: next row, or the bottom boundary row)
+        float sba, sbb;
+        if (il < kFusedMax - 1) lds_ld2(&L.S1[il + 1][ja], sba, sbb);
+        else lds_ld2(&L.Sb[ja], sba, sbb);
+        const float sra = s2b;
+        const float srb = ja + 2 < kFusedMax ? L.S2[il][ja + 2] : L.Sr[il];
+        const float dsa = div4(s1a, sba, s2a, sra), dsb = div4(s1b, sbb, s2b, srb);
+        float fa, fb, ga, gb;
+        ld2(f_tile + (long long)il * W + ja, fa, fb);
+        ld2(gf_tile + (long long)il * W + ja, ga, gb);
+        st2(gf_tile + (long long)il * W + ja, fmaf(-invL, dsa, ga), fmaf(-invL, dsb, gb));
+        fs += (double)fa * dsa + (double)fb * dsb;
+    }
+    if (c.last) {  // bottom boundary edges: s copies -tau lambda
+        float sa, sb;
+        lds_ld2(&L.Sb[ja], sa, sb);
+        float xa, xb;
+        ld2(x1 + (long long)kFusedMax * P1 + ja, xa, xb);
+        if (!bot_bnd) {
+            const float *lb = lam + (long long)tl.r * W + tl.ca;
+            xa = fmaf(-tau, lb[ja], xa);
+            xb = fmaf(-tau, lb[ja + 1], xb);
+        }
+        sp += (double)xa * sa + (double)xb * sb;
+        const float ha = bot_bnd ? 0.0f : hL * sa, hbv = bot_bnd ? 0.0f : hL * sb;
+        st2(hb1 + (long long)kFusedMax * P1 + ja, ha, hbv);
+        st2(pb1 + (long long)kFusedMax * P1 + ja, bot_bnd ? 0.0f : A.ba + ha, bot_bnd ? 0.0f : A.bb + hbv);
+    }
+    if (lane < kR) {  // right boundary edges: s copies -tau lambda
+        const int il = il0 + lane;
+        const float sr = L.Sr[il];
+        float xr = x2[(long long)il * P2 + kFusedMax];
+        if (!right_bnd) xr = fmaf(-tau, lam[im.nlh + (long long)tl.c * H + tl.ra + il], xr);
+        sp += (double)xr * sr;
+        const float hr = right_bnd ? 0.0f : hL * sr;
+        hb2[(long long)il * P2 + kFusedMax] = hr;
+        pb2[(long long)il * P2 + kFusedMax] = right_bnd ? 0.0f : L.rx[rxs][il] + hr;
+    }
+    acc += dA * (double)itau * sp - dA * fs;
+    // fixed-order reduction over the workgroup
+    acc = wave_sum_d(acc);
+    if (lane == 0) L.red[s] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tot = 0.0;
+        for (int w = 0; w < kWaves; ++w) tot += L.red[w];
+        a.galpha[t] += tot;
+    }
+}
+
+namespace {
+
+using BwdKernel = void (*)(FusedBwdArgs);
+
+template <int... Ks>
+struct BwdTable {
+    static BwdKernel get(int K)
+    {
+        BwdKernel k = nullptr;
+        ((K == Ks ? (k = k_fused_bwd<Ks>, 0) : 0), ...);
+        return k;
+    }
+};
+using Bwd = BwdTable<1, 2, 3, 4, 5, 6, 7, 8, 10>;
+
+}  // namespace
+
+bool fused_bwd_supported(int K) { return Bwd::get(K) != nullptr; }
+
+hipError_t launch_fused_bwd(const FusedBwdArgs &a, int nsub, hipStream_t s)
+{
+    if (nsub <= 0) return hipSuccess;
+    const BwdKernel k = Bwd::get(a.n_inner);
+    if (!k) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k, dim3(nsub), dim3(1024), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace dtv

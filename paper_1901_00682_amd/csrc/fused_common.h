@@ -241,8 +241,28 @@ __device__ __forceinline__ void full_row_div(const Slot &Y, const float *RYr, in
 }
 
 // fused_step on a full tile; same arithmetic per edge, hence the same result
-template <bool mom>
-__device__ __forceinline__ void full_step(const FullCtx &c, FusedLds &S, const Slot &X, Slot &Y, int sx, float beta)
+// Record of one step on a full tile (reverse mode), one word per thread of the
+// workgroup for each of kRecWords words (word w of thread t at
+// rec[w * kRecThreads + t], dtvdd_internal.h):
+//   0..31  y on the thread's edges, 4 r + (0 e1a, 1 e1b, 2 e2a, 3 e2b)
+//   32, 33 y on the bottom boundary edges (strip 15), 34 y on the right boundary
+//          edge of row 8 s + lane (lanes 0..7)
+//   35..50 d = div_s y of the thread's pixels, 35 + 2 r + (0 column a, 1 column b)
+//   51     projection mask of the 32 edges (bit 4 r + q set when -1 < z < 1 on
+//          an edge that is a variable), 52 the same for the bottom edges (bits 0,
+//          1) and the right boundary edge (bit 2)
+
+// projected step value and, when recording, the mask bit of its derivative
+template <bool REC>
+__device__ __forceinline__ float proj(float z, float lo, float hi, unsigned &m, int bit)
+{
+    if constexpr (REC) m |= (z > lo && z < hi) ? (1u << bit) : 0u;
+    return __builtin_amdgcn_fmed3f(z, lo, hi);
+}
+
+template <bool mom, bool REC = false>
+__device__ __forceinline__ void full_step(const FullCtx &c, FusedLds &S, const Slot &X, Slot &Y, int sx, float beta,
+                                          float *rec = nullptr)
 {
     // The phases are written without branches wherever a select does the job:
     // a branch splits the step into blocks and the compiler then sinks the row
@@ -263,6 +283,18 @@ __device__ __forceinline__ void full_step(const FullCtx &c, FusedLds &S, const S
     }
     Y.ba = mom ? fista_y(X.ba, Y.ba, beta) : X.ba;  // meaningful in strip 15 only
     Y.bb = mom ? fista_y(X.bb, Y.bb, beta) : X.bb;
+    if constexpr (REC) {
+#pragma unroll
+        for (int r = 0; r < kR; ++r) {
+            rec[(4 * r + 0) * kRecThreads] = Y.e1a[r];
+            rec[(4 * r + 1) * kRecThreads] = Y.e1b[r];
+            rec[(4 * r + 2) * kRecThreads] = Y.e2a[r];
+            rec[(4 * r + 3) * kRecThreads] = Y.e2b[r];
+        }
+        rec[32 * kRecThreads] = Y.ba;
+        rec[33 * kRecThreads] = Y.bb;
+        if (c.lane < kR) rec[34 * kRecThreads] = RY[olr];
+    }
     float *yt = &S.yt[sx][0][0] + oy;  // this strip's row of the exchange buffer (strip 0's is unused)
     lds_st2(yt, Y.e1a[0], Y.e1b[0]);
     __syncthreads();
@@ -285,37 +317,46 @@ __device__ __forceinline__ void full_step(const FullCtx &c, FusedLds &S, const S
     dua = c.s > 0 ? dua : 0.0f;
     dub = c.s > 0 ? dub : 0.0f;
     const float *c1 = &S.c1[0][0] + oc, *c2 = &S.c2[0][0] + oc;
+    unsigned m0 = 0, m1 = 0;  // projection masks (recording)
 #pragma unroll
     for (int r = 0; r < kR; ++r) {
         __builtin_amdgcn_sched_barrier(0);  // one row at a time: bounds the registers in flight
         float da = da7, db = db7;
         if (r < kR - 1) full_row_div(Y, RYr, r, Y.e1a[r + 1], Y.e1b[r + 1], da, db);
+        if constexpr (REC) {
+            rec[(35 + 2 * r) * kRecThreads] = da;
+            rec[(36 + 2 * r) * kRecThreads] = db;
+        }
         const float dlb = from_left(db);
         float c1a, c1b, c2a, c2b;
         lds_ld2(c1 + r * kFusedMax, c1a, c1b);
         lds_ld2(c2 + r * kFusedMax, c2a, c2b);
-        if (r == 0) {  // the top edges of the tile collapse to 0 on the image boundary
-            Y.e1a[r] = __builtin_amdgcn_fmed3f(fista_z(Y.e1a[r], dua, da, c1a, ak, kL), c.lo1, c.hi1);
-            Y.e1b[r] = __builtin_amdgcn_fmed3f(fista_z(Y.e1b[r], dub, db, c1b, ak, kL), c.lo1, c.hi1);
-        } else {
-            Y.e1a[r] = fista_edge(Y.e1a[r], dua, da, c1a, ak, kL);
-            Y.e1b[r] = fista_edge(Y.e1b[r], dub, db, c1b, ak, kL);
-        }
-        Y.e2a[r] = __builtin_amdgcn_fmed3f(fista_z(Y.e2a[r], dlb, da, c2a, ak, kL), c.lo2a, c.hi2a);
-        Y.e2b[r] = fista_edge(Y.e2b[r], da, db, c2b, ak, kL);
+        // the top edges of the tile collapse to 0 on the image boundary (bounds lo1, hi1 on row 0)
+        const float lo1 = r == 0 ? c.lo1 : -1.0f, hi1 = r == 0 ? c.hi1 : 1.0f;
+        Y.e1a[r] = proj<REC>(fista_z(Y.e1a[r], dua, da, c1a, ak, kL), lo1, hi1, m0, 4 * r + 0);
+        Y.e1b[r] = proj<REC>(fista_z(Y.e1b[r], dub, db, c1b, ak, kL), lo1, hi1, m0, 4 * r + 1);
+        Y.e2a[r] = proj<REC>(fista_z(Y.e2a[r], dlb, da, c2a, ak, kL), c.lo2a, c.hi2a, m0, 4 * r + 2);
+        Y.e2b[r] = proj<REC>(fista_z(Y.e2b[r], da, db, c2b, ak, kL), -1.0f, 1.0f, m0, 4 * r + 3);
         if (r == kR - 1) {  // bottom boundary edges of the tile (strip 15, unless on the image boundary)
             float cba, cbb;
             lds_ld2(S.cb + (oy - c.s * kFusedMax), cba, cbb);
             // only strip 15 uses them; they collapse to 0 on the image boundary
-            Y.ba = __builtin_amdgcn_fmed3f(fista_z(Y.ba, da, 0.0f, cba, ak, kL), c.lob, c.hib);
-            Y.bb = __builtin_amdgcn_fmed3f(fista_z(Y.bb, db, 0.0f, cbb, ak, kL), c.lob, c.hib);
+            Y.ba = proj<REC>(fista_z(Y.ba, da, 0.0f, cba, ak, kL), c.lob, c.hib, m1, 0);
+            Y.bb = proj<REC>(fista_z(Y.bb, db, 0.0f, cbb, ak, kL), c.lob, c.hib, m1, 1);
         }
         if (c.lane == 63) S.dR[orow + r] = db;  // the last column's d, for the right boundary edges
         pin4(Y.e1a[r], Y.e1b[r], Y.e2a[r], Y.e2b[r]);
         dua = da;
         dub = db;
     }
-    if (!c.right_bnd && c.lane < kR) RY[olr] = fista_edge(RY[olr], S.dR[olr], 0.0f, S.cr[olr], ak, kL);
+    if (!c.right_bnd && c.lane < kR) {
+        const float z = fista_z(RY[olr], S.dR[olr], 0.0f, S.cr[olr], ak, kL);
+        RY[olr] = proj<REC>(z, -1.0f, 1.0f, m1, 2);
+    }
+    if constexpr (REC) {
+        rec[51 * kRecThreads] = __uint_as_float(m0);
+        rec[52 * kRecThreads] = __uint_as_float(m1);
+    }
 }
 
 struct GenericStep {
@@ -366,12 +407,14 @@ __device__ __forceinline__ int run_steps(const C &c, FusedLds &S, Slot &A, Slot 
 // costs register copies, and spills where the caller keeps more state live).
 // x_K ends in A when K is even and in B when K is odd; returns the LDS slot of
 // the right boundary column holding it (K & 1).
-template <int K, int k = 1>
-__device__ __forceinline__ int full_steps_fixed(const FullCtx &c, FusedLds &S, Slot &X, Slot &Y, const float *beta)
+template <int K, bool REC = false, int k = 1>
+__device__ __forceinline__ int full_steps_fixed(const FullCtx &c, FusedLds &S, Slot &X, Slot &Y, const float *beta,
+                                                float *rec = nullptr, long long rec_step = 0)
 {
     if constexpr (k <= K) {
-        full_step<(k >= 3)>(c, S, X, Y, (k - 1) & 1, k >= 3 ? beta[k] : 0.0f);
-        return full_steps_fixed<K, k + 1>(c, S, Y, X, beta);
+        full_step<(k >= 3), REC>(c, S, X, Y, (k - 1) & 1, k >= 3 ? beta[k] : 0.0f,
+                                 REC ? rec + (k - 1) * rec_step : nullptr);
+        return full_steps_fixed<K, REC, k + 1>(c, S, Y, X, beta, rec, rec_step);
     } else {
         return K & 1;
     }

@@ -334,4 +334,25 @@ hipError_t launch_alpha_reduce(const StreamTile *tiles, int ntiles, int nimg, co
     return hipGetLastError();
 }
 
+// the same with the per-subdomain partial sums of the fused reverse steps added
+__global__ void k_alpha_reduce2(const StreamTile *tiles, int ntiles, const double *galpha, const SubTile *subs,
+                                int nsub, const double *gsub, float *out)
+{
+    const int img = blockIdx.x;
+    if (threadIdx.x != 0) return;
+    double acc = 0.0;
+    for (int t = 0; t < ntiles; ++t)
+        if (tiles[t].img == img) acc += galpha[t];
+    for (int t = 0; t < nsub; ++t)
+        if (subs[t].img == img) acc += gsub[t];
+    out[img] = (float)acc;
+}
+
+hipError_t launch_alpha_reduce2(const StreamTile *tiles, int ntiles, const double *galpha, const SubTile *subs,
+                                int nsub, const double *gsub, int nimg, float *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_alpha_reduce2, dim3(nimg), dim3(64), 0, s, tiles, ntiles, galpha, subs, nsub, gsub, out);
+    return hipGetLastError();
+}
+
 }  // namespace dtv

@@ -1,0 +1,75 @@
+"""Reverse mode with the fused kernels (every subdomain 128 x 128: a recording
+forward launch and an on-chip reverse launch per outer step) against the FP64
+oracle's reverse pass; independence of the checkpoint spacing and of batching."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1901_00682_amd import synth
+from tests.helpers import rel_l2
+from tests.test_gpu_backward import gpu_grad
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _problem(H, W, seed):
+    rng = np.random.default_rng(seed)
+    g = synth.shapes(H, W, rng)
+    f = (g + synth.gaussian((H, W), 0.1, rng)).astype(np.float32)
+    return f, rng.standard_normal((H, W))
+
+
+@pytest.mark.parametrize("H,W,alpha,n_outer,K,C", [
+    (256, 256, 8.0, 6, 5, 4),
+    (384, 256, 5.0, 5, 4, 2),
+    (256, 384, 12.0, 4, 3, 10),
+    (128, 256, 8.0, 3, 1, 1),
+    (256, 256, 6.0, 3, 10, 2),
+])
+def test_fused_backward_matches_oracle(H, W, alpha, n_outer, K, C):
+    rc, cc = np.arange(0, H + 1, 128), np.arange(0, W + 1, 128)
+    _say(f"[fused backward] {H}x{W} {n_outer}x{K} ckpt {C}")
+    f, ubar = _problem(H, W, H + 3 * W + K)
+    gf, ga, plan, _ = gpu_grad([f], [alpha], rc, cc, [ubar], n_outer, K, C)
+    o = oracle.Oracle(oracle.Problem(f.astype(np.float64), alpha, rc, cc, n_inner=K))
+    fbar, abar = o.backward(n_outer, ubar.astype(np.float32).astype(np.float64))
+    e_f = rel_l2(gf[0], fbar)
+    e_a = abs(ga[0] - abar) / abs(abar)
+    _say(f"  dl/df rel L2 {e_f:.2e}   dl/dalpha rel {e_a:.2e}")
+    assert e_f <= 1e-4
+    assert e_a <= 1e-4
+
+
+def test_fused_backward_independent_of_checkpoint_spacing():
+    H, W = 256, 384
+    rc, cc = np.arange(0, H + 1, 128), np.arange(0, W + 1, 128)
+    f, ubar = _problem(H, W, 21)
+    res = [gpu_grad([f], [8.0], rc, cc, [ubar], 7, 5, C) for C in (1, 3, 7, 20)]
+    for r in res[1:]:
+        assert np.array_equal(r[0], res[0][0]) and np.array_equal(r[1], res[0][1])
+
+
+def test_fused_backward_batched_equals_single():
+    H, W = 256, 256
+    rc, cc = np.arange(0, H + 1, 128), np.arange(0, W + 1, 128)
+    probs = [_problem(H, W, 30 + b) for b in range(3)]
+    alphas = [4.0, 8.0, 12.0]
+    gfb, gab, _, _ = gpu_grad([p[0] for p in probs], alphas, rc, cc, [p[1] for p in probs], 5, 5, 2)
+    for b in range(3):
+        gf1, ga1, _, _ = gpu_grad([probs[b][0]], [alphas[b]], rc, cc, [probs[b][1]], 5, 5, 2)
+        assert np.array_equal(gfb[b], gf1[0])
+        assert np.array_equal(gab[b], ga1[0])
