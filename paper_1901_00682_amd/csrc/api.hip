@@ -155,7 +155,7 @@ struct dtv_dd_plan {
     float *pb() const { return (float *)(ws + off_pb); }
     float *lb() const { return (float *)(ws + off_lb); }
     double *galpha() const { return (double *)(ws + off_galpha); }
-    float *frec() const { return (float *)(ws + off_frec); }       // step records of the fused forward
+    float4 *frec() const { return (float4 *)(ws + off_frec); }     // step records of the fused forward
     double *gsub() const { return (double *)(ws + off_gsub); }     // per-subdomain alpha partial sums
     double *dout() const { return (double *)(ws + off_dout); }
     unsigned long long *xch() const { return (unsigned long long *)(ws + off_xch); }
@@ -390,7 +390,7 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
         pl->fbwd = pl->fused_ok && pl->n_full == (int)nsub && fused_record_supported(p.n_inner) &&
                    fused_bwd_supported(p.n_inner);
         if (pl->fbwd) {
-            pl->off_frec = take(sizeof(float) * (size_t)p.n_inner * nsub * kRecWords * kRecThreads);
+            pl->off_frec = take(sizeof(float4) * (size_t)p.n_inner * nsub * kRecGroups * kRecThreads);
             pl->off_gsub = take(sizeof(double) * nsub);
         } else {
             pl->off_xrec = take(sizeof(float) * E * (size_t)p.n_inner);
@@ -1039,7 +1039,7 @@ static int backward_fused(dtv_dd_plan *pl, const float *d_f, float *d_grad_f, fl
     ba.n_inner = K;
     for (int k = 1; k <= K; ++k) ba.beta[k] = beta[k];
     // one outer step of the fused forward from a state (p~, lambda state) to p~ out, lambda state out
-    auto forward = [&](const float *st, float *p_out, float *lam_out, float *rec) -> int {
+    auto forward = [&](const float *st, float *p_out, float *lam_out, float4 *rec) -> int {
         fa.base1 = st;
         fa.base2 = st + pl->tot_p1;
         fa.lam = st + E;

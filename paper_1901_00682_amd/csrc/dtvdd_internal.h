@@ -48,7 +48,7 @@ struct SubTile {
 
 constexpr int kStreamCols = 63;   // output columns per wave
 constexpr int kRowChoices = 4;    // rows per strip of the streaming kernels: 4, 8, 16 or 32
-constexpr int kRecWords = 53;     // words per thread in a step record of the fused kernel (fused_common.h)
+constexpr int kRecGroups = 10;    // float4 groups per thread in a step record of the fused kernel (fused_common.h)
 constexpr int kRecThreads = 1024; // threads of a fused workgroup
 inline int row_index(int R) { return R <= 4 ? 0 : R <= 8 ? 1 : R <= 16 ? 2 : 3; }
 constexpr int kFusedMax = 128;    // largest subdomain side handled by the fused kernel
@@ -115,7 +115,7 @@ struct FusedArgs {
     const float *lam;            // lambda state of step n (lambda^n, p_s^(n-1), p_t^(n-1))
     float *lam_out;              // fused kernel: lambda state of step n + 1 (not aliasing lam)
     float sigma;
-    float *rec;                  // reverse mode: the step records of full tiles (fused_common.h), or null
+    float4 *rec;                 // reverse mode: the step records of full tiles (fused_common.h), or null
     const float *f;
     float *out1, *out2;          // p~^(n+1)
     float tau, inv_tau;
@@ -183,7 +183,7 @@ hipError_t launch_persist_fista(const PersistArgs &a, int nsub, hipStream_t s);
 struct FusedBwdArgs {
     const ImgDev *imgs;
     const SubTile *subs;
-    const float *rec;            // the forward's step records (all subdomains, all steps)
+    const float4 *rec;           // the forward's step records (all subdomains, all steps)
     const float *x0_1, *x0_2;    // p~^n
     const float *lam;            // lambda state holding lambda^(n+1)
     const float *f;

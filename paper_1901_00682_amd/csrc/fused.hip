@@ -256,10 +256,12 @@ __global__ __launch_bounds__(1024) void k_fused_fista(FusedArgs a, int first)
         fc.hib = c.bot_bnd ? 0.0f : 1.0f;
         fc.ak = c.ak;
         fc.kL = c.kL;
+        fc.qa = (float)(-im.dA * (double)a.inv_tau);
+        fc.qb = (float)(-im.dB);
         if constexpr (KF > 0) {
             if constexpr (REC) {
-                const long long rec_step = (long long)gridDim.x * kRecWords * kRecThreads;
-                float *rec = a.rec + (long long)t * kRecWords * kRecThreads + threadIdx.x;
+                const long long rec_step = (long long)gridDim.x * kRecGroups * kRecThreads;
+                float4 *rec = a.rec + (long long)t * kRecGroups * kRecThreads + threadIdx.x;
                 rx_slot = full_steps_fixed<KF, true>(fc, S, A, B, a.beta, rec, rec_step);
             } else {
                 rx_slot = full_steps_fixed<KF>(fc, S, A, B, a.beta);

@@ -12,9 +12,8 @@
 // kept per edge in LDS.  The alpha derivative of z_k,
 //   dA ((phat - y_k) / tau - (f_b - f_a)) - dB div_s^*(div_s y_k),
 // with dA = 8 / (alpha L)^2 and dB = -1 / (tau (alpha L)^2), is collected as
-//   -dB sum_k <div zbar_k, div y_k> - dA/tau sum_k <zbar_k, y_k>
-//   + dA/tau <phat, S> - dA <f, div S>
-// with y_k and div y_k from the forward's record.
+//   sum_k <zbar_k, q_k> + dA/tau <phat, S> - dA <f, div S>,
+// q_k = -dA/tau y_k - dB div_s^*(div_s y_k) per edge from the forward's record.
 //
 // The layout on chip is the forward's: wave s holds rows 8 s .. 8 s + 7, lane
 // l columns 2 l and 2 l + 1, the two adjoint slots in VGPRs, the right
@@ -68,9 +67,9 @@ __device__ __forceinline__ double wave_sum_d(double x)
     return x;
 }
 
-// word w of this thread in a step record: rec is the subdomain's record of
-// the step (uniform), tid the thread; the word base stays in scalar registers
-__device__ __forceinline__ float rw(const float *rec, int w, int tid) { return (rec + w * kRecThreads)[tid]; }
+// group g of this thread in a step record: rec is the subdomain's record of
+// the step (uniform), tid the thread; the group base stays in scalar registers
+__device__ __forceinline__ float4 rg(const float4 *rec, int g, int tid) { return (rec + g * kRecThreads)[tid]; }
 
 // One reverse step.  On entry Z holds xbar_k (complete) and P xbar_{k-1}
 // (partial); on exit P holds xbar_{k-1} (complete) and Z xbar_{k-2} (partial).
@@ -78,7 +77,7 @@ __device__ __forceinline__ float rw(const float *rec, int w, int tid) { return (
 // of the step.
 template <bool mom>
 __device__ __forceinline__ void bwd_step(const BwdCtx &c, BwdLds &L, Slot &Z, Slot &P, int sx, float beta,
-                                         const float *rec, double &acc_zy, double &acc_dd)
+                                         const float4 *rec, double &acc_q)
 {
     float *RZ = L.rx[sx];
     float *RP = L.rx[sx ^ 1];
@@ -87,11 +86,15 @@ __device__ __forceinline__ void bwd_step(const BwdCtx &c, BwdLds &L, Slot &Z, Sl
     const int tid = opaque(c.s * 64 + c.lane), oc = opaque(c.il0 * kFusedMax + c.ja);
     const int row = c.il0 + c.lane;  // lanes 0..7: right boundary edge of this row
     float *S1 = &L.S1[0][0] + oc, *S2 = &L.S2[0][0] + oc;
-    // (1) zbar on every owned edge, S += zbar, <zbar, y>
-    const unsigned m0 = __float_as_uint(rw(rec, 51, tid));
-    const unsigned m1 = __float_as_uint(rw(rec, 52, tid));
-    // the step's dot products are summed in FP32 over the thread's 35 edges / 16 pixels and
-    // then added to the FP64 accumulators
+    // (1) zbar on every owned edge, S += zbar, <zbar, q>.  The step's record is
+    // loaded first (ten 16-byte loads in flight together) and consumed after.
+    float4 q[kRecGroups];
+#pragma unroll
+    for (int g = 0; g < kRecGroups; ++g) q[g] = rg(rec, g, tid);
+    const unsigned m0 = __float_as_uint(q[8].w);
+    const unsigned m1 = __float_as_uint(q[9].x);
+    // the step's dot product is summed in FP32 over the thread's 35 edges and then
+    // added to the FP64 accumulator
     float zy = 0.0f;
 #pragma unroll
     for (int r = 0; r < kR; ++r) {
@@ -99,10 +102,10 @@ __device__ __forceinline__ void bwd_step(const BwdCtx &c, BwdLds &L, Slot &Z, Sl
         Z.e1b[r] = (m0 >> (4 * r + 1)) & 1u ? Z.e1b[r] : 0.0f;
         Z.e2a[r] = (m0 >> (4 * r + 2)) & 1u ? Z.e2a[r] : 0.0f;
         Z.e2b[r] = (m0 >> (4 * r + 3)) & 1u ? Z.e2b[r] : 0.0f;
-        zy = fmaf(Z.e1a[r], rw(rec, 4 * r + 0, tid), zy);
-        zy = fmaf(Z.e1b[r], rw(rec, 4 * r + 1, tid), zy);
-        zy = fmaf(Z.e2a[r], rw(rec, 4 * r + 2, tid), zy);
-        zy = fmaf(Z.e2b[r], rw(rec, 4 * r + 3, tid), zy);
+        zy = fmaf(Z.e1a[r], q[r].x, zy);
+        zy = fmaf(Z.e1b[r], q[r].y, zy);
+        zy = fmaf(Z.e2a[r], q[r].z, zy);
+        zy = fmaf(Z.e2b[r], q[r].w, zy);
         float s1a, s1b, s2a, s2b;
         lds_ld2(S1 + r * kFusedMax, s1a, s1b);
         lds_ld2(S2 + r * kFusedMax, s2a, s2b);
@@ -114,7 +117,7 @@ __device__ __forceinline__ void bwd_step(const BwdCtx &c, BwdLds &L, Slot &Z, Sl
     Z.ba = c.last && (m1 & 1u) ? Z.ba : 0.0f;
     Z.bb = c.last && (m1 & 2u) ? Z.bb : 0.0f;
     if (c.last) {
-        zy = fmaf(Z.ba, rw(rec, 32, tid), fmaf(Z.bb, rw(rec, 33, tid), zy));
+        zy = fmaf(Z.ba, q[8].x, fmaf(Z.bb, q[8].y, zy));
         float sa, sb;
         lds_ld2(&L.Sb[c.ja], sa, sb);
         lds_st2(&L.Sb[c.ja], sa + Z.ba, sb + Z.bb);
@@ -122,10 +125,10 @@ __device__ __forceinline__ void bwd_step(const BwdCtx &c, BwdLds &L, Slot &Z, Sl
     if (c.lane < kR) {
         const float zr = (m1 & 4u) ? RZ[row] : 0.0f;
         RZ[row] = zr;
-        zy = fmaf(zr, rw(rec, 34, tid), zy);
+        zy = fmaf(zr, q[8].z, zy);
         L.Sr[row] += zr;
     }
-    acc_zy += (double)zy;
+    acc_q += (double)zy;
     lds_st2(&L.zt[sx][c.s][c.ja], Z.e1a[0], Z.e1b[0]);
     __syncthreads();
 
@@ -140,17 +143,15 @@ __device__ __forceinline__ void bwd_step(const BwdCtx &c, BwdLds &L, Slot &Z, Sl
     lds_st2(&L.dl[c.s][c.ja], da7, db7);
     __syncthreads();
 
-    // (3) row sweep: div zbar, <div zbar, div y>, ybar and the adjoint updates
+    // (3) row sweep: div zbar, ybar and the adjoint updates
     float dua = 0.0f, dub = 0.0f;  // div zbar of the row above (0 above the tile)
     if (c.s > 0) lds_ld2(&L.dl[c.s - 1][c.ja], dua, dub);
-    float dd = 0.0f;
     const float bk = 1.0f + beta;
 #pragma unroll
     for (int r = 0; r < kR; ++r) {
         __builtin_amdgcn_sched_barrier(0);  // one row at a time: bounds the registers in flight
         float da = da7, db = db7;
         if (r < kR - 1) full_row_div(Z, RZr, r, Z.e1a[r + 1], Z.e1b[r + 1], da, db);
-        dd = fmaf(da, rw(rec, 35 + 2 * r, tid), fmaf(db, rw(rec, 36 + 2 * r, tid), dd));
         const float dlb = from_left(db);  // div zbar of column a - 1 (0 left of the tile)
         float y1a = fmaf(-kL, dua - da, ak * Z.e1a[r]);
         float y1b = fmaf(-kL, dub - db, ak * Z.e1b[r]);
@@ -191,11 +192,10 @@ __device__ __forceinline__ void bwd_step(const BwdCtx &c, BwdLds &L, Slot &Z, Sl
         }
         if (c.lane == 63) L.dR[c.il0 + r] = db;  // div zbar of the last column
         pin4(P.e1a[r], P.e1b[r], P.e2a[r], P.e2b[r]);
-        pin4(Z.e1a[r], Z.e1b[r], Z.e2a[r], dd);
+        pin4(Z.e1a[r], Z.e1b[r], Z.e2a[r], Z.e2b[r]);
         dua = da;
         dub = db;
     }
-    acc_dd += (double)dd;
     if (c.lane < kR) {  // right boundary edges
         const float yr = c.right_var ? fmaf(-kL, L.dR[row], ak * RZ[row]) : 0.0f;
         if (mom) {
@@ -211,12 +211,11 @@ __device__ __forceinline__ void bwd_step(const BwdCtx &c, BwdLds &L, Slot &Z, Sl
 // reverse steps k = K .. 1 (the slots swap roles every step)
 template <int K, int k = K>
 __device__ __forceinline__ void bwd_steps(const BwdCtx &c, BwdLds &L, Slot &Z, Slot &P, const float *beta,
-                                          const float *rec, long long rec_step, double &acc_zy, double &acc_dd)
+                                          const float4 *rec, long long rec_step, double &acc_q)
 {
     if constexpr (k >= 1) {
-        bwd_step<(k >= 3)>(c, L, Z, P, (K - k) & 1, k >= 3 ? beta[k] : 0.0f, rec + (k - 1) * rec_step, acc_zy,
-                           acc_dd);
-        bwd_steps<K, k - 1>(c, L, P, Z, beta, rec, rec_step, acc_zy, acc_dd);
+        bwd_step<(k >= 3)>(c, L, Z, P, (K - k) & 1, k >= 3 ? beta[k] : 0.0f, rec + (k - 1) * rec_step, acc_q);
+        bwd_steps<K, k - 1>(c, L, P, Z, beta, rec, rec_step, acc_q);
     }
 }
 
@@ -277,10 +276,10 @@ __global__ __launch_bounds__(1024) void k_fused_bwd(FusedBwdArgs a)
     __syncthreads();
 
     // ---- the K reverse steps; xbar_0 ends in A (right column in rx[K & 1])
-    double acc_zy = 0.0, acc_dd = 0.0;
-    const long long rec_step = (long long)gridDim.x * kRecWords * kRecThreads;
-    const float *rec = a.rec + (long long)t * kRecWords * kRecThreads;  // uniform: this subdomain's record
-    bwd_steps<KF>(c, L, A, B, a.beta, rec, rec_step, acc_zy, acc_dd);
+    double acc_q = 0.0;  // sum_k <zbar_k, q_k>
+    const long long rec_step = (long long)gridDim.x * kRecGroups * kRecThreads;
+    const float4 *rec = a.rec + (long long)t * kRecGroups * kRecThreads;  // uniform: this subdomain's record
+    bwd_steps<KF>(c, L, A, B, a.beta, rec, rec_step, acc_q);
     if constexpr (KF & 1) copy_slot(A, B);
     const int rxs = KF & 1;
     __syncthreads();
@@ -288,7 +287,7 @@ __global__ __launch_bounds__(1024) void k_fused_bwd(FusedBwdArgs a)
     // ---- outputs: pbar^n = xbar_0 + phatbar, phatbar = S / (L tau) (0 on the image boundary),
     // fbar += -div S / L, and the alpha derivative
     const double dA = im.dA, dB = im.dB;
-    double acc = -dB * acc_dd - dA * (double)itau * acc_zy;
+    double acc = acc_q;
     const float *lam = a.lam + im.lam;
     double sp = 0.0, fs = 0.0;  // <phat, S>, <f, div S>
 #pragma unroll

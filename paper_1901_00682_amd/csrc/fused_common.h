@@ -194,6 +194,7 @@ struct FullCtx {
     // tile's bottom edges
     float lo1, hi1, lo2a, hi2a, lob, hib;
     float ak, kL;
+    float qa, qb;  // recording: the weights of y and of d_b - d_a in the record word q
 };
 
 __device__ __forceinline__ int opaque(int x)
@@ -241,16 +242,19 @@ __device__ __forceinline__ void full_row_div(const Slot &Y, const float *RYr, in
 }
 
 // fused_step on a full tile; same arithmetic per edge, hence the same result
-// Record of one step on a full tile (reverse mode), one word per thread of the
-// workgroup for each of kRecWords words (word w of thread t at
-// rec[w * kRecThreads + t], dtvdd_internal.h):
-//   0..31  y on the thread's edges, 4 r + (0 e1a, 1 e1b, 2 e2a, 3 e2b)
-//   32, 33 y on the bottom boundary edges (strip 15), 34 y on the right boundary
-//          edge of row 8 s + lane (lanes 0..7)
-//   35..50 d = div_s y of the thread's pixels, 35 + 2 r + (0 column a, 1 column b)
-//   51     projection mask of the 32 edges (bit 4 r + q set when -1 < z < 1 on
-//          an edge that is a variable), 52 the same for the bottom edges (bits 0,
-//          1) and the right boundary edge (bit 2)
+// Record of one step on a full tile (reverse mode): kRecGroups groups of four
+// words per thread of the workgroup (group g of thread t is the float4 at
+// rec4[g * kRecThreads + t], dtvdd_internal.h):
+//   g = 0..7  q = qa y + qb (d_b - d_a) on the edges e1a, e1b, e2a, e2b of row r = g:
+//             the alpha derivative of z is (dA/tau)(phat - y) - dA (f_b - f_a)
+//             - dB (d_b - d_a), and q carries its y-dependent part (qa = -dA/tau,
+//             qb = -dB)
+//   g = 8     q on the bottom boundary edges a, b (strip 15), q on the right
+//             boundary edge of row 8 s + lane (lanes 0..7), the projection mask of
+//             the 32 edges (bit 4 r + i set when -1 < z < 1 on an edge that is a
+//             variable)
+//   g = 9     the projection mask of the bottom edges (bits 0, 1) and of the right
+//             boundary edge (bit 2); three unused words
 
 // projected step value and, when recording, the mask bit of its derivative
 template <bool REC>
@@ -262,7 +266,7 @@ __device__ __forceinline__ float proj(float z, float lo, float hi, unsigned &m, 
 
 template <bool mom, bool REC = false>
 __device__ __forceinline__ void full_step(const FullCtx &c, FusedLds &S, const Slot &X, Slot &Y, int sx, float beta,
-                                          float *rec = nullptr)
+                                          float4 *rec = nullptr)
 {
     // The phases are written without branches wherever a select does the job:
     // a branch splits the step into blocks and the compiler then sinks the row
@@ -283,18 +287,6 @@ __device__ __forceinline__ void full_step(const FullCtx &c, FusedLds &S, const S
     }
     Y.ba = mom ? fista_y(X.ba, Y.ba, beta) : X.ba;  // meaningful in strip 15 only
     Y.bb = mom ? fista_y(X.bb, Y.bb, beta) : X.bb;
-    if constexpr (REC) {
-#pragma unroll
-        for (int r = 0; r < kR; ++r) {
-            rec[(4 * r + 0) * kRecThreads] = Y.e1a[r];
-            rec[(4 * r + 1) * kRecThreads] = Y.e1b[r];
-            rec[(4 * r + 2) * kRecThreads] = Y.e2a[r];
-            rec[(4 * r + 3) * kRecThreads] = Y.e2b[r];
-        }
-        rec[32 * kRecThreads] = Y.ba;
-        rec[33 * kRecThreads] = Y.bb;
-        if (c.lane < kR) rec[34 * kRecThreads] = RY[olr];
-    }
     float *yt = &S.yt[sx][0][0] + oy;  // this strip's row of the exchange buffer (strip 0's is unused)
     lds_st2(yt, Y.e1a[0], Y.e1b[0]);
     __syncthreads();
@@ -317,17 +309,18 @@ __device__ __forceinline__ void full_step(const FullCtx &c, FusedLds &S, const S
     dua = c.s > 0 ? dua : 0.0f;
     dub = c.s > 0 ? dub : 0.0f;
     const float *c1 = &S.c1[0][0] + oc, *c2 = &S.c2[0][0] + oc;
-    unsigned m0 = 0, m1 = 0;  // projection masks (recording)
+    unsigned m0 = 0, m1 = 0;               // projection masks (recording)
+    float qba = 0.0f, qbb = 0.0f, qr = 0.0f;  // q of the bottom and right boundary edges (recording)
 #pragma unroll
     for (int r = 0; r < kR; ++r) {
         __builtin_amdgcn_sched_barrier(0);  // one row at a time: bounds the registers in flight
         float da = da7, db = db7;
         if (r < kR - 1) full_row_div(Y, RYr, r, Y.e1a[r + 1], Y.e1b[r + 1], da, db);
-        if constexpr (REC) {
-            rec[(35 + 2 * r) * kRecThreads] = da;
-            rec[(36 + 2 * r) * kRecThreads] = db;
-        }
         const float dlb = from_left(db);
+        if constexpr (REC)
+            rec[r * kRecThreads] =
+                make_float4(fmaf(c.qb, dua - da, c.qa * Y.e1a[r]), fmaf(c.qb, dub - db, c.qa * Y.e1b[r]),
+                            fmaf(c.qb, dlb - da, c.qa * Y.e2a[r]), fmaf(c.qb, da - db, c.qa * Y.e2b[r]));
         float c1a, c1b, c2a, c2b;
         lds_ld2(c1 + r * kFusedMax, c1a, c1b);
         lds_ld2(c2 + r * kFusedMax, c2a, c2b);
@@ -340,6 +333,10 @@ __device__ __forceinline__ void full_step(const FullCtx &c, FusedLds &S, const S
         if (r == kR - 1) {  // bottom boundary edges of the tile (strip 15, unless on the image boundary)
             float cba, cbb;
             lds_ld2(S.cb + (oy - c.s * kFusedMax), cba, cbb);
+            if constexpr (REC) {
+                qba = fmaf(c.qb, da, c.qa * Y.ba);
+                qbb = fmaf(c.qb, db, c.qa * Y.bb);
+            }
             // only strip 15 uses them; they collapse to 0 on the image boundary
             Y.ba = proj<REC>(fista_z(Y.ba, da, 0.0f, cba, ak, kL), c.lob, c.hib, m1, 0);
             Y.bb = proj<REC>(fista_z(Y.bb, db, 0.0f, cbb, ak, kL), c.lob, c.hib, m1, 1);
@@ -349,13 +346,16 @@ __device__ __forceinline__ void full_step(const FullCtx &c, FusedLds &S, const S
         dua = da;
         dub = db;
     }
-    if (!c.right_bnd && c.lane < kR) {
-        const float z = fista_z(RY[olr], S.dR[olr], 0.0f, S.cr[olr], ak, kL);
-        RY[olr] = proj<REC>(z, -1.0f, 1.0f, m1, 2);
+    if (c.lane < kR) {
+        if constexpr (REC) qr = fmaf(c.qb, S.dR[olr], c.qa * RY[olr]);
+        if (!c.right_bnd) {
+            const float z = fista_z(RY[olr], S.dR[olr], 0.0f, S.cr[olr], ak, kL);
+            RY[olr] = proj<REC>(z, -1.0f, 1.0f, m1, 2);
+        }
     }
     if constexpr (REC) {
-        rec[51 * kRecThreads] = __uint_as_float(m0);
-        rec[52 * kRecThreads] = __uint_as_float(m1);
+        rec[8 * kRecThreads] = make_float4(qba, qbb, qr, __uint_as_float(m0));
+        rec[9 * kRecThreads] = make_float4(__uint_as_float(m1), 0.0f, 0.0f, 0.0f);
     }
 }
 
@@ -409,7 +409,7 @@ __device__ __forceinline__ int run_steps(const C &c, FusedLds &S, Slot &A, Slot 
 // the right boundary column holding it (K & 1).
 template <int K, bool REC = false, int k = 1>
 __device__ __forceinline__ int full_steps_fixed(const FullCtx &c, FusedLds &S, Slot &X, Slot &Y, const float *beta,
-                                                float *rec = nullptr, long long rec_step = 0)
+                                                float4 *rec = nullptr, long long rec_step = 0)
 {
     if constexpr (k <= K) {
         full_step<(k >= 3), REC>(c, S, X, Y, (k - 1) & 1, k >= 3 ? beta[k] : 0.0f,
