@@ -53,6 +53,7 @@ class _Params(ctypes.Structure):
         ("tau", ctypes.c_double), ("sigma", ctypes.c_double),
         ("tau0", ctypes.c_double), ("sigma0", ctypes.c_double), ("gamma", ctypes.c_double),
         ("n_inner", ctypes.c_int),
+        ("cv_c1", ctypes.c_double), ("cv_c2", ctypes.c_double),
     ]
 
 
@@ -88,7 +89,8 @@ def load(path: str = LIB_PATH):
     lib.orc_primal_energy.restype = ctypes.c_double
     lib.orc_primal_energy.argtypes = [vp, _D, _D, _U8]
     lib.orc_proj_box.argtypes = [ctypes.c_long, _D, _D]
-    lib.orc_prox.argtypes = [ctypes.c_int, ctypes.c_long, _D, _D, _U8, ctypes.c_double, _D]
+    lib.orc_prox.argtypes = [ctypes.c_int, ctypes.c_long, _D, _D, _U8, ctypes.c_double, ctypes.c_double,
+                             ctypes.c_double, _D]
     lib.orc_n_done.restype = ctypes.c_int
     lib.orc_n_done.argtypes = [vp]
     lib.orc_threads.restype = ctypes.c_int
@@ -108,7 +110,7 @@ def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
-FIDELITY = {"L2": 0, "L1": 1}
+FIDELITY = {"L2": 0, "L1": 1, "CV": 2}
 INNER = {"FISTA": 0, "CP2": 1}
 
 
@@ -130,6 +132,8 @@ class Problem:
     gamma: float | None = None   # default 1/(8 tau)
     n_inner: int = 10
     no_prox_term: bool = False
+    c1: float = 0.6              # Chan-Vese intensities (fidelity "CV"), eq. (CCV)
+    c2: float = 0.1
 
 
 class Oracle:
@@ -149,7 +153,8 @@ class Oracle:
         gamma = prob.gamma if prob.gamma is not None else 1.0 / (8.0 * prob.tau)
         self.params = _Params(H, W, self.ny, self.nx, float(prob.alpha), FIDELITY[prob.fidelity],
                               INNER[prob.inner], int(prob.no_prox_term), float(prob.tau), float(prob.sigma),
-                              float(prob.tau0), float(prob.sigma0), float(gamma), int(prob.n_inner))
+                              float(prob.tau0), float(prob.sigma0), float(gamma), int(prob.n_inner),
+                              float(prob.c1), float(prob.c2))
         self.f = f
         self.mask = None if prob.mask is None else np.ascontiguousarray(prob.mask, dtype=np.uint8)
         self._mp = None if self.mask is None else self.mask.ctypes.data_as(_U8)
@@ -283,12 +288,12 @@ def proj_box(p):
     return out
 
 
-def prox(fidelity: str, z, f, a: float, mask=None):
+def prox(fidelity: str, z, f, a: float, mask=None, c1: float = 0.6, c2: float = 0.1):
     z, f = _f64(z), _f64(f)
     out = np.empty_like(z)
     m = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
     load().orc_prox(FIDELITY[fidelity], z.size, _dp(z), _dp(f), None if m is None else m.ctypes.data_as(_U8),
-                    float(a), _dp(out))
+                    float(a), float(c1), float(c2), _dp(out))
     return out
 
 

@@ -30,13 +30,14 @@
 
 #define ORC_L2 0
 #define ORC_L1 1
+#define ORC_CV 2
 #define ORC_FISTA 0
 #define ORC_CP2 1
 
 typedef struct {
     int H, W, ny, nx;
     double alpha;
-    int fidelity;      /* ORC_L2 or ORC_L1 (Sec. 3) */
+    int fidelity;      /* ORC_L2, ORC_L1 or ORC_CV (Sec. 3) */
     int inner;         /* ORC_FISTA or ORC_CP2 (local solver) */
     int no_prox_term;  /* 1: drop the 1/(2 tau)|p - phat|^2 term of the local
                           problem (the limit 1/tau -> 0); used only to compare a
@@ -44,6 +45,8 @@ typedef struct {
     double tau, sigma;          /* outer step sizes of Algorithm 1 */
     double tau0, sigma0, gamma; /* accelerated local primal-dual (Sec. 5) */
     int n_inner;                /* local iterations per outer step */
+    double cv_c1, cv_c2;        /* ORC_CV: the two intensities of the convex
+                                   Chan-Vese model, eq. (CCV) */
 } orc_params;
 
 typedef struct {
@@ -148,13 +151,24 @@ static void divT_local(const orc_state *st, const orc_sub *S, const double *v, d
         }
 }
 
-/* prox of sigma*alpha*F_s at one pixel (Sec. 3 and the inpainting prox of
-   Sec. 5): a = sigma*alpha. */
-static double prox_fidelity(int fidelity, double z, double f, unsigned char m, double a)
+/* g = (f - c1)^2 - (f - c2)^2 of the convex Chan-Vese model, eq. (CCV). */
+static double cv_g(const orc_params *P, double f)
+{
+    double a = f - P->cv_c1, b = f - P->cv_c2;
+    return a * a - b * b;
+}
+
+/* prox of a*F at one pixel, a = sigma*alpha (Sec. 3 and the inpainting prox
+   of Sec. 5):
+     L2: argmin (a/2)(u - f)^2 + (1/2)(u - z)^2 = (z + a f)/(1 + a);
+     L1: f + shr(z - f, a), eq. (shrinkage) with 0/|0| = 0;
+     CV: F(u) = <u, g> + chi_{0 <= u <= 1}(u) gives the projection of z - a g
+         onto [0, 1] (Sec. 3, segmentation). */
+static double prox_fidelity(const orc_params *P, double z, double f, unsigned char m, double a)
 {
     if (!m) return z; /* pixel in the inpainting set D */
-    if (fidelity == ORC_L2) return (z + a * f) / (1.0 + a);
-    /* L1: f + shr(z - f, a), eq. (shrinkage) with 0/|0| = 0 */
+    if (P->fidelity == ORC_L2) return (z + a * f) / (1.0 + a);
+    if (P->fidelity == ORC_CV) return fmin(fmax(z - a * cv_g(P, f), 0.0), 1.0);
     double d = z - f;
     double mag = fmax(fabs(d) - a, 0.0);
     double sgn = d > 0 ? 1.0 : (d < 0 ? -1.0 : 0.0);
@@ -245,7 +259,7 @@ static void local_cp2(const orc_state *st, orc_sub *S)
     for (int it = 0; it < P->n_inner; it++) {
         div_local(S, xb1, xb2, S->v);
         for (int i = 0; i < h * w; i++)
-            S->u[i] = prox_fidelity(P->fidelity, S->u[i] + sk * S->v[i], S->f[i], S->m[i], sk * P->alpha);
+            S->u[i] = prox_fidelity(P, S->u[i] + sk * S->v[i], S->f[i], S->m[i], sk * P->alpha);
         divT_local(st, S, S->u, S->q1, S->q2);
         for (int e = 0; e < n1; e++) {
             double pbar = x1[e] - tk * S->q1[e];
@@ -306,6 +320,10 @@ orc_state *orc_create(const orc_params *prm, const int *row_cuts, const int *col
                       const double *f, const unsigned char *mask)
 {
     if (!prm || prm->H < 1 || prm->W < 1 || prm->ny < 1 || prm->nx < 1 || !(prm->alpha > 0)) return NULL;
+    if (prm->fidelity < ORC_L2 || prm->fidelity > ORC_CV) return NULL;
+    /* the local FISTA solves the ROF dual only; the Chan-Vese model has no mask */
+    if (prm->inner == ORC_FISTA && (prm->fidelity != ORC_L2 || mask)) return NULL;
+    if (prm->fidelity == ORC_CV && mask) return NULL;
     if (row_cuts[0] != 0 || row_cuts[prm->ny] != prm->H) return NULL;
     if (col_cuts[0] != 0 || col_cuts[prm->nx] != prm->W) return NULL;
     for (int r = 0; r < prm->ny; r++) if (row_cuts[r + 1] <= row_cuts[r]) return NULL;
@@ -481,7 +499,9 @@ double orc_tv(int H, int W, const double *u)
     return tv;
 }
 
-/* Primal energy J(u) = alpha F(u) + TV(u), eq. (model). */
+/* Primal energy J(u) = alpha F(u) + TV(u), eq. (model).  For the Chan-Vese
+   fidelity F(u) = <u, g>; the indicator of [0, 1] is left out (the local
+   prox keeps every iterate inside). */
 double orc_primal_energy(const orc_state *st, const double *u, const double *f, const unsigned char *mask)
 {
     const orc_params *P = &st->prm;
@@ -490,7 +510,8 @@ double orc_primal_energy(const orc_state *st, const double *u, const double *f, 
     for (size_t i = 0; i < n; i++) {
         if (mask && !mask[i]) continue;
         double d = u[i] - f[i];
-        fid += P->fidelity == ORC_L2 ? 0.5 * d * d : fabs(d);
+        if (P->fidelity == ORC_CV) fid += u[i] * cv_g(P, f[i]);
+        else fid += P->fidelity == ORC_L2 ? 0.5 * d * d : fabs(d);
     }
     return P->alpha * fid + orc_tv(P->H, P->W, u);
 }
@@ -525,9 +546,11 @@ static void assemble_pavg(const orc_state *st, double *g1, double *g2)
 
 /* Diagnostics of the current iterate:
      out[0] = J(u), the primal energy of the assembled u;
-     out[1] = D(p_avg) = -<f, div p_avg> - |div p_avg|^2/(2 alpha), the dual
-              value of the conforming average (finite for L2 without mask,
-              NaN otherwise);
+     out[1] = D(p_avg) = -(alpha F)^*(div p_avg), the dual value of the
+              conforming average: for L2 -<f, d> - |d|^2/(2 alpha), for the
+              Chan-Vese fidelity sum over pixels of min(0, alpha g - d)
+              (d = div p_avg; finite for L2 and CV without mask, NaN
+              otherwise);
      out[2] = J - D, the primal-dual gap (>= 0 by weak duality; NaN when D is);
      out[3] = |B p|_2, the interface jump. */
 void orc_diagnostics(const orc_state *st, const double *f_global, const unsigned char *mask, double *out)
@@ -542,18 +565,20 @@ void orc_diagnostics(const orc_state *st, const double *f_global, const unsigned
     int has_mask = 0;
     if (mask)
         for (size_t i = 0; i < n; i++) if (!mask[i]) { has_mask = 1; break; }
-    if (P->fidelity == ORC_L2 && !has_mask) {
+    if ((P->fidelity == ORC_L2 || P->fidelity == ORC_CV) && !has_mask) {
         double *g1 = dalloc((size_t)(H + 1) * W), *g2 = dalloc((size_t)H * (W + 1));
         assemble_pavg(st, g1, g2);
-        double lin = 0.0, quad = 0.0;
+        double lin = 0.0, quad = 0.0, cv = 0.0;
         for (int i = 0; i < H; i++)
             for (int j = 0; j < W; j++) {
                 double d = (g1[(size_t)(i + 1) * W + j] - g1[(size_t)i * W + j])
                          + (g2[(size_t)i * (W + 1) + j + 1] - g2[(size_t)i * (W + 1) + j]);
-                lin += f_global[(size_t)i * W + j] * d;
+                double fv = f_global[(size_t)i * W + j];
+                lin += fv * d;
                 quad += d * d;
+                cv += fmin(0.0, P->alpha * cv_g(P, fv) - d);
             }
-        D = -lin - quad / (2.0 * P->alpha);
+        D = P->fidelity == ORC_CV ? cv : -lin - quad / (2.0 * P->alpha);
         free(g1); free(g2);
     }
     double nb = 0.0;
@@ -782,9 +807,15 @@ void orc_proj_box(long n, const double *p, double *out)
 }
 
 /* elementwise prox of sigma*alpha*F, exposed for the closed-form pins */
-void orc_prox(int fidelity, long n, const double *z, const double *f, const unsigned char *m, double a, double *out)
+void orc_prox(int fidelity, long n, const double *z, const double *f, const unsigned char *m, double a,
+              double c1, double c2, double *out)
 {
-    for (long i = 0; i < n; i++) out[i] = prox_fidelity(fidelity, z[i], f[i], m ? m[i] : 1, a);
+    orc_params P;
+    memset(&P, 0, sizeof P);
+    P.fidelity = fidelity;
+    P.cv_c1 = c1;
+    P.cv_c2 = c2;
+    for (long i = 0; i < n; i++) out[i] = prox_fidelity(&P, z[i], f[i], m ? m[i] : 1, a);
 }
 
 int orc_n_done(const orc_state *st) { return st->n_done; }

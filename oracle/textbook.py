@@ -14,8 +14,10 @@ copy) shows up as a disagreement.
   * the accelerated primal-dual method (Chambolle & Pock 2011, Alg. 2) on the
     full saddle problem eq. (model_pd);
   * exact references on tiny images: the dual ROF problem as a box-constrained
-    least-squares problem (solved by BVLS, certified by the KKT conditions), and
-    TV-L1 (with or without inpainting mask) as a linear program.
+    least-squares problem (solved by BVLS, certified by the KKT conditions),
+    TV-L1 (with or without inpainting mask) and the convex Chan-Vese model
+    eq. (CCV) as linear programs, and the binary Chan-Vese problem by
+    enumeration of every pixel set.
 """
 from __future__ import annotations
 
@@ -80,16 +82,24 @@ def fista_dual_rof(f, alpha, n_iter, q=None):
     return x1, x2, f + fd_div(x1, x2, H, W) / alpha
 
 
-def _prox(fidelity, z, f, m, a):
+def cv_g(f, c1, c2):
+    """g = (f - c1)^2 - (f - c2)^2 of eq. (CCV)."""
+    f = np.asarray(f, dtype=np.float64)
+    return (f - c1) ** 2 - (f - c2) ** 2
+
+
+def _prox(fidelity, z, f, m, a, c1=0.6, c2=0.1):
     if fidelity == "L2":
         out = (z + a * f) / (1.0 + a)
+    elif fidelity == "CV":
+        out = np.minimum(np.maximum(z - a * cv_g(f, c1, c2), 0.0), 1.0)
     else:
         d = z - f
         out = f + np.sign(d) * np.maximum(np.abs(d) - a, 0.0)
     return np.where(m, out, z)
 
 
-def cp2_full(f, alpha, n_iter, tau0, sigma0, gamma, fidelity="L2", mask=None, q=None, u=None):
+def cp2_full(f, alpha, n_iter, tau0, sigma0, gamma, fidelity="L2", mask=None, q=None, u=None, c1=0.6, c2=0.1):
     """Chambolle-Pock Alg. 2 on min_q max_u <div q, u> + chi_C(q) - alpha F(u)
     (the saddle form of Sec. 5 without the proximal term): u is the ascent
     variable, q the accelerated one."""
@@ -104,7 +114,7 @@ def cp2_full(f, alpha, n_iter, tau0, sigma0, gamma, fidelity="L2", mask=None, q=
     xb1, xb2 = x1.copy(), x2.copy()
     tk, sk = tau0, sigma0
     for _ in range(n_iter):
-        y = _prox(fidelity, y + sk * fd_div(xb1, xb2, H, W), f, m, sk * alpha)
+        y = _prox(fidelity, y + sk * fd_div(xb1, xb2, H, W), f, m, sk * alpha, c1, c2)
         d1, d2 = fd_grad(y)          # div^* y = -D y
         z1 = np.clip(x1 - tk * (-d1), -1.0, 1.0)
         z2 = np.clip(x2 - tk * (-d2), -1.0, 1.0)
@@ -188,6 +198,56 @@ def tvl1_exact_energy(f, alpha, mask=None):
         raise RuntimeError(res.message)
     u = res.x[:n].reshape(H, W)
     return float(res.fun), u
+
+
+def _diff_matrix(H, W):
+    """Rows of D: one per interior edge, (u_b - u_a) with b below / right of a."""
+    n = H * W
+    rows = []
+    for i in range(H - 1):
+        for j in range(W):
+            r = np.zeros(n); r[(i + 1) * W + j] = 1; r[i * W + j] = -1; rows.append(r)
+    for i in range(H):
+        for j in range(W - 1):
+            r = np.zeros(n); r[i * W + j + 1] = 1; r[i * W + j] = -1; rows.append(r)
+    return np.array(rows).reshape(-1, n)
+
+
+def cv_exact_energy(f, alpha, c1, c2):
+    """Exact minimum of alpha <u, g> + TV(u) over 0 <= u <= 1 (eq. CCV) on a
+    tiny image, as a linear program over (u, t) with |Du| <= t."""
+    from scipy.optimize import linprog
+
+    f = np.asarray(f, dtype=np.float64)
+    H, W = f.shape
+    n = H * W
+    Dm = _diff_matrix(H, W)
+    ne = Dm.shape[0]
+    c = np.concatenate([alpha * cv_g(f, c1, c2).ravel(), np.ones(ne)])
+    A_ub = np.block([[Dm, -np.eye(ne)], [-Dm, -np.eye(ne)]])
+    b_ub = np.zeros(2 * ne)
+    bounds = [(0.0, 1.0)] * n + [(0, None)] * ne
+    res = linprog(c, A_ub=A_ub, b_ub=b_ub, bounds=bounds, method="highs-ds",
+                  options={"primal_feasibility_tolerance": 1e-10, "dual_feasibility_tolerance": 1e-10})
+    if res.status != 0:
+        raise RuntimeError(res.message)
+    return float(res.fun), res.x[:n].reshape(H, W)
+
+
+def cv_binary_min(f, alpha, c1, c2):
+    """Minimum of alpha sum_{x in S} g_x + (number of edges cut by S) over every
+    pixel set S of a tiny image (at most 20 pixels), by enumeration."""
+    f = np.asarray(f, dtype=np.float64)
+    H, W = f.shape
+    n = H * W
+    if n > 20:
+        raise ValueError("too many pixels to enumerate")
+    g = cv_g(f, c1, c2).ravel()
+    S = ((np.arange(1 << n)[:, None] >> np.arange(n)[None, :]) & 1).astype(np.float64)
+    Dm = _diff_matrix(H, W)
+    E = alpha * S @ g + np.abs(S @ Dm.T).sum(axis=1)
+    k = int(np.argmin(E))
+    return float(E[k]), S[k].reshape(H, W)
 
 
 def div_norm_sq(apply_div, apply_divT, n_in, iters=2000, seed=0):
