@@ -78,6 +78,8 @@ def workload(name: str):
         return synth.config2(size=8192)
     if name == "tvl1":
         return synth.config3()
+    if name == "cv2048":
+        return synth.cv_case()
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -176,12 +178,93 @@ def run_diff(args):
     }
 
 
+def run_dd_vs_full(args):
+    """Decomposed against undecomposed on one GPU (Sec. 6 compares the method
+    with the primal-dual method on the full-dimension problem): wall-clock time
+    of a plain solve until the relative primal energy error (J(u) - J*)/J*
+    falls below 1e-5 (the outer stopping rule of Sec. 6), on the 2048 x 2048
+    ROF image.  J* comes from a long undecomposed FISTA run whose FP64
+    primal-dual gap bounds its own error.  Each iteration count of a doubling
+    sequence is a separate timed solve (no diagnostics inside the timed
+    region); J(u) is evaluated after it with the FP64 diagnostics."""
+    import torch
+
+    from paper_1901_00682_amd import dtvdd, synth
+
+    c = synth.config2()
+    H, W = c.f.shape
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    f = torch.from_numpy(np.ascontiguousarray(c.f).ravel()).to(dev)
+    full_img = dtvdd.Image(H, W, np.array([0, H]), np.array([0, W]), c.alpha)
+    dd_img = dtvdd.Image(H, W, c.row_cuts, c.col_cuts, c.alpha)
+    tol = 1e-5
+
+    def timed(plan):
+        st = plan.new_state()
+        plan.solve(f, state=st, want_stats=False)  # warm-up (and the autotuner's first look)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(max(1, args.steps // 5)):
+            t0 = time.perf_counter()
+            plan.solve(f, state=st, want_stats=False)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        J, D, gap, _ = plan.diagnostics(f, st)[0]
+        return float(np.median(ts)), float(J), float(D)
+
+    ref = dtvdd.Plan([full_img], full_problem=True, n_outer=1, n_inner=args.ref_iters, device=dev)
+    st = ref.new_state()
+    ref.solve(f, state=st, want_stats=False)
+    Jr, Dr, gr, _ = (float(x) for x in ref.diagnostics(f, st)[0])
+    Jstar = Jr
+    methods = {
+        "dd_16x16_fista5": (lambda n: dtvdd.Plan([dd_img], n_outer=n, n_inner=c.n_inner, device=dev),
+                            [25 * 2 ** k for k in range(11)], c.n_inner),
+        "full_fista": (lambda n: dtvdd.Plan([full_img], full_problem=True, n_outer=1, n_inner=n, device=dev),
+                       [100 * 2 ** k for k in range(9)], 1),
+        "full_cp": (lambda n: dtvdd.Plan([full_img], full_problem=True, inner="CP2", n_outer=1, n_inner=n,
+                                         tau0=10.0, sigma0=1.0 / 80.0, gamma=1.0 / 400.0, device=dev),
+                    [100 * 2 ** k for k in range(9)], 1),
+    }
+    res = {}
+    for name, (mk, counts, per) in methods.items():
+        rows, hit = [], None
+        for n in counts:
+            plan = mk(n)
+            dt, J, D = timed(plan)
+            err = (J - Jstar) / Jstar
+            rows.append({"count": n, "ms": dt * 1e3, "rel_energy_error": err, "schedule": plan.schedule()})
+            print(f"[dd_vs_full] {name} count {n}: {dt * 1e3:.2f} ms, rel err {err:.3e}", file=sys.stderr, flush=True)
+            del plan
+            if err < tol:
+                hit = rows[-1]
+                break
+        res[name] = {"runs": rows, "reached": hit is not None,
+                     "ms_to_tol": hit["ms"] if hit else None,
+                     "iterations_to_tol": (hit["count"] * per) if hit else None}
+    dd = res["dd_16x16_fista5"]["ms_to_tol"]
+    best_full = min([v["ms_to_tol"] for k, v in res.items() if k != "dd_16x16_fista5" and v["ms_to_tol"]],
+                    default=None)
+    return {
+        "metric": "ms to (J - J*)/J* < 1e-5, 2048^2 ROF: 16x16 decomposition vs undecomposed",
+        "value": dd, "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": dd, "higher_is_better": False, "scaling": "strong", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{c.name}: {H}x{W}, alpha {c.alpha}; counts double until the tolerance is met",
+                   "tolerance": tol},
+        "reference": {"iterations": args.ref_iters, "J": Jr, "D": Dr, "gap_over_J": gr / Jr},
+        "methods": res,
+        "full_over_dd": (best_full / dd) if (dd and best_full) else None,
+    }
+
+
 def cpu_baseline(c, outer_sample: int) -> dict:
     import oracle
 
     o = oracle.Oracle(oracle.Problem(c.f.astype(np.float64), c.alpha, c.row_cuts, c.col_cuts, fidelity=c.fidelity,
                                      inner=c.inner, mask=c.mask, tau=c.tau, sigma=c.sigma, tau0=c.tau0,
-                                     sigma0=c.sigma0, gamma=c.gamma, n_inner=c.n_inner))
+                                     sigma0=c.sigma0, gamma=c.gamma, n_inner=c.n_inner, **c.extra))
     t0 = time.perf_counter()
     o.run(outer_sample)
     dt = time.perf_counter() - t0
@@ -199,6 +282,7 @@ def main():
     ap.add_argument("--workload", default="rof2048")
     ap.add_argument("--schedule", default="auto")
     ap.add_argument("--cpu-outer", type=int, default=500, help="outer steps of the oracle sample (0: skip)")
+    ap.add_argument("--ref-iters", type=int, default=20000, help="dd_vs_full: FISTA iterations of the J* run")
     ap.add_argument("--calibrate-copy", action="store_true", help="also run a 256 MiB device copy (counter scale)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -217,6 +301,9 @@ def main():
     if args.workload == "diff":
         print(json.dumps(run_diff(args)), flush=True)
         return
+    if args.workload == "dd_vs_full":
+        print(json.dumps(run_dd_vs_full(args)), flush=True)
+        return
     c = workload(args.workload)
     H, W = c.f.shape
     dev = torch.device("cuda:0")
@@ -227,7 +314,7 @@ def main():
     img = dtvdd.Image(H, W, c.row_cuts, c.col_cuts, c.alpha)
     kw = dict(fidelity=c.fidelity, inner=c.inner, has_mask=c.mask is not None, tau=c.tau, sigma=c.sigma,
               tau0=c.tau0, sigma0=c.sigma0, gamma=c.gamma, n_outer=c.n_outer, n_inner=c.n_inner,
-              schedule=args.schedule, device=dev)
+              schedule=args.schedule, device=dev, **c.extra)
     plan = dtvdd.Plan([img], **kw)
     state = plan.new_state()
     for _ in range(args.warmup):

@@ -71,6 +71,10 @@ extern "C" {
 /* fidelity (Sec. 3) */
 #define DTV_L2 0
 #define DTV_L1 1
+#define DTV_CV 2             /* convex Chan-Vese segmentation, eq. (CCV): F(u) = <u, g> + the
+                                indicator of 0 <= u <= 1, g = (f - c1)^2 - (f - c2)^2 (c1, c2 =
+                                cv_c1, cv_c2); prox_{a F}(z) = projection of z - a g onto [0, 1];
+                                CP2 only, no mask */
 
 /* local solver */
 #define DTV_INNER_FISTA 0    /* projected FISTA on the local dual; L2 without mask only */
@@ -79,8 +83,10 @@ extern "C" {
 /* kernel schedule of the local solves (numerically identical results) */
 #define DTV_SCHED_AUTO 0     /* pick by measurement: the first solve of a plan whose shape the
                                 process has not seen runs its first outer steps in short timed
-                                chunks, one per candidate (schedule x streaming rows), keeps the
-                                fastest for the remaining steps and caches it per shape (the
+                                chunks, one per candidate (schedule x streaming rows; the
+                                persistent launch at two chunk lengths, to separate its fixed
+                                cost from its cost per step), keeps the one that would finish
+                                the remaining steps first and caches it per shape (the
                                 schedules round identically, so the result does not depend on
                                 the choice); with too few outer steps, or with time_kernels, a
                                 fixed rule picks: persistent, else fused, else streaming */
@@ -109,7 +115,7 @@ typedef struct {
    parameters of Sec. 5 (defaults used by the paper: tau = 50, tau sigma = 1/2,
    tau0 = 10, tau0 sigma0 = 1/8, gamma = 1/(8 tau)). */
 typedef struct {
-    int32_t fidelity;          /* DTV_L2 or DTV_L1 */
+    int32_t fidelity;          /* DTV_L2, DTV_L1 or DTV_CV */
     int32_t inner;             /* DTV_INNER_FISTA or DTV_INNER_CP2 */
     int32_t has_mask;          /* 1: d_mask is given */
     double tau, sigma;         /* > 0, tau * sigma <= 1/2 (|B|^2 = 2, Prop. B_norm) */
@@ -117,7 +123,7 @@ typedef struct {
     double gamma;              /* CP2: 0 <= gamma <= 1/tau (G_s^* is 1/tau-uniformly convex) */
     int32_t n_outer, n_inner;  /* iteration counts; n_outer >= 0, n_inner >= 1 */
     int32_t diag_every;        /* 0: none; k > 0: FP64 diagnostics every k outer steps and after the last */
-    double gap_tol;            /* > 0 (single L2 image without mask, diag_every > 0): stop at the
+    double gap_tol;            /* > 0 (single L2 or CV image without mask, diag_every > 0): stop at the
                                   first diagnostic step with gap <= gap_tol * |J| */
     int32_t warm_start;        /* 0: start from p~ = 0, lambda = 0, u = f; 1: continue from the
                                   state held in d_p1, d_p2, d_lambda (and d_u for CP2) */
@@ -132,6 +138,16 @@ typedef struct {
                                   the per-step schedules from a captured hipGraph (when no
                                   per-step host work is asked for: diagnostics, checkpoints,
                                   kernel timing) */
+    double cv_c1, cv_c2;       /* DTV_CV: the two region intensities of eq. (CCV); finite */
+    int32_t full_problem;      /* 1: the undecomposed problem (Sec. 6 compares against it): every
+                                  image is one subdomain (ny = nx = 1) and the local problem has no
+                                  proximal term (the limit 1/tau -> 0, so tau and sigma play no
+                                  part), i.e. the local solver is the plain method on the whole
+                                  dual problem -- FISTA on the dual ROF problem, or the
+                                  primal-dual method of Chambolle and Pock with tau0, sigma0 and
+                                  gamma >= 0; each outer step restarts it from the current
+                                  iterate (n_outer = 1: n_inner plain iterations); no
+                                  save_for_backward */
 } dtv_dd_params;
 
 /* Where image `image` lives in the concatenated buffers (element offsets). */
@@ -169,9 +185,12 @@ int dtv_dd_bind_workspace(dtv_dd_plan *plan, void *d_ws, size_t bytes);
    d_lambda: outputs (and inputs when warm_start = 1).
    h_stats: NULL, or host room for n_images * (n_outer / diag_every + 1) rows of
    5 doubles [outer step, J(u), D(p_avg), gap = J - D, |B p~|_2], image-major;
-   *n_rows (may be NULL) receives the number of rows per image.  D and gap are
-   NaN unless the fidelity is L2 without mask.  Returns DTV_ENONFINITE if a
-   diagnostic is not finite. */
+   *n_rows (may be NULL) receives the number of rows per image.  J(u) =
+   alpha F(u) + TV(u) (for DTV_CV, F(u) = <u, g> without the indicator: the
+   prox keeps u in [0, 1]); D(p) = -(alpha F)^*(div p): -<f, div p> -
+   |div p|^2/(2 alpha) for L2, sum over pixels of min(0, alpha g - div p) for
+   DTV_CV, NaN (and so the gap) for L1 and for masked problems.  Returns
+   DTV_ENONFINITE if a diagnostic is not finite. */
 int dtv_dd_solve(dtv_dd_plan *plan, const float *d_f, const uint8_t *d_mask, float *d_u, float *d_p1,
                  float *d_p2, float *d_lambda, double *h_stats, int32_t *n_rows, void *stream);
 

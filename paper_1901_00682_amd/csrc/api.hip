@@ -87,6 +87,7 @@ struct dtv_dd_plan {
     int64_t tot_px = 0, tot_p1 = 0, tot_p2 = 0, tot_lam = 0;
     int schedule = DTV_SCHED_STREAM;
     int rows = 16;  // rows per wave strip of the streaming kernels
+    double inv_tau = 0.0;  // 1/tau of the local proximal term (0 for the undecomposed problem)
 
     // metadata uploaded to the workspace at bind time
     std::vector<ImgDev> h_imgs;
@@ -225,23 +226,35 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
     if (!imgs || !prm || !out) return fail(DTV_EINVAL, "null argument");
     if (n_images < 1) return fail(DTV_EINVAL, "n_images must be >= 1");
     const dtv_dd_params &p = *prm;
-    if (p.fidelity != DTV_L2 && p.fidelity != DTV_L1) return fail(DTV_EINVAL, "fidelity must be DTV_L2 or DTV_L1");
+    if (p.fidelity != DTV_L2 && p.fidelity != DTV_L1 && p.fidelity != DTV_CV)
+        return fail(DTV_EINVAL, "fidelity must be DTV_L2, DTV_L1 or DTV_CV");
     if (p.inner != DTV_INNER_FISTA && p.inner != DTV_INNER_CP2) return fail(DTV_EINVAL, "unknown inner solver");
     if (p.inner == DTV_INNER_FISTA && (p.fidelity != DTV_L2 || p.has_mask))
         return fail(DTV_EINVAL, "FISTA local solver needs the L2 fidelity without mask (use CP2)");
-    if (!finite_pos(p.tau) || !finite_pos(p.sigma)) return fail(DTV_EINVAL, "tau and sigma must be positive");
-    if (p.tau * p.sigma > 0.5 * (1.0 + 1e-12)) return fail(DTV_EINVAL, "tau * sigma must be <= 1/2");
+    if (p.fidelity == DTV_CV && p.has_mask) return fail(DTV_EINVAL, "the Chan-Vese fidelity takes no mask");
+    if (p.fidelity == DTV_CV && (!std::isfinite(p.cv_c1) || !std::isfinite(p.cv_c2)))
+        return fail(DTV_EINVAL, "cv_c1 and cv_c2 must be finite");
+    if (p.full_problem != 0 && p.full_problem != 1) return fail(DTV_EINVAL, "full_problem must be 0 or 1");
+    const bool full = p.full_problem != 0;
+    if (!full) {
+        if (!finite_pos(p.tau) || !finite_pos(p.sigma)) return fail(DTV_EINVAL, "tau and sigma must be positive");
+        if (p.tau * p.sigma > 0.5 * (1.0 + 1e-12)) return fail(DTV_EINVAL, "tau * sigma must be <= 1/2");
+    }
     if (p.inner == DTV_INNER_CP2) {
         if (!finite_pos(p.tau0) || !finite_pos(p.sigma0)) return fail(DTV_EINVAL, "tau0 and sigma0 must be positive");
         if (8.0 * p.tau0 * p.sigma0 > 1.0 + 1e-12) return fail(DTV_EINVAL, "8 tau0 sigma0 must be <= 1");
-        if (!(p.gamma >= 0.0) || p.gamma > 1.0 / p.tau * (1.0 + 1e-12))
-            return fail(DTV_EINVAL, "gamma must lie in [0, 1/tau]");
+        if (!(p.gamma >= 0.0) || !std::isfinite(p.gamma)) return fail(DTV_EINVAL, "gamma must be finite and >= 0");
+        if (!full && p.gamma > 1.0 / p.tau * (1.0 + 1e-12)) return fail(DTV_EINVAL, "gamma must lie in [0, 1/tau]");
     }
+    if (full && p.save_for_backward) return fail(DTV_EINVAL, "full_problem takes no save_for_backward");
+    if (full)
+        for (int b = 0; b < n_images; ++b)
+            if (imgs[b].ny != 1 || imgs[b].nx != 1) return fail(DTV_EINVAL, "full_problem needs ny = nx = 1");
     if (p.n_outer < 0 || p.n_inner < 1) return fail(DTV_EINVAL, "n_outer must be >= 0 and n_inner >= 1");
     if (p.diag_every < 0) return fail(DTV_EINVAL, "diag_every must be >= 0");
     if (p.gap_tol < 0.0 || !std::isfinite(p.gap_tol)) return fail(DTV_EINVAL, "gap_tol must be finite and >= 0");
-    if (p.gap_tol > 0.0 && (n_images != 1 || p.fidelity != DTV_L2 || p.has_mask || p.diag_every <= 0))
-        return fail(DTV_EINVAL, "gap_tol needs one L2 image without mask and diag_every > 0");
+    if (p.gap_tol > 0.0 && (n_images != 1 || p.fidelity == DTV_L1 || p.has_mask || p.diag_every <= 0))
+        return fail(DTV_EINVAL, "gap_tol needs one L2 or Chan-Vese image without mask and diag_every > 0");
     if (p.save_for_backward && (p.inner != DTV_INNER_FISTA || p.ckpt_every < 1))
         return fail(DTV_EINVAL, "save_for_backward needs FISTA and ckpt_every >= 1");
     if (p.save_for_backward && p.gap_tol > 0.0) return fail(DTV_EINVAL, "save_for_backward needs fixed iteration counts");
@@ -295,7 +308,8 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
     pl->tot_lam = ol;
 
     // device metadata: image descriptors, info words, cuts, work lists
-    const double tau = p.tau;
+    // 1/tau of the local proximal term; 0 for the undecomposed problem
+    pl->inv_tau = full ? 0.0 : 1.0 / p.tau;
     for (int b = 0; b < n_images; ++b) {
         const ImgHost &h = pl->imgs[b];
         ImgDev g{};
@@ -316,14 +330,14 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
         for (int v : h.rcut) pl->h_info.push_back(v);
         g.ccut = (long long)pl->h_info.size();
         for (int v : h.ccut) pl->h_info.push_back(v);
-        const double L = 8.0 / h.alpha + 1.0 / tau;
+        const double L = 8.0 / h.alpha + pl->inv_tau;
         g.alpha = (float)h.alpha;
         g.inv_alpha = (float)(1.0 / h.alpha);
         g.invL = (float)(1.0 / L);
-        g.a_keep = (float)(1.0 - 1.0 / (L * tau));
+        g.a_keep = full ? 1.0f : (float)(1.0 - 1.0 / (L * p.tau));
         g.kL = (float)(1.0 / (h.alpha * L));
         g.dA = 8.0 / ((h.alpha * L) * (h.alpha * L));
-        g.dB = -1.0 / (tau * (h.alpha * L) * (h.alpha * L));
+        g.dB = -pl->inv_tau / ((h.alpha * L) * (h.alpha * L));
         pl->h_imgs.push_back(g);
         for (int ri = 0; ri < kRowChoices; ++ri)
             for (int i0 = 0; i0 < h.H; i0 += 4 << ri)
@@ -495,18 +509,19 @@ static int run_diag(dtv_dd_plan *pl, const float *f, const uint8_t *mask, const 
                     const float *p2, hipStream_t s, double *rows /* n x 4 */, bool *nonfinite)
 {
     HIP_TRY(launch_diag(pl->d_imgs(), pl->n, pl->maxH, pl->maxW, pl->d_info(), p1, p2, f, u, mask,
-                        pl->prm.fidelity, pl->partials(), pl->diag_nblk, pl->dout(), s),
+                        pl->prm.fidelity, pl->prm.cv_c1, pl->prm.cv_c2, pl->partials(), pl->diag_nblk, pl->dout(), s),
             "diagnostics kernels");
     HIP_TRY(hipMemcpyAsync(pl->h_diag, pl->dout(), sizeof(double) * 6 * pl->n, hipMemcpyDeviceToHost, s),
             "diagnostics copy");
     HIP_TRY(hipStreamSynchronize(s), "diagnostics sync");
-    const bool dual_ok = pl->prm.fidelity == DTV_L2 && !pl->prm.has_mask;
+    const bool dual_ok = pl->prm.fidelity != DTV_L1 && !pl->prm.has_mask;
+    const bool cv = pl->prm.fidelity == DTV_CV;
     *nonfinite = false;
     for (int b = 0; b < pl->n; ++b) {
         const double *q = pl->h_diag + 6 * b;
         const double alpha = pl->imgs[b].alpha;
         const double J = alpha * q[0] + q[1];
-        const double D = dual_ok ? -q[2] - q[3] / (2.0 * alpha) : NAN;
+        const double D = !dual_ok ? NAN : (cv ? q[2] : -q[2] - q[3] / (2.0 * alpha));
         rows[4 * b + 0] = J;
         rows[4 * b + 1] = D;
         rows[4 * b + 2] = J - D;
@@ -653,7 +668,7 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
     fa.f = d_f;
     fa.sigma = (float)P.sigma;
     fa.tau = (float)P.tau;
-    fa.inv_tau = (float)(1.0 / P.tau);
+    fa.inv_tau = (float)pl->inv_tau;
     fa.n_inner = std::min(K, kMaxFusedInner);
     for (int k = 1; k <= fa.n_inner; ++k) fa.beta[k] = beta[k];
 
@@ -727,7 +742,7 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
                 a.lam = lam_cur; a.f = d_f;
                 a.c1 = bufs[3].p1; a.c2 = bufs[3].p2;
                 a.out1 = bufs[io].p1; a.out2 = bufs[io].p2;
-                a.beta = beta[k]; a.tau = (float)P.tau; a.inv_tau = (float)(1.0 / P.tau);
+                a.beta = beta[k]; a.tau = (float)P.tau; a.inv_tau = (float)pl->inv_tau;
                 const int mode = k == 1 ? kFistaFirst : (k == 2 ? kFistaPlain : kFistaMomentum);
                 int rc = with_host ? tm.begin() : DTV_OK;
                 if (rc != DTV_OK) return rc;
@@ -755,9 +770,11 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
                 a.out1 = bufs[io].p1; a.out2 = bufs[io].p2;
                 a.theta_prev = it >= 1 ? (float)th[it - 1] : 0.0f;
                 a.sk = (float)sk[it]; a.tk = (float)tk[it]; a.tau = (float)P.tau;
-                a.c_keep = (float)(P.tau / (P.tau + tk[it]));
-                a.c_anchor = (float)(tk[it] / (P.tau + tk[it]));
+                a.c_keep = P.full_problem ? 1.0f : (float)(P.tau / (P.tau + tk[it]));
+                a.c_anchor = P.full_problem ? 0.0f : (float)(tk[it] / (P.tau + tk[it]));
                 a.fidelity = P.fidelity;
+                a.cv_c1 = (float)P.cv_c1;
+                a.cv_c2 = (float)P.cv_c2;
                 int rc = with_host ? tm.begin() : DTV_OK;
                 if (rc != DTV_OK) return rc;
                 HIP_TRY(launch_cp2_step(a, it >= 1, rows, q, with_host ? tm.e0 : nullptr, with_host ? tm.e1 : nullptr),
@@ -886,37 +903,51 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
     };
 
     int n = 0;
-    // ---- autotuner: the first solve of an untuned plan runs its first outer steps in timed chunks
+    // ---- autotuner: the first solve of an untuned plan runs its first outer steps in timed chunks.
+    // A per-step schedule costs its chunk time per step; the persistent launch has a fixed part (loading
+    // and storing every tile) besides its per-step part, so it is timed over chunks of c and 2c steps
+    // and priced as fixed + per-step * (the steps left), the way the rest of the solve would run it.
     if (!pl->tuned && !host_work && P.n_outer > 0) {
         const std::vector<Choice> cands = candidates(pl);
         const int nc = (int)cands.size();
-        const int chunk = std::min(16, P.n_outer / (2 * std::max(nc, 1)) - 1);
+        const int chunk = std::min(16, P.n_outer / (2 * (std::max(nc, 1) + 2)) - 1);
         if (nc > 1 && chunk >= 2) {
             hipEvent_t e0 = nullptr, e1 = nullptr;
             HIP_TRY(hipEventCreate(&e0), "event create");
             HIP_TRY(hipEventCreate(&e1), "event create");
-            double best = 0.0;
-            int bi = -1, rc = DTV_OK;
-            for (int c = 0; c < nc && rc == DTV_OK; ++c) {  // one untimed step each (first use of each kernel)
-                rc = run_range(n, n + 1, cands[c].schedule, cands[c].rows, false);
-                n += 1;
-            }
-            for (int c = 0; c < nc && rc == DTV_OK; ++c) {
+            int rc = DTV_OK;
+            auto time_range = [&](const Choice &ch, int count, double *ms_out) {
                 if (hipEventRecord(e0, s) != hipSuccess) rc = fail(DTV_EHIP, "event record");
-                if (rc == DTV_OK) rc = run_range(n, n + chunk, cands[c].schedule, cands[c].rows, false);
+                if (rc == DTV_OK) rc = run_range(n, n + count, ch.schedule, ch.rows, false);
                 if (rc == DTV_OK && hipEventRecord(e1, s) != hipSuccess) rc = fail(DTV_EHIP, "event record");
                 float ms = 0.0f;
                 if (rc == DTV_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
                     rc = fail(DTV_EHIP, "autotune timing");
-                n += chunk;
-                if (rc == DTV_OK && (bi < 0 || ms < best)) {
-                    best = ms;
-                    bi = c;
+                n += count;
+                *ms_out = ms;
+            };
+            for (int c = 0; c < nc && rc == DTV_OK; ++c) {  // one untimed step each (first use of each kernel)
+                rc = run_range(n, n + 1, cands[c].schedule, cands[c].rows, false);
+                n += 1;
+            }
+            std::vector<double> fixed(nc, 0.0), per_step(nc, 0.0);
+            for (int c = 0; c < nc && rc == DTV_OK; ++c) {
+                double t1 = 0.0, t2 = 0.0;
+                time_range(cands[c], chunk, &t1);
+                per_step[c] = t1 / chunk;
+                if (rc == DTV_OK && cands[c].schedule == DTV_SCHED_PERSIST) {
+                    time_range(cands[c], 2 * chunk, &t2);
+                    per_step[c] = std::max((t2 - t1) / chunk, 0.25 * t2 / (2 * chunk));
+                    fixed[c] = std::max(t1 - per_step[c] * chunk, 0.0);
                 }
             }
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);
             if (rc != DTV_OK) return rc;
+            const double left = std::max(P.n_outer - n, 1);
+            int bi = 0;
+            for (int c = 1; c < nc; ++c)
+                if (fixed[c] + per_step[c] * left < fixed[bi] + per_step[bi] * left) bi = c;
             pl->schedule = cands[bi].schedule;
             pl->rows = cands[bi].rows;
             pl->tuned = true;
@@ -995,7 +1026,7 @@ static int rec_outer(dtv_dd_plan *pl, const float *state, const float *d_f, bool
             a.z1 = pl->zrec(k - 1);
             a.z2 = pl->zrec(k - 1) + pl->tot_p1;
         }
-        a.beta = beta[k]; a.tau = (float)P.tau; a.inv_tau = (float)(1.0 / P.tau);
+        a.beta = beta[k]; a.tau = (float)P.tau; a.inv_tau = (float)pl->inv_tau;
         const int mode = k == 1 ? kFistaFirst : (k == 2 ? kFistaPlain : kFistaMomentum);
         HIP_TRY(launch_fista_step(a, mode, rows, s), "FISTA step (recompute)");
     }
@@ -1019,7 +1050,7 @@ static int backward_fused(dtv_dd_plan *pl, const float *d_f, float *d_grad_f, fl
     fa.f = d_f;
     fa.sigma = (float)P.sigma;
     fa.tau = (float)P.tau;
-    fa.inv_tau = (float)(1.0 / P.tau);
+    fa.inv_tau = (float)pl->inv_tau;
     fa.n_inner = K;
     for (int k = 1; k <= K; ++k) fa.beta[k] = beta[k];
     FusedBwdArgs ba{};
@@ -1035,7 +1066,7 @@ static int backward_fused(dtv_dd_plan *pl, const float *d_f, float *d_grad_f, fl
     ba.gf = d_grad_f;
     ba.galpha = pl->gsub();
     ba.tau = (float)P.tau;
-    ba.inv_tau = (float)(1.0 / P.tau);
+    ba.inv_tau = (float)pl->inv_tau;
     ba.n_inner = K;
     for (int k = 1; k <= K; ++k) ba.beta[k] = beta[k];
     // one outer step of the fused forward from a state (p~, lambda state) to p~ out, lambda state out
@@ -1141,7 +1172,7 @@ extern "C" int dtv_dd_backward(dtv_dd_plan *pl, const float *d_f, const float *d
                 a.gb1 = pl->xb((k + 1) % 3); a.gb2 = pl->xb((k + 1) % 3) + pl->tot_p1;
                 a.gh1 = pl->hb(); a.gh2 = pl->hb() + pl->tot_p1;
                 a.gf = d_grad_f; a.galpha = pl->galpha();
-                a.beta = beta[k]; a.tau = (float)P.tau; a.inv_tau = (float)(1.0 / P.tau);
+                a.beta = beta[k]; a.tau = (float)P.tau; a.inv_tau = (float)pl->inv_tau;
                 HIP_TRY(launch_fista_bwd_step(a, k >= 3, rows, s), "FISTA reverse step");
                 // xbar_k is consumed; its buffer becomes xbar_{k-3}
                 if (k >= 3) HIP_TRY(hipMemsetAsync(pl->xb(k % 3), 0, sizeof(float) * E, s), "clear");

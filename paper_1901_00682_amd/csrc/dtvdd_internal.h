@@ -141,8 +141,9 @@ struct Cp2StepArgs {
     float sk;                 // sigma_k
     float tk;                 // tau_k
     float tau;                // outer tau
-    float c_keep, c_anchor;   // tau/(tau+tau_k), tau_k/(tau+tau_k)
-    int fidelity;
+    float c_keep, c_anchor;   // tau/(tau+tau_k), tau_k/(tau+tau_k) (1 and 0 without the proximal term)
+    int fidelity;             // 0 L2, 1 L1, 2 convex Chan-Vese
+    float cv_c1, cv_c2;       // Chan-Vese intensities
 };
 
 // Kernel launchers (kernels.hip).
@@ -158,9 +159,11 @@ hipError_t launch_u_from_p(const ImgDev *imgs, int nimg, int maxH, int maxW, con
 hipError_t launch_zero_boundary(const ImgDev *imgs, int nimg, int maxH, int maxW, float *p1, float *p2,
                                 hipStream_t s);
 // FP64 diagnostics: per image 6 partial sums reduced into out[img*6 + q]:
-// q = 0 fidelity sum, 1 TV, 2 <f, div p_avg>, 3 |div p_avg|^2, 4 |B p|^2, 5 non-finite count.
+// q = 0 fidelity sum, 1 TV, 2 <f, div p_avg> (Chan-Vese: sum of min(0, alpha g - div p_avg)),
+// 3 |div p_avg|^2, 4 |B p|^2, 5 non-finite count.
 hipError_t launch_diag(const ImgDev *imgs, int nimg, int maxH, int maxW, const int *info, const float *p1,
                        const float *p2, const float *f, const float *u, const uint8_t *mask, int fidelity,
+                       double cv_c1, double cv_c2,
                        double *partials, int nblk_per_img, double *out, hipStream_t s);
 int diag_blocks_per_image(int maxH, int maxW);
 // Persistent schedule: every outer step in one cooperative launch (persist.hip).

@@ -247,10 +247,19 @@ hipError_t launch_fista_step(const FistaStepArgs &a, int mode, int rows, hipStre
 //   xbar = x_{k-1} + theta_prev (x_{k-1} - x_{k-2})
 //   u_k  = prox_{sigma_k alpha F}(u_{k-1} + sigma_k div_s xbar)   (per pixel)
 //   x_k  = clamp((tau (x_{k-1} - tau_k div_s^* u_k) + tau_k phat) / (tau + tau_k))
-__device__ __forceinline__ float prox_fid(int fidelity, float z, float fv, bool observed, float a)
+// prox of a F at one pixel: L2 (z + a f)/(1 + a); L1 f + shr(z - f, a), eq.
+// (shrinkage); convex Chan-Vese (Sec. 3, segmentation) the projection of z - a g
+// onto [0, 1], with g = (f - c1)^2 - (f - c2)^2 evaluated as (c2 - c1)((f - c1) + (f - c2)),
+// the same value without the cancellation of two squares.
+__device__ __forceinline__ float prox_fid(int fidelity, float z, float fv, bool observed, float a, float c1,
+                                          float c2)
 {
     if (!observed) return z;
     if (fidelity == 0) return (z + a * fv) / (1.0f + a);
+    if (fidelity == 2) {
+        const float g = (c2 - c1) * ((fv - c1) + (fv - c2));
+        return fminf(fmaxf(fmaf(-a, g, z), 0.0f), 1.0f);
+    }
     const float d = z - fv;
     const float mag = fmaxf(fabsf(d) - a, 0.0f);
     return d > 0.0f ? fv + mag : (d < 0.0f ? fv - mag : fv);
@@ -285,6 +294,7 @@ __global__ __launch_bounds__(64) void k_cp2_step(Cp2StepArgs a)
     const float th = a.theta_prev, sk = a.sk, tk = a.tk, tau = a.tau;
     const float ck = a.c_keep, ca = a.c_anchor, sa = a.sk * im.alpha;
     const int fid = a.fidelity;
+    const float cv1 = a.cv_c1, cv2 = a.cv_c2;
 
     auto xbar1 = [&](long long idx, float &x) -> float {
         x = xa1[idx];
@@ -299,7 +309,7 @@ __global__ __launch_bounds__(64) void k_cp2_step(Cp2StepArgs a)
     auto unew = [&](int i, float xt, float xb, float xl, float xr) -> float {
         const long long px = (long long)i * W + j;
         const float d = (xb - xt) + (xr - xl);
-        return prox_fid(fid, fmaf(sk, d, uin[px]), f[px], mk ? mk[px] != 0 : true, sa);
+        return prox_fid(fid, fmaf(sk, d, uin[px]), f[px], mk ? mk[px] != 0 : true, sa, cv1, cv2);
     };
     auto pupdate = [&](float x, float du, float anchor) -> float {
         const float pbar = fmaf(-tk, du, x);  // x - tau_k div^* u
@@ -451,8 +461,8 @@ hipError_t launch_zero_boundary(const ImgDev *imgs, int nimg, int maxH, int maxW
 // (a5) FP64 diagnostics.  Per pixel, in double precision:
 //   fidelity term, TV terms |u(i+1,j) - u(i,j)| + |u(i,j+1) - u(i,j)|,
 //   d = div p_avg (interface dofs averaged over their two copies),
-//   f d and d^2, and |p_s - p_t|^2 for the interface edges below / right of
-//   the pixel.  Fixed-order reductions (wave shuffles, then a fixed tree), so
+//   f d and d^2 (Chan-Vese: min(0, alpha g - d), the pixel's share of the dual
+//   value), and |p_s - p_t|^2 for the interface edges below / right of the pixel.  Fixed-order reductions (wave shuffles, then a fixed tree), so
 //   results are bitwise reproducible.
 constexpr int kDiagRows = 32;  // rows per diagnostics block (4 rows per pass, 8 passes)
 
@@ -466,7 +476,8 @@ __device__ __forceinline__ double wave_sum(double x)
 
 __global__ __launch_bounds__(256) void k_diag(const ImgDev *imgs, const int *info, const float *p1,
                                               const float *p2, const float *f, const float *u,
-                                              const uint8_t *mask, int fidelity, double *partials)
+                                              const uint8_t *mask, int fidelity, double cv_c1, double cv_c2,
+                                              double *partials)
 {
     const ImgDev im = imgs[blockIdx.z];
     const int j = blockIdx.x * 64 + (threadIdx.x & 63);
@@ -482,7 +493,10 @@ __global__ __launch_bounds__(256) void k_diag(const ImgDev *imgs, const int *inf
         const long long px = im.px + (long long)i * W + j;
         const double uv = u[px], fv = f[px];
         const bool obs = mask ? mask[px] != 0 : true;
-        if (obs) {
+        const double g = (fv - cv_c1) * (fv - cv_c1) - (fv - cv_c2) * (fv - cv_c2);
+        if (fidelity == 2) {
+            acc[0] += uv * g;
+        } else if (obs) {
             const double d = uv - fv;
             acc[0] += fidelity == 0 ? 0.5 * d * d : fabs(d);
         }
@@ -504,7 +518,7 @@ __global__ __launch_bounds__(256) void k_diag(const ImgDev *imgs, const int *inf
             er = 0.5 * (er + t);
         }
         const double d = (eb - et) + (er - el);
-        acc[2] += fv * d;
+        acc[2] += fidelity == 2 ? fmin(0.0, (double)im.alpha * g - d) : fv * d;
         acc[3] += d * d;
         if (!isfinite(uv) || !isfinite(et) || !isfinite(el) || !isfinite(eb) || !isfinite(er)) acc[5] += 1.0;
     }
@@ -545,10 +559,11 @@ __global__ __launch_bounds__(256) void k_diag_final(const double *partials, int 
 
 hipError_t launch_diag(const ImgDev *imgs, int nimg, int maxH, int maxW, const int *info, const float *p1,
                        const float *p2, const float *f, const float *u, const uint8_t *mask, int fidelity,
-                       double *partials, int nblk_per_img, double *out, hipStream_t s)
+                       double cv_c1, double cv_c2, double *partials, int nblk_per_img, double *out, hipStream_t s)
 {
     dim3 grid((maxW + 63) / 64, (maxH + kDiagRows - 1) / kDiagRows, nimg);
-    hipLaunchKernelGGL(k_diag, grid, dim3(256), 0, s, imgs, info, p1, p2, f, u, mask, fidelity, partials);
+    hipLaunchKernelGGL(k_diag, grid, dim3(256), 0, s, imgs, info, p1, p2, f, u, mask, fidelity, cv_c1, cv_c2,
+                       partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_diag_final, dim3(nimg), dim3(256), 0, s, partials, nblk_per_img, out);

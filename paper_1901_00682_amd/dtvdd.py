@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "_build", "libdtvdd.so")
 
 DTV_OK, DTV_EINVAL, DTV_ENOWS, DTV_EHIP, DTV_ESTATE, DTV_ENONFINITE = 0, -1, -2, -3, -4, -5
-FIDELITY = {"L2": 0, "L1": 1}
+FIDELITY = {"L2": 0, "L1": 1, "CV": 2}
 INNER = {"FISTA": 0, "CP2": 1}
 SCHEDULE = {"auto": 0, "stream": 1, "fused": 2, "persistent": 3}
 SCHEDULE_NAME = {v: k for k, v in SCHEDULE.items()}
@@ -50,7 +50,8 @@ class Params(ctypes.Structure):
                 ("gap_tol", ctypes.c_double), ("warm_start", ctypes.c_int32),
                 ("save_for_backward", ctypes.c_int32), ("ckpt_every", ctypes.c_int32),
                 ("schedule", ctypes.c_int32), ("time_kernels", ctypes.c_int32), ("rows", ctypes.c_int32),
-                ("no_graphs", ctypes.c_int32)]
+                ("no_graphs", ctypes.c_int32), ("cv_c1", ctypes.c_double), ("cv_c2", ctypes.c_double),
+                ("full_problem", ctypes.c_int32)]
 
 
 class Layout(ctypes.Structure):
@@ -125,7 +126,8 @@ class Plan:
     def __init__(self, images, *, fidelity="L2", inner=None, has_mask=False, tau=50.0, sigma=0.01, tau0=10.0,
                  sigma0=1.0 / 80.0, gamma=None, n_outer=100, n_inner=10, diag_every=0, gap_tol=0.0,
                  warm_start=False, save_for_backward=False, ckpt_every=20, schedule="auto",
-                 time_kernels=False, rows=0, graphs=True, device=None, bind=True):
+                 time_kernels=False, rows=0, graphs=True, c1=0.6, c2=0.1, full_problem=False, device=None,
+                 bind=True):
         import torch
 
         L = lib()
@@ -148,7 +150,7 @@ class Plan:
                              float(tau0), float(sigma0), float(gamma), int(n_outer), int(n_inner),
                              int(diag_every), float(gap_tol), int(warm_start), int(save_for_backward),
                              int(ckpt_every), SCHEDULE[schedule], int(time_kernels), int(rows),
-                             int(not graphs))
+                             int(not graphs), float(c1), float(c2), int(full_problem))
         h = ctypes.c_void_p()
         _check(L.dtv_dd_setup(descs, len(self.images), ctypes.byref(self.params), ctypes.byref(h)))
         self.h = h

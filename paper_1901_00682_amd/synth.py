@@ -193,3 +193,17 @@ def config5(n_images: int = 16, size: int = 512, grid: int = 4, n_outer: int = 2
         cases.append(Case(f"diff{b}", f, 8.0, floor_cuts(size, grid), floor_cuts(size, grid),
                           clean=clean.astype(np.float32), n_outer=n_outer, n_inner=5))
     return cases
+
+
+def cv_case(size: int = 2048, tile: int = 128, n_outer: int = 500, n_inner: int = 5) -> Case:
+    """Convex Chan-Vese segmentation (stand-in for the 2048 x 2048 test image of
+    the segmentation experiment): the piecewise-constant shapes image plus noise
+    sd 0.05, subdomains of `tile` x `tile`, alpha 10, c1 = 0.6, c2 = 0.1, outer
+    tau = 1, tau sigma = 1/2, local primal-dual tau0 = 10, tau0 sigma0 = 1/8,
+    gamma = 1/(8 tau)."""
+    k = size // tile
+    clean = shapes(size, size, rng_for(6, IMAGE))
+    f = (clean + gaussian((size, size), 0.05, rng_for(6, NOISE))).astype(np.float32)
+    return Case(f"cv{size}_{k}x{k}", f, 10.0, floor_cuts(size, k), floor_cuts(size, k), fidelity="CV",
+                inner="CP2", clean=clean.astype(np.float32), n_outer=n_outer, n_inner=n_inner, tau=1.0,
+                sigma=0.5, gamma=1.0 / 8.0, extra={"c1": 0.6, "c2": 0.1})

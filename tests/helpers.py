@@ -16,10 +16,10 @@ def rel_l2(a, b) -> float:
 
 
 def oracle_for(f32, alpha, row_cuts, col_cuts, *, fidelity="L2", inner="FISTA", mask=None, tau=50.0,
-               sigma=0.01, tau0=10.0, sigma0=1 / 80, gamma=None, n_inner=10):
+               sigma=0.01, tau0=10.0, sigma0=1 / 80, gamma=None, n_inner=10, **kw):
     return oracle.Oracle(oracle.Problem(np.asarray(f32, dtype=np.float64), float(alpha), np.asarray(row_cuts),
                                         np.asarray(col_cuts), fidelity=fidelity, inner=inner, mask=mask, tau=tau,
-                                        sigma=sigma, tau0=tau0, sigma0=sigma0, gamma=gamma, n_inner=n_inner))
+                                        sigma=sigma, tau0=tau0, sigma0=sigma0, gamma=gamma, n_inner=n_inner, **kw))
 
 
 def gpu_image_state(plan, state, image=0):

@@ -86,11 +86,31 @@ def test_valid_setup_and_layout():
     (dict(rows=5), "rows"),
     (dict(no_graphs=2), "no_graphs"),
     (dict(schedule=3), "persistent"),
+    (dict(fidelity=2), "FISTA"),
+    (dict(fidelity=2, inner=1, has_mask=1), "Chan-Vese"),
+    (dict(fidelity=2, inner=1, cv_c1=float("inf")), "cv_c1"),
+    (dict(full_problem=1), "full_problem needs"),
+    (dict(full_problem=2), "full_problem must"),
+    (dict(full_problem=1, rc=(0, 64), cc=(0, 64), save_for_backward=1), "save_for_backward"),
+    (dict(full_problem=1, rc=(0, 64), cc=(0, 64), inner=1, gamma=-1.0), "gamma"),
 ])
 def test_validation_errors(kw, msg):
     code, h = _setup(**kw)
     assert code == dtvdd.DTV_EINVAL
     assert msg in dtvdd.lib().dtv_last_error().decode()
+
+
+@pytest.mark.parametrize("kw", [
+    dict(fidelity=2, inner=1, tau=1.0, sigma=0.5, gamma=0.125, cv_c1=0.6, cv_c2=0.1),
+    dict(fidelity=2, inner=1, tau=1.0, sigma=0.5, gamma=0.125, gap_tol=1e-4, diag_every=5),
+    # the undecomposed problem ignores tau and sigma, and gamma has no 1/tau bound
+    dict(full_problem=1, rc=(0, 64), cc=(0, 64), tau=0.0, sigma=0.0),
+    dict(full_problem=1, rc=(0, 64), cc=(0, 64), inner=1, fidelity=1, tau=0.0, sigma=0.0, gamma=5.0),
+])
+def test_valid_chan_vese_and_full_problem(kw):
+    code, h = _setup(**kw)
+    assert code == 0, dtvdd.lib().dtv_last_error().decode()
+    dtvdd.lib().dtv_dd_destroy(h)
 
 
 def test_solve_rejects_missing_workspace_and_nulls():
