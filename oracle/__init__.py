@@ -54,6 +54,7 @@ class _Params(ctypes.Structure):
         ("tau0", ctypes.c_double), ("sigma0", ctypes.c_double), ("gamma", ctypes.c_double),
         ("n_inner", ctypes.c_int),
         ("cv_c1", ctypes.c_double), ("cv_c2", ctypes.c_double),
+        ("inner_tol", ctypes.c_double),
     ]
 
 
@@ -94,6 +95,9 @@ def load(path: str = LIB_PATH):
     lib.orc_n_done.restype = ctypes.c_int
     lib.orc_n_done.argtypes = [vp]
     lib.orc_threads.restype = ctypes.c_int
+    lib.orc_inner_counts.argtypes = [vp, _L]
+    lib.orc_inner_margin.restype = ctypes.c_double
+    lib.orc_inner_margin.argtypes = [vp]
     if hasattr(lib, "orc_backward"):
         lib.orc_backward.restype = ctypes.c_int
         lib.orc_backward.argtypes = [vp, ctypes.c_int, _D, _U8, _D, _D, _D]
@@ -134,6 +138,7 @@ class Problem:
     no_prox_term: bool = False
     c1: float = 0.6              # Chan-Vese intensities (fidelity "CV"), eq. (CCV)
     c2: float = 0.1
+    inner_tol: float = 0.0       # > 0: inner stopping rule of Sec. 6 (FISTA), n_inner is the cap
 
 
 class Oracle:
@@ -154,7 +159,7 @@ class Oracle:
         self.params = _Params(H, W, self.ny, self.nx, float(prob.alpha), FIDELITY[prob.fidelity],
                               INNER[prob.inner], int(prob.no_prox_term), float(prob.tau), float(prob.sigma),
                               float(prob.tau0), float(prob.sigma0), float(gamma), int(prob.n_inner),
-                              float(prob.c1), float(prob.c2))
+                              float(prob.c1), float(prob.c2), float(prob.inner_tol))
         self.f = f
         self.mask = None if prob.mask is None else np.ascontiguousarray(prob.mask, dtype=np.uint8)
         self._mp = None if self.mask is None else self.mask.ctypes.data_as(_U8)
@@ -184,6 +189,17 @@ class Oracle:
         got = self.lib.orc_run(self.h, int(n_outer), op, int(diag_every), _dp(self.f), self._mp,
                                _dp(stats), rows)
         return stats[:got]
+
+    def inner_counts(self) -> np.ndarray:
+        """[n_subdomains, 2] local steps (total, most in one outer step), row-major."""
+        out = np.zeros(2 * self.ny * self.nx, dtype=np.int64)
+        self.lib.orc_inner_counts(self.h, out.ctypes.data_as(_L))
+        return out.reshape(-1, 2)
+
+    def inner_margin(self) -> float:
+        """Smallest |log(relative change^2 / tol^2)| over every stopping test so
+        far: how close any decision came to the threshold."""
+        return float(self.lib.orc_inner_margin(self.h))
 
     @property
     def n_done(self) -> int:

@@ -47,6 +47,10 @@ typedef struct {
     int n_inner;                /* local iterations per outer step */
     double cv_c1, cv_c2;        /* ORC_CV: the two intensities of the convex
                                    Chan-Vese model, eq. (CCV) */
+    double inner_tol;           /* > 0 (FISTA): stop a local solve once the
+                                   relative change of its iterate falls below
+                                   inner_tol (the inner stopping rule of Sec. 6);
+                                   n_inner is then the cap */
 } orc_params;
 
 typedef struct {
@@ -58,6 +62,10 @@ typedef struct {
     double *f;           /* local data */
     unsigned char *m;    /* 1 = observed pixel, 0 = pixel in the inpainting set D */
     double *h1, *h2;     /* proximal anchor phat restricted to the subdomain */
+    long steps_total;    /* local steps taken over all outer steps */
+    int steps_max;       /* most local steps in one outer step */
+    double margin;       /* smallest |log(dsq / (tol^2 nsq))| over the stopping tests so far
+                            (how far every decision was from the threshold; test aid) */
     /* work arrays of the local solvers */
     double *a1, *a2, *b1, *b2, *v, *q1, *q2;
 } orc_sub;
@@ -197,6 +205,7 @@ static void local_fista(const orc_state *st, orc_sub *S)
     memcpy(y1, x1, sizeof(double) * n1);
     memcpy(y2, x2, sizeof(double) * n2);
     double t = 1.0;
+    int taken = 0;
     for (int it = 0; it < P->n_inner; it++) {
         div_local(S, y1, y2, S->v);
         for (int i = 0; i < h * w; i++) S->v[i] = S->f[i] + S->v[i] / P->alpha;
@@ -219,6 +228,17 @@ static void local_fista(const orc_state *st, orc_sub *S)
             if (!dof2(st, S, 0)) z2[y * (w + 1)] = 0.0;
             if (!dof2(st, S, w)) z2[y * (w + 1) + w] = 0.0;
         }
+        /* relative change of the local iterate, |x_{k+1} - x_k|_2 / |x_{k+1}|_2,
+           over every dof of the subdomain (Sec. 6, inner stopping rule) */
+        double dsq = 0.0, nsq = 0.0;
+        for (int e = 0; e < n1; e++) {
+            dsq += (z1[e] - x1[e]) * (z1[e] - x1[e]);
+            nsq += z1[e] * z1[e];
+        }
+        for (int e = 0; e < n2; e++) {
+            dsq += (z2[e] - x2[e]) * (z2[e] - x2[e]);
+            nsq += z2[e] * z2[e];
+        }
         double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
         double beta = (t - 1.0) / tn;
         for (int e = 0; e < n1; e++) {
@@ -230,7 +250,18 @@ static void local_fista(const orc_state *st, orc_sub *S)
             x2[e] = z2[e];
         }
         t = tn;
+        taken = it + 1;
+        if (P->inner_tol > 0.0 && taken < P->n_inner) {
+            double thr = P->inner_tol * P->inner_tol * nsq;
+            if (dsq > 0.0 && thr > 0.0) {
+                double m = fabs(log(dsq / thr));
+                if (m < S->margin) S->margin = m;
+            }
+            if (dsq == 0.0 || dsq < thr) break;
+        }
     }
+    S->steps_total += taken;
+    if (taken > S->steps_max) S->steps_max = taken;
     /* primal recovery for ROF: u_s = f_s + div_s p_s / alpha (Sec. 4) */
     div_local(S, x1, x2, S->v);
     for (int i = 0; i < h * w; i++) S->u[i] = S->f[i] + S->v[i] / P->alpha;
@@ -352,6 +383,7 @@ orc_state *orc_create(const orc_params *prm, const int *row_cuts, const int *col
             S->b1 = dalloc(n1); S->b2 = dalloc(n2);
             S->q1 = dalloc(n1); S->q2 = dalloc(n2);
             S->u = dalloc(np); S->f = dalloc(np); S->v = dalloc(np);
+            S->margin = INFINITY;
             S->m = (unsigned char *)malloc(np ? np : 1);
             for (int y = 0; y < S->h; y++)
                 for (int x = 0; x < S->w; x++) {
@@ -819,6 +851,23 @@ void orc_prox(int fidelity, long n, const double *z, const double *f, const unsi
 }
 
 int orc_n_done(const orc_state *st) { return st->n_done; }
+
+/* Local steps per subdomain (row-major over the grid): out[2 s] = total over
+   all outer steps run so far, out[2 s + 1] = most in one outer step. */
+double orc_inner_margin(const orc_state *st)
+{
+    double m = INFINITY;
+    for (int s = 0; s < st->nsub; s++) m = fmin(m, st->sub[s].margin);
+    return m;
+}
+
+void orc_inner_counts(const orc_state *st, long *out)
+{
+    for (int s = 0; s < st->nsub; s++) {
+        out[2 * s] = st->sub[s].steps_total;
+        out[2 * s + 1] = st->sub[s].steps_max;
+    }
+}
 
 #ifdef _OPENMP
 #include <omp.h>
