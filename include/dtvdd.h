@@ -148,6 +148,14 @@ typedef struct {
                                   gamma >= 0; each outer step restarts it from the current
                                   iterate (n_outer = 1: n_inner plain iterations); no
                                   save_for_backward */
+    double inner_tol;          /* > 0: adaptive local solves (Sec. 6 stops them by relative change):
+                                  each subdomain stops its FISTA steps in an outer step after the
+                                  first step k with |p_k - p_(k-1)|_2 < inner_tol |p_k|_2 over its
+                                  own edge dofs (or p_k = p_(k-1)), at most n_inner (the cap, <=
+                                  100000) steps; the norms are summed in FP64.  FISTA with the
+                                  fused schedule (or auto, which then takes it) only: every
+                                  subdomain at most 128 x 128, no save_for_backward.  0: fixed
+                                  n_inner steps */
 } dtv_dd_params;
 
 /* Where image `image` lives in the concatenated buffers (element offsets). */
@@ -220,6 +228,14 @@ int dtv_dd_schedule(const dtv_dd_plan *plan, int32_t *schedule);
    plan's first solve, 2 = taken from the process-wide cache of an earlier
    plan with the same shape, 3 = set explicitly in dtv_dd_params. */
 int dtv_dd_choice(const dtv_dd_plan *plan, int32_t *schedule, int32_t *rows, int32_t *source);
+
+/* Local steps of every subdomain in the last solve: h_counts receives 2
+   int32 per subdomain, [total over the outer steps, most in one outer step],
+   image-major and row-major over each image's subdomain grid (n_outer *
+   n_inner and n_inner without inner_tol; zeros before the first solve).
+   With inner_tol it reads them from the device: stream-ordered on `stream`,
+   returns after they arrive. */
+int dtv_dd_inner_counts(dtv_dd_plan *plan, int32_t *h_counts, void *stream);
 
 void dtv_dd_destroy(dtv_dd_plan *plan);
 

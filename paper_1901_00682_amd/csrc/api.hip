@@ -120,6 +120,10 @@ struct dtv_dd_plan {
     size_t off_ckpt = 0, off_seg = 0, off_xrec = 0, off_zrec = 0, off_lam1 = 0, off_xb = 0, off_hb = 0, off_pb = 0,
            off_lb = 0, off_galpha = 0, off_frec = 0, off_gsub = 0;
     bool fbwd = false;        // reverse mode with the fused kernels (every subdomain 128 x 128)
+    bool adaptive = false;    // inner_tol > 0: the fused kernel stops each local solve by the relative-change rule
+    size_t off_beta = 0, off_counts = 0;  // adaptive: momentum table, per-subdomain step counts
+    int last_outer = 0;       // outer steps run by the last solve
+    bool solved = false;      // a solve has run
     bool saved = false;       // the last solve saved its checkpoints
     int saved_outer = 0;      // outer steps of that solve
 
@@ -162,6 +166,8 @@ struct dtv_dd_plan {
     unsigned long long *xch() const { return (unsigned long long *)(ws + off_xch); }
     float *lamw() const { return (float *)(ws + off_lamw); }  // second lambda state (fused schedule)
     unsigned *sync_words() const { return (unsigned *)(ws + off_sync); }  // error flag of the persistent kernel
+    float *beta_tab() const { return (float *)(ws + off_beta); }
+    int *counts() const { return (int *)(ws + off_counts); }
 };
 
 // ---------------------------------------------------------------------------
@@ -190,6 +196,7 @@ static std::vector<Choice> candidates(const dtv_dd_plan *pl)
 {
     const dtv_dd_params &p = pl->prm;
     std::vector<Choice> c;
+    if (pl->adaptive) return {{DTV_SCHED_FUSED, pl->rows}};  // the stopping rule lives in the fused kernel
     const bool any = p.schedule == DTV_SCHED_AUTO;
     if ((any || p.schedule == DTV_SCHED_PERSIST) && pl->persist_ok) c.push_back({DTV_SCHED_PERSIST, pl->rows});
     if ((any || p.schedule == DTV_SCHED_FUSED) && pl->fused_ok) c.push_back({DTV_SCHED_FUSED, pl->rows});
@@ -247,6 +254,12 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
         if (!full && p.gamma > 1.0 / p.tau * (1.0 + 1e-12)) return fail(DTV_EINVAL, "gamma must lie in [0, 1/tau]");
     }
     if (full && p.save_for_backward) return fail(DTV_EINVAL, "full_problem takes no save_for_backward");
+    if (!(p.inner_tol >= 0.0) || !std::isfinite(p.inner_tol)) return fail(DTV_EINVAL, "inner_tol must be finite and >= 0");
+    if (p.inner_tol > 0.0 && (p.inner != DTV_INNER_FISTA || p.save_for_backward ||
+                              (p.schedule != DTV_SCHED_AUTO && p.schedule != DTV_SCHED_FUSED)))
+        return fail(DTV_EINVAL, "inner_tol needs FISTA, the fused schedule (or auto) and no save_for_backward");
+    if (p.inner_tol > 0.0 && p.n_inner > kMaxAdaptiveInner)
+        return fail(DTV_EINVAL, "inner_tol: n_inner (the cap) must be <= 100000");
     if (full)
         for (int b = 0; b < n_images; ++b)
             if (imgs[b].ny != 1 || imgs[b].nx != 1) return fail(DTV_EINVAL, "full_problem needs ny = nx = 1");
@@ -351,16 +364,22 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
     std::stable_partition(pl->h_subs.begin(), pl->h_subs.end(),
                           [](const SubTile &st) { return st.h == kFusedMax && st.w == kFusedMax; });
     for (const SubTile &st : pl->h_subs) pl->n_full += st.h == kFusedMax && st.w == kFusedMax;
-    pl->fused_ok = p.inner == DTV_INNER_FISTA && p.n_inner <= kMaxFusedInner;
+    pl->adaptive = p.inner_tol > 0.0;
+    pl->fused_ok = p.inner == DTV_INNER_FISTA && (p.n_inner <= kMaxFusedInner || pl->adaptive);
     for (const SubTile &st : pl->h_subs)
         if (st.h > kFusedMax || st.w > kFusedMax) pl->fused_ok = false;
+    if (pl->adaptive && !pl->fused_ok) {
+        delete pl;
+        return fail(DTV_EINVAL, "inner_tol needs subdomains of at most 128 x 128 (the fused schedule)");
+    }
     if (p.schedule == DTV_SCHED_FUSED && !pl->fused_ok) {
         delete pl;
         return fail(DTV_EINVAL, "the fused schedule needs FISTA, n_inner <= 64 and subdomains of at most 128 x 128");
     }
     {
         const int nsub = (int)pl->h_subs.size();
-        pl->persist_ok = pl->fused_ok && nsub > 0 && pl->n_full == nsub && p.diag_every == 0 && !p.save_for_backward;
+        pl->persist_ok = pl->fused_ok && nsub > 0 && pl->n_full == nsub && p.diag_every == 0 && !p.save_for_backward &&
+                         !pl->adaptive;
         int dev = 0;
         if (pl->persist_ok && hipGetDevice(&dev) == hipSuccess)
             pl->persist_ok = persist_supported(dev) && nsub <= persist_capacity(dev);
@@ -392,6 +411,8 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
     pl->off_xch = take(pl->persist_ok ? sizeof(unsigned long long) * 2 * (size_t)pl->tot_lam : 0);
     pl->off_sync = take(2 * sizeof(unsigned));
     pl->off_lamw = take(sizeof(float) * (size_t)pl->tot_lam);
+    pl->off_beta = take(pl->adaptive ? sizeof(float) * (size_t)(p.n_inner + 1) : 0);
+    pl->off_counts = take(pl->adaptive ? sizeof(int) * 2 * pl->h_subs.size() : 0);
     if (p.save_for_backward) {
         const size_t E = (size_t)(pl->tot_p1 + pl->tot_p2);
         pl->state_floats = E + (size_t)pl->tot_lam;
@@ -467,6 +488,8 @@ extern "C" int dtv_dd_workspace_bytes(const dtv_dd_plan *pl, size_t *bytes)
     return DTV_OK;
 }
 
+static std::vector<float> fista_betas(int K);
+
 extern "C" int dtv_dd_bind_workspace(dtv_dd_plan *pl, void *d_ws, size_t bytes)
 {
     if (!pl || !d_ws) return fail(DTV_EINVAL, "null argument");
@@ -477,6 +500,11 @@ extern "C" int dtv_dd_bind_workspace(dtv_dd_plan *pl, void *d_ws, size_t bytes)
             "upload image descriptors");
     HIP_TRY(hipMemcpy(ws + pl->off_info, pl->h_info.data(), sizeof(int) * pl->h_info.size(), hipMemcpyHostToDevice),
             "upload info words");
+    if (pl->adaptive) {
+        const std::vector<float> beta = fista_betas(pl->prm.n_inner);
+        HIP_TRY(hipMemcpy(ws + pl->off_beta, beta.data(), sizeof(float) * beta.size(), hipMemcpyHostToDevice),
+                "upload momentum table");
+    }
     for (int ri = 0; ri < kRowChoices; ++ri)
         HIP_TRY(hipMemcpy(ws + pl->off_tiles[ri], pl->h_tiles[ri].data(), sizeof(StreamTile) * pl->h_tiles[ri].size(),
                           hipMemcpyHostToDevice),
@@ -671,6 +699,14 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
     fa.inv_tau = (float)pl->inv_tau;
     fa.n_inner = std::min(K, kMaxFusedInner);
     for (int k = 1; k <= fa.n_inner; ++k) fa.beta[k] = beta[k];
+    if (pl->adaptive) {
+        fa.n_inner = K;
+        fa.tol2 = P.inner_tol * P.inner_tol;
+        fa.beta_dev = pl->beta_tab();
+        fa.counts = pl->counts();
+        HIP_TRY(hipMemsetAsync(pl->counts(), 0, sizeof(int) * 2 * pl->h_subs.size(), s), "clear step counts");
+    }
+    int stop_at = P.n_outer;
 
     auto emit_stats = [&](int step, const float *u, const EdgeBuf &b) -> int {
         bool nf = false;
@@ -796,7 +832,10 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
             }
             int rc = emit_stats(n + 1, u, bufs[base]);
             if (rc != DTV_OK) return rc;
-            if (P.gap_tol > 0.0 && drow[2] <= P.gap_tol * std::fabs(drow[0])) stop = true;
+            if (P.gap_tol > 0.0 && drow[2] <= P.gap_tol * std::fabs(drow[0])) {
+                stop = true;
+                stop_at = n + 1;
+            }
         }
         return DTV_OK;
     };
@@ -983,8 +1022,38 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
     }
     int rc = tm.collect();
     if (rc != DTV_OK) return rc;
+    pl->last_outer = stop ? stop_at : P.n_outer;
+    pl->solved = true;
     if (n_rows) *n_rows = nrow;
     if (nonfinite) return fail(DTV_ENONFINITE, "non-finite value in the diagnostics");
+    return DTV_OK;
+}
+
+extern "C" int dtv_dd_inner_counts(dtv_dd_plan *pl, int32_t *h_counts, void *stream)
+{
+    if (!pl || !h_counts) return fail(DTV_EINVAL, "null argument");
+    const size_t nsub = pl->h_subs.size();
+    std::vector<int> dev(2 * nsub, 0);
+    if (pl->solved && pl->adaptive) {
+        hipStream_t s = (hipStream_t)stream;
+        HIP_TRY(hipMemcpyAsync(dev.data(), pl->counts(), sizeof(int) * 2 * nsub, hipMemcpyDeviceToHost, s),
+                "step counts");
+        HIP_TRY(hipStreamSynchronize(s), "step counts");
+    } else if (pl->solved) {
+        for (size_t t = 0; t < nsub; ++t) {
+            dev[2 * t] = pl->last_outer * pl->prm.n_inner;
+            dev[2 * t + 1] = pl->last_outer > 0 ? pl->prm.n_inner : 0;
+        }
+    }
+    // the work list holds the full subdomains first: put the counts back in grid order
+    std::vector<int64_t> first(pl->n + 1, 0);
+    for (int b = 0; b < pl->n; ++b) first[b + 1] = first[b] + (int64_t)pl->imgs[b].ny * pl->imgs[b].nx;
+    for (size_t t = 0; t < nsub; ++t) {
+        const SubTile &st = pl->h_subs[t];
+        const int64_t g = first[st.img] + (int64_t)st.r * pl->imgs[st.img].nx + st.c;
+        h_counts[2 * g] = dev[2 * t];
+        h_counts[2 * g + 1] = dev[2 * t + 1];
+    }
     return DTV_OK;
 }
 

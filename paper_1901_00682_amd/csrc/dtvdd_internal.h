@@ -53,6 +53,7 @@ constexpr int kRecThreads = 1024; // threads of a fused workgroup
 inline int row_index(int R) { return R <= 4 ? 0 : R <= 8 ? 1 : R <= 16 ? 2 : 3; }
 constexpr int kFusedMax = 128;    // largest subdomain side handled by the fused kernel
 constexpr int kMaxFusedInner = 64;  // largest n_inner of the fused kernel
+constexpr int kMaxAdaptiveInner = 100000;  // largest cap on the local steps with adaptive stopping
 
 // FISTA step of the streaming schedule.  The local gradient step
 //   z = y - (1/L) [div_s^*(f + div_s y / alpha) + (y - phat)/tau]
@@ -121,6 +122,11 @@ struct FusedArgs {
     float tau, inv_tau;
     int n_inner;
     float beta[kMaxFusedInner + 1];  // beta[k], k = 1..n_inner
+    // adaptive inner stopping (tol2 > 0): up to n_inner steps per subdomain, momentum table
+    // beta_dev[k] in device memory, per-subdomain [total steps, most steps in one outer step]
+    double tol2;
+    const float *beta_dev;
+    int *counts;
 };
 
 struct Cp2StepArgs {

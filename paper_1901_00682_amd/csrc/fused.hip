@@ -33,7 +33,8 @@ using namespace fused;
 // tiles first; the full launch takes that prefix, the other launch the rest).
 // KF > 0: full tiles with n_inner = KF (steps unrolled); KF = 0: any n_inner.
 // REC: also record every step for reverse mode (full tiles, KF > 0; a.rec).
-template <bool kFull, int KF, bool REC = false>
+// ADAPT: stop each subdomain's steps by the relative-change rule (a.tol2, KF = 0).
+template <bool kFull, int KF, bool REC = false, bool ADAPT = false>
 __global__ __launch_bounds__(1024) void k_fused_fista(FusedArgs a, int first)
 {
     __shared__ FusedLds S;
@@ -236,6 +237,8 @@ __global__ __launch_bounds__(1024) void k_fused_fista(FusedArgs a, int first)
     // steps 1 and 2 have no momentum (beta = 0); x_K ends in slot A
     const int K = a.n_inner;
     int rx_slot = 0;  // LDS slot of the right boundary edges holding x_K
+    int taken = K;    // steps taken (adaptive stopping)
+    __shared__ double red[ADAPT ? 2 * kWaves : 1];
     if constexpr (kFull) {
         FullCtx fc;
         fc.s = c.s;
@@ -258,7 +261,9 @@ __global__ __launch_bounds__(1024) void k_fused_fista(FusedArgs a, int first)
         fc.kL = c.kL;
         fc.qa = (float)(-im.dA * (double)a.inv_tau);
         fc.qb = (float)(-im.dB);
-        if constexpr (KF > 0) {
+        if constexpr (ADAPT) {
+            rx_slot = run_steps_adaptive<FullStep>(fc, S, A, B, K, a.beta_dev, a.tol2, red, taken);
+        } else if constexpr (KF > 0) {
             if constexpr (REC) {
                 const long long rec_step = (long long)gridDim.x * kRecGroups * kRecThreads;
                 float4 *rec = a.rec + (long long)t * kRecGroups * kRecThreads + threadIdx.x;
@@ -270,8 +275,17 @@ __global__ __launch_bounds__(1024) void k_fused_fista(FusedArgs a, int first)
         } else {
             rx_slot = run_steps<FullStep>(fc, S, A, B, K, a.beta);
         }
+    } else if constexpr (ADAPT) {
+        rx_slot = run_steps_adaptive<GenericStep>(c, S, A, B, K, a.beta_dev, a.tol2, red, taken);
     } else {
         rx_slot = run_steps<GenericStep>(c, S, A, B, K, a.beta);
+    }
+    if constexpr (ADAPT) {
+        if (threadIdx.x == 0) {  // the only workgroup of this subdomain in this launch
+            int *cnt = a.counts + 2 * (long long)t;
+            cnt[0] += taken;
+            cnt[1] = max(cnt[1], taken);
+        }
     }
 
     // ---- store x_K (now in slot A) as p~^(n+1)
@@ -332,9 +346,31 @@ namespace {
 hipError_t launch_fused_fista(const FusedArgs &a, int nsub, int nfull, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     if (nsub <= 0) return hipSuccess;
-    if (a.n_inner < 1 || a.n_inner > kMaxFusedInner || nfull < 0 || nfull > nsub) return hipErrorInvalidValue;
+    const bool adapt = a.tol2 > 0.0;
+    if (a.n_inner < 1 || (!adapt && a.n_inner > kMaxFusedInner) || nfull < 0 || nfull > nsub)
+        return hipErrorInvalidValue;
     const int npart = nsub - nfull;
-    if (a.rec && (npart > 0 || !Full::get(a.n_inner, true))) return hipErrorInvalidValue;
+    if (a.rec && (adapt || npart > 0 || !Full::get(a.n_inner, true))) return hipErrorInvalidValue;
+    if (adapt && (!a.beta_dev || !a.counts)) return hipErrorInvalidValue;
+    if (adapt) {
+        if (nfull > 0) {
+            hipEvent_t stop = npart > 0 ? nullptr : e1;
+            if (e0)
+                hipExtLaunchKernelGGL((k_fused_fista<true, 0, false, true>), dim3(nfull), dim3(1024), 0, s, e0, stop,
+                                      0, a, 0);
+            else
+                hipLaunchKernelGGL((k_fused_fista<true, 0, false, true>), dim3(nfull), dim3(1024), 0, s, a, 0);
+        }
+        if (npart > 0) {
+            hipEvent_t start = nfull > 0 ? nullptr : e0;
+            if (e0)
+                hipExtLaunchKernelGGL((k_fused_fista<false, 0, false, true>), dim3(npart), dim3(1024), 0, s, start,
+                                      e1, 0, a, nfull);
+            else
+                hipLaunchKernelGGL((k_fused_fista<false, 0, false, true>), dim3(npart), dim3(1024), 0, s, a, nfull);
+        }
+        return hipGetLastError();
+    }
     // the timing events bracket both launches
     if (nfull > 0) {
         const FusedKernel kf = Full::get(a.n_inner, a.rec != nullptr);

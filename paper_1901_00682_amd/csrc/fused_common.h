@@ -376,6 +376,116 @@ struct FullStep {
     }
 };
 
+// ---- adaptive inner stopping -------------------------------------------------
+// The local solve of a subdomain stops after step k once
+//   |x_k - x_{k-1}|_2 < tol |x_k|_2   (or x_k = x_{k-1})
+// over all of the subdomain's edge dofs, or after the cap K.  Each thread sums
+// its own edges in FP32; the sums are reduced per wave and over the 16 waves
+// in FP64, in a fixed order, and every thread takes the same decision.
+
+// Partial sums of |x_k - x_{k-1}|^2 and |x_k|^2 over the thread's edges: N
+// holds x_k, O holds x_{k-1}; the right boundary edges are in LDS slots so ^ 1
+// (x_k) and so (x_{k-1}).
+__device__ __forceinline__ void conv_acc(float n, float o, float &dd, float &nn)
+{
+    const float d = n - o;
+    dd = fmaf(d, d, dd);
+    nn = fmaf(n, n, nn);
+}
+
+__device__ __forceinline__ void conv_sums(const Ctx &c, const FusedLds &S, const Slot &O, const Slot &N, int so,
+                                          float &dd, float &nn)
+{
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {  // edges outside the tile hold 0 in both slots
+        conv_acc(N.e1a[r], O.e1a[r], dd, nn);
+        conv_acc(N.e1b[r], O.e1b[r], dd, nn);
+        conv_acc(N.e2a[r], O.e2a[r], dd, nn);
+        conv_acc(N.e2b[r], O.e2b[r], dd, nn);
+    }
+    if (c.has_bottom) {
+        if (c.acta) conv_acc(N.ba, O.ba, dd, nn);
+        if (c.actb) conv_acc(N.bb, O.bb, dd, nn);
+    }
+    if (c.lastcol_a || c.lastcol_b)
+#pragma unroll
+        for (int r = 0; r < kR; ++r)
+            if (c.il0 + r < c.h) conv_acc(S.rx[so ^ 1][c.il0 + r], S.rx[so][c.il0 + r], dd, nn);
+}
+
+__device__ __forceinline__ void conv_sums(const FullCtx &c, const FusedLds &S, const Slot &O, const Slot &N, int so,
+                                          float &dd, float &nn)
+{
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+        conv_acc(N.e1a[r], O.e1a[r], dd, nn);
+        conv_acc(N.e1b[r], O.e1b[r], dd, nn);
+        conv_acc(N.e2a[r], O.e2a[r], dd, nn);
+        conv_acc(N.e2b[r], O.e2b[r], dd, nn);
+    }
+    if (c.last) {  // the bottom boundary edges are meaningful in strip 15 only
+        conv_acc(N.ba, O.ba, dd, nn);
+        conv_acc(N.bb, O.bb, dd, nn);
+    }
+    if (c.lane < kR) conv_acc(S.rx[so ^ 1][c.olr], S.rx[so][c.olr], dd, nn);  // lanes 0..7: right column
+}
+
+__device__ __forceinline__ double wave_sum_f64(double x)
+{
+    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+// red: 2 doubles per wave of LDS.  Reading red after the barrier is safe against
+// the next step's writes: those come after the two barriers of that step.
+__device__ __forceinline__ bool block_converged(int s, int lane, float dd, float nn, double tol2, double *red)
+{
+    const double d = wave_sum_f64((double)dd), n = wave_sum_f64((double)nn);
+    if (lane == 0) {
+        red[2 * s] = d;
+        red[2 * s + 1] = n;
+    }
+    __syncthreads();
+    double D = 0.0, N = 0.0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        D += red[2 * w];
+        N += red[2 * w + 1];
+    }
+    return D == 0.0 || D < tol2 * N;
+}
+
+// Up to K steps from x_0 in A (B holds a copy) with the stopping rule above
+// (tol2 = tol^2); x_k ends in A.  beta: the momentum table (beta[k], k >= 3).
+// Returns the LDS slot of the right boundary edges holding x_k; taken = k.
+template <class Step, class C>
+__device__ __forceinline__ int run_steps_adaptive(const C &c, FusedLds &S, Slot &A, Slot &B, int K, const float *beta,
+                                                  double tol2, double *red, int &taken)
+{
+    int k = 1;
+    for (;; ++k) {
+        float dd = 0.0f, nn = 0.0f;
+        if (k & 1) {  // x_{k-1} in A (slot 0), x_k into B
+            if (k >= 3) Step::template step<true>(c, S, A, B, 0, beta[k]);
+            else Step::template step<false>(c, S, A, B, 0, 0.0f);
+            if (k == K) break;
+            conv_sums(c, S, A, B, 0, dd, nn);
+        } else {      // x_{k-1} in B (slot 1), x_k into A
+            if (k >= 3) Step::template step<true>(c, S, B, A, 1, beta[k]);
+            else Step::template step<false>(c, S, B, A, 1, 0.0f);
+            if (k == K) break;
+            conv_sums(c, S, B, A, 1, dd, nn);
+        }
+        if (block_converged(c.s, c.lane, dd, nn, tol2, red)) break;
+    }
+    taken = k;
+    if (k & 1) {
+        copy_slot(A, B);
+        return 1;
+    }
+    return 0;
+}
+
 // K projected-FISTA steps from x_0 in A (B holds a copy); x_K ends in A.
 // Steps 1 and 2 have no momentum (beta = 0).  Returns the LDS slot of the
 // right boundary edges that holds x_K.

@@ -26,8 +26,8 @@ SCHEDULE_NAME = {v: k for k, v in SCHEDULE.items()}
 
 # every entry point declared in include/dtvdd.h
 EXPORTS = ("dtv_dd_setup", "dtv_dd_layout", "dtv_dd_workspace_bytes", "dtv_dd_bind_workspace", "dtv_dd_solve",
-           "dtv_dd_diagnostics", "dtv_dd_backward", "dtv_dd_kernel_time", "dtv_dd_schedule", "dtv_dd_choice", "dtv_dd_destroy",
-           "dtv_last_error")
+           "dtv_dd_diagnostics", "dtv_dd_backward", "dtv_dd_kernel_time", "dtv_dd_schedule", "dtv_dd_choice",
+           "dtv_dd_inner_counts", "dtv_dd_destroy", "dtv_last_error")
 
 
 class DtvError(RuntimeError):
@@ -51,7 +51,7 @@ class Params(ctypes.Structure):
                 ("save_for_backward", ctypes.c_int32), ("ckpt_every", ctypes.c_int32),
                 ("schedule", ctypes.c_int32), ("time_kernels", ctypes.c_int32), ("rows", ctypes.c_int32),
                 ("no_graphs", ctypes.c_int32), ("cv_c1", ctypes.c_double), ("cv_c2", ctypes.c_double),
-                ("full_problem", ctypes.c_int32)]
+                ("full_problem", ctypes.c_int32), ("inner_tol", ctypes.c_double)]
 
 
 class Layout(ctypes.Structure):
@@ -86,6 +86,7 @@ def lib(path: str = LIB_PATH):
                                      ctypes.POINTER(dbl)]
     L.dtv_dd_schedule.argtypes = [vp, ctypes.POINTER(i32)]
     L.dtv_dd_choice.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.dtv_dd_inner_counts.argtypes = [vp, ctypes.POINTER(i32), vp]
     L.dtv_dd_destroy.argtypes = [vp]
     L.dtv_dd_destroy.restype = None
     L.dtv_last_error.restype = ctypes.c_char_p
@@ -126,8 +127,8 @@ class Plan:
     def __init__(self, images, *, fidelity="L2", inner=None, has_mask=False, tau=50.0, sigma=0.01, tau0=10.0,
                  sigma0=1.0 / 80.0, gamma=None, n_outer=100, n_inner=10, diag_every=0, gap_tol=0.0,
                  warm_start=False, save_for_backward=False, ckpt_every=20, schedule="auto",
-                 time_kernels=False, rows=0, graphs=True, c1=0.6, c2=0.1, full_problem=False, device=None,
-                 bind=True):
+                 time_kernels=False, rows=0, graphs=True, c1=0.6, c2=0.1, full_problem=False, inner_tol=0.0,
+                 device=None, bind=True):
         import torch
 
         L = lib()
@@ -150,7 +151,7 @@ class Plan:
                              float(tau0), float(sigma0), float(gamma), int(n_outer), int(n_inner),
                              int(diag_every), float(gap_tol), int(warm_start), int(save_for_backward),
                              int(ckpt_every), SCHEDULE[schedule], int(time_kernels), int(rows),
-                             int(not graphs), float(c1), float(c2), int(full_problem))
+                             int(not graphs), float(c1), float(c2), int(full_problem), float(inner_tol))
         h = ctypes.c_void_p()
         _check(L.dtv_dd_setup(descs, len(self.images), ctypes.byref(self.params), ctypes.byref(h)))
         self.h = h
@@ -247,6 +248,15 @@ class Plan:
         _check(lib().dtv_dd_backward(self.h, _ptr(f), _ptr(grad_u.contiguous()), _ptr(grad_f), _ptr(grad_alpha),
                                      self._stream(stream)))
         return grad_f, grad_alpha
+
+    def inner_counts(self, stream=None) -> np.ndarray:
+        """[n_subdomains, 2] local steps of the last solve per subdomain (total,
+        most in one outer step), image-major, row-major over each grid."""
+        nsub = sum((len(im.row_cuts) - 1) * (len(im.col_cuts) - 1) for im in self.images)
+        out = np.zeros(2 * nsub, dtype=np.int32)
+        _check(lib().dtv_dd_inner_counts(self.h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                         self._stream(stream)))
+        return out.reshape(nsub, 2)
 
     def kernel_time(self):
         ms, n, nm, b = ctypes.c_double(), ctypes.c_int64(), ctypes.c_char_p(), ctypes.c_double()

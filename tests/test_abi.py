@@ -93,6 +93,12 @@ def test_valid_setup_and_layout():
     (dict(full_problem=2), "full_problem must"),
     (dict(full_problem=1, rc=(0, 64), cc=(0, 64), save_for_backward=1), "save_for_backward"),
     (dict(full_problem=1, rc=(0, 64), cc=(0, 64), inner=1, gamma=-1.0), "gamma"),
+    (dict(inner_tol=-1.0), "inner_tol"),
+    (dict(inner_tol=1e-3, inner=1), "inner_tol needs FISTA"),
+    (dict(inner_tol=1e-3, schedule=1), "inner_tol needs FISTA"),
+    (dict(inner_tol=1e-3, save_for_backward=1), "inner_tol needs FISTA"),
+    (dict(inner_tol=1e-3, H=300, W=300, rc=(0, 150, 300), cc=(0, 150, 300)), "at most 128"),
+    (dict(inner_tol=1e-3, n_inner=100001), "cap"),
 ])
 def test_validation_errors(kw, msg):
     code, h = _setup(**kw)
@@ -111,6 +117,21 @@ def test_valid_chan_vese_and_full_problem(kw):
     code, h = _setup(**kw)
     assert code == 0, dtvdd.lib().dtv_last_error().decode()
     dtvdd.lib().dtv_dd_destroy(h)
+
+
+def test_inner_counts_before_any_solve_are_zero():
+    L = dtvdd.lib()
+    for kw in (dict(), dict(inner_tol=1e-3, n_inner=500)):
+        code, h = _setup(**kw)
+        assert code == 0, L.dtv_last_error().decode()
+        out = np.full(8, -1, dtype=np.int32)
+        assert L.dtv_dd_inner_counts(h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), None) == 0
+        assert not out.any()
+        sc = ctypes.c_int32()
+        assert L.dtv_dd_schedule(h, ctypes.byref(sc)) == 0
+        if kw:
+            assert sc.value == 2  # the adaptive rule runs in the fused kernel
+        L.dtv_dd_destroy(h)
 
 
 def test_solve_rejects_missing_workspace_and_nulls():
