@@ -365,21 +365,26 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
                           [](const SubTile &st) { return st.h == kFusedMax && st.w == kFusedMax; });
     for (const SubTile &st : pl->h_subs) pl->n_full += st.h == kFusedMax && st.w == kFusedMax;
     pl->adaptive = p.inner_tol > 0.0;
-    pl->fused_ok = p.inner == DTV_INNER_FISTA && (p.n_inner <= kMaxFusedInner || pl->adaptive);
-    for (const SubTile &st : pl->h_subs)
-        if (st.h > kFusedMax || st.w > kFusedMax) pl->fused_ok = false;
+    if (p.inner == DTV_INNER_FISTA) {
+        pl->fused_ok = p.n_inner <= kMaxFusedInner || pl->adaptive;
+        for (const SubTile &st : pl->h_subs)
+            if (st.h > kFusedMax || st.w > kFusedMax) pl->fused_ok = false;
+    } else {  // the fused primal-dual kernel takes full 128 x 128 subdomains only
+        pl->fused_ok = p.n_inner <= kMaxFusedInner && !pl->h_subs.empty() && pl->n_full == (int)pl->h_subs.size();
+    }
     if (pl->adaptive && !pl->fused_ok) {
         delete pl;
         return fail(DTV_EINVAL, "inner_tol needs subdomains of at most 128 x 128 (the fused schedule)");
     }
     if (p.schedule == DTV_SCHED_FUSED && !pl->fused_ok) {
         delete pl;
-        return fail(DTV_EINVAL, "the fused schedule needs FISTA, n_inner <= 64 and subdomains of at most 128 x 128");
+        return fail(DTV_EINVAL, "the fused schedule needs n_inner <= 64 and subdomains of at most 128 x 128 (FISTA) "
+                                "or of exactly 128 x 128 (CP2)");
     }
     {
         const int nsub = (int)pl->h_subs.size();
-        pl->persist_ok = pl->fused_ok && nsub > 0 && pl->n_full == nsub && p.diag_every == 0 && !p.save_for_backward &&
-                         !pl->adaptive;
+        pl->persist_ok = p.inner == DTV_INNER_FISTA && pl->fused_ok && nsub > 0 && pl->n_full == nsub &&
+                         p.diag_every == 0 && !p.save_for_backward && !pl->adaptive;
         int dev = 0;
         if (pl->persist_ok && hipGetDevice(&dev) == hipSuccess)
             pl->persist_ok = persist_supported(dev) && nsub <= persist_capacity(dev);
@@ -630,7 +635,7 @@ static std::vector<float> fista_betas(int K);
 static int next_base(int sched, bool cp2, int K, int base)
 {
     if (sched == DTV_SCHED_PERSIST) return base;
-    if (sched == DTV_SCHED_FUSED) return base == 0 ? 1 : 0;
+    if (sched == DTV_SCHED_FUSED) return cp2 ? base : (base == 0 ? 1 : 0);  // the fused CP2 kernel works in place
     if (!cp2) {
         int rot[3] = {base, 0, 0}, q = 1;
         for (int k = 0; k < 3; ++k)
@@ -745,12 +750,41 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
             if (rc != DTV_OK) return rc;
         }
         // (a1) multipliers from the extrapolated interface jump: inside the fused kernel, else a launch
-        if (sched != DTV_SCHED_FUSED)
+        if (sched != DTV_SCHED_FUSED || cp2)
             HIP_TRY(launch_lambda(pl->d_imgs(), pl->n, pl->max_nlam, pl->d_info(), bufs[base].p1, bufs[base].p2,
                                   lam_cur, (float)P.sigma, q),
                     "lambda update");
         // (a2)+(a3) local solves; the anchor phat is formed on the fly from p~^n and lambda
-        if (sched == DTV_SCHED_FUSED) {
+        if (sched == DTV_SCHED_FUSED && cp2) {
+            FusedCp2Args ca{};
+            ca.imgs = pl->d_imgs();
+            ca.subs = pl->d_subs();
+            ca.p1 = bufs[base].p1;
+            ca.p2 = bufs[base].p2;
+            ca.lam = lam_cur;
+            ca.f = d_f;
+            ca.mask = mask;
+            ca.u = u_cur;
+            ca.tau = (float)P.tau;
+            ca.fidelity = P.fidelity;
+            ca.cv_c1 = (float)P.cv_c1;
+            ca.cv_c2 = (float)P.cv_c2;
+            ca.n_inner = K;
+            for (int it = 0; it < K; ++it) {
+                ca.tk[it] = (float)tk[it];
+                ca.sk[it] = (float)sk[it];
+                ca.th[it] = (float)th[it];
+                ca.ck[it] = P.full_problem ? 1.0f : (float)(P.tau / (P.tau + tk[it]));
+                ca.ca[it] = P.full_problem ? 0.0f : (float)(tk[it] / (P.tau + tk[it]));
+            }
+            int rc = with_host ? tm.begin() : DTV_OK;
+            if (rc != DTV_OK) return rc;
+            HIP_TRY(launch_fused_cp2(ca, (int)pl->h_subs.size(), q, with_host ? tm.e0 : nullptr,
+                                     with_host ? tm.e1 : nullptr),
+                    "fused CP2");
+            rc = with_host ? tm.end() : DTV_OK;
+            if (rc != DTV_OK) return rc;
+        } else if (sched == DTV_SCHED_FUSED) {
             const int out = next_base(sched, cp2, K, base);
             fa.base1 = bufs[base].p1; fa.base2 = bufs[base].p2;
             fa.out1 = bufs[out].p1; fa.out2 = bufs[out].p2;
@@ -886,8 +920,8 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
             for (int i = 0; i < 8; ++i) {
                 seq.push_back(state(b, uf, lp));
                 b = next_base(sched, cp2, K, b);
-                if (cp2 && (K & 1)) uf = !uf;
-                if (sched == DTV_SCHED_FUSED) lp = !lp;
+                if (cp2 && sched != DTV_SCHED_FUSED && (K & 1)) uf = !uf;
+                if (sched == DTV_SCHED_FUSED && !cp2) lp = !lp;
             }
             int start = -1, period = 0;
             for (int i = 0; i < 4 && start < 0; ++i)
@@ -1267,11 +1301,14 @@ extern "C" int dtv_dd_kernel_time(const dtv_dd_plan *pl, double *avg_ms, int64_t
     const bool cp2 = pl->prm.inner == DTV_INNER_CP2;
     const bool fused = pl->schedule == DTV_SCHED_FUSED;
     const bool persist = pl->schedule == DTV_SCHED_PERSIST;
-    if (name) *name = persist ? "k_persist_fista" : fused ? "k_fused_fista" : (cp2 ? "k_cp2_step" : "k_fista_step");
+    if (name)
+        *name = persist ? "k_persist_fista"
+                        : fused ? (cp2 ? "k_fused_cp2" : "k_fused_fista") : (cp2 ? "k_cp2_step" : "k_fista_step");
     if (bytes_per_launch) {
         // Algorithmic HBM bytes of one timed launch (E = edge dofs of the torn
         // p~, N = pixels, 4 bytes each), averaged over the launches of an outer step.
         //   fused: read p~^n and f, write p~^(n+1)                                 4 (2E + N)
+        //   fused CP2: read p~^n, u, f (+ mask bytes), write p~^(n+1), u           4 (2E + 3N) + mask
         //   streaming FISTA step 1: read x_0 and f, write c' and x_1                4 (3E + N)
         //   streaming FISTA step 2: read x_1 and c', write x_2                      4 (3E)
         //   streaming FISTA step k >= 3: read x_{k-1}, x_{k-2}, c', write x_k       4 (4E)
@@ -1291,6 +1328,8 @@ extern "C" int dtv_dd_kernel_time(const dtv_dd_plan *pl, double *avg_ms, int64_t
             // one launch for the whole solve: read p~^0, f and the lambda state, write p~^N and the
             // lambda state, and per outer step write and read two 8-byte exchange words per multiplier
             *bytes_per_launch = 4.0 * (2 * E + N + 6 * lam) + 32.0 * lam * pl->prm.n_outer;
+        } else if (fused && cp2) {
+            *bytes_per_launch = 4.0 * (2 * E + 3 * N) + mb;
         } else if (fused) {
             *bytes_per_launch = 4.0 * (2 * E + N);
         } else {

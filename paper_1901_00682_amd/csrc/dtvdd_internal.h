@@ -129,6 +129,25 @@ struct FusedArgs {
     int *counts;
 };
 
+// Fused local primal-dual solves on full 128 x 128 subdomains (fused_cp2.hip).
+// Step k + 1 (k = 0 .. n_inner - 1) uses tau_k = tk[k], sigma_k = sk[k], the
+// extrapolation theta_k = th[k] of its result, and the weights c_keep = ck[k],
+// c_anchor = ca[k] of the dual update.
+struct FusedCp2Args {
+    const ImgDev *imgs;
+    const SubTile *subs;       // the (full) subdomains
+    float *p1, *p2;            // p~^n in, p~^(n+1) out (each tile reads and writes only its own copies)
+    const float *lam;          // lambda state after the multiplier update (lambda^(n+1) first)
+    const float *f;
+    const uint8_t *mask;       // NULL: every pixel observed
+    float *u;                  // u in and out
+    float tau;
+    int fidelity;              // 0 L2, 1 L1, 2 convex Chan-Vese
+    float cv_c1, cv_c2;
+    int n_inner;
+    float tk[kMaxFusedInner], sk[kMaxFusedInner], th[kMaxFusedInner], ck[kMaxFusedInner], ca[kMaxFusedInner];
+};
+
 struct Cp2StepArgs {
     const ImgDev *imgs;
     const StreamTile *tiles;
@@ -160,6 +179,8 @@ hipError_t launch_fista_step(const FistaStepArgs &a, int mode, int rows, hipStre
                              hipEvent_t e1 = nullptr);
 hipError_t launch_cp2_step(const Cp2StepArgs &a, bool extrapolate, int rows, hipStream_t s, hipEvent_t e0 = nullptr,
                            hipEvent_t e1 = nullptr);
+hipError_t launch_fused_cp2(const FusedCp2Args &a, int nsub, hipStream_t s, hipEvent_t e0 = nullptr,
+                            hipEvent_t e1 = nullptr);
 hipError_t launch_u_from_p(const ImgDev *imgs, int nimg, int maxH, int maxW, const int *info, const float *p1,
                            const float *p2, const float *f, float *u, hipStream_t s);
 hipError_t launch_zero_boundary(const ImgDev *imgs, int nimg, int maxH, int maxW, float *p1, float *p2,

@@ -17,6 +17,7 @@
 // (the library is built with -ffp-contract=off so that the streaming and
 // fused schedules round identically).
 #include "dtvdd_internal.h"
+#include "cp2_ops.h"
 #include "fista_ops.h"
 
 namespace dtv {
@@ -247,24 +248,6 @@ hipError_t launch_fista_step(const FistaStepArgs &a, int mode, int rows, hipStre
 //   xbar = x_{k-1} + theta_prev (x_{k-1} - x_{k-2})
 //   u_k  = prox_{sigma_k alpha F}(u_{k-1} + sigma_k div_s xbar)   (per pixel)
 //   x_k  = clamp((tau (x_{k-1} - tau_k div_s^* u_k) + tau_k phat) / (tau + tau_k))
-// prox of a F at one pixel: L2 (z + a f)/(1 + a); L1 f + shr(z - f, a), eq.
-// (shrinkage); convex Chan-Vese (Sec. 3, segmentation) the projection of z - a g
-// onto [0, 1], with g = (f - c1)^2 - (f - c2)^2 evaluated as (c2 - c1)((f - c1) + (f - c2)),
-// the same value without the cancellation of two squares.
-__device__ __forceinline__ float prox_fid(int fidelity, float z, float fv, bool observed, float a, float c1,
-                                          float c2)
-{
-    if (!observed) return z;
-    if (fidelity == 0) return (z + a * fv) / (1.0f + a);
-    if (fidelity == 2) {
-        const float g = (c2 - c1) * ((fv - c1) + (fv - c2));
-        return fminf(fmaxf(fmaf(-a, g, z), 0.0f), 1.0f);
-    }
-    const float d = z - fv;
-    const float mag = fmaxf(fabsf(d) - a, 0.0f);
-    return d > 0.0f ? fv + mag : (d < 0.0f ? fv - mag : fv);
-}
-
 template <int R, bool EXT>
 __global__ __launch_bounds__(64) void k_cp2_step(Cp2StepArgs a)
 {
@@ -309,12 +292,9 @@ __global__ __launch_bounds__(64) void k_cp2_step(Cp2StepArgs a)
     auto unew = [&](int i, float xt, float xb, float xl, float xr) -> float {
         const long long px = (long long)i * W + j;
         const float d = (xb - xt) + (xr - xl);
-        return prox_fid(fid, fmaf(sk, d, uin[px]), f[px], mk ? mk[px] != 0 : true, sa, cv1, cv2);
+        return cp2_u(fid, uin[px], d, sk, f[px], mk ? mk[px] != 0 : true, sa, cv1, cv2);
     };
-    auto pupdate = [&](float x, float du, float anchor) -> float {
-        const float pbar = fmaf(-tk, du, x);  // x - tau_k div^* u
-        return clamp1(fmaf(ck, pbar, ca * anchor));
-    };
+    auto pupdate = [&](float x, float du, float anchor) -> float { return clamp1(cp2_pre(x, du, anchor, tk, ck, ca)); };
 
     const int i0 = tile.i0;
     const int iend = min(i0 + R, H);

@@ -1,0 +1,134 @@
+"""Fused local primal-dual solves (one workgroup per 128 x 128 subdomain, all
+inner steps on chip) against the streaming kernel, bitwise, on every
+combination of image-boundary and interface sides, every fidelity (L2, L1 with
+and without mask, convex Chan-Vese), several inner counts, the undecomposed
+problem and warm starts; and against the FP64 oracle to relative L2 <= 1e-5."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1901_00682_amd import synth
+from tests.helpers import compare, gpu_image_state, oracle_for
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1901_00682_amd import dtvdd
+    dtvdd.lib()
+
+
+GEOMS = {
+    "full3x3": (384, 384, [0, 128, 256, 384], [0, 128, 256, 384]),
+    "full2x4": (256, 512, [0, 128, 256], [0, 128, 256, 384, 512]),
+    "full1x1": (128, 128, [0, 128], [0, 128]),
+}
+FID = {
+    # name: fidelity, masked, alpha, extra parameters
+    "l2": ("L2", False, 8.0, {}),
+    "l1_mask": ("L1", True, 1.5, {}),
+    "l2_mask": ("L2", True, 6.0, {}),
+    "cv": ("CV", False, 10.0, dict(tau=1.0, sigma=0.5, gamma=1.0 / 8.0, c1=0.6, c2=0.1)),
+}
+
+
+def _input(geom, fid, seed):
+    H, W, rc, cc = GEOMS[geom]
+    rng = np.random.default_rng(seed)
+    clean = synth.shapes(H, W, rng)
+    fidelity, masked, alpha, extra = FID[fid]
+    f = synth.salt_and_pepper(clean, 0.3, rng) if fidelity == "L1" else clean + synth.gaussian((H, W), 0.05, rng)
+    mask = None
+    if masked:
+        mask = synth.stroke_mask(H, W, 0.1, rng)
+        f = np.where(mask == 1, f, 0.0)
+    return f.astype(np.float32), mask, alpha, extra, np.array(rc), np.array(cc)
+
+
+def run_gpu(f32, alpha, rc, cc, mask=None, state=None, **kw):
+    from paper_1901_00682_amd import dtvdd
+    H, W = f32.shape
+    plan = dtvdd.Plan([dtvdd.Image(H, W, rc, cc, alpha)], has_mask=mask is not None, inner="CP2", **kw)
+    ft = torch.from_numpy(np.ascontiguousarray(f32).ravel()).cuda()
+    mt = None if mask is None else torch.from_numpy(np.ascontiguousarray(mask, dtype=np.uint8).ravel()).cuda()
+    st, stats = plan.solve(ft, mt, state=state)
+    torch.cuda.synchronize()
+    return plan, st, stats
+
+
+CASES = [("full3x3", "l2", 5), ("full3x3", "l1_mask", 3), ("full3x3", "cv", 5), ("full3x3", "l2_mask", 2),
+         ("full2x4", "cv", 1), ("full2x4", "l1_mask", 4), ("full1x1", "l2", 6), ("full1x1", "cv", 3)]
+
+
+@pytest.mark.parametrize("geom,fid,K", CASES)
+def test_fused_cp2_equals_stream_bitwise(geom, fid, K):
+    f, mask, alpha, extra, rc, cc = _input(geom, fid, 300 + K)
+    fidelity = FID[fid][0]
+    _say(f"[fused cp2==stream] {geom} {fid} K={K}")
+    res = {}
+    for sch in ("stream", "fused"):
+        plan, st, _ = run_gpu(f, alpha, rc, cc, mask=mask, fidelity=fidelity, n_outer=7, n_inner=K, schedule=sch,
+                              **extra)
+        assert plan.schedule() == sch
+        res[sch] = gpu_image_state(plan, st)
+    for q in res["stream"]:
+        assert np.array_equal(res["stream"][q], res["fused"][q]), q
+    o = oracle_for(f, alpha, rc, cc, fidelity=fidelity, inner="CP2", mask=mask, n_inner=K,
+                   **{k: v for k, v in extra.items()})
+    o.run(7)
+    errs = compare(res["fused"], o)
+    _say(f"  errors {errs}")
+
+
+def test_fused_cp2_full_problem_and_warm_start():
+    """The undecomposed problem (no proximal term) and a resumed solve."""
+    f, mask, alpha, extra, rc, cc = _input("full1x1", "l2", 41)
+    outs = {}
+    for sch in ("stream", "fused"):
+        plan, st, _ = run_gpu(f, alpha, rc, cc, n_outer=2, n_inner=20, schedule=sch, full_problem=True, gamma=0.0)
+        outs[sch] = gpu_image_state(plan, st)
+    for q in outs["stream"]:
+        assert np.array_equal(outs["stream"][q], outs["fused"][q]), q
+    f, mask, alpha, extra, rc, cc = _input("full2x4", "cv", 42)
+    outs = {}
+    for sch in ("stream", "fused"):
+        plan, st, _ = run_gpu(f, alpha, rc, cc, n_outer=3, n_inner=4, schedule=sch, fidelity="CV", **extra)
+        plan2 = None
+        from paper_1901_00682_amd import dtvdd
+        plan2 = dtvdd.Plan([dtvdd.Image(256, 512, rc, cc, alpha)], inner="CP2", fidelity="CV", n_outer=2, n_inner=4,
+                           schedule=sch, warm_start=True, **extra)
+        ft = torch.from_numpy(np.ascontiguousarray(f).ravel()).cuda()
+        plan2.solve(ft, state=st)
+        torch.cuda.synchronize()
+        outs[sch] = gpu_image_state(plan2, st)
+    for q in outs["stream"]:
+        assert np.array_equal(outs["stream"][q], outs["fused"][q]), q
+
+
+def test_fused_cp2_cv_full_size_with_diagnostics():
+    """The segmentation workload at full size through the fused kernel (the
+    schedule the autotuner can pick), against the oracle, with the FP64
+    diagnostics."""
+    c = synth.cv_case(n_outer=10)
+    _say(f"[fused cp2] {c.name} 10x{c.n_inner}")
+    extra = dict(tau=c.tau, sigma=c.sigma, gamma=c.gamma, **c.extra)
+    plan, st, stats = run_gpu(c.f, c.alpha, c.row_cuts, c.col_cuts, fidelity="CV", n_outer=10, n_inner=c.n_inner,
+                              schedule="fused", diag_every=5, **extra)
+    o = oracle_for(c.f, c.alpha, c.row_cuts, c.col_cuts, fidelity="CV", inner="CP2", n_inner=c.n_inner, **extra)
+    ost = o.run(10, diag_every=5)
+    errs = compare(gpu_image_state(plan, st), o)
+    _say(f"  errors {errs}")
+    g = stats[0]
+    for q in (1, 2):
+        assert np.max(np.abs(g[:, q] - ost[:, q]) / np.abs(ost[:, q])) <= 1e-6
