@@ -383,18 +383,20 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
     }
     {
         const int nsub = (int)pl->h_subs.size();
-        pl->persist_ok = p.inner == DTV_INNER_FISTA && pl->fused_ok && nsub > 0 && pl->n_full == nsub &&
-                         p.diag_every == 0 && !p.save_for_backward && !pl->adaptive;
+        pl->persist_ok = pl->fused_ok && nsub > 0 && pl->n_full == nsub && p.diag_every == 0 && !p.save_for_backward &&
+                         !pl->adaptive;
         int dev = 0;
         if (pl->persist_ok && hipGetDevice(&dev) == hipSuccess)
-            pl->persist_ok = persist_supported(dev) && nsub <= persist_capacity(dev);
+            pl->persist_ok = persist_supported(dev) &&
+                             nsub <= (p.inner == DTV_INNER_CP2 ? persist_cp2_capacity(dev) : persist_capacity(dev));
         else
             pl->persist_ok = false;
     }
     if (p.schedule == DTV_SCHED_PERSIST && !pl->persist_ok) {
         delete pl;
-        return fail(DTV_EINVAL, "the persistent schedule needs FISTA, n_inner <= 64, every subdomain 128 x 128, all "
-                                "subdomains resident on the device at once, diag_every = 0 and no save_for_backward");
+        return fail(DTV_EINVAL, "the persistent schedule needs n_inner <= 64, every subdomain 128 x 128, all "
+                                "subdomains resident on the device at once, diag_every = 0, no save_for_backward and "
+                                "no inner_tol");
     }
 
     // workspace layout
@@ -739,6 +741,31 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
                     "checkpoint");
         return DTV_OK;
     };
+    // arguments of the fused and persistent primal-dual kernels (state pointers: the current buffers)
+    auto cp2_args = [&]() {
+        FusedCp2Args ca{};
+        ca.imgs = pl->d_imgs();
+        ca.subs = pl->d_subs();
+        ca.p1 = bufs[base].p1;
+        ca.p2 = bufs[base].p2;
+        ca.lam = lam_cur;
+        ca.f = d_f;
+        ca.mask = mask;
+        ca.u = u_cur;
+        ca.tau = (float)P.tau;
+        ca.fidelity = P.fidelity;
+        ca.cv_c1 = (float)P.cv_c1;
+        ca.cv_c2 = (float)P.cv_c2;
+        ca.n_inner = std::min(K, kMaxFusedInner);
+        for (int it = 0; it < ca.n_inner; ++it) {
+            ca.tk[it] = (float)tk[it];
+            ca.sk[it] = (float)sk[it];
+            ca.th[it] = (float)th[it];
+            ca.ck[it] = P.full_problem ? 1.0f : (float)(P.tau / (P.tau + tk[it]));
+            ca.ca[it] = P.full_problem ? 0.0f : (float)(tk[it] / (P.tau + tk[it]));
+        }
+        return ca;
+    };
     pl->saved = false;
     const bool host_work = P.diag_every > 0 || P.save_for_backward || P.time_kernels;
 
@@ -756,27 +783,7 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
                     "lambda update");
         // (a2)+(a3) local solves; the anchor phat is formed on the fly from p~^n and lambda
         if (sched == DTV_SCHED_FUSED && cp2) {
-            FusedCp2Args ca{};
-            ca.imgs = pl->d_imgs();
-            ca.subs = pl->d_subs();
-            ca.p1 = bufs[base].p1;
-            ca.p2 = bufs[base].p2;
-            ca.lam = lam_cur;
-            ca.f = d_f;
-            ca.mask = mask;
-            ca.u = u_cur;
-            ca.tau = (float)P.tau;
-            ca.fidelity = P.fidelity;
-            ca.cv_c1 = (float)P.cv_c1;
-            ca.cv_c2 = (float)P.cv_c2;
-            ca.n_inner = K;
-            for (int it = 0; it < K; ++it) {
-                ca.tk[it] = (float)tk[it];
-                ca.sk[it] = (float)sk[it];
-                ca.th[it] = (float)th[it];
-                ca.ck[it] = P.full_problem ? 1.0f : (float)(P.tau / (P.tau + tk[it]));
-                ca.ca[it] = P.full_problem ? 0.0f : (float)(tk[it] / (P.tau + tk[it]));
-            }
+            FusedCp2Args ca = cp2_args();
             int rc = with_host ? tm.begin() : DTV_OK;
             if (rc != DTV_OK) return rc;
             HIP_TRY(launch_fused_cp2(ca, (int)pl->h_subs.size(), q, with_host ? tm.e0 : nullptr,
@@ -879,28 +886,40 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
         unsigned *sync = pl->sync_words();
         HIP_TRY(hipMemsetAsync(sync, 0, 2 * sizeof(unsigned), s), "clear error flag");
         HIP_TRY(hipMemsetAsync(pl->xch(), 0, sizeof(unsigned long long) * 2 * (size_t)pl->tot_lam, s), "clear exchange");
-        PersistArgs pa{};
-        pa.fa = fa;
-        pa.fa.base1 = pa.fa.out1 = bufs[base].p1;
-        pa.fa.base2 = pa.fa.out2 = bufs[base].p2;
-        pa.fa.lam = lam_cur;
-        pa.lam_out = lam_cur;
-        pa.xch = pl->xch();
-        pa.xch_stride = pl->tot_lam;
-        pa.err = (int *)sync;
-        pa.n_outer = count;
-        pa.sigma = (float)P.sigma;
         int rc = tm.begin();
         if (rc != DTV_OK) return rc;
         if (tm.e0) HIP_TRY(hipEventRecord(tm.e0, s), "event");
-        HIP_TRY(launch_persist_fista(pa, (int)pl->h_subs.size(), s), "persistent FISTA");
+        if (cp2) {
+            PersistCp2Args pc{};
+            pc.ca = cp2_args();
+            pc.lam_out = lam_cur;
+            pc.xch = pl->xch();
+            pc.xch_stride = pl->tot_lam;
+            pc.err = (int *)sync;
+            pc.n_outer = count;
+            pc.sigma = (float)P.sigma;
+            HIP_TRY(launch_persist_cp2(pc, (int)pl->h_subs.size(), s), "persistent primal-dual");
+        } else {
+            PersistArgs pa{};
+            pa.fa = fa;
+            pa.fa.base1 = pa.fa.out1 = bufs[base].p1;
+            pa.fa.base2 = pa.fa.out2 = bufs[base].p2;
+            pa.fa.lam = lam_cur;
+            pa.lam_out = lam_cur;
+            pa.xch = pl->xch();
+            pa.xch_stride = pl->tot_lam;
+            pa.err = (int *)sync;
+            pa.n_outer = count;
+            pa.sigma = (float)P.sigma;
+            HIP_TRY(launch_persist_fista(pa, (int)pl->h_subs.size(), s), "persistent FISTA");
+        }
         if (tm.e1) HIP_TRY(hipEventRecord(tm.e1, s), "event");
         rc = tm.end();
         if (rc != DTV_OK) return rc;
         int err = 0;
         HIP_TRY(hipMemcpyAsync(&err, sync, sizeof(int), hipMemcpyDeviceToHost, s), "exchange status");
         HIP_TRY(hipStreamSynchronize(s), "exchange status");
-        if (err) return fail(DTV_EHIP, "persistent FISTA: a wait for a neighbouring subdomain timed out");
+        if (err) return fail(DTV_EHIP, "persistent schedule: a wait for a neighbouring subdomain timed out");
         return DTV_OK;
     };
 
@@ -1302,7 +1321,7 @@ extern "C" int dtv_dd_kernel_time(const dtv_dd_plan *pl, double *avg_ms, int64_t
     const bool fused = pl->schedule == DTV_SCHED_FUSED;
     const bool persist = pl->schedule == DTV_SCHED_PERSIST;
     if (name)
-        *name = persist ? "k_persist_fista"
+        *name = persist ? (cp2 ? "k_persist_cp2" : "k_persist_fista")
                         : fused ? (cp2 ? "k_fused_cp2" : "k_fused_fista") : (cp2 ? "k_cp2_step" : "k_fista_step");
     if (bytes_per_launch) {
         // Algorithmic HBM bytes of one timed launch (E = edge dofs of the torn
@@ -1327,7 +1346,8 @@ extern "C" int dtv_dd_kernel_time(const dtv_dd_plan *pl, double *avg_ms, int64_t
         if (persist) {
             // one launch for the whole solve: read p~^0, f and the lambda state, write p~^N and the
             // lambda state, and per outer step write and read two 8-byte exchange words per multiplier
-            *bytes_per_launch = 4.0 * (2 * E + N + 6 * lam) + 32.0 * lam * pl->prm.n_outer;
+            // (primal-dual: u read and written once more, mask bytes read once)
+            *bytes_per_launch = 4.0 * (2 * E + N + 6 * lam) + 32.0 * lam * pl->prm.n_outer + (cp2 ? 8.0 * N + mb : 0.0);
         } else if (fused && cp2) {
             *bytes_per_launch = 4.0 * (2 * E + 3 * N) + mb;
         } else if (fused) {

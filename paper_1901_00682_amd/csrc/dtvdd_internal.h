@@ -148,6 +148,18 @@ struct FusedCp2Args {
     float tk[kMaxFusedInner], sk[kMaxFusedInner], th[kMaxFusedInner], ck[kMaxFusedInner], ca[kMaxFusedInner];
 };
 
+// Persistent primal-dual schedule (persist_cp2.hip): every outer step in one cooperative launch,
+// p~, u and lambda updated in place; xch, err as in PersistArgs.
+struct PersistCp2Args {
+    FusedCp2Args ca;
+    float *lam_out;
+    unsigned long long *xch;
+    long long xch_stride;
+    int *err;
+    int n_outer;
+    float sigma;
+};
+
 struct Cp2StepArgs {
     const ImgDev *imgs;
     const StreamTile *tiles;
@@ -181,6 +193,8 @@ hipError_t launch_cp2_step(const Cp2StepArgs &a, bool extrapolate, int rows, hip
                            hipEvent_t e1 = nullptr);
 hipError_t launch_fused_cp2(const FusedCp2Args &a, int nsub, hipStream_t s, hipEvent_t e0 = nullptr,
                             hipEvent_t e1 = nullptr);
+hipError_t launch_persist_cp2(const PersistCp2Args &a, int nsub, hipStream_t s);
+int persist_cp2_capacity(int device);
 hipError_t launch_u_from_p(const ImgDev *imgs, int nimg, int maxH, int maxW, const int *info, const float *p1,
                            const float *p2, const float *f, float *u, hipStream_t s);
 hipError_t launch_zero_boundary(const ImgDev *imgs, int nimg, int maxH, int maxW, float *p1, float *p2,

@@ -3,71 +3,14 @@
 // eq. (local), any fidelity of Sec. 3) on full 128 x 128 subdomains: one
 // 1024-thread workgroup owns one subdomain and runs all n_inner steps of an
 // outer iteration on chip.
-//
-// Layout on chip (as in the fused FISTA kernel): wave s owns pixel rows
-// 8 s .. 8 s + 7 of the tile, lane l owns columns 2l ("a") and 2l + 1 ("b");
-// each thread owns the top and left edges of its 16 pixels, strip 15 the
-// tile's bottom boundary edges, lanes 0..7 of each strip the right boundary
-// edges of the strip's rows (in LDS).
-//   VGPRs: x_k on the owned edges, u, f (and the observed bits) of the pixels.
-//   LDS:   the anchor phat of every edge (128 KB), u of each strip's last row,
-//          xbar of each strip's first-row top edges, u of the last column.
-// The step is reordered so that xbar never needs a register slot of its own:
-// u_1 = prox(u_0 + sigma_1 div x_0) first; then step k updates x_k from u_k
-// row by row, forms xbar_k on the row's edges and, one row behind, the
-// divergence of xbar_k and u_(k+1).  Two barriers per step: (A) u of the
-// strips' last rows, (B) xbar of their first rows.
-//
-// The per-element arithmetic is that of the streaming kernel (cp2_ops.h), so
-// both schedules give bitwise identical results.
-#include "cp2_ops.h"
-#include "fused_common.h"
+// The on-chip layout and the step are those of cp2_tile.h; this kernel loads
+// the tile, forms the anchors from p~^n and lambda^(n+1), solves and stores.
+#include "cp2_tile.h"
 
 namespace dtv {
 
 using namespace fused;
-
-namespace {
-
-struct Cp2Lds {
-    // the small arrays first, so that their offsets fit the 16-bit immediate of LDS instructions
-    float ab[kFusedMax];              // anchor of the bottom boundary edges (per column)
-    float ar[kFusedMax];              // anchor of the right boundary edges (per row)
-    float rx[kFusedMax];              // right boundary edges: x_k (per row)
-    float rxb[kFusedMax];             // right boundary edges: xbar_k (per row)
-    float uR[kFusedMax];              // u of the last column (per row)
-    float ut[kWaves][kFusedMax];      // u of each strip's last row
-    float xt[kWaves][kFusedMax];      // xbar of the top edges of each strip's first row
-    float a1[kFusedMax][kFusedMax];   // anchor of the edge above pixel (il, jl)
-    float a2[kFusedMax][kFusedMax];   // anchor of the edge left of pixel (il, jl)
-};
-
-__device__ __forceinline__ void ld2g(const float *p, float &x, float &y)
-{
-    float2 v;
-    __builtin_memcpy(&v, p, 8);
-    x = v.x;
-    y = v.y;
-}
-
-__device__ __forceinline__ void st2g(float *p, float x, float y)
-{
-    const float2 v = make_float2(x, y);
-    __builtin_memcpy(p, &v, 8);
-}
-
-// divergence of the two pixels of a row from xbar on their edges: top (ta, tb),
-// bottom (ba, bb), left (la, lb); the right edge of column b is the next lane's
-// left edge of column a, or the tile's right boundary edge rxb on lane 63
-__device__ __forceinline__ void div_pair(float ta, float tb, float ba, float bb, float la, float lb, float rxb,
-                                         float &da, float &db)
-{
-    const float rb = from_right_or(la, rxb);
-    da = div4(ta, ba, la, lb);
-    db = div4(tb, bb, lb, rb);
-}
-
-}  // namespace
+using namespace cp2tile;
 
 // FID: the fidelity (0 L2, 1 L1, 2 convex Chan-Vese); MASK: an inpainting mask is given
 template <int FID, bool MASK>
@@ -96,8 +39,6 @@ __global__ __launch_bounds__(1024) void k_fused_cp2(FusedCp2Args a)
     const uint8_t *m_tile = MASK ? a.mask + px0 : nullptr;
     const float *lam = a.lam + im.lam;
     const float tau = a.tau, alpha = im.alpha, cv1 = a.cv_c1, cv2 = a.cv_c2;
-    constexpr int fid = FID;
-    const int K = a.n_inner;
     // clamp bounds, (-1, 1) or (0, 0) for edges on the image boundary (no dof)
     const float lo1 = (top_bnd && s == 0) ? 0.0f : -1.0f, hi1 = -lo1;
     const float lo2a = (left_bnd && lane == 0) ? 0.0f : -1.0f, hi2a = -lo2a;
@@ -162,121 +103,28 @@ __global__ __launch_bounds__(1024) void k_fused_cp2(FusedCp2Args a)
         for (int r = 0; r < kR; ++r) {
             const int il = il0 + r;
             S.rx[il] = xr[r];
-            S.rxb[il] = xr[r];  // xbar_0 = x_0
             float ar = xr[r];
             if (!right_bnd) ar = fmaf(-tau, lam[im.nlh + (long long)tl.c * H + tl.ra + il], ar);
             S.ar[il] = ar;
         }
-    // xbar_0 = x_0 of the first row's top edges, for the strip above
-    if (s > 0) lds_st2(&S.xt[s][ja], X.e1a[0], X.e1b[0]);
-    __syncthreads();
-
-    auto observed = [&](int bit) { return ((obs >> bit) & 1u) != 0; };
-
-    // ---- u_1 = prox(u_0 + sigma_1 div x_0)
-    {
-        const float sk = a.sk[0], sa = sk * alpha;
-#pragma unroll
-        for (int r = 0; r < kR; ++r) {
-            float ba_ = 0.0f, bb_ = 0.0f;
-            if (r < kR - 1) {
-                ba_ = X.e1a[r + 1];
-                bb_ = X.e1b[r + 1];
-            } else if (!last) {
-                lds_ld2(&S.xt[s + 1][ja], ba_, bb_);
-            } else {
-                ba_ = X.ba;
-                bb_ = X.bb;
-            }
-            float da, db;
-            div_pair(X.e1a[r], X.e1b[r], ba_, bb_, X.e2a[r], X.e2b[r], S.rxb[il0 + r], da, db);
-            ua[r] = cp2_u(fid, ua[r], da, sk, fa[r], observed(2 * r), sa, cv1, cv2);
-            ub[r] = cp2_u(fid, ub[r], db, sk, fb[r], observed(2 * r + 1), sa, cv1, cv2);
-        }
-    }
-
-    // ---- the K steps
-    for (int k = 1; k <= K; ++k) {
-        const float tk = a.tk[k - 1], ck = a.ck[k - 1], ca = a.ca[k - 1], th = a.th[k - 1];
-        const bool ext = k < K;  // u_(k+1) is needed
-        const float skn = ext ? a.sk[k] : 0.0f, san = skn * alpha;
-        // (A) publish u_k of the strip's last row (for the strip below) and of the last column
-        if (!last) lds_st2(&S.ut[s][ja], ua[kR - 1], ub[kR - 1]);
-        if (lane == 63)
-#pragma unroll
-            for (int r = 0; r < kR; ++r) S.uR[il0 + r] = ub[r];
-        __syncthreads();
-
-        // (B) right boundary edges of the strip's rows (lanes 0..7), du = u of the last column
-        if (lane < kR) {
-            const int il = il0 + lane;
-            const float xo = S.rx[il];
-            const float xn = right_bnd ? xo : clamp1(cp2_pre(xo, S.uR[il], S.ar[il], tk, ck, ca));
-            S.rx[il] = xn;
-            S.rxb[il] = fmaf(th, xn - xo, xn);
-        }
-        // row sweep: x_k on the row's edges, xbar_k, and one row behind, u_(k+1)
-        float uua = 0.0f, uub = 0.0f;  // u_k of the row above (0 above the tile: one-sided copy)
-        if (s > 0) lds_ld2(&S.ut[s - 1][ja], uua, uub);
-        float pta = 0.0f, ptb = 0.0f, pla = 0.0f, plb = 0.0f;  // xbar_k on the previous row's top / left edges
-#pragma unroll
-        for (int r = 0; r < kR; ++r) {
-            __builtin_amdgcn_sched_barrier(0);  // one row at a time: bounds the registers in flight
-            const int il = il0 + r;
-            const float ura = ua[r], urb = ub[r];
-            const float ul = from_left(urb);  // u of column a - 1 (lane 0: left of the tile, 0)
-            float A1a, A1b, A2a, A2b;
-            lds_ld2(&S.a1[il][ja], A1a, A1b);
-            lds_ld2(&S.a2[il][ja], A2a, A2b);
-            const float o1a = X.e1a[r], o1b = X.e1b[r], o2a = X.e2a[r], o2b = X.e2b[r];
-            const float l1 = r == 0 ? lo1 : -1.0f, h1 = r == 0 ? hi1 : 1.0f;
-            const float n1a = __builtin_amdgcn_fmed3f(cp2_pre(o1a, uua - ura, A1a, tk, ck, ca), l1, h1);
-            const float n1b = __builtin_amdgcn_fmed3f(cp2_pre(o1b, uub - urb, A1b, tk, ck, ca), l1, h1);
-            const float n2a = __builtin_amdgcn_fmed3f(cp2_pre(o2a, ul - ura, A2a, tk, ck, ca), lo2a, hi2a);
-            const float n2b = clamp1(cp2_pre(o2b, ura - urb, A2b, tk, ck, ca));
-            X.e1a[r] = n1a;
-            X.e1b[r] = n1b;
-            X.e2a[r] = n2a;
-            X.e2b[r] = n2b;
-            if (ext) {
-                const float b1a = fmaf(th, n1a - o1a, n1a), b1b = fmaf(th, n1b - o1b, n1b);
-                const float b2a = fmaf(th, n2a - o2a, n2a), b2b = fmaf(th, n2b - o2b, n2b);
-                if (r == 0 && s > 0) lds_st2(&S.xt[s][ja], b1a, b1b);
-                if (r > 0) {
-                    float da, db;
-                    div_pair(pta, ptb, b1a, b1b, pla, plb, S.rxb[il - 1], da, db);
-                    ua[r - 1] = cp2_u(fid, ua[r - 1], da, skn, fa[r - 1], observed(2 * r - 2), san, cv1, cv2);
-                    ub[r - 1] = cp2_u(fid, ub[r - 1], db, skn, fb[r - 1], observed(2 * r - 1), san, cv1, cv2);
-                }
-                pta = b1a;
-                ptb = b1b;
-                pla = b2a;
-                plb = b2b;
-            }
-            uua = ura;
-            uub = urb;
-            pin4(X.e1a[r], X.e1b[r], X.e2a[r], X.e2b[r]);
-        }
-        // bottom boundary edges of the tile (strip 15), du = u_k of the last row
-        float bxa = 0.0f, bxb = 0.0f;  // their xbar_k
-        if (last && !bot_bnd) {
-            const float oba = X.ba, obb = X.bb;
-            X.ba = clamp1(cp2_pre(oba, ua[kR - 1], S.ab[ja], tk, ck, ca));
-            X.bb = clamp1(cp2_pre(obb, ub[kR - 1], S.ab[jb], tk, ck, ca));
-            bxa = fmaf(th, X.ba - oba, X.ba);
-            bxb = fmaf(th, X.bb - obb, X.bb);
-        }
-        if (ext) {
-            __syncthreads();
-            // (C) the last row: its bottom edges are the next strip's first-row top edges
-            float ba_ = bxa, bb_ = bxb;
-            if (!last) lds_ld2(&S.xt[s + 1][ja], ba_, bb_);
-            float da, db;
-            div_pair(pta, ptb, ba_, bb_, pla, plb, S.rxb[il0 + kR - 1], da, db);
-            ua[kR - 1] = cp2_u(fid, ua[kR - 1], da, skn, fa[kR - 1], observed(2 * kR - 2), san, cv1, cv2);
-            ub[kR - 1] = cp2_u(fid, ub[kR - 1], db, skn, fb[kR - 1], observed(2 * kR - 1), san, cv1, cv2);
-        }
-    }
+    // ---- (a3) the local solve
+    Cp2Ctx cx;
+    cx.s = s;
+    cx.lane = lane;
+    cx.ja = ja;
+    cx.jb = jb;
+    cx.il0 = il0;
+    cx.last = last;
+    cx.bot_bnd = bot_bnd;
+    cx.right_bnd = right_bnd;
+    cx.lo1 = lo1;
+    cx.hi1 = hi1;
+    cx.lo2a = lo2a;
+    cx.hi2a = hi2a;
+    cx.alpha = alpha;
+    cx.cv1 = cv1;
+    cx.cv2 = cv2;
+    solve<FID>(cx, S, X, ua, ub, fa, fb, obs, a);
 
     // ---- store x_K as p~^(n+1) and u_K
 #pragma unroll

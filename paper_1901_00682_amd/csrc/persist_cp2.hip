@@ -1,0 +1,246 @@
+// Persistent schedule of Algorithm 1 (Lee & Park, arXiv 1901.00682) with the
+// local accelerated primal-dual solver of Sec. 5 (any fidelity of Sec. 3):
+// one cooperative launch runs every outer step.
+//
+// Each workgroup owns one full 128 x 128 subdomain for the whole solve; x, u
+// and f stay in VGPRs (the layout of cp2_tile.h) from the first outer step to
+// the last.  Per outer step n:
+//   (1) each tile forms q = 2 p^n - p^(n-1) on its own interface copies and
+//       publishes them (exchange.h);
+//   (2) meanwhile it writes the anchors phat = p^n of every edge to LDS;
+//   (3) it waits for its neighbours' copies on the same edges, and both tiles
+//       of an interface edge compute lambda^(n+1) = lambda^n + sigma (q_s - q_t)
+//       with the operations of the multiplier-update kernel;
+//   (4) the anchors of the interface copies become p^n -/+ tau lambda^(n+1);
+//   (5) the n_inner primal-dual steps (cp2tile::solve).
+// lambda^n and the tile's own previous copies live in LDS.
+//
+// The arithmetic per edge, pixel and multiplier is that of the streaming and
+// fused schedules, so all three give bitwise identical results.
+#include "cp2_tile.h"
+#include "exchange.h"
+
+namespace dtv {
+
+using namespace fused;
+using namespace cp2tile;
+using namespace xchg;
+
+namespace {
+
+struct PersistCp2Lds {
+    Cp2Lds t;
+    float lam[kSides][kFusedMax];    // lambda on the tile's interface edges
+    float prv[kSides][kFusedMax];    // the tile's own copies on those edges at the previous outer step
+    float stage[kSides][kFusedMax];  // the current copies on the top, bottom and left sides
+    int ok;                          // every wait of the current step completed
+};
+
+}  // namespace
+
+// FID: the fidelity (0 L2, 1 L1, 2 convex Chan-Vese); MASK: an inpainting mask is given
+template <int FID, bool MASK>
+__global__ __launch_bounds__(1024) void k_persist_cp2(PersistCp2Args pa)
+{
+    __shared__ PersistCp2Lds L;
+    Cp2Lds &S = L.t;
+    const FusedCp2Args &a = pa.ca;
+    const int t = xcd_remap(blockIdx.x, gridDim.x);
+    const SubTile tl = a.subs[t];
+    const ImgDev im = a.imgs[tl.img];
+    const int s = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform strip index
+    const int lane = threadIdx.x & 63;
+    const int ja = 2 * lane, jb = ja + 1;
+    const int il0 = kR * s;
+    const int H = im.H, W = im.W;
+    const bool top_bnd = tl.ra == 0, bot_bnd = tl.ra + kFusedMax == H;
+    const bool left_bnd = tl.ca == 0, right_bnd = tl.ca + kFusedMax == W;
+    const bool last = s == kWaves - 1;
+    const long long P1 = im.pitch1, P2 = im.pitch2;
+    const long long row1 = (long long)tl.ra + tl.r;  // P1 row of the tile's edge row 0
+    const long long col2 = (long long)tl.ca + tl.c;  // P2 column of the tile's edge column 0
+    float *p1_tile = a.p1 + im.p1 + row1 * P1 + tl.ca;
+    float *p2_tile = a.p2 + im.p2 + (long long)tl.ra * P2 + col2;
+    const long long px0 = im.px + (long long)tl.ra * W + tl.ca;
+    const float *f_tile = a.f + px0;
+    float *u_tile = a.u + px0;
+    const float tau = a.tau;
+    const long long nlam = im.nlam;
+
+    Cp2Ctx cx;
+    cx.s = s;
+    cx.lane = lane;
+    cx.ja = ja;
+    cx.jb = jb;
+    cx.il0 = il0;
+    cx.last = last;
+    cx.bot_bnd = bot_bnd;
+    cx.right_bnd = right_bnd;
+    cx.lo1 = (top_bnd && s == 0) ? 0.0f : -1.0f;
+    cx.hi1 = -cx.lo1;
+    cx.lo2a = (left_bnd && lane == 0) ? 0.0f : -1.0f;
+    cx.hi2a = -cx.lo2a;
+    cx.alpha = im.alpha;
+    cx.cv1 = a.cv_c1;
+    cx.cv2 = a.cv_c2;
+
+    // side work (multiplier update): waves 0..7, side = wave / 2 (wave-uniform), edge
+    // si = 64 (wave % 2) + lane; the lambda index is side_base + si
+    const int side = s >> 1;
+    const bool side_wave = s < 2 * kSides && side_exists(im, tl, side);
+    const bool side_s = side == 1 || side == 3;  // s copies: bottom and right sides
+    const long long side_base = side_wave ? side_edge(im, tl, side, 0) : 0;
+
+    // ---- load p~^0, u, f and the lambda state
+    Slot X;
+    float ua[kR], ub[kR], fa[kR], fb[kR];
+    unsigned obs = 0xFFFFu;  // observed pixels: bit 2r (column a), 2r + 1 (column b) of row r
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+        const int il = il0 + r;
+        ld2g(p1_tile + (long long)il * P1 + ja, X.e1a[r], X.e1b[r]);
+        ld2g(p2_tile + (long long)il * P2 + ja, X.e2a[r], X.e2b[r]);
+        ld2g(f_tile + (long long)il * W + ja, fa[r], fb[r]);
+        ld2g(u_tile + (long long)il * W + ja, ua[r], ub[r]);
+    }
+    X.ba = X.bb = 0.0f;
+    if (last) ld2g(p1_tile + (long long)kFusedMax * P1 + ja, X.ba, X.bb);
+    if (lane < kR) S.rx[il0 + lane] = p2_tile[(long long)(il0 + lane) * P2 + kFusedMax];
+    if constexpr (MASK) {
+        const uint8_t *m_tile = a.mask + px0;
+        obs = 0;
+#pragma unroll
+        for (int r = 0; r < kR; ++r) {
+            const uint8_t *mr = m_tile + (long long)(il0 + r) * W + ja;
+            obs |= (mr[0] != 0 ? 1u : 0u) << (2 * r);
+            obs |= (mr[1] != 0 ? 1u : 0u) << (2 * r + 1);
+        }
+    }
+    if (side_wave) {
+        const int si = (s & 1) * 64 + lane;
+        const float *ls = a.lam + im.lam + side_base;
+        L.lam[side][si] = ls[si];
+        L.prv[side][si] = ls[(side_s ? nlam : 2 * nlam) + si];
+    }
+    bool ok = true;
+
+    for (int n = 0; n < pa.n_outer; ++n) {
+        // ---- (1) stage the current iterate on the top, bottom and left sides (the right
+        // boundary column is in S.rx)
+        __syncthreads();
+        if (s == 0) lds_st2(&L.stage[0][ja], X.e1a[0], X.e1b[0]);
+        if (last) lds_st2(&L.stage[1][ja], X.ba, X.bb);
+        if (lane == 0) {
+#pragma unroll
+            for (int r = 0; r < kR; ++r) L.stage[2][il0 + r] = X.e2a[r];
+        }
+        if (threadIdx.x == 0) L.ok = 1;
+        __syncthreads();
+        // ---- publish q = 2 p^n - p^(n-1) on the tile's interface copies
+        const int si = (s & 1) * 64 + opaque(lane);
+        unsigned long long *xch = pa.xch + (long long)(n & 1) * pa.xch_stride + im.lam + side_base + si;
+        float x_side = 0.0f, q_own = 0.0f;
+        if (side_wave) {
+            x_side = side == 3 ? S.rx[si] : L.stage[side][si];
+            q_own = 2.0f * x_side - L.prv[side][si];
+            L.prv[side][si] = x_side;
+            publish(xch + (side_s ? 0 : nlam), q_own, n);
+        }
+
+        // ---- (2) anchors phat = p^n on every edge (the interface copies get their multiplier
+        // term in (4)) while the neighbours' copies travel
+#pragma unroll
+        for (int r = 0; r < kR; ++r) {
+            const int il = il0 + r;
+            lds_st2(&S.a1[il][ja], X.e1a[r], X.e1b[r]);
+            lds_st2(&S.a2[il][ja], X.e2a[r], X.e2b[r]);
+        }
+        if (last) lds_st2(&S.ab[ja], X.ba, X.bb);
+        if (lane < kR) S.ar[il0 + lane] = S.rx[il0 + lane];
+        __syncthreads();
+
+        // ---- (3) the neighbour's copy of each interface edge, lambda^(n+1), and (4) the anchor of
+        // the tile's copy: phat = p^n + tau lambda on t copies (top, left), - tau lambda on s copies
+        if (side_wave) {
+            float q_oth = 0.0f;
+            if (fetch(xch + (side_s ? nlam : 0), n, q_oth)) {
+                const float qs = side_s ? q_own : q_oth, qt = side_s ? q_oth : q_own;
+                const float lam = L.lam[side][si] + pa.sigma * (qs - qt);
+                L.lam[side][si] = lam;
+                if (side == 0) S.a1[0][si] = fmaf(tau, lam, x_side);
+                else if (side == 2) S.a2[si][0] = fmaf(tau, lam, x_side);
+                else if (side == 1) S.ab[si] = fmaf(-tau, lam, x_side);
+                else S.ar[si] = fmaf(-tau, lam, x_side);
+            } else {
+                L.ok = 0;
+                atomicOr(pa.err, 1);
+            }
+        }
+        __syncthreads();
+        ok = L.ok != 0;
+        if (!ok) break;  // a neighbour stopped publishing: leave (the host reports the error)
+
+        // ---- (5) the local primal-dual solve
+        solve<FID>(cx, S, X, ua, ub, fa, fb, obs, a);
+    }
+
+    // ---- store p~^N, u and the lambda state (lambda^N and the copies of the last multiplier update)
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+        const int il = il0 + r;
+        st2g(p1_tile + (long long)il * P1 + ja, X.e1a[r], X.e1b[r]);
+        st2g(p2_tile + (long long)il * P2 + ja, X.e2a[r], X.e2b[r]);
+        st2g(u_tile + (long long)il * W + ja, ua[r], ub[r]);
+    }
+    if (last) st2g(p1_tile + (long long)kFusedMax * P1 + ja, X.ba, X.bb);
+    if (lane < kR) p2_tile[(long long)(il0 + lane) * P2 + kFusedMax] = S.rx[il0 + lane];
+    if (side_wave && ok) {
+        const int si = (s & 1) * 64 + lane;
+        float *ls = pa.lam_out + im.lam + side_base;
+        if (side_s) {
+            ls[si] = L.lam[side][si];
+            ls[nlam + si] = L.prv[side][si];
+        } else {
+            ls[2 * nlam + si] = L.prv[side][si];
+        }
+    }
+}
+
+namespace {
+
+using PersistCp2Kernel = void (*)(PersistCp2Args);
+
+PersistCp2Kernel persist_cp2_kernel(int fidelity, bool mask)
+{
+    switch (fidelity) {
+    case 0: return mask ? k_persist_cp2<0, true> : k_persist_cp2<0, false>;
+    case 1: return mask ? k_persist_cp2<1, true> : k_persist_cp2<1, false>;
+    case 2: return mask ? nullptr : k_persist_cp2<2, false>;
+    default: return nullptr;
+    }
+}
+
+}  // namespace
+
+int persist_cp2_capacity(int device)
+{
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persist_cp2<1, true>, 1024, 0) != hipSuccess)
+        return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
+    return per_cu * cus;
+}
+
+hipError_t launch_persist_cp2(const PersistCp2Args &a, int nsub, hipStream_t s)
+{
+    if (nsub <= 0 || a.n_outer <= 0) return hipSuccess;
+    if (a.ca.n_inner < 1 || a.ca.n_inner > kMaxFusedInner) return hipErrorInvalidValue;
+    const PersistCp2Kernel k = persist_cp2_kernel(a.ca.fidelity, a.ca.mask != nullptr);
+    if (!k) return hipErrorInvalidValue;
+    PersistCp2Args arg = a;
+    void *args[] = {&arg};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k), dim3(nsub), dim3(1024), args, 0, s);
+}
+
+}  // namespace dtv

@@ -132,3 +132,45 @@ def test_fused_cp2_cv_full_size_with_diagnostics():
     g = stats[0]
     for q in (1, 2):
         assert np.max(np.abs(g[:, q] - ost[:, q]) / np.abs(ost[:, q])) <= 1e-6
+
+
+PCASES = [("full3x3", "l2", 5, 6), ("full3x3", "l1_mask", 3, 5), ("full3x3", "cv", 5, 7), ("full2x4", "cv", 1, 4),
+          ("full2x4", "l2_mask", 4, 3), ("full1x1", "l1_mask", 2, 5)]
+
+
+@pytest.mark.parametrize("geom,fid,K,n_outer", PCASES)
+def test_persistent_cp2_equals_fused_bitwise(geom, fid, K, n_outer):
+    """Every outer step in one cooperative launch (x, u and f kept on chip,
+    interface copies exchanged point to point) against the fused kernel."""
+    f, mask, alpha, extra, rc, cc = _input(geom, fid, 500 + K + n_outer)
+    fidelity = FID[fid][0]
+    _say(f"[persistent cp2==fused] {geom} {fid} K={K} outer={n_outer}")
+    res = {}
+    for sch in ("fused", "persistent"):
+        plan, st, _ = run_gpu(f, alpha, rc, cc, mask=mask, fidelity=fidelity, n_outer=n_outer, n_inner=K,
+                              schedule=sch, **extra)
+        assert plan.schedule() == sch
+        res[sch] = gpu_image_state(plan, st)
+    for q in res["fused"]:
+        assert np.array_equal(res["fused"][q], res["persistent"][q]), q
+
+
+def test_persistent_cp2_resume_and_oracle():
+    """Two persistent solves back to back (warm start from the returned state)
+    equal one longer solve, and match the oracle."""
+    from paper_1901_00682_amd import dtvdd
+    f, mask, alpha, extra, rc, cc = _input("full3x3", "cv", 77)
+    plan, st, _ = run_gpu(f, alpha, rc, cc, fidelity="CV", n_outer=8, n_inner=3, schedule="persistent", **extra)
+    one = gpu_image_state(plan, st)
+    p1, s1, _ = run_gpu(f, alpha, rc, cc, fidelity="CV", n_outer=5, n_inner=3, schedule="persistent", **extra)
+    p2 = dtvdd.Plan([dtvdd.Image(384, 384, rc, cc, alpha)], inner="CP2", fidelity="CV", n_outer=3, n_inner=3,
+                    schedule="persistent", warm_start=True, **extra)
+    ft = torch.from_numpy(np.ascontiguousarray(f).ravel()).cuda()
+    p2.solve(ft, state=s1)
+    torch.cuda.synchronize()
+    two = gpu_image_state(p2, s1)
+    for q in one:
+        assert np.array_equal(one[q], two[q]), q
+    o = oracle_for(f, alpha, rc, cc, fidelity="CV", inner="CP2", n_inner=3, **extra)
+    o.run(8)
+    compare(one, o)
