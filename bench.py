@@ -31,10 +31,13 @@ FP32_PEAK_TFLOPS = 157.3  # MI355X vector FP32 (256 CUs x 128 lanes x 2 flops x 
 
 # source files of each timed kernel (the counters in profiles/traffic.txt are keyed by their hash)
 KERNEL_SOURCES = {
-    "k_persist_fista": ["persist.hip", "fused_common.h", "fista_ops.h", "dtvdd_internal.h"],
+    "k_persist_fista": ["persist.hip", "exchange.h", "fused_common.h", "fista_ops.h", "dtvdd_internal.h"],
     "k_fused_fista": ["fused.hip", "fused_common.h", "fista_ops.h", "dtvdd_internal.h"],
     "k_fista_step": ["kernels.hip", "fista_ops.h", "dtvdd_internal.h"],
-    "k_cp2_step": ["kernels.hip", "fista_ops.h", "dtvdd_internal.h"],
+    "k_cp2_step": ["kernels.hip", "cp2_ops.h", "fista_ops.h", "dtvdd_internal.h"],
+    "k_fused_cp2": ["fused_cp2.hip", "cp2_tile.h", "cp2_ops.h", "fused_common.h", "fista_ops.h", "dtvdd_internal.h"],
+    "k_persist_cp2": ["persist_cp2.hip", "cp2_tile.h", "cp2_ops.h", "exchange.h", "fused_common.h", "fista_ops.h",
+                      "dtvdd_internal.h"],
 }
 
 
@@ -67,6 +70,19 @@ def fista_flops_per_pixel(K: int) -> float:
     edge and outer step, c' = (phat / tau - (f_b - f_a)) / L (4)."""
     plain, mom = 2 * (5 + 1) + 3, 2 * (3 + 5 + 1) + 3
     return 2 * 4 + plain * min(K, 2) + mom * max(K - 2, 0)
+
+
+CP2_PROX_FLOPS = {"L2": 4, "L1": 5, "CV": 8}
+
+
+def cp2_flops_per_pixel(K: int, fidelity: str) -> float:
+    """Algorithmic FP32 operations per pixel of one outer step with K local
+    primal-dual steps (an FMA counts 2): per edge and step, the dual update
+    x_k = clamp(c_keep (x - tau_k (u_b - u_a)) + c_anchor phat) (7); per edge
+    and step but the last, xbar = x + theta (x - x_prev) (3); per pixel and
+    step, the divergence of xbar (3) and the primal update prox(u + sigma_k d)
+    (2 + the prox: L2 4, L1 5, Chan-Vese 8)."""
+    return 2 * 7 * K + 2 * 3 * (K - 1) + K * (3 + 2 + CP2_PROX_FLOPS[fidelity])
 
 
 def workload(name: str):
@@ -348,9 +364,11 @@ def main():
     kt = tplan.kernel_time()
     avg_ms = float(np.mean(launch_ms))
     achieved = kt["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9
-    if kt["name"] == "k_persist_fista":
+    if kt["name"] in ("k_persist_fista", "k_persist_cp2"):
         # one launch per solve, iterates on chip across outer steps: bound by the vector ALUs
-        flops = fista_flops_per_pixel(c.n_inner) * H * W * c.n_outer
+        per_px = (fista_flops_per_pixel(c.n_inner) if kt["name"] == "k_persist_fista"
+                  else cp2_flops_per_pixel(c.n_inner, c.fidelity))
+        flops = per_px * H * W * c.n_outer
         tflops = flops / (avg_ms * 1e-3) / 1e12
         roofline = {"bound": "alu", "kernel": kt["name"], "achieved": tflops, "peak": FP32_PEAK_TFLOPS,
                     "unit": "TFLOP/s", "frac": tflops / FP32_PEAK_TFLOPS,
