@@ -265,34 +265,30 @@ __global__ __launch_bounds__(64) void k_cp2_step(Cp2StepArgs a)
     const bool outlane = colok && lane >= 1;
     const long long P1 = im.pitch1, P2 = im.pitch2;
 
-    const float *xa1 = a.xa1 + im.p1, *xa2 = a.xa2 + im.p2;
-    const float *xb1 = EXT ? a.xb1 + im.p1 : nullptr, *xb2 = EXT ? a.xb2 + im.p2 : nullptr;
-    const float *b1 = a.base1 + im.p1, *b2 = a.base2 + im.p2;
-    const float *lam = a.lam + im.lam;
-    const float *f = a.f + im.px;
-    const uint8_t *mk = a.mask ? a.mask + im.px : nullptr;
-    const float *uin = a.u_in + im.px;
-    float *uout = a.u_out + im.px;
-    float *o1 = a.out1 + im.p1, *o2 = a.out2 + im.p2;
+    // the outputs alias none of the inputs (distinct buffers), so every load of a
+    // row can be issued before the previous row's stores complete
+    const float *__restrict__ xa1 = a.xa1 + im.p1;
+    const float *__restrict__ xa2 = a.xa2 + im.p2;
+    const float *__restrict__ xb1 = EXT ? a.xb1 + im.p1 : nullptr;
+    const float *__restrict__ xb2 = EXT ? a.xb2 + im.p2 : nullptr;
+    const float *__restrict__ b1 = a.base1 + im.p1;
+    const float *__restrict__ b2 = a.base2 + im.p2;
+    const float *__restrict__ lam = a.lam + im.lam;
+    const float *__restrict__ f = a.f + im.px;
+    const uint8_t *__restrict__ mk = a.mask ? a.mask + im.px : nullptr;
+    const float *__restrict__ uin = a.u_in + im.px;
+    float *__restrict__ uout = a.u_out + im.px;
+    float *__restrict__ o1 = a.out1 + im.p1;
+    float *__restrict__ o2 = a.out2 + im.p2;
     const float th = a.theta_prev, sk = a.sk, tk = a.tk, tau = a.tau;
     const float ck = a.c_keep, ca = a.c_anchor, sa = a.sk * im.alpha;
     const int fid = a.fidelity;
     const float cv1 = a.cv_c1, cv2 = a.cv_c2;
 
-    auto xbar1 = [&](long long idx, float &x) -> float {
-        x = xa1[idx];
-        if constexpr (EXT) return fmaf(th, x - xb1[idx], x);
+    // xbar = x + theta (x - x_prev) from the two loaded values
+    auto xbar = [&](float x, float xp) -> float {
+        if constexpr (EXT) return fmaf(th, x - xp, x);
         return x;
-    };
-    auto xbar2 = [&](long long idx, float &x) -> float {
-        x = xa2[idx];
-        if constexpr (EXT) return fmaf(th, x - xb2[idx], x);
-        return x;
-    };
-    auto unew = [&](int i, float xt, float xb, float xl, float xr) -> float {
-        const long long px = (long long)i * W + j;
-        const float d = (xb - xt) + (xr - xl);
-        return cp2_u(fid, uin[px], d, sk, f[px], mk ? mk[px] != 0 : true, sa, cv1, cv2);
     };
     auto pupdate = [&](float x, float du, float anchor) -> float { return clamp1(cp2_pre(x, du, anchor, tk, ck, ca)); };
 
@@ -300,69 +296,112 @@ __global__ __launch_bounds__(64) void k_cp2_step(Cp2StepArgs a)
     const int iend = min(i0 + R, H);
     float u_up = 0.0f, xbar_carry = 0.0f, x_carry = 0.0f;
     bool have = false;
-    if (i0 > 0 && !info_first(a.info[im.rinfo + i0])) {
+    if (i0 > 0 && !info_first(a.info[im.rinfo + i0])) {  // the row above, in the same subdomain
         const int i = i0 - 1;
-        const int top = i + info_sub(a.info[im.rinfo + i]);
+        const long long top = i + info_sub(a.info[im.rinfo + i]);
         if (colok) {
-            float x;
-            const float xt = xbar1(top * P1 + j, x);
-            const float xb = xbar1((top + 1) * P1 + j, x_carry);
-            const float xl = xbar2(i * P2 + left, x), xr = xbar2(i * P2 + left + 1, x);
-            u_up = unew(i, xt, xb, xl, xr);
-            xbar_carry = xb;
+            const long long px = (long long)i * W + j;
+            const float xt = xa1[top * P1 + j], xb = xa1[(top + 1) * P1 + j];
+            const float xl = xa2[i * P2 + left], xr = xa2[i * P2 + left + 1];
+            float xtp = 0.0f, xbp = 0.0f, xlp = 0.0f, xrp = 0.0f;
+            if constexpr (EXT) {
+                xtp = xb1[top * P1 + j];
+                xbp = xb1[(top + 1) * P1 + j];
+                xlp = xb2[i * P2 + left];
+                xrp = xb2[i * P2 + left + 1];
+            }
+            const float uv = uin[px], fv = f[px];
+            const bool obs = mk ? mk[px] != 0 : true;
+            const float bt = xbar(xt, xtp), bb = xbar(xb, xbp);
+            const float d = (bb - bt) + (xbar(xr, xrp) - xbar(xl, xlp));
+            u_up = cp2_u(fid, uv, d, sk, fv, obs, sa, cv1, cv2);
+            xbar_carry = bb;
+            x_carry = xb;
         }
         have = true;
     }
-    for (int i = i0; i < iend; ++i) {
-        const int rw = a.info[im.rinfo + i];
-        const int rs = info_sub(rw);
-        const bool rfirst = info_first(rw), rlast = info_last(rw);
+    // Every load of a row, issued one row ahead (software pipeline): row i + 1's loads are in
+    // flight while row i is computed and stored.  The top edge of a row is the bottom edge of the
+    // row above, carried in registers, except at the first row of a subdomain.
+    struct Row {
+        int rw;
+        float xt, xtp, xb, xbp, xl, xlp, xr, xrp, uv, fv, at, al, ab, ar, lt, ll, lb, lr;
+        unsigned mv;
+    };
+    auto load_row = [&](int i, Row &r) {
+        r.rw = a.info[im.rinfo + i];
+        const int rs = info_sub(r.rw);
+        const bool rfirst = info_first(r.rw), rlast = info_last(r.rw);
         const long long top = i + rs;
+        const long long px = (long long)i * W + j;
+        r.xt = r.xtp = r.xb = r.xbp = r.xl = r.xlp = r.xr = r.xrp = 0.0f;
+        r.uv = r.fv = r.at = r.al = r.ab = r.ar = 0.0f;
+        r.lt = r.ll = r.lb = r.lr = 0.0f;
+        r.mv = 1;
+        if (colok) {
+            if (mk) r.mv = mk[px];  // first: loads complete in order, so its use waits on it alone
+            if (rfirst) {
+                r.xt = xa1[top * P1 + j];
+                if constexpr (EXT) r.xtp = xb1[top * P1 + j];
+            }
+            r.xb = xa1[(top + 1) * P1 + j];
+            r.xl = xa2[i * P2 + left];
+            r.xr = xa2[i * P2 + left + 1];
+            if constexpr (EXT) {
+                r.xbp = xb1[(top + 1) * P1 + j];
+                r.xlp = xb2[i * P2 + left];
+                r.xrp = xb2[i * P2 + left + 1];
+            }
+            r.uv = uin[px];
+            r.fv = f[px];
+            // anchors p~^n of the four edges, and lambda on the interface copies
+            r.at = b1[top * P1 + j];
+            r.ab = b1[(top + 1) * P1 + j];
+            r.al = b2[i * P2 + left];
+            r.ar = b2[i * P2 + left + 1];
+            if (rfirst && i > 0) r.lt = lam[(long long)(rs - 1) * W + j];
+            if (cfirst && j > 0) r.ll = lam[im.nlh + (long long)(cs - 1) * H + i];
+            if (rlast && i < H - 1) r.lb = lam[(long long)rs * W + j];
+            if (clast && j < W - 1) r.lr = lam[im.nlh + (long long)cs * H + i];
+        }
+    };
+    Row cur, nxt;
+    load_row(i0, cur);
+    for (int i = i0; i < iend; ++i) {
+        if (i + 1 < iend) load_row(i + 1, nxt);
+        const int rs = info_sub(cur.rw);
+        const bool rfirst = info_first(cur.rw), rlast = info_last(cur.rw);
+        const long long top = i + rs;
+        const long long px = (long long)i * W + j;
         if (rfirst) {
             have = false;
             u_up = 0.0f;
         }
-        float u = 0.0f, xt = 0.0f, xb = 0.0f, xl = 0.0f, xr = 0.0f;
-        float pt = 0.0f, pb = 0.0f, pl = 0.0f, pr = 0.0f;  // current x on the four edges
+        // ---- u_k of the pixel from xbar_{k-1} on its four edges
+        float u = 0.0f, bxb = 0.0f, xt = cur.xt;
         if (colok) {
-            if (have) {
-                xt = xbar_carry;
-                pt = x_carry;
-            } else {
-                xt = xbar1(top * P1 + j, pt);
-            }
-            xb = xbar1((top + 1) * P1 + j, pb);
-            xl = xbar2(i * P2 + left, pl);
-            xr = xbar2(i * P2 + left + 1, pr);
-            u = unew(i, xt, xb, xl, xr);
+            const float bxt = have ? xbar_carry : xbar(cur.xt, cur.xtp);
+            if (have) xt = x_carry;
+            bxb = xbar(cur.xb, cur.xbp);
+            const float d = (bxb - bxt) + (xbar(cur.xr, cur.xrp) - xbar(cur.xl, cur.xlp));
+            u = cp2_u(fid, cur.uv, d, sk, cur.fv, cur.mv != 0, sa, cv1, cv2);
         }
         float u_left = __shfl_up(u, 1, 64);
         if (cfirst) u_left = 0.0f;
+        // ---- x_k on the pixel's top and left edges, and on its bottom / right edges at the
+        // subdomain's last row / column (anchors -/+ tau lambda on the interface copies)
         if (outlane) {
-            uout[(long long)i * W + j] = u;
-            if (i > 0) {
-                float anchor = b1[top * P1 + j];
-                if (rfirst) anchor = fmaf(tau, lam[(long long)(rs - 1) * W + j], anchor);
-                o1[top * P1 + j] = pupdate(pt, u_up - u, anchor);
-            }
-            if (j > 0) {
-                float anchor = b2[i * P2 + left];
-                if (cfirst) anchor = fmaf(tau, lam[im.nlh + (long long)(cs - 1) * H + i], anchor);
-                o2[i * P2 + left] = pupdate(pl, u_left - u, anchor);
-            }
-            if (rlast && i < H - 1) {
-                const float anchor = fmaf(-tau, lam[(long long)rs * W + j], b1[(top + 1) * P1 + j]);
-                o1[(top + 1) * P1 + j] = pupdate(pb, u, anchor);
-            }
-            if (clast && j < W - 1) {
-                const float anchor = fmaf(-tau, lam[im.nlh + (long long)cs * H + i], b2[i * P2 + left + 1]);
-                o2[i * P2 + left + 1] = pupdate(pr, u, anchor);
-            }
+            uout[px] = u;
+            if (i > 0) o1[top * P1 + j] = pupdate(xt, u_up - u, rfirst ? fmaf(tau, cur.lt, cur.at) : cur.at);
+            if (j > 0) o2[i * P2 + left] = pupdate(cur.xl, u_left - u, cfirst ? fmaf(tau, cur.ll, cur.al) : cur.al);
+            if (rlast && i < H - 1) o1[(top + 1) * P1 + j] = pupdate(cur.xb, u, fmaf(-tau, cur.lb, cur.ab));
+            if (clast && j < W - 1) o2[i * P2 + left + 1] = pupdate(cur.xr, u, fmaf(-tau, cur.lr, cur.ar));
         }
         u_up = u;
-        xbar_carry = xb;
-        x_carry = pb;
+        xbar_carry = bxb;
+        x_carry = cur.xb;
         have = true;
+        cur = nxt;
     }
 }
 
