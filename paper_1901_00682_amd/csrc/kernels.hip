@@ -85,24 +85,28 @@ __global__ __launch_bounds__(64) void k_fista_step(FistaStepArgs a)
     const bool outlane = colok && lane >= 1;
     const long long P1 = im.pitch1, P2 = im.pitch2;
 
-    const float *xa1 = a.xa1 + im.p1, *xa2 = a.xa2 + im.p2;
-    const float *xb1 = MOM ? a.xb1 + im.p1 : nullptr, *xb2 = MOM ? a.xb2 + im.p2 : nullptr;
-    float *c1 = a.c1 + im.p1, *c2 = a.c2 + im.p2;
-    const float *lam = a.lam + im.lam;
-    const float *f = a.f + im.px;
-    float *o1 = a.out1 + im.p1, *o2 = a.out2 + im.p2;
+    // the outputs (new iterate, c' in the first step, pre-projection records) alias none of the
+    // inputs, so every load of a row is issued before the row's stores
+    const float *__restrict__ xa1 = a.xa1 + im.p1;
+    const float *__restrict__ xa2 = a.xa2 + im.p2;
+    const float *__restrict__ xb1 = MOM ? a.xb1 + im.p1 : nullptr;
+    const float *__restrict__ xb2 = MOM ? a.xb2 + im.p2 : nullptr;
+    float *__restrict__ c1 = a.c1 + im.p1;
+    float *__restrict__ c2 = a.c2 + im.p2;
+    const float *__restrict__ lam = a.lam + im.lam;
+    const float *__restrict__ f = a.f + im.px;
+    float *__restrict__ o1 = a.out1 + im.p1;
+    float *__restrict__ o2 = a.out2 + im.p2;
     const bool rec = a.z1 != nullptr;
-    float *zr1 = rec ? a.z1 + im.p1 : nullptr, *zr2 = rec ? a.z2 + im.p2 : nullptr;
+    float *__restrict__ zr1 = rec ? a.z1 + im.p1 : nullptr;
+    float *__restrict__ zr2 = rec ? a.z2 + im.p2 : nullptr;
     const float beta = a.beta, tau = a.tau, itau = a.inv_tau;
     const float invL = im.invL, ak = im.a_keep, kL = im.kL;
 
-    auto y1 = [&](long long idx) -> float {
-        if constexpr (MOM) return fista_y(xa1[idx], xb1[idx], beta);
-        return xa1[idx];
-    };
-    auto y2 = [&](long long idx) -> float {
-        if constexpr (MOM) return fista_y(xa2[idx], xb2[idx], beta);
-        return xa2[idx];
+    // y = x + beta (x - x_prev) from the two loaded values
+    auto yv = [&](float x, float xp) -> float {
+        if constexpr (MOM) return fista_y(x, xp, beta);
+        return x;
     };
 
     const int i0 = tile.i0;
@@ -112,12 +116,21 @@ __global__ __launch_bounds__(64) void k_fista_step(FistaStepArgs a)
     if (i0 > 0 && !info_first(a.info[im.rinfo + i0])) {
         // halo row: divergence of the pixel above the strip, same subdomain
         const int i = i0 - 1;
-        const int top = i + info_sub(a.info[im.rinfo + i]);
+        const long long top = i + info_sub(a.info[im.rinfo + i]);
         if (colok) {
-            const float yt = y1(top * P1 + j), yb = y1((top + 1) * P1 + j);
-            d_up = div4(yt, yb, y2(i * P2 + left), y2(i * P2 + left + 1));
-            y_carry = yb;
+            const float xt = xa1[top * P1 + j], xb = xa1[(top + 1) * P1 + j];
+            const float xl = xa2[i * P2 + left], xr = xa2[i * P2 + left + 1];
+            float xtp = 0.0f, xbp = 0.0f, xlp = 0.0f, xrp = 0.0f;
+            if constexpr (MOM) {
+                xtp = xb1[top * P1 + j];
+                xbp = xb1[(top + 1) * P1 + j];
+                xlp = xb2[i * P2 + left];
+                xrp = xb2[i * P2 + left + 1];
+            }
             if constexpr (FIRST) f_up = f[(long long)i * W + j];
+            const float yb = yv(xb, xbp);
+            d_up = div4(yv(xt, xtp), yb, yv(xl, xlp), yv(xr, xrp));
+            y_carry = yb;
         }
         have = true;
     }
@@ -131,14 +144,42 @@ __global__ __launch_bounds__(64) void k_fista_step(FistaStepArgs a)
             d_up = 0.0f;
             f_up = 0.0f;
         }
-        float d = 0.0f, yt = 0.0f, yb = 0.0f, yl = 0.0f, yr = 0.0f, fv = 0.0f;
+        // ---- every load of the row first
+        float xt = 0.0f, xtp = 0.0f, xb = 0.0f, xbp = 0.0f, xl = 0.0f, xlp = 0.0f, xr = 0.0f, xrp = 0.0f;
+        float fv = 0.0f, ct = 0.0f, cl = 0.0f, cb = 0.0f, cr = 0.0f, lt = 0.0f, ll = 0.0f, lb = 0.0f, lr = 0.0f;
         if (colok) {
-            yt = have ? y_carry : y1(top * P1 + j);
-            yb = y1((top + 1) * P1 + j);
-            yl = y2(i * P2 + left);
-            yr = y2(i * P2 + left + 1);
+            if (!have) {
+                xt = xa1[top * P1 + j];
+                if constexpr (MOM) xtp = xb1[top * P1 + j];
+            }
+            xb = xa1[(top + 1) * P1 + j];
+            xl = xa2[i * P2 + left];
+            xr = xa2[i * P2 + left + 1];
+            if constexpr (MOM) {
+                xbp = xb1[(top + 1) * P1 + j];
+                xlp = xb2[i * P2 + left];
+                xrp = xb2[i * P2 + left + 1];
+            }
+            if constexpr (FIRST) {
+                fv = f[(long long)i * W + j];
+                if (rfirst && i > 0) lt = lam[(long long)(rs - 1) * W + j];
+                if (cfirst && j > 0) ll = lam[im.nlh + (long long)(cs - 1) * H + i];
+                if (rlast && i < H - 1) lb = lam[(long long)rs * W + j];
+                if (clast && j < W - 1) lr = lam[im.nlh + (long long)cs * H + i];
+            } else {
+                ct = c1[top * P1 + j];
+                cl = c2[i * P2 + left];
+                cb = c1[(top + 1) * P1 + j];
+                cr = c2[i * P2 + left + 1];
+            }
+        }
+        float d = 0.0f, yt = 0.0f, yb = 0.0f, yl = 0.0f, yr = 0.0f;
+        if (colok) {
+            yt = have ? y_carry : yv(xt, xtp);
+            yb = yv(xb, xbp);
+            yl = yv(xl, xlp);
+            yr = yv(xr, xrp);
             d = div4(yt, yb, yl, yr);
-            if constexpr (FIRST) fv = f[(long long)i * W + j];
         }
         float d_left = __shfl_up(d, 1, 64);
         float f_left = 0.0f;
@@ -149,52 +190,40 @@ __global__ __launch_bounds__(64) void k_fista_step(FistaStepArgs a)
         }
         if (outlane) {
             if (i > 0) {  // edge above the pixel (interior, or t copy of an interface)
-                float c;
+                float c = ct;
                 if constexpr (FIRST) {
-                    float anchor = yt;
-                    if (rfirst) anchor = fmaf(tau, lam[(long long)(rs - 1) * W + j], anchor);
-                    c = fista_cprime(anchor, f_up, fv, itau, invL);
+                    c = fista_cprime(rfirst ? fmaf(tau, lt, yt) : yt, f_up, fv, itau, invL);
                     c1[top * P1 + j] = c;
-                } else {
-                    c = c1[top * P1 + j];
                 }
                 const float z = fista_z(yt, d_up, d, c, ak, kL);
                 o1[top * P1 + j] = clamp1(z);
                 if (rec) zr1[top * P1 + j] = z;
             }
             if (j > 0) {  // edge left of the pixel
-                float c;
+                float c = cl;
                 if constexpr (FIRST) {
-                    float anchor = yl;
-                    if (cfirst) anchor = fmaf(tau, lam[im.nlh + (long long)(cs - 1) * H + i], anchor);
-                    c = fista_cprime(anchor, f_left, fv, itau, invL);
+                    c = fista_cprime(cfirst ? fmaf(tau, ll, yl) : yl, f_left, fv, itau, invL);
                     c2[i * P2 + left] = c;
-                } else {
-                    c = c2[i * P2 + left];
                 }
                 const float z = fista_z(yl, d_left, d, c, ak, kL);
                 o2[i * P2 + left] = clamp1(z);
                 if (rec) zr2[i * P2 + left] = z;
             }
             if (rlast && i < H - 1) {  // s copy below the last row of the subdomain
-                float c;
+                float c = cb;
                 if constexpr (FIRST) {
-                    c = fista_cprime(fmaf(-tau, lam[(long long)rs * W + j], yb), fv, 0.0f, itau, invL);
+                    c = fista_cprime(fmaf(-tau, lb, yb), fv, 0.0f, itau, invL);
                     c1[(top + 1) * P1 + j] = c;
-                } else {
-                    c = c1[(top + 1) * P1 + j];
                 }
                 const float z = fista_z(yb, d, 0.0f, c, ak, kL);
                 o1[(top + 1) * P1 + j] = clamp1(z);
                 if (rec) zr1[(top + 1) * P1 + j] = z;
             }
             if (clast && j < W - 1) {  // s copy right of the last column
-                float c;
+                float c = cr;
                 if constexpr (FIRST) {
-                    c = fista_cprime(fmaf(-tau, lam[im.nlh + (long long)cs * H + i], yr), fv, 0.0f, itau, invL);
+                    c = fista_cprime(fmaf(-tau, lr, yr), fv, 0.0f, itau, invL);
                     c2[i * P2 + left + 1] = c;
-                } else {
-                    c = c2[i * P2 + left + 1];
                 }
                 const float z = fista_z(yr, d, 0.0f, c, ak, kL);
                 o2[i * P2 + left + 1] = clamp1(z);
