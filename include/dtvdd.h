@@ -92,11 +92,12 @@ extern "C" {
                                 fixed rule picks: persistent, else fused, else streaming */
 #define DTV_SCHED_STREAM 1   /* one launch per inner step over all subdomains */
 #define DTV_SCHED_FUSED 2    /* one workgroup per subdomain runs all inner steps on chip
-                                (FISTA, subdomains up to 128 x 128) */
+                                (FISTA: subdomains up to 128 x 128; CP2: every subdomain
+                                exactly 128 x 128) */
 #define DTV_SCHED_PERSIST 3  /* one cooperative launch runs every outer step; the iterates stay
-                                on chip between outer steps (FISTA, every subdomain exactly
-                                128 x 128, all of them resident on the device at once, no
-                                diagnostics, no save_for_backward) */
+                                on chip between outer steps (FISTA or CP2, every subdomain
+                                exactly 128 x 128, all of them resident on the device at once,
+                                no diagnostics, no save_for_backward) */
 
 typedef struct dtv_dd_plan dtv_dd_plan; /* opaque, owned by the library */
 
@@ -153,9 +154,9 @@ typedef struct {
                                   first step k with |p_k - p_(k-1)|_2 < inner_tol |p_k|_2 over its
                                   own edge dofs (or p_k = p_(k-1)), at most n_inner (the cap, <=
                                   100000) steps; the norms are summed in FP64.  FISTA with the
-                                  fused schedule (or auto, which then takes it) only: every
-                                  subdomain at most 128 x 128, no save_for_backward.  0: fixed
-                                  n_inner steps */
+                                  fused or the persistent schedule (or auto, which picks
+                                  between them) only: every subdomain at most 128 x 128, no
+                                  save_for_backward.  0: fixed n_inner steps */
 } dtv_dd_params;
 
 /* Where image `image` lives in the concatenated buffers (element offsets). */

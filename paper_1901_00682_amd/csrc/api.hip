@@ -189,6 +189,8 @@ static int check_cuts(const int32_t *given, int parts, int n, std::vector<int> &
 
 static bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
+static bool any_of_sched(int requested, int sched) { return requested == DTV_SCHED_AUTO || requested == sched; }
+
 // The autotuner's candidates: the schedules the plan admits (persistent, fused,
 // streaming) times the streaming rows (4, 8, 16, 32), restricted by explicit
 // choices in the parameters.
@@ -196,7 +198,11 @@ static std::vector<Choice> candidates(const dtv_dd_plan *pl)
 {
     const dtv_dd_params &p = pl->prm;
     std::vector<Choice> c;
-    if (pl->adaptive) return {{DTV_SCHED_FUSED, pl->rows}};  // the stopping rule lives in the fused kernel
+    if (pl->adaptive) {  // the stopping rule lives in the fused and persistent FISTA kernels
+        if ((any_of_sched(p.schedule, DTV_SCHED_PERSIST)) && pl->persist_ok) c.push_back({DTV_SCHED_PERSIST, pl->rows});
+        if (any_of_sched(p.schedule, DTV_SCHED_FUSED)) c.push_back({DTV_SCHED_FUSED, pl->rows});
+        return c;
+    }
     const bool any = p.schedule == DTV_SCHED_AUTO;
     if ((any || p.schedule == DTV_SCHED_PERSIST) && pl->persist_ok) c.push_back({DTV_SCHED_PERSIST, pl->rows});
     if ((any || p.schedule == DTV_SCHED_FUSED) && pl->fused_ok) c.push_back({DTV_SCHED_FUSED, pl->rows});
@@ -255,9 +261,9 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
     }
     if (full && p.save_for_backward) return fail(DTV_EINVAL, "full_problem takes no save_for_backward");
     if (!(p.inner_tol >= 0.0) || !std::isfinite(p.inner_tol)) return fail(DTV_EINVAL, "inner_tol must be finite and >= 0");
-    if (p.inner_tol > 0.0 && (p.inner != DTV_INNER_FISTA || p.save_for_backward ||
-                              (p.schedule != DTV_SCHED_AUTO && p.schedule != DTV_SCHED_FUSED)))
-        return fail(DTV_EINVAL, "inner_tol needs FISTA, the fused schedule (or auto) and no save_for_backward");
+    if (p.inner_tol > 0.0 && (p.inner != DTV_INNER_FISTA || p.save_for_backward || p.schedule == DTV_SCHED_STREAM))
+        return fail(DTV_EINVAL, "inner_tol needs FISTA, the fused or persistent schedule (or auto) and no "
+                                "save_for_backward");
     if (p.inner_tol > 0.0 && p.n_inner > kMaxAdaptiveInner)
         return fail(DTV_EINVAL, "inner_tol: n_inner (the cap) must be <= 100000");
     if (full)
@@ -383,8 +389,7 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
     }
     {
         const int nsub = (int)pl->h_subs.size();
-        pl->persist_ok = pl->fused_ok && nsub > 0 && pl->n_full == nsub && p.diag_every == 0 && !p.save_for_backward &&
-                         !pl->adaptive;
+        pl->persist_ok = pl->fused_ok && nsub > 0 && pl->n_full == nsub && p.diag_every == 0 && !p.save_for_backward;
         int dev = 0;
         if (pl->persist_ok && hipGetDevice(&dev) == hipSuccess)
             pl->persist_ok = persist_supported(dev) &&
@@ -394,9 +399,9 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
     }
     if (p.schedule == DTV_SCHED_PERSIST && !pl->persist_ok) {
         delete pl;
-        return fail(DTV_EINVAL, "the persistent schedule needs n_inner <= 64, every subdomain 128 x 128, all "
-                                "subdomains resident on the device at once, diag_every = 0, no save_for_backward and "
-                                "no inner_tol");
+        return fail(DTV_EINVAL, "the persistent schedule needs n_inner <= 64 (or inner_tol), every subdomain 128 x "
+                                "128, all subdomains resident on the device at once, diag_every = 0 and no "
+                                "save_for_backward");
     }
 
     // workspace layout

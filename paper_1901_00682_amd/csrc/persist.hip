@@ -43,6 +43,7 @@ struct PersistLds {
     FusedLds f;
     float lam[kSides][kFusedMax];  // lambda on the tile's interface edges
     float prv[kSides][kFusedMax];  // the tile's own copies on those edges at the previous outer step
+    double red[2 * kWaves];        // adaptive stopping: the per-wave sums of the relative-change test
     int ok;                        // every wait of the current step completed
 };
 
@@ -62,8 +63,10 @@ __device__ __forceinline__ void st2g(float *p, float x, float y)
 
 }  // namespace
 
-// KF > 0: the kernel for n_inner = KF (steps unrolled); KF = 0: any n_inner
-template <int KF>
+// KF > 0: the kernel for n_inner = KF (steps unrolled); KF = 0: any n_inner.
+// ADAPT (KF = 0): each local solve stops by the relative-change rule (fused_common.h,
+// a.fa.tol2, cap n_inner); the steps taken are counted per subdomain.
+template <int KF, bool ADAPT = false>
 __global__ __launch_bounds__(1024) void k_persist_fista(PersistArgs a)
 {
     __shared__ PersistLds L;
@@ -136,6 +139,7 @@ __global__ __launch_bounds__(1024) void k_persist_fista(PersistArgs a)
     }
     int rx_slot = 0;  // LDS slot of the right boundary column holding the current iterate
     bool ok = true;
+    int steps_total = 0, steps_max = 0;  // adaptive stopping: local steps of this subdomain
 
     for (int n = 0; n < a.n_outer; ++n) {
         // ---- (1) stage the current iterate on the four sides (dl is free between local solves)
@@ -217,7 +221,12 @@ __global__ __launch_bounds__(1024) void k_persist_fista(PersistArgs a)
         if (!ok) break;  // a neighbour stopped publishing: leave (the host reports the error)
 
         // ---- (5) the local FISTA solves
-        if constexpr (KF > 0) {
+        if constexpr (ADAPT) {
+            int taken = 0;
+            rx_slot = run_steps_adaptive<FullStep>(fc, S, A, B, a.fa.n_inner, a.fa.beta_dev, a.fa.tol2, L.red, taken);
+            steps_total += taken;
+            steps_max = max(steps_max, taken);
+        } else if constexpr (KF > 0) {
             rx_slot = full_steps_fixed<KF>(fc, S, A, B, a.fa.beta);
             if constexpr (KF & 1) copy_slot(A, B);
         } else {
@@ -238,6 +247,13 @@ __global__ __launch_bounds__(1024) void k_persist_fista(PersistArgs a)
         }
         if (fc.last) st2g(q1_tile + (long long)kFusedMax * P1 + ja, A.ba, A.bb);
         if (lane < kR) q2_tile[(long long)(il0 + lane) * P2 + kFusedMax] = S.rx[rx_slot][il0 + lane];
+    }
+    if constexpr (ADAPT) {
+        if (threadIdx.x == 0) {  // the subdomain's only workgroup
+            int *cnt = a.fa.counts + 2 * (long long)t;
+            cnt[0] += steps_total;
+            cnt[1] = max(cnt[1], steps_max);
+        }
     }
     if (side_wave && ok) {
         const int si = (s & 1) * 64 + lane;
@@ -287,11 +303,13 @@ int persist_capacity(int device)
 hipError_t launch_persist_fista(const PersistArgs &a, int nsub, hipStream_t s)
 {
     if (nsub <= 0 || a.n_outer <= 0) return hipSuccess;
-    if (a.fa.n_inner < 1 || a.fa.n_inner > kMaxFusedInner) return hipErrorInvalidValue;
+    const bool adapt = a.fa.tol2 > 0.0;
+    if (a.fa.n_inner < 1 || a.fa.n_inner > (adapt ? kMaxAdaptiveInner : kMaxFusedInner)) return hipErrorInvalidValue;
+    if (adapt && (!a.fa.beta_dev || !a.fa.counts)) return hipErrorInvalidValue;
     PersistArgs arg = a;
     void *args[] = {&arg};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(Persist::get(a.fa.n_inner)), dim3(nsub),
-                                      dim3(1024), args, 0, s);
+    const PersistKernel k = adapt ? k_persist_fista<0, true> : Persist::get(a.fa.n_inner);
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k), dim3(nsub), dim3(1024), args, 0, s);
 }
 
 }  // namespace dtv

@@ -71,7 +71,7 @@ def test_adaptive_matches_oracle(geom, tol, cap, n_outer, seed):
     assert o.inner_margin() > margin_needed(tol), f"oracle decision within {o.inner_margin():.2e} of the threshold"
     _say(f"[adaptive] {geom} {H}x{W} tol={tol} cap={cap} outer={n_outer}")
     plan, state, _ = run_gpu(f, 8.0, rc, cc, n_outer=n_outer, n_inner=cap, inner_tol=tol)
-    assert plan.schedule() == "fused"
+    assert plan.schedule() in ("fused", "persistent")
     got = plan.inner_counts()
     want = o.inner_counts()
     _say(f"  steps per subdomain {got[:, 0].tolist()} (cap {cap * n_outer})")
@@ -119,6 +119,26 @@ def test_huge_tolerance_takes_one_step():
     for q in ga:
         assert np.array_equal(ga[q], gf[q]), q
     assert np.all(pa.inner_counts() == [4, 1])
+
+
+@pytest.mark.parametrize("tol,cap,n_outer", [(5e-3, 30, 10), (1e-30, 7, 4), (3e-3, 150, 3)])
+def test_adaptive_persistent_equals_fused(tol, cap, n_outer):
+    """The stopping rule inside the persistent kernel (every outer step in
+    one launch): bitwise the fused schedule's iterates and step counts."""
+    H, W, rc, cc = 384, 384, [0, 128, 256, 384], [0, 128, 256, 384]
+    rng = np.random.default_rng(61 + cap)
+    f = (synth.shapes(H, W, rng) + synth.gaussian((H, W), 0.1, rng)).astype(np.float32)
+    _say(f"[adaptive persistent==fused] tol={tol} cap={cap} outer={n_outer}")
+    res, counts = {}, {}
+    for sch in ("fused", "persistent"):
+        plan, st, _ = run_gpu(f, 8.0, rc, cc, n_outer=n_outer, n_inner=cap, inner_tol=tol, schedule=sch)
+        assert plan.schedule() == sch
+        res[sch] = gpu_image_state(plan, st)
+        counts[sch] = plan.inner_counts()
+    assert np.array_equal(counts["fused"], counts["persistent"])
+    for q in res["fused"]:
+        assert np.array_equal(res["fused"][q], res["persistent"][q]), q
+    _say(f"  steps per subdomain {counts['fused'][:, 0].tolist()}")
 
 
 def test_adaptive_counts_reset_between_solves():

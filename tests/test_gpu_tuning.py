@@ -119,3 +119,43 @@ def test_autotune_measures_caches_and_keeps_numerics():
     assert c["source"] == "cached"
     assert (c["schedule"], c["rows"]) == (after["schedule"], after["rows"])
     _say(f"  chose {after}")
+
+
+@pytest.mark.parametrize("fidelity,K", [("CV", 5), ("L1", 4)])
+def test_graph_replays_fused_cp2(fidelity, K):
+    """The fused primal-dual schedule updates p~ and u in place (one multiplier
+    launch and one fused launch per outer step): graph replays equal the eager
+    solve on every replay, and the autotuned choice equals both."""
+    from paper_1901_00682_amd import dtvdd
+    H, W = 256, 384
+    rng = np.random.default_rng(90 + K)
+    clean = synth.shapes(H, W, rng)
+    f = (synth.salt_and_pepper(clean, 0.3, rng) if fidelity == "L1" else clean + synth.gaussian((H, W), 0.05, rng))
+    f = f.astype(np.float32)
+    extra = dict(tau=1.0, sigma=0.5, gamma=1.0 / 8.0, c1=0.6, c2=0.1) if fidelity == "CV" else {}
+    im = dtvdd.Image(H, W, [0, 128, 256], [0, 128, 256, 384], 5.0)
+    ft = torch.from_numpy(f.ravel()).cuda()
+    _say(f"[graph] fused cp2 {fidelity} K={K}")
+    eager = dtvdd.Plan([im], inner="CP2", fidelity=fidelity, n_outer=13, n_inner=K, schedule="fused", graphs=False,
+                       **extra)
+    se, _ = eager.solve(ft)
+    torch.cuda.synchronize()
+    ref = gpu_image_state(eager, se)
+    plan = dtvdd.Plan([im], inner="CP2", fidelity=fidelity, n_outer=13, n_inner=K, schedule="fused", **extra)
+    st = plan.new_state()
+    for rep in range(3):
+        plan.solve(ft, state=st)
+        torch.cuda.synchronize()
+        g = gpu_image_state(plan, st)
+        for q in ref:
+            assert np.array_equal(ref[q], g[q]), (rep, q)
+        eager.solve(ft)  # eager work between the replays
+    auto = dtvdd.Plan([im], inner="CP2", fidelity=fidelity, n_outer=60, n_inner=K, **extra)
+    sa, _ = auto.solve(ft)
+    fixed = dtvdd.Plan([im], inner="CP2", fidelity=fidelity, n_outer=60, n_inner=K, schedule="stream", rows=16,
+                       graphs=False, **extra)
+    sf, _ = fixed.solve(ft)
+    torch.cuda.synchronize()
+    for k in ("u", "p1", "p2", "lam"):
+        assert torch.equal(sa[k], sf[k]), k
+    _say(f"  autotuned {auto.choice()}")
