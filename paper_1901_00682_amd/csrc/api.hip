@@ -223,7 +223,8 @@ static std::string shape_key(const dtv_dd_plan *pl)
     (void)hipGetDevice(&dev);
     std::string k = "dev" + std::to_string(dev) + ":" + std::to_string(p.inner) + ":" + std::to_string(p.fidelity) +
                     ":" + std::to_string(p.has_mask) + ":" + std::to_string(p.n_inner) + ":" +
-                    std::to_string(p.schedule) + ":" + std::to_string(p.rows);
+                    std::to_string(p.schedule) + ":" + std::to_string(p.rows) + ":" +
+                    std::to_string(pl->adaptive ? 1 : 0) + ":" + std::to_string(p.full_problem);
     for (const ImgHost &h : pl->imgs) {
         k += "|" + std::to_string(h.H) + "x" + std::to_string(h.W) + ":";
         for (int v : h.rcut) k += std::to_string(v) + ",";
@@ -464,7 +465,14 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
         pl->key = shape_key(pl);
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(pl->key);
-        if (it != g_tune_cache.end()) {
+        // a cached choice is taken only where this plan admits it (the key covers what decides that)
+        bool admitted = false;
+        if (it != g_tune_cache.end())
+            for (const Choice &ch : candidates(pl))
+                if (ch.schedule == it->second.schedule && (ch.schedule != DTV_SCHED_STREAM || ch.rows == it->second.rows ||
+                                                           p.rows == 0))
+                    admitted = true;
+        if (it != g_tune_cache.end() && admitted) {
             pl->schedule = it->second.schedule;
             pl->rows = it->second.rows;
             pl->tuned = true;

@@ -152,3 +152,24 @@ def test_adaptive_counts_reset_between_solves():
     first = plan.inner_counts().copy()
     plan.solve(ft)
     assert np.array_equal(plan.inner_counts(), first)
+
+
+def test_adaptive_plan_does_not_take_a_fixed_count_choice():
+    """A measured choice of a fixed-count plan of the same shape is not reused
+    by an adaptive plan (the streaming schedule has no stopping rule)."""
+    from paper_1901_00682_amd import dtvdd
+    H, W, rc, cc = GEOMS["mixed"]
+    rng = np.random.default_rng(91)
+    f = (synth.shapes(H, W, rng) + synth.gaussian((H, W), 0.1, rng)).astype(np.float32)
+    ft = torch.from_numpy(f.ravel()).cuda()
+    im = dtvdd.Image(H, W, np.asarray(rc), np.asarray(cc), 8.0)
+    fixed = dtvdd.Plan([im], n_outer=80, n_inner=40)
+    fixed.solve(ft)
+    torch.cuda.synchronize()
+    adaptive = dtvdd.Plan([im], n_outer=80, n_inner=40, inner_tol=1e-2)
+    ch = adaptive.choice()
+    _say(f"  fixed-count plan chose {fixed.choice()}; adaptive plan starts from {ch}")
+    assert ch["schedule"] in ("fused", "persistent") and ch["source"] != "cached"
+    adaptive.solve(ft)
+    torch.cuda.synchronize()
+    assert adaptive.inner_counts()[:, 0].max() < 80 * 40
