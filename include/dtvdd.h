@@ -149,6 +149,9 @@ typedef struct {
                                   gamma >= 0; each outer step restarts it from the current
                                   iterate (n_outer = 1: n_inner plain iterations); no
                                   save_for_backward */
+    int32_t spin_limit;        /* persistent schedules: polls of one exchange word before a
+                                  tile gives up on a neighbour and the solve returns DTV_EHIP;
+                                  0: the default (2^21, about 0.1 s) */
     double inner_tol;          /* > 0: adaptive local solves (Sec. 6 stops them by relative change):
                                   each subdomain stops its FISTA steps in an outer step after the
                                   first step k with |p_k - p_(k-1)|_2 < inner_tol |p_k|_2 over its

@@ -282,6 +282,7 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
     if (p.rows != 0 && p.rows != 4 && p.rows != 8 && p.rows != 16 && p.rows != 32)
         return fail(DTV_EINVAL, "rows must be 0, 4, 8, 16 or 32");
     if (p.no_graphs != 0 && p.no_graphs != 1) return fail(DTV_EINVAL, "no_graphs must be 0 or 1");
+    if (p.spin_limit < 0) return fail(DTV_EINVAL, "spin_limit must be >= 0");
 
     dtv_dd_plan *pl = new dtv_dd_plan();
     pl->prm = p;
@@ -895,6 +896,7 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
     };
 
     // outer steps [n0, n0 + count) in one persistent launch; p~ and lambda updated in place
+    const unsigned spin_limit = P.spin_limit > 0 ? (unsigned)P.spin_limit : kSpinLimitDefault;
     auto run_persist = [&](int count) -> int {
         unsigned *sync = pl->sync_words();
         HIP_TRY(hipMemsetAsync(sync, 0, 2 * sizeof(unsigned), s), "clear error flag");
@@ -911,6 +913,7 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
             pc.err = (int *)sync;
             pc.n_outer = count;
             pc.sigma = (float)P.sigma;
+            pc.spin_limit = spin_limit;
             HIP_TRY(launch_persist_cp2(pc, (int)pl->h_subs.size(), s), "persistent primal-dual");
         } else {
             PersistArgs pa{};
@@ -924,6 +927,7 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
             pa.err = (int *)sync;
             pa.n_outer = count;
             pa.sigma = (float)P.sigma;
+            pa.spin_limit = spin_limit;
             HIP_TRY(launch_persist_fista(pa, (int)pl->h_subs.size(), s), "persistent FISTA");
         }
         if (tm.e1) HIP_TRY(hipEventRecord(tm.e1, s), "event");

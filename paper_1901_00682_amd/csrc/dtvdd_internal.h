@@ -54,6 +54,7 @@ inline int row_index(int R) { return R <= 4 ? 0 : R <= 8 ? 1 : R <= 16 ? 2 : 3; 
 constexpr int kFusedMax = 128;    // largest subdomain side handled by the fused kernel
 constexpr int kMaxFusedInner = 64;  // largest n_inner of the fused kernel
 constexpr int kMaxAdaptiveInner = 100000;  // largest cap on the local steps with adaptive stopping
+constexpr unsigned kSpinLimitDefault = 1u << 21;  // persistent schedules: polls of one exchange word (~0.1 s)
 
 // FISTA step of the streaming schedule.  The local gradient step
 //   z = y - (1/L) [div_s^*(f + div_s y / alpha) + (y - phat)/tau]
@@ -158,6 +159,7 @@ struct PersistCp2Args {
     int *err;
     int n_outer;
     float sigma;
+    unsigned spin_limit;
 };
 
 struct Cp2StepArgs {
@@ -217,6 +219,7 @@ struct PersistArgs {
     int *err;                 // set to 1 when a wait for a neighbour times out, 0 at launch
     int n_outer;
     float sigma;
+    unsigned spin_limit;      // polls of one exchange word before a wait gives up
 };
 bool persist_supported(int device);
 int persist_capacity(int device);  // workgroups of the persistent kernel resident at once

@@ -18,7 +18,6 @@ namespace dtv {
 namespace xchg {
 
 constexpr int kSides = 4;                // 0 top (t copies), 1 bottom (s), 2 left (t), 3 right (s)
-constexpr unsigned kSpinLimit = 1u << 21;  // polls of one exchange word before a tile gives up (~0.1 s)
 
 // exchange word: the copy in the low half, its outer step + 1 in the high half
 __device__ __forceinline__ void publish(unsigned long long *w, float q, int n)
@@ -27,10 +26,10 @@ __device__ __forceinline__ void publish(unsigned long long *w, float q, int n)
     __hip_atomic_store(w, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// waits for the step-n word; false after kSpinLimit polls
-__device__ __forceinline__ bool fetch(const unsigned long long *w, int n, float &q)
+// waits for the step-n word; false after `limit` polls
+__device__ __forceinline__ bool fetch(const unsigned long long *w, int n, float &q, unsigned limit)
 {
-    for (unsigned spins = 0; spins < kSpinLimit; ++spins) {
+    for (unsigned spins = 0; spins < limit; ++spins) {
         const unsigned long long v = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if ((unsigned)(v >> 32) == (unsigned)(n + 1)) {
             q = __uint_as_float((unsigned)v);

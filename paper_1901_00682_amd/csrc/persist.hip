@@ -203,7 +203,7 @@ __global__ __launch_bounds__(1024) void k_persist_fista(PersistArgs a)
             const int pj = side == 2 ? 0 : side == 3 ? kFusedMax - 1 : si;
             const float fp = f_tile[(long long)pi * W + pj];
             float q_oth = 0.0f;
-            if (fetch(xch + (side_s ? nlam : 0), n, q_oth)) {
+            if (fetch(xch + (side_s ? nlam : 0), n, q_oth, a.spin_limit)) {
                 const float qs = side_s ? q_own : q_oth, qt = side_s ? q_oth : q_own;
                 const float lam = L.lam[side][si] + a.sigma * (qs - qt);
                 L.lam[side][si] = lam;

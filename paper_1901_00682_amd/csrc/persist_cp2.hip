@@ -163,7 +163,7 @@ __global__ __launch_bounds__(1024) void k_persist_cp2(PersistCp2Args pa)
         // the tile's copy: phat = p^n + tau lambda on t copies (top, left), - tau lambda on s copies
         if (side_wave) {
             float q_oth = 0.0f;
-            if (fetch(xch + (side_s ? nlam : 0), n, q_oth)) {
+            if (fetch(xch + (side_s ? nlam : 0), n, q_oth, pa.spin_limit)) {
                 const float qs = side_s ? q_own : q_oth, qt = side_s ? q_oth : q_own;
                 const float lam = L.lam[side][si] + pa.sigma * (qs - qt);
                 L.lam[side][si] = lam;

@@ -99,6 +99,7 @@ def test_valid_setup_and_layout():
     (dict(inner_tol=1e-3, save_for_backward=1), "inner_tol needs FISTA"),
     (dict(inner_tol=1e-3, H=300, W=300, rc=(0, 150, 300), cc=(0, 150, 300)), "at most 128"),
     (dict(inner_tol=1e-3, n_inner=100001), "cap"),
+    (dict(spin_limit=-1), "spin_limit"),
 ])
 def test_validation_errors(kw, msg):
     code, h = _setup(**kw)

@@ -126,3 +126,33 @@ def test_persistent_rejected_when_not_applicable():
     with pytest.raises(dtvdd.DtvError):  # per-step diagnostics
         dtvdd.Plan([dtvdd.Image(256, 256, [0, 128, 256], [0, 128, 256], 8.0)], n_outer=2, diag_every=1,
                    schedule="persistent")
+
+
+@pytest.mark.parametrize("inner", ["FISTA", "CP2"])
+def test_exchange_timeout_is_reported(inner):
+    """The persistent schedules' waits are bounded; a poll limit of 1, forced
+    from the host, makes a wait give up unless the neighbour's word is already
+    there.  The solve then either completes and equals the normal solve, or
+    returns DTV_EHIP naming the timeout (every tile leaves its loop, so the
+    launch drains); a normal solve afterwards is unaffected."""
+    from paper_1901_00682_amd import dtvdd
+    H, W, rc, cc = GEOMS["full3x3"]
+    f = _image(H, W, 99)
+    ft = torch.from_numpy(f.ravel()).cuda()
+    im = dtvdd.Image(H, W, rc, cc, 8.0)
+    kw = dict(n_outer=20, n_inner=5, schedule="persistent", inner=inner)
+    ref, _ = dtvdd.Plan([im], **kw).solve(ft)
+    torch.cuda.synchronize()
+    try:
+        got, _ = dtvdd.Plan([im], spin_limit=1, **kw).solve(ft)
+        torch.cuda.synchronize()
+        for k in ("u", "p1", "p2", "lam"):
+            assert torch.equal(ref[k], got[k]), k
+        _say("  spin limit 1: every word was there in time")
+    except dtvdd.DtvError as e:
+        assert e.code == dtvdd.DTV_EHIP and "timed out" in str(e)
+        _say(f"  spin limit 1: {e}")
+    again, _ = dtvdd.Plan([im], **kw).solve(ft)
+    torch.cuda.synchronize()
+    for k in ("u", "p1", "p2", "lam"):
+        assert torch.equal(ref[k], again[k]), k
