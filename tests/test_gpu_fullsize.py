@@ -69,10 +69,11 @@ def _full_diff(n_outer):
     ubar = np.random.default_rng(55).standard_normal((B, H, W)).astype(np.float32)
     plan = dtvdd.Plan(imgs, n_outer=n_outer, n_inner=K, save_for_backward=True, ckpt_every=20)
     f = torch.from_numpy(np.stack([c.f for c in cases]).ravel()).cuda()
-    plan.solve(f, want_stats=False)
+    st, _ = plan.solve(f, want_stats=False)
     gf, ga = plan.backward(f, torch.from_numpy(ubar.ravel()).cuda())
     torch.cuda.synchronize()
-    return cases, ubar, gf.cpu().numpy().astype(np.float64).reshape(B, H, W), ga.cpu().numpy().astype(np.float64)
+    return (cases, ubar, gf.cpu().numpy().astype(np.float64).reshape(B, H, W), ga.cpu().numpy().astype(np.float64),
+            plan, st)
 
 
 def _oracle_grad(c, ubar, n_outer, f=None):
@@ -85,7 +86,7 @@ def test_differentiation_full_size_one_segment():
     """16 x 512^2, 4 x 4 subdomains, 5 inner steps, one checkpoint segment (20
     outer steps): the gradients of a sampled image against the oracle's
     reverse pass to 1e-4."""
-    cases, ubar, gf, ga = _full_diff(20)
+    cases, ubar, gf, ga, _, _ = _full_diff(20)
     b = 9
     fbar, abar = _oracle_grad(cases[b], ubar[b], 20)
     e_f, e_a = rel_l2(gf[b], fbar), abs(ga[b] - abar) / abs(abar)
@@ -103,9 +104,20 @@ def test_differentiation_full_size_within_conditioning():
     FP64 one by a few 1e-6 (relative L2 of p).  The GPU gradients must agree
     with the oracle's within three times the oracle's own change under a 1e-5
     perturbation (measured here, not assumed)."""
-    cases, ubar, gf, ga = _full_diff(200)
+    cases, ubar, gf, ga, plan, st = _full_diff(200)
     b = 9
     c = cases[b]
+    # active sets of the final iterate (edges at +-1), GPU against oracle
+    o = oracle_for(c.f, c.alpha, c.row_cuts, c.col_cuts, n_inner=c.n_inner)
+    o.run(200)
+    Q1, Q2 = o.to_torn(o.export()["p"])
+    g = gpu_image_state(plan, st, b)
+    act_o = np.concatenate([(np.abs(Q1) == 1.0).ravel(), (np.abs(Q2) == 1.0).ravel()])
+    act_g = np.concatenate([(np.abs(g["P1"]) == 1.0).ravel(), (np.abs(g["P2"]) == 1.0).ravel()])
+    differ = int((act_o != act_g).sum())
+    _say(f"[full size, 200 outer] active edges: oracle {int(act_o.sum())}, GPU {int(act_g.sum())}, "
+         f"differing {differ} of {act_o.size}")
+    assert differ <= 1e-3 * act_o.size
     _say("[full size, 200 outer] oracle reverse passes (unperturbed, perturbed f)")
     fbar, abar = _oracle_grad(c, ubar[b], 200)
     f0 = c.f.astype(np.float64)
