@@ -142,6 +142,16 @@ __global__ __launch_bounds__(1024) void k_persist_fista(PersistArgs a)
     int steps_total = 0, steps_max = 0;  // adaptive stopping: local steps of this subdomain
 
     for (int n = 0; n < a.n_outer; ++n) {
+        // ---- f of the strip's rows for the rebuild of c' (4a), issued first so that the loads
+        // travel during the staging and the publication (the second iterate slot is dead here)
+        // per outer step, so that the row addresses are formed here and not hoisted out of the loop
+        const int jo = opaque(ja);
+        float fra[kR], frb[kR];
+#pragma unroll
+        for (int r = 0; r < kR; ++r) ld2g(f_tile + (long long)(il0 + r) * W + jo, fra[r], frb[r]);
+        float fua = 0.0f, fub = 0.0f;  // f of the row above (0 above the tile)
+        if (il0 > 0) ld2g(f_tile + (long long)(il0 - 1) * W + jo, fua, fub);
+
         // ---- (1) stage the current iterate on the four sides (dl is free between local solves)
         __syncthreads();
         if (s == 0) lds_st2(&S.dl[0][ja], A.e1a[0], A.e1b[0]);
@@ -168,14 +178,6 @@ __global__ __launch_bounds__(1024) void k_persist_fista(PersistArgs a)
         // ---- (4a) while the neighbours' copies travel: c' of every edge from the anchor p^n (the
         // interface copies get their multiplier term in (4b)) and f, as in the fused kernel's prologue
         {
-            // per outer step, so that the row addresses are formed here and not hoisted out of the loop
-            const int jo = opaque(ja);
-            // all rows' loads first, then the conditional one (its wait covers them all)
-            float fra[kR], frb[kR];
-#pragma unroll
-            for (int r = 0; r < kR; ++r) ld2g(f_tile + (long long)(il0 + r) * W + jo, fra[r], frb[r]);
-            float fua = 0.0f, fub = 0.0f;  // f of the row above (0 above the tile)
-            if (il0 > 0) ld2g(f_tile + (long long)(il0 - 1) * W + jo, fua, fub);
 #pragma unroll
             for (int r = 0; r < kR; ++r) {
                 const int il = il0 + r;
