@@ -29,17 +29,12 @@ using namespace fused;
 
 
 
-// kFull: every tile of the launch is 128 x 128 (the list holds the full
-// tiles first; the full launch takes that prefix, the other launch the rest).
-// KF > 0: full tiles with n_inner = KF (steps unrolled); KF = 0: any n_inner.
-// REC: also record every step for reverse mode (full tiles, KF > 0; a.rec).
-// ADAPT: stop each subdomain's steps by the relative-change rule (a.tol2, KF = 0).
-template <bool kFull, int KF, bool REC = false, bool ADAPT = false>
-__global__ __launch_bounds__(1024) void k_fused_fista(FusedArgs a, int first)
+// One workgroup's work on subdomain t.  LS holds lambda^(n+1) on the top, bottom, left and
+// right sides; red is the reduction buffer of the adaptive rule (2 kWaves doubles).
+template <bool kFull, int KF, bool REC, bool ADAPT>
+__device__ __forceinline__ void fused_tile(const FusedArgs &a, int t, FusedLds &S, float (&LS)[4][kFusedMax],
+                                           double *red)
 {
-    __shared__ FusedLds S;
-    __shared__ float LS[4][kFusedMax];  // lambda^(n+1) on the top, bottom, left and right sides
-    const int t = first + xcd_remap(blockIdx.x, gridDim.x);
     const SubTile tl = a.subs[t];
     const ImgDev im = a.imgs[tl.img];
     Ctx c;
@@ -238,7 +233,6 @@ __global__ __launch_bounds__(1024) void k_fused_fista(FusedArgs a, int first)
     const int K = a.n_inner;
     int rx_slot = 0;  // LDS slot of the right boundary edges holding x_K
     int taken = K;    // steps taken (adaptive stopping)
-    __shared__ double red[ADAPT ? 2 * kWaves : 1];
     if constexpr (kFull) {
         FullCtx fc;
         fc.s = c.s;
@@ -318,6 +312,41 @@ __global__ __launch_bounds__(1024) void k_fused_fista(FusedArgs a, int first)
     }
 }
 
+// kFull: every tile of the launch is 128 x 128 (the list holds the full
+// tiles first; the full launch takes that prefix, the other launch the rest).
+// KF > 0: full tiles with n_inner = KF (steps unrolled); KF = 0: any n_inner.
+// REC: also record every step for reverse mode (full tiles, KF > 0; a.rec).
+// ADAPT: stop each subdomain's steps by the relative-change rule (a.tol2, KF = 0).
+template <bool kFull, int KF, bool REC = false, bool ADAPT = false>
+__global__ __launch_bounds__(1024) void k_fused_fista(FusedArgs a, int first)
+{
+    __shared__ FusedLds S;
+    __shared__ float LS[4][kFusedMax];
+    __shared__ double red[ADAPT ? 2 * kWaves : 1];
+    fused_tile<kFull, KF, REC, ADAPT>(a, first + xcd_remap(blockIdx.x, gridDim.x), S, LS, red);
+}
+
+// Both kinds of tile in one launch (fixed n_inner, no recording): blocks
+// [0, npad) take the partial tiles nfull .. nfull + npart - 1 (npad = npart
+// rounded up to a multiple of 8; the extra blocks exit at once), the rest the
+// full tiles 0 .. nfull - 1.  The partial tiles, slower per workgroup, are
+// dispatched first, spread over the XCDs; the full tiles keep the XCD-aware
+// order, and no launch boundary separates the two kinds.
+template <int KF>
+__global__ __launch_bounds__(1024) void k_fused_fista_mixed(FusedArgs a, int nfull, int npart)
+{
+    __shared__ FusedLds S;
+    __shared__ float LS[4][kFusedMax];
+    __shared__ double red[1];
+    const int npad = (npart + 7) & ~7;
+    const int b = blockIdx.x;
+    if (b < npad) {
+        if (b < npart) fused_tile<false, 0, false, false>(a, nfull + b, S, LS, red);
+    } else {
+        fused_tile<true, KF, false, false>(a, xcd_remap(b - npad, gridDim.x - npad), S, LS, red);
+    }
+}
+
 namespace {
 
 using FusedKernel = void (*)(FusedArgs, int);
@@ -334,6 +363,19 @@ struct FullTable {
     }
 };
 using Full = FullTable<1, 2, 3, 4, 5, 6, 7, 8, 10>;
+
+using MixedKernel = void (*)(FusedArgs, int, int);
+
+template <int... Ks>
+struct MixedTable {
+    static MixedKernel get(int K)
+    {
+        MixedKernel k = nullptr;
+        ((K == Ks ? (k = k_fused_fista_mixed<Ks>, 0) : 0), ...);
+        return k ? k : k_fused_fista_mixed<0>;
+    }
+};
+using Mixed = MixedTable<1, 2, 3, 4, 5, 6, 7, 8, 10>;
 
 }  // namespace
 
@@ -369,6 +411,15 @@ hipError_t launch_fused_fista(const FusedArgs &a, int nsub, int nfull, hipStream
             else
                 hipLaunchKernelGGL((k_fused_fista<false, 0, false, true>), dim3(npart), dim3(1024), 0, s, a, nfull);
         }
+        return hipGetLastError();
+    }
+    if (nfull > 0 && npart > 0 && !a.rec) {  // one launch for both kinds of tile
+        const MixedKernel km = Mixed::get(a.n_inner);
+        const int grid = ((npart + 7) & ~7) + nfull;
+        if (e0)
+            hipExtLaunchKernelGGL(km, dim3(grid), dim3(1024), 0, s, e0, e1, 0, a, nfull, npart);
+        else
+            hipLaunchKernelGGL(km, dim3(grid), dim3(1024), 0, s, a, nfull, npart);
         return hipGetLastError();
     }
     // the timing events bracket both launches

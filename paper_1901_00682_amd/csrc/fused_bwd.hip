@@ -139,7 +139,7 @@ __device__ __forceinline__ void bwd_step(const BwdCtx &c, BwdLds &L, Slot &Z, Sl
     za7 = c.last ? Z.ba : za7;
     zb7 = c.last ? Z.bb : zb7;
     float da7, db7;
-    full_row_div(Z, RZr, kR - 1, za7, zb7, da7, db7);
+    full_row_div(Z, RZr[kR - 1], kR - 1, za7, zb7, da7, db7);
     lds_st2(&L.dl[c.s][c.ja], da7, db7);
     __syncthreads();
 
@@ -151,7 +151,7 @@ __device__ __forceinline__ void bwd_step(const BwdCtx &c, BwdLds &L, Slot &Z, Sl
     for (int r = 0; r < kR; ++r) {
         __builtin_amdgcn_sched_barrier(0);  // one row at a time: bounds the registers in flight
         float da = da7, db = db7;
-        if (r < kR - 1) full_row_div(Z, RZr, r, Z.e1a[r + 1], Z.e1b[r + 1], da, db);
+        if (r < kR - 1) full_row_div(Z, RZr[r], r, Z.e1a[r + 1], Z.e1b[r + 1], da, db);
         const float dlb = from_left(db);  // div zbar of column a - 1 (0 left of the tile)
         float y1a = fmaf(-kL, dua - da, ak * Z.e1a[r]);
         float y1b = fmaf(-kL, dub - db, ak * Z.e1b[r]);

@@ -231,12 +231,12 @@ __device__ __forceinline__ float from_right_or(float x, float edge)
         __builtin_amdgcn_update_dpp(__float_as_int(edge), __float_as_int(x), 0x130, 0xF, 0xF, false));
 }
 
-// unscaled divergence of the two pixels of row r of a full tile; RYr points
-// at the right boundary edge of the strip's first row
-__device__ __forceinline__ void full_row_div(const Slot &Y, const float *RYr, int r, float ya_below, float yb_below,
+// unscaled divergence of the two pixels of row r of a full tile; ry is y on
+// the right boundary edge of the row
+__device__ __forceinline__ void full_row_div(const Slot &Y, float ry, int r, float ya_below, float yb_below,
                                              float &da, float &db)
 {
-    const float yrb = from_right_or(Y.e2a[r], RYr[r]);
+    const float yrb = from_right_or(Y.e2a[r], ry);
     da = div4(Y.e1a[r], ya_below, Y.e2a[r], Y.e2b[r]);
     db = div4(Y.e1b[r], yb_below, Y.e2b[r], yrb);
 }
@@ -285,21 +285,23 @@ __device__ __forceinline__ void full_step(const FullCtx &c, FusedLds &S, const S
         Y.e2b[r] = mom ? fista_y(X.e2b[r], Y.e2b[r], beta) : X.e2b[r];
         pin4(Y.e1a[r], Y.e1b[r], Y.e2a[r], Y.e2b[r]);
     }
-    Y.ba = mom ? fista_y(X.ba, Y.ba, beta) : X.ba;  // meaningful in strip 15 only
-    Y.bb = mom ? fista_y(X.bb, Y.bb, beta) : X.bb;
+    if (REC || c.last) {  // the bottom boundary edges (strip 15)
+        Y.ba = mom ? fista_y(X.ba, Y.ba, beta) : X.ba;
+        Y.bb = mom ? fista_y(X.bb, Y.bb, beta) : X.bb;
+    }
     float *yt = &S.yt[sx][0][0] + oy;  // this strip's row of the exchange buffer (strip 0's is unused)
     lds_st2(yt, Y.e1a[0], Y.e1b[0]);
     __syncthreads();
 
     // (2) d of the strip's last row, published for the strip below
-    const float *RYr = RY + orow;
+    const float *RYr = RY + orow;  // y on the right boundary edges of the strip's rows (lane 63 uses them)
     float ya7, yb7;  // y on the edges below the last row
     lds_ld2(yt + kFusedMax, ya7, yb7);  // strip 15 reads a neighbouring array here and discards it
     ya7 = c.last ? Y.ba : ya7;
     yb7 = c.last ? Y.bb : yb7;
     float *dl = &S.dl[0][0] + oy;
     float da7, db7;  // d of the last row (the row sweep reuses it)
-    full_row_div(Y, RYr, kR - 1, ya7, yb7, da7, db7);
+    full_row_div(Y, RYr[kR - 1], kR - 1, ya7, yb7, da7, db7);
     lds_st2(dl, da7, db7);
     __syncthreads();
 
@@ -315,7 +317,7 @@ __device__ __forceinline__ void full_step(const FullCtx &c, FusedLds &S, const S
     for (int r = 0; r < kR; ++r) {
         __builtin_amdgcn_sched_barrier(0);  // one row at a time: bounds the registers in flight
         float da = da7, db = db7;
-        if (r < kR - 1) full_row_div(Y, RYr, r, Y.e1a[r + 1], Y.e1b[r + 1], da, db);
+        if (r < kR - 1) full_row_div(Y, RYr[r], r, Y.e1a[r + 1], Y.e1b[r + 1], da, db);
         const float dlb = from_left(db);
         if constexpr (REC)
             rec[r * kRecThreads] =
@@ -330,19 +332,23 @@ __device__ __forceinline__ void full_step(const FullCtx &c, FusedLds &S, const S
         Y.e1b[r] = proj<REC>(fista_z(Y.e1b[r], dub, db, c1b, ak, kL), lo1, hi1, m0, 4 * r + 1);
         Y.e2a[r] = proj<REC>(fista_z(Y.e2a[r], dlb, da, c2a, ak, kL), c.lo2a, c.hi2a, m0, 4 * r + 2);
         Y.e2b[r] = proj<REC>(fista_z(Y.e2b[r], da, db, c2b, ak, kL), -1.0f, 1.0f, m0, 4 * r + 3);
-        if (r == kR - 1) {  // bottom boundary edges of the tile (strip 15, unless on the image boundary)
+        // bottom boundary edges of the tile (strip 15; 0 on the image boundary).  The branch is
+        // wave-uniform; the recording step keeps the straight line (fewer registers live).
+        if (r == kR - 1 && (REC || c.last)) {
             float cba, cbb;
             lds_ld2(S.cb + (oy - c.s * kFusedMax), cba, cbb);
             if constexpr (REC) {
                 qba = fmaf(c.qb, da, c.qa * Y.ba);
                 qbb = fmaf(c.qb, db, c.qa * Y.bb);
             }
-            // only strip 15 uses them; they collapse to 0 on the image boundary
+            // they collapse to 0 on the image boundary
             Y.ba = proj<REC>(fista_z(Y.ba, da, 0.0f, cba, ak, kL), c.lob, c.hib, m1, 0);
             Y.bb = proj<REC>(fista_z(Y.bb, db, 0.0f, cbb, ak, kL), c.lob, c.hib, m1, 1);
         }
-        if (c.lane == 63) S.dR[orow + r] = db;  // the last column's d, for the right boundary edges
         pin4(Y.e1a[r], Y.e1b[r], Y.e2a[r], Y.e2b[r]);
+        // the last column's d, for the right boundary edges; stored after the row's updates so
+        // that the lane shift of d above stays in one block with its use and folds into it
+        if (c.lane == 63) S.dR[orow + r] = db;
         dua = da;
         dub = db;
     }
