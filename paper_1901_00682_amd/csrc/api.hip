@@ -1337,9 +1337,12 @@ extern "C" int dtv_dd_kernel_time(const dtv_dd_plan *pl, double *avg_ms, int64_t
     const bool cp2 = pl->prm.inner == DTV_INNER_CP2;
     const bool fused = pl->schedule == DTV_SCHED_FUSED;
     const bool persist = pl->schedule == DTV_SCHED_PERSIST;
+    // full and ragged subdomains share one fused FISTA launch unless the solve is adaptive
+    const bool mixed = pl->n_full > 0 && pl->n_full < (int)pl->h_subs.size() && !pl->adaptive;
     if (name)
         *name = persist ? (cp2 ? "k_persist_cp2" : "k_persist_fista")
-                        : fused ? (cp2 ? "k_fused_cp2" : "k_fused_fista") : (cp2 ? "k_cp2_step" : "k_fista_step");
+                : fused ? (cp2 ? "k_fused_cp2" : mixed ? "k_fused_fista_mixed" : "k_fused_fista")
+                        : (cp2 ? "k_cp2_step" : "k_fista_step");
     if (bytes_per_launch) {
         // Algorithmic HBM bytes of one timed launch (E = edge dofs of the torn
         // p~, N = pixels, 4 bytes each), averaged over the launches of an outer step.

@@ -113,6 +113,9 @@ def test_fused_equals_stream_bitwise(geom, K):
     for sch in ("stream", "fused"):
         plan, state, _, _, _ = run_gpu(f, 8.0, rc, cc, n_outer=6, n_inner=K, schedule=sch)
         assert plan.schedule() == sch
+        if sch == "fused":  # full and ragged subdomains share one launch when both occur
+            want = "k_fused_fista_mixed" if geom == "mixed" else "k_fused_fista"
+            assert plan.kernel_time()["name"] == want
         res[sch] = gpu_image_state(plan, state)
     for q in res["stream"]:
         assert np.array_equal(res["stream"][q], res["fused"][q]), q
