@@ -152,13 +152,16 @@ __global__ __launch_bounds__(1024) void k_persist_fista(PersistArgs a)
         float fua = 0.0f, fub = 0.0f;  // f of the row above (0 above the tile)
         if (il0 > 0) ld2g(f_tile + (long long)(il0 - 1) * W + jo, fua, fub);
 
-        // ---- (1) stage the current iterate on the four sides (dl is free between local solves)
-        __syncthreads();
-        if (s == 0) lds_st2(&S.dl[0][ja], A.e1a[0], A.e1b[0]);
-        if (fc.last) lds_st2(&S.dl[1][ja], A.ba, A.bb);
+        // ---- (1) stage the current iterate on the top, bottom and left sides.  The staging rows
+        // are LDS rows that the steps write but never read, so no barrier has to separate these
+        // stores from the last step's reads: d of strip 15's last row (no strip below reads it),
+        // the parity-0 top-edge row of strip 0 (no strip above reads it), and the last column's d
+        // (each wave's own rows, written and read by that wave alone).
+        if (s == 0) lds_st2(&S.dl[kWaves - 1][ja], A.e1a[0], A.e1b[0]);
+        if (fc.last) lds_st2(&S.yt[0][0][ja], A.ba, A.bb);
         if (lane == 0) {
 #pragma unroll
-            for (int r = 0; r < kR; ++r) S.dl[2][il0 + r] = A.e2a[r];
+            for (int r = 0; r < kR; ++r) S.dR[il0 + r] = A.e2a[r];
         }
         if (threadIdx.x == 0) L.ok = 1;
         __syncthreads();
@@ -167,7 +170,7 @@ __global__ __launch_bounds__(1024) void k_persist_fista(PersistArgs a)
         unsigned long long *xch = a.xch + (long long)(n & 1) * a.xch_stride + im.lam + side_base + si;
         float x_side = 0.0f, q_own = 0.0f;
         if (side_wave) {
-            x_side = side == 3 ? S.rx[rx_slot][si] : S.dl[side][si];
+            x_side = side == 3 ? S.rx[rx_slot][si] : side == 0 ? S.dl[kWaves - 1][si] : side == 1 ? S.yt[0][0][si] : S.dR[si];
             q_own = 2.0f * x_side - L.prv[side][si];
             L.prv[side][si] = x_side;
             publish(xch + (side_s ? 0 : nlam), q_own, n);

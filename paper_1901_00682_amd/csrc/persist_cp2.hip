@@ -126,8 +126,8 @@ __global__ __launch_bounds__(1024) void k_persist_cp2(PersistCp2Args pa)
 
     for (int n = 0; n < pa.n_outer; ++n) {
         // ---- (1) stage the current iterate on the top, bottom and left sides (the right
-        // boundary column is in S.rx)
-        __syncthreads();
+        // boundary column is in S.rx).  The staging rows are read only by the publication below,
+        // and the previous solve's barriers separate that read from these stores.
         if (s == 0) lds_st2(&L.stage[0][ja], X.e1a[0], X.e1b[0]);
         if (last) lds_st2(&L.stage[1][ja], X.ba, X.bb);
         if (lane == 0) {
