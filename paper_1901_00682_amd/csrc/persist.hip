@@ -178,27 +178,33 @@ __global__ __launch_bounds__(1024) void k_persist_fista(PersistArgs a)
         // the right boundary column of the iterate goes to slot 0 (the first step reads it there)
         if (rx_slot == 1 && lane < kR) S.rx[0][il0 + lane] = S.rx[1][il0 + lane];
 
-        // ---- (4a) while the neighbours' copies travel: c' of every edge from the anchor p^n (the
-        // interface copies get their multiplier term in (4b)) and f, as in the fused kernel's prologue
+        // ---- (4a) while the neighbours' copies travel: c' of every edge from the anchor p^n and f,
+        // as in the fused kernel's prologue, except the interface copies, which (4b) writes once
+        // lambda^(n+1) is known; the two phases write disjoint entries, so no barrier separates them
         {
+            const bool top_if = side_exists(im, tl, 0), bot_if = side_exists(im, tl, 1);
+            const bool left_if = side_exists(im, tl, 2), right_if = side_exists(im, tl, 3);
 #pragma unroll
             for (int r = 0; r < kR; ++r) {
                 const int il = il0 + r;
                 const float fva = fra[r], fvb = frb[r];
                 const float fla = from_left(fvb);  // f of column a - 1 (lane 0: left of the tile, 0)
-                lds_st2(&S.c1[il][ja], fista_cprime(A.e1a[r], fua, fva, itau, invL),
-                        fista_cprime(A.e1b[r], fub, fvb, itau, invL));
-                lds_st2(&S.c2[il][ja], fista_cprime(A.e2a[r], ja > 0 ? fla : 0.0f, fva, itau, invL),
-                        fista_cprime(A.e2b[r], fva, fvb, itau, invL));
-                if (il == kFusedMax - 1)  // bottom boundary edges
+                if (!(il == 0 && top_if))
+                    lds_st2(&S.c1[il][ja], fista_cprime(A.e1a[r], fua, fva, itau, invL),
+                            fista_cprime(A.e1b[r], fub, fvb, itau, invL));
+                const float c2a = fista_cprime(A.e2a[r], ja > 0 ? fla : 0.0f, fva, itau, invL);
+                const float c2b = fista_cprime(A.e2b[r], fva, fvb, itau, invL);
+                if (ja == 0 && left_if) S.c2[il][1] = c2b;
+                else lds_st2(&S.c2[il][ja], c2a, c2b);
+                if (il == kFusedMax - 1 && !bot_if)  // bottom boundary edges on the image boundary
                     lds_st2(&S.cb[ja], fista_cprime(A.ba, fva, 0.0f, itau, invL),
                             fista_cprime(A.bb, fvb, 0.0f, itau, invL));
-                if (lane == 63) S.cr[il] = fista_cprime(S.rx[0][il], fvb, 0.0f, itau, invL);  // right boundary edge
+                if (lane == 63 && !right_if)  // right boundary edge on the image boundary
+                    S.cr[il] = fista_cprime(S.rx[0][il], fvb, 0.0f, itau, invL);
                 fua = fva;
                 fub = fvb;
             }
         }
-        __syncthreads();
 
         // ---- (2) the neighbour's copy of each interface edge, (3) lambda^(n+1), (4b) c' of the
         // interface copies from phat = p^n -/+ tau lambda^(n+1) (t copies +, s copies -)
