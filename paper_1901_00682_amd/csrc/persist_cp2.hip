@@ -147,17 +147,22 @@ __global__ __launch_bounds__(1024) void k_persist_cp2(PersistCp2Args pa)
             publish(xch + (side_s ? 0 : nlam), q_own, n);
         }
 
-        // ---- (2) anchors phat = p^n on every edge (the interface copies get their multiplier
-        // term in (4)) while the neighbours' copies travel
+        // ---- (2) anchors phat = p^n while the neighbours' copies travel, on every edge but the
+        // interface copies, which (4) writes with their multiplier term; the two phases write
+        // disjoint entries, so no barrier separates them
+        {
+            const bool top_if = side_exists(im, tl, 0), bot_if = side_exists(im, tl, 1);
+            const bool left_if = side_exists(im, tl, 2), right_if = side_exists(im, tl, 3);
 #pragma unroll
-        for (int r = 0; r < kR; ++r) {
-            const int il = il0 + r;
-            lds_st2(&S.a1[il][ja], X.e1a[r], X.e1b[r]);
-            lds_st2(&S.a2[il][ja], X.e2a[r], X.e2b[r]);
+            for (int r = 0; r < kR; ++r) {
+                const int il = il0 + r;
+                if (!(il == 0 && top_if)) lds_st2(&S.a1[il][ja], X.e1a[r], X.e1b[r]);
+                if (ja == 0 && left_if) S.a2[il][1] = X.e2b[r];
+                else lds_st2(&S.a2[il][ja], X.e2a[r], X.e2b[r]);
+            }
+            if (last && !bot_if) lds_st2(&S.ab[ja], X.ba, X.bb);
+            if (lane < kR && !right_if) S.ar[il0 + lane] = S.rx[il0 + lane];
         }
-        if (last) lds_st2(&S.ab[ja], X.ba, X.bb);
-        if (lane < kR) S.ar[il0 + lane] = S.rx[il0 + lane];
-        __syncthreads();
 
         // ---- (3) the neighbour's copy of each interface edge, lambda^(n+1), and (4) the anchor of
         // the tile's copy: phat = p^n + tau lambda on t copies (top, left), - tau lambda on s copies
