@@ -97,13 +97,13 @@ FUSED_GEOMS = {
 }
 
 
-@pytest.mark.parametrize("geom,K", [("mixed", k) for k in (1, 2, 3, 4, 5, 7)]
+@pytest.mark.parametrize("geom,K", [("mixed", k) for k in (1, 2, 3, 4, 5, 7, 9)]
                          + [("full3x3", k) for k in (1, 2, 5, 6)] + [("full1x1", 3)])
 def test_fused_equals_stream_bitwise(geom, K):
     """The two schedules of the FISTA local solves round identically: full
     128 x 128 subdomains (the specialised kernel) with image boundaries and
     interfaces on every combination of sides, ragged ones, and every parity of
-    the inner count."""
+    the inner count (K = 9 takes the runtime step loop)."""
     rng = np.random.default_rng(100 + K + 1000 * list(FUSED_GEOMS).index(geom))
     H, W, rc, cc = FUSED_GEOMS[geom]
     rc, cc = np.array(rc), np.array(cc)
