@@ -651,7 +651,7 @@ static std::vector<float> fista_betas(int K);
 static int next_base(int sched, bool cp2, int K, int base)
 {
     if (sched == DTV_SCHED_PERSIST) return base;
-    if (sched == DTV_SCHED_FUSED) return cp2 ? base : (base == 0 ? 1 : 0);  // the fused CP2 kernel works in place
+    if (sched == DTV_SCHED_FUSED) return base == 0 ? 1 : 0;  // the fused kernels read one buffer and write the other
     if (!cp2) {
         int rot[3] = {base, 0, 0}, q = 1;
         for (int k = 0; k < 3; ++k)
@@ -762,7 +762,10 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
         ca.subs = pl->d_subs();
         ca.p1 = bufs[base].p1;
         ca.p2 = bufs[base].p2;
+        ca.out1 = ca.p1;  // in place (the persistent kernel); the fused step sets its own outputs
+        ca.out2 = ca.p2;
         ca.lam = lam_cur;
+        ca.sigma = (float)P.sigma;
         ca.f = d_f;
         ca.mask = mask;
         ca.u = u_cur;
@@ -790,14 +793,18 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
             int rc = save_state(n / P.ckpt_every, bufs[base]);
             if (rc != DTV_OK) return rc;
         }
-        // (a1) multipliers from the extrapolated interface jump: inside the fused kernel, else a launch
-        if (sched != DTV_SCHED_FUSED || cp2)
+        // (a1) multipliers from the extrapolated interface jump: inside the fused kernels, else a launch
+        if (sched != DTV_SCHED_FUSED)
             HIP_TRY(launch_lambda(pl->d_imgs(), pl->n, pl->max_nlam, pl->d_info(), bufs[base].p1, bufs[base].p2,
                                   lam_cur, (float)P.sigma, q),
                     "lambda update");
         // (a2)+(a3) local solves; the anchor phat is formed on the fly from p~^n and lambda
         if (sched == DTV_SCHED_FUSED && cp2) {
+            const int out = next_base(sched, cp2, K, base);
             FusedCp2Args ca = cp2_args();
+            ca.out1 = bufs[out].p1;
+            ca.out2 = bufs[out].p2;
+            ca.lam_out = lam_other();
             int rc = with_host ? tm.begin() : DTV_OK;
             if (rc != DTV_OK) return rc;
             HIP_TRY(launch_fused_cp2(ca, (int)pl->h_subs.size(), q, with_host ? tm.e0 : nullptr,
@@ -805,6 +812,8 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
                     "fused CP2");
             rc = with_host ? tm.end() : DTV_OK;
             if (rc != DTV_OK) return rc;
+            base = out;
+            lam_cur = lam_other();
         } else if (sched == DTV_SCHED_FUSED) {
             const int out = next_base(sched, cp2, K, base);
             fa.base1 = bufs[base].p1; fa.base2 = bufs[base].p2;
@@ -957,7 +966,7 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
                 seq.push_back(state(b, uf, lp));
                 b = next_base(sched, cp2, K, b);
                 if (cp2 && sched != DTV_SCHED_FUSED && (K & 1)) uf = !uf;
-                if (sched == DTV_SCHED_FUSED && !cp2) lp = !lp;
+                if (sched == DTV_SCHED_FUSED) lp = !lp;
             }
             int start = -1, period = 0;
             for (int i = 0; i < 4 && start < 0; ++i)

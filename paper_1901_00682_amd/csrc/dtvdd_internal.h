@@ -137,8 +137,12 @@ struct FusedArgs {
 struct FusedCp2Args {
     const ImgDev *imgs;
     const SubTile *subs;       // the (full) subdomains
-    float *p1, *p2;            // p~^n in, p~^(n+1) out (each tile reads and writes only its own copies)
-    const float *lam;          // lambda state after the multiplier update (lambda^(n+1) first)
+    float *p1, *p2;            // p~^n in (the persistent kernel: also p~^(n+1) out, in place)
+    float *out1, *out2;        // fused kernel: p~^(n+1) out (not p1, p2: the tiles read each other's copies)
+    const float *lam;          // fused kernel: lambda state before the multiplier update;
+                               // persistent kernel: lambda state in
+    float *lam_out;            // fused kernel: lambda state after the update (not lam)
+    float sigma;               // multiplier step
     const float *f;
     const uint8_t *mask;       // NULL: every pixel observed
     float *u;                  // u in and out

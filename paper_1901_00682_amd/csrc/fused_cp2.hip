@@ -4,7 +4,10 @@
 // 1024-thread workgroup owns one subdomain and runs all n_inner steps of an
 // outer iteration on chip.
 // The on-chip layout and the step are those of cp2_tile.h; this kernel loads
-// the tile, forms the anchors from p~^n and lambda^(n+1), solves and stores.
+// the tile, updates the multipliers of its interfaces (Algorithm 1, first
+// line), forms the anchors from p~^n and lambda^(n+1), solves and stores
+// p~^(n+1) into the other edge buffer (a neighbouring tile may still read this
+// tile's copies of p~^n for its own multiplier update).
 #include "cp2_tile.h"
 
 namespace dtv {
@@ -17,6 +20,7 @@ template <int FID, bool MASK>
 __global__ __launch_bounds__(1024) void k_fused_cp2(FusedCp2Args a)
 {
     __shared__ Cp2Lds S;
+    __shared__ float LS[4][kFusedMax];  // lambda^(n+1) on the top, bottom, left and right sides
     const int t = xcd_remap(blockIdx.x, gridDim.x);
     const SubTile tl = a.subs[t];
     const ImgDev im = a.imgs[tl.img];
@@ -31,13 +35,14 @@ __global__ __launch_bounds__(1024) void k_fused_cp2(FusedCp2Args a)
     const long long P1 = im.pitch1, P2 = im.pitch2;
     const long long row1 = (long long)tl.ra + tl.r;  // P1 row of the tile's edge row 0
     const long long col2 = (long long)tl.ca + tl.c;  // P2 column of the tile's edge column 0
-    float *p1_tile = a.p1 + im.p1 + row1 * P1 + tl.ca;
-    float *p2_tile = a.p2 + im.p2 + (long long)tl.ra * P2 + col2;
+    const float *p1_tile = a.p1 + im.p1 + row1 * P1 + tl.ca;
+    const float *p2_tile = a.p2 + im.p2 + (long long)tl.ra * P2 + col2;
+    float *q1_tile = a.out1 + im.p1 + row1 * P1 + tl.ca;
+    float *q2_tile = a.out2 + im.p2 + (long long)tl.ra * P2 + col2;
     const long long px0 = im.px + (long long)tl.ra * W + tl.ca;
     const float *f_tile = a.f + px0;
     float *u_tile = a.u + px0;
     const uint8_t *m_tile = MASK ? a.mask + px0 : nullptr;
-    const float *lam = a.lam + im.lam;
     const float tau = a.tau, alpha = im.alpha, cv1 = a.cv_c1, cv2 = a.cv_c2;
     // clamp bounds, (-1, 1) or (0, 0) for edges on the image boundary (no dof)
     const float lo1 = (top_bnd && s == 0) ? 0.0f : -1.0f, hi1 = -lo1;
@@ -73,6 +78,62 @@ __global__ __launch_bounds__(1024) void k_fused_cp2(FusedCp2Args a)
         }
     }
 
+    // ---- (a1) lambda^(n+1) = lambda^n + sigma [(2 p_s^n - p_s^(n-1)) - (2 p_t^n - p_t^(n-1))] on the
+    // tile's interface edges, with the operations of the multiplier kernel (the two tiles of an
+    // interface compute the same value).  Waves 0..7 take the top, bottom, left and right sides
+    // (two waves each, edge si = 64 (wave % 2) + lane).  The new lambda state goes to lam_out:
+    // lambda^(n+1) and p_s^n by the s side (bottom, right), p_t^n by the t side (top, left).
+    {
+        const int side = s >> 1, si = (s & 1) * 64 + lane;
+        bool has = false;
+        long long e = 0, ips = 0, ipt = 0;  // lambda index; P1 or P2 offsets of the s and t copies
+        if (s < 2 * 4) {
+            const long long rs = (long long)(tl.ra + si) * P2;  // P2 row of a left / right edge
+            switch (side) {
+            case 0:  // top: the tile above holds the s copy
+                has = tl.r > 0;
+                e = (long long)(tl.r - 1) * W + tl.ca + si;
+                ips = (row1 - 1) * P1 + tl.ca + si;
+                ipt = row1 * P1 + tl.ca + si;
+                break;
+            case 1:  // bottom: the tile below holds the t copy
+                has = !bot_bnd;
+                e = (long long)tl.r * W + tl.ca + si;
+                ips = (row1 + kFusedMax) * P1 + tl.ca + si;
+                ipt = (row1 + kFusedMax + 1) * P1 + tl.ca + si;
+                break;
+            case 2:  // left: the tile on the left holds the s copy
+                has = tl.c > 0;
+                e = im.nlh + (long long)(tl.c - 1) * H + tl.ra + si;
+                ips = rs + col2 - 1;
+                ipt = rs + col2;
+                break;
+            default:  // right: the tile on the right holds the t copy
+                has = !right_bnd;
+                e = im.nlh + (long long)tl.c * H + tl.ra + si;
+                ips = rs + col2 + kFusedMax;
+                ipt = rs + col2 + kFusedMax + 1;
+                break;
+            }
+        }
+        if (has) {
+            const float *pp = side < 2 ? a.p1 + im.p1 : a.p2 + im.p2;
+            const float ps = pp[ips], pt = pp[ipt];
+            const float *Li = a.lam + im.lam;
+            float *Lo = a.lam_out + im.lam;
+            const long long nl = im.nlam;
+            const float l1 = Li[e] + a.sigma * ((2.0f * ps - Li[nl + e]) - (2.0f * pt - Li[2 * nl + e]));
+            LS[side][si] = l1;
+            if (side == 1 || side == 3) {
+                Lo[e] = l1;
+                Lo[nl + e] = ps;
+            } else {
+                Lo[2 * nl + e] = pt;
+            }
+        }
+    }
+    __syncthreads();
+
     // ---- (a2) anchors phat = p~^n, with +tau lambda^(n+1) on the t copies (top edges below an
     // interface, left edges right of one) and -tau lambda^(n+1) on the s copies (bottom, right)
 #pragma unroll
@@ -80,20 +141,18 @@ __global__ __launch_bounds__(1024) void k_fused_cp2(FusedCp2Args a)
         const int il = il0 + r;
         float a1a = X.e1a[r], a1b = X.e1b[r], a2a = X.e2a[r];
         if (il == 0 && tl.r > 0) {
-            const float *lr = lam + (long long)(tl.r - 1) * W + tl.ca;
-            a1a = fmaf(tau, lr[ja], a1a);
-            a1b = fmaf(tau, lr[jb], a1b);
+            a1a = fmaf(tau, LS[0][ja], a1a);
+            a1b = fmaf(tau, LS[0][jb], a1b);
         }
-        if (ja == 0 && tl.c > 0) a2a = fmaf(tau, lam[im.nlh + (long long)(tl.c - 1) * H + tl.ra + il], a2a);
+        if (ja == 0 && tl.c > 0) a2a = fmaf(tau, LS[2][il], a2a);
         lds_st2(&S.a1[il][ja], a1a, a1b);
         lds_st2(&S.a2[il][ja], a2a, X.e2b[r]);
     }
     if (last) {
         float aba = X.ba, abb = X.bb;
         if (!bot_bnd) {
-            const float *lr = lam + (long long)tl.r * W + tl.ca;
-            aba = fmaf(-tau, lr[ja], aba);
-            abb = fmaf(-tau, lr[jb], abb);
+            aba = fmaf(-tau, LS[1][ja], aba);
+            abb = fmaf(-tau, LS[1][jb], abb);
         }
         S.ab[ja] = aba;
         S.ab[jb] = abb;
@@ -104,7 +163,7 @@ __global__ __launch_bounds__(1024) void k_fused_cp2(FusedCp2Args a)
             const int il = il0 + r;
             S.rx[il] = xr[r];
             float ar = xr[r];
-            if (!right_bnd) ar = fmaf(-tau, lam[im.nlh + (long long)tl.c * H + tl.ra + il], ar);
+            if (!right_bnd) ar = fmaf(-tau, LS[3][il], ar);
             S.ar[il] = ar;
         }
     // ---- (a3) the local solve
@@ -130,12 +189,12 @@ __global__ __launch_bounds__(1024) void k_fused_cp2(FusedCp2Args a)
 #pragma unroll
     for (int r = 0; r < kR; ++r) {
         const int il = il0 + r;
-        st2g(p1_tile + (long long)il * P1 + ja, X.e1a[r], X.e1b[r]);
-        st2g(p2_tile + (long long)il * P2 + ja, X.e2a[r], X.e2b[r]);
+        st2g(q1_tile + (long long)il * P1 + ja, X.e1a[r], X.e1b[r]);
+        st2g(q2_tile + (long long)il * P2 + ja, X.e2a[r], X.e2b[r]);
         st2g(u_tile + (long long)il * W + ja, ua[r], ub[r]);
-        if (lane == 63) p2_tile[(long long)il * P2 + kFusedMax] = S.rx[il];
+        if (lane == 63) q2_tile[(long long)il * P2 + kFusedMax] = S.rx[il];
     }
-    if (last) st2g(p1_tile + (long long)kFusedMax * P1 + ja, X.ba, X.bb);
+    if (last) st2g(q1_tile + (long long)kFusedMax * P1 + ja, X.ba, X.bb);
 }
 
 namespace {
@@ -156,6 +215,10 @@ hipError_t launch_fused_cp2(const FusedCp2Args &a, int nsub, hipStream_t s, hipE
 {
     if (nsub <= 0) return hipSuccess;
     if (a.n_inner < 1 || a.n_inner > kMaxFusedInner) return hipErrorInvalidValue;
+    // p~^(n+1) and the new lambda state go to buffers of their own: other tiles read p~^n and
+    // lambda^n (without interfaces there is no lambda state)
+    if (!a.out1 || !a.out2 || a.out1 == a.p1 || a.out2 == a.p2 || (a.lam && a.lam_out == a.lam))
+        return hipErrorInvalidValue;
     const bool m = a.mask != nullptr;
     switch (a.fidelity) {
     case 0: return m ? launch_cp2_variant<0, true>(a, nsub, s, e0, e1) : launch_cp2_variant<0, false>(a, nsub, s, e0, e1);
