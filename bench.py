@@ -304,6 +304,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="rof2048")
     ap.add_argument("--schedule", default="auto")
+    ap.add_argument("--rows", type=int, default=0, help="streaming strip height (0: the plan picks)")
     ap.add_argument("--cpu-outer", type=int, default=500, help="outer steps of the oracle sample (0: skip)")
     ap.add_argument("--ref-iters", type=int, default=20000, help="dd_vs_full: FISTA iterations of the J* run")
     ap.add_argument("--adaptive-tol", type=float, default=1e-3, help="dd_vs_full: inner_tol of the adaptive run")
@@ -339,7 +340,7 @@ def main():
     img = dtvdd.Image(H, W, c.row_cuts, c.col_cuts, c.alpha)
     kw = dict(fidelity=c.fidelity, inner=c.inner, has_mask=c.mask is not None, tau=c.tau, sigma=c.sigma,
               tau0=c.tau0, sigma0=c.sigma0, gamma=c.gamma, n_outer=c.n_outer, n_inner=c.n_inner,
-              schedule=args.schedule, device=dev, **c.extra)
+              schedule=args.schedule, rows=args.rows, device=dev, **c.extra)
     plan = dtvdd.Plan([img], **kw)
     state = plan.new_state()
     for _ in range(args.warmup):
