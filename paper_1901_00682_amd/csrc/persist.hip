@@ -7,14 +7,16 @@
 // outer step.  Per outer step n:
 //   (1) each tile forms q = 2 p^n - p^(n-1) on its own interface copies (the
 //       extrapolated copies of the multiplier update) and publishes them;
-//   (4a) meanwhile it rebuilds c' of every edge from the anchor p^n and f
-//       (fista_ops.h);
+//   (4a) meanwhile it rebuilds c' of every edge but the interface copies from
+//       the anchor p^n and f (fista_ops.h);
 //   (2) it waits for the copies its neighbours publish on the same edges;
 //   (3) both tiles of an interface edge compute lambda^(n+1) = lambda^n +
 //       sigma (q_s - q_t) from the two copies, with the operations of the
 //       multiplier-update kernel, so both hold the same value;
-//   (4b) c' of the interface copies is redone from phat = p^n -/+ tau lambda;
+//   (4b) c' of the interface copies from phat = p^n -/+ tau lambda^(n+1);
 //   (5) the n_inner FISTA steps of the fused kernel (full_step).
+// Two workgroup barriers per outer step besides the steps' own: after the
+// staging of the copies (1) and before the steps (5).
 // lambda^n and the tile's own previous copies live in LDS.
 //
 // Synchronisation is point to point, between the two tiles of an interface:

@@ -7,11 +7,12 @@
 // the last.  Per outer step n:
 //   (1) each tile forms q = 2 p^n - p^(n-1) on its own interface copies and
 //       publishes them (exchange.h);
-//   (2) meanwhile it writes the anchors phat = p^n of every edge to LDS;
+//   (2) meanwhile it writes the anchors phat = p^n of every edge but the
+//       interface copies to LDS;
 //   (3) it waits for its neighbours' copies on the same edges, and both tiles
 //       of an interface edge compute lambda^(n+1) = lambda^n + sigma (q_s - q_t)
 //       with the operations of the multiplier-update kernel;
-//   (4) the anchors of the interface copies become p^n -/+ tau lambda^(n+1);
+//   (4) the anchors of the interface copies, p^n -/+ tau lambda^(n+1);
 //   (5) the n_inner primal-dual steps (cp2tile::solve).
 // lambda^n and the tile's own previous copies live in LDS.
 //
