@@ -95,6 +95,7 @@ struct dtv_dd_plan {
     std::vector<StreamTile> h_tiles[kRowChoices];  // streaming work lists, strips of 4 << ri rows
     std::vector<SubTile> h_subs;
     int n_full = 0;         // h_subs[0, n_full) are 128 x 128
+    int n_framed = 0;       // h_subs[n_full, n_full + n_framed): framed (fused.hip), the rest any other
     // schedule choice: the fixed rule until measured (or cached, or explicit)
     bool tuned = false;
     int choice_source = 0;  // 0 rule, 1 measured, 2 cached, 3 explicit
@@ -368,10 +369,21 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
                 pl->h_subs.push_back(SubTile{b, r, c, h.rcut[r], h.ccut[c], h.rcut[r + 1] - h.rcut[r],
                                              h.ccut[c + 1] - h.ccut[c], 0});
     }
-    // full 128 x 128 subdomains first: the fused schedule runs them with a specialised kernel
+    // full 128 x 128 subdomains first, then framed ones (smaller, with each short side on the image
+    // boundary): the fused schedule runs both with the specialised full-tile step
+    auto is_full = [](const SubTile &st) { return st.h == kFusedMax && st.w == kFusedMax; };
+    auto is_framed = [&](const SubTile &st) {
+        const ImgHost &h = pl->imgs[st.img];
+        return !is_full(st) && st.h <= kFusedMax && st.w <= kFusedMax && (st.h == kFusedMax || st.r == h.ny - 1) &&
+               (st.w == kFusedMax || st.c == h.nx - 1);
+    };
     std::stable_partition(pl->h_subs.begin(), pl->h_subs.end(),
-                          [](const SubTile &st) { return st.h == kFusedMax && st.w == kFusedMax; });
-    for (const SubTile &st : pl->h_subs) pl->n_full += st.h == kFusedMax && st.w == kFusedMax;
+                          [&](const SubTile &st) { return is_full(st) || is_framed(st); });
+    std::stable_partition(pl->h_subs.begin(), pl->h_subs.end(), is_full);
+    for (const SubTile &st : pl->h_subs) {
+        pl->n_full += is_full(st);
+        pl->n_framed += is_framed(st);
+    }
     pl->adaptive = p.inner_tol > 0.0;
     if (p.inner == DTV_INNER_FISTA) {
         pl->fused_ok = p.n_inner <= kMaxFusedInner || pl->adaptive;
@@ -822,7 +834,8 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
             fa.lam_out = lam_other();
             int rc = with_host ? tm.begin() : DTV_OK;
             if (rc != DTV_OK) return rc;
-            HIP_TRY(launch_fused_fista(fa, (int)pl->h_subs.size(), pl->n_full, q, with_host ? tm.e0 : nullptr,
+            HIP_TRY(launch_fused_fista(fa, (int)pl->h_subs.size(), pl->n_full, pl->n_framed, q,
+                                       with_host ? tm.e0 : nullptr,
                                        with_host ? tm.e1 : nullptr),
                     "fused FISTA");
             rc = with_host ? tm.end() : DTV_OK;
@@ -1226,7 +1239,8 @@ static int backward_fused(dtv_dd_plan *pl, const float *d_f, float *d_grad_f, fl
         fa.out2 = p_out + pl->tot_p1;
         fa.lam_out = lam_out;
         fa.rec = rec;
-        HIP_TRY(launch_fused_fista(fa, nsub, pl->n_full, s), rec ? "fused FISTA (recording)" : "fused FISTA");
+        HIP_TRY(launch_fused_fista(fa, nsub, pl->n_full, pl->n_framed, s),
+                rec ? "fused FISTA (recording)" : "fused FISTA");
         return DTV_OK;
     };
     for (int sg = pl->nseg - 1; sg >= 0; --sg) {
@@ -1347,7 +1361,7 @@ extern "C" int dtv_dd_kernel_time(const dtv_dd_plan *pl, double *avg_ms, int64_t
     const bool fused = pl->schedule == DTV_SCHED_FUSED;
     const bool persist = pl->schedule == DTV_SCHED_PERSIST;
     // full and ragged subdomains share one fused FISTA launch unless the solve is adaptive
-    const bool mixed = pl->n_full > 0 && pl->n_full < (int)pl->h_subs.size() && !pl->adaptive;
+    const bool mixed = pl->n_full < (int)pl->h_subs.size() && !pl->adaptive;
     if (name)
         *name = persist ? (cp2 ? "k_persist_cp2" : "k_persist_fista")
                 : fused ? (cp2 ? "k_fused_cp2" : mixed ? "k_fused_fista_mixed" : "k_fused_fista")

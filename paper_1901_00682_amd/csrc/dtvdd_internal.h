@@ -251,9 +251,11 @@ hipError_t launch_fused_bwd(const FusedBwdArgs &a, int nsub, hipStream_t s);
 
 // whether the fused kernel can record its steps for this inner count (full tiles only)
 bool fused_record_supported(int K);
-// subs[0, nfull) are 128 x 128 tiles (specialised kernel), subs[nfull, nsub) the others
-hipError_t launch_fused_fista(const FusedArgs &a, int nsub, int nfull, hipStream_t s, hipEvent_t e0 = nullptr,
-                              hipEvent_t e1 = nullptr);
+// subs[0, nfull) are 128 x 128 tiles (specialised kernel), subs[nfull, nfull + nframed) framed
+// tiles (smaller, their short sides on the image boundary: the specialised kernel in a 128 x 128
+// frame), the rest any other tiles of at most 128 x 128
+hipError_t launch_fused_fista(const FusedArgs &a, int nsub, int nfull, int nframed, hipStream_t s,
+                              hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
 // reverse-mode kernels (kernels_bwd.hip)
 hipError_t launch_fista_bwd_step(const FistaBwdArgs &a, bool momentum, int rows, hipStream_t s);

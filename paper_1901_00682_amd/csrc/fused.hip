@@ -31,7 +31,9 @@ using namespace fused;
 
 // One workgroup's work on subdomain t.  LS holds lambda^(n+1) on the top, bottom, left and
 // right sides; red is the reduction buffer of the adaptive rule (2 kWaves doubles).
-template <bool kFull, int KF, bool REC, bool ADAPT>
+// FR (with kFull): a framed tile, smaller than 128 x 128 with its short sides on the image
+// boundary, run by the full-tile step in a 128 x 128 frame (full_step<.., FR>).
+template <bool kFull, int KF, bool REC, bool ADAPT, bool FR = false>
 __device__ __forceinline__ void fused_tile(const FusedArgs &a, int t, FusedLds &S, float (&LS)[4][kFusedMax],
                                            double *red)
 {
@@ -43,8 +45,9 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, int t, FusedLds &
     c.ja = 2 * c.lane;
     c.jb = c.ja + 1;
     c.il0 = kR * c.s;
-    c.h = kFull ? kFusedMax : tl.h;
-    c.w = kFull ? kFusedMax : tl.w;
+    constexpr bool kShape = kFull && !FR;  // the tile is 128 x 128 (known at compile time)
+    c.h = kShape ? kFusedMax : tl.h;
+    c.w = kShape ? kFusedMax : tl.w;
     c.acta = c.ja < c.w;
     c.actb = c.jb < c.w;
     c.lastcol_a = c.ja == c.w - 1;
@@ -96,7 +99,7 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, int t, FusedLds &
         const int il = il0 + r;
         float x1a = 0.0f, x1b = 0.0f, x2a = 0.0f, x2b = 0.0f;
         fva[r] = fvb[r] = xr[r] = 0.0f;
-        if (kFull || il < h) {  // (always on full tiles)
+        if (kShape || il < h) {  // (always on full tiles)
             const float *p1r = p1_tile + (long long)il * P1;
             const float *p2r = p2_tile + (long long)il * P2;
             const float *fr = f_tile + (long long)il * W;
@@ -126,7 +129,7 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, int t, FusedLds &
 #pragma unroll
     for (int r = 0; r < kR; ++r) {
         const int il = il0 + r;
-        if ((kFull || il < h) && lastcol) xr[r] = p2_tile[(long long)il * P2 + w];  // right boundary edge of the row
+        if ((kShape || il < h) && lastcol) xr[r] = p2_tile[(long long)il * P2 + w];  // right boundary edge of the row
     }
 
     // ---- (a1) lambda^(n+1) = lambda^n + sigma [(2 p_s^n - p_s^(n-1)) - (2 p_t^n - p_t^(n-1))] on the
@@ -188,7 +191,49 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, int t, FusedLds &
     for (int r = 0; r < kR; ++r) {
         const int il = il0 + r;
         const float fla = from_left(fvb[r]);  // f of column a - 1 (lane 0: left of the tile, 0)
-        if (kFull || il < h) {  // (always on full tiles)
+        if constexpr (FR) {
+            // every c' entry of the frame written once: the tile's edges as below, 0 outside it
+            float c1a = 0.0f, c1b = 0.0f, c2a = 0.0f, c2b = 0.0f;
+            if (il < h) {
+                float ata = A.e1a[r], atb = A.e1b[r];
+                if (il == 0 && tl.r > 0) {
+                    if (c.acta) ata = fmaf(tau, LS[0][ja], ata);
+                    if (c.actb) atb = fmaf(tau, LS[0][jb], atb);
+                }
+                float ala = A.e2a[r];
+                if (ja == 0 && tl.c > 0) ala = fmaf(tau, LS[2][il], ala);
+                if (c.acta) {
+                    c1a = fista_cprime(ata, fua, fva[r], itau, invL);
+                    c2a = fista_cprime(ala, ja > 0 ? fla : 0.0f, fva[r], itau, invL);
+                }
+                if (c.actb) {
+                    c1b = fista_cprime(atb, fub, fvb[r], itau, invL);
+                    c2b = fista_cprime(A.e2b[r], fva[r], fvb[r], itau, invL);
+                }
+            }
+            lds_st2(&S.c1[il][ja], c1a, c1b);
+            lds_st2(&S.c2[il][ja], c2a, c2b);
+            if (il == kFusedMax - 1) {  // the frame's bottom edges: the tile's when h = 128
+                float cba = 0.0f, cbb = 0.0f;
+                if (h == kFusedMax) {
+                    if (c.acta) cba = fista_cprime(c.bot_bnd ? A.ba : fmaf(-tau, LS[1][ja], A.ba), fva[r], 0.0f, itau,
+                                                   invL);
+                    if (c.actb) cbb = fista_cprime(c.bot_bnd ? A.bb : fmaf(-tau, LS[1][jb], A.bb), fvb[r], 0.0f, itau,
+                                                   invL);
+                }
+                lds_st2(&S.cb[ja], cba, cbb);
+            }
+            if (c.lane == 63) {  // the frame's right edges: the tile's when w = 128
+                float xv = 0.0f, cv = 0.0f;
+                if (w == kFusedMax && il < h) {
+                    xv = xr[r];
+                    cv = fista_cprime(c.right_bnd ? xr[r] : fmaf(-tau, LS[3][il], xr[r]), fvb[r], 0.0f, itau, invL);
+                }
+                S.rx[0][il] = xv;
+                S.rx[1][il] = xv;
+                S.cr[il] = cv;
+            }
+        } else if (kShape || il < h) {  // (always on full tiles)
             // top edges (t copies of an interface on the tile's first row)
             float ata = A.e1a[r], atb = A.e1b[r];
             if (il == 0 && tl.r > 0) {
@@ -255,8 +300,27 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, int t, FusedLds &
         fc.kL = c.kL;
         fc.qa = (float)(-im.dA * (double)a.inv_tau);
         fc.qb = (float)(-im.dB);
+        fc.lo2b = -1.0f;
+        fc.hi2b = 1.0f;
+        fc.zrows = 0u;
+        if constexpr (FR) {
+            // the boundary lines of a framed tile: the left edges of column w, the top edges of row h
+            const bool za = w < kFusedMax && ja == w, zb = w < kFusedMax && jb == w;
+            fc.lo2a = za ? 0.0f : fc.lo2a;
+            fc.hi2a = za ? 0.0f : fc.hi2a;
+            fc.lo2b = zb ? 0.0f : -1.0f;
+            fc.hi2b = zb ? 0.0f : 1.0f;
+            const int zr = h - il0;
+            fc.zrows = (h < kFusedMax && zr >= 0 && zr < kR) ? 1u << zr : 0u;
+            fc.right_bnd = c.right_bnd || w < kFusedMax;  // the frame's right column lies outside the tile
+        }
         if constexpr (ADAPT) {
             rx_slot = run_steps_adaptive<FullStep>(fc, S, A, B, K, a.beta_dev, a.tol2, red, taken);
+        } else if constexpr (FR && KF > 0) {
+            rx_slot = full_steps_fixed<KF, false, true>(fc, S, A, B, a.beta);
+            if constexpr (KF & 1) copy_slot(A, B);
+        } else if constexpr (FR) {
+            rx_slot = run_steps<FramedStep>(fc, S, A, B, K, a.beta);
         } else if constexpr (KF > 0) {
             if constexpr (REC) {
                 const long long rec_step = (long long)gridDim.x * kRecGroups * kRecThreads;
@@ -302,10 +366,11 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, int t, FusedLds &
                 q1[ja] = A.e1a[r];
                 q2[ja] = A.e2a[r];
             }
-            if (c.lastcol_a || c.lastcol_b) q2[w] = S.rx[rx_slot][il];
+            // the right boundary edge; a framed tile narrower than 128 has it on the image boundary
+            if ((c.lastcol_a || c.lastcol_b) && (!FR || w == kFusedMax)) q2[w] = S.rx[rx_slot][il];
         }
     }
-    if (c.has_bottom) {
+    if (c.has_bottom && (!FR || h == kFusedMax)) {
         float *qb = q1_tile + (long long)h * P1;
         if (c.actb) st2(qb + ja, A.ba, A.bb);
         else if (c.acta) qb[ja] = A.ba;
@@ -326,24 +391,26 @@ __global__ __launch_bounds__(1024) void k_fused_fista(FusedArgs a, int first)
     fused_tile<kFull, KF, REC, ADAPT>(a, first + xcd_remap(blockIdx.x, gridDim.x), S, LS, red);
 }
 
-// Both kinds of tile in one launch (fixed n_inner, no recording): blocks
-// [0, npad) take the partial tiles nfull .. nfull + npart - 1 (npad = npart
-// rounded up to a multiple of 8; the extra blocks exit at once), the rest the
-// full tiles 0 .. nfull - 1.  The partial tiles, slower per workgroup, are
-// dispatched first, spread over the XCDs; the full tiles keep the XCD-aware
-// order, and no launch boundary separates the two kinds.
+// Every kind of tile in one launch (fixed n_inner, no recording).  The list holds the full
+// tiles first, then the framed ones, then the other (general) ones; blocks [0, gpad) take the
+// general tiles, [gpad, gpad + fpad) the framed ones (gpad, fpad: the counts rounded up to a
+// multiple of 8; the extra blocks exit at once), the rest the full tiles.  The slower kinds are
+// dispatched first, spread over the XCDs; the full tiles keep the XCD-aware order, and no launch
+// boundary separates the kinds.
 template <int KF>
-__global__ __launch_bounds__(1024) void k_fused_fista_mixed(FusedArgs a, int nfull, int npart)
+__global__ __launch_bounds__(1024) void k_fused_fista_mixed(FusedArgs a, int nfull, int nframed, int ngen)
 {
     __shared__ FusedLds S;
     __shared__ float LS[4][kFusedMax];
     __shared__ double red[1];
-    const int npad = (npart + 7) & ~7;
+    const int gpad = (ngen + 7) & ~7, fpad = (nframed + 7) & ~7;
     const int b = blockIdx.x;
-    if (b < npad) {
-        if (b < npart) fused_tile<false, 0, false, false>(a, nfull + b, S, LS, red);
+    if (b < gpad) {
+        if (b < ngen) fused_tile<false, 0, false, false>(a, nfull + nframed + b, S, LS, red);
+    } else if (b < gpad + fpad) {
+        if (b - gpad < nframed) fused_tile<true, KF, false, false, true>(a, nfull + b - gpad, S, LS, red);
     } else {
-        fused_tile<true, KF, false, false>(a, xcd_remap(b - npad, gridDim.x - npad), S, LS, red);
+        fused_tile<true, KF, false, false>(a, xcd_remap(b - gpad - fpad, gridDim.x - gpad - fpad), S, LS, red);
     }
 }
 
@@ -364,7 +431,7 @@ struct FullTable {
 };
 using Full = FullTable<1, 2, 3, 4, 5, 6, 7, 8, 10>;
 
-using MixedKernel = void (*)(FusedArgs, int, int);
+using MixedKernel = void (*)(FusedArgs, int, int, int);
 
 template <int... Ks>
 struct MixedTable {
@@ -385,7 +452,8 @@ namespace {
 
 }  // namespace
 
-hipError_t launch_fused_fista(const FusedArgs &a, int nsub, int nfull, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
+hipError_t launch_fused_fista(const FusedArgs &a, int nsub, int nfull, int nframed, hipStream_t s, hipEvent_t e0,
+                              hipEvent_t e1)
 {
     if (nsub <= 0) return hipSuccess;
     const bool adapt = a.tol2 > 0.0;
@@ -413,13 +481,15 @@ hipError_t launch_fused_fista(const FusedArgs &a, int nsub, int nfull, hipStream
         }
         return hipGetLastError();
     }
-    if (nfull > 0 && npart > 0 && !a.rec) {  // one launch for both kinds of tile
+    if (nframed < 0 || nframed > npart) return hipErrorInvalidValue;
+    if (npart > 0 && !a.rec) {  // one launch for every kind of tile
         const MixedKernel km = Mixed::get(a.n_inner);
-        const int grid = ((npart + 7) & ~7) + nfull;
+        const int ngen = npart - nframed;
+        const int grid = ((ngen + 7) & ~7) + ((nframed + 7) & ~7) + nfull;
         if (e0)
-            hipExtLaunchKernelGGL(km, dim3(grid), dim3(1024), 0, s, e0, e1, 0, a, nfull, npart);
+            hipExtLaunchKernelGGL(km, dim3(grid), dim3(1024), 0, s, e0, e1, 0, a, nfull, nframed, ngen);
         else
-            hipLaunchKernelGGL(km, dim3(grid), dim3(1024), 0, s, a, nfull, npart);
+            hipLaunchKernelGGL(km, dim3(grid), dim3(1024), 0, s, a, nfull, nframed, ngen);
         return hipGetLastError();
     }
     // the timing events bracket both launches

@@ -195,6 +195,11 @@ struct FullCtx {
     float lo1, hi1, lo2a, hi2a, lob, hib;
     float ak, kL;
     float qa, qb;  // recording: the weights of y and of d_b - d_a in the record word q
+    // framed tiles only (a subdomain smaller than 128 x 128 whose short sides lie on the image
+    // boundary, run in a 128 x 128 frame): clamp bounds of the left edge of column b, and the
+    // strip's rows whose top edges are the tile's bottom boundary (bit r: row 8 s + r)
+    float lo2b, hi2b;
+    unsigned zrows;
 };
 
 __device__ __forceinline__ int opaque(int x)
@@ -264,7 +269,12 @@ __device__ __forceinline__ float proj(float z, float lo, float hi, unsigned &m, 
     return __builtin_amdgcn_fmed3f(z, lo, hi);
 }
 
-template <bool mom, bool REC = false>
+// FR: a framed tile.  The tile's h x w pixels sit at the top left of the 128 x 128 frame, its
+// bottom and right sides (when shorter than the frame) on the image boundary.  Outside the tile
+// every edge starts at 0 with c' = 0; the edges of the two boundary lines (the top edges of row
+// h, the left edges of column w) are clamped to 0, so the pixels outside keep d = 0 and the
+// tile's own edges are updated exactly as in a tile of its own size.
+template <bool mom, bool REC = false, bool FR = false>
 __device__ __forceinline__ void full_step(const FullCtx &c, FusedLds &S, const Slot &X, Slot &Y, int sx, float beta,
                                           float4 *rec = nullptr)
 {
@@ -326,12 +336,19 @@ __device__ __forceinline__ void full_step(const FullCtx &c, FusedLds &S, const S
         float c1a, c1b, c2a, c2b;
         lds_ld2(c1 + r * kFusedMax, c1a, c1b);
         lds_ld2(c2 + r * kFusedMax, c2a, c2b);
-        // the top edges of the tile collapse to 0 on the image boundary (bounds lo1, hi1 on row 0)
-        const float lo1 = r == 0 ? c.lo1 : -1.0f, hi1 = r == 0 ? c.hi1 : 1.0f;
+        // the top edges of the tile collapse to 0 on the image boundary (bounds lo1, hi1 on row 0),
+        // and in a framed tile on its bottom boundary line
+        float lo1 = r == 0 ? c.lo1 : -1.0f, hi1 = r == 0 ? c.hi1 : 1.0f;
+        if constexpr (FR) {
+            const bool zr = ((c.zrows >> r) & 1u) != 0;
+            lo1 = zr ? 0.0f : lo1;
+            hi1 = zr ? 0.0f : hi1;
+        }
         Y.e1a[r] = proj<REC>(fista_z(Y.e1a[r], dua, da, c1a, ak, kL), lo1, hi1, m0, 4 * r + 0);
         Y.e1b[r] = proj<REC>(fista_z(Y.e1b[r], dub, db, c1b, ak, kL), lo1, hi1, m0, 4 * r + 1);
         Y.e2a[r] = proj<REC>(fista_z(Y.e2a[r], dlb, da, c2a, ak, kL), c.lo2a, c.hi2a, m0, 4 * r + 2);
-        Y.e2b[r] = proj<REC>(fista_z(Y.e2b[r], da, db, c2b, ak, kL), -1.0f, 1.0f, m0, 4 * r + 3);
+        Y.e2b[r] = proj<REC>(fista_z(Y.e2b[r], da, db, c2b, ak, kL), FR ? c.lo2b : -1.0f, FR ? c.hi2b : 1.0f, m0,
+                             4 * r + 3);
         // bottom boundary edges of the tile (strip 15; 0 on the image boundary).  The branch is
         // wave-uniform; the recording step keeps the straight line (fewer registers live).
         if (r == kR - 1 && (REC || c.last)) {
@@ -379,6 +396,15 @@ struct FullStep {
                                                 float beta)
     {
         full_step<mom>(c, S, X, Y, sx, beta);
+    }
+};
+
+struct FramedStep {
+    template <bool mom>
+    __device__ __forceinline__ static void step(const FullCtx &c, FusedLds &S, const Slot &X, Slot &Y, int sx,
+                                                float beta)
+    {
+        full_step<mom, false, true>(c, S, X, Y, sx, beta);
     }
 };
 
@@ -523,14 +549,14 @@ __device__ __forceinline__ int run_steps(const C &c, FusedLds &S, Slot &A, Slot 
 // costs register copies, and spills where the caller keeps more state live).
 // x_K ends in A when K is even and in B when K is odd; returns the LDS slot of
 // the right boundary column holding it (K & 1).
-template <int K, bool REC = false, int k = 1>
+template <int K, bool REC = false, bool FR = false, int k = 1>
 __device__ __forceinline__ int full_steps_fixed(const FullCtx &c, FusedLds &S, Slot &X, Slot &Y, const float *beta,
                                                 float4 *rec = nullptr, long long rec_step = 0)
 {
     if constexpr (k <= K) {
-        full_step<(k >= 3), REC>(c, S, X, Y, (k - 1) & 1, k >= 3 ? beta[k] : 0.0f,
-                                 REC ? rec + (k - 1) * rec_step : nullptr);
-        return full_steps_fixed<K, REC, k + 1>(c, S, Y, X, beta, rec, rec_step);
+        full_step<(k >= 3), REC, FR>(c, S, X, Y, (k - 1) & 1, k >= 3 ? beta[k] : 0.0f,
+                                     REC ? rec + (k - 1) * rec_step : nullptr);
+        return full_steps_fixed<K, REC, FR, k + 1>(c, S, Y, X, beta, rec, rec_step);
     } else {
         return K & 1;
     }

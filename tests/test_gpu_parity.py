@@ -94,11 +94,17 @@ FUSED_GEOMS = {
     "full3x3": (384, 384, [0, 128, 256, 384], [0, 128, 256, 384]),
     # one full tile bounded by the image on all sides
     "full1x1": (128, 128, [0, 128], [0, 128]),
+    # framed tiles: the last row (43 rows) and the last column (45 columns, odd) of subdomains
+    # end on the image boundary, so they run the full-tile step in a 128 x 128 frame
+    "framed": (299, 301, [0, 128, 256, 299], [0, 128, 256, 301]),
+    # framed tiles beside general ragged ones (a 57-column subdomain with interfaces on both sides)
+    "framed_mixed": (200, 313, [0, 128, 200], [0, 128, 185, 313]),
 }
 
 
 @pytest.mark.parametrize("geom,K", [("mixed", k) for k in (1, 2, 3, 4, 5, 7, 9)]
-                         + [("full3x3", k) for k in (1, 2, 5, 6)] + [("full1x1", 3)])
+                         + [("full3x3", k) for k in (1, 2, 5, 6)] + [("full1x1", 3)]
+                         + [("framed", k) for k in (1, 2, 5, 9)] + [("framed_mixed", k) for k in (3, 5)])
 def test_fused_equals_stream_bitwise(geom, K):
     """The two schedules of the FISTA local solves round identically: full
     128 x 128 subdomains (the specialised kernel) with image boundaries and
@@ -114,7 +120,7 @@ def test_fused_equals_stream_bitwise(geom, K):
         plan, state, _, _, _ = run_gpu(f, 8.0, rc, cc, n_outer=6, n_inner=K, schedule=sch)
         assert plan.schedule() == sch
         if sch == "fused":  # full and ragged subdomains share one launch when both occur
-            want = "k_fused_fista_mixed" if geom == "mixed" else "k_fused_fista"
+            want = "k_fused_fista" if geom.startswith("full") else "k_fused_fista_mixed"
             assert plan.kernel_time()["name"] == want
         res[sch] = gpu_image_state(plan, state)
     for q in res["stream"]:
