@@ -96,6 +96,10 @@ struct dtv_dd_plan {
     std::vector<SubTile> h_subs;
     int n_full = 0;         // h_subs[0, n_full) are 128 x 128
     int n_framed = 0;       // h_subs[n_full, n_full + n_framed): framed (fused.hip), the rest any other
+    // persistent FISTA schedule: the subdomains grouped by image into launches that fit on the device
+    // at once (p_subs: the groups one after the other, each image's subdomains in grid order)
+    std::vector<SubTile> p_subs;
+    std::vector<int> p_group;  // first subdomain of each group in p_subs, then p_subs.size()
     // schedule choice: the fixed rule until measured (or cached, or explicit)
     bool tuned = false;
     int choice_source = 0;  // 0 rule, 1 measured, 2 cached, 3 explicit
@@ -108,7 +112,7 @@ struct dtv_dd_plan {
     bool persist_ok = false;  // the persistent schedule applies (full tiles, all resident, no per-step host work)
 
     // workspace layout (byte offsets)
-    size_t off_imgs = 0, off_info = 0, off_tiles[kRowChoices] = {0, 0, 0, 0}, off_subs = 0, off_buf[3] = {0, 0, 0},
+    size_t off_imgs = 0, off_info = 0, off_tiles[kRowChoices] = {0, 0, 0, 0}, off_subs = 0, off_psubs = 0, off_buf[3] = {0, 0, 0},
            off_u2 = 0,
            off_part = 0, off_dout = 0, off_xch = 0, off_sync = 0, off_lamw = 0, ws_bytes = 0;
     int diag_nblk = 0;
@@ -143,6 +147,7 @@ struct dtv_dd_plan {
 
     const ImgDev *d_imgs() const { return (const ImgDev *)(ws + off_imgs); }
     const SubTile *d_subs() const { return (const SubTile *)(ws + off_subs); }
+    const SubTile *d_psubs() const { return (const SubTile *)(ws + off_psubs); }
     const int *d_info() const { return (const int *)(ws + off_info); }
     const StreamTile *d_tiles(int R) const { return (const StreamTile *)(ws + off_tiles[row_index(R)]); }
     int ntiles(int R) const { return (int)h_tiles[row_index(R)].size(); }
@@ -402,20 +407,53 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
                                 "or of exactly 128 x 128 (CP2)");
     }
     {
+        // persistent: full subdomains (FISTA: or framed ones), no per-step host work; the primal-dual
+        // kernel and adaptive stopping take every subdomain in one launch, fixed-count FISTA runs the
+        // images in groups of launches, each group resident on the device at once
         const int nsub = (int)pl->h_subs.size();
-        pl->persist_ok = pl->fused_ok && nsub > 0 && pl->n_full == nsub && p.diag_every == 0 && !p.save_for_backward;
+        const bool fista = p.inner == DTV_INNER_FISTA;
+        const bool one_launch = !fista || pl->adaptive;
+        pl->persist_ok = pl->fused_ok && nsub > 0 && p.diag_every == 0 && !p.save_for_backward &&
+                         (pl->n_full == nsub || (!one_launch && pl->n_full + pl->n_framed == nsub));
         int dev = 0;
-        if (pl->persist_ok && hipGetDevice(&dev) == hipSuccess)
-            pl->persist_ok = persist_supported(dev) &&
-                             nsub <= (p.inner == DTV_INNER_CP2 ? persist_cp2_capacity(dev) : persist_capacity(dev));
-        else
+        if (pl->persist_ok && hipGetDevice(&dev) == hipSuccess && persist_supported(dev)) {
+            const int cap = fista ? persist_capacity(dev) : persist_cp2_capacity(dev);
+            if (one_launch) {
+                pl->persist_ok = nsub <= cap;
+                if (pl->persist_ok) {
+                    pl->p_subs = pl->h_subs;
+                    pl->p_group = {0, nsub};
+                }
+            } else {
+                pl->p_group = {0};
+                int in_group = 0;
+                for (int b = 0; b < n_images && pl->persist_ok; ++b) {
+                    const int nt = pl->imgs[b].ny * pl->imgs[b].nx;
+                    if (nt > cap) pl->persist_ok = false;
+                    if (in_group + nt > cap) {
+                        pl->p_group.push_back((int)pl->p_subs.size());
+                        in_group = 0;
+                    }
+                    for (const SubTile &st : pl->h_subs)
+                        if (st.img == b) pl->p_subs.push_back(st);
+                    in_group += nt;
+                }
+                pl->p_group.push_back((int)pl->p_subs.size());
+            }
+        } else {
             pl->persist_ok = false;
+        }
+        if (!pl->persist_ok) {
+            pl->p_subs.clear();
+            pl->p_group.clear();
+        }
     }
     if (p.schedule == DTV_SCHED_PERSIST && !pl->persist_ok) {
         delete pl;
         return fail(DTV_EINVAL, "the persistent schedule needs n_inner <= 64 (or inner_tol), every subdomain 128 x "
-                                "128, all subdomains resident on the device at once, diag_every = 0 and no "
-                                "save_for_backward");
+                                "128 (fixed-count FISTA: or smaller with its short sides on the image boundary), "
+                                "each image's subdomains resident on the device at once (primal-dual or inner_tol: "
+                                "all of them), diag_every = 0 and no save_for_backward");
     }
 
     // workspace layout
@@ -429,6 +467,7 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
     pl->off_info = take(sizeof(int) * pl->h_info.size());
     for (int ri = 0; ri < kRowChoices; ++ri) pl->off_tiles[ri] = take(sizeof(StreamTile) * pl->h_tiles[ri].size());
     pl->off_subs = take(sizeof(SubTile) * pl->h_subs.size());
+    pl->off_psubs = take(sizeof(SubTile) * std::max<size_t>(1, pl->p_subs.size()));
     for (int k = 0; k < 3; ++k) pl->off_buf[k] = take(sizeof(float) * (size_t)(pl->tot_p1 + pl->tot_p2));
     pl->off_u2 = take(p.inner == DTV_INNER_CP2 ? sizeof(float) * (size_t)pl->tot_px : 0);
     pl->diag_nblk = diag_blocks_per_image(pl->maxH, pl->maxW);
@@ -544,6 +583,10 @@ extern "C" int dtv_dd_bind_workspace(dtv_dd_plan *pl, void *d_ws, size_t bytes)
                 "upload work list");
     HIP_TRY(hipMemcpy(ws + pl->off_subs, pl->h_subs.data(), sizeof(SubTile) * pl->h_subs.size(), hipMemcpyHostToDevice),
             "upload subdomain list");
+    if (!pl->p_subs.empty())
+        HIP_TRY(hipMemcpy(ws + pl->off_psubs, pl->p_subs.data(), sizeof(SubTile) * pl->p_subs.size(),
+                          hipMemcpyHostToDevice),
+                "upload subdomain groups");
     // rotation buffers start at zero so that their boundary (non-dof) edges are 0
     for (int k = 0; k < 3; ++k)
         HIP_TRY(hipMemset(ws + pl->off_buf[k], 0, sizeof(float) * (size_t)(pl->tot_p1 + pl->tot_p2)), "clear buffers");
@@ -950,7 +993,14 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
             pa.n_outer = count;
             pa.sigma = (float)P.sigma;
             pa.spin_limit = spin_limit;
-            HIP_TRY(launch_persist_fista(pa, (int)pl->h_subs.size(), s), "persistent FISTA");
+            // one cooperative launch per group of images; the groups share nothing
+            for (size_t g = 0; g + 1 < pl->p_group.size(); ++g) {
+                bool frames = false;  // the group holds framed subdomains
+                for (int i = pl->p_group[g]; i < pl->p_group[g + 1]; ++i)
+                    frames = frames || pl->p_subs[i].h < kFusedMax || pl->p_subs[i].w < kFusedMax;
+                pa.fa.subs = pl->d_psubs() + pl->p_group[g];
+                HIP_TRY(launch_persist_fista(pa, pl->p_group[g + 1] - pl->p_group[g], frames, s), "persistent FISTA");
+            }
         }
         if (tm.e1) HIP_TRY(hipEventRecord(tm.e1, s), "event");
         rc = tm.end();

@@ -227,7 +227,7 @@ struct PersistArgs {
 };
 bool persist_supported(int device);
 int persist_capacity(int device);  // workgroups of the persistent kernel resident at once
-hipError_t launch_persist_fista(const PersistArgs &a, int nsub, hipStream_t s);
+hipError_t launch_persist_fista(const PersistArgs &a, int nsub, bool frames, hipStream_t s);
 
 // Reverse mode of one outer step on full 128 x 128 subdomains (fused_bwd.hip),
 // from the step records of the fused kernel.

@@ -65,23 +65,24 @@ __device__ __forceinline__ void st2g(float *p, float x, float y)
 
 }  // namespace
 
-// KF > 0: the kernel for n_inner = KF (steps unrolled); KF = 0: any n_inner.
+// The whole solve of subdomain t.  KF > 0: n_inner = KF (steps unrolled); KF = 0: any n_inner.
 // ADAPT (KF = 0): each local solve stops by the relative-change rule (fused_common.h,
-// a.fa.tol2, cap n_inner); the steps taken are counted per subdomain.
-template <int KF, bool ADAPT = false>
-__global__ __launch_bounds__(1024) void k_persist_fista(PersistArgs a)
+// a.fa.tol2, cap n_inner); the steps taken are counted per subdomain.  FR: a framed tile (smaller
+// than 128 x 128, its short sides on the image boundary: full_step<.., FR> in a 128 x 128 frame,
+// with p~ and f zero outside the tile).
+template <int KF, bool ADAPT, bool FR>
+__device__ __forceinline__ void persist_tile(const PersistArgs &a, PersistLds &L, int t)
 {
-    __shared__ PersistLds L;
     FusedLds &S = L.f;
-    const int t = xcd_remap(blockIdx.x, gridDim.x);
     const SubTile tl = a.fa.subs[t];
     const ImgDev im = a.fa.imgs[tl.img];
+    const int h = FR ? tl.h : kFusedMax, w = FR ? tl.w : kFusedMax;
     const int s = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // strip (wave) index
     const int lane = threadIdx.x & 63;
     const int ja = 2 * lane, il0 = kR * s;
     const int H = im.H, W = im.W;
-    const bool top_bnd = tl.ra == 0, bot_bnd = tl.ra + kFusedMax == H;
-    const bool left_bnd = tl.ca == 0, right_bnd = tl.ca + kFusedMax == W;
+    const bool top_bnd = tl.ra == 0, bot_bnd = tl.ra + h == H;
+    const bool left_bnd = tl.ca == 0, right_bnd = tl.ca + w == W;
     const long long P1 = im.pitch1, P2 = im.pitch2;
     const long long row1 = (long long)tl.ra + tl.r;  // P1 row of the tile's edge row 0
     const long long col2 = (long long)tl.ca + tl.c;  // P2 column of the tile's edge column 0
@@ -110,11 +111,28 @@ __global__ __launch_bounds__(1024) void k_persist_fista(PersistArgs a)
     }
     fc.ak = im.a_keep;
     fc.kL = im.kL;
+    fc.lo2b = -1.0f;
+    fc.hi2b = 1.0f;
+    fc.zrows = 0u;
+    if constexpr (FR) {
+        // the boundary lines of a framed tile: the left edges of column w, the top edges of row h
+        const bool za = w < kFusedMax && ja == w, zb = w < kFusedMax && ja + 1 == w;
+        fc.lo2a = za ? 0.0f : fc.lo2a;
+        fc.hi2a = za ? 0.0f : fc.hi2a;
+        fc.lo2b = zb ? 0.0f : -1.0f;
+        fc.hi2b = zb ? 0.0f : 1.0f;
+        const int zr = h - il0;
+        fc.zrows = (h < kFusedMax && zr >= 0 && zr < kR) ? 1u << zr : 0u;
+        fc.right_bnd = right_bnd || w < kFusedMax;  // the frame's right column lies outside the tile
+    }
 
     // side work (multiplier update): waves 0..7, side = wave / 2 (wave-uniform), edge
-    // si = 64 (wave % 2) + lane; the lambda index is side_base + si
+    // si = 64 (wave % 2) + lane; the lambda index is side_base + si.  A framed tile's sides are
+    // shorter than 128 (lanes beyond the side's length idle); its bottom and right sides, when
+    // shorter than the frame, lie on the image boundary and do not exist.
     const int side = s >> 1;
     const bool side_wave = s < 2 * kSides && side_exists(im, tl, side);
+    const bool side_lane = side_wave && (s & 1) * 64 + lane < (side < 2 ? w : h);
     const bool side_s = side == 1 || side == 3;  // s copies: bottom and right sides
     const long long side_base = side_wave ? side_edge(im, tl, side, 0) : 0;
 
@@ -127,13 +145,26 @@ __global__ __launch_bounds__(1024) void k_persist_fista(PersistArgs a)
 #pragma unroll
         for (int r = 0; r < kR; ++r) {
             const int il = il0 + r;
-            ld2g(p1_tile + (long long)il * P1 + ja, A.e1a[r], A.e1b[r]);
-            ld2g(p2_tile + (long long)il * P2 + ja, A.e2a[r], A.e2b[r]);
+            A.e1a[r] = A.e1b[r] = A.e2a[r] = A.e2b[r] = 0.0f;
+            if (!FR || (il < h && ja + 1 < w)) {
+                ld2g(p1_tile + (long long)il * P1 + ja, A.e1a[r], A.e1b[r]);
+                ld2g(p2_tile + (long long)il * P2 + ja, A.e2a[r], A.e2b[r]);
+            } else if (il < h && ja < w) {  // framed: the tile's last column alone
+                A.e1a[r] = p1_tile[(long long)il * P1 + ja];
+                A.e2a[r] = p2_tile[(long long)il * P2 + ja];
+            }
         }
-        if (fc.last) ld2g(p1_tile + (long long)kFusedMax * P1 + ja, A.ba, A.bb);
-        if (lane < kR) S.rx[0][il0 + lane] = p2_tile[(long long)(il0 + lane) * P2 + kFusedMax];
+        if (fc.last && (!FR || (h == kFusedMax && ja + 1 < w))) {
+            ld2g(p1_tile + (long long)kFusedMax * P1 + ja, A.ba, A.bb);
+        } else if (fc.last && h == kFusedMax && ja < w) {  // framed: the tile's last column alone
+            A.ba = p1_tile[(long long)kFusedMax * P1 + ja];
+        }
+        if (lane < kR)
+            S.rx[0][il0 + lane] = (!FR || (w == kFusedMax && il0 + lane < h))
+                                      ? p2_tile[(long long)(il0 + lane) * P2 + kFusedMax]
+                                      : 0.0f;
     }
-    if (side_wave) {
+    if (side_lane) {
         const int si = (s & 1) * 64 + lane;
         const float *ls = a.fa.lam + im.lam + side_base;
         L.lam[side][si] = ls[si];
@@ -150,9 +181,14 @@ __global__ __launch_bounds__(1024) void k_persist_fista(PersistArgs a)
         const int jo = opaque(ja);
         float fra[kR], frb[kR];
 #pragma unroll
-        for (int r = 0; r < kR; ++r) ld2g(f_tile + (long long)(il0 + r) * W + jo, fra[r], frb[r]);
+        for (int r = 0; r < kR; ++r) {
+            fra[r] = frb[r] = 0.0f;  // (a framed tile: 0 outside the tile)
+            if (!FR || (il0 + r < h && ja + 1 < w)) ld2g(f_tile + (long long)(il0 + r) * W + jo, fra[r], frb[r]);
+            else if (il0 + r < h && ja < w) fra[r] = f_tile[(long long)(il0 + r) * W + jo];
+        }
         float fua = 0.0f, fub = 0.0f;  // f of the row above (0 above the tile)
-        if (il0 > 0) ld2g(f_tile + (long long)(il0 - 1) * W + jo, fua, fub);
+        if (il0 > 0 && (!FR || (il0 - 1 < h && ja + 1 < w))) ld2g(f_tile + (long long)(il0 - 1) * W + jo, fua, fub);
+        else if (FR && il0 > 0 && il0 - 1 < h && ja < w) fua = f_tile[(long long)(il0 - 1) * W + jo];
 
         // ---- (1) stage the current iterate on the top, bottom and left sides.  The staging rows
         // are LDS rows that the steps write but never read, so no barrier has to separate these
@@ -171,7 +207,7 @@ __global__ __launch_bounds__(1024) void k_persist_fista(PersistArgs a)
         const int si = (s & 1) * 64 + opaque(lane);
         unsigned long long *xch = a.xch + (long long)(n & 1) * a.xch_stride + im.lam + side_base + si;
         float x_side = 0.0f, q_own = 0.0f;
-        if (side_wave) {
+        if (side_lane) {
             x_side = side == 3 ? S.rx[rx_slot][si] : side == 0 ? S.dl[kWaves - 1][si] : side == 1 ? S.yt[0][0][si] : S.dR[si];
             q_own = 2.0f * x_side - L.prv[side][si];
             L.prv[side][si] = x_side;
@@ -210,7 +246,7 @@ __global__ __launch_bounds__(1024) void k_persist_fista(PersistArgs a)
 
         // ---- (2) the neighbour's copy of each interface edge, (3) lambda^(n+1), (4b) c' of the
         // interface copies from phat = p^n -/+ tau lambda^(n+1) (t copies +, s copies -)
-        if (side_wave) {
+        if (side_lane) {
             // the pixel of the tile next to the edge (its f enters the edge's c')
             const int pi = side == 0 ? 0 : side == 1 ? kFusedMax - 1 : si;
             const int pj = side == 2 ? 0 : side == 3 ? kFusedMax - 1 : si;
@@ -240,8 +276,10 @@ __global__ __launch_bounds__(1024) void k_persist_fista(PersistArgs a)
             steps_total += taken;
             steps_max = max(steps_max, taken);
         } else if constexpr (KF > 0) {
-            rx_slot = full_steps_fixed<KF>(fc, S, A, B, a.fa.beta);
+            rx_slot = full_steps_fixed<KF, false, FR>(fc, S, A, B, a.fa.beta);
             if constexpr (KF & 1) copy_slot(A, B);
+        } else if constexpr (FR) {
+            rx_slot = run_steps<FramedStep>(fc, S, A, B, a.fa.n_inner, a.fa.beta);
         } else {
             rx_slot = run_steps<FullStep>(fc, S, A, B, a.fa.n_inner, a.fa.beta);
         }
@@ -255,20 +293,30 @@ __global__ __launch_bounds__(1024) void k_persist_fista(PersistArgs a)
 #pragma unroll
         for (int r = 0; r < kR; ++r) {
             const int il = il0 + r;
-            st2g(q1_tile + (long long)il * P1 + ja, A.e1a[r], A.e1b[r]);
-            st2g(q2_tile + (long long)il * P2 + ja, A.e2a[r], A.e2b[r]);
+            if (!FR || (il < h && ja + 1 < w)) {
+                st2g(q1_tile + (long long)il * P1 + ja, A.e1a[r], A.e1b[r]);
+                st2g(q2_tile + (long long)il * P2 + ja, A.e2a[r], A.e2b[r]);
+            } else if (il < h && ja < w) {  // framed: the tile's last column alone
+                q1_tile[(long long)il * P1 + ja] = A.e1a[r];
+                q2_tile[(long long)il * P2 + ja] = A.e2a[r];
+            }
         }
-        if (fc.last) st2g(q1_tile + (long long)kFusedMax * P1 + ja, A.ba, A.bb);
-        if (lane < kR) q2_tile[(long long)(il0 + lane) * P2 + kFusedMax] = S.rx[rx_slot][il0 + lane];
+        // the frame's bottom row and right column: a framed tile's own only when it spans the frame
+        if (fc.last && (!FR || (h == kFusedMax && ja + 1 < w)))
+            st2g(q1_tile + (long long)kFusedMax * P1 + ja, A.ba, A.bb);
+        else if (fc.last && h == kFusedMax && ja < w)
+            q1_tile[(long long)kFusedMax * P1 + ja] = A.ba;
+        if (lane < kR && (!FR || (w == kFusedMax && il0 + lane < h)))
+            q2_tile[(long long)(il0 + lane) * P2 + kFusedMax] = S.rx[rx_slot][il0 + lane];
     }
     if constexpr (ADAPT) {
-        if (threadIdx.x == 0) {  // the subdomain's only workgroup
+        if (threadIdx.x == 0) {  // the subdomain's only workgroup (adaptive: one launch, the plan's list)
             int *cnt = a.fa.counts + 2 * (long long)t;
             cnt[0] += steps_total;
             cnt[1] = max(cnt[1], steps_max);
         }
     }
-    if (side_wave && ok) {
+    if (side_lane && ok) {
         const int si = (s & 1) * 64 + lane;
         float *ls = a.lam_out + im.lam + side_base;
         if (side_s) {
@@ -277,6 +325,24 @@ __global__ __launch_bounds__(1024) void k_persist_fista(PersistArgs a)
         } else {
             ls[2 * nlam + si] = L.prv[side][si];
         }
+    }
+}
+
+// Every outer step of the subdomains subs[0, gridDim.x) in one cooperative launch, one
+// workgroup per subdomain.  FRAMES: some of them are framed tiles (smaller than 128 x 128),
+// which take the framed step; without it every subdomain is 128 x 128 (a kernel with one path,
+// which keeps the registers of the other out of the full tiles' loop).
+template <int KF, bool ADAPT = false, bool FRAMES = false>
+__global__ __launch_bounds__(1024) void k_persist_fista(PersistArgs a)
+{
+    __shared__ PersistLds L;
+    const int t = xcd_remap(blockIdx.x, gridDim.x);
+    if constexpr (FRAMES) {
+        const SubTile &tl = a.fa.subs[t];
+        if (tl.h == kFusedMax && tl.w == kFusedMax) persist_tile<KF, ADAPT, false>(a, L, t);
+        else persist_tile<KF, ADAPT, true>(a, L, t);
+    } else {
+        persist_tile<KF, ADAPT, false>(a, L, t);
     }
 }
 
@@ -294,11 +360,11 @@ using PersistKernel = void (*)(PersistArgs);
 // kernels with the inner step count unrolled, for the common counts
 template <int... Ks>
 struct PersistTable {
-    static PersistKernel get(int K)
+    static PersistKernel get(int K, bool frames)
     {
         PersistKernel k = nullptr;
-        ((K == Ks ? (k = k_persist_fista<Ks>, 0) : 0), ...);
-        return k ? k : k_persist_fista<0>;
+        ((K == Ks ? (k = frames ? k_persist_fista<Ks, false, true> : k_persist_fista<Ks>, 0) : 0), ...);
+        return k ? k : frames ? k_persist_fista<0, false, true> : k_persist_fista<0>;
     }
 };
 using Persist = PersistTable<1, 2, 3, 4, 5, 6, 7, 8, 10>;
@@ -313,7 +379,7 @@ int persist_capacity(int device)
     return per_cu * cus;
 }
 
-hipError_t launch_persist_fista(const PersistArgs &a, int nsub, hipStream_t s)
+hipError_t launch_persist_fista(const PersistArgs &a, int nsub, bool frames, hipStream_t s)
 {
     if (nsub <= 0 || a.n_outer <= 0) return hipSuccess;
     const bool adapt = a.fa.tol2 > 0.0;
@@ -321,7 +387,8 @@ hipError_t launch_persist_fista(const PersistArgs &a, int nsub, hipStream_t s)
     if (adapt && (!a.fa.beta_dev || !a.fa.counts)) return hipErrorInvalidValue;
     PersistArgs arg = a;
     void *args[] = {&arg};
-    const PersistKernel k = adapt ? k_persist_fista<0, true> : Persist::get(a.fa.n_inner);
+    if (adapt && frames) return hipErrorInvalidValue;  // adaptive stopping: 128 x 128 subdomains only
+    const PersistKernel k = adapt ? k_persist_fista<0, true> : Persist::get(a.fa.n_inner, frames);
     return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k), dim3(nsub), dim3(1024), args, 0, s);
 }
 

@@ -48,12 +48,17 @@ GEOMS = {
     "full3x3": (384, 384, [0, 128, 256, 384], [0, 128, 256, 384]),
     "full1x1": (128, 128, [0, 128], [0, 128]),
     "full2x4": (256, 512, [0, 128, 256], [0, 128, 256, 384, 512]),
+    # framed tiles: the last subdomain row (43 rows) and column (45 columns) end on the image boundary
+    "framed3x3": (299, 301, [0, 128, 256, 299], [0, 128, 256, 301]),
+    # one framed tile alone (smaller than 128 x 128 on all sides)
+    "framed1x1": (77, 100, [0, 77], [0, 100]),
 }
 
 
 @pytest.mark.parametrize("geom,K,n_outer", [("full3x3", 1, 5), ("full3x3", 2, 6), ("full3x3", 5, 7),
                                             ("full3x3", 11, 3), ("full1x1", 3, 4), ("full2x4", 4, 9),
-                                            ("full2x4", 10, 2)])
+                                            ("full2x4", 10, 2), ("framed3x3", 5, 6), ("framed3x3", 2, 4),
+                                            ("framed3x3", 9, 3), ("framed1x1", 4, 5)])
 def test_persistent_equals_fused_bitwise(geom, K, n_outer):
     from paper_1901_00682_amd import dtvdd
     H, W, rc, cc = GEOMS[geom]
@@ -88,6 +93,22 @@ def test_persistent_several_images():
         a, b = gpu_image_state(plan, st, k), gpu_image_state(one, st1)
         for q in a:
             assert np.array_equal(a[q], b[q]), (k, q)
+
+
+def test_persistent_groups_of_images():
+    """Three images of 90 subdomains each (full and framed tiles) do not fit on the device at
+    once: the persistent schedule runs them as groups of launches and equals the fused
+    schedule bitwise."""
+    from paper_1901_00682_amd import dtvdd
+    H, W = 1100, 1200
+    imgs = [dtvdd.Image(H, W, synth.tile_cuts(H, 128), synth.tile_cuts(W, 128), 4.0 + 2 * k) for k in range(3)]
+    fs = [_image(H, W, 70 + k) for k in range(3)]
+    _say("[persist] three images, 270 subdomains, groups of launches")
+    pp, sp, _ = _solve(imgs, fs, "persistent", 4, 5)
+    assert pp.schedule() == "persistent"
+    pf, sf, _ = _solve(imgs, fs, "fused", 4, 5)
+    for k in ("u", "p1", "p2", "lam"):
+        assert torch.equal(sp[k], sf[k]), k
 
 
 def test_persistent_resume_bitwise():
