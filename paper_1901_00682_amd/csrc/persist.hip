@@ -1,10 +1,12 @@
 // Persistent schedule of Algorithm 1 (Lee & Park, arXiv 1901.00682) for ROF
 // with FISTA local solves: one cooperative launch runs every outer step.
 //
-// Each workgroup owns one full 128 x 128 subdomain for the whole solve; its
-// iterate stays in VGPRs (the slots of the fused kernel) from the first outer
-// step to the last, so p~ crosses HBM twice per solve instead of twice per
-// outer step.  Per outer step n:
+// Each workgroup owns one 128 x 128 subdomain (or a framed one: smaller, with
+// its short sides on the image boundary, held in a 128 x 128 frame) for the
+// whole solve; its iterate stays in VGPRs (the slots of the fused kernel) from
+// the first outer step to the last, so p~ crosses HBM twice per solve instead
+// of twice per outer step.  The images of a plan whose subdomains do not all
+// fit on the device at once run as groups of launches.  Per outer step n:
 //   (1) each tile forms q = 2 p^n - p^(n-1) on its own interface copies (the
 //       extrapolated copies of the multiplier update) and publishes them;
 //   (4a) meanwhile it rebuilds c' of every edge but the interface copies from
