@@ -331,21 +331,14 @@ __device__ __forceinline__ void persist_tile(const PersistArgs &a, PersistLds &L
 }
 
 // Every outer step of the subdomains subs[0, gridDim.x) in one cooperative launch, one
-// workgroup per subdomain.  FRAMES: some of them are framed tiles (smaller than 128 x 128),
-// which take the framed step; without it every subdomain is 128 x 128 (a kernel with one path,
-// which keeps the registers of the other out of the full tiles' loop).
+// workgroup per subdomain.  FRAMES: some of them are framed tiles (smaller than 128 x 128); then
+// every tile takes the framed path, which on a 128 x 128 tile does what the full-tile path does
+// (one path per kernel keeps the registers of the other out of its loop).
 template <int KF, bool ADAPT = false, bool FRAMES = false>
 __global__ __launch_bounds__(1024) void k_persist_fista(PersistArgs a)
 {
     __shared__ PersistLds L;
-    const int t = xcd_remap(blockIdx.x, gridDim.x);
-    if constexpr (FRAMES) {
-        const SubTile &tl = a.fa.subs[t];
-        if (tl.h == kFusedMax && tl.w == kFusedMax) persist_tile<KF, ADAPT, false>(a, L, t);
-        else persist_tile<KF, ADAPT, true>(a, L, t);
-    } else {
-        persist_tile<KF, ADAPT, false>(a, L, t);
-    }
+    persist_tile<KF, ADAPT, FRAMES>(a, L, xcd_remap(blockIdx.x, gridDim.x));
 }
 
 bool persist_supported(int device)
