@@ -92,6 +92,8 @@ def workload(name: str):
         return synth.config2()
     if name == "rof8192":
         return synth.config2(size=8192)
+    if name == "rof2000":  # 16 x 16 equal subdomains of 125 x 125: every one framed, interfaces on all sides
+        return synth.rof_case("rof2000_16x16", 2000, 2000, 16, 16, 8.0, 0.1, 500, 5, workload=2)
     if name == "tvl1":
         return synth.config3()
     if name == "cv2048":

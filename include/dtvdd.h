@@ -97,9 +97,9 @@ extern "C" {
 #define DTV_SCHED_PERSIST 3  /* one cooperative launch runs every outer step; the iterates stay
                                 on chip between outer steps (no diagnostics, no
                                 save_for_backward).  FISTA with a fixed inner count: every
-                                subdomain 128 x 128, or smaller with its short sides on the
-                                image boundary; each image's subdomains resident on the
-                                device at once, the images run in groups of launches.  CP2 or
+                                subdomain at most 128 x 128 (smaller ones run in a 128 x 128
+                                frame); each image's subdomains resident on the device at
+                                once, the images run in groups of launches.  CP2 or
                                 inner_tol: every subdomain exactly 128 x 128, all of them
                                 resident at once (one launch) */
 

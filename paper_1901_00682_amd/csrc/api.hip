@@ -197,6 +197,17 @@ static bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
 static bool any_of_sched(int requested, int sched) { return requested == DTV_SCHED_AUTO || requested == sched; }
 
+// How the full-tile step runs a subdomain: 0 a full 128 x 128 tile; 1 a framed tile (smaller, each
+// short side on the image boundary); 2 any other tile of at most 128 x 128 (framed, with masks);
+// 3 larger than 128 in either direction (the streaming kernels only)
+static int frame_kind(const dtv_dd_plan *pl, const SubTile &st)
+{
+    if (st.h > kFusedMax || st.w > kFusedMax) return 3;
+    if (st.h == kFusedMax && st.w == kFusedMax) return 0;
+    const ImgHost &h = pl->imgs[st.img];
+    return (st.h == kFusedMax || st.r == h.ny - 1) && (st.w == kFusedMax || st.c == h.nx - 1) ? 1 : 2;
+}
+
 // The autotuner's candidates: the schedules the plan admits (persistent, fused,
 // streaming) times the streaming rows (4, 8, 16, 32), restricted by explicit
 // choices in the parameters.
@@ -375,13 +386,10 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
                                              h.ccut[c + 1] - h.ccut[c], 0});
     }
     // full 128 x 128 subdomains first, then framed ones (smaller, with each short side on the image
-    // boundary): the fused schedule runs both with the specialised full-tile step
-    auto is_full = [](const SubTile &st) { return st.h == kFusedMax && st.w == kFusedMax; };
-    auto is_framed = [&](const SubTile &st) {
-        const ImgHost &h = pl->imgs[st.img];
-        return !is_full(st) && st.h <= kFusedMax && st.w <= kFusedMax && (st.h == kFusedMax || st.r == h.ny - 1) &&
-               (st.w == kFusedMax || st.c == h.nx - 1);
-    };
+    // boundary), then the rest: the fused schedule runs all three with the specialised full-tile
+    // step (frame_kind)
+    auto is_full = [&](const SubTile &st) { return frame_kind(pl, st) == 0; };
+    auto is_framed = [&](const SubTile &st) { return frame_kind(pl, st) == 1; };
     std::stable_partition(pl->h_subs.begin(), pl->h_subs.end(),
                           [&](const SubTile &st) { return is_full(st) || is_framed(st); });
     std::stable_partition(pl->h_subs.begin(), pl->h_subs.end(), is_full);
@@ -407,14 +415,15 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
                                 "or of exactly 128 x 128 (CP2)");
     }
     {
-        // persistent: full subdomains (FISTA: or framed ones), no per-step host work; the primal-dual
-        // kernel and adaptive stopping take every subdomain in one launch, fixed-count FISTA runs the
-        // images in groups of launches, each group resident on the device at once
+        // persistent: full subdomains (fixed-count FISTA: any of at most 128 x 128), no per-step host
+        // work; the primal-dual kernel and adaptive stopping take every subdomain in one launch,
+        // fixed-count FISTA runs the images in groups of launches, each group resident on the
+        // device at once
         const int nsub = (int)pl->h_subs.size();
         const bool fista = p.inner == DTV_INNER_FISTA;
         const bool one_launch = !fista || pl->adaptive;
         pl->persist_ok = pl->fused_ok && nsub > 0 && p.diag_every == 0 && !p.save_for_backward &&
-                         (pl->n_full == nsub || (!one_launch && pl->n_full + pl->n_framed == nsub));
+                         (pl->n_full == nsub || !one_launch);
         int dev = 0;
         if (pl->persist_ok && hipGetDevice(&dev) == hipSuccess && persist_supported(dev)) {
             const int cap = fista ? persist_capacity(dev) : persist_cp2_capacity(dev);
@@ -995,9 +1004,9 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
             pa.spin_limit = spin_limit;
             // one cooperative launch per group of images; the groups share nothing
             for (size_t g = 0; g + 1 < pl->p_group.size(); ++g) {
-                bool frames = false;  // the group holds framed subdomains
+                int frames = 0;  // the most general kind of subdomain in the group (frame_kind)
                 for (int i = pl->p_group[g]; i < pl->p_group[g + 1]; ++i)
-                    frames = frames || pl->p_subs[i].h < kFusedMax || pl->p_subs[i].w < kFusedMax;
+                    frames = std::max(frames, frame_kind(pl, pl->p_subs[i]));
                 pa.fa.subs = pl->d_psubs() + pl->p_group[g];
                 HIP_TRY(launch_persist_fista(pa, pl->p_group[g + 1] - pl->p_group[g], frames, s), "persistent FISTA");
             }

@@ -214,7 +214,9 @@ hipError_t launch_diag(const ImgDev *imgs, int nimg, int maxH, int maxW, const i
                        double *partials, int nblk_per_img, double *out, hipStream_t s);
 int diag_blocks_per_image(int maxH, int maxW);
 // Persistent schedule: every outer step in one cooperative launch (persist.hip).
-// All subdomains are full 128 x 128 tiles and the grid fits on the device at once.
+// The subdomains of the launch are at most 128 x 128 and resident on the device at once.
+// frames: 0 every one is a full 128 x 128 tile, 1 the smaller ones have their short sides on the
+// image boundary, 2 any smaller ones (run in a 128 x 128 frame with masks).
 struct PersistArgs {
     FusedArgs fa;          // base = p~^0 (read), out = p~^N (written; may alias base), lam = lambda state in
     float *lam_out;        // lambda state out (may alias fa.lam)
@@ -227,7 +229,7 @@ struct PersistArgs {
 };
 bool persist_supported(int device);
 int persist_capacity(int device);  // workgroups of the persistent kernel resident at once
-hipError_t launch_persist_fista(const PersistArgs &a, int nsub, bool frames, hipStream_t s);
+hipError_t launch_persist_fista(const PersistArgs &a, int nsub, int frames, hipStream_t s);
 
 // Reverse mode of one outer step on full 128 x 128 subdomains (fused_bwd.hip),
 // from the step records of the fused kernel.
@@ -253,7 +255,8 @@ hipError_t launch_fused_bwd(const FusedBwdArgs &a, int nsub, hipStream_t s);
 bool fused_record_supported(int K);
 // subs[0, nfull) are 128 x 128 tiles (specialised kernel), subs[nfull, nfull + nframed) framed
 // tiles (smaller, their short sides on the image boundary: the specialised kernel in a 128 x 128
-// frame), the rest any other tiles of at most 128 x 128
+// frame), the rest any other tiles of at most 128 x 128 (the specialised kernel in a frame, with
+// masks; the general kernel with adaptive stopping or recording)
 hipError_t launch_fused_fista(const FusedArgs &a, int nsub, int nfull, int nframed, hipStream_t s,
                               hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 

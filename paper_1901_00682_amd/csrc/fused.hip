@@ -31,9 +31,11 @@ using namespace fused;
 
 // One workgroup's work on subdomain t.  LS holds lambda^(n+1) on the top, bottom, left and
 // right sides; red is the reduction buffer of the adaptive rule (2 kWaves doubles).
-// FR (with kFull): a framed tile, smaller than 128 x 128 with its short sides on the image
-// boundary, run by the full-tile step in a 128 x 128 frame (full_step<.., FR>).
-template <bool kFull, int KF, bool REC, bool ADAPT, bool FR = false>
+// FR (with kFull): a framed tile, smaller than 128 x 128, run by the full-tile step in a
+// 128 x 128 frame (full_step<.., FR>): FR = 1 when its short sides lie on the image boundary,
+// FR = 2 for any tile of at most 128 x 128 (its bottom edges sit in frame row h and its right
+// edges in frame column w, interface copies or not).
+template <bool kFull, int KF, bool REC, bool ADAPT, int FR = 0>
 __device__ __forceinline__ void fused_tile(const FusedArgs &a, int t, FusedLds &S, float (&LS)[4][kFusedMax],
                                            double *red)
 {
@@ -90,6 +92,9 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, int t, FusedLds &
     const float *p1_tile = b1 + row1 * P1 + tl.ca;                          // edge above pixel (0, 0)
     const float *p2_tile = b2 + (long long)tl.ra * P2 + col2;               // edge left of pixel (0, 0)
     const bool lastcol = c.lastcol_a || c.lastcol_b;
+    // columns of the left edges held in registers: 0 .. w - 1, and w (the right edges) when a
+    // framed tile with masks is narrower than the frame
+    const bool l2a = FR == 2 ? ja <= w : c.acta, l2b = FR == 2 ? jb <= w : c.actb;
     float fva[kR], fvb[kR];  // f of the strip's rows at columns a and b
     float xr[kR];            // right boundary edges of the rows (last-column lane)
     float fua = 0.0f, fub = 0.0f;  // f of the row above (0 above the tile)
@@ -109,19 +114,26 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, int t, FusedLds &
                 ld2(fr + ja, fva[r], fvb[r]);
             } else if (c.acta) {
                 x1a = p1r[ja];
-                x2a = p2r[ja];
                 fva[r] = fr[ja];
+                if (l2b) ld2(p2r + ja, x2a, x2b);
+                else x2a = p2r[ja];
+            } else if (l2a) {
+                x2a = p2r[ja];
             }
+        } else if (FR == 2 && il == h) {  // the tile's bottom edges, in frame row h < 128
+            const float *p1r = p1_tile + (long long)il * P1;
+            if (c.actb) ld2(p1r + ja, x1a, x1b);
+            else if (c.acta) x1a = p1r[ja];
         }
         A.e1a[r] = x1a; A.e2a[r] = x2a; A.e1b[r] = x1b; A.e2b[r] = x2b;
     }
     // ... then the conditional ones (waiting on one of these waits on everything issued before it)
-    if (il0 > 0 && il0 < h) {
+    if (il0 > 0 && (il0 < h || (FR == 2 && il0 == h))) {
         const float *fr = f_tile + (long long)(il0 - 1) * W;
         if (c.actb) ld2(fr + ja, fua, fub);
         else if (c.acta) fua = fr[ja];
     }
-    if (c.has_bottom) {  // bottom boundary edges
+    if (c.has_bottom && (!FR || h == kFusedMax)) {  // bottom boundary edges (the frame's own when framed)
         const float *pb = p1_tile + (long long)h * P1;
         if (c.acta) A.ba = pb[ja];
         if (c.actb) A.bb = pb[jb];
@@ -129,7 +141,8 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, int t, FusedLds &
 #pragma unroll
     for (int r = 0; r < kR; ++r) {
         const int il = il0 + r;
-        if ((kShape || il < h) && lastcol) xr[r] = p2_tile[(long long)il * P2 + w];  // right boundary edge of the row
+        if ((kShape || il < h) && lastcol && (!FR || w == kFusedMax))
+            xr[r] = p2_tile[(long long)il * P2 + w];  // right boundary edge of the row
     }
 
     // ---- (a1) lambda^(n+1) = lambda^n + sigma [(2 p_s^n - p_s^(n-1)) - (2 p_t^n - p_t^(n-1))] on the
@@ -193,23 +206,32 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, int t, FusedLds &
         const float fla = from_left(fvb[r]);  // f of column a - 1 (lane 0: left of the tile, 0)
         if constexpr (FR) {
             // every c' entry of the frame written once: the tile's edges as below, 0 outside it
+            // (with masks, row h < 128 holds the tile's bottom edges and column w < 128 its right
+            // edges: s copies of an interface, anchored with -tau lambda, unless on the image
+            // boundary; f is 0 below and right of the tile)
             float c1a = 0.0f, c1b = 0.0f, c2a = 0.0f, c2b = 0.0f;
-            if (il < h) {
+            if (il < h || (FR == 2 && il == h)) {
                 float ata = A.e1a[r], atb = A.e1b[r];
                 if (il == 0 && tl.r > 0) {
                     if (c.acta) ata = fmaf(tau, LS[0][ja], ata);
                     if (c.actb) atb = fmaf(tau, LS[0][jb], atb);
                 }
-                float ala = A.e2a[r];
+                if (FR == 2 && il == h && !c.bot_bnd) {
+                    if (c.acta) ata = fmaf(-tau, LS[1][ja], ata);
+                    if (c.actb) atb = fmaf(-tau, LS[1][jb], atb);
+                }
+                if (c.acta) c1a = fista_cprime(ata, fua, fva[r], itau, invL);
+                if (c.actb) c1b = fista_cprime(atb, fub, fvb[r], itau, invL);
+            }
+            if (il < h) {
+                float ala = A.e2a[r], alb = A.e2b[r];
                 if (ja == 0 && tl.c > 0) ala = fmaf(tau, LS[2][il], ala);
-                if (c.acta) {
-                    c1a = fista_cprime(ata, fua, fva[r], itau, invL);
-                    c2a = fista_cprime(ala, ja > 0 ? fla : 0.0f, fva[r], itau, invL);
+                if (FR == 2 && !c.right_bnd) {
+                    if (ja == w) ala = fmaf(-tau, LS[3][il], ala);
+                    if (jb == w) alb = fmaf(-tau, LS[3][il], alb);
                 }
-                if (c.actb) {
-                    c1b = fista_cprime(atb, fub, fvb[r], itau, invL);
-                    c2b = fista_cprime(A.e2b[r], fva[r], fvb[r], itau, invL);
-                }
+                if (l2a) c2a = fista_cprime(ala, ja > 0 ? fla : 0.0f, fva[r], itau, invL);
+                if (l2b) c2b = fista_cprime(alb, fva[r], fvb[r], itau, invL);
             }
             lds_st2(&S.c1[il][ja], c1a, c1b);
             lds_st2(&S.c2[il][ja], c2a, c2b);
@@ -303,24 +325,32 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, int t, FusedLds &
         fc.lo2b = -1.0f;
         fc.hi2b = 1.0f;
         fc.zrows = 0u;
+        fc.mrows = 0xFFu;
+        fc.lva = fc.lvb = true;
         if constexpr (FR) {
-            // the boundary lines of a framed tile: the left edges of column w, the top edges of row h
-            const bool za = w < kFusedMax && ja == w, zb = w < kFusedMax && jb == w;
+            // the boundary lines of a framed tile: the left edges of column w, the top edges of
+            // row h; clamped when on the image boundary (always, without masks)
+            const bool rz = FR == 1 || c.right_bnd, bz = FR == 1 || c.bot_bnd;
+            const bool za = rz && w < kFusedMax && ja == w, zb = rz && w < kFusedMax && jb == w;
             fc.lo2a = za ? 0.0f : fc.lo2a;
             fc.hi2a = za ? 0.0f : fc.hi2a;
             fc.lo2b = zb ? 0.0f : -1.0f;
             fc.hi2b = zb ? 0.0f : 1.0f;
             const int zr = h - il0;
-            fc.zrows = (h < kFusedMax && zr >= 0 && zr < kR) ? 1u << zr : 0u;
+            fc.zrows = (bz && h < kFusedMax && zr >= 0 && zr < kR) ? 1u << zr : 0u;
             fc.right_bnd = c.right_bnd || w < kFusedMax;  // the frame's right column lies outside the tile
+            // the pixels inside the tile: rows il0 .. h - 1 of the strip, columns below w
+            fc.mrows = zr >= kR ? 0xFFu : zr <= 0 ? 0u : (1u << zr) - 1u;
+            fc.lva = c.acta;
+            fc.lvb = c.actb;
         }
         if constexpr (ADAPT) {
             rx_slot = run_steps_adaptive<FullStep>(fc, S, A, B, K, a.beta_dev, a.tol2, red, taken);
         } else if constexpr (FR && KF > 0) {
-            rx_slot = full_steps_fixed<KF, false, true>(fc, S, A, B, a.beta);
+            rx_slot = full_steps_fixed<KF, false, FR>(fc, S, A, B, a.beta);
             if constexpr (KF & 1) copy_slot(A, B);
         } else if constexpr (FR) {
-            rx_slot = run_steps<FramedStep>(fc, S, A, B, K, a.beta);
+            rx_slot = run_steps<FramedStep<FR>>(fc, S, A, B, K, a.beta);
         } else if constexpr (KF > 0) {
             if constexpr (REC) {
                 const long long rec_step = (long long)gridDim.x * kRecGroups * kRecThreads;
@@ -364,10 +394,18 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, int t, FusedLds &
                 st2(q2 + ja, A.e2a[r], A.e2b[r]);
             } else if (c.acta) {
                 q1[ja] = A.e1a[r];
+                if (l2b) st2(q2 + ja, A.e2a[r], A.e2b[r]);
+                else q2[ja] = A.e2a[r];
+            } else if (l2a) {
                 q2[ja] = A.e2a[r];
             }
-            // the right boundary edge; a framed tile narrower than 128 has it on the image boundary
+            // the right boundary edge: a framed tile narrower than 128 holds it in column w with
+            // masks, and has it on the image boundary without
             if ((c.lastcol_a || c.lastcol_b) && (!FR || w == kFusedMax)) q2[w] = S.rx[rx_slot][il];
+        } else if (FR == 2 && il == h) {  // the bottom edges of a framed tile lower than 128
+            float *q1 = q1_tile + (long long)il * P1;
+            if (c.actb) st2(q1 + ja, A.e1a[r], A.e1b[r]);
+            else if (c.acta) q1[ja] = A.e1a[r];
         }
     }
     if (c.has_bottom && (!FR || h == kFusedMax)) {
@@ -392,9 +430,10 @@ __global__ __launch_bounds__(1024) void k_fused_fista(FusedArgs a, int first)
 }
 
 // Every kind of tile in one launch (fixed n_inner, no recording).  The list holds the full
-// tiles first, then the framed ones, then the other (general) ones; blocks [0, gpad) take the
-// general tiles, [gpad, gpad + fpad) the framed ones (gpad, fpad: the counts rounded up to a
-// multiple of 8; the extra blocks exit at once), the rest the full tiles.  The slower kinds are
+// tiles first, then the framed ones (short sides on the image boundary), then the others, which
+// run framed with masks; blocks [0, gpad) take the other tiles, [gpad, gpad + fpad) the framed
+// ones (gpad, fpad: the counts rounded up to a multiple of 8; the extra blocks exit at once),
+// the rest the full tiles.  The slower kinds are
 // dispatched first, spread over the XCDs; the full tiles keep the XCD-aware order, and no launch
 // boundary separates the kinds.
 template <int KF>
@@ -406,9 +445,9 @@ __global__ __launch_bounds__(1024) void k_fused_fista_mixed(FusedArgs a, int nfu
     const int gpad = (ngen + 7) & ~7, fpad = (nframed + 7) & ~7;
     const int b = blockIdx.x;
     if (b < gpad) {
-        if (b < ngen) fused_tile<false, 0, false, false>(a, nfull + nframed + b, S, LS, red);
+        if (b < ngen) fused_tile<true, KF, false, false, 2>(a, nfull + nframed + b, S, LS, red);
     } else if (b < gpad + fpad) {
-        if (b - gpad < nframed) fused_tile<true, KF, false, false, true>(a, nfull + b - gpad, S, LS, red);
+        if (b - gpad < nframed) fused_tile<true, KF, false, false, 1>(a, nfull + b - gpad, S, LS, red);
     } else {
         fused_tile<true, KF, false, false>(a, xcd_remap(b - gpad - fpad, gridDim.x - gpad - fpad), S, LS, red);
     }

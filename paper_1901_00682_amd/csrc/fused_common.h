@@ -195,11 +195,14 @@ struct FullCtx {
     float lo1, hi1, lo2a, hi2a, lob, hib;
     float ak, kL;
     float qa, qb;  // recording: the weights of y and of d_b - d_a in the record word q
-    // framed tiles only (a subdomain smaller than 128 x 128 whose short sides lie on the image
-    // boundary, run in a 128 x 128 frame): clamp bounds of the left edge of column b, and the
-    // strip's rows whose top edges are the tile's bottom boundary (bit r: row 8 s + r)
+    // framed tiles only (a subdomain smaller than 128 x 128 run in a 128 x 128 frame): clamp
+    // bounds of the left edge of column b, the strip's rows whose top edges are the tile's bottom
+    // boundary on the image boundary (bit r: row 8 s + r), and, with masks, the strip's rows inside
+    // the tile and whether columns a and b are inside it
     float lo2b, hi2b;
     unsigned zrows;
+    unsigned mrows;
+    bool lva, lvb;
 };
 
 __device__ __forceinline__ int opaque(int x)
@@ -261,6 +264,14 @@ __device__ __forceinline__ void full_row_div(const Slot &Y, float ry, int r, flo
 //   g = 9     the projection mask of the bottom edges (bits 0, 1) and of the right
 //             boundary edge (bit 2); three unused words
 
+// a framed tile with masks: d is 0 on the pixels outside the tile (row r of the strip)
+__device__ __forceinline__ void dmask(const FullCtx &c, int r, float &da, float &db)
+{
+    const bool row = ((c.mrows >> r) & 1u) != 0;
+    da = (row && c.lva) ? da : 0.0f;
+    db = (row && c.lvb) ? db : 0.0f;
+}
+
 // projected step value and, when recording, the mask bit of its derivative
 template <bool REC>
 __device__ __forceinline__ float proj(float z, float lo, float hi, unsigned &m, int bit)
@@ -269,12 +280,16 @@ __device__ __forceinline__ float proj(float z, float lo, float hi, unsigned &m, 
     return __builtin_amdgcn_fmed3f(z, lo, hi);
 }
 
-// FR: a framed tile.  The tile's h x w pixels sit at the top left of the 128 x 128 frame, its
-// bottom and right sides (when shorter than the frame) on the image boundary.  Outside the tile
-// every edge starts at 0 with c' = 0; the edges of the two boundary lines (the top edges of row
-// h, the left edges of column w) are clamped to 0, so the pixels outside keep d = 0 and the
-// tile's own edges are updated exactly as in a tile of its own size.
-template <bool mom, bool REC = false, bool FR = false>
+// FR: a framed tile.  The tile's h x w pixels sit at the top left of the 128 x 128 frame; its
+// bottom edges are the top edges of frame row h and its right edges the left edges of frame
+// column w (the frame's own bottom row and right column when h or w is 128).  Outside the tile
+// every edge starts at 0 with c' = 0.  A side on the image boundary is clamped to 0.
+//   FR = 1: the short sides (h or w below 128) lie on the image boundary; their clamped edges
+//           keep d = 0 on the pixels outside, so the tile's edges see exactly the values of a
+//           tile of its own size.
+//   FR = 2: any tile; d of the pixels outside is set to 0 (masks), so a short side may be an
+//           interface whose copies are updated in the frame.
+template <bool mom, bool REC = false, int FR = 0>
 __device__ __forceinline__ void full_step(const FullCtx &c, FusedLds &S, const Slot &X, Slot &Y, int sx, float beta,
                                           float4 *rec = nullptr)
 {
@@ -312,6 +327,7 @@ __device__ __forceinline__ void full_step(const FullCtx &c, FusedLds &S, const S
     float *dl = &S.dl[0][0] + oy;
     float da7, db7;  // d of the last row (the row sweep reuses it)
     full_row_div(Y, RYr[kR - 1], kR - 1, ya7, yb7, da7, db7);
+    if constexpr (FR == 2) dmask(c, kR - 1, da7, db7);
     lds_st2(dl, da7, db7);
     __syncthreads();
 
@@ -327,7 +343,10 @@ __device__ __forceinline__ void full_step(const FullCtx &c, FusedLds &S, const S
     for (int r = 0; r < kR; ++r) {
         __builtin_amdgcn_sched_barrier(0);  // one row at a time: bounds the registers in flight
         float da = da7, db = db7;
-        if (r < kR - 1) full_row_div(Y, RYr[r], r, Y.e1a[r + 1], Y.e1b[r + 1], da, db);
+        if (r < kR - 1) {
+            full_row_div(Y, RYr[r], r, Y.e1a[r + 1], Y.e1b[r + 1], da, db);
+            if constexpr (FR == 2) dmask(c, r, da, db);
+        }
         const float dlb = from_left(db);
         if constexpr (REC)
             rec[r * kRecThreads] =
@@ -399,12 +418,13 @@ struct FullStep {
     }
 };
 
+template <int FR>
 struct FramedStep {
     template <bool mom>
     __device__ __forceinline__ static void step(const FullCtx &c, FusedLds &S, const Slot &X, Slot &Y, int sx,
                                                 float beta)
     {
-        full_step<mom, false, true>(c, S, X, Y, sx, beta);
+        full_step<mom, false, FR>(c, S, X, Y, sx, beta);
     }
 };
 
@@ -549,7 +569,7 @@ __device__ __forceinline__ int run_steps(const C &c, FusedLds &S, Slot &A, Slot 
 // costs register copies, and spills where the caller keeps more state live).
 // x_K ends in A when K is even and in B when K is odd; returns the LDS slot of
 // the right boundary column holding it (K & 1).
-template <int K, bool REC = false, bool FR = false, int k = 1>
+template <int K, bool REC = false, int FR = 0, int k = 1>
 __device__ __forceinline__ int full_steps_fixed(const FullCtx &c, FusedLds &S, Slot &X, Slot &Y, const float *beta,
                                                 float4 *rec = nullptr, long long rec_step = 0)
 {

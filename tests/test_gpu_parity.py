@@ -99,17 +99,26 @@ FUSED_GEOMS = {
     "framed": (299, 301, [0, 128, 256, 299], [0, 128, 256, 301]),
     # framed tiles beside general ragged ones (a 57-column subdomain with interfaces on both sides)
     "framed_mixed": (200, 313, [0, 128, 200], [0, 128, 185, 313]),
+    # equal cuts below 128: every tile is framed with interfaces on its short sides (127 rows, the
+    # bottom edges in the last row of the frame's last strip; 127 or 128 columns)
+    "floor": (381, 383, [0, 127, 254, 381], [0, 128, 255, 383]),
+    # subdomains one pixel high or wide between two interfaces
+    "thin": (257, 257, [0, 128, 129, 257], [0, 128, 129, 257]),
+    # 120 rows (the bottom edges open a strip), 64 and 8 columns (even: the right edges in column a)
+    "strip8": (360, 200, [0, 120, 240, 360], [0, 64, 192, 200]),
 }
 
 
 @pytest.mark.parametrize("geom,K", [("mixed", k) for k in (1, 2, 3, 4, 5, 7, 9)]
                          + [("full3x3", k) for k in (1, 2, 5, 6)] + [("full1x1", 3)]
-                         + [("framed", k) for k in (1, 2, 5, 9)] + [("framed_mixed", k) for k in (3, 5)])
+                         + [("framed", k) for k in (1, 2, 5, 9)] + [("framed_mixed", k) for k in (3, 5)]
+                         + [("floor", 5), ("floor", 9), ("thin", 4), ("strip8", 5), ("strip8", 2)])
 def test_fused_equals_stream_bitwise(geom, K):
     """The two schedules of the FISTA local solves round identically: full
     128 x 128 subdomains (the specialised kernel) with image boundaries and
-    interfaces on every combination of sides, ragged ones, and every parity of
-    the inner count (K = 9 takes the runtime step loop)."""
+    interfaces on every combination of sides, smaller ones run in a 128 x 128
+    frame (short sides on the image boundary or interfaces, 1 to 127 pixels),
+    and every parity of the inner count (K = 9 takes the runtime step loop)."""
     rng = np.random.default_rng(100 + K + 1000 * list(FUSED_GEOMS).index(geom))
     H, W, rc, cc = FUSED_GEOMS[geom]
     rc, cc = np.array(rc), np.array(cc)

@@ -1,7 +1,9 @@
 """The persistent schedule (every outer step in one cooperative launch, the
 iterates kept on chip between outer steps) against the fused and streaming
 schedules, bitwise, and against the FP64 oracle: full-tile geometries with
-image boundaries on every combination of sides, several images in one plan,
+image boundaries on every combination of sides, smaller subdomains run in a
+128 x 128 frame (short sides on the image boundary or interfaces), several
+images in one plan,
 odd and even inner counts (unrolled and generic kernels), resume from a
 returned state."""
 import sys
@@ -52,13 +54,23 @@ GEOMS = {
     "framed3x3": (299, 301, [0, 128, 256, 299], [0, 128, 256, 301]),
     # one framed tile alone (smaller than 128 x 128 on all sides)
     "framed1x1": (77, 100, [0, 77], [0, 100]),
+    # framed tiles with interfaces on their short sides (masks): ragged cuts beside full tiles
+    "mixed": (300, 357, [0, 128, 256, 300], [0, 101, 229, 357]),
+    # equal cuts below 128 (127 rows; 127 or 128 columns)
+    "floor": (381, 383, [0, 127, 254, 381], [0, 128, 255, 383]),
+    # subdomains one pixel high or wide between two interfaces
+    "thin": (257, 257, [0, 128, 129, 257], [0, 128, 129, 257]),
+    # 120 rows (the bottom edges open a strip), 64 and 8 columns (the right edges in column a)
+    "strip8": (360, 200, [0, 120, 240, 360], [0, 64, 192, 200]),
 }
 
 
 @pytest.mark.parametrize("geom,K,n_outer", [("full3x3", 1, 5), ("full3x3", 2, 6), ("full3x3", 5, 7),
                                             ("full3x3", 11, 3), ("full1x1", 3, 4), ("full2x4", 4, 9),
                                             ("full2x4", 10, 2), ("framed3x3", 5, 6), ("framed3x3", 2, 4),
-                                            ("framed3x3", 9, 3), ("framed1x1", 4, 5)])
+                                            ("framed3x3", 9, 3), ("framed1x1", 4, 5), ("mixed", 5, 6),
+                                            ("mixed", 9, 3), ("floor", 5, 5), ("floor", 2, 4), ("thin", 3, 6),
+                                            ("strip8", 5, 5), ("strip8", 4, 3)])
 def test_persistent_equals_fused_bitwise(geom, K, n_outer):
     from paper_1901_00682_amd import dtvdd
     H, W, rc, cc = GEOMS[geom]
@@ -141,9 +153,12 @@ def test_persistent_config2():
 
 def test_persistent_rejected_when_not_applicable():
     from paper_1901_00682_amd import dtvdd
-    with pytest.raises(dtvdd.DtvError):  # ragged tiles
-        dtvdd.Plan([dtvdd.Image(300, 357, [0, 128, 256, 300], [0, 101, 229, 357], 8.0)], n_outer=2,
+    with pytest.raises(dtvdd.DtvError):  # a subdomain wider than 128
+        dtvdd.Plan([dtvdd.Image(300, 357, [0, 128, 256, 300], [0, 200, 357], 8.0)], n_outer=2,
                    schedule="persistent")
+    with pytest.raises(dtvdd.DtvError):  # ragged tiles, primal-dual local solves (full tiles only)
+        dtvdd.Plan([dtvdd.Image(300, 357, [0, 128, 256, 300], [0, 101, 229, 357], 8.0)], n_outer=2,
+                   schedule="persistent", inner="CP2")
     with pytest.raises(dtvdd.DtvError):  # per-step diagnostics
         dtvdd.Plan([dtvdd.Image(256, 256, [0, 128, 256], [0, 128, 256], 8.0)], n_outer=2, diag_every=1,
                    schedule="persistent")
