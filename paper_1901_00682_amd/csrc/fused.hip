@@ -104,6 +104,10 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, int t, FusedLds &
         const int il = il0 + r;
         float x1a = 0.0f, x1b = 0.0f, x2a = 0.0f, x2b = 0.0f;
         fva[r] = fvb[r] = xr[r] = 0.0f;
+        // (the zeros of the edges are written in every lane before the loads, pinned there:
+        // written only in the lanes that skip a load, a zero would wait for the other lanes' load
+        // into the same register, and the rows' loads would not overlap)
+        if constexpr (!kShape) pin4(x1a, x1b, x2a, x2b);
         if (kShape || il < h) {  // (always on full tiles)
             const float *p1r = p1_tile + (long long)il * P1;
             const float *p2r = p2_tile + (long long)il * P2;
