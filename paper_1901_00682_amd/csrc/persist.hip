@@ -236,10 +236,16 @@ __device__ __forceinline__ void persist_tile(const PersistArgs &a, PersistLds &L
         if constexpr (FR == 2) {
             // the bottom edges from row h, the right edges from column w (the parity-1 top-edge row
             // of strip 0, also written by the steps and never read)
+            if (in_row && h >= il0 && h < il0 + kR) {  // the strip holding row h
 #pragma unroll
-            for (int r = 0; r < kR; ++r) {
-                if (in_row && il0 + r == h) lds_st2(&S.yt[0][0][ja], A.e1a[r], A.e1b[r]);
-                if (in_col && ja == (w & ~1) && il0 + r < h) S.yt[1][0][il0 + r] = (w & 1) ? A.e2b[r] : A.e2a[r];
+                for (int r = 0; r < kR; ++r)
+                    if (il0 + r == h) lds_st2(&S.yt[0][0][ja], A.e1a[r], A.e1b[r]);
+            }
+            if (in_col && ja == (w & ~1) && il0 < h) {  // the lane holding column w
+                const bool odd = (w & 1) != 0;
+#pragma unroll
+                for (int r = 0; r < kR; ++r)
+                    if (il0 + r < h) S.yt[1][0][il0 + r] = odd ? A.e2b[r] : A.e2a[r];
             }
         }
         if (threadIdx.x == 0) L.ok = 1;
@@ -281,11 +287,8 @@ __device__ __forceinline__ void persist_tile(const PersistArgs &a, PersistLds &L
                 const bool if_row = (il == 0 && top_if) || (in_row && il == h && bot_if);
                 const float c1a = fista_cprime(A.e1a[r], fua, fva, itau, invL);
                 const float c1b = fista_cprime(A.e1b[r], fub, fvb, itau, invL);
-                if (FR < 2) {
-                    if (!if_row) lds_st2(&S.c1[il][ja], c1a, c1b);
-                } else {
-                    st_pair(&S.c1[il][ja], c1a, c1b, if_row && ja < w, if_row && ja + 1 < w);
-                }
+                if (!if_row) lds_st2(&S.c1[il][ja], c1a, c1b);
+                else if (FR == 2) st_pair(&S.c1[il][ja], c1a, c1b, ja < w, ja + 1 < w);  // outside the tile
                 // the interface columns: column 0 (left), column w < 128 (right, with masks); rows below h
                 const float c2a = fista_cprime(A.e2a[r], ja > 0 ? fla : 0.0f, fva, itau, invL);
                 const float c2b = fista_cprime(A.e2b[r], fva, fvb, itau, invL);
@@ -295,7 +298,8 @@ __device__ __forceinline__ void persist_tile(const PersistArgs &a, PersistLds &L
                     if (ja == 0 && left_if) S.c2[il][1] = c2b;
                     else lds_st2(&S.c2[il][ja], c2a, c2b);
                 } else {
-                    st_pair(&S.c2[il][ja], c2a, c2b, if_a, if_b);
+                    if (!(if_a || if_b)) lds_st2(&S.c2[il][ja], c2a, c2b);
+                    else st_pair(&S.c2[il][ja], c2a, c2b, if_a, if_b);
                 }
                 // the frame's bottom edges and right column: the tile's boundary edges on the image
                 // boundary, or (framed) outside the tile

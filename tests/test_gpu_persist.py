@@ -151,6 +151,26 @@ def test_persistent_config2():
         assert torch.equal(sp[k], sf[k]), k
 
 
+def test_persistent_floor_cuts_full_size():
+    """2000 x 2000 cut into 16 x 16 equal subdomains of 125 x 125 (every one framed, with
+    interfaces on its short sides), 500 outer x 5 FISTA: the persistent launch equals the fused
+    and streaming schedules bitwise."""
+    from paper_1901_00682_amd import dtvdd
+    H = W = 2000
+    rc = cc = synth.floor_cuts(H, 16)
+    f = _image(H, W, 2000)
+    im = dtvdd.Image(H, W, rc, cc, 8.0)
+    _say("[persist] 2000x2000 16x16 floor cuts, persistent vs fused vs stream")
+    res = {}
+    for sch in ("persistent", "fused", "stream"):
+        plan, st, _ = _solve([im], [f], sch, 500, 5)
+        assert plan.schedule() == sch
+        res[sch] = st
+    for sch in ("fused", "stream"):
+        for k in ("u", "p1", "p2", "lam"):
+            assert torch.equal(res["persistent"][k], res[sch][k]), (sch, k)
+
+
 def test_persistent_rejected_when_not_applicable():
     from paper_1901_00682_amd import dtvdd
     with pytest.raises(dtvdd.DtvError):  # a subdomain wider than 128
