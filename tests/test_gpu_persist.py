@@ -123,6 +123,22 @@ def test_persistent_groups_of_images():
         assert torch.equal(sp[k], sf[k]), k
 
 
+def test_persistent_groups_of_images_masked_frames():
+    """Three images cut into 9 x 10 equal subdomains (122 x 120 and 123 x 120: framed, with
+    interfaces on their short sides), 270 subdomains in groups of launches: the persistent
+    schedule equals the fused one bitwise."""
+    from paper_1901_00682_amd import dtvdd
+    H, W = 1100, 1200
+    imgs = [dtvdd.Image(H, W, synth.floor_cuts(H, 9), synth.floor_cuts(W, 10), 4.0 + 2 * k) for k in range(3)]
+    fs = [_image(H, W, 80 + k) for k in range(3)]
+    _say("[persist] three images, 270 masked framed subdomains, groups of launches")
+    pp, sp, _ = _solve(imgs, fs, "persistent", 4, 5)
+    assert pp.schedule() == "persistent"
+    pf, sf, _ = _solve(imgs, fs, "fused", 4, 5)
+    for k in ("u", "p1", "p2", "lam"):
+        assert torch.equal(sp[k], sf[k]), k
+
+
 def test_persistent_resume_bitwise():
     """3 + 4 outer steps through the returned state equal 7 in one launch."""
     from paper_1901_00682_amd import dtvdd
