@@ -286,7 +286,7 @@ __global__ __launch_bounds__(1024) void k_fused_bwd(FusedBwdArgs a)
 
     // ---- outputs: pbar^n = xbar_0 + phatbar, phatbar = S / (L tau) (0 on the image boundary),
     // fbar += -div S / L, and the alpha derivative
-    const double dA = im.dA, dB = im.dB;
+    const double dA = im.dA;
     double acc = acc_q;
     const float *lam = a.lam + im.lam;
     double sp = 0.0, fs = 0.0;  // <phat, S>, <f, div S>
