@@ -92,8 +92,8 @@ extern "C" {
                                 fixed rule picks: persistent, else fused, else streaming */
 #define DTV_SCHED_STREAM 1   /* one launch per inner step over all subdomains */
 #define DTV_SCHED_FUSED 2    /* one workgroup per subdomain runs all inner steps on chip
-                                (FISTA: subdomains up to 128 x 128; CP2: every subdomain
-                                exactly 128 x 128) */
+                                (FISTA: subdomains up to 128 x 128; CP2: 128 x 128, or smaller
+                                with the short sides on the image boundary) */
 #define DTV_SCHED_PERSIST 3  /* one cooperative launch runs every outer step; the iterates stay
                                 on chip between outer steps (no diagnostics, no
                                 save_for_backward).  FISTA with a fixed inner count: every

@@ -402,8 +402,9 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
         pl->fused_ok = p.n_inner <= kMaxFusedInner || pl->adaptive;
         for (const SubTile &st : pl->h_subs)
             if (st.h > kFusedMax || st.w > kFusedMax) pl->fused_ok = false;
-    } else {  // the fused primal-dual kernel takes full 128 x 128 subdomains only
-        pl->fused_ok = p.n_inner <= kMaxFusedInner && !pl->h_subs.empty() && pl->n_full == (int)pl->h_subs.size();
+    } else {  // the fused primal-dual kernel takes 128 x 128 subdomains and framed ones
+        pl->fused_ok = p.n_inner <= kMaxFusedInner && !pl->h_subs.empty() &&
+                       pl->n_full + pl->n_framed == (int)pl->h_subs.size();
     }
     if (pl->adaptive && !pl->fused_ok) {
         delete pl;
@@ -412,7 +413,7 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
     if (p.schedule == DTV_SCHED_FUSED && !pl->fused_ok) {
         delete pl;
         return fail(DTV_EINVAL, "the fused schedule needs n_inner <= 64 and subdomains of at most 128 x 128 (FISTA) "
-                                "or of exactly 128 x 128 (CP2)");
+                                "or of 128 x 128, smaller only with their short sides on the image boundary (CP2)");
     }
     {
         // persistent: full subdomains (fixed-count FISTA: any of at most 128 x 128), no per-step host
@@ -869,6 +870,7 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
             ca.out1 = bufs[out].p1;
             ca.out2 = bufs[out].p2;
             ca.lam_out = lam_other();
+            ca.frames = pl->n_full < (int)pl->h_subs.size();
             int rc = with_host ? tm.begin() : DTV_OK;
             if (rc != DTV_OK) return rc;
             HIP_TRY(launch_fused_cp2(ca, (int)pl->h_subs.size(), q, with_host ? tm.e0 : nullptr,

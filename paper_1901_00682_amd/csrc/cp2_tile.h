@@ -73,13 +73,23 @@ struct Cp2Ctx {
     bool last, bot_bnd, right_bnd;
     float lo1, hi1, lo2a, hi2a;  // clamp bounds of the first row's top edges and of column a's left edge
     float alpha, cv1, cv2;
+    // framed tiles only (smaller than 128 x 128, short sides on the image boundary, run in a
+    // 128 x 128 frame): clamp bounds of column b's left edge, and the strip's rows whose top edges
+    // are the tile's bottom boundary (bit r: row 8 s + r)
+    float lo2b, hi2b;
+    unsigned zrows;
 };
 
 // The n_inner steps of one outer step from x_0 (X, and the right boundary
 // column in S.rx) and u_0, with the anchors in S.a1, a2, ab, ar (written by
 // every thread before the call; the first barrier here orders them).  On
 // return X, S.rx and (ua, ub) hold x_K and u_K.
-template <int FID>
+// FR: a framed tile, its h x w pixels at the top left of the frame and its short sides on the
+// image boundary.  Outside the tile x, u, f and the anchors start at 0; the top edges of row h and
+// the left edges of column w are clamped to 0 like other image-boundary edges, so no value
+// outside reaches the tile's edges and pixels (the pixels outside may move, bounded, under the
+// Chan-Vese prox, which is not zero at f = 0).
+template <int FID, bool FR = false>
 __device__ __forceinline__ void solve(const Cp2Ctx &c, Cp2Lds &S, Slot &X, float (&ua)[kR], float (&ub)[kR],
                                       const float (&fa)[kR], const float (&fb)[kR], unsigned obs,
                                       const FusedCp2Args &a)
@@ -153,11 +163,17 @@ __device__ __forceinline__ void solve(const Cp2Ctx &c, Cp2Lds &S, Slot &X, float
             lds_ld2(&S.a1[il][ja], A1a, A1b);
             lds_ld2(&S.a2[il][ja], A2a, A2b);
             const float o1a = X.e1a[r], o1b = X.e1b[r], o2a = X.e2a[r], o2b = X.e2b[r];
-            const float l1 = r == 0 ? lo1 : -1.0f, h1 = r == 0 ? hi1 : 1.0f;
+            float l1 = r == 0 ? lo1 : -1.0f, h1 = r == 0 ? hi1 : 1.0f;
+            if constexpr (FR) {
+                const bool zr = ((c.zrows >> r) & 1u) != 0;
+                l1 = zr ? 0.0f : l1;
+                h1 = zr ? 0.0f : h1;
+            }
             const float n1a = __builtin_amdgcn_fmed3f(cp2_pre(o1a, uua - ura, A1a, tk, ck, ca), l1, h1);
             const float n1b = __builtin_amdgcn_fmed3f(cp2_pre(o1b, uub - urb, A1b, tk, ck, ca), l1, h1);
             const float n2a = __builtin_amdgcn_fmed3f(cp2_pre(o2a, ul - ura, A2a, tk, ck, ca), lo2a, hi2a);
-            const float n2b = clamp1(cp2_pre(o2b, ura - urb, A2b, tk, ck, ca));
+            const float n2b = FR ? __builtin_amdgcn_fmed3f(cp2_pre(o2b, ura - urb, A2b, tk, ck, ca), c.lo2b, c.hi2b)
+                                 : clamp1(cp2_pre(o2b, ura - urb, A2b, tk, ck, ca));
             X.e1a[r] = n1a;
             X.e1b[r] = n1b;
             X.e2a[r] = n2a;

@@ -136,7 +136,7 @@ struct FusedArgs {
 // c_anchor = ca[k] of the dual update.
 struct FusedCp2Args {
     const ImgDev *imgs;
-    const SubTile *subs;       // the (full) subdomains
+    const SubTile *subs;       // the subdomains (full, or framed in the fused kernel)
     float *p1, *p2;            // p~^n in (the persistent kernel: also p~^(n+1) out, in place)
     float *out1, *out2;        // fused kernel: p~^(n+1) out (not p1, p2: the tiles read each other's copies)
     const float *lam;          // fused kernel: lambda state before the multiplier update;
@@ -150,6 +150,8 @@ struct FusedCp2Args {
     int fidelity;              // 0 L2, 1 L1, 2 convex Chan-Vese
     float cv_c1, cv_c2;
     int n_inner;
+    int frames;                // fused kernel: some subdomains are framed (smaller than 128 x 128,
+                               // their short sides on the image boundary)
     float tk[kMaxFusedInner], sk[kMaxFusedInner], th[kMaxFusedInner], ck[kMaxFusedInner], ca[kMaxFusedInner];
 };
 

@@ -1,8 +1,9 @@
 // Fused schedule of the local accelerated primal-dual solves (Lee & Park,
 // arXiv 1901.00682, Sec. 5: Chambolle-Pock Alg. 2 on the local saddle problem
-// eq. (local), any fidelity of Sec. 3) on full 128 x 128 subdomains: one
-// 1024-thread workgroup owns one subdomain and runs all n_inner steps of an
-// outer iteration on chip.
+// eq. (local), any fidelity of Sec. 3) on 128 x 128 subdomains, or smaller
+// ones whose short sides lie on the image boundary (framed: run in a 128 x 128
+// frame): one 1024-thread workgroup owns one subdomain and runs all n_inner
+// steps of an outer iteration on chip.
 // The on-chip layout and the step are those of cp2_tile.h; this kernel loads
 // the tile, updates the multipliers of its interfaces (Algorithm 1, first
 // line), forms the anchors from p~^n and lambda^(n+1), solves and stores
@@ -15,8 +16,10 @@ namespace dtv {
 using namespace fused;
 using namespace cp2tile;
 
-// FID: the fidelity (0 L2, 1 L1, 2 convex Chan-Vese); MASK: an inpainting mask is given
-template <int FID, bool MASK>
+// FID: the fidelity (0 L2, 1 L1, 2 convex Chan-Vese); MASK: an inpainting mask is given;
+// FR: some subdomains are framed tiles (every tile then takes the framed path, which on a
+// 128 x 128 tile does what the full-tile path does)
+template <int FID, bool MASK, bool FR>
 __global__ __launch_bounds__(1024) void k_fused_cp2(FusedCp2Args a)
 {
     __shared__ Cp2Lds S;
@@ -29,8 +32,9 @@ __global__ __launch_bounds__(1024) void k_fused_cp2(FusedCp2Args a)
     const int ja = 2 * lane, jb = ja + 1;
     const int il0 = kR * s;
     const int H = im.H, W = im.W;
-    const bool top_bnd = tl.ra == 0, bot_bnd = tl.ra + kFusedMax == H;
-    const bool left_bnd = tl.ca == 0, right_bnd = tl.ca + kFusedMax == W;
+    const int h = FR ? tl.h : kFusedMax, w = FR ? tl.w : kFusedMax;
+    const bool top_bnd = tl.ra == 0, bot_bnd = tl.ra + h == H;
+    const bool left_bnd = tl.ca == 0, right_bnd = tl.ca + w == W;
     const bool last = s == kWaves - 1;
     const long long P1 = im.pitch1, P2 = im.pitch2;
     const long long row1 = (long long)tl.ra + tl.r;  // P1 row of the tile's edge row 0
@@ -53,28 +57,46 @@ __global__ __launch_bounds__(1024) void k_fused_cp2(FusedCp2Args a)
     float xr[kR];  // lane 63: the right boundary edges of the strip's rows
     unsigned obs = 0xFFFFu;  // observed pixels: bit 2r (column a), 2r + 1 (column b) of row r
 
-    // ---- load p~^n, u, f (every load first, then the conditional ones)
+    // ---- load p~^n, u, f (every load first, then the conditional ones).  A framed tile loads its
+    // own h x w pixels and edges; the rest of the frame starts at 0 (the zeros are written in every
+    // lane before the loads, so that no load waits for another lane's load into the same register)
 #pragma unroll
     for (int r = 0; r < kR; ++r) {
         const int il = il0 + r;
-        ld2g(p1_tile + (long long)il * P1 + ja, X.e1a[r], X.e1b[r]);
-        ld2g(p2_tile + (long long)il * P2 + ja, X.e2a[r], X.e2b[r]);
-        ld2g(f_tile + (long long)il * W + ja, fa[r], fb[r]);
-        ld2g(u_tile + (long long)il * W + ja, ua[r], ub[r]);
         xr[r] = 0.0f;
+        if constexpr (FR) {
+            X.e1a[r] = X.e1b[r] = X.e2a[r] = X.e2b[r] = 0.0f;
+            fa[r] = fb[r] = ua[r] = ub[r] = 0.0f;
+            pin4(X.e1a[r], X.e1b[r], X.e2a[r], X.e2b[r]);
+            pin4(fa[r], fb[r], ua[r], ub[r]);
+        }
+        if (!FR || (il < h && ja + 1 < w)) {
+            ld2g(p1_tile + (long long)il * P1 + ja, X.e1a[r], X.e1b[r]);
+            ld2g(p2_tile + (long long)il * P2 + ja, X.e2a[r], X.e2b[r]);
+            ld2g(f_tile + (long long)il * W + ja, fa[r], fb[r]);
+            ld2g(u_tile + (long long)il * W + ja, ua[r], ub[r]);
+        } else if (il < h && ja < w) {  // framed: the tile's last column alone
+            X.e1a[r] = p1_tile[(long long)il * P1 + ja];
+            X.e2a[r] = p2_tile[(long long)il * P2 + ja];
+            fa[r] = f_tile[(long long)il * W + ja];
+            ua[r] = u_tile[(long long)il * W + ja];
+        }
     }
     X.ba = X.bb = 0.0f;
-    if (last) ld2g(p1_tile + (long long)kFusedMax * P1 + ja, X.ba, X.bb);
-    if (lane == 63)
+    if (last && (!FR || (h == kFusedMax && ja + 1 < w))) ld2g(p1_tile + (long long)kFusedMax * P1 + ja, X.ba, X.bb);
+    else if (FR && last && h == kFusedMax && ja < w) X.ba = p1_tile[(long long)kFusedMax * P1 + ja];
+    if (lane == 63 && (!FR || w == kFusedMax))
 #pragma unroll
-        for (int r = 0; r < kR; ++r) xr[r] = p2_tile[(long long)(il0 + r) * P2 + kFusedMax];
+        for (int r = 0; r < kR; ++r)
+            if (!FR || il0 + r < h) xr[r] = p2_tile[(long long)(il0 + r) * P2 + kFusedMax];
     if constexpr (MASK) {
-        obs = 0;
+        obs = 0;  // (a framed tile: the pixels outside it are unobserved)
 #pragma unroll
         for (int r = 0; r < kR; ++r) {
+            if (FR && il0 + r >= h) continue;
             const uint8_t *mr = m_tile + (long long)(il0 + r) * W + ja;
-            obs |= (mr[0] != 0 ? 1u : 0u) << (2 * r);
-            obs |= (mr[1] != 0 ? 1u : 0u) << (2 * r + 1);
+            if (!FR || ja < w) obs |= (mr[0] != 0 ? 1u : 0u) << (2 * r);
+            if (!FR || ja + 1 < w) obs |= (mr[1] != 0 ? 1u : 0u) << (2 * r + 1);
         }
     }
 
@@ -87,7 +109,7 @@ __global__ __launch_bounds__(1024) void k_fused_cp2(FusedCp2Args a)
         const int side = s >> 1, si = (s & 1) * 64 + lane;
         bool has = false;
         long long e = 0, ips = 0, ipt = 0;  // lambda index; P1 or P2 offsets of the s and t copies
-        if (s < 2 * 4) {
+        if (s < 2 * 4 && (!FR || si < (side < 2 ? w : h))) {
             const long long rs = (long long)(tl.ra + si) * P2;  // P2 row of a left / right edge
             switch (side) {
             case 0:  // top: the tile above holds the s copy
@@ -141,18 +163,18 @@ __global__ __launch_bounds__(1024) void k_fused_cp2(FusedCp2Args a)
         const int il = il0 + r;
         float a1a = X.e1a[r], a1b = X.e1b[r], a2a = X.e2a[r];
         if (il == 0 && tl.r > 0) {
-            a1a = fmaf(tau, LS[0][ja], a1a);
-            a1b = fmaf(tau, LS[0][jb], a1b);
+            if (!FR || ja < w) a1a = fmaf(tau, LS[0][ja], a1a);
+            if (!FR || jb < w) a1b = fmaf(tau, LS[0][jb], a1b);
         }
-        if (ja == 0 && tl.c > 0) a2a = fmaf(tau, LS[2][il], a2a);
+        if (ja == 0 && tl.c > 0 && (!FR || il < h)) a2a = fmaf(tau, LS[2][il], a2a);
         lds_st2(&S.a1[il][ja], a1a, a1b);
         lds_st2(&S.a2[il][ja], a2a, X.e2b[r]);
     }
     if (last) {
         float aba = X.ba, abb = X.bb;
-        if (!bot_bnd) {
-            aba = fmaf(-tau, LS[1][ja], aba);
-            abb = fmaf(-tau, LS[1][jb], abb);
+        if (!bot_bnd) {  // (lambda exists on the tile's own columns only)
+            if (!FR || ja < w) aba = fmaf(-tau, LS[1][ja], aba);
+            if (!FR || jb < w) abb = fmaf(-tau, LS[1][jb], abb);
         }
         S.ab[ja] = aba;
         S.ab[jb] = abb;
@@ -163,7 +185,7 @@ __global__ __launch_bounds__(1024) void k_fused_cp2(FusedCp2Args a)
             const int il = il0 + r;
             S.rx[il] = xr[r];
             float ar = xr[r];
-            if (!right_bnd) ar = fmaf(-tau, LS[3][il], ar);
+            if (!right_bnd && (!FR || il < h)) ar = fmaf(-tau, LS[3][il], ar);
             S.ar[il] = ar;
         }
     // ---- (a3) the local solve
@@ -183,18 +205,42 @@ __global__ __launch_bounds__(1024) void k_fused_cp2(FusedCp2Args a)
     cx.alpha = alpha;
     cx.cv1 = cv1;
     cx.cv2 = cv2;
-    solve<FID>(cx, S, X, ua, ub, fa, fb, obs, a);
+    cx.lo2b = -1.0f;
+    cx.hi2b = 1.0f;
+    cx.zrows = 0u;
+    if constexpr (FR) {
+        // the boundary lines of a framed tile (the left edges of column w, the top edges of row h);
+        // the frame's bottom row and right column lie outside a tile shorter or narrower than it
+        const bool za = w < kFusedMax && ja == w, zb = w < kFusedMax && jb == w;
+        cx.lo2a = za ? 0.0f : cx.lo2a;
+        cx.hi2a = za ? 0.0f : cx.hi2a;
+        cx.lo2b = zb ? 0.0f : -1.0f;
+        cx.hi2b = zb ? 0.0f : 1.0f;
+        const int zr = h - il0;
+        cx.zrows = (h < kFusedMax && zr >= 0 && zr < kR) ? 1u << zr : 0u;
+        cx.bot_bnd = bot_bnd || h < kFusedMax;
+        cx.right_bnd = right_bnd || w < kFusedMax;
+    }
+    solve<FID, FR>(cx, S, X, ua, ub, fa, fb, obs, a);
 
     // ---- store x_K as p~^(n+1) and u_K
 #pragma unroll
     for (int r = 0; r < kR; ++r) {
         const int il = il0 + r;
-        st2g(q1_tile + (long long)il * P1 + ja, X.e1a[r], X.e1b[r]);
-        st2g(q2_tile + (long long)il * P2 + ja, X.e2a[r], X.e2b[r]);
-        st2g(u_tile + (long long)il * W + ja, ua[r], ub[r]);
-        if (lane == 63) q2_tile[(long long)il * P2 + kFusedMax] = S.rx[il];
+        if (!FR || (il < h && ja + 1 < w)) {
+            st2g(q1_tile + (long long)il * P1 + ja, X.e1a[r], X.e1b[r]);
+            st2g(q2_tile + (long long)il * P2 + ja, X.e2a[r], X.e2b[r]);
+            st2g(u_tile + (long long)il * W + ja, ua[r], ub[r]);
+        } else if (il < h && ja < w) {  // framed: the tile's last column alone
+            q1_tile[(long long)il * P1 + ja] = X.e1a[r];
+            q2_tile[(long long)il * P2 + ja] = X.e2a[r];
+            u_tile[(long long)il * W + ja] = ua[r];
+        }
+        // the frame's right column and bottom row: a framed tile's own only when it spans the frame
+        if (lane == 63 && (!FR || (w == kFusedMax && il < h))) q2_tile[(long long)il * P2 + kFusedMax] = S.rx[il];
     }
-    if (last) st2g(q1_tile + (long long)kFusedMax * P1 + ja, X.ba, X.bb);
+    if (last && (!FR || (h == kFusedMax && ja + 1 < w))) st2g(q1_tile + (long long)kFusedMax * P1 + ja, X.ba, X.bb);
+    else if (FR && last && h == kFusedMax && ja < w) q1_tile[(long long)kFusedMax * P1 + ja] = X.ba;
 }
 
 namespace {
@@ -202,10 +248,11 @@ namespace {
 template <int FID, bool MASK>
 hipError_t launch_cp2_variant(const FusedCp2Args &a, int nsub, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
+    auto k = a.frames ? k_fused_cp2<FID, MASK, true> : k_fused_cp2<FID, MASK, false>;
     if (e0)
-        hipExtLaunchKernelGGL((k_fused_cp2<FID, MASK>), dim3(nsub), dim3(1024), 0, s, e0, e1, 0, a);
+        hipExtLaunchKernelGGL(k, dim3(nsub), dim3(1024), 0, s, e0, e1, 0, a);
     else
-        hipLaunchKernelGGL((k_fused_cp2<FID, MASK>), dim3(nsub), dim3(1024), 0, s, a);
+        hipLaunchKernelGGL(k, dim3(nsub), dim3(1024), 0, s, a);
     return hipGetLastError();
 }
 

@@ -33,6 +33,10 @@ GEOMS = {
     "full3x3": (384, 384, [0, 128, 256, 384], [0, 128, 256, 384]),
     "full2x4": (256, 512, [0, 128, 256], [0, 128, 256, 384, 512]),
     "full1x1": (128, 128, [0, 128], [0, 128]),
+    # framed tiles: the last subdomain row (43 rows) and column (45 columns) end on the image boundary
+    "framed3x3": (299, 301, [0, 128, 256, 299], [0, 128, 256, 301]),
+    # one framed tile alone (smaller than 128 x 128 on all sides)
+    "framed1x1": (77, 100, [0, 77], [0, 100]),
 }
 FID = {
     # name: fidelity, masked, alpha, extra parameters
@@ -68,7 +72,9 @@ def run_gpu(f32, alpha, rc, cc, mask=None, state=None, **kw):
 
 
 CASES = [("full3x3", "l2", 5), ("full3x3", "l1_mask", 3), ("full3x3", "cv", 5), ("full3x3", "l2_mask", 2),
-         ("full2x4", "cv", 1), ("full2x4", "l1_mask", 4), ("full1x1", "l2", 6), ("full1x1", "cv", 3)]
+         ("full2x4", "cv", 1), ("full2x4", "l1_mask", 4), ("full1x1", "l2", 6), ("full1x1", "cv", 3),
+         ("framed3x3", "l2", 5), ("framed3x3", "l1_mask", 3), ("framed3x3", "cv", 4), ("framed3x3", "l2_mask", 2),
+         ("framed1x1", "cv", 5), ("framed1x1", "l1_mask", 2)]
 
 
 @pytest.mark.parametrize("geom,fid,K", CASES)
