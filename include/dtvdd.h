@@ -99,9 +99,11 @@ extern "C" {
                                 save_for_backward).  FISTA with a fixed inner count: every
                                 subdomain at most 128 x 128 (smaller ones run in a 128 x 128
                                 frame); each image's subdomains resident on the device at
-                                once, the images run in groups of launches.  CP2 or
-                                inner_tol: every subdomain exactly 128 x 128, all of them
-                                resident at once (one launch) */
+                                once, the images run in groups of launches.  CP2: every
+                                subdomain 128 x 128, or smaller with its short sides on the
+                                image boundary; inner_tol: every subdomain exactly 128 x 128.
+                                These two run every subdomain in one launch, all resident at
+                                once */
 
 typedef struct dtv_dd_plan dtv_dd_plan; /* opaque, owned by the library */
 

@@ -416,15 +416,16 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
                                 "or of 128 x 128, smaller only with their short sides on the image boundary (CP2)");
     }
     {
-        // persistent: full subdomains (fixed-count FISTA: any of at most 128 x 128), no per-step host
-        // work; the primal-dual kernel and adaptive stopping take every subdomain in one launch,
+        // persistent: full subdomains (fixed-count FISTA: any of at most 128 x 128; the primal-dual
+        // kernel: also framed ones), no per-step host work; the primal-dual kernel and adaptive
+        // stopping take every subdomain in one launch,
         // fixed-count FISTA runs the images in groups of launches, each group resident on the
         // device at once
         const int nsub = (int)pl->h_subs.size();
         const bool fista = p.inner == DTV_INNER_FISTA;
         const bool one_launch = !fista || pl->adaptive;
         pl->persist_ok = pl->fused_ok && nsub > 0 && p.diag_every == 0 && !p.save_for_backward &&
-                         (pl->n_full == nsub || !one_launch);
+                         (pl->n_full == nsub || !one_launch || (!fista && pl->n_full + pl->n_framed == nsub));
         int dev = 0;
         if (pl->persist_ok && hipGetDevice(&dev) == hipSuccess && persist_supported(dev)) {
             const int cap = fista ? persist_capacity(dev) : persist_cp2_capacity(dev);
@@ -990,6 +991,7 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
             pc.n_outer = count;
             pc.sigma = (float)P.sigma;
             pc.spin_limit = spin_limit;
+            pc.ca.frames = pl->n_full < (int)pl->h_subs.size();
             HIP_TRY(launch_persist_cp2(pc, (int)pl->h_subs.size(), s), "persistent primal-dual");
         } else {
             PersistArgs pa{};

@@ -40,7 +40,9 @@ struct PersistCp2Lds {
 }  // namespace
 
 // FID: the fidelity (0 L2, 1 L1, 2 convex Chan-Vese); MASK: an inpainting mask is given
-template <int FID, bool MASK>
+// FR: some subdomains are framed tiles (smaller than 128 x 128, their short sides on the image
+// boundary, run in a 128 x 128 frame as in the fused kernel); every tile then takes that path
+template <int FID, bool MASK, bool FR = false>
 __global__ __launch_bounds__(1024) void k_persist_cp2(PersistCp2Args pa)
 {
     __shared__ PersistCp2Lds L;
@@ -54,8 +56,9 @@ __global__ __launch_bounds__(1024) void k_persist_cp2(PersistCp2Args pa)
     const int ja = 2 * lane, jb = ja + 1;
     const int il0 = kR * s;
     const int H = im.H, W = im.W;
-    const bool top_bnd = tl.ra == 0, bot_bnd = tl.ra + kFusedMax == H;
-    const bool left_bnd = tl.ca == 0, right_bnd = tl.ca + kFusedMax == W;
+    const int h = FR ? tl.h : kFusedMax, w = FR ? tl.w : kFusedMax;
+    const bool top_bnd = tl.ra == 0, bot_bnd = tl.ra + h == H;
+    const bool left_bnd = tl.ca == 0, right_bnd = tl.ca + w == W;
     const bool last = s == kWaves - 1;
     const long long P1 = im.pitch1, P2 = im.pitch2;
     const long long row1 = (long long)tl.ra + tl.r;  // P1 row of the tile's edge row 0
@@ -84,11 +87,28 @@ __global__ __launch_bounds__(1024) void k_persist_cp2(PersistCp2Args pa)
     cx.alpha = im.alpha;
     cx.cv1 = a.cv_c1;
     cx.cv2 = a.cv_c2;
+    cx.lo2b = -1.0f;
+    cx.hi2b = 1.0f;
+    cx.zrows = 0u;
+    if constexpr (FR) {
+        // the boundary lines of a framed tile (the left edges of column w, the top edges of row h);
+        // the frame's bottom row and right column lie outside a tile shorter or narrower than it
+        const bool za = w < kFusedMax && ja == w, zb = w < kFusedMax && jb == w;
+        cx.lo2a = za ? 0.0f : cx.lo2a;
+        cx.hi2a = za ? 0.0f : cx.hi2a;
+        cx.lo2b = zb ? 0.0f : -1.0f;
+        cx.hi2b = zb ? 0.0f : 1.0f;
+        const int zr = h - il0;
+        cx.zrows = (h < kFusedMax && zr >= 0 && zr < kR) ? 1u << zr : 0u;
+        cx.bot_bnd = bot_bnd || h < kFusedMax;
+        cx.right_bnd = right_bnd || w < kFusedMax;
+    }
 
     // side work (multiplier update): waves 0..7, side = wave / 2 (wave-uniform), edge
     // si = 64 (wave % 2) + lane; the lambda index is side_base + si
     const int side = s >> 1;
-    const bool side_wave = s < 2 * kSides && side_exists(im, tl, side);
+    const bool side_wave = s < 2 * kSides && side_exists(im, tl, side) &&
+                           (!FR || (s & 1) * 64 + lane < (side < 2 ? w : h));  // (a framed tile's sides are shorter)
     const bool side_s = side == 1 || side == 3;  // s copies: bottom and right sides
     const long long side_base = side_wave ? side_edge(im, tl, side, 0) : 0;
 
@@ -96,26 +116,57 @@ __global__ __launch_bounds__(1024) void k_persist_cp2(PersistCp2Args pa)
     Slot X;
     float ua[kR], ub[kR], fa[kR], fb[kR];
     unsigned obs = 0xFFFFu;  // observed pixels: bit 2r (column a), 2r + 1 (column b) of row r
+    // (a framed tile: its own h x w pixels and edges; the rest of the frame starts at 0, the zeros
+    // written in every lane before the loads)
 #pragma unroll
     for (int r = 0; r < kR; ++r) {
         const int il = il0 + r;
-        ld2g(p1_tile + (long long)il * P1 + ja, X.e1a[r], X.e1b[r]);
-        ld2g(p2_tile + (long long)il * P2 + ja, X.e2a[r], X.e2b[r]);
-        ld2g(f_tile + (long long)il * W + ja, fa[r], fb[r]);
-        ld2g(u_tile + (long long)il * W + ja, ua[r], ub[r]);
+        if constexpr (FR) {
+            X.e1a[r] = X.e1b[r] = X.e2a[r] = X.e2b[r] = 0.0f;
+            fa[r] = fb[r] = ua[r] = ub[r] = 0.0f;
+            pin4(X.e1a[r], X.e1b[r], X.e2a[r], X.e2b[r]);
+            pin4(fa[r], fb[r], ua[r], ub[r]);
+        }
+        if (!FR || (il < h && ja + 1 < w)) {
+            ld2g(p1_tile + (long long)il * P1 + ja, X.e1a[r], X.e1b[r]);
+            ld2g(p2_tile + (long long)il * P2 + ja, X.e2a[r], X.e2b[r]);
+            ld2g(f_tile + (long long)il * W + ja, fa[r], fb[r]);
+            ld2g(u_tile + (long long)il * W + ja, ua[r], ub[r]);
+        } else if (il < h && ja < w) {  // framed: the tile's last column alone
+            X.e1a[r] = p1_tile[(long long)il * P1 + ja];
+            X.e2a[r] = p2_tile[(long long)il * P2 + ja];
+            fa[r] = f_tile[(long long)il * W + ja];
+            ua[r] = u_tile[(long long)il * W + ja];
+        }
     }
     X.ba = X.bb = 0.0f;
-    if (last) ld2g(p1_tile + (long long)kFusedMax * P1 + ja, X.ba, X.bb);
-    if (lane < kR) S.rx[il0 + lane] = p2_tile[(long long)(il0 + lane) * P2 + kFusedMax];
+    if (last && (!FR || (h == kFusedMax && ja + 1 < w))) ld2g(p1_tile + (long long)kFusedMax * P1 + ja, X.ba, X.bb);
+    else if (FR && last && h == kFusedMax && ja < w) X.ba = p1_tile[(long long)kFusedMax * P1 + ja];
+    if (lane < kR)
+        S.rx[il0 + lane] = (!FR || (w == kFusedMax && il0 + lane < h))
+                               ? p2_tile[(long long)(il0 + lane) * P2 + kFusedMax] : 0.0f;
     if constexpr (MASK) {
         const uint8_t *m_tile = a.mask + px0;
-        obs = 0;
+        obs = 0;  // (a framed tile: the pixels outside it are unobserved)
 #pragma unroll
         for (int r = 0; r < kR; ++r) {
+            if (FR && il0 + r >= h) continue;
             const uint8_t *mr = m_tile + (long long)(il0 + r) * W + ja;
-            obs |= (mr[0] != 0 ? 1u : 0u) << (2 * r);
-            obs |= (mr[1] != 0 ? 1u : 0u) << (2 * r + 1);
+            if (!FR || ja < w) obs |= (mr[0] != 0 ? 1u : 0u) << (2 * r);
+            if (!FR || ja + 1 < w) obs |= (mr[1] != 0 ? 1u : 0u) << (2 * r + 1);
         }
+    }
+    if constexpr (FR) {
+        // anchors that the loop below never writes on a framed tile: the frame's first row and
+        // column and its bottom row and right column outside the tile (the loop skips the rows
+        // and columns that hold interface copies; (4) writes the tile's own entries); ordered
+        // before the loop's reads by its barriers
+        if (s == 0) lds_st2(&S.a1[0][ja], 0.0f, 0.0f);
+        if (last) lds_st2(&S.ab[ja], 0.0f, 0.0f);
+        if (lane == 0)
+#pragma unroll
+            for (int r = 0; r < kR; ++r) S.a2[il0 + r][0] = 0.0f;
+        if (lane < kR) S.ar[il0 + lane] = 0.0f;
     }
     if (side_wave) {
         const int si = (s & 1) * 64 + lane;
@@ -187,7 +238,7 @@ __global__ __launch_bounds__(1024) void k_persist_cp2(PersistCp2Args pa)
         if (!ok) break;  // a neighbour stopped publishing: leave (the host reports the error)
 
         // ---- (5) the local primal-dual solve
-        solve<FID>(cx, S, X, ua, ub, fa, fb, obs, a);
+        solve<FID, FR>(cx, S, X, ua, ub, fa, fb, obs, a);
     }
 
     // ---- store p~^N, u and the lambda state (lambda^N and the copies of the last multiplier update)
@@ -195,12 +246,21 @@ __global__ __launch_bounds__(1024) void k_persist_cp2(PersistCp2Args pa)
 #pragma unroll
     for (int r = 0; r < kR; ++r) {
         const int il = il0 + r;
-        st2g(p1_tile + (long long)il * P1 + ja, X.e1a[r], X.e1b[r]);
-        st2g(p2_tile + (long long)il * P2 + ja, X.e2a[r], X.e2b[r]);
-        st2g(u_tile + (long long)il * W + ja, ua[r], ub[r]);
+        if (!FR || (il < h && ja + 1 < w)) {
+            st2g(p1_tile + (long long)il * P1 + ja, X.e1a[r], X.e1b[r]);
+            st2g(p2_tile + (long long)il * P2 + ja, X.e2a[r], X.e2b[r]);
+            st2g(u_tile + (long long)il * W + ja, ua[r], ub[r]);
+        } else if (il < h && ja < w) {  // framed: the tile's last column alone
+            p1_tile[(long long)il * P1 + ja] = X.e1a[r];
+            p2_tile[(long long)il * P2 + ja] = X.e2a[r];
+            u_tile[(long long)il * W + ja] = ua[r];
+        }
     }
-    if (last) st2g(p1_tile + (long long)kFusedMax * P1 + ja, X.ba, X.bb);
-    if (lane < kR) p2_tile[(long long)(il0 + lane) * P2 + kFusedMax] = S.rx[il0 + lane];
+    // the frame's bottom row and right column: a framed tile's own only when it spans the frame
+    if (last && (!FR || (h == kFusedMax && ja + 1 < w))) st2g(p1_tile + (long long)kFusedMax * P1 + ja, X.ba, X.bb);
+    else if (FR && last && h == kFusedMax && ja < w) p1_tile[(long long)kFusedMax * P1 + ja] = X.ba;
+    if (lane < kR && (!FR || (w == kFusedMax && il0 + lane < h)))
+        p2_tile[(long long)(il0 + lane) * P2 + kFusedMax] = S.rx[il0 + lane];
     if (side_wave && ok) {
         const int si = (s & 1) * 64 + lane;
         float *ls = pa.lam_out + im.lam + side_base;
@@ -217,14 +277,20 @@ namespace {
 
 using PersistCp2Kernel = void (*)(PersistCp2Args);
 
-PersistCp2Kernel persist_cp2_kernel(int fidelity, bool mask)
+template <bool FR>
+PersistCp2Kernel persist_cp2_variant(int fidelity, bool mask)
 {
     switch (fidelity) {
-    case 0: return mask ? k_persist_cp2<0, true> : k_persist_cp2<0, false>;
-    case 1: return mask ? k_persist_cp2<1, true> : k_persist_cp2<1, false>;
-    case 2: return mask ? nullptr : k_persist_cp2<2, false>;
+    case 0: return mask ? k_persist_cp2<0, true, FR> : k_persist_cp2<0, false, FR>;
+    case 1: return mask ? k_persist_cp2<1, true, FR> : k_persist_cp2<1, false, FR>;
+    case 2: return mask ? nullptr : k_persist_cp2<2, false, FR>;
     default: return nullptr;
     }
+}
+
+PersistCp2Kernel persist_cp2_kernel(int fidelity, bool mask, bool frames)
+{
+    return frames ? persist_cp2_variant<true>(fidelity, mask) : persist_cp2_variant<false>(fidelity, mask);
 }
 
 }  // namespace
@@ -242,7 +308,7 @@ hipError_t launch_persist_cp2(const PersistCp2Args &a, int nsub, hipStream_t s)
 {
     if (nsub <= 0 || a.n_outer <= 0) return hipSuccess;
     if (a.ca.n_inner < 1 || a.ca.n_inner > kMaxFusedInner) return hipErrorInvalidValue;
-    const PersistCp2Kernel k = persist_cp2_kernel(a.ca.fidelity, a.ca.mask != nullptr);
+    const PersistCp2Kernel k = persist_cp2_kernel(a.ca.fidelity, a.ca.mask != nullptr, a.ca.frames != 0);
     if (!k) return hipErrorInvalidValue;
     PersistCp2Args arg = a;
     void *args[] = {&arg};

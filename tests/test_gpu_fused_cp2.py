@@ -141,7 +141,8 @@ def test_fused_cp2_cv_full_size_with_diagnostics():
 
 
 PCASES = [("full3x3", "l2", 5, 6), ("full3x3", "l1_mask", 3, 5), ("full3x3", "cv", 5, 7), ("full2x4", "cv", 1, 4),
-          ("full2x4", "l2_mask", 4, 3), ("full1x1", "l1_mask", 2, 5)]
+          ("full2x4", "l2_mask", 4, 3), ("full1x1", "l1_mask", 2, 5), ("framed3x3", "cv", 5, 4),
+          ("framed3x3", "l1_mask", 3, 3), ("framed1x1", "l2", 4, 5), ("framed1x1", "cv", 2, 3)]
 
 
 @pytest.mark.parametrize("geom,fid,K,n_outer", PCASES)
