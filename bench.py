@@ -98,6 +98,12 @@ def workload(name: str):
         return synth.config3()
     if name == "cv2048":
         return synth.cv_case()
+    if name == "cv2000":  # cut at multiples of 128: the last subdomain row and column (80 wide) are framed
+        c = synth.cv_case(size=2000)
+        c.name = "cv2000_128cuts"
+        c.row_cuts = synth.tile_cuts(2000, 128)
+        c.col_cuts = synth.tile_cuts(2000, 128)
+        return c
     raise SystemExit(f"unknown workload {name}")
 
 
