@@ -17,7 +17,13 @@ copy) shows up as a disagreement.
     least-squares problem (solved by BVLS, certified by the KKT conditions),
     TV-L1 (with or without inpainting mask) and the convex Chan-Vese model
     eq. (CCV) as linear programs, and the binary Chan-Vese problem by
-    enumeration of every pixel set.
+    enumeration of every pixel set;
+  * the decomposed saddle problem (DD) of Sec. 4 on one global torn vector,
+    with matrices of the torn divergence and of B built from their
+    definitions, iterated by the textbook Chambolle-Pock method (their
+    Alg. 1) with every proximal step solved exactly by BVLS, so that sigma,
+    tau and the proximal weight 1/tau enter exactly as the textbook states
+    them.
 """
 from __future__ import annotations
 
@@ -261,3 +267,111 @@ def div_norm_sq(apply_div, apply_divT, n_in, iters=2000, seed=0):
         lam = float(np.linalg.norm(y))
         x = y / lam
     return lam
+
+
+# --- the decomposed saddle problem (DD) on one global torn vector -----------
+def torn_operators(H, W, row_cuts, col_cuts):
+    """Dense matrices of the torn divergence and of the jump operator B on one
+    global vector of torn edge dofs (Sec. 2.3-2.4), built here from their
+    definitions and not from the oracle.
+
+    The vector follows the oracle's documented export layout (subdomains
+    row-major; per subdomain p1 [(h+1) x w], edge above local row k, then
+    p2 [h x (w+1)], edge left of local column k), so results can be compared
+    entry by entry.  Returns (Div [H*W x n_p], Bm [n_lam x n_p], dof [n_p]):
+      * (Div p) at a pixel is the outward flux through its four edges, taken
+        from its own subdomain's copies;
+      * dof is False on edges of the image boundary (not in H_0(div));
+      * (B p)_e = (copy of the upper / left subdomain) - (copy of the lower /
+        right one), multipliers ordered horizontal interfaces first
+        [(ny-1) x W], then vertical ones [(nx-1) x H]."""
+    rc, cc = [int(a) for a in row_cuts], [int(a) for a in col_cuts]
+    ny, nx = len(rc) - 1, len(cc) - 1
+    base, o = {}, 0
+    for r in range(ny):
+        for c in range(nx):
+            h, w = rc[r + 1] - rc[r], cc[c + 1] - cc[c]
+            base[r, c] = (o, o + (h + 1) * w, h, w)
+            o += (h + 1) * w + h * (w + 1)
+    n_p = o
+    Div = np.zeros((H * W, n_p))
+    dof = np.zeros(n_p, bool)
+    for (r, c), (o1, o2, h, w) in base.items():
+        ra, ca = rc[r], cc[c]
+        for y in range(h):
+            for x in range(w):
+                g = (ra + y) * W + ca + x
+                Div[g, o1 + (y + 1) * w + x] += 1.0
+                Div[g, o1 + y * w + x] -= 1.0
+                Div[g, o2 + y * (w + 1) + x + 1] += 1.0
+                Div[g, o2 + y * (w + 1) + x] -= 1.0
+        for k in range(h + 1):
+            on_boundary = (k == 0 and r == 0) or (k == h and r == ny - 1)
+            dof[o1 + k * w: o1 + (k + 1) * w] = not on_boundary
+        for k in range(w + 1):
+            on_boundary = (k == 0 and c == 0) or (k == w and c == nx - 1)
+            dof[o2 + k: o2 + h * (w + 1): w + 1] = not on_boundary
+    Bm = np.zeros(((ny - 1) * W + (nx - 1) * H, n_p))
+    for r in range(1, ny):
+        for j in range(W):
+            c = int(np.searchsorted(cc, j, side="right")) - 1
+            s1, _, hs, ws = base[r - 1, c]
+            t1, _, _, wt = base[r, c]
+            e = (r - 1) * W + j
+            Bm[e, s1 + hs * ws + j - cc[c]] = 1.0
+            Bm[e, t1 + j - cc[c]] = -1.0
+    for c in range(1, nx):
+        for i in range(H):
+            r = int(np.searchsorted(rc, i, side="right")) - 1
+            _, s2, _, ws = base[r, c - 1]
+            _, t2, _, wt = base[r, c]
+            e = (ny - 1) * W + (c - 1) * H + i
+            Bm[e, s2 + (i - rc[r]) * (ws + 1) + ws] = 1.0
+            Bm[e, t2 + (i - rc[r]) * (wt + 1)] = -1.0
+    return Div, Bm, dof
+
+
+def rof_dual_prox(f, alpha, tau, v, Div, dof):
+    """prox of tau G at v, G(p) = (alpha F)^*(div~ p) + chi_C(p) for the ROF
+    fidelity F(u) = |u - f|^2 / 2: the minimiser of
+        (alpha/2)|f + div~ p / alpha|^2 + |p - v|^2 / (2 tau)   over |p_e| <= 1
+    (the local problems eq. (DD_local_dual) of every subdomain at once; they
+    are independent, so one bounded least-squares problem holds them all).
+    Solved exactly by BVLS; non-dof edges stay 0."""
+    from scipy.optimize import lsq_linear
+
+    nd = int(dof.sum())
+    A = np.vstack([Div[:, dof] / np.sqrt(alpha), np.eye(nd) / np.sqrt(tau)])
+    b = np.concatenate([-np.sqrt(alpha) * np.asarray(f, dtype=np.float64).ravel(),
+                        np.asarray(v)[dof] / np.sqrt(tau)])
+    res = lsq_linear(A, b, bounds=(-1.0, 1.0), method="bvls", tol=1e-15, lsmr_tol=None, max_iter=10000)
+    p = np.zeros(len(dof))
+    p[dof] = res.x
+    return p
+
+
+def dd_saddle_cp(f, alpha, row_cuts, col_cuts, tau, sigma, n_outer, p=None, p_prev=None, lam=None):
+    """Chambolle-Pock 2011, Algorithm 1 (theta = 1), on the saddle problem
+    (DD) of Sec. 4, min over torn p, max over lambda of
+        G(p) + <B p, lambda>,   G = sum_s (alpha F_s)^*(div p_s) + chi_C,
+    for the ROF fidelity, written in the textbook's own variables:
+        y_{n+1} = y_n + sigma K xbar_n          (F^* = 0: lambda is free)
+        x_{n+1} = prox_{tau G}(x_n - tau K^* y_{n+1})
+        xbar_{n+1} = 2 x_{n+1} - x_n
+    with x = p, y = lambda, K = B, every prox exact (rof_dual_prox) on the
+    global torn vector.  Starts from (p, p_prev, lam) (default all 0, the
+    start of Algorithm 1).  Returns the list of (p, lam, u) after each step,
+    u = f + div~ p / alpha (the primal recovery of the ROF case)."""
+    f = np.asarray(f, dtype=np.float64)
+    H, W = f.shape
+    Div, Bm, dof = torn_operators(H, W, row_cuts, col_cuts)
+    x = np.zeros(Bm.shape[1]) if p is None else np.array(p, dtype=np.float64)
+    x_old = x.copy() if p_prev is None else np.array(p_prev, dtype=np.float64)
+    y = np.zeros(Bm.shape[0]) if lam is None else np.array(lam, dtype=np.float64)
+    out = []
+    for _ in range(n_outer):
+        xbar = 2.0 * x - x_old
+        y = y + sigma * (Bm @ xbar)
+        x_old, x = x, rof_dual_prox(f, alpha, tau, x - tau * (Bm.T @ y), Div, dof)
+        out.append((x.copy(), y.copy(), f + (Div @ x).reshape(H, W) / alpha))
+    return out
