@@ -203,10 +203,10 @@ def run_diff(args):
 
 
 def run_dd_vs_full(args):
-    """Decomposed against undecomposed on one GPU (Sec. 6 compares the method
+    """Decomposed against undecomposed on one GPU (Sec. 5 compares the method
     with the primal-dual method on the full-dimension problem): wall-clock time
     of a plain solve until the relative primal energy error (J(u) - J*)/J*
-    falls below 1e-5 (the outer stopping rule of Sec. 6), on the 2048 x 2048
+    falls below 1e-5 (the outer stopping rule of Sec. 5.1), on the 2048 x 2048
     ROF image.  J* comes from a long undecomposed FISTA run whose FP64
     primal-dual gap bounds its own error.  Each iteration count of a doubling
     sequence is a separate timed solve (no diagnostics inside the timed

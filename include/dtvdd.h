@@ -46,9 +46,13 @@
  * message of the last failing call on the calling thread is returned by
  * dtv_last_error().  Arguments are validated before anything is enqueued,
  * so a failing call leaves every output untouched.  Calls are stream-ordered
- * on the given stream (a hipStream_t, NULL = default stream); the host only
- * waits when diagnostics are requested (h_stats, gap_tol).  A plan is not
- * thread-safe; distinct plans are independent.
+ * on the given stream (a hipStream_t, NULL = default stream).  The host waits
+ * only where a call says so: dtv_dd_bind_workspace (synchronous uploads),
+ * dtv_dd_solve with diagnostics (h_stats, gap_tol), with time_kernels, or
+ * on the autotuner's first solve of a shape (DTV_SCHED_AUTO), and the calls
+ * that return device results to the host (dtv_dd_diagnostics, dtv_dd_status,
+ * dtv_dd_inner_counts with inner_tol).  A plan is not thread-safe; distinct
+ * plans are independent.
  */
 #ifndef DTVDD_H
 #define DTVDD_H
@@ -146,7 +150,7 @@ typedef struct {
                                   per-step host work is asked for: diagnostics, checkpoints,
                                   kernel timing) */
     double cv_c1, cv_c2;       /* DTV_CV: the two region intensities of eq. (CCV); finite */
-    int32_t full_problem;      /* 1: the undecomposed problem (Sec. 6 compares against it): every
+    int32_t full_problem;      /* 1: the undecomposed problem (Sec. 5 compares against it): every
                                   image is one subdomain (ny = nx = 1) and the local problem has no
                                   proximal term (the limit 1/tau -> 0, so tau and sigma play no
                                   part), i.e. the local solver is the plain method on the whole
@@ -156,9 +160,10 @@ typedef struct {
                                   iterate (n_outer = 1: n_inner plain iterations); no
                                   save_for_backward */
     int32_t spin_limit;        /* persistent schedules: polls of one exchange word before a
-                                  tile gives up on a neighbour and the solve returns DTV_EHIP;
-                                  0: the default (2^21, about 0.1 s) */
-    double inner_tol;          /* > 0: adaptive local solves (Sec. 6 stops them by relative change):
+                                  tile gives up on a neighbour and its launch ends early
+                                  (dtv_dd_status then returns DTV_EHIP); 0: the default (2^21,
+                                  about 0.1 s) */
+    double inner_tol;          /* > 0: adaptive local solves (Sec. 5.1 stops them by relative change):
                                   each subdomain stops its FISTA steps in an outer step after the
                                   first step k with |p_k - p_(k-1)|_2 < inner_tol |p_k|_2 over its
                                   own edge dofs (or p_k = p_(k-1)), at most n_inner (the cap, <=
@@ -181,7 +186,8 @@ typedef struct {
 } dtv_layout;
 
 /* Validate the problem and build a plan.  imgs: n_images >= 1 descriptors.
-   Batched solves (n_images > 1) require inner = FISTA and no mask. */
+   Batched solves (n_images > 1) take every solver, fidelity and mask the
+   single-image solve takes; gap_tol needs a single image. */
 int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const dtv_dd_params *prm, dtv_dd_plan **out);
 
 /* Layout of one image (image in [0, n_images)); image = -1 reports totals:
@@ -208,9 +214,20 @@ int dtv_dd_bind_workspace(dtv_dd_plan *plan, void *d_ws, size_t bytes);
    prox keeps u in [0, 1]); D(p) = -(alpha F)^*(div p): -<f, div p> -
    |div p|^2/(2 alpha) for L2, sum over pixels of min(0, alpha g - div p) for
    DTV_CV, NaN (and so the gap) for L1 and for masked problems.  Returns
-   DTV_ENONFINITE if a diagnostic is not finite. */
+   DTV_ENONFINITE if a diagnostic is not finite.  Without diagnostics,
+   time_kernels or a first autotuned solve the call only enqueues work; the
+   persistent schedule's wait status is read with dtv_dd_status.
+   Workspace: the bound one (dtv_dd_bind_workspace), DTV_ENOWS without. */
 int dtv_dd_solve(dtv_dd_plan *plan, const float *d_f, const uint8_t *d_mask, float *d_u, float *d_p1,
                  float *d_p2, float *d_lambda, double *h_stats, int32_t *n_rows, void *stream);
+
+/* Outcome of the last solve's persistent launches: a persistent schedule lets a subdomain wait a
+   bounded number of polls (spin_limit) for each neighbour's interface copies; a wait that gives up
+   sets an error word in the workspace that solve used, and the launch ends early.  The solve itself
+   does not wait for its launches, so it cannot see that word; this call copies it to the host
+   (stream-ordered on `stream`, returns after it arrives) and returns DTV_EHIP if any wait gave up,
+   DTV_OK otherwise (also when the last solve ran no persistent launch). */
+int dtv_dd_status(dtv_dd_plan *plan, void *stream);
 
 /* FP64 diagnostics of a given state (same quantities as a row of h_stats,
    without the step count): h_out receives 4 doubles per image. */

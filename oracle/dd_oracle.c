@@ -49,7 +49,7 @@ typedef struct {
                                    Chan-Vese model, eq. (CCV) */
     double inner_tol;           /* > 0 (FISTA): stop a local solve once the
                                    relative change of its iterate falls below
-                                   inner_tol (the inner stopping rule of Sec. 6);
+                                   inner_tol (the inner stopping rule of Sec. 5.1);
                                    n_inner is then the cap */
 } orc_params;
 
@@ -229,7 +229,7 @@ static void local_fista(const orc_state *st, orc_sub *S)
             if (!dof2(st, S, w)) z2[y * (w + 1) + w] = 0.0;
         }
         /* relative change of the local iterate, |x_{k+1} - x_k|_2 / |x_{k+1}|_2,
-           over every dof of the subdomain (Sec. 6, inner stopping rule) */
+           over every dof of the subdomain (Sec. 5.1, inner stopping rule) */
         double dsq = 0.0, nsq = 0.0;
         for (int e = 0; e < n1; e++) {
             dsq += (z1[e] - x1[e]) * (z1[e] - x1[e]);

@@ -94,6 +94,7 @@ struct dtv_dd_plan {
     std::vector<int> h_info;
     std::vector<StreamTile> h_tiles[kRowChoices];  // streaming work lists, strips of 4 << ri rows
     std::vector<SubTile> h_subs;
+    std::vector<float> h_beta;  // adaptive stopping: the FISTA momentum table (beta[k], k = 0 .. n_inner)
     int n_full = 0;         // h_subs[0, n_full) are 128 x 128
     int n_framed = 0;       // h_subs[n_full, n_full + n_framed): framed (fused.hip), the rest any other
     // persistent FISTA schedule: the subdomains grouped by image into launches that fit on the device
@@ -110,6 +111,10 @@ struct dtv_dd_plan {
     GraphKey gkey;
     bool fused_ok = false;  // every subdomain fits the fused kernel
     bool persist_ok = false;  // the persistent schedule applies (full tiles, all resident, no per-step host work)
+
+    char *run_ws = nullptr;    // workspace of the last solve: the bound one, or the scratch array
+    bool ran_persist = false;  // the last solve ran the persistent schedule (its error word is in run_ws)
+    size_t buf_bytes = 0;      // bytes of each rotation buffer (0: the plan runs only the persistent schedule)
 
     // workspace layout (byte offsets)
     size_t off_imgs = 0, off_info = 0, off_tiles[kRowChoices] = {0, 0, 0, 0}, off_subs = 0, off_psubs = 0, off_buf[3] = {0, 0, 0},
@@ -139,6 +144,8 @@ struct dtv_dd_plan {
 
     ~dtv_dd_plan()
     {
+        // a replay of the plan's graph may still be in flight on the caller's stream
+        if (gexec) (void)hipDeviceSynchronize();
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
@@ -174,6 +181,8 @@ struct dtv_dd_plan {
     unsigned *sync_words() const { return (unsigned *)(ws + off_sync); }  // error flag of the persistent kernel
     float *beta_tab() const { return (float *)(ws + off_beta); }
     int *counts() const { return (int *)(ws + off_counts); }
+    const int *run_counts() const { return (const int *)(run_ws + off_counts); }
+    const unsigned *run_sync_words() const { return (const unsigned *)(run_ws + off_sync); }
 };
 
 // ---------------------------------------------------------------------------
@@ -194,6 +203,8 @@ static int check_cuts(const int32_t *given, int parts, int n, std::vector<int> &
 }
 
 static bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+static std::vector<float> fista_betas(int K);
 
 static bool any_of_sched(int requested, int sched) { return requested == DTV_SCHED_AUTO || requested == sched; }
 
@@ -398,6 +409,7 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
         pl->n_framed += is_framed(st);
     }
     pl->adaptive = p.inner_tol > 0.0;
+    if (pl->adaptive) pl->h_beta = fista_betas(p.n_inner);
     if (p.inner == DTV_INNER_FISTA) {
         pl->fused_ok = p.n_inner <= kMaxFusedInner || pl->adaptive;
         for (const SubTile &st : pl->h_subs)
@@ -479,14 +491,18 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
     for (int ri = 0; ri < kRowChoices; ++ri) pl->off_tiles[ri] = take(sizeof(StreamTile) * pl->h_tiles[ri].size());
     pl->off_subs = take(sizeof(SubTile) * pl->h_subs.size());
     pl->off_psubs = take(sizeof(SubTile) * std::max<size_t>(1, pl->p_subs.size()));
-    for (int k = 0; k < 3; ++k) pl->off_buf[k] = take(sizeof(float) * (size_t)(pl->tot_p1 + pl->tot_p2));
-    pl->off_u2 = take(p.inner == DTV_INNER_CP2 ? sizeof(float) * (size_t)pl->tot_px : 0);
+    // the persistent schedule updates p~, u and lambda in place: a plan that runs only that schedule
+    // needs no rotation buffers, no second u and no second lambda state
+    const bool persist_only = p.schedule == DTV_SCHED_PERSIST;
+    pl->buf_bytes = persist_only ? 0 : sizeof(float) * (size_t)(pl->tot_p1 + pl->tot_p2);
+    for (int k = 0; k < 3; ++k) pl->off_buf[k] = take(pl->buf_bytes);
+    pl->off_u2 = take(p.inner == DTV_INNER_CP2 && !persist_only ? sizeof(float) * (size_t)pl->tot_px : 0);
     pl->diag_nblk = diag_blocks_per_image(pl->maxH, pl->maxW);
     pl->off_part = take(sizeof(double) * 6 * (size_t)pl->diag_nblk * n_images);
     pl->off_dout = take(sizeof(double) * 6 * (size_t)n_images);
     pl->off_xch = take(pl->persist_ok ? sizeof(unsigned long long) * 2 * (size_t)pl->tot_lam : 0);
     pl->off_sync = take(2 * sizeof(unsigned));
-    pl->off_lamw = take(sizeof(float) * (size_t)pl->tot_lam);
+    pl->off_lamw = take(persist_only ? 0 : sizeof(float) * (size_t)pl->tot_lam);
     pl->off_beta = take(pl->adaptive ? sizeof(float) * (size_t)(p.n_inner + 1) : 0);
     pl->off_counts = take(pl->adaptive ? sizeof(int) * 2 * pl->h_subs.size() : 0);
     if (p.save_for_backward) {
@@ -583,11 +599,9 @@ extern "C" int dtv_dd_bind_workspace(dtv_dd_plan *pl, void *d_ws, size_t bytes)
             "upload image descriptors");
     HIP_TRY(hipMemcpy(ws + pl->off_info, pl->h_info.data(), sizeof(int) * pl->h_info.size(), hipMemcpyHostToDevice),
             "upload info words");
-    if (pl->adaptive) {
-        const std::vector<float> beta = fista_betas(pl->prm.n_inner);
-        HIP_TRY(hipMemcpy(ws + pl->off_beta, beta.data(), sizeof(float) * beta.size(), hipMemcpyHostToDevice),
+    if (pl->adaptive)
+        HIP_TRY(hipMemcpy(ws + pl->off_beta, pl->h_beta.data(), sizeof(float) * pl->h_beta.size(), hipMemcpyHostToDevice),
                 "upload momentum table");
-    }
     for (int ri = 0; ri < kRowChoices; ++ri)
         HIP_TRY(hipMemcpy(ws + pl->off_tiles[ri], pl->h_tiles[ri].data(), sizeof(StreamTile) * pl->h_tiles[ri].size(),
                           hipMemcpyHostToDevice),
@@ -600,7 +614,7 @@ extern "C" int dtv_dd_bind_workspace(dtv_dd_plan *pl, void *d_ws, size_t bytes)
                 "upload subdomain groups");
     // rotation buffers start at zero so that their boundary (non-dof) edges are 0
     for (int k = 0; k < 3; ++k)
-        HIP_TRY(hipMemset(ws + pl->off_buf[k], 0, sizeof(float) * (size_t)(pl->tot_p1 + pl->tot_p2)), "clear buffers");
+        if (pl->buf_bytes) HIP_TRY(hipMemset(ws + pl->off_buf[k], 0, pl->buf_bytes), "clear buffers");
     // reverse-mode buffers: the step kernels write dof edges only, so the
     // boundary entries of every edge buffer must start (and stay) at zero
     if (pl->prm.save_for_backward)
@@ -730,23 +744,35 @@ static int next_base(int sched, bool cp2, int K, int base)
     return sc[(K - 1) % 3];
 }
 
-extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_mask, float *d_u, float *d_p1,
-                            float *d_p2, float *d_lambda, double *h_stats, int32_t *n_rows, void *stream)
+// Arguments every solve entry point checks before anything is enqueued.
+static int check_solve_args(const dtv_dd_plan *pl, const float *d_f, const uint8_t *d_mask, const float *d_u,
+                            const float *d_p1, const float *d_p2, const float *d_lambda)
 {
     if (!pl || !d_f || !d_u || !d_p1 || !d_p2) return fail(DTV_EINVAL, "null argument");
     if (!d_lambda && pl->tot_lam > 0) return fail(DTV_EINVAL, "null argument (lambda)");
+    if (pl->prm.has_mask && !d_mask) return fail(DTV_EINVAL, "mask expected (has_mask = 1)");
+    return DTV_OK;
+}
+
+// The solve, on the workspace pl->ws.  noalloc: the outer steps are enqueued eagerly (no graph is
+// captured), the autotuner does not run (the plan's current choice is used) and nothing waits on
+// the host; the caller has checked that no per-step host work (diagnostics, checkpoints, kernel
+// timing) is asked for.
+static int solve_impl(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_mask, float *d_u, float *d_p1,
+                      float *d_p2, float *d_lambda, double *h_stats, int32_t *n_rows, void *stream, bool noalloc)
+{
     const dtv_dd_params &P = pl->prm;
-    if (P.has_mask && !d_mask) return fail(DTV_EINVAL, "mask expected (has_mask = 1)");
-    if (!pl->ws) return fail(DTV_ENOWS, "no workspace bound");
     hipStream_t s = (hipStream_t)stream;
+    pl->run_ws = pl->ws;
+    pl->ran_persist = false;
     const uint8_t *mask = P.has_mask ? d_mask : nullptr;
     const bool cp2 = P.inner == DTV_INNER_CP2;
     const int K = P.n_inner;
 
     if (!P.warm_start) {
-        HIP_TRY(hipMemsetAsync(d_p1, 0, sizeof(float) * (size_t)pl->tot_p1, s), "clear p1");
-        HIP_TRY(hipMemsetAsync(d_p2, 0, sizeof(float) * (size_t)pl->tot_p2, s), "clear p2");
-        if (pl->tot_lam > 0) HIP_TRY(hipMemsetAsync(d_lambda, 0, sizeof(float) * (size_t)pl->tot_lam, s), "clear lambda");
+        HIP_TRY(launch_fill_zero(d_p1, sizeof(float) * (size_t)pl->tot_p1, s), "clear p1");
+        HIP_TRY(launch_fill_zero(d_p2, sizeof(float) * (size_t)pl->tot_p2, s), "clear p2");
+        if (pl->tot_lam > 0) HIP_TRY(launch_fill_zero(d_lambda, sizeof(float) * (size_t)pl->tot_lam, s), "clear lambda");
         if (cp2) HIP_TRY(hipMemcpyAsync(d_u, d_f, sizeof(float) * (size_t)pl->tot_px, hipMemcpyDeviceToDevice, s), "u = f");
     }
     HIP_TRY(launch_zero_boundary(pl->d_imgs(), pl->n, pl->maxH, pl->maxW, d_p1, d_p2, s), "zero boundary");
@@ -791,7 +817,7 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
         fa.tol2 = P.inner_tol * P.inner_tol;
         fa.beta_dev = pl->beta_tab();
         fa.counts = pl->counts();
-        HIP_TRY(hipMemsetAsync(pl->counts(), 0, sizeof(int) * 2 * pl->h_subs.size(), s), "clear step counts");
+        HIP_TRY(launch_fill_zero(pl->counts(), sizeof(int) * 2 * pl->h_subs.size(), s), "clear step counts");
     }
     int stop_at = P.n_outer;
 
@@ -976,8 +1002,8 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
     const unsigned spin_limit = P.spin_limit > 0 ? (unsigned)P.spin_limit : kSpinLimitDefault;
     auto run_persist = [&](int count) -> int {
         unsigned *sync = pl->sync_words();
-        HIP_TRY(hipMemsetAsync(sync, 0, 2 * sizeof(unsigned), s), "clear error flag");
-        HIP_TRY(hipMemsetAsync(pl->xch(), 0, sizeof(unsigned long long) * 2 * (size_t)pl->tot_lam, s), "clear exchange");
+        HIP_TRY(launch_fill_zero(sync, 2 * sizeof(unsigned), s), "clear error flag");
+        HIP_TRY(launch_fill_zero(pl->xch(), sizeof(unsigned long long) * 2 * (size_t)pl->tot_lam, s), "clear exchange");
         int rc = tm.begin();
         if (rc != DTV_OK) return rc;
         if (tm.e0) HIP_TRY(hipEventRecord(tm.e0, s), "event");
@@ -1018,10 +1044,8 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
         if (tm.e1) HIP_TRY(hipEventRecord(tm.e1, s), "event");
         rc = tm.end();
         if (rc != DTV_OK) return rc;
-        int err = 0;
-        HIP_TRY(hipMemcpyAsync(&err, sync, sizeof(int), hipMemcpyDeviceToHost, s), "exchange status");
-        HIP_TRY(hipStreamSynchronize(s), "exchange status");
-        if (err) return fail(DTV_EHIP, "persistent schedule: a wait for a neighbouring subdomain timed out");
+        // a wait that gave up leaves its flag in the workspace; dtv_dd_status reads it
+        pl->ran_persist = true;
         return DTV_OK;
     };
 
@@ -1101,7 +1125,7 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
     // A per-step schedule costs its chunk time per step; the persistent launch has a fixed part (loading
     // and storing every tile) besides its per-step part, so it is timed over chunks of c and 2c steps
     // and priced as fixed + per-step * (the steps left), the way the rest of the solve would run it.
-    if (!pl->tuned && !host_work && P.n_outer > 0) {
+    if (!pl->tuned && !host_work && !noalloc && P.n_outer > 0) {
         const std::vector<Choice> cands = candidates(pl);
         const int nc = (int)cands.size();
         const int chunk = std::min(16, P.n_outer / (2 * (std::max(nc, 1) + 2)) - 1);
@@ -1151,7 +1175,7 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
         }
     }
     {
-        int rc = run_range(n, P.n_outer, pl->schedule, pl->rows, true);
+        int rc = run_range(n, P.n_outer, pl->schedule, pl->rows, !noalloc);
         if (rc != DTV_OK) return rc;
     }
 
@@ -1184,6 +1208,27 @@ extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_
     return DTV_OK;
 }
 
+extern "C" int dtv_dd_solve(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_mask, float *d_u, float *d_p1,
+                            float *d_p2, float *d_lambda, double *h_stats, int32_t *n_rows, void *stream)
+{
+    int rc = check_solve_args(pl, d_f, d_mask, d_u, d_p1, d_p2, d_lambda);
+    if (rc != DTV_OK) return rc;
+    if (!pl->ws) return fail(DTV_ENOWS, "no workspace bound");
+    return solve_impl(pl, d_f, d_mask, d_u, d_p1, d_p2, d_lambda, h_stats, n_rows, stream, false);
+}
+
+extern "C" int dtv_dd_status(dtv_dd_plan *pl, void *stream)
+{
+    if (!pl) return fail(DTV_EINVAL, "null argument");
+    if (!pl->ran_persist || !pl->run_ws) return DTV_OK;
+    hipStream_t s = (hipStream_t)stream;
+    unsigned err = 0;
+    HIP_TRY(hipMemcpyAsync(&err, pl->run_sync_words(), sizeof(unsigned), hipMemcpyDeviceToHost, s), "exchange status");
+    HIP_TRY(hipStreamSynchronize(s), "exchange status");
+    if (err) return fail(DTV_EHIP, "persistent schedule: a wait for a neighbouring subdomain timed out");
+    return DTV_OK;
+}
+
 extern "C" int dtv_dd_inner_counts(dtv_dd_plan *pl, int32_t *h_counts, void *stream)
 {
     if (!pl || !h_counts) return fail(DTV_EINVAL, "null argument");
@@ -1191,7 +1236,7 @@ extern "C" int dtv_dd_inner_counts(dtv_dd_plan *pl, int32_t *h_counts, void *str
     std::vector<int> dev(2 * nsub, 0);
     if (pl->solved && pl->adaptive) {
         hipStream_t s = (hipStream_t)stream;
-        HIP_TRY(hipMemcpyAsync(dev.data(), pl->counts(), sizeof(int) * 2 * nsub, hipMemcpyDeviceToHost, s),
+        HIP_TRY(hipMemcpyAsync(dev.data(), pl->run_counts(), sizeof(int) * 2 * nsub, hipMemcpyDeviceToHost, s),
                 "step counts");
         HIP_TRY(hipStreamSynchronize(s), "step counts");
     } else if (pl->solved) {

@@ -205,6 +205,8 @@ hipError_t launch_persist_cp2(const PersistCp2Args &a, int nsub, hipStream_t s);
 int persist_cp2_capacity(int device);
 hipError_t launch_u_from_p(const ImgDev *imgs, int nimg, int maxH, int maxW, const int *info, const float *p1,
                            const float *p2, const float *f, float *u, hipStream_t s);
+// zero `bytes` bytes (a multiple of 4) at p with a fill kernel
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
 hipError_t launch_zero_boundary(const ImgDev *imgs, int nimg, int maxH, int maxW, float *p1, float *p2,
                                 hipStream_t s);
 // FP64 diagnostics: per image 6 partial sums reduced into out[img*6 + q]:

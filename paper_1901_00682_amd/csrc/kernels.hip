@@ -16,6 +16,8 @@
 // Arithmetic is FP32 with explicit fmaf where a fused multiply-add is meant
 // (the library is built with -ffp-contract=off so that the streaming and
 // fused schedules round identically).
+#include <algorithm>
+
 #include "dtvdd_internal.h"
 #include "cp2_ops.h"
 #include "fista_ops.h"
@@ -483,6 +485,25 @@ hipError_t launch_u_from_p(const ImgDev *imgs, int nimg, int maxH, int maxW, con
 }
 
 // Boundary edges of the image carry no dof: keep them at zero.
+// Zero fill of `words` 32-bit words (every buffer the solver clears is a
+// multiple of 4 bytes and 4-byte aligned).  A kernel rather than
+// hipMemsetAsync, so that a caller may capture the whole solve in a hipGraph
+// without memset nodes.
+__global__ __launch_bounds__(256) void k_fill_zero(unsigned *p, long long words)
+{
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < words; k += stride) p[k] = 0u;
+}
+
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s)
+{
+    const long long words = (long long)(bytes / 4);
+    if (words == 0) return hipSuccess;
+    const long long blocks = std::min<long long>((words + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, s, (unsigned *)p, words);
+    return hipGetLastError();
+}
+
 __global__ __launch_bounds__(256) void k_zero_boundary(const ImgDev *imgs, float *p1, float *p2)
 {
     const ImgDev im = imgs[blockIdx.y];

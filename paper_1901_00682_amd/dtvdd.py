@@ -9,8 +9,10 @@ solvers of Sec. 5; the C-ABI is documented in include/dtvdd.h.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 from dataclasses import dataclass
 
 import numpy as np
@@ -27,7 +29,7 @@ SCHEDULE_NAME = {v: k for k, v in SCHEDULE.items()}
 # every entry point declared in include/dtvdd.h
 EXPORTS = ("dtv_dd_setup", "dtv_dd_layout", "dtv_dd_workspace_bytes", "dtv_dd_bind_workspace", "dtv_dd_solve",
            "dtv_dd_diagnostics", "dtv_dd_backward", "dtv_dd_kernel_time", "dtv_dd_schedule", "dtv_dd_choice",
-           "dtv_dd_inner_counts", "dtv_dd_destroy", "dtv_last_error")
+           "dtv_dd_inner_counts", "dtv_dd_status", "dtv_dd_destroy", "dtv_last_error")
 
 
 class DtvError(RuntimeError):
@@ -87,6 +89,7 @@ def lib(path: str = LIB_PATH):
     L.dtv_dd_schedule.argtypes = [vp, ctypes.POINTER(i32)]
     L.dtv_dd_choice.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.dtv_dd_inner_counts.argtypes = [vp, ctypes.POINTER(i32), vp]
+    L.dtv_dd_status.argtypes = [vp, vp]
     L.dtv_dd_destroy.argtypes = [vp]
     L.dtv_dd_destroy.restype = None
     L.dtv_last_error.restype = ctypes.c_char_p
@@ -119,6 +122,18 @@ class Image:
 
 def floor_cuts(n: int, parts: int) -> np.ndarray:
     return np.array([(k * n) // parts for k in range(parts + 1)], dtype=np.int32)
+
+
+# Plans still alive at interpreter exit are destroyed by an exit hook, while
+# the HIP runtime is still up: the plan's graph, stream, events and pinned
+# buffer are released before the runtime tears itself down.
+_live_plans: "weakref.WeakSet[Plan]" = weakref.WeakSet()
+
+
+@atexit.register
+def _destroy_live_plans():
+    for p in list(_live_plans):
+        p.close()
 
 
 class Plan:
@@ -157,6 +172,7 @@ class Plan:
         _check(L.dtv_dd_setup(descs, len(self.images), ctypes.byref(self.params), ctypes.byref(h)))
         self.h = h
         self._L = L
+        _live_plans.add(self)
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         self.ws = None
         if bind:
@@ -165,12 +181,17 @@ class Plan:
             self.ws = torch.empty(max(int(nb.value), 256), dtype=torch.uint8, device=self.device)
             _check(L.dtv_dd_bind_workspace(self.h, ctypes.c_void_p(self.ws.data_ptr()), int(nb.value)))
 
-    def __del__(self):
+    def close(self):
+        """Destroy the library plan (idempotent); the workspace tensor is
+        released with the object."""
         h = getattr(self, "h", None)
         L = getattr(self, "_L", None)  # held by the plan: module globals may be gone at interpreter exit
         if h is not None and h.value and L is not None:
             L.dtv_dd_destroy(h)
-            self.h = None
+        self.h = None
+
+    def __del__(self):
+        self.close()
 
     @property
     def n_images(self) -> int:
@@ -208,10 +229,17 @@ class Plan:
             stream = torch.cuda.current_stream(self.device)
         return ctypes.c_void_p(stream.cuda_stream)
 
-    def solve(self, f, mask=None, state=None, stream=None, want_stats=True):
+    def status(self, stream=None):
+        """Raise DtvError if a persistent launch of the last solve gave up a
+        wait for a neighbouring subdomain (waits for the stream)."""
+        _check(lib().dtv_dd_status(self.h, self._stream(stream)))
+
+    def solve(self, f, mask=None, state=None, stream=None, want_stats=True, check=True):
         """Run the plan.  f: flat float32 device tensor (images concatenated);
         state: dict from new_state() (allocated when None).  Returns
-        (state, stats) with stats an array [n_images, rows, 5] or None."""
+        (state, stats) with stats an array [n_images, rows, 5] or None.
+        check: read the persistent schedule's wait status afterwards (waits for
+        the stream); False leaves the call asynchronous (see status())."""
         import torch
 
         if state is None:
@@ -228,6 +256,8 @@ class Plan:
                                   _ptr(state["p2"]), _ptr(state["lam"]), sp, ctypes.byref(nrow),
                                   self._stream(stream))
         _check(code)
+        if check:
+            self.status(stream)
         st = stats[: self.n_images * rows * 5].reshape(self.n_images, rows, 5)[:, : nrow.value] if sp else None
         return state, st
 

@@ -178,3 +178,4 @@ def test_schedule_choice_reporting():
     assert (sc.value, r.value, src.value) == (1, 8, 3)
     L.dtv_dd_destroy(h)
     assert L.dtv_dd_choice(None, None, None, None) == dtvdd.DTV_EINVAL
+

@@ -1,4 +1,4 @@
-"""Adaptive local solves (the inner stopping rule of Sec. 6) on the GPU: the
+"""Adaptive local solves (the inner stopping rule of Sec. 5.1) on the GPU: the
 per-subdomain step counts equal the FP64 oracle's and the iterates match it to
 relative L2 <= 1e-5; the rule degenerates to the fixed-count path (bitwise) for
 a vanishing tolerance and to one step for a huge one.

@@ -1,6 +1,6 @@
 """Convex Chan-Vese segmentation (Sec. 3, eq. CCV, with the local primal-dual
-solver of Sec. 6) and the undecomposed problem (the N = 1 comparison of
-Sec. 6) on the GPU against the FP64 oracle at matched iteration counts:
+solver of Sec. 5) and the undecomposed problem (the N = 1 comparison of
+Sec. 5) on the GPU against the FP64 oracle at matched iteration counts:
 relative L2 <= 1e-5 on u and on p, FP64 diagnostics within 1e-6 relative."""
 import sys
 

@@ -1,5 +1,5 @@
 """Pins of the oracle's convex Chan-Vese fidelity (Sec. 3, eq. CCV; the
-segmentation experiment of Sec. 6 with its outer parameters tau = 1,
+segmentation experiment of Sec. 5.3 with its outer parameters tau = 1,
 tau sigma = 1/2).
 
 The references are independent of the oracle's decomposed code: the prox by

@@ -1,4 +1,4 @@
-"""Pins of the oracle's inner stopping rule (Sec. 6: a local solve stops once
+"""Pins of the oracle's inner stopping rule (Sec. 5.1: a local solve stops once
 |p^(k+1) - p^(k)|_2 / |p^(k+1)|_2 falls below a tolerance).
 
 The reference for the rule is computed outside the oracle: fixed-count runs of
