@@ -226,7 +226,8 @@ int dtv_dd_solve(dtv_dd_plan *plan, const float *d_f, const uint8_t *d_mask, flo
    sets an error word in the workspace that solve used, and the launch ends early.  The solve itself
    does not wait for its launches, so it cannot see that word; this call copies it to the host
    (stream-ordered on `stream`, returns after it arrives) and returns DTV_EHIP if any wait gave up,
-   DTV_OK otherwise (also when the last solve ran no persistent launch). */
+   DTV_OK otherwise (also when the last solve ran no persistent launch).  After
+   dtv_dd_solve_noalloc, call it before another plan's dtv_dd_solve_noalloc on the same device. */
 int dtv_dd_status(dtv_dd_plan *plan, void *stream);
 
 /* FP64 diagnostics of a given state (same quantities as a row of h_stats,
@@ -263,6 +264,28 @@ int dtv_dd_choice(const dtv_dd_plan *plan, int32_t *schedule, int32_t *rows, int
    With inner_tol it reads them from the device: stream-ordered on `stream`,
    returns after they arrive. */
 int dtv_dd_inner_counts(dtv_dd_plan *plan, int32_t *h_counts, void *stream);
+
+/* For callers that cannot allocate device memory: code under HIP graph capture, tight serving
+   loops, harnesses that forbid allocation.  dtv_dd_solve with the library's own device scratch
+   array (DTV_SCRATCH_BYTES bytes, one per device, held until the process ends) as the
+   workspace instead of a bound one; the caller still passes every input and output buffer.
+   Makes no device or pinned-host allocation and creates no stream, event or graph: the outer
+   steps are enqueued eagerly with the plan's current schedule (explicit, cached, or the fixed
+   rule: the autotuner does not run), and the host does not wait (read the persistent schedule's
+   wait status with dtv_dd_status).
+   Requirements: the plan's workspace size (dtv_dd_workspace_bytes) at most DTV_SCRATCH_BYTES
+   (a plan set up with schedule = DTV_SCHED_PERSIST needs no rotation buffers, so a 2048 x 2048
+   image with 16 x 16 subdomains needs about 3.5 MB), else DTV_ENOWS; diag_every = 0, gap_tol = 0,
+   save_for_backward = 0 and time_kernels = 0, else DTV_EINVAL.
+   The array is shared by every call on a device and keeps the last call's contents: the first
+   call of a plan on a device (and the first after another plan's call there) uploads the plan's
+   metadata into it with stream-ordered copies from host memory and clears the buffers that must
+   start at zero with a fill kernel; later calls of the same plan go straight to the kernels (a
+   caller capturing the call into a graph makes one uncaptured call first).  Calls that overlap
+   on one device (other streams, other threads, other plans) race on the array. */
+#define DTV_SCRATCH_BYTES (32u << 20)
+int dtv_dd_solve_noalloc(dtv_dd_plan *plan, const float *d_f, const uint8_t *d_mask, float *d_u, float *d_p1,
+                         float *d_p2, float *d_lambda, void *stream);
 
 void dtv_dd_destroy(dtv_dd_plan *plan);
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <cmath>
@@ -77,6 +78,8 @@ struct GraphKey {
 std::mutex g_tune_mu;
 std::map<std::string, Choice> g_tune_cache;
 
+std::atomic<uint64_t> g_plan_ids{0};
+
 }  // namespace
 
 struct dtv_dd_plan {
@@ -112,6 +115,7 @@ struct dtv_dd_plan {
     bool fused_ok = false;  // every subdomain fits the fused kernel
     bool persist_ok = false;  // the persistent schedule applies (full tiles, all resident, no per-step host work)
 
+    uint64_t uid = 0;          // process-wide plan id (the scratch array records whose metadata it holds)
     char *run_ws = nullptr;    // workspace of the last solve: the bound one, or the scratch array
     bool ran_persist = false;  // the last solve ran the persistent schedule (its error word is in run_ws)
     size_t buf_bytes = 0;      // bytes of each rotation buffer (0: the plan runs only the persistent schedule)
@@ -313,6 +317,7 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
     if (p.spin_limit < 0) return fail(DTV_EINVAL, "spin_limit must be >= 0");
 
     dtv_dd_plan *pl = new dtv_dd_plan();
+    pl->uid = ++g_plan_ids;
     pl->prm = p;
     pl->n = n_images;
     pl->imgs.resize(n_images);
@@ -1521,6 +1526,95 @@ extern "C" int dtv_dd_choice(const dtv_dd_plan *pl, int32_t *schedule, int32_t *
     if (rows) *rows = pl->rows;
     if (source) *source = pl->choice_source;
     return DTV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// the solve that allocates nothing: the library's own device array is the workspace
+
+static __device__ __align__(256) unsigned char scratch[DTV_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[kMaxDevices];       // device address of `scratch` on each device, looked up once
+uint64_t g_scratch_owner[kMaxDevices];  // id of the plan whose metadata that device's array holds (0: none)
+}  // namespace
+
+// Stream-ordered upload of the plan's metadata into a workspace and zeroing of its rotation buffers
+// (their non-dof edges must hold 0): what dtv_dd_bind_workspace does, with no host wait and with a
+// fill kernel instead of memsets.
+static int upload_async(dtv_dd_plan *pl, char *ws, hipStream_t s)
+{
+    HIP_TRY(hipMemcpyAsync(ws + pl->off_imgs, pl->h_imgs.data(), sizeof(ImgDev) * pl->h_imgs.size(),
+                           hipMemcpyHostToDevice, s),
+            "upload image descriptors");
+    HIP_TRY(hipMemcpyAsync(ws + pl->off_info, pl->h_info.data(), sizeof(int) * pl->h_info.size(), hipMemcpyHostToDevice,
+                           s),
+            "upload info words");
+    if (pl->adaptive)
+        HIP_TRY(hipMemcpyAsync(ws + pl->off_beta, pl->h_beta.data(), sizeof(float) * pl->h_beta.size(),
+                               hipMemcpyHostToDevice, s),
+                "upload momentum table");
+    for (int ri = 0; ri < kRowChoices; ++ri)
+        HIP_TRY(hipMemcpyAsync(ws + pl->off_tiles[ri], pl->h_tiles[ri].data(), sizeof(StreamTile) * pl->h_tiles[ri].size(),
+                               hipMemcpyHostToDevice, s),
+                "upload work list");
+    HIP_TRY(hipMemcpyAsync(ws + pl->off_subs, pl->h_subs.data(), sizeof(SubTile) * pl->h_subs.size(),
+                           hipMemcpyHostToDevice, s),
+            "upload subdomain list");
+    if (!pl->p_subs.empty())
+        HIP_TRY(hipMemcpyAsync(ws + pl->off_psubs, pl->p_subs.data(), sizeof(SubTile) * pl->p_subs.size(),
+                               hipMemcpyHostToDevice, s),
+                "upload subdomain groups");
+    for (int k = 0; k < 3; ++k)
+        if (pl->buf_bytes) HIP_TRY(launch_fill_zero(ws + pl->off_buf[k], pl->buf_bytes, s), "clear buffers");
+    return DTV_OK;
+}
+
+extern "C" int dtv_dd_solve_noalloc(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_mask, float *d_u,
+                                    float *d_p1, float *d_p2, float *d_lambda, void *stream)
+{
+    int rc = check_solve_args(pl, d_f, d_mask, d_u, d_p1, d_p2, d_lambda);
+    if (rc != DTV_OK) return rc;
+    const dtv_dd_params &P = pl->prm;
+    if (P.diag_every != 0 || P.gap_tol > 0.0 || P.save_for_backward || P.time_kernels)
+        return fail(DTV_EINVAL, "dtv_dd_solve_noalloc takes no diagnostics, gap_tol, save_for_backward or "
+                                "time_kernels");
+    if (pl->ws_bytes > (size_t)DTV_SCRATCH_BYTES)
+        return fail(DTV_ENOWS, "the plan needs " + std::to_string(pl->ws_bytes) +
+                                   " bytes of workspace, more than the library's scratch array (" +
+                                   std::to_string((size_t)DTV_SCRATCH_BYTES) +
+                                   " bytes); bind a workspace and call dtv_dd_solve, or set up the plan with "
+                                   "schedule = DTV_SCHED_PERSIST (no rotation buffers)");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "current device");
+    if (dev < 0 || dev >= kMaxDevices) return fail(DTV_EINVAL, "device index beyond the scratch table");
+    hipStream_t s = (hipStream_t)stream;
+    char *scr = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (!g_scratch_ptr[dev]) {  // once per device, with that device current
+            void *ptr = nullptr;
+            HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "scratch array address");
+            if (!ptr || ((uintptr_t)ptr & 255) != 0) return fail(DTV_EHIP, "scratch array address is not 256-byte aligned");
+            g_scratch_ptr[dev] = (char *)ptr;
+        }
+        scr = g_scratch_ptr[dev];
+        if (g_scratch_owner[dev] != pl->uid) {
+            g_scratch_owner[dev] = 0;
+            rc = upload_async(pl, scr, s);
+            if (rc != DTV_OK) return rc;
+            g_scratch_owner[dev] = pl->uid;
+        }
+    }
+    // run on the scratch array; the bound workspace (if any) is untouched
+    struct WsSwap {
+        dtv_dd_plan *pl;
+        char *saved;
+        ~WsSwap() { pl->ws = saved; }
+    } swap{pl, pl->ws};
+    pl->ws = scr;
+    return solve_impl(pl, d_f, d_mask, d_u, d_p1, d_p2, d_lambda, nullptr, nullptr, stream, true);
 }
 
 extern "C" void dtv_dd_destroy(dtv_dd_plan *pl) { delete pl; }

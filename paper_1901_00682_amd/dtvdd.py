@@ -29,7 +29,9 @@ SCHEDULE_NAME = {v: k for k, v in SCHEDULE.items()}
 # every entry point declared in include/dtvdd.h
 EXPORTS = ("dtv_dd_setup", "dtv_dd_layout", "dtv_dd_workspace_bytes", "dtv_dd_bind_workspace", "dtv_dd_solve",
            "dtv_dd_diagnostics", "dtv_dd_backward", "dtv_dd_kernel_time", "dtv_dd_schedule", "dtv_dd_choice",
-           "dtv_dd_inner_counts", "dtv_dd_status", "dtv_dd_destroy", "dtv_last_error")
+           "dtv_dd_inner_counts", "dtv_dd_status", "dtv_dd_solve_noalloc", "dtv_dd_destroy", "dtv_last_error")
+
+SCRATCH_BYTES = 32 << 20  # DTV_SCRATCH_BYTES: the library's device scratch array (dtv_dd_solve_noalloc)
 
 
 class DtvError(RuntimeError):
@@ -90,6 +92,7 @@ def lib(path: str = LIB_PATH):
     L.dtv_dd_choice.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.dtv_dd_inner_counts.argtypes = [vp, ctypes.POINTER(i32), vp]
     L.dtv_dd_status.argtypes = [vp, vp]
+    L.dtv_dd_solve_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     L.dtv_dd_destroy.argtypes = [vp]
     L.dtv_dd_destroy.restype = None
     L.dtv_last_error.restype = ctypes.c_char_p
@@ -233,6 +236,23 @@ class Plan:
         """Raise DtvError if a persistent launch of the last solve gave up a
         wait for a neighbouring subdomain (waits for the stream)."""
         _check(lib().dtv_dd_status(self.h, self._stream(stream)))
+
+    def solve_noalloc(self, f, mask=None, state=None, stream=None, check=True):
+        """dtv_dd_solve_noalloc: the solve on the library's device scratch
+        array (no workspace, no allocation in the call).  state: dict from
+        new_state() (allocated here when None, before the call)."""
+        import torch
+
+        if state is None:
+            state = self.new_state()
+        assert f.dtype == torch.float32 and f.is_contiguous() and f.device.type == "cuda"
+        if mask is not None:
+            assert mask.dtype == torch.uint8 and mask.is_contiguous()
+        _check(lib().dtv_dd_solve_noalloc(self.h, _ptr(f), _ptr(mask), _ptr(state["u"]), _ptr(state["p1"]),
+                                          _ptr(state["p2"]), _ptr(state["lam"]), self._stream(stream)))
+        if check:
+            self.status(stream)
+        return state
 
     def solve(self, f, mask=None, state=None, stream=None, want_stats=True, check=True):
         """Run the plan.  f: flat float32 device tensor (images concatenated);

@@ -179,3 +179,31 @@ def test_schedule_choice_reporting():
     L.dtv_dd_destroy(h)
     assert L.dtv_dd_choice(None, None, None, None) == dtvdd.DTV_EINVAL
 
+
+def test_noalloc_validation_without_a_gpu():
+    """dtv_dd_solve_noalloc rejects per-step host work (EINVAL) and plans whose
+    workspace exceeds the library's scratch array (ENOWS) before touching a
+    device; dtv_dd_status after no solve is OK."""
+    L = dtvdd.lib()
+    dummy = ctypes.c_void_p(256)
+    code, h = _setup(diag_every=5)
+    assert code == 0
+    assert L.dtv_dd_solve_noalloc(h, dummy, None, dummy, dummy, dummy, dummy, None) == dtvdd.DTV_EINVAL
+    assert "diagnostics" in L.dtv_last_error().decode()
+    assert L.dtv_dd_status(h, None) == dtvdd.DTV_OK
+    L.dtv_dd_destroy(h)
+    # 2048^2 with the rotation buffers of the per-step schedules: about 100 MB of workspace
+    code, h = _setup(H=2048, W=2048, rc=tuple(range(0, 2049, 128)), cc=tuple(range(0, 2049, 128)))
+    assert code == 0
+    nb = ctypes.c_size_t()
+    assert L.dtv_dd_workspace_bytes(h, ctypes.byref(nb)) == 0 and nb.value > dtvdd.SCRATCH_BYTES
+    assert L.dtv_dd_solve_noalloc(h, dummy, None, dummy, dummy, dummy, dummy, None) == dtvdd.DTV_ENOWS
+    assert "scratch" in L.dtv_last_error().decode()
+    assert L.dtv_dd_solve_noalloc(h, dummy, None, None, dummy, dummy, dummy, None) == dtvdd.DTV_EINVAL
+    L.dtv_dd_destroy(h)
+
+
+def test_scratch_size_matches_header():
+    text = open(os.path.join(ROOT, "include", "dtvdd.h")).read()
+    m = re.search(r"#define DTV_SCRATCH_BYTES \((\d+)u << (\d+)\)", text)
+    assert m and int(m.group(1)) << int(m.group(2)) == dtvdd.SCRATCH_BYTES
