@@ -138,7 +138,7 @@ class Problem:
     no_prox_term: bool = False
     c1: float = 0.6              # Chan-Vese intensities (fidelity "CV"), eq. (CCV)
     c2: float = 0.1
-    inner_tol: float = 0.0       # > 0: inner stopping rule of Sec. 5.1 (FISTA), n_inner is the cap
+    inner_tol: float = 0.0       # > 0: inner stopping rule of Sec. 5.1 (either local solver), n_inner the cap
 
 
 class Oracle:

@@ -47,10 +47,11 @@ typedef struct {
     int n_inner;                /* local iterations per outer step */
     double cv_c1, cv_c2;        /* ORC_CV: the two intensities of the convex
                                    Chan-Vese model, eq. (CCV) */
-    double inner_tol;           /* > 0 (FISTA): stop a local solve once the
-                                   relative change of its iterate falls below
-                                   inner_tol (the inner stopping rule of Sec. 5.1);
-                                   n_inner is then the cap */
+    double inner_tol;           /* > 0: stop a local solve once the relative
+                                   change of its dual iterate falls below
+                                   inner_tol (the inner stopping rule of Sec. 5.1,
+                                   for either local solver); n_inner is then the
+                                   cap */
 } orc_params;
 
 typedef struct {
@@ -186,6 +187,40 @@ static double prox_fidelity(const orc_params *P, double z, double f, unsigned ch
 /* ------------------------------------------------------------------ */
 /* local solvers                                                        */
 
+/* |z - x|^2 and |z|^2 over every dof of the subdomain (z the new dual
+   iterate, x the previous one; non-dof edges hold 0 in both). */
+static void rel_change(const orc_sub *S, const double *z1, const double *z2, const double *x1, const double *x2,
+                       double *dsq, double *nsq)
+{
+    int n1 = (S->h + 1) * S->w, n2 = S->h * (S->w + 1);
+    double d = 0.0, n = 0.0;
+    for (int e = 0; e < n1; e++) {
+        d += (z1[e] - x1[e]) * (z1[e] - x1[e]);
+        n += z1[e] * z1[e];
+    }
+    for (int e = 0; e < n2; e++) {
+        d += (z2[e] - x2[e]) * (z2[e] - x2[e]);
+        n += z2[e] * z2[e];
+    }
+    *dsq = d;
+    *nsq = n;
+}
+
+/* The inner stopping rule of Sec. 5.1: after local step `taken` (of at most
+   n_inner), stop when |p^(k+1) - p^(k)|_2 < inner_tol |p^(k+1)|_2, or when the
+   iterate did not move.  Records how close the decision came to the threshold
+   (test aid). */
+static int inner_converged(const orc_params *P, orc_sub *S, int taken, double dsq, double nsq)
+{
+    if (!(P->inner_tol > 0.0) || taken >= P->n_inner) return 0;
+    double thr = P->inner_tol * P->inner_tol * nsq;
+    if (dsq > 0.0 && thr > 0.0) {
+        double m = fabs(log(dsq / thr));
+        if (m < S->margin) S->margin = m;
+    }
+    return dsq == 0.0 || dsq < thr;
+}
+
 /* Projected FISTA (Beck and Teboulle) on the local dual problem of
    eq. (DD_local_dual) for the ROF fidelity without mask:
      min_{p in C_s} (alpha/2)|f_s + div_s p / alpha|^2 + (1/(2 tau))|p - phat_s|^2.
@@ -230,15 +265,8 @@ static void local_fista(const orc_state *st, orc_sub *S)
         }
         /* relative change of the local iterate, |x_{k+1} - x_k|_2 / |x_{k+1}|_2,
            over every dof of the subdomain (Sec. 5.1, inner stopping rule) */
-        double dsq = 0.0, nsq = 0.0;
-        for (int e = 0; e < n1; e++) {
-            dsq += (z1[e] - x1[e]) * (z1[e] - x1[e]);
-            nsq += z1[e] * z1[e];
-        }
-        for (int e = 0; e < n2; e++) {
-            dsq += (z2[e] - x2[e]) * (z2[e] - x2[e]);
-            nsq += z2[e] * z2[e];
-        }
+        double dsq, nsq;
+        rel_change(S, z1, z2, x1, x2, &dsq, &nsq);
         double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
         double beta = (t - 1.0) / tn;
         for (int e = 0; e < n1; e++) {
@@ -251,14 +279,7 @@ static void local_fista(const orc_state *st, orc_sub *S)
         }
         t = tn;
         taken = it + 1;
-        if (P->inner_tol > 0.0 && taken < P->n_inner) {
-            double thr = P->inner_tol * P->inner_tol * nsq;
-            if (dsq > 0.0 && thr > 0.0) {
-                double m = fabs(log(dsq / thr));
-                if (m < S->margin) S->margin = m;
-            }
-            if (dsq == 0.0 || dsq < thr) break;
-        }
+        if (inner_converged(P, S, taken, dsq, nsq)) break;
     }
     S->steps_total += taken;
     if (taken > S->steps_max) S->steps_max = taken;
@@ -275,7 +296,9 @@ static void local_fista(const orc_state *st, orc_sub *S)
           = proj_C((tau (p - tau_k div_s^* u) + tau_k phat)/(tau + tau_k))
      theta = 1/sqrt(1 + 2 gamma tau_k), tau_k <- theta tau_k,
      sigma_k <- sigma_k / theta, xbar = p' + theta (p' - p).
-   Warm start (p_s, u_s) from the previous outer step, step sizes reset. */
+   Warm start (p_s, u_s) from the previous outer step, step sizes reset.
+   With inner_tol the relative-change rule of Sec. 5.1 on p stops the solve
+   (the state is then (p^(k), u^(k)) of the last step taken). */
 static void local_cp2(const orc_state *st, orc_sub *S)
 {
     const orc_params *P = &st->prm;
@@ -287,6 +310,7 @@ static void local_cp2(const orc_state *st, orc_sub *S)
     memcpy(xb1, x1, sizeof(double) * n1);
     memcpy(xb2, x2, sizeof(double) * n2);
     double tk = P->tau0, sk = P->sigma0;
+    int taken = 0;
     for (int it = 0; it < P->n_inner; it++) {
         div_local(S, xb1, xb2, S->v);
         for (int i = 0; i < h * w; i++)
@@ -310,6 +334,8 @@ static void local_cp2(const orc_state *st, orc_sub *S)
             if (!dof2(st, S, 0)) z2[y * (w + 1)] = 0.0;
             if (!dof2(st, S, w)) z2[y * (w + 1) + w] = 0.0;
         }
+        double dsq, nsq;
+        rel_change(S, z1, z2, x1, x2, &dsq, &nsq);
         double theta = 1.0 / sqrt(1.0 + 2.0 * P->gamma * tk);
         tk = theta * tk;
         sk = sk / theta;
@@ -321,7 +347,11 @@ static void local_cp2(const orc_state *st, orc_sub *S)
             xb2[e] = z2[e] + theta * (z2[e] - x2[e]);
             x2[e] = z2[e];
         }
+        taken = it + 1;
+        if (inner_converged(P, S, taken, dsq, nsq)) break;
     }
+    S->steps_total += taken;
+    if (taken > S->steps_max) S->steps_max = taken;
 }
 
 /* ------------------------------------------------------------------ */
