@@ -105,9 +105,8 @@ extern "C" {
                                 frame); each image's subdomains resident on the device at
                                 once, the images run in groups of launches.  CP2: every
                                 subdomain 128 x 128, or smaller with its short sides on the
-                                image boundary; inner_tol: every subdomain exactly 128 x 128.
-                                These two run every subdomain in one launch, all resident at
-                                once */
+                                image boundary.  CP2 and inner_tol run every subdomain in one
+                                launch, all resident at once */
 
 typedef struct dtv_dd_plan dtv_dd_plan; /* opaque, owned by the library */
 
@@ -164,13 +163,15 @@ typedef struct {
                                   (dtv_dd_status then returns DTV_EHIP); 0: the default (2^21,
                                   about 0.1 s) */
     double inner_tol;          /* > 0: adaptive local solves (Sec. 5.1 stops them by relative change):
-                                  each subdomain stops its FISTA steps in an outer step after the
-                                  first step k with |p_k - p_(k-1)|_2 < inner_tol |p_k|_2 over its
-                                  own edge dofs (or p_k = p_(k-1)), at most n_inner (the cap, <=
-                                  100000) steps; the norms are summed in FP64.  FISTA with the
-                                  fused or the persistent schedule (or auto, which picks
-                                  between them) only: every subdomain at most 128 x 128, no
-                                  save_for_backward.  0: fixed n_inner steps */
+                                  each subdomain stops its local steps (FISTA or primal-dual) in
+                                  an outer step after the first step k with |p_k - p_(k-1)|_2 <
+                                  inner_tol |p_k|_2 over its own edge dofs (or p_k = p_(k-1)), at
+                                  most n_inner (the cap, <= 100000) steps; the norms are summed in
+                                  FP64; the primal-dual state is then (p_k, u_k).  The fused or
+                                  the persistent schedule (or auto, which picks between them)
+                                  only: every subdomain at most 128 x 128 (FISTA), or 128 x 128
+                                  or smaller with its short sides on the image boundary (CP2);
+                                  no save_for_backward.  0: fixed n_inner steps */
 } dtv_dd_params;
 
 /* Where image `image` lives in the concatenated buffers (element offsets). */

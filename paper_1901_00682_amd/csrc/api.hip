@@ -98,6 +98,7 @@ struct dtv_dd_plan {
     std::vector<StreamTile> h_tiles[kRowChoices];  // streaming work lists, strips of 4 << ri rows
     std::vector<SubTile> h_subs;
     std::vector<float> h_beta;  // adaptive stopping: the FISTA momentum table (beta[k], k = 0 .. n_inner)
+    std::vector<float> h_cp2tab;  // adaptive stopping: the primal-dual step scalars (FusedCp2Args::tab)
     int n_full = 0;         // h_subs[0, n_full) are 128 x 128
     int n_framed = 0;       // h_subs[n_full, n_full + n_framed): framed (fused.hip), the rest any other
     // persistent FISTA schedule: the subdomains grouped by image into launches that fit on the device
@@ -136,6 +137,7 @@ struct dtv_dd_plan {
     bool fbwd = false;        // reverse mode with the fused kernels (every subdomain 128 x 128)
     bool adaptive = false;    // inner_tol > 0: the fused kernel stops each local solve by the relative-change rule
     size_t off_beta = 0, off_counts = 0;  // adaptive: momentum table, per-subdomain step counts
+    size_t off_cp2tab = 0;                // adaptive primal-dual: the step scalars
     int last_outer = 0;       // outer steps run by the last solve
     bool solved = false;      // a solve has run
     bool saved = false;       // the last solve saved its checkpoints
@@ -184,6 +186,7 @@ struct dtv_dd_plan {
     float *lamw() const { return (float *)(ws + off_lamw); }  // second lambda state (fused schedule)
     unsigned *sync_words() const { return (unsigned *)(ws + off_sync); }  // error flag of the persistent kernel
     float *beta_tab() const { return (float *)(ws + off_beta); }
+    const float *cp2_tab() const { return (const float *)(ws + off_cp2tab); }
     int *counts() const { return (int *)(ws + off_counts); }
     const int *run_counts() const { return (const int *)(run_ws + off_counts); }
     const unsigned *run_sync_words() const { return (const unsigned *)(run_ws + off_sync); }
@@ -210,6 +213,31 @@ static bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
 static std::vector<float> fista_betas(int K);
 
+// Step sizes of the local accelerated primal-dual method (Chambolle-Pock Alg. 2, Sec. 5): step
+// k + 1 uses tau_k = tk[k], sigma_k = sk[k] and the extrapolation theta_k = th[k], with
+// theta_k = 1/sqrt(1 + 2 gamma tau_k), tau_(k+1) = theta_k tau_k, sigma_(k+1) = sigma_k / theta_k,
+// reset to (tau0, sigma0) every outer step; computed in double precision.
+static void cp2_steps(const dtv_dd_params &P, int K, std::vector<double> &tk, std::vector<double> &sk,
+                      std::vector<double> &th)
+{
+    tk.assign(K + 1, 0.0);
+    sk.assign(K + 1, 0.0);
+    th.assign(K + 1, 0.0);
+    double a = P.tau0, b = P.sigma0;
+    for (int it = 0; it < K; ++it) {
+        tk[it] = a;
+        sk[it] = b;
+        th[it] = 1.0 / std::sqrt(1.0 + 2.0 * P.gamma * a);
+        a *= th[it];
+        b /= th[it];
+    }
+}
+
+// the weights of the local dual update: tau / (tau + tau_k) on x - tau_k div^* u and
+// tau_k / (tau + tau_k) on the anchor (1 and 0 without the proximal term)
+static float cp2_keep(const dtv_dd_params &P, double tk) { return P.full_problem ? 1.0f : (float)(P.tau / (P.tau + tk)); }
+static float cp2_anchor(const dtv_dd_params &P, double tk) { return P.full_problem ? 0.0f : (float)(tk / (P.tau + tk)); }
+
 static bool any_of_sched(int requested, int sched) { return requested == DTV_SCHED_AUTO || requested == sched; }
 
 // How the full-tile step runs a subdomain: 0 a full 128 x 128 tile; 1 a framed tile (smaller, each
@@ -230,7 +258,7 @@ static std::vector<Choice> candidates(const dtv_dd_plan *pl)
 {
     const dtv_dd_params &p = pl->prm;
     std::vector<Choice> c;
-    if (pl->adaptive) {  // the stopping rule lives in the fused and persistent FISTA kernels
+    if (pl->adaptive) {  // the stopping rule lives in the fused and persistent kernels
         if ((any_of_sched(p.schedule, DTV_SCHED_PERSIST)) && pl->persist_ok) c.push_back({DTV_SCHED_PERSIST, pl->rows});
         if (any_of_sched(p.schedule, DTV_SCHED_FUSED)) c.push_back({DTV_SCHED_FUSED, pl->rows});
         return c;
@@ -294,9 +322,8 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
     }
     if (full && p.save_for_backward) return fail(DTV_EINVAL, "full_problem takes no save_for_backward");
     if (!(p.inner_tol >= 0.0) || !std::isfinite(p.inner_tol)) return fail(DTV_EINVAL, "inner_tol must be finite and >= 0");
-    if (p.inner_tol > 0.0 && (p.inner != DTV_INNER_FISTA || p.save_for_backward || p.schedule == DTV_SCHED_STREAM))
-        return fail(DTV_EINVAL, "inner_tol needs FISTA, the fused or persistent schedule (or auto) and no "
-                                "save_for_backward");
+    if (p.inner_tol > 0.0 && (p.save_for_backward || p.schedule == DTV_SCHED_STREAM))
+        return fail(DTV_EINVAL, "inner_tol needs the fused or persistent schedule (or auto) and no save_for_backward");
     if (p.inner_tol > 0.0 && p.n_inner > kMaxAdaptiveInner)
         return fail(DTV_EINVAL, "inner_tol: n_inner (the cap) must be <= 100000");
     if (full)
@@ -414,18 +441,27 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
         pl->n_framed += is_framed(st);
     }
     pl->adaptive = p.inner_tol > 0.0;
-    if (pl->adaptive) pl->h_beta = fista_betas(p.n_inner);
+    if (pl->adaptive && p.inner == DTV_INNER_FISTA) pl->h_beta = fista_betas(p.n_inner);
+    if (pl->adaptive && p.inner == DTV_INNER_CP2) {
+        std::vector<double> tk, sk, th;
+        cp2_steps(p, p.n_inner, tk, sk, th);
+        for (int it = 0; it < p.n_inner; ++it) {
+            const float v[5] = {(float)tk[it], (float)sk[it], (float)th[it], cp2_keep(p, tk[it]), cp2_anchor(p, tk[it])};
+            pl->h_cp2tab.insert(pl->h_cp2tab.end(), v, v + 5);
+        }
+    }
     if (p.inner == DTV_INNER_FISTA) {
         pl->fused_ok = p.n_inner <= kMaxFusedInner || pl->adaptive;
         for (const SubTile &st : pl->h_subs)
             if (st.h > kFusedMax || st.w > kFusedMax) pl->fused_ok = false;
     } else {  // the fused primal-dual kernel takes 128 x 128 subdomains and framed ones
-        pl->fused_ok = p.n_inner <= kMaxFusedInner && !pl->h_subs.empty() &&
+        pl->fused_ok = (p.n_inner <= kMaxFusedInner || pl->adaptive) && !pl->h_subs.empty() &&
                        pl->n_full + pl->n_framed == (int)pl->h_subs.size();
     }
     if (pl->adaptive && !pl->fused_ok) {
         delete pl;
-        return fail(DTV_EINVAL, "inner_tol needs subdomains of at most 128 x 128 (the fused schedule)");
+        return fail(DTV_EINVAL, "inner_tol needs the fused schedule's subdomains: at most 128 x 128 (FISTA), or "
+                                "128 x 128 or smaller with their short sides on the image boundary (CP2)");
     }
     if (p.schedule == DTV_SCHED_FUSED && !pl->fused_ok) {
         delete pl;
@@ -442,7 +478,7 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
         const bool fista = p.inner == DTV_INNER_FISTA;
         const bool one_launch = !fista || pl->adaptive;
         pl->persist_ok = pl->fused_ok && nsub > 0 && p.diag_every == 0 && !p.save_for_backward &&
-                         (pl->n_full == nsub || !one_launch || (!fista && pl->n_full + pl->n_framed == nsub));
+                         (fista || pl->n_full + pl->n_framed == nsub);
         int dev = 0;
         if (pl->persist_ok && hipGetDevice(&dev) == hipSuccess && persist_supported(dev)) {
             const int cap = fista ? persist_capacity(dev) : persist_cp2_capacity(dev);
@@ -508,8 +544,9 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
     pl->off_xch = take(pl->persist_ok ? sizeof(unsigned long long) * 2 * (size_t)pl->tot_lam : 0);
     pl->off_sync = take(2 * sizeof(unsigned));
     pl->off_lamw = take(persist_only ? 0 : sizeof(float) * (size_t)pl->tot_lam);
-    pl->off_beta = take(pl->adaptive ? sizeof(float) * (size_t)(p.n_inner + 1) : 0);
+    pl->off_beta = take(sizeof(float) * pl->h_beta.size());
     pl->off_counts = take(pl->adaptive ? sizeof(int) * 2 * pl->h_subs.size() : 0);
+    pl->off_cp2tab = take(sizeof(float) * pl->h_cp2tab.size());
     if (p.save_for_backward) {
         const size_t E = (size_t)(pl->tot_p1 + pl->tot_p2);
         pl->state_floats = E + (size_t)pl->tot_lam;
@@ -604,9 +641,13 @@ extern "C" int dtv_dd_bind_workspace(dtv_dd_plan *pl, void *d_ws, size_t bytes)
             "upload image descriptors");
     HIP_TRY(hipMemcpy(ws + pl->off_info, pl->h_info.data(), sizeof(int) * pl->h_info.size(), hipMemcpyHostToDevice),
             "upload info words");
-    if (pl->adaptive)
+    if (!pl->h_beta.empty())
         HIP_TRY(hipMemcpy(ws + pl->off_beta, pl->h_beta.data(), sizeof(float) * pl->h_beta.size(), hipMemcpyHostToDevice),
                 "upload momentum table");
+    if (!pl->h_cp2tab.empty())
+        HIP_TRY(hipMemcpy(ws + pl->off_cp2tab, pl->h_cp2tab.data(), sizeof(float) * pl->h_cp2tab.size(),
+                          hipMemcpyHostToDevice),
+                "upload primal-dual step table");
     for (int ri = 0; ri < kRowChoices; ++ri)
         HIP_TRY(hipMemcpy(ws + pl->off_tiles[ri], pl->h_tiles[ri].data(), sizeof(StreamTile) * pl->h_tiles[ri].size(),
                           hipMemcpyHostToDevice),
@@ -784,17 +825,8 @@ static int solve_impl(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_mask, 
 
     // step parameters, computed in double precision on the host
     const std::vector<float> beta = fista_betas(K);  // FISTA momentum of step k (1-based); 0 for k = 1, 2
-    std::vector<double> tk(K + 1), sk(K + 1), th(K + 1);
-    {
-        double a = P.tau0, b = P.sigma0;
-        for (int it = 0; it < K; ++it) {
-            tk[it] = a;
-            sk[it] = b;
-            th[it] = 1.0 / std::sqrt(1.0 + 2.0 * P.gamma * a);
-            a *= th[it];
-            b /= th[it];
-        }
-    }
+    std::vector<double> tk, sk, th;
+    cp2_steps(P, K, tk, sk, th);
 
     // edge buffers: 0 = the caller's p~, 1..3 = workspace
     EdgeBuf bufs[4] = {{d_p1, d_p2}, {pl->buf1(0), pl->buf2(0)}, {pl->buf1(1), pl->buf2(1)}, {pl->buf1(2), pl->buf2(2)}};
@@ -875,8 +907,14 @@ static int solve_impl(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_mask, 
             ca.tk[it] = (float)tk[it];
             ca.sk[it] = (float)sk[it];
             ca.th[it] = (float)th[it];
-            ca.ck[it] = P.full_problem ? 1.0f : (float)(P.tau / (P.tau + tk[it]));
-            ca.ca[it] = P.full_problem ? 0.0f : (float)(tk[it] / (P.tau + tk[it]));
+            ca.ck[it] = cp2_keep(P, tk[it]);
+            ca.ca[it] = cp2_anchor(P, tk[it]);
+        }
+        if (pl->adaptive) {  // the cap may exceed the argument tables: the scalars come from the workspace
+            ca.n_inner = K;
+            ca.tol2 = P.inner_tol * P.inner_tol;
+            ca.tab = pl->cp2_tab();
+            ca.counts = pl->counts();
         }
         return ca;
     };
@@ -969,8 +1007,8 @@ static int solve_impl(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_mask, 
                 a.out1 = bufs[io].p1; a.out2 = bufs[io].p2;
                 a.theta_prev = it >= 1 ? (float)th[it - 1] : 0.0f;
                 a.sk = (float)sk[it]; a.tk = (float)tk[it]; a.tau = (float)P.tau;
-                a.c_keep = P.full_problem ? 1.0f : (float)(P.tau / (P.tau + tk[it]));
-                a.c_anchor = P.full_problem ? 0.0f : (float)(tk[it] / (P.tau + tk[it]));
+                a.c_keep = cp2_keep(P, tk[it]);
+                a.c_anchor = cp2_anchor(P, tk[it]);
                 a.fidelity = P.fidelity;
                 a.cv_c1 = (float)P.cv_c1;
                 a.cv_c2 = (float)P.cv_c2;
@@ -1551,10 +1589,14 @@ static int upload_async(dtv_dd_plan *pl, char *ws, hipStream_t s)
     HIP_TRY(hipMemcpyAsync(ws + pl->off_info, pl->h_info.data(), sizeof(int) * pl->h_info.size(), hipMemcpyHostToDevice,
                            s),
             "upload info words");
-    if (pl->adaptive)
+    if (!pl->h_beta.empty())
         HIP_TRY(hipMemcpyAsync(ws + pl->off_beta, pl->h_beta.data(), sizeof(float) * pl->h_beta.size(),
                                hipMemcpyHostToDevice, s),
                 "upload momentum table");
+    if (!pl->h_cp2tab.empty())
+        HIP_TRY(hipMemcpyAsync(ws + pl->off_cp2tab, pl->h_cp2tab.data(), sizeof(float) * pl->h_cp2tab.size(),
+                               hipMemcpyHostToDevice, s),
+                "upload primal-dual step table");
     for (int ri = 0; ri < kRowChoices; ++ri)
         HIP_TRY(hipMemcpyAsync(ws + pl->off_tiles[ri], pl->h_tiles[ri].data(), sizeof(StreamTile) * pl->h_tiles[ri].size(),
                                hipMemcpyHostToDevice, s),

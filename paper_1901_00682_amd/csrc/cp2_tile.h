@@ -19,6 +19,13 @@
 //
 // The per-element arithmetic is that of the streaming kernel (cp2_ops.h), so
 // all schedules give bitwise identical results.
+//
+// Adaptive stopping (the inner rule of Sec. 5.1): after step k the tile sums
+// |x_k - x_(k-1)|^2 and |x_k|^2 over its edges (FP32 per thread, then FP64
+// over the workgroup in a fixed order) and stops when the first is below
+// tol^2 times the second.  Step k has already formed u_(k+1) one row behind
+// the x update, so u_k is written to the tile's own pixels of the u buffer at
+// the start of the step (no other tile reads them) and read back on a stop.
 #pragma once
 
 #include "cp2_ops.h"
@@ -36,6 +43,7 @@ struct Cp2Lds {
     float rx[kFusedMax];              // right boundary edges: x_k (per row)
     float rxb[kFusedMax];             // right boundary edges: xbar_k (per row)
     float uR[kFusedMax];              // u of the last column (per row)
+    double red[2 * kWaves];           // adaptive stopping: per-wave sums of the relative-change test
     float ut[kWaves][kFusedMax];      // u of each strip's last row
     float xt[kWaves][kFusedMax];      // xbar of the top edges of each strip's first row
     float a1[kFusedMax][kFusedMax];   // anchor of the edge above pixel (il, jl)
@@ -78,21 +86,56 @@ struct Cp2Ctx {
     // are the tile's bottom boundary (bit r: row 8 s + r)
     float lo2b, hi2b;
     unsigned zrows;
+    // adaptive stopping: the tile's pixels in the u buffer (row pitch W), its extent (h x w)
+    float *u_tile;
+    int W, h, w;
 };
+
+// u of the thread's pixels inside the tile to / from the u buffer (adaptive stopping)
+template <bool FR>
+__device__ __forceinline__ void save_u(const Cp2Ctx &c, const float (&ua)[kR], const float (&ub)[kR])
+{
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+        const int il = c.il0 + r;
+        float *p = c.u_tile + (long long)il * c.W + c.ja;
+        if (!FR || (il < c.h && c.jb < c.w)) st2g(p, ua[r], ub[r]);
+        else if (il < c.h && c.ja < c.w) p[0] = ua[r];
+    }
+}
+
+template <bool FR>
+__device__ __forceinline__ void load_u(const Cp2Ctx &c, float (&ua)[kR], float (&ub)[kR])
+{
+    // volatile: past the vector L1, which may hold the values of an earlier outer step
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+        const int il = c.il0 + r;
+        volatile const float *p = c.u_tile + (long long)il * c.W + c.ja;
+        if (!FR || (il < c.h && c.jb < c.w)) {
+            ua[r] = p[0];
+            ub[r] = p[1];
+        } else if (il < c.h && c.ja < c.w) {
+            ua[r] = p[0];
+        }
+    }
+}
 
 // The n_inner steps of one outer step from x_0 (X, and the right boundary
 // column in S.rx) and u_0, with the anchors in S.a1, a2, ab, ar (written by
 // every thread before the call; the first barrier here orders them).  On
-// return X, S.rx and (ua, ub) hold x_K and u_K.
+// return X, S.rx and (ua, ub) hold x_K and u_K.  ADAPT: at most n_inner steps,
+// the step scalars from a.tab, stopping by the relative-change rule; returns
+// the steps taken (n_inner without ADAPT).
 // FR: a framed tile, its h x w pixels at the top left of the frame and its short sides on the
 // image boundary.  Outside the tile x, u, f and the anchors start at 0; the top edges of row h and
 // the left edges of column w are clamped to 0 like other image-boundary edges, so no value
 // outside reaches the tile's edges and pixels (the pixels outside may move, bounded, under the
 // Chan-Vese prox, which is not zero at f = 0).
-template <int FID, bool FR = false>
-__device__ __forceinline__ void solve(const Cp2Ctx &c, Cp2Lds &S, Slot &X, float (&ua)[kR], float (&ub)[kR],
-                                      const float (&fa)[kR], const float (&fb)[kR], unsigned obs,
-                                      const FusedCp2Args &a)
+template <int FID, bool FR = false, bool ADAPT = false>
+__device__ __forceinline__ int solve(const Cp2Ctx &c, Cp2Lds &S, Slot &X, float (&ua)[kR], float (&ub)[kR],
+                                     const float (&fa)[kR], const float (&fb)[kR], unsigned obs,
+                                     const FusedCp2Args &a)
 {
     const int s = c.s, lane = c.lane, ja = c.ja, jb = c.jb, il0 = c.il0;
     const bool last = c.last, bot_bnd = c.bot_bnd, right_bnd = c.right_bnd;
@@ -109,7 +152,7 @@ __device__ __forceinline__ void solve(const Cp2Ctx &c, Cp2Lds &S, Slot &X, float
 
     // ---- u_1 = prox(u_0 + sigma_1 div x_0)
     {
-        const float sk = a.sk[0], sa = sk * alpha;
+        const float sk = ADAPT ? a.tab[1] : a.sk[0], sa = sk * alpha;
 #pragma unroll
         for (int r = 0; r < kR; ++r) {
             float ba_ = 0.0f, bb_ = 0.0f;
@@ -130,10 +173,27 @@ __device__ __forceinline__ void solve(const Cp2Ctx &c, Cp2Lds &S, Slot &X, float
     }
 
     // ---- the K steps
+    int taken = K;
     for (int k = 1; k <= K; ++k) {
-        const float tk = a.tk[k - 1], ck = a.ck[k - 1], ca = a.ca[k - 1], th = a.th[k - 1];
+        float tk, ck, ca, th;
+        if constexpr (ADAPT) {
+            const float *tb = a.tab + 5 * (k - 1);
+            tk = tb[0];
+            th = tb[2];
+            ck = tb[3];
+            ca = tb[4];
+        } else {
+            tk = a.tk[k - 1];
+            ck = a.ck[k - 1];
+            ca = a.ca[k - 1];
+            th = a.th[k - 1];
+        }
         const bool ext = k < K;  // u_(k+1) is needed
-        const float skn = ext ? a.sk[k] : 0.0f, san = skn * alpha;
+        const float skn = ext ? (ADAPT ? a.tab[5 * k + 1] : a.sk[k]) : 0.0f, san = skn * alpha;
+        float dd = 0.0f, nn = 0.0f;  // adaptive: |x_k - x_(k-1)|^2, |x_k|^2 over the thread's edges
+        if constexpr (ADAPT) {
+            if (ext) save_u<FR>(c, ua, ub);  // u_k, in case the rule stops after this step
+        }
         // (A) publish u_k of the strip's last row (for the strip below) and of the last column
         if (!last) lds_st2(&S.ut[s][ja], ua[kR - 1], ub[kR - 1]);
         if (lane == 63)
@@ -148,6 +208,7 @@ __device__ __forceinline__ void solve(const Cp2Ctx &c, Cp2Lds &S, Slot &X, float
             const float xn = right_bnd ? xo : clamp1(cp2_pre(xo, S.uR[il], S.ar[il], tk, ck, ca));
             S.rx[il] = xn;
             S.rxb[il] = fmaf(th, xn - xo, xn);
+            if constexpr (ADAPT) conv_acc(xn, xo, dd, nn);
         }
         // row sweep: x_k on the row's edges, xbar_k, and one row behind, u_(k+1)
         float uua = 0.0f, uub = 0.0f;  // u_k of the row above (0 above the tile: one-sided copy)
@@ -178,6 +239,15 @@ __device__ __forceinline__ void solve(const Cp2Ctx &c, Cp2Lds &S, Slot &X, float
             X.e1b[r] = n1b;
             X.e2a[r] = n2a;
             X.e2b[r] = n2b;
+            if constexpr (ADAPT) {
+                conv_acc(n1a, o1a, dd, nn);
+                conv_acc(n1b, o1b, dd, nn);
+                conv_acc(n2a, o2a, dd, nn);
+                conv_acc(n2b, o2b, dd, nn);
+                // the sums are formed here, row by row: left to the compiler they are deferred and
+                // keep every row's old and new values alive (register spills)
+                asm volatile("" : "+v"(dd), "+v"(nn));
+            }
             if (ext) {
                 const float b1a = fmaf(th, n1a - o1a, n1a), b1b = fmaf(th, n1b - o1b, n1b);
                 const float b2a = fmaf(th, n2a - o2a, n2a), b2b = fmaf(th, n2b - o2b, n2b);
@@ -205,6 +275,10 @@ __device__ __forceinline__ void solve(const Cp2Ctx &c, Cp2Lds &S, Slot &X, float
             X.bb = clamp1(cp2_pre(obb, ub[kR - 1], S.ab[jb], tk, ck, ca));
             bxa = fmaf(th, X.ba - oba, X.ba);
             bxb = fmaf(th, X.bb - obb, X.bb);
+            if constexpr (ADAPT) {
+                conv_acc(X.ba, oba, dd, nn);
+                conv_acc(X.bb, obb, dd, nn);
+            }
         }
         if (ext) {
             __syncthreads();
@@ -215,8 +289,19 @@ __device__ __forceinline__ void solve(const Cp2Ctx &c, Cp2Lds &S, Slot &X, float
             div_pair(pta, ptb, ba_, bb_, pla, plb, S.rxb[il0 + kR - 1], da, db);
             ua[kR - 1] = cp2_u(fid, ua[kR - 1], da, skn, fa[kR - 1], observed(2 * kR - 2), san, cv1, cv2);
             ub[kR - 1] = cp2_u(fid, ub[kR - 1], db, skn, fb[kR - 1], observed(2 * kR - 1), san, cv1, cv2);
+            if constexpr (ADAPT) {
+                // the decision is the same in every thread (one FP64 sum in a fixed order)
+                if (block_converged(s, lane, dd, nn, a.tol2, S.red)) {
+                    taken = k;
+                    break;
+                }
+            }
         }
     }
+    if constexpr (ADAPT) {
+        if (taken < K) load_u<FR>(c, ua, ub);  // back to u_k: the state of the last step taken
+    }
+    return taken;
 }
 
 }  // namespace cp2tile

@@ -153,6 +153,12 @@ struct FusedCp2Args {
     int frames;                // fused kernel: some subdomains are framed (smaller than 128 x 128,
                                // their short sides on the image boundary)
     float tk[kMaxFusedInner], sk[kMaxFusedInner], th[kMaxFusedInner], ck[kMaxFusedInner], ca[kMaxFusedInner];
+    // adaptive inner stopping (tol2 > 0): up to n_inner steps per subdomain with the step scalars
+    // of step k + 1 in device memory, tab[5 k .. 5 k + 4] = tk, sk, th, ck, ca (k < n_inner), and
+    // per-subdomain [total steps, most steps in one outer step] in counts
+    double tol2;
+    const float *tab;
+    int *counts;
 };
 
 // Persistent primal-dual schedule (persist_cp2.hip): every outer step in one cooperative launch,

@@ -18,8 +18,8 @@ using namespace cp2tile;
 
 // FID: the fidelity (0 L2, 1 L1, 2 convex Chan-Vese); MASK: an inpainting mask is given;
 // FR: some subdomains are framed tiles (every tile then takes the framed path, which on a
-// 128 x 128 tile does what the full-tile path does)
-template <int FID, bool MASK, bool FR>
+// 128 x 128 tile does what the full-tile path does); ADAPT: adaptive stopping (cp2_tile.h)
+template <int FID, bool MASK, bool FR, bool ADAPT = false>
 __global__ __launch_bounds__(1024) void k_fused_cp2(FusedCp2Args a)
 {
     __shared__ Cp2Lds S;
@@ -221,7 +221,18 @@ __global__ __launch_bounds__(1024) void k_fused_cp2(FusedCp2Args a)
         cx.bot_bnd = bot_bnd || h < kFusedMax;
         cx.right_bnd = right_bnd || w < kFusedMax;
     }
-    solve<FID, FR>(cx, S, X, ua, ub, fa, fb, obs, a);
+    cx.u_tile = u_tile;
+    cx.W = W;
+    cx.h = h;
+    cx.w = w;
+    const int taken = solve<FID, FR, ADAPT>(cx, S, X, ua, ub, fa, fb, obs, a);
+    if constexpr (ADAPT) {
+        if (threadIdx.x == 0) {  // the subdomain's only workgroup of this launch
+            int *cnt = a.counts + 2 * (long long)t;
+            cnt[0] += taken;
+            cnt[1] = max(cnt[1], taken);
+        }
+    }
 
     // ---- store x_K as p~^(n+1) and u_K
 #pragma unroll
@@ -248,7 +259,9 @@ namespace {
 template <int FID, bool MASK>
 hipError_t launch_cp2_variant(const FusedCp2Args &a, int nsub, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
-    auto k = a.frames ? k_fused_cp2<FID, MASK, true> : k_fused_cp2<FID, MASK, false>;
+    const bool adapt = a.tol2 > 0.0;
+    auto k = a.frames ? (adapt ? k_fused_cp2<FID, MASK, true, true> : k_fused_cp2<FID, MASK, true, false>)
+                      : (adapt ? k_fused_cp2<FID, MASK, false, true> : k_fused_cp2<FID, MASK, false, false>);
     if (e0)
         hipExtLaunchKernelGGL(k, dim3(nsub), dim3(1024), 0, s, e0, e1, 0, a);
     else
@@ -261,7 +274,9 @@ hipError_t launch_cp2_variant(const FusedCp2Args &a, int nsub, hipStream_t s, hi
 hipError_t launch_fused_cp2(const FusedCp2Args &a, int nsub, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     if (nsub <= 0) return hipSuccess;
-    if (a.n_inner < 1 || a.n_inner > kMaxFusedInner) return hipErrorInvalidValue;
+    const bool adapt = a.tol2 > 0.0;
+    if (a.n_inner < 1 || a.n_inner > (adapt ? kMaxAdaptiveInner : kMaxFusedInner)) return hipErrorInvalidValue;
+    if (adapt && (!a.tab || !a.counts)) return hipErrorInvalidValue;
     // p~^(n+1) and the new lambda state go to buffers of their own: other tiles read p~^n and
     // lambda^n (without interfaces there is no lambda state)
     if (!a.out1 || !a.out2 || a.out1 == a.p1 || a.out2 == a.p2 || (a.lam && a.lam_out == a.lam))

@@ -68,7 +68,7 @@ __device__ __forceinline__ void st2g(float *p, float x, float y)
 
 // The whole solve of subdomain t.  KF > 0: n_inner = KF (steps unrolled); KF = 0: any n_inner.
 // ADAPT (KF = 0): each local solve stops by the relative-change rule (fused_common.h,
-// a.fa.tol2, cap n_inner); the steps taken are counted per subdomain.  FR: a framed tile, smaller
+// a.fa.tol2, cap n_inner), full or framed tiles; the steps taken are counted per subdomain.  FR: a framed tile, smaller
 // than 128 x 128 (full_step<.., FR> in a 128 x 128 frame, with p~ and f zero outside the tile):
 // FR = 1 with its short sides on the image boundary, FR = 2 for any tile, whose bottom edges then
 // lie in frame row h and its right edges in frame column w, interface copies or not.
@@ -196,6 +196,17 @@ __device__ __forceinline__ void persist_tile(const PersistArgs &a, PersistLds &L
         if (lane == 0)
 #pragma unroll
             for (int r = 0; r < kR; ++r) S.c2[il0 + r][0] = 0.0f;
+    }
+    if constexpr (FR != 0) {
+        // c' of the frame's right column below the tile and of its bottom row right of the tile: the
+        // rebuild below never writes them when the tile's side there is an interface (it writes the
+        // tile's own copies only).  At 0 the edges there stay 0: they cannot reach the tile either
+        // way, but the stopping rule sums every edge of the frame.
+        if (lane < kR && il0 + lane >= h) S.cr[il0 + lane] = 0.0f;
+        if (s == 0) {
+            if (ja >= w) S.cb[ja] = 0.0f;
+            if (ja + 1 >= w) S.cb[ja + 1] = 0.0f;
+        }
     }
     int rx_slot = 0;  // LDS slot of the right boundary column holding the current iterate
     bool ok = true;
@@ -343,7 +354,12 @@ __device__ __forceinline__ void persist_tile(const PersistArgs &a, PersistLds &L
         // ---- (5) the local FISTA solves
         if constexpr (ADAPT) {
             int taken = 0;
-            rx_slot = run_steps_adaptive<FullStep>(fc, S, A, B, a.fa.n_inner, a.fa.beta_dev, a.fa.tol2, L.red, taken);
+            if constexpr (FR)
+                rx_slot = run_steps_adaptive<FramedStep<FR>>(fc, S, A, B, a.fa.n_inner, a.fa.beta_dev, a.fa.tol2, L.red,
+                                                             taken);
+            else
+                rx_slot = run_steps_adaptive<FullStep>(fc, S, A, B, a.fa.n_inner, a.fa.beta_dev, a.fa.tol2, L.red,
+                                                       taken);
             steps_total += taken;
             steps_max = max(steps_max, taken);
         } else if constexpr (KF > 0) {
@@ -463,8 +479,11 @@ hipError_t launch_persist_fista(const PersistArgs &a, int nsub, int frames, hipS
     if (adapt && (!a.fa.beta_dev || !a.fa.counts)) return hipErrorInvalidValue;
     PersistArgs arg = a;
     void *args[] = {&arg};
-    if (frames < 0 || frames > 2 || (adapt && frames)) return hipErrorInvalidValue;  // adaptive: 128 x 128 only
-    const PersistKernel k = adapt ? k_persist_fista<0, true> : Persist::get(a.fa.n_inner, frames);
+    if (frames < 0 || frames > 2) return hipErrorInvalidValue;
+    const PersistKernel k = !adapt ? Persist::get(a.fa.n_inner, frames)
+                            : frames == 2 ? k_persist_fista<0, true, 2>
+                            : frames == 1 ? k_persist_fista<0, true, 1>
+                                          : k_persist_fista<0, true, 0>;
     return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k), dim3(nsub), dim3(1024), args, 0, s);
 }
 

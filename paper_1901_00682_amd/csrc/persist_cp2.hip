@@ -41,8 +41,10 @@ struct PersistCp2Lds {
 
 // FID: the fidelity (0 L2, 1 L1, 2 convex Chan-Vese); MASK: an inpainting mask is given
 // FR: some subdomains are framed tiles (smaller than 128 x 128, their short sides on the image
-// boundary, run in a 128 x 128 frame as in the fused kernel); every tile then takes that path
-template <int FID, bool MASK, bool FR = false>
+// boundary, run in a 128 x 128 frame as in the fused kernel); every tile then takes that path.
+// ADAPT: every local solve stops by the relative-change rule (cp2_tile.h); the steps taken are
+// counted per subdomain.
+template <int FID, bool MASK, bool FR = false, bool ADAPT = false>
 __global__ __launch_bounds__(1024) void k_persist_cp2(PersistCp2Args pa)
 {
     __shared__ PersistCp2Lds L;
@@ -103,6 +105,11 @@ __global__ __launch_bounds__(1024) void k_persist_cp2(PersistCp2Args pa)
         cx.bot_bnd = bot_bnd || h < kFusedMax;
         cx.right_bnd = right_bnd || w < kFusedMax;
     }
+    cx.u_tile = u_tile;
+    cx.W = W;
+    cx.h = h;
+    cx.w = w;
+    int steps_total = 0, steps_max = 0;  // adaptive stopping: local steps of this subdomain
 
     // side work (multiplier update): waves 0..7, side = wave / 2 (wave-uniform), edge
     // si = 64 (wave % 2) + lane; the lambda index is side_base + si
@@ -238,7 +245,11 @@ __global__ __launch_bounds__(1024) void k_persist_cp2(PersistCp2Args pa)
         if (!ok) break;  // a neighbour stopped publishing: leave (the host reports the error)
 
         // ---- (5) the local primal-dual solve
-        solve<FID, FR>(cx, S, X, ua, ub, fa, fb, obs, a);
+        const int taken = solve<FID, FR, ADAPT>(cx, S, X, ua, ub, fa, fb, obs, a);
+        if constexpr (ADAPT) {
+            steps_total += taken;
+            steps_max = max(steps_max, taken);
+        }
     }
 
     // ---- store p~^N, u and the lambda state (lambda^N and the copies of the last multiplier update)
@@ -261,6 +272,13 @@ __global__ __launch_bounds__(1024) void k_persist_cp2(PersistCp2Args pa)
     else if (FR && last && h == kFusedMax && ja < w) p1_tile[(long long)kFusedMax * P1 + ja] = X.ba;
     if (lane < kR && (!FR || (w == kFusedMax && il0 + lane < h)))
         p2_tile[(long long)(il0 + lane) * P2 + kFusedMax] = S.rx[il0 + lane];
+    if constexpr (ADAPT) {
+        if (threadIdx.x == 0) {  // the subdomain's only workgroup (one launch holds every subdomain)
+            int *cnt = a.counts + 2 * (long long)t;
+            cnt[0] += steps_total;
+            cnt[1] = max(cnt[1], steps_max);
+        }
+    }
     if (side_wave && ok) {
         const int si = (s & 1) * 64 + lane;
         float *ls = pa.lam_out + im.lam + side_base;
@@ -277,20 +295,22 @@ namespace {
 
 using PersistCp2Kernel = void (*)(PersistCp2Args);
 
-template <bool FR>
+template <bool FR, bool AD>
 PersistCp2Kernel persist_cp2_variant(int fidelity, bool mask)
 {
     switch (fidelity) {
-    case 0: return mask ? k_persist_cp2<0, true, FR> : k_persist_cp2<0, false, FR>;
-    case 1: return mask ? k_persist_cp2<1, true, FR> : k_persist_cp2<1, false, FR>;
-    case 2: return mask ? nullptr : k_persist_cp2<2, false, FR>;
+    case 0: return mask ? k_persist_cp2<0, true, FR, AD> : k_persist_cp2<0, false, FR, AD>;
+    case 1: return mask ? k_persist_cp2<1, true, FR, AD> : k_persist_cp2<1, false, FR, AD>;
+    case 2: return mask ? nullptr : k_persist_cp2<2, false, FR, AD>;
     default: return nullptr;
     }
 }
 
-PersistCp2Kernel persist_cp2_kernel(int fidelity, bool mask, bool frames)
+PersistCp2Kernel persist_cp2_kernel(int fidelity, bool mask, bool frames, bool adapt)
 {
-    return frames ? persist_cp2_variant<true>(fidelity, mask) : persist_cp2_variant<false>(fidelity, mask);
+    if (adapt)
+        return frames ? persist_cp2_variant<true, true>(fidelity, mask) : persist_cp2_variant<false, true>(fidelity, mask);
+    return frames ? persist_cp2_variant<true, false>(fidelity, mask) : persist_cp2_variant<false, false>(fidelity, mask);
 }
 
 }  // namespace
@@ -307,8 +327,10 @@ int persist_cp2_capacity(int device)
 hipError_t launch_persist_cp2(const PersistCp2Args &a, int nsub, hipStream_t s)
 {
     if (nsub <= 0 || a.n_outer <= 0) return hipSuccess;
-    if (a.ca.n_inner < 1 || a.ca.n_inner > kMaxFusedInner) return hipErrorInvalidValue;
-    const PersistCp2Kernel k = persist_cp2_kernel(a.ca.fidelity, a.ca.mask != nullptr, a.ca.frames != 0);
+    const bool adapt = a.ca.tol2 > 0.0;
+    if (a.ca.n_inner < 1 || a.ca.n_inner > (adapt ? kMaxAdaptiveInner : kMaxFusedInner)) return hipErrorInvalidValue;
+    if (adapt && (!a.ca.tab || !a.ca.counts)) return hipErrorInvalidValue;
+    const PersistCp2Kernel k = persist_cp2_kernel(a.ca.fidelity, a.ca.mask != nullptr, a.ca.frames != 0, adapt);
     if (!k) return hipErrorInvalidValue;
     PersistCp2Args arg = a;
     void *args[] = {&arg};

@@ -94,9 +94,9 @@ def test_valid_setup_and_layout():
     (dict(full_problem=1, rc=(0, 64), cc=(0, 64), save_for_backward=1), "save_for_backward"),
     (dict(full_problem=1, rc=(0, 64), cc=(0, 64), inner=1, gamma=-1.0), "gamma"),
     (dict(inner_tol=-1.0), "inner_tol"),
-    (dict(inner_tol=1e-3, inner=1), "inner_tol needs FISTA"),
-    (dict(inner_tol=1e-3, schedule=1), "inner_tol needs FISTA"),
-    (dict(inner_tol=1e-3, save_for_backward=1), "inner_tol needs FISTA"),
+    (dict(inner_tol=1e-3, inner=1), "inner_tol needs the fused schedule's subdomains"),
+    (dict(inner_tol=1e-3, schedule=1), "inner_tol needs the fused or persistent"),
+    (dict(inner_tol=1e-3, save_for_backward=1), "inner_tol needs the fused or persistent"),
     (dict(inner_tol=1e-3, H=300, W=300, rc=(0, 150, 300), cc=(0, 150, 300)), "at most 128"),
     (dict(inner_tol=1e-3, n_inner=100001), "cap"),
     (dict(spin_limit=-1), "spin_limit"),
