@@ -38,6 +38,8 @@ KERNEL_SOURCES = {
     "k_fused_cp2": ["fused_cp2.hip", "cp2_tile.h", "cp2_ops.h", "fused_common.h", "fista_ops.h", "dtvdd_internal.h"],
     "k_persist_cp2": ["persist_cp2.hip", "cp2_tile.h", "cp2_ops.h", "exchange.h", "fused_common.h", "fista_ops.h",
                       "dtvdd_internal.h"],
+    "k_fused_bwd": ["fused_bwd.hip", "fused_common.h", "fista_ops.h", "dtvdd_internal.h"],
+    "k_fused_fista_rec": ["fused.hip", "fused_common.h", "fista_ops.h", "dtvdd_internal.h"],
 }
 
 
@@ -107,9 +109,10 @@ def workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def run_batched(args):
-    """64 mixed-size ROF images in one plan (one launch per outer step over
-    every subdomain of every image) against the same images solved one by one."""
+def batched_measure(steps: int, warmup: int, schedule: str = "auto") -> dict:
+    """64 mixed-size ROF images in one plan (the persistent schedule runs them
+    in groups of cooperative launches) against the same images solved one by
+    one, back to back; both timed with the host clock around whole solves."""
     import torch
 
     from paper_1901_00682_amd import dtvdd, synth
@@ -119,20 +122,21 @@ def run_batched(args):
     imgs = [dtvdd.Image(c.f.shape[0], c.f.shape[1], c.row_cuts, c.col_cuts, c.alpha) for c in cases]
     n_outer, K = cases[0].n_outer, cases[0].n_inner
     px = sum(c.f.size for c in cases)
+    tiles = sum((len(c.row_cuts) - 1) * (len(c.col_cuts) - 1) for c in cases)
     f = torch.from_numpy(np.concatenate([c.f.ravel() for c in cases])).to(dev)
-    plan = dtvdd.Plan(imgs, n_outer=n_outer, n_inner=K, schedule=args.schedule, device=dev, time_kernels=True)
+    plan = dtvdd.Plan(imgs, n_outer=n_outer, n_inner=K, schedule=schedule, device=dev)
     st = plan.new_state()
-    for _ in range(args.warmup):
+    for _ in range(max(warmup, 1)):
         plan.solve(f, state=st, want_stats=False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        plan.solve(f, state=st, want_stats=False)
+    for _ in range(steps):
+        plan.solve(f, state=st, want_stats=False, check=False)
     torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.steps
-    kt = plan.kernel_time()
+    dt = (time.perf_counter() - t0) / steps
+    plan.status()
     # the same images one plan each, solved back to back
-    plans = [dtvdd.Plan([im], n_outer=n_outer, n_inner=K, schedule=args.schedule, device=dev) for im in imgs]
+    plans = [dtvdd.Plan([im], n_outer=n_outer, n_inner=K, schedule=schedule, device=dev) for im in imgs]
     fs = [torch.from_numpy(c.f.ravel()).to(dev) for c in cases]
     sts = [p.new_state() for p in plans]
     for p, fi, si in zip(plans, fs, sts):
@@ -140,9 +144,43 @@ def run_batched(args):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for p, fi, si in zip(plans, fs, sts):
-        p.solve(fi, state=si, want_stats=False)
+        p.solve(fi, state=si, want_stats=False, check=False)
     torch.cuda.synchronize()
     dt_seq = time.perf_counter() - t0
+    for p in plans:
+        p.status()
+        p.close()
+    out = {"workload": f"{len(cases)} ROF images, {px} pixels, {tiles} subdomains (cut at multiples of 128, "
+                       f"ragged edge tiles), {n_outer} outer x {K} inner",
+           "value": px * n_outer * K / dt, "unit": "pixel-inner-iterations/s", "ms_per_solve": dt * 1e3,
+           "steps": steps, "schedule": plan.schedule(),
+           "sequential_plain": {"value": px * n_outer * K / dt_seq, "ms": dt_seq * 1e3},
+           "over_sequential": dt_seq / dt}
+    plan.close()
+    return out
+
+
+def run_batched(args):
+    """The batched workload alone, with the timing of its dominant kernel."""
+    import torch
+
+    from paper_1901_00682_amd import dtvdd, synth
+
+    b = batched_measure(args.steps, args.warmup, args.schedule)
+    cases = synth.config4()
+    dev = torch.device("cuda:0")
+    imgs = [dtvdd.Image(c.f.shape[0], c.f.shape[1], c.row_cuts, c.col_cuts, c.alpha) for c in cases]
+    n_outer, K = cases[0].n_outer, cases[0].n_inner
+    px = sum(c.f.size for c in cases)
+    f = torch.from_numpy(np.concatenate([c.f.ravel() for c in cases])).to(dev)
+    plan = dtvdd.Plan(imgs, n_outer=n_outer, n_inner=K, schedule=args.schedule, device=dev, time_kernels=True)
+    st = plan.new_state()
+    plan.solve(f, state=st, want_stats=False)
+    plan.solve(f, state=st, want_stats=False)
+    torch.cuda.synchronize()
+    dt = b["ms_per_solve"] * 1e-3
+    dt_seq = b["sequential_plain"]["ms"] * 1e-3
+    kt = plan.kernel_time()
     tiles = sum((len(c.row_cuts) - 1) * (len(c.col_cuts) - 1) for c in cases)
     return {
         "metric": METRIC, "value": px * n_outer * K / dt, "unit": "pixel-inner-iterations/s", "n_gpus": 1,
@@ -157,8 +195,13 @@ def run_batched(args):
     }
 
 
-def run_diff(args):
-    """Forward and reverse mode of 16 unrolled 512 x 512 ROF solves."""
+def backward_measure(steps: int, warmup: int, schedule: str = "auto") -> dict:
+    """Forward and reverse mode of 16 unrolled 512 x 512 ROF solves (loss
+    |u - g|^2): the plain forward, the forward that keeps checkpoints, and the
+    backward, each timed with the host clock around the call; then one more
+    backward with HIP events around every launch of the reverse kernel and of
+    the recording forward (their rooflines: algorithmic bytes over the average
+    launch)."""
     import torch
 
     from paper_1901_00682_amd import dtvdd, synth
@@ -172,12 +215,12 @@ def run_diff(args):
     imgs = [dtvdd.Image(H, W, c.row_cuts, c.col_cuts, c.alpha) for c in cases]
     n_outer, K = cases[0].n_outer, cases[0].n_inner
     plan = dtvdd.Plan(imgs, n_outer=n_outer, n_inner=K, save_for_backward=True, ckpt_every=20,
-                      schedule=args.schedule, device=dev)
-    plain = dtvdd.Plan(imgs, n_outer=n_outer, n_inner=K, schedule=args.schedule, device=dev)
+                      schedule=schedule, device=dev)
+    plain = dtvdd.Plan(imgs, n_outer=n_outer, n_inner=K, schedule=schedule, device=dev)
     fl = f.reshape(-1)
     st, sp = plan.new_state(), plain.new_state()
     tf, tb, tp = [], [], []
-    for it in range(args.warmup + args.steps):
+    for it in range(warmup + steps):
         torch.cuda.synchronize(); t0 = time.perf_counter()
         plain.solve(fl, state=sp, want_stats=False)
         torch.cuda.synchronize(); t1 = time.perf_counter()
@@ -187,18 +230,50 @@ def run_diff(args):
         gu = 2.0 * (u - g.reshape(-1))
         plan.backward(fl, gu)
         torch.cuda.synchronize(); t3 = time.perf_counter()
-        if it >= args.warmup:
+        if it >= warmup:
             tp.append(t1 - t0); tf.append(t2 - t1); tb.append(t3 - t2)
+    # the kernels of one more backward, timed launch by launch
+    tplan = dtvdd.Plan(imgs, n_outer=n_outer, n_inner=K, save_for_backward=True, ckpt_every=20,
+                       schedule=schedule, device=dev, time_kernels=True)
+    ts = tplan.new_state()
+    tplan.solve(fl, state=ts, want_stats=False)
+    tplan.backward(fl, 2.0 * (ts["u"][: B * H * W] - g.reshape(-1)))
+    torch.cuda.synchronize()
+    kern = {}
+    for which in (0, 1):
+        kt = tplan.backward_kernel_time(which)
+        if kt["launches"] > 0:
+            gbs = kt["bytes_per_launch"] / (kt["avg_ms"] * 1e-3) / 1e9
+            kern["reverse" if which == 0 else "recording_forward"] = {
+                "bound": "hbm", "kernel": kt["name"], "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": gbs / HBM_PEAK_GBS, "traffic": measured_traffic(kt["name"].split()[0] + (
+                    "_rec" if which == 1 else ""), "diff"),
+                "avg_launch_us": kt["avg_ms"] * 1e3, "launches": kt["launches"],
+                "bytes_per_launch": kt["bytes_per_launch"]}
     px = B * H * W
+    out = {"workload": f"differentiation: {B} x {H}x{W} ROF, 4x4 subdomains, {n_outer} outer x {K} inner, "
+                       "loss |u - g|^2, gradient in f and alpha, checkpoint every 20 outer steps",
+           "plain_forward_ms": float(np.median(tp)) * 1e3,
+           "forward_with_checkpoints_ms": float(np.median(tf)) * 1e3,
+           "backward_ms": float(np.median(tb)) * 1e3,
+           "backward_over_forward": float(np.median(tb)) / float(np.median(tp)),
+           "forward_value": px * n_outer * K / float(np.median(tp)), "unit": "pixel-inner-iterations/s",
+           "steps": steps, "schedule": plan.schedule(), "kernels": kern}
+    for p in (plan, plain, tplan):
+        p.close()
+    return out
+
+
+def run_diff(args):
+    """Forward and reverse mode of 16 unrolled 512 x 512 ROF solves."""
+    b = backward_measure(args.steps, args.warmup, args.schedule)
     return {
-        "metric": METRIC, "value": px * n_outer * K / float(np.median(tf)), "unit": "pixel-inner-iterations/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": float(np.median(tf + tb)) * 1e3,
+        "metric": METRIC, "value": b["forward_value"], "unit": "pixel-inner-iterations/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": b["forward_with_checkpoints_ms"] + b["backward_ms"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"differentiation: {B} x {H}x{W} ROF, 4x4 subdomains, {n_outer} outer x {K} inner, "
-                               "checkpoint every 20 outer steps", "schedule": plan.schedule()},
-        "forward_ms": float(np.median(tf)) * 1e3, "forward_with_checkpoints_ms": float(np.median(tf)) * 1e3,
-        "plain_forward_ms": float(np.median(tp)) * 1e3, "backward_ms": float(np.median(tb)) * 1e3,
-        "backward_over_forward": float(np.median(tb)) / float(np.median(tp)),
+        "config": {"workload": b["workload"], "schedule": b["schedule"]},
+        "roofline": b["kernels"].get("reverse"), "backward": b,
     }
 
 
@@ -290,19 +365,47 @@ def run_dd_vs_full(args):
     }
 
 
-def cpu_baseline(c, outer_sample: int) -> dict:
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(c, outer_sample: int, outer_single: int) -> dict:
+    """The FP64 oracle on the host cores: the first outer_sample outer steps
+    with every thread of its parallel loop over subdomains, and the first
+    outer_single steps on one thread."""
     import oracle
 
-    o = oracle.Oracle(oracle.Problem(c.f.astype(np.float64), c.alpha, c.row_cuts, c.col_cuts, fidelity=c.fidelity,
-                                     inner=c.inner, mask=c.mask, tau=c.tau, sigma=c.sigma, tau0=c.tau0,
-                                     sigma0=c.sigma0, gamma=c.gamma, n_inner=c.n_inner, **c.extra))
-    t0 = time.perf_counter()
-    o.run(outer_sample)
-    dt = time.perf_counter() - t0
+    def timed(n_outer):
+        o = oracle.Oracle(oracle.Problem(c.f.astype(np.float64), c.alpha, c.row_cuts, c.col_cuts,
+                                         fidelity=c.fidelity, inner=c.inner, mask=c.mask, tau=c.tau, sigma=c.sigma,
+                                         tau0=c.tau0, sigma0=c.sigma0, gamma=c.gamma, n_inner=c.n_inner, **c.extra))
+        t0 = time.perf_counter()
+        o.run(n_outer)
+        return time.perf_counter() - t0
+
     H, W = c.f.shape
-    return {"value": H * W * outer_sample * c.n_inner / dt, "unit": "pixel-inner-iterations/s",
-            "cores": oracle.threads(), "kind": "oracle",
-            "sample": f"first {outer_sample} of {c.n_outer} outer steps of the same workload, FP64, {dt:.1f} s"}
+    threads = oracle.threads()
+    dt = timed(outer_sample)
+    out = {"value": H * W * outer_sample * c.n_inner / dt, "unit": "pixel-inner-iterations/s",
+           "cores": threads, "kind": "oracle", "cpu_model": cpu_model(), "logical_cpus": os.cpu_count(),
+           "sample": f"first {outer_sample} of {c.n_outer} outer steps of the same workload, FP64, {threads} "
+                     f"threads, {dt:.1f} s"}
+    if outer_single > 0:
+        oracle.set_threads(1)
+        try:
+            d1 = timed(outer_single)
+        finally:
+            oracle.set_threads(threads)
+        out["single_thread"] = {"value": H * W * outer_single * c.n_inner / d1, "cores": 1,
+                                "sample": f"first {outer_single} outer steps, FP64, 1 thread, {d1:.1f} s"}
+    return out
 
 
 def main():
@@ -314,6 +417,8 @@ def main():
     ap.add_argument("--schedule", default="auto")
     ap.add_argument("--rows", type=int, default=0, help="streaming strip height (0: the plan picks)")
     ap.add_argument("--cpu-outer", type=int, default=500, help="outer steps of the oracle sample (0: skip)")
+    ap.add_argument("--cpu-outer-single", type=int, default=20, help="outer steps of the one-thread oracle sample")
+    ap.add_argument("--no-extra", action="store_true", help="default workload: skip the batched and backward blocks")
     ap.add_argument("--ref-iters", type=int, default=20000, help="dd_vs_full: FISTA iterations of the J* run")
     ap.add_argument("--adaptive-tol", type=float, default=1e-3, help="dd_vs_full: inner_tol of the adaptive run")
     ap.add_argument("--adaptive-cap", type=int, default=100, help="dd_vs_full: local step cap of the adaptive run")
@@ -356,9 +461,10 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        plan.solve(f, m, state=state, stream=stream, want_stats=False)
+        plan.solve(f, m, state=state, stream=stream, want_stats=False, check=False)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    plan.status(stream)
     px_it = H * W * c.n_outer * c.n_inner * args.steps / dt
     # kernel timing: the same solves with HIP events around every launch of the
     # dominant kernel on the solve stream
@@ -429,8 +535,16 @@ def main():
     eff = per_outer * c.n_outer / (dt / args.steps) / 1e9
     out["hot_path_streaming_model"] = {"bytes_per_outer_step": per_outer, "effective_GBs": eff,
                                        "frac_of_hbm_peak": eff / HBM_PEAK_GBS}
+    plan.close()
+    tplan.close()
+    if args.workload == "rof2048" and not args.no_extra:
+        # the rest of the metric (batched vs plain, and the reverse mode), measured in the same run
+        b = batched_measure(min(args.steps, 5), 1)
+        b["over_plain"] = b["value"] / px_it
+        out["batched"] = b
+        out["backward"] = backward_measure(min(args.steps, 5), 1)
     if args.cpu_outer > 0:
-        out["cpu_baseline"] = cpu_baseline(c, min(args.cpu_outer, c.n_outer))
+        out["cpu_baseline"] = cpu_baseline(c, min(args.cpu_outer, c.n_outer), min(args.cpu_outer_single, c.n_outer))
     print(json.dumps(out), flush=True)
 
 

@@ -249,6 +249,14 @@ int dtv_dd_backward(dtv_dd_plan *plan, const float *d_f, const float *d_grad_u, 
 int dtv_dd_kernel_time(const dtv_dd_plan *plan, double *avg_ms, int64_t *launches, const char **name,
                        double *bytes_per_launch);
 
+/* Average duration (ms) of the reverse mode's kernel launches timed in the last dtv_dd_backward
+   of a plan with time_kernels = 1 and the fused reverse (every subdomain 128 x 128): which = 0
+   the on-chip reverse steps (k_fused_bwd, one launch per outer step), which = 1 the recording
+   forward (one launch per outer step); their count, the kernel's name and its algorithmic HBM
+   bytes per launch.  Zeros when nothing was timed. */
+int dtv_dd_backward_kernel_time(const dtv_dd_plan *plan, int32_t which, double *avg_ms, int64_t *launches,
+                                const char **name, double *bytes_per_launch);
+
 /* The schedule the plan will use (DTV_SCHED_STREAM, DTV_SCHED_FUSED or DTV_SCHED_PERSIST). */
 int dtv_dd_schedule(const dtv_dd_plan *plan, int32_t *schedule);
 

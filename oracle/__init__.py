@@ -95,6 +95,7 @@ def load(path: str = LIB_PATH):
     lib.orc_n_done.restype = ctypes.c_int
     lib.orc_n_done.argtypes = [vp]
     lib.orc_threads.restype = ctypes.c_int
+    lib.orc_set_threads.argtypes = [ctypes.c_int]
     lib.orc_inner_counts.argtypes = [vp, _L]
     lib.orc_inner_margin.restype = ctypes.c_double
     lib.orc_inner_margin.argtypes = [vp]
@@ -316,6 +317,11 @@ def prox(fidelity: str, z, f, a: float, mask=None, c1: float = 0.6, c2: float = 
 def threads() -> int:
     """Threads used by the oracle's parallel loop over subdomains."""
     return int(load().orc_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loop over subdomains from now on."""
+    load().orc_set_threads(int(n))
 
 
 def tv(u) -> float:

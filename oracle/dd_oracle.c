@@ -912,6 +912,16 @@ int orc_threads(void)
 #endif
 }
 
+/* Threads of the parallel loop over subdomains from now on (n >= 1). */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------ */
 /* reverse mode of the unrolled solve (FISTA local solver, L2, no mask)  */
 /*

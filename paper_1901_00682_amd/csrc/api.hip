@@ -147,6 +147,11 @@ struct dtv_dd_plan {
     std::vector<hipEvent_t> events;
     double t_ms = 0.0;
     int64_t t_count = 0;
+    // timing of the reverse mode's kernels (time_kernels): [0] the on-chip reverse steps,
+    // [1] the recording forward; events in pairs, start and stop of each launch
+    std::vector<hipEvent_t> bwd_events[2];
+    double tb_ms[2] = {0.0, 0.0};
+    int64_t tb_count[2] = {0, 0};
 
     ~dtv_dd_plan()
     {
@@ -155,6 +160,8 @@ struct dtv_dd_plan {
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
+        for (auto &v : bwd_events)
+            for (hipEvent_t e : v) (void)hipEventDestroy(e);
         if (h_diag) (void)hipHostFree(h_diag);
     }
 
@@ -1381,6 +1388,23 @@ static int backward_fused(dtv_dd_plan *pl, const float *d_f, float *d_grad_f, fl
     ba.inv_tau = (float)pl->inv_tau;
     ba.n_inner = K;
     for (int k = 1; k <= K; ++k) ba.beta[k] = beta[k];
+    // with time_kernels: a pair of events around every launch of the two kernels of a reverse step
+    const bool timed = P.time_kernels != 0;
+    size_t used[2] = {0, 0};
+    auto events = [&](int which, hipEvent_t *e0, hipEvent_t *e1) -> int {
+        *e0 = *e1 = nullptr;
+        if (!timed) return DTV_OK;
+        std::vector<hipEvent_t> &v = pl->bwd_events[which];
+        while (v.size() < used[which] + 2) {
+            hipEvent_t e;
+            HIP_TRY(hipEventCreate(&e), "event create");
+            v.push_back(e);
+        }
+        *e0 = v[used[which]];
+        *e1 = v[used[which] + 1];
+        used[which] += 2;
+        return DTV_OK;
+    };
     // one outer step of the fused forward from a state (p~, lambda state) to p~ out, lambda state out
     auto forward = [&](const float *st, float *p_out, float *lam_out, float4 *rec) -> int {
         fa.base1 = st;
@@ -1390,7 +1414,12 @@ static int backward_fused(dtv_dd_plan *pl, const float *d_f, float *d_grad_f, fl
         fa.out2 = p_out + pl->tot_p1;
         fa.lam_out = lam_out;
         fa.rec = rec;
-        HIP_TRY(launch_fused_fista(fa, nsub, pl->n_full, pl->n_framed, s),
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (rec) {
+            int rc = events(1, &e0, &e1);
+            if (rc != DTV_OK) return rc;
+        }
+        HIP_TRY(launch_fused_fista(fa, nsub, pl->n_full, pl->n_framed, s, e0, e1),
                 rec ? "fused FISTA (recording)" : "fused FISTA");
         return DTV_OK;
     };
@@ -1408,7 +1437,10 @@ static int backward_fused(dtv_dd_plan *pl, const float *d_f, float *d_grad_f, fl
             if (rc != DTV_OK) return rc;
             ba.x0_1 = st;
             ba.x0_2 = st + pl->tot_p1;
-            HIP_TRY(launch_fused_bwd(ba, nsub, s), "fused reverse steps");
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            rc = events(0, &e0, &e1);
+            if (rc != DTV_OK) return rc;
+            HIP_TRY(launch_fused_bwd(ba, nsub, s, e0, e1), "fused reverse steps");
             HIP_TRY(launch_bwd_interface(pl->d_imgs(), pl->n, pl->max_nlam, pl->d_info(), pl->hb(),
                                          pl->hb() + pl->tot_p1, pl->pb(), pl->pb() + pl->tot_p1, pl->lb(),
                                          (float)P.tau, (float)P.sigma, s),
@@ -1419,6 +1451,19 @@ static int backward_fused(dtv_dd_plan *pl, const float *d_f, float *d_grad_f, fl
     HIP_TRY(launch_alpha_reduce2(pl->d_tiles(rows), pl->ntiles(rows), pl->galpha(), pl->d_subs(), nsub, pl->gsub(),
                                  pl->n, d_grad_alpha, s),
             "alpha reduce");
+    if (timed) {
+        HIP_TRY(hipStreamSynchronize(s), "timing sync");
+        for (int w = 0; w < 2; ++w) {
+            double tot = 0.0;
+            for (size_t k = 0; k < used[w]; k += 2) {
+                float ms = 0.0f;
+                HIP_TRY(hipEventElapsedTime(&ms, pl->bwd_events[w][k], pl->bwd_events[w][k + 1]), "event elapsed");
+                tot += ms;
+            }
+            pl->tb_count[w] = (int64_t)(used[w] / 2);
+            pl->tb_ms[w] = used[w] ? tot / (double)(used[w] / 2) : 0.0;
+        }
+    }
     return DTV_OK;
 }
 
@@ -1553,6 +1598,31 @@ extern "C" int dtv_dd_kernel_time(const dtv_dd_plan *pl, double *avg_ms, int64_t
             }
             *bytes_per_launch = tot / K;
         }
+    }
+    return DTV_OK;
+}
+
+extern "C" int dtv_dd_backward_kernel_time(const dtv_dd_plan *pl, int32_t which, double *avg_ms, int64_t *launches,
+                                           const char **name, double *bytes_per_launch)
+{
+    if (!pl) return fail(DTV_EINVAL, "null argument");
+    if (which != 0 && which != 1) return fail(DTV_EINVAL, "which must be 0 (reverse steps) or 1 (recording forward)");
+    if (avg_ms) *avg_ms = pl->tb_ms[which];
+    if (launches) *launches = pl->tb_count[which];
+    if (name) *name = which == 0 ? "k_fused_bwd" : "k_fused_fista (recording)";
+    if (bytes_per_launch) {
+        // Algorithmic HBM bytes of one launch (E = edge dofs of the torn p~, N = pixels, K = n_inner,
+        // 4 bytes each; a step record is kRecGroups * 16 bytes per thread, 10 bytes per pixel):
+        //   reverse steps: read the K records, pbar^(n+1), p~^n, f and fbar; write pbar^n, phatbar
+        //                  and fbar                                                 4 (4E + 3N) + 10 K N
+        //   recording forward: read p~^n and f; write p~^(n+1) and the K records     4 (2E + N) + 10 K N
+        double E = 0.0, N = 0.0;
+        for (const ImgHost &h : pl->imgs) {
+            E += (double)(h.H + h.ny) * h.W + (double)h.H * (h.W + h.nx);
+            N += (double)h.H * h.W;
+        }
+        const double rec = (double)kRecGroups * 16.0 / 16.0 * (double)pl->prm.n_inner * N;  // 16 pixels per thread
+        *bytes_per_launch = which == 0 ? 4.0 * (4 * E + 3 * N) + rec : 4.0 * (2 * E + N) + rec;
     }
     return DTV_OK;
 }

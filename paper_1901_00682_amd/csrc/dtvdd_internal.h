@@ -259,7 +259,8 @@ struct FusedBwdArgs {
     float beta[kMaxFusedInner + 1];
 };
 bool fused_bwd_supported(int K);
-hipError_t launch_fused_bwd(const FusedBwdArgs &a, int nsub, hipStream_t s);
+hipError_t launch_fused_bwd(const FusedBwdArgs &a, int nsub, hipStream_t s, hipEvent_t e0 = nullptr,
+                            hipEvent_t e1 = nullptr);
 
 // whether the fused kernel can record its steps for this inner count (full tiles only)
 bool fused_record_supported(int K);

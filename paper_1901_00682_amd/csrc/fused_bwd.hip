@@ -385,12 +385,15 @@ using Bwd = BwdTable<1, 2, 3, 4, 5, 6, 7, 8, 10>;
 
 bool fused_bwd_supported(int K) { return Bwd::get(K) != nullptr; }
 
-hipError_t launch_fused_bwd(const FusedBwdArgs &a, int nsub, hipStream_t s)
+hipError_t launch_fused_bwd(const FusedBwdArgs &a, int nsub, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     if (nsub <= 0) return hipSuccess;
     const BwdKernel k = Bwd::get(a.n_inner);
     if (!k) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k, dim3(nsub), dim3(1024), 0, s, a);
+    if (e0)
+        hipExtLaunchKernelGGL(k, dim3(nsub), dim3(1024), 0, s, e0, e1, 0, a);
+    else
+        hipLaunchKernelGGL(k, dim3(nsub), dim3(1024), 0, s, a);
     return hipGetLastError();
 }
 

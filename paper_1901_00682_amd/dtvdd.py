@@ -28,7 +28,7 @@ SCHEDULE_NAME = {v: k for k, v in SCHEDULE.items()}
 
 # every entry point declared in include/dtvdd.h
 EXPORTS = ("dtv_dd_setup", "dtv_dd_layout", "dtv_dd_workspace_bytes", "dtv_dd_bind_workspace", "dtv_dd_solve",
-           "dtv_dd_diagnostics", "dtv_dd_backward", "dtv_dd_kernel_time", "dtv_dd_schedule", "dtv_dd_choice",
+           "dtv_dd_diagnostics", "dtv_dd_backward", "dtv_dd_kernel_time", "dtv_dd_backward_kernel_time", "dtv_dd_schedule", "dtv_dd_choice",
            "dtv_dd_inner_counts", "dtv_dd_status", "dtv_dd_solve_noalloc", "dtv_dd_destroy", "dtv_last_error")
 
 SCRATCH_BYTES = 32 << 20  # DTV_SCRATCH_BYTES: the library's device scratch array (dtv_dd_solve_noalloc)
@@ -88,6 +88,8 @@ def lib(path: str = LIB_PATH):
     L.dtv_dd_backward.argtypes = [vp, vp, vp, vp, vp, vp]
     L.dtv_dd_kernel_time.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_char_p),
                                      ctypes.POINTER(dbl)]
+    L.dtv_dd_backward_kernel_time.argtypes = [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64),
+                                              ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(dbl)]
     L.dtv_dd_schedule.argtypes = [vp, ctypes.POINTER(i32)]
     L.dtv_dd_choice.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.dtv_dd_inner_counts.argtypes = [vp, ctypes.POINTER(i32), vp]
@@ -312,6 +314,14 @@ class Plan:
     def kernel_time(self):
         ms, n, nm, b = ctypes.c_double(), ctypes.c_int64(), ctypes.c_char_p(), ctypes.c_double()
         _check(lib().dtv_dd_kernel_time(self.h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(nm), ctypes.byref(b)))
+        return {"avg_ms": ms.value, "launches": n.value, "name": nm.value.decode(), "bytes_per_launch": b.value}
+
+    def backward_kernel_time(self, which: int = 0):
+        """Timing of the last backward's launches (time_kernels): which = 0 the
+        reverse steps, 1 the recording forward."""
+        ms, n, nm, b = ctypes.c_double(), ctypes.c_int64(), ctypes.c_char_p(), ctypes.c_double()
+        _check(lib().dtv_dd_backward_kernel_time(self.h, int(which), ctypes.byref(ms), ctypes.byref(n),
+                                                 ctypes.byref(nm), ctypes.byref(b)))
         return {"avg_ms": ms.value, "launches": n.value, "name": nm.value.decode(), "bytes_per_launch": b.value}
 
     # -- views in the documented layout --------------------------------------
