@@ -1612,17 +1612,19 @@ extern "C" int dtv_dd_backward_kernel_time(const dtv_dd_plan *pl, int32_t which,
     if (name) *name = which == 0 ? "k_fused_bwd" : "k_fused_fista (recording)";
     if (bytes_per_launch) {
         // Algorithmic HBM bytes of one launch (E = edge dofs of the torn p~, N = pixels, K = n_inner,
-        // 4 bytes each; a step record is kRecGroups * 16 bytes per thread, 10 bytes per pixel):
-        //   reverse steps: read the K records, pbar^(n+1), p~^n, f and fbar; write pbar^n, phatbar
-        //                  and fbar                                                 4 (4E + 3N) + 10 K N
-        //   recording forward: read p~^n and f; write p~^(n+1) and the K records     4 (2E + N) + 10 K N
+        // 4 bytes each; a step record is kRecGroups 16-byte groups per thread of 16 pixels, R = 9
+        // bytes per pixel; phatbar is written on the interface copies only, a negligible part):
+        //   reverse steps: read the K records, pbar^(n+1), p~^n, f and fbar; write pbar^n and fbar
+        //                                                                           4 (3E + 3N) + R K N
+        //   recording forward: read p~^n and f; write p~^(n+1) and the K records     4 (2E + N) + R K N
         double E = 0.0, N = 0.0;
         for (const ImgHost &h : pl->imgs) {
             E += (double)(h.H + h.ny) * h.W + (double)h.H * (h.W + h.nx);
             N += (double)h.H * h.W;
         }
-        const double rec = (double)kRecGroups * 16.0 / 16.0 * (double)pl->prm.n_inner * N;  // 16 pixels per thread
-        *bytes_per_launch = which == 0 ? 4.0 * (4 * E + 3 * N) + rec : 4.0 * (2 * E + N) + rec;
+        const double R = (double)kRecGroups * 16.0 / 16.0;
+        const double rec = R * (double)pl->prm.n_inner * N;
+        *bytes_per_launch = which == 0 ? 4.0 * (3 * E + 3 * N) + rec : 4.0 * (2 * E + N) + rec;
     }
     return DTV_OK;
 }

@@ -48,7 +48,7 @@ struct SubTile {
 
 constexpr int kStreamCols = 63;   // output columns per wave
 constexpr int kRowChoices = 4;    // rows per strip of the streaming kernels: 4, 8, 16 or 32
-constexpr int kRecGroups = 10;    // float4 groups per thread in a step record of the fused kernel (fused_common.h)
+constexpr int kRecGroups = 9;     // float4 groups per thread in a step record of the fused kernel (fused_common.h)
 constexpr int kRecThreads = 1024; // threads of a fused workgroup
 inline int row_index(int R) { return R <= 4 ? 0 : R <= 8 ? 1 : R <= 16 ? 2 : 3; }
 constexpr int kFusedMax = 128;    // largest subdomain side handled by the fused kernel

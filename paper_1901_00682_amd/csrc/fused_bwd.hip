@@ -87,25 +87,30 @@ __device__ __forceinline__ void bwd_step(const BwdCtx &c, BwdLds &L, Slot &Z, Sl
     const int row = c.il0 + c.lane;  // lanes 0..7: right boundary edge of this row
     float *S1 = &L.S1[0][0] + oc, *S2 = &L.S2[0][0] + oc;
     // (1) zbar on every owned edge, S += zbar, <zbar, q>.  The step's record is
-    // loaded first (ten 16-byte loads in flight together) and consumed after.
-    float4 q[kRecGroups];
+    // loaded in two halves: group 8 (boundary edges and mask) and rows 0..3 first,
+    // rows 4..7 once rows 0..1 are consumed, so that at most five groups are held
+    // at once (all nine at once take more registers than the slots leave).
+    float4 q[4];
+    const float4 g8 = rg(rec, 8, tid);
 #pragma unroll
-    for (int g = 0; g < kRecGroups; ++g) q[g] = rg(rec, g, tid);
-    const unsigned m0 = __float_as_uint(q[8].w);
-    const unsigned m1 = __float_as_uint(q[9].x);
+    for (int g = 0; g < 4; ++g) q[g] = rg(rec, g, tid);
+    const unsigned m0 = __float_as_uint(g8.w);
     // the step's dot product is summed in FP32 over the thread's 35 edges and then
     // added to the FP64 accumulator
     float zy = 0.0f;
 #pragma unroll
     for (int r = 0; r < kR; ++r) {
+        __builtin_amdgcn_sched_barrier(0);
+        const float4 qr = q[r & 3];
+        if (r >= 2 && r < 6) q[(r + 2) & 3] = rg(rec, r + 2, tid);  // rows 4..7 into the registers of rows 0..3
         Z.e1a[r] = (m0 >> (4 * r + 0)) & 1u ? Z.e1a[r] : 0.0f;
         Z.e1b[r] = (m0 >> (4 * r + 1)) & 1u ? Z.e1b[r] : 0.0f;
         Z.e2a[r] = (m0 >> (4 * r + 2)) & 1u ? Z.e2a[r] : 0.0f;
         Z.e2b[r] = (m0 >> (4 * r + 3)) & 1u ? Z.e2b[r] : 0.0f;
-        zy = fmaf(Z.e1a[r], q[r].x, zy);
-        zy = fmaf(Z.e1b[r], q[r].y, zy);
-        zy = fmaf(Z.e2a[r], q[r].z, zy);
-        zy = fmaf(Z.e2b[r], q[r].w, zy);
+        zy = fmaf(Z.e1a[r], qr.x, zy);
+        zy = fmaf(Z.e1b[r], qr.y, zy);
+        zy = fmaf(Z.e2a[r], qr.z, zy);
+        zy = fmaf(Z.e2b[r], qr.w, zy);
         float s1a, s1b, s2a, s2b;
         lds_ld2(S1 + r * kFusedMax, s1a, s1b);
         lds_ld2(S2 + r * kFusedMax, s2a, s2b);
@@ -113,19 +118,21 @@ __device__ __forceinline__ void bwd_step(const BwdCtx &c, BwdLds &L, Slot &Z, Sl
         lds_st2(S2 + r * kFusedMax, s2a + Z.e2a[r], s2b + Z.e2b[r]);
         pin4(Z.e1a[r], Z.e1b[r], Z.e2a[r], zy);
     }
-    // bottom boundary edges: strip 15 only
-    Z.ba = c.last && (m1 & 1u) ? Z.ba : 0.0f;
-    Z.bb = c.last && (m1 & 2u) ? Z.bb : 0.0f;
+    // bottom boundary edges (strip 15) and right boundary edges (lanes 0..7): q is a NaN where
+    // the projection's derivative is 0
+    const bool mba = !__builtin_isnan(g8.x), mbb = !__builtin_isnan(g8.y), mr = !__builtin_isnan(g8.z);
+    Z.ba = c.last && mba ? Z.ba : 0.0f;
+    Z.bb = c.last && mbb ? Z.bb : 0.0f;
     if (c.last) {
-        zy = fmaf(Z.ba, q[8].x, fmaf(Z.bb, q[8].y, zy));
+        zy = fmaf(Z.ba, mba ? g8.x : 0.0f, fmaf(Z.bb, mbb ? g8.y : 0.0f, zy));
         float sa, sb;
         lds_ld2(&L.Sb[c.ja], sa, sb);
         lds_st2(&L.Sb[c.ja], sa + Z.ba, sb + Z.bb);
     }
     if (c.lane < kR) {
-        const float zr = (m1 & 4u) ? RZ[row] : 0.0f;
+        const float zr = mr ? RZ[row] : 0.0f;
         RZ[row] = zr;
-        zy = fmaf(zr, q[8].z, zy);
+        zy = fmaf(zr, mr ? g8.z : 0.0f, zy);
         L.Sr[row] += zr;
     }
     acc_q += (double)zy;
@@ -290,6 +297,11 @@ __global__ __launch_bounds__(1024) void k_fused_bwd(FusedBwdArgs a)
     double acc = acc_q;
     const float *lam = a.lam + im.lam;
     double sp = 0.0, fs = 0.0;  // <phat, S>, <f, div S>
+    // the row addresses of pbar are formed again here (kept from the prologue they would stay live
+    // through the steps, in scratch); phatbar is needed on the interface copies only (the interface
+    // transpose reads nothing else), so it is written there alone
+    asm volatile("" : "+s"(pb1), "+s"(pb2));
+    const bool top_if = tl.r > 0, left_if = tl.c > 0;
 #pragma unroll
     for (int r = 0; r < kR; ++r) {
         const int il = il0 + r;
@@ -312,8 +324,8 @@ __global__ __launch_bounds__(1024) void k_fused_bwd(FusedBwdArgs a)
         const bool tv = !(il == 0 && top_bnd);
         const float h1a = tv ? hL * s1a : 0.0f, h1b = tv ? hL * s1b : 0.0f;
         const float h2a = c.left_var ? hL * s2a : 0.0f, h2b = hL * s2b;
-        st2(hb1 + (long long)il * P1 + ja, h1a, h1b);
-        st2(hb2 + (long long)il * P2 + ja, h2a, h2b);
+        if (il == 0 && top_if) st2(hb1 + ja, h1a, h1b);
+        if (ja == 0 && left_if) hb2[(long long)il * P2] = h2a;
         st2(pb1 + (long long)il * P1 + ja, tv ? A.e1a[r] + h1a : 0.0f, tv ? A.e1b[r] + h1b : 0.0f);
         st2(pb2 + (long long)il * P2 + ja, c.left_var ? A.e2a[r] + h2a : 0.0f, A.e2b[r] + h2b);
         // div S of the row's pixels (bottom edge: next row, or the bottom boundary row)
@@ -341,7 +353,7 @@ __global__ __launch_bounds__(1024) void k_fused_bwd(FusedBwdArgs a)
         }
         sp += (double)xa * sa + (double)xb * sb;
         const float ha = bot_bnd ? 0.0f : hL * sa, hbv = bot_bnd ? 0.0f : hL * sb;
-        st2(hb1 + (long long)kFusedMax * P1 + ja, ha, hbv);
+        if (!bot_bnd) st2(hb1 + (long long)kFusedMax * P1 + ja, ha, hbv);
         st2(pb1 + (long long)kFusedMax * P1 + ja, bot_bnd ? 0.0f : A.ba + ha, bot_bnd ? 0.0f : A.bb + hbv);
     }
     if (lane < kR) {  // right boundary edges: s copies -tau lambda
@@ -351,7 +363,7 @@ __global__ __launch_bounds__(1024) void k_fused_bwd(FusedBwdArgs a)
         if (!right_bnd) xr = fmaf(-tau, lam[im.nlh + (long long)tl.c * H + tl.ra + il], xr);
         sp += (double)xr * sr;
         const float hr = right_bnd ? 0.0f : hL * sr;
-        hb2[(long long)il * P2 + kFusedMax] = hr;
+        if (!right_bnd) hb2[(long long)il * P2 + kFusedMax] = hr;
         pb2[(long long)il * P2 + kFusedMax] = right_bnd ? 0.0f : L.rx[rxs][il] + hr;
     }
     acc += dA * (double)itau * sp - dA * fs;

@@ -257,12 +257,12 @@ __device__ __forceinline__ void full_row_div(const Slot &Y, float ry, int r, flo
 //             the alpha derivative of z is (dA/tau)(phat - y) - dA (f_b - f_a)
 //             - dB (d_b - d_a), and q carries its y-dependent part (qa = -dA/tau,
 //             qb = -dB)
-//   g = 8     q on the bottom boundary edges a, b (strip 15), q on the right
-//             boundary edge of row 8 s + lane (lanes 0..7), the projection mask of
-//             the 32 edges (bit 4 r + i set when -1 < z < 1 on an edge that is a
-//             variable)
-//   g = 9     the projection mask of the bottom edges (bits 0, 1) and of the right
-//             boundary edge (bit 2); three unused words
+//   g = 8     q on the bottom boundary edges a, b (strip 15) and on the right
+//             boundary edge of row 8 s + lane (lanes 0..7), each a NaN where the
+//             projection is not differentiable there (|z| >= 1, an edge that is not a
+//             variable, or a thread that holds no such edge), and the projection mask
+//             of the 32 other edges (bit 4 r + i set when -1 < z < 1 on an edge that
+//             is a variable)
 
 // a framed tile with masks: d is 0 on the pixels outside the tile (row r of the strip)
 __device__ __forceinline__ void dmask(const FullCtx &c, int r, float &da, float &db)
@@ -396,8 +396,9 @@ __device__ __forceinline__ void full_step(const FullCtx &c, FusedLds &S, const S
         }
     }
     if constexpr (REC) {
-        rec[8 * kRecThreads] = make_float4(qba, qbb, qr, __uint_as_float(m0));
-        rec[9 * kRecThreads] = make_float4(__uint_as_float(m1), 0.0f, 0.0f, 0.0f);
+        const float nan = __builtin_nanf("");
+        rec[8 * kRecThreads] = make_float4((m1 & 1u) ? qba : nan, (m1 & 2u) ? qbb : nan, (m1 & 4u) ? qr : nan,
+                                           __uint_as_float(m0));
     }
 }
 
