@@ -135,6 +135,8 @@ struct dtv_dd_plan {
     size_t off_ckpt = 0, off_seg = 0, off_xrec = 0, off_zrec = 0, off_lam1 = 0, off_xb = 0, off_hb = 0, off_pb = 0,
            off_lb = 0, off_galpha = 0, off_frec = 0, off_gsub = 0;
     bool fbwd = false;        // reverse mode with the fused kernels (every subdomain 128 x 128)
+    bool seg_rec = false;     // fused reverse: the step records of a whole checkpoint segment are kept
+    size_t rec_step = 0;      // bytes of one outer step's records
     bool adaptive = false;    // inner_tol > 0: the fused kernel stops each local solve by the relative-change rule
     size_t off_beta = 0, off_counts = 0;  // adaptive: momentum table, per-subdomain step counts
     size_t off_cp2tab = 0;                // adaptive primal-dual: the step scalars
@@ -186,7 +188,8 @@ struct dtv_dd_plan {
     float *pb() const { return (float *)(ws + off_pb); }
     float *lb() const { return (float *)(ws + off_lb); }
     double *galpha() const { return (double *)(ws + off_galpha); }
-    float4 *frec() const { return (float4 *)(ws + off_frec); }     // step records of the fused forward
+    // step records of the fused forward: outer step q of the segment (q = 0 without seg_rec)
+    float4 *frec(int q = 0) const { return (float4 *)(ws + off_frec + (size_t)q * rec_step); }
     double *gsub() const { return (double *)(ws + off_gsub); }     // per-subdomain alpha partial sums
     double *dout() const { return (double *)(ws + off_dout); }
     unsigned long long *xch() const { return (unsigned long long *)(ws + off_xch); }
@@ -561,12 +564,17 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
         pl->nseg = (p.n_outer + C - 1) / C;
         const int segmax = std::min(C, std::max(p.n_outer, 1));
         pl->off_ckpt = take(sizeof(float) * pl->state_floats * (size_t)(pl->nseg + 1));
-        pl->off_seg = take(sizeof(float) * pl->state_floats * (size_t)segmax);
+        // a segment's states before each of its steps and after its last one
+        pl->off_seg = take(sizeof(float) * pl->state_floats * (size_t)(segmax + 1));
         const size_t nsub = pl->h_subs.size();
         pl->fbwd = pl->fused_ok && pl->n_full == (int)nsub && fused_record_supported(p.n_inner) &&
                    fused_bwd_supported(p.n_inner);
         if (pl->fbwd) {
-            pl->off_frec = take(sizeof(float4) * (size_t)p.n_inner * nsub * kRecGroups * kRecThreads);
+            // the records of a whole segment when they fit the budget (the segment's states are then
+            // recomputed by the recording launches themselves), else of one outer step
+            pl->rec_step = sizeof(float4) * (size_t)p.n_inner * nsub * kRecGroups * kRecThreads;
+            pl->seg_rec = (size_t)segmax * pl->rec_step <= kSegRecordBytes;
+            pl->off_frec = take(pl->rec_step * (size_t)(pl->seg_rec ? segmax : 1));
             pl->off_gsub = take(sizeof(double) * nsub);
         } else {
             pl->off_xrec = take(sizeof(float) * E * (size_t)p.n_inner);
@@ -1375,8 +1383,6 @@ static int backward_fused(dtv_dd_plan *pl, const float *d_f, float *d_grad_f, fl
     FusedBwdArgs ba{};
     ba.imgs = pl->d_imgs();
     ba.subs = pl->d_subs();
-    ba.rec = pl->frec();
-    ba.lam = pl->lam1();
     ba.f = d_f;
     ba.pb1 = pl->pb();
     ba.pb2 = pl->pb() + pl->tot_p1;
@@ -1423,28 +1429,48 @@ static int backward_fused(dtv_dd_plan *pl, const float *d_f, float *d_grad_f, fl
                 rec ? "fused FISTA (recording)" : "fused FISTA");
         return DTV_OK;
     };
+    // the reverse of outer step q of the segment, from its state seg(q), the lambda state after its
+    // multiplier update (lam_next) and its records
+    auto reverse = [&](int q, const float *lam_next, const float4 *rec) -> int {
+        const float *st = pl->seg(q);
+        ba.x0_1 = st;
+        ba.x0_2 = st + pl->tot_p1;
+        ba.lam = lam_next;
+        ba.rec = rec;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        int rc = events(0, &e0, &e1);
+        if (rc != DTV_OK) return rc;
+        HIP_TRY(launch_fused_bwd(ba, nsub, s, e0, e1), "fused reverse steps");
+        HIP_TRY(launch_bwd_interface(pl->d_imgs(), pl->n, pl->max_nlam, pl->d_info(), pl->hb(), pl->hb() + pl->tot_p1,
+                                     pl->pb(), pl->pb() + pl->tot_p1, pl->lb(), (float)P.tau, (float)P.sigma, s),
+                "interface reverse");
+        return DTV_OK;
+    };
     for (int sg = pl->nseg - 1; sg >= 0; --sg) {
         const int n0 = sg * C, n1 = std::min(N, n0 + C), m = n1 - n0;
         HIP_TRY(hipMemcpyAsync(pl->seg(0), pl->ckpt(sg), sizeof(float) * pl->state_floats, hipMemcpyDeviceToDevice, s),
                 "restore checkpoint");
+        if (pl->seg_rec) {
+            // one recording launch per outer step recomputes the segment's states and keeps every record
+            for (int q = 0; q < m; ++q) {
+                int rc = forward(pl->seg(q), pl->seg(q + 1), pl->seg(q + 1) + E, pl->frec(q));
+                if (rc != DTV_OK) return rc;
+            }
+            for (int q = m - 1; q >= 0; --q) {
+                int rc = reverse(q, pl->seg(q + 1) + E, pl->frec(q));
+                if (rc != DTV_OK) return rc;
+            }
+            continue;
+        }
         for (int q = 0; q + 1 < m; ++q) {  // the segment's states
             int rc = forward(pl->seg(q), pl->seg(q + 1), pl->seg(q + 1) + E, nullptr);
             if (rc != DTV_OK) return rc;
         }
-        for (int q = m - 1; q >= 0; --q) {  // its outer steps in reverse
-            const float *st = pl->seg(q);
-            int rc = forward(st, pl->buf1(0), pl->lam1(), pl->frec());
+        for (int q = m - 1; q >= 0; --q) {  // its outer steps in reverse, each recorded again
+            int rc = forward(pl->seg(q), pl->buf1(0), pl->lam1(), pl->frec());
             if (rc != DTV_OK) return rc;
-            ba.x0_1 = st;
-            ba.x0_2 = st + pl->tot_p1;
-            hipEvent_t e0 = nullptr, e1 = nullptr;
-            rc = events(0, &e0, &e1);
+            rc = reverse(q, pl->lam1(), pl->frec());
             if (rc != DTV_OK) return rc;
-            HIP_TRY(launch_fused_bwd(ba, nsub, s, e0, e1), "fused reverse steps");
-            HIP_TRY(launch_bwd_interface(pl->d_imgs(), pl->n, pl->max_nlam, pl->d_info(), pl->hb(),
-                                         pl->hb() + pl->tot_p1, pl->pb(), pl->pb() + pl->tot_p1, pl->lb(),
-                                         (float)P.tau, (float)P.sigma, s),
-                    "interface reverse");
         }
     }
     const int rows = pl->rows;

@@ -50,6 +50,7 @@ constexpr int kStreamCols = 63;   // output columns per wave
 constexpr int kRowChoices = 4;    // rows per strip of the streaming kernels: 4, 8, 16 or 32
 constexpr int kRecGroups = 9;     // float4 groups per thread in a step record of the fused kernel (fused_common.h)
 constexpr int kRecThreads = 1024; // threads of a fused workgroup
+constexpr size_t kSegRecordBytes = size_t(4) << 30;  // reverse mode: most bytes of step records kept at once
 inline int row_index(int R) { return R <= 4 ? 0 : R <= 8 ? 1 : R <= 16 ? 2 : 3; }
 constexpr int kFusedMax = 128;    // largest subdomain side handled by the fused kernel
 constexpr int kMaxFusedInner = 64;  // largest n_inner of the fused kernel
