@@ -181,3 +181,47 @@ def test_persistent_cp2_resume_and_oracle():
     o = oracle_for(f, alpha, rc, cc, fidelity="CV", inner="CP2", n_inner=3, **extra)
     o.run(8)
     compare(one, o)
+
+
+@pytest.mark.timeout(900)
+def test_cv2000_schedules_bitwise_and_oracle():
+    """The segmentation workload on 2000 x 2000 cut at multiples of 128 (the
+    last subdomain row and column 80 wide: framed tiles), at its benchmarked
+    length of 500 outer x 5 steps: the persistent, fused and streaming
+    schedules give bitwise the same state, which matches the oracle."""
+    c = synth.cv_case(size=2000)
+    rc = cc = synth.tile_cuts(2000, 128)
+    extra = dict(tau=c.tau, sigma=c.sigma, gamma=c.gamma, **c.extra)
+    res = {}
+    for sch in ("persistent", "fused", "stream"):
+        _say(f"[cv2000] {sch} {c.n_outer}x{c.n_inner}")
+        plan, st, _ = run_gpu(c.f, c.alpha, rc, cc, fidelity="CV", n_outer=c.n_outer, n_inner=c.n_inner,
+                              schedule=sch, **extra)
+        assert plan.schedule() == sch
+        res[sch] = gpu_image_state(plan, st)
+    for sch in ("fused", "stream"):
+        for q in res["persistent"]:
+            assert np.array_equal(res["persistent"][q], res[sch][q]), (sch, q)
+    _say("[cv2000] oracle (CPU)")
+    o = oracle_for(c.f, c.alpha, rc, cc, fidelity="CV", inner="CP2", n_inner=c.n_inner, **extra)
+    o.run(c.n_outer)
+    errs = compare(res["persistent"], o)
+    _say(f"  errors {errs}")
+
+
+def test_persistent_cp2_framed_l1_mask_long():
+    """Framed tiles keep the part of the frame outside the tile in registers
+    across outer steps: TV-L1 with an inpainting mask over 120 outer steps,
+    persistent against fused bitwise and against the oracle."""
+    f, mask, alpha, extra, rc, cc = _input("framed3x3", "l1_mask", 901)
+    res = {}
+    for sch in ("fused", "persistent"):
+        plan, st, _ = run_gpu(f, alpha, rc, cc, mask=mask, fidelity="L1", n_outer=120, n_inner=5, schedule=sch)
+        assert plan.schedule() == sch
+        res[sch] = gpu_image_state(plan, st)
+    for q in res["fused"]:
+        assert np.array_equal(res["fused"][q], res["persistent"][q]), q
+    o = oracle_for(f, alpha, rc, cc, fidelity="L1", inner="CP2", mask=mask, n_inner=5)
+    o.run(120)
+    errs = compare(res["persistent"], o)
+    _say(f"  framed L1 + mask, 120 outer: errors {errs}")
