@@ -33,6 +33,7 @@ FP32_PEAK_TFLOPS = 157.3  # MI355X vector FP32 (256 CUs x 128 lanes x 2 flops x 
 KERNEL_SOURCES = {
     "k_persist_fista": ["persist.hip", "exchange.h", "fused_common.h", "fista_ops.h", "dtvdd_internal.h"],
     "k_fused_fista": ["fused.hip", "fused_common.h", "fista_ops.h", "dtvdd_internal.h"],
+    "k_fused_fista_staggered": ["fused.hip", "fused_common.h", "fista_ops.h", "dtvdd_internal.h"],
     "k_fista_step": ["kernels.hip", "fista_ops.h", "dtvdd_internal.h"],
     "k_cp2_step": ["kernels.hip", "cp2_ops.h", "fista_ops.h", "dtvdd_internal.h"],
     "k_fused_cp2": ["fused_cp2.hip", "cp2_tile.h", "cp2_ops.h", "fused_common.h", "fista_ops.h", "dtvdd_internal.h"],

@@ -114,6 +114,7 @@ struct dtv_dd_plan {
     hipGraphExec_t gexec = nullptr;
     GraphKey gkey;
     bool fused_ok = false;  // every subdomain fits the fused kernel
+    int stagger_blocks = 0, stagger_ticks = 0;  // fused FISTA over many rounds of full tiles (fused.hip)
     bool persist_ok = false;  // the persistent schedule applies (full tiles, all resident, no per-step host work)
 
     uint64_t uid = 0;          // process-wide plan id (the scratch array records whose metadata it holds)
@@ -472,6 +473,17 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
         delete pl;
         return fail(DTV_EINVAL, "inner_tol needs the fused schedule's subdomains: at most 128 x 128 (FISTA), or "
                                 "128 x 128 or smaller with their short sides on the image boundary (CP2)");
+    }
+    if (p.inner == DTV_INNER_FISTA && pl->fused_ok && !pl->adaptive && pl->n_full == (int)pl->h_subs.size()) {
+        // more full tiles than four rounds of the device: delay half the CUs by about the on-chip part
+        // of a tile (c' and the steps: 1 us + 2.2 us per step, in 10 ns ticks; the best of a sweep of
+        // 5 to 15 us at 8192 x 8192 with 5 steps)
+        int dev = 0;
+        const int cap = hipGetDevice(&dev) == hipSuccess ? fused_capacity(dev) : 0;
+        if (cap > 0 && pl->n_full >= 4 * cap) {
+            pl->stagger_blocks = (cap / 2) & ~7;
+            pl->stagger_ticks = 100 + 220 * std::min(p.n_inner, kMaxFusedInner);
+        }
     }
     if (p.schedule == DTV_SCHED_FUSED && !pl->fused_ok) {
         delete pl;
@@ -863,6 +875,8 @@ static int solve_impl(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_mask, 
     fa.tau = (float)P.tau;
     fa.inv_tau = (float)pl->inv_tau;
     fa.n_inner = std::min(K, kMaxFusedInner);
+    fa.stagger_blocks = pl->stagger_blocks;
+    fa.stagger_ticks = pl->stagger_ticks;
     for (int k = 1; k <= fa.n_inner; ++k) fa.beta[k] = beta[k];
     if (pl->adaptive) {
         fa.n_inner = K;
@@ -1586,7 +1600,10 @@ extern "C" int dtv_dd_kernel_time(const dtv_dd_plan *pl, double *avg_ms, int64_t
     const bool mixed = pl->n_full < (int)pl->h_subs.size() && !pl->adaptive;
     if (name)
         *name = persist ? (cp2 ? "k_persist_cp2" : "k_persist_fista")
-                : fused ? (cp2 ? "k_fused_cp2" : mixed ? "k_fused_fista_mixed" : "k_fused_fista")
+                : fused ? (cp2 ? "k_fused_cp2"
+                               : mixed ? "k_fused_fista_mixed"
+                               : pl->stagger_blocks > 0 ? "k_fused_fista_staggered"
+                                                        : "k_fused_fista")
                         : (cp2 ? "k_cp2_step" : "k_fista_step");
     if (bytes_per_launch) {
         // Algorithmic HBM bytes of one timed launch (E = edge dofs of the torn

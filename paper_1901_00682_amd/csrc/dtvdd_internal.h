@@ -129,6 +129,9 @@ struct FusedArgs {
     double tol2;
     const float *beta_dev;
     int *counts;
+    // launches of many rounds of full tiles: delaying blocks ahead of the tiles and their
+    // delay in ticks of the 100 MHz constant clock (0: none; fused.hip)
+    int stagger_blocks, stagger_ticks;
 };
 
 // Fused local primal-dual solves on full 128 x 128 subdomains (fused_cp2.hip).
@@ -265,6 +268,8 @@ hipError_t launch_fused_bwd(const FusedBwdArgs &a, int nsub, hipStream_t s, hipE
 
 // whether the fused kernel can record its steps for this inner count (full tiles only)
 bool fused_record_supported(int K);
+// workgroups of the full-tile fused kernel resident on the device at once
+int fused_capacity(int device);
 // subs[0, nfull) are 128 x 128 tiles (specialised kernel), subs[nfull, nfull + nframed) framed
 // tiles (smaller, their short sides on the image boundary: the specialised kernel in a 128 x 128
 // frame), the rest any other tiles of at most 128 x 128 (the specialised kernel in a frame, with

@@ -433,6 +433,32 @@ __global__ __launch_bounds__(1024) void k_fused_fista(FusedArgs a, int first)
     fused_tile<kFull, KF, REC, ADAPT>(a, first + xcd_remap(blockIdx.x, gridDim.x), S, LS, red);
 }
 
+// Full tiles, fixed n_inner, in a launch of many rounds (more subdomains than the device holds at
+// once).  A workgroup's LDS fills a CU, so a tile's loads and stores never overlap its own steps,
+// and workgroups that start together stay in step: every CU loads, then every CU computes while
+// HBM idles.  Blocks [0, a.stagger_blocks) hold their CU for a.stagger_ticks of the 100 MHz
+// constant clock and leave, so that those CUs start their first tile later; from then on one
+// half of the CUs loads and stores while the other half runs its steps.  (The delaying blocks
+// are dealt to the XCDs round-robin like any others, half the CUs of each.)
+template <int KF>
+__global__ __launch_bounds__(1024) void k_fused_fista_staggered(FusedArgs a)
+{
+    __shared__ FusedLds S;
+    __shared__ float LS[4][kFusedMax];
+    __shared__ double red[1];
+    const int b = blockIdx.x, nd = a.stagger_blocks;
+    if (b < nd) {
+        if (threadIdx.x == 0) {
+            const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+            while (__builtin_amdgcn_s_memrealtime() - t0 < (unsigned long long)a.stagger_ticks)
+                __builtin_amdgcn_s_sleep(4);
+        }
+        __syncthreads();
+        return;
+    }
+    fused_tile<true, KF, false, false>(a, xcd_remap(b - nd, gridDim.x - nd), S, LS, red);
+}
+
 // Every kind of tile in one launch (fixed n_inner, no recording).  The list holds the full
 // tiles first, then the framed ones (short sides on the image boundary), then the others, which
 // run framed with masks; blocks [0, gpad) take the other tiles, [gpad, gpad + fpad) the framed
@@ -475,6 +501,7 @@ struct FullTable {
 using Full = FullTable<1, 2, 3, 4, 5, 6, 7, 8, 10>;
 
 using MixedKernel = void (*)(FusedArgs, int, int, int);
+using FusedKernel1 = void (*)(FusedArgs);
 
 template <int... Ks>
 struct MixedTable {
@@ -487,9 +514,28 @@ struct MixedTable {
 };
 using Mixed = MixedTable<1, 2, 3, 4, 5, 6, 7, 8, 10>;
 
+template <int... Ks>
+struct StaggerTable {
+    static FusedKernel1 get(int K)
+    {
+        FusedKernel1 k = nullptr;
+        ((K == Ks ? (k = k_fused_fista_staggered<Ks>, 0) : 0), ...);
+        return k ? k : k_fused_fista_staggered<0>;
+    }
+};
+using Stagger = StaggerTable<1, 2, 3, 4, 5, 6, 7, 8, 10>;
+
 }  // namespace
 
 bool fused_record_supported(int K) { return Full::get(K, true) != nullptr; }
+
+int fused_capacity(int device)
+{
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fused_fista<true, 0>, 1024, 0) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
+    return per_cu * cus;
+}
 
 namespace {
 
@@ -533,6 +579,15 @@ hipError_t launch_fused_fista(const FusedArgs &a, int nsub, int nfull, int nfram
             hipExtLaunchKernelGGL(km, dim3(grid), dim3(1024), 0, s, e0, e1, 0, a, nfull, nframed, ngen);
         else
             hipLaunchKernelGGL(km, dim3(grid), dim3(1024), 0, s, a, nfull, nframed, ngen);
+        return hipGetLastError();
+    }
+    if (npart == 0 && !a.rec && a.stagger_blocks > 0) {  // many rounds of full tiles
+        const FusedKernel1 k = Stagger::get(a.n_inner);
+        const int grid = nfull + a.stagger_blocks;
+        if (e0)
+            hipExtLaunchKernelGGL(k, dim3(grid), dim3(1024), 0, s, e0, e1, 0, a);
+        else
+            hipLaunchKernelGGL(k, dim3(grid), dim3(1024), 0, s, a);
         return hipGetLastError();
     }
     // the timing events bracket both launches

@@ -139,6 +139,33 @@ def test_fused_equals_stream_bitwise(geom, K):
     compare(res["fused"], o)
 
 
+@pytest.mark.parametrize("K", [5, 9])
+def test_staggered_fused_equals_stream_bitwise(K):
+    """An image of 32 x 32 full subdomains (four rounds of the device's 256 CUs
+    or more) runs the fused schedule as the staggered launch, whose first
+    workgroups only delay half the CUs: the tiles' arithmetic is the fused
+    kernel's, so the result equals the streaming schedule bitwise."""
+    import torch
+
+    props = torch.cuda.get_device_properties(0)
+    if 32 * 32 < 4 * props.multi_processor_count:
+        pytest.skip("the device holds a quarter of the subdomains at once")
+    rng = np.random.default_rng(500 + K)
+    H = W = 4096
+    cuts = np.arange(0, H + 1, 128)
+    f = rng.uniform(size=(H, W)).astype(np.float32)
+    _say(f"[staggered==stream] {H}x{W} K={K}")
+    res = {}
+    for sch in ("stream", "fused"):
+        plan, state, _, _, _ = run_gpu(f, 8.0, cuts, cuts, n_outer=3, n_inner=K, schedule=sch)
+        assert plan.schedule() == sch
+        if sch == "fused":
+            assert plan.kernel_time()["name"] == "k_fused_fista_staggered"
+        res[sch] = gpu_image_state(plan, state)
+    for q in res["stream"]:
+        assert np.array_equal(res["stream"][q], res["fused"][q]), q
+
+
 def test_parity_config1_with_diagnostics():
     c = synth.config1()
     _say("[parity] config1 64x64 2x2 100x10 with diagnostics")
