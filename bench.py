@@ -36,6 +36,7 @@ KERNEL_SOURCES = {
     "k_fused_fista_staggered": ["fused.hip", "fused_common.h", "fista_ops.h", "dtvdd_internal.h"],
     "k_fista_step": ["kernels.hip", "fista_ops.h", "dtvdd_internal.h"],
     "k_cp2_step": ["kernels.hip", "cp2_ops.h", "fista_ops.h", "dtvdd_internal.h"],
+    "k_cp2_pair": ["cp2_pair.hip", "cp2_ops.h", "fista_ops.h", "dtvdd_internal.h"],
     "k_fused_cp2": ["fused_cp2.hip", "cp2_tile.h", "cp2_ops.h", "fused_common.h", "fista_ops.h", "dtvdd_internal.h"],
     "k_persist_cp2": ["persist_cp2.hip", "cp2_tile.h", "cp2_ops.h", "exchange.h", "fused_common.h", "fista_ops.h",
                       "dtvdd_internal.h"],

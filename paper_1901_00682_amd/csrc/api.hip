@@ -96,6 +96,7 @@ struct dtv_dd_plan {
     std::vector<ImgDev> h_imgs;
     std::vector<int> h_info;
     std::vector<StreamTile> h_tiles[kRowChoices];  // streaming work lists, strips of 4 << ri rows
+    std::vector<StreamTile> h_ptiles[kRowChoices];  // the same for the two-step primal-dual kernel (kPairCols)
     std::vector<SubTile> h_subs;
     std::vector<float> h_beta;  // adaptive stopping: the FISTA momentum table (beta[k], k = 0 .. n_inner)
     std::vector<float> h_cp2tab;  // adaptive stopping: the primal-dual step scalars (FusedCp2Args::tab)
@@ -121,9 +122,11 @@ struct dtv_dd_plan {
     char *run_ws = nullptr;    // workspace of the last solve: the bound one, or the scratch array
     bool ran_persist = false;  // the last solve ran the persistent schedule (its error word is in run_ws)
     size_t buf_bytes = 0;      // bytes of each rotation buffer (0: the plan runs only the persistent schedule)
+    bool pairs = false;        // the streaming primal-dual schedule runs its local steps two per launch
 
     // workspace layout (byte offsets)
-    size_t off_imgs = 0, off_info = 0, off_tiles[kRowChoices] = {0, 0, 0, 0}, off_subs = 0, off_psubs = 0, off_buf[3] = {0, 0, 0},
+    size_t off_imgs = 0, off_info = 0, off_tiles[kRowChoices] = {0, 0, 0, 0}, off_ptiles[kRowChoices] = {0, 0, 0, 0},
+           off_subs = 0, off_psubs = 0, off_buf[4] = {0, 0, 0, 0},
            off_u2 = 0,
            off_part = 0, off_dout = 0, off_xch = 0, off_sync = 0, off_lamw = 0, ws_bytes = 0;
     int diag_nblk = 0;
@@ -174,6 +177,11 @@ struct dtv_dd_plan {
     const int *d_info() const { return (const int *)(ws + off_info); }
     const StreamTile *d_tiles(int R) const { return (const StreamTile *)(ws + off_tiles[row_index(R)]); }
     int ntiles(int R) const { return (int)h_tiles[row_index(R)].size(); }
+    const StreamTile *d_ptiles(int R) const { return (const StreamTile *)(ws + off_ptiles[row_index(R)]); }
+    int nptiles(int R) const { return (int)h_ptiles[row_index(R)].size(); }
+    // rotation buffer k: three always (FISTA: x in two, c' in the third), a fourth for the
+    // two-step primal-dual launches
+    size_t buf_size(int k) const { return k < 3 || pairs ? buf_bytes : 0; }
     float *buf1(int k) const { return (float *)(ws + off_buf[k]); }
     float *buf2(int k) const { return (float *)(ws + off_buf[k]) + tot_p1; }
     float *u2() const { return (float *)(ws + off_u2); }
@@ -353,6 +361,7 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
         return fail(DTV_EINVAL, "rows must be 0, 4, 8, 16 or 32");
     if (p.no_graphs != 0 && p.no_graphs != 1) return fail(DTV_EINVAL, "no_graphs must be 0 or 1");
     if (p.spin_limit < 0) return fail(DTV_EINVAL, "spin_limit must be >= 0");
+    if (p.steps_per_launch < 0 || p.steps_per_launch > 2) return fail(DTV_EINVAL, "steps_per_launch must be 0, 1 or 2");
 
     dtv_dd_plan *pl = new dtv_dd_plan();
     pl->uid = ++g_plan_ids;
@@ -434,6 +443,10 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
         for (int ri = 0; ri < kRowChoices; ++ri)
             for (int i0 = 0; i0 < h.H; i0 += 4 << ri)
                 for (int j0 = 0; j0 < h.W; j0 += kStreamCols) pl->h_tiles[ri].push_back(StreamTile{b, i0, j0, 0});
+        if (p.inner == DTV_INNER_CP2)
+            for (int ri = 0; ri < kRowChoices; ++ri)
+                for (int i0 = 0; i0 < h.H; i0 += 4 << ri)
+                    for (int j0 = 0; j0 < h.W; j0 += kPairCols) pl->h_ptiles[ri].push_back(StreamTile{b, i0, j0, 0});
         for (int r = 0; r < h.ny; ++r)
             for (int c = 0; c < h.nx; ++c)
                 pl->h_subs.push_back(SubTile{b, r, c, h.rcut[r], h.ccut[c], h.rcut[r + 1] - h.rcut[r],
@@ -552,13 +565,15 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
     pl->off_imgs = take(sizeof(ImgDev) * pl->h_imgs.size());
     pl->off_info = take(sizeof(int) * pl->h_info.size());
     for (int ri = 0; ri < kRowChoices; ++ri) pl->off_tiles[ri] = take(sizeof(StreamTile) * pl->h_tiles[ri].size());
+    for (int ri = 0; ri < kRowChoices; ++ri) pl->off_ptiles[ri] = take(sizeof(StreamTile) * pl->h_ptiles[ri].size());
     pl->off_subs = take(sizeof(SubTile) * pl->h_subs.size());
     pl->off_psubs = take(sizeof(SubTile) * std::max<size_t>(1, pl->p_subs.size()));
     // the persistent schedule updates p~, u and lambda in place: a plan that runs only that schedule
     // needs no rotation buffers, no second u and no second lambda state
     const bool persist_only = p.schedule == DTV_SCHED_PERSIST;
     pl->buf_bytes = persist_only ? 0 : sizeof(float) * (size_t)(pl->tot_p1 + pl->tot_p2);
-    for (int k = 0; k < 3; ++k) pl->off_buf[k] = take(pl->buf_bytes);
+    pl->pairs = p.inner == DTV_INNER_CP2 && !persist_only && p.n_inner >= 2 && p.steps_per_launch != 1;
+    for (int k = 0; k < 4; ++k) pl->off_buf[k] = take(pl->buf_size(k));
     pl->off_u2 = take(p.inner == DTV_INNER_CP2 && !persist_only ? sizeof(float) * (size_t)pl->tot_px : 0);
     pl->diag_nblk = diag_blocks_per_image(pl->maxH, pl->maxW);
     pl->off_part = take(sizeof(double) * 6 * (size_t)pl->diag_nblk * n_images);
@@ -679,6 +694,11 @@ extern "C" int dtv_dd_bind_workspace(dtv_dd_plan *pl, void *d_ws, size_t bytes)
         HIP_TRY(hipMemcpy(ws + pl->off_tiles[ri], pl->h_tiles[ri].data(), sizeof(StreamTile) * pl->h_tiles[ri].size(),
                           hipMemcpyHostToDevice),
                 "upload work list");
+    for (int ri = 0; ri < kRowChoices; ++ri)
+        if (!pl->h_ptiles[ri].empty())
+            HIP_TRY(hipMemcpy(ws + pl->off_ptiles[ri], pl->h_ptiles[ri].data(),
+                              sizeof(StreamTile) * pl->h_ptiles[ri].size(), hipMemcpyHostToDevice),
+                    "upload work list");
     HIP_TRY(hipMemcpy(ws + pl->off_subs, pl->h_subs.data(), sizeof(SubTile) * pl->h_subs.size(), hipMemcpyHostToDevice),
             "upload subdomain list");
     if (!pl->p_subs.empty())
@@ -686,8 +706,8 @@ extern "C" int dtv_dd_bind_workspace(dtv_dd_plan *pl, void *d_ws, size_t bytes)
                           hipMemcpyHostToDevice),
                 "upload subdomain groups");
     // rotation buffers start at zero so that their boundary (non-dof) edges are 0
-    for (int k = 0; k < 3; ++k)
-        if (pl->buf_bytes) HIP_TRY(hipMemset(ws + pl->off_buf[k], 0, pl->buf_bytes), "clear buffers");
+    for (int k = 0; k < 4; ++k)
+        if (pl->buf_size(k)) HIP_TRY(hipMemset(ws + pl->off_buf[k], 0, pl->buf_size(k)), "clear buffers");
     // reverse-mode buffers: the step kernels write dof edges only, so the
     // boundary entries of every edge buffer must start (and stay) at zero
     if (pl->prm.save_for_backward)
@@ -801,7 +821,7 @@ struct Timer {
 static std::vector<float> fista_betas(int K);
 
 // next rotation state of the edge buffers after one outer step (see outer_step)
-static int next_base(int sched, bool cp2, int K, int base)
+static int next_base(int sched, bool cp2, int K, int base, bool pairs)
 {
     if (sched == DTV_SCHED_PERSIST) return base;
     if (sched == DTV_SCHED_FUSED) return base == 0 ? 1 : 0;  // the fused kernels read one buffer and write the other
@@ -811,11 +831,17 @@ static int next_base(int sched, bool cp2, int K, int base)
             if (k != base) rot[q++] = k;
         return rot[K % 3];
     }
-    int sc[3], q = 0;
-    for (int k = 0; k < 4; ++k)
+    // primal-dual: x_k in the (k - 1)-th of the buffers other than the base, three of them (four
+    // with two-step launches, which write x_k and x_(k+1) while reading x_(k-1) and x_(k-2))
+    const int nb = pairs ? 5 : 4, ns = nb - 1;
+    int sc[4] = {0, 0, 0, 0}, q = 0;
+    for (int k = 0; k < nb; ++k)
         if (k != base) sc[q++] = k;
-    return sc[(K - 1) % 3];
+    return sc[(K - 1) % ns];
 }
+
+// launches of one streaming primal-dual outer step (each swaps the two u buffers)
+static int cp2_launches(int K, bool pairs) { return pairs ? K / 2 + (K & 1) : K; }
 
 // Arguments every solve entry point checks before anything is enqueued.
 static int check_solve_args(const dtv_dd_plan *pl, const float *d_f, const uint8_t *d_mask, const float *d_u,
@@ -856,7 +882,8 @@ static int solve_impl(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_mask, 
     cp2_steps(P, K, tk, sk, th);
 
     // edge buffers: 0 = the caller's p~, 1..3 = workspace
-    EdgeBuf bufs[4] = {{d_p1, d_p2}, {pl->buf1(0), pl->buf2(0)}, {pl->buf1(1), pl->buf2(1)}, {pl->buf1(2), pl->buf2(2)}};
+    EdgeBuf bufs[5] = {{d_p1, d_p2}, {pl->buf1(0), pl->buf2(0)}, {pl->buf1(1), pl->buf2(1)}, {pl->buf1(2), pl->buf2(2)},
+                       {pl->buf1(3), pl->buf2(3)}};
     int base = 0;
     float *u_cur = d_u;       // CP2: current u buffer (d_u or the workspace copy)
     float *lam_cur = d_lambda;  // current lambda state (the fused schedule alternates with the workspace copy)
@@ -964,7 +991,7 @@ static int solve_impl(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_mask, 
                     "lambda update");
         // (a2)+(a3) local solves; the anchor phat is formed on the fly from p~^n and lambda
         if (sched == DTV_SCHED_FUSED && cp2) {
-            const int out = next_base(sched, cp2, K, base);
+            const int out = next_base(sched, cp2, K, base, pl->pairs);
             FusedCp2Args ca = cp2_args();
             ca.out1 = bufs[out].p1;
             ca.out2 = bufs[out].p2;
@@ -980,7 +1007,7 @@ static int solve_impl(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_mask, 
             base = out;
             lam_cur = lam_other();
         } else if (sched == DTV_SCHED_FUSED) {
-            const int out = next_base(sched, cp2, K, base);
+            const int out = next_base(sched, cp2, K, base, pl->pairs);
             fa.base1 = bufs[base].p1; fa.base2 = bufs[base].p2;
             fa.out1 = bufs[out].p1; fa.out2 = bufs[out].p2;
             fa.lam = lam_cur;
@@ -1019,13 +1046,45 @@ static int solve_impl(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_mask, 
             }
             base = rot[K % 3];
         } else {
-            int sc[3], r = 0;
-            for (int k = 0; k < 4; ++k)
+            // x_k in sc[(k - 1) % ns]: the ns buffers other than the base (next_base); each launch
+            // reads x_(k-1) and x_(k-2) and writes x_k (and x_(k+1)) to other buffers
+            const int nb = pl->pairs ? 5 : 4, ns = nb - 1;
+            int sc[4] = {0, 0, 0, 0}, r = 0;
+            for (int k = 0; k < nb; ++k)
                 if (k != base) sc[r++] = k;
-            for (int k = 1; k <= K; ++k) {
-                const int ia = k == 1 ? base : sc[(k - 2) % 3];
-                const int ib = k >= 3 ? sc[(k - 3) % 3] : base;
-                const int io = sc[(k - 1) % 3];
+            auto xbuf = [&](int k) { return k <= 0 ? base : sc[(k - 1) % ns]; };
+            int k = 1;
+            for (; pl->pairs && k + 1 <= K; k += 2) {  // steps k and k + 1 in one launch
+                const int it = k - 1;
+                Cp2PairArgs a{};
+                a.imgs = pl->d_imgs(); a.tiles = pl->d_ptiles(rows); a.ntiles = pl->nptiles(rows); a.info = pl->d_info();
+                const int ia = xbuf(k - 1), ib = xbuf(k - 2);
+                a.xa1 = bufs[ia].p1; a.xa2 = bufs[ia].p2; a.xb1 = bufs[ib].p1; a.xb2 = bufs[ib].p2;
+                a.base1 = bufs[base].p1; a.base2 = bufs[base].p2; a.lam = lam_cur; a.f = d_f; a.mask = mask;
+                float *u_next = u_cur == d_u ? pl->u2() : d_u;
+                a.u_in = u_cur; a.u_out = u_next;
+                a.outk1 = bufs[xbuf(k)].p1; a.outk2 = bufs[xbuf(k)].p2;
+                a.outn1 = bufs[xbuf(k + 1)].p1; a.outn2 = bufs[xbuf(k + 1)].p2;
+                a.theta_a = it >= 1 ? (float)th[it - 1] : 0.0f;
+                a.sk_a = (float)sk[it]; a.tk_a = (float)tk[it];
+                a.ck_a = cp2_keep(P, tk[it]); a.ca_a = cp2_anchor(P, tk[it]);
+                a.theta_b = (float)th[it];
+                a.sk_b = (float)sk[it + 1]; a.tk_b = (float)tk[it + 1];
+                a.ck_b = cp2_keep(P, tk[it + 1]); a.ca_b = cp2_anchor(P, tk[it + 1]);
+                a.tau = (float)P.tau;
+                a.fidelity = P.fidelity;
+                a.cv_c1 = (float)P.cv_c1;
+                a.cv_c2 = (float)P.cv_c2;
+                int rc = with_host ? tm.begin() : DTV_OK;
+                if (rc != DTV_OK) return rc;
+                HIP_TRY(launch_cp2_pair(a, it >= 1, rows, q, with_host ? tm.e0 : nullptr, with_host ? tm.e1 : nullptr),
+                        "CP2 step pair");
+                rc = with_host ? tm.end() : DTV_OK;
+                if (rc != DTV_OK) return rc;
+                u_cur = u_next;
+            }
+            for (; k <= K; ++k) {
+                const int ia = xbuf(k - 1), ib = xbuf(k - 2), io = xbuf(k);
                 const int it = k - 1;
                 Cp2StepArgs a{};
                 a.imgs = pl->d_imgs(); a.tiles = pl->d_tiles(rows); a.ntiles = pl->ntiles(rows); a.info = pl->d_info();
@@ -1049,7 +1108,7 @@ static int solve_impl(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_mask, 
                 if (rc != DTV_OK) return rc;
                 u_cur = u_next;
             }
-            base = sc[(K - 1) % 3];
+            base = xbuf(K);
         }
         const bool last = n == P.n_outer - 1;
         if (with_host && P.diag_every > 0 && ((n + 1) % P.diag_every == 0 || last)) {
@@ -1136,8 +1195,8 @@ static int solve_impl(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_mask, 
             bool uf = u_cur != d_u, lp = lam_cur != d_lambda;
             for (int i = 0; i < 8; ++i) {
                 seq.push_back(state(b, uf, lp));
-                b = next_base(sched, cp2, K, b);
-                if (cp2 && sched != DTV_SCHED_FUSED && (K & 1)) uf = !uf;
+                b = next_base(sched, cp2, K, b, pl->pairs);
+                if (cp2 && sched != DTV_SCHED_FUSED && (cp2_launches(K, pl->pairs) & 1)) uf = !uf;
                 if (sched == DTV_SCHED_FUSED) lp = !lp;
             }
             int start = -1, period = 0;
@@ -1604,7 +1663,7 @@ extern "C" int dtv_dd_kernel_time(const dtv_dd_plan *pl, double *avg_ms, int64_t
                                : mixed ? "k_fused_fista_mixed"
                                : pl->stagger_blocks > 0 ? "k_fused_fista_staggered"
                                                         : "k_fused_fista")
-                        : (cp2 ? "k_cp2_step" : "k_fista_step");
+                        : (cp2 ? (pl->pairs ? "k_cp2_pair" : "k_cp2_step") : "k_fista_step");
     if (bytes_per_launch) {
         // Algorithmic HBM bytes of one timed launch (E = edge dofs of the torn
         // p~, N = pixels, 4 bytes each), averaged over the launches of an outer step.
@@ -1615,6 +1674,9 @@ extern "C" int dtv_dd_kernel_time(const dtv_dd_plan *pl, double *avg_ms, int64_t
         //   streaming FISTA step k >= 3: read x_{k-1}, x_{k-2}, c', write x_k       4 (4E)
         //   CP2 step 1: read x_0, u, f (+ mask bytes), write x_1, u                 4 (2E + 3N) + mask
         //   CP2 step k >= 2: read x_{k-1}, x_{k-2}, anchor base, u, f (+ mask), write 4 (4E + 3N) + mask
+        //   CP2 two-step launch (k, k + 1): read x_{k-1}, x_{k-2} (k >= 2), anchor base, u, f (+ mask),
+        //     write x_k, x_{k+1}, u                                 4 (5E + 3N) + mask (k = 1: 4 (3E + 3N) + mask)
+        //   (the streaming CP2 figure is the average over the launches of an outer step)
         double E = 0.0, N = 0.0;
         for (const ImgHost &h : pl->imgs) {
             E += (double)(h.H + h.ny) * h.W + (double)h.H * (h.W + h.nx);
@@ -1634,6 +1696,11 @@ extern "C" int dtv_dd_kernel_time(const dtv_dd_plan *pl, double *avg_ms, int64_t
             *bytes_per_launch = 4.0 * (2 * E + 3 * N) + mb;
         } else if (fused) {
             *bytes_per_launch = 4.0 * (2 * E + N);
+        } else if (cp2 && pl->pairs) {
+            int k = 1, nl = 0;
+            for (; k + 1 <= K; k += 2, ++nl) tot += (k == 1 ? 4.0 * (3 * E + 3 * N) : 4.0 * (5 * E + 3 * N)) + mb;
+            for (; k <= K; ++k, ++nl) tot += (k == 1 ? 4.0 * (2 * E + 3 * N) : 4.0 * (4 * E + 3 * N)) + mb;
+            *bytes_per_launch = tot / nl;
         } else {
             for (int k = 1; k <= K; ++k) {
                 if (cp2) tot += (k == 1 ? 4.0 * (2 * E + 3 * N) : 4.0 * (4 * E + 3 * N)) + mb;
@@ -1716,6 +1783,11 @@ static int upload_async(dtv_dd_plan *pl, char *ws, hipStream_t s)
         HIP_TRY(hipMemcpyAsync(ws + pl->off_tiles[ri], pl->h_tiles[ri].data(), sizeof(StreamTile) * pl->h_tiles[ri].size(),
                                hipMemcpyHostToDevice, s),
                 "upload work list");
+    for (int ri = 0; ri < kRowChoices; ++ri)
+        if (!pl->h_ptiles[ri].empty())
+            HIP_TRY(hipMemcpyAsync(ws + pl->off_ptiles[ri], pl->h_ptiles[ri].data(),
+                                   sizeof(StreamTile) * pl->h_ptiles[ri].size(), hipMemcpyHostToDevice, s),
+                    "upload work list");
     HIP_TRY(hipMemcpyAsync(ws + pl->off_subs, pl->h_subs.data(), sizeof(SubTile) * pl->h_subs.size(),
                            hipMemcpyHostToDevice, s),
             "upload subdomain list");
@@ -1723,8 +1795,8 @@ static int upload_async(dtv_dd_plan *pl, char *ws, hipStream_t s)
         HIP_TRY(hipMemcpyAsync(ws + pl->off_psubs, pl->p_subs.data(), sizeof(SubTile) * pl->p_subs.size(),
                                hipMemcpyHostToDevice, s),
                 "upload subdomain groups");
-    for (int k = 0; k < 3; ++k)
-        if (pl->buf_bytes) HIP_TRY(launch_fill_zero(ws + pl->off_buf[k], pl->buf_bytes, s), "clear buffers");
+    for (int k = 0; k < 4; ++k)
+        if (pl->buf_size(k)) HIP_TRY(launch_fill_zero(ws + pl->off_buf[k], pl->buf_size(k), s), "clear buffers");
     return DTV_OK;
 }
 

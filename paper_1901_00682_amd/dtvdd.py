@@ -55,7 +55,8 @@ class Params(ctypes.Structure):
                 ("save_for_backward", ctypes.c_int32), ("ckpt_every", ctypes.c_int32),
                 ("schedule", ctypes.c_int32), ("time_kernels", ctypes.c_int32), ("rows", ctypes.c_int32),
                 ("no_graphs", ctypes.c_int32), ("cv_c1", ctypes.c_double), ("cv_c2", ctypes.c_double),
-                ("full_problem", ctypes.c_int32), ("spin_limit", ctypes.c_int32), ("inner_tol", ctypes.c_double)]
+                ("full_problem", ctypes.c_int32), ("spin_limit", ctypes.c_int32), ("inner_tol", ctypes.c_double),
+                ("steps_per_launch", ctypes.c_int32)]
 
 
 class Layout(ctypes.Structure):
@@ -148,7 +149,7 @@ class Plan:
                  sigma0=1.0 / 80.0, gamma=None, n_outer=100, n_inner=10, diag_every=0, gap_tol=0.0,
                  warm_start=False, save_for_backward=False, ckpt_every=20, schedule="auto",
                  time_kernels=False, rows=0, graphs=True, c1=0.6, c2=0.1, full_problem=False, inner_tol=0.0,
-                 spin_limit=0, device=None, bind=True):
+                 spin_limit=0, steps_per_launch=0, device=None, bind=True):
         import torch
 
         L = lib()
@@ -172,7 +173,7 @@ class Plan:
                              int(diag_every), float(gap_tol), int(warm_start), int(save_for_backward),
                              int(ckpt_every), SCHEDULE[schedule], int(time_kernels), int(rows),
                              int(not graphs), float(c1), float(c2), int(full_problem), int(spin_limit),
-                             float(inner_tol))
+                             float(inner_tol), int(steps_per_launch))
         h = ctypes.c_void_p()
         _check(L.dtv_dd_setup(descs, len(self.images), ctypes.byref(self.params), ctypes.byref(h)))
         self.h = h
