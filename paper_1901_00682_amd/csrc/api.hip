@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "dtvdd.h"
+#include "cp2_pair.h"
 #include "dtvdd_internal.h"
 
 using namespace dtv;

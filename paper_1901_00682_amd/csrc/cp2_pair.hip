@@ -24,7 +24,7 @@
 // The per-element arithmetic is that of the one-step kernel (cp2_ops.h), in
 // the same order, so a pair launch equals two one-step launches bitwise.
 #include "cp2_ops.h"
-#include "dtvdd_internal.h"
+#include "cp2_pair.h"
 #include "fista_ops.h"
 
 namespace dtv {
