@@ -43,21 +43,22 @@ struct PairRow {
 
 // what step k leaves of a row for step k + 1
 struct PairMid {
-    int rw;
+    int rw;                            // row info word, with bit 31 set when the pixel is observed
     float u;                           // u_k
     float kt, kl, kb, kr;              // x_k on the top, left, bottom (last row), right (last column) edges
     float mt, ml, mb, mr;              // x_{k-1} on the same edges (mb, mr: the bottom and right edges)
     float fv;
-    unsigned mv;
-    float at, al, ab, ar, lt, ll, lb, lr;
+    float at, al, ab, ar;              // the anchors phat of the four edges (-/+ tau lambda on interface copies)
 };
 
 }  // namespace
 
 // EXT: step k extrapolates xbar_{k-1} = x_{k-1} + theta_{k-1} (x_{k-1} - x_{k-2}) (k >= 2); step
-// k + 1 always extrapolates xbar_k = x_k + theta_k (x_k - x_{k-1}).
+// k + 1 always extrapolates xbar_k = x_k + theta_k (x_k - x_{k-1}).  The kernel is bound by memory
+// latency, so it asks for five waves per SIMD (at most 96 VGPRs; the one value that then spills is
+// stored before the row loop and reloaded after it).
 template <int R, bool EXT>
-__global__ __launch_bounds__(64) void k_cp2_pair(Cp2PairArgs a)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_cp2_pair(Cp2PairArgs a)
 {
     const int t = xcd_remap(blockIdx.x, gridDim.x);
     const StreamTile tile = a.tiles[t];
@@ -151,8 +152,9 @@ __global__ __launch_bounds__(64) void k_cp2_pair(Cp2PairArgs a)
     // row of a subdomain); stores u_{k+1}, x_k and x_{k+1} of rows inside the strip
     float u_upB = 0.0f;
     auto step_b = [&](int q, const PairMid &m, float kbot, float mbot) {
-        const bool rfirst = info_first(m.rw), rlast = info_last(m.rw);
-        const long long tp = q + info_sub(m.rw);
+        const int rw = m.rw & 0x7FFFFFFF;
+        const bool rfirst = info_first(rw), rlast = info_last(rw);
+        const long long tp = q + info_sub(rw);
         const long long px = (long long)q * W + j;
         if (rfirst) u_upB = 0.0f;
         // x_k on the right edge: the next lane's left edge, or the column's own at a subdomain's last column
@@ -163,7 +165,7 @@ __global__ __launch_bounds__(64) void k_cp2_pair(Cp2PairArgs a)
             const float bxt = xbarB(m.kt, m.mt);
             const float bxb = xbarB(kbot, mbot);
             const float d = (bxb - bxt) + (xbarB(krr, m.mr) - xbarB(m.kl, m.ml));
-            u1 = cp2_u(fid, m.u, d, skb, m.fv, m.mv != 0, sab, cv1, cv2);
+            u1 = cp2_u(fid, m.u, d, skb, m.fv, m.rw < 0, sab, cv1, cv2);
         }
         float u_left = __shfl_up(u1, 1, 64);
         if (cfirst) u_left = 0.0f;
@@ -171,19 +173,19 @@ __global__ __launch_bounds__(64) void k_cp2_pair(Cp2PairArgs a)
             uout[px] = u1;
             if (q > 0) {
                 ka1[tp * P1 + j] = m.kt;
-                kb1[tp * P1 + j] = pupB(m.kt, u_upB - u1, rfirst ? fmaf(tau, m.lt, m.at) : m.at);
+                kb1[tp * P1 + j] = pupB(m.kt, u_upB - u1, m.at);
             }
             if (j > 0) {
                 ka2[q * P2 + left] = m.kl;
-                kb2[q * P2 + left] = pupB(m.kl, u_left - u1, cfirst ? fmaf(tau, m.ll, m.al) : m.al);
+                kb2[q * P2 + left] = pupB(m.kl, u_left - u1, m.al);
             }
             if (rlast && q < H - 1) {
                 ka1[(tp + 1) * P1 + j] = m.kb;
-                kb1[(tp + 1) * P1 + j] = pupB(m.kb, u1, fmaf(-tau, m.lb, m.ab));
+                kb1[(tp + 1) * P1 + j] = pupB(m.kb, u1, m.ab);
             }
             if (clast && j < W - 1) {
                 ka2[q * P2 + left + 1] = m.kr;
-                kb2[q * P2 + left + 1] = pupB(m.kr, u1, fmaf(-tau, m.lr, m.ar));
+                kb2[q * P2 + left + 1] = pupB(m.kr, u1, m.ar);
             }
         }
         u_upB = u1;
@@ -215,26 +217,22 @@ __global__ __launch_bounds__(64) void k_cp2_pair(Cp2PairArgs a)
         if (cfirst) u_left = 0.0f;
         // x_k on the row's edges (0 on the image boundary, where the buffers hold 0)
         PairMid m;
-        m.rw = cur.rw;
+        m.rw = cur.rw | (cur.mv != 0 ? (int)0x80000000u : 0);
         m.u = u;
-        m.kt = i > 0 ? pupA(xt, u_upA - u, rfirst ? fmaf(tau, cur.lt, cur.at) : cur.at) : 0.0f;
-        m.kl = j > 0 ? pupA(cur.xl, u_left - u, cfirst ? fmaf(tau, cur.ll, cur.al) : cur.al) : 0.0f;
-        m.kb = (rlast && i < H - 1) ? pupA(cur.xb, u, fmaf(-tau, cur.lb, cur.ab)) : 0.0f;
-        m.kr = (clast && j < W - 1) ? pupA(cur.xr, u, fmaf(-tau, cur.lr, cur.ar)) : 0.0f;
+        // the anchors of both steps: t copies + tau lambda, s copies - tau lambda
+        m.at = rfirst ? fmaf(tau, cur.lt, cur.at) : cur.at;
+        m.al = cfirst ? fmaf(tau, cur.ll, cur.al) : cur.al;
+        m.ab = fmaf(-tau, cur.lb, cur.ab);
+        m.ar = fmaf(-tau, cur.lr, cur.ar);
+        m.kt = i > 0 ? pupA(xt, u_upA - u, m.at) : 0.0f;
+        m.kl = j > 0 ? pupA(cur.xl, u_left - u, m.al) : 0.0f;
+        m.kb = (rlast && i < H - 1) ? pupA(cur.xb, u, m.ab) : 0.0f;
+        m.kr = (clast && j < W - 1) ? pupA(cur.xr, u, m.ar) : 0.0f;
         m.mt = xt;
         m.ml = cur.xl;
         m.mb = cur.xb;
         m.mr = cur.xr;
         m.fv = cur.fv;
-        m.mv = cur.mv;
-        m.at = cur.at;
-        m.al = cur.al;
-        m.ab = cur.ab;
-        m.ar = cur.ar;
-        m.lt = cur.lt;
-        m.ll = cur.ll;
-        m.lb = cur.lb;
-        m.lr = cur.lr;
         // ---- step k + 1 on the row above, now that x_k on its bottom edge is known
         if (have_prev) {
             const bool plast = info_last(prev.rw);
