@@ -99,8 +99,9 @@ extern "C" {
                                 (FISTA: subdomains up to 128 x 128; CP2: 128 x 128, or smaller
                                 with the short sides on the image boundary) */
 #define DTV_SCHED_PERSIST 3  /* one cooperative launch runs every outer step; the iterates stay
-                                on chip between outer steps (no diagnostics, no
-                                save_for_backward).  FISTA with a fixed inner count: every
+                                on chip between outer steps (no diagnostics; with
+                                save_for_backward one launch per checkpoint segment, the
+                                state saved between them).  FISTA with a fixed inner count: every
                                 subdomain at most 128 x 128 (smaller ones run in a 128 x 128
                                 frame); each image's subdomains resident on the device at
                                 once, the images run in groups of launches.  CP2: every

@@ -513,7 +513,7 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
         const int nsub = (int)pl->h_subs.size();
         const bool fista = p.inner == DTV_INNER_FISTA;
         const bool one_launch = !fista || pl->adaptive;
-        pl->persist_ok = pl->fused_ok && nsub > 0 && p.diag_every == 0 && !p.save_for_backward &&
+        pl->persist_ok = pl->fused_ok && nsub > 0 && p.diag_every == 0 &&
                          (fista || pl->n_full + pl->n_framed == nsub);
         int dev = 0;
         if (pl->persist_ok && hipGetDevice(&dev) == hipSuccess && persist_supported(dev)) {
@@ -553,7 +553,7 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
         return fail(DTV_EINVAL, "the persistent schedule needs n_inner <= 64 (or inner_tol), every subdomain 128 x "
                                 "128 (fixed-count FISTA: or smaller with its short sides on the image boundary), "
                                 "each image's subdomains resident on the device at once (primal-dual or inner_tol: "
-                                "all of them), diag_every = 0 and no save_for_backward");
+                                "all of them) and diag_every = 0");
     }
 
     // workspace layout
@@ -571,7 +571,8 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
     pl->off_psubs = take(sizeof(SubTile) * std::max<size_t>(1, pl->p_subs.size()));
     // the persistent schedule updates p~, u and lambda in place: a plan that runs only that schedule
     // needs no rotation buffers, no second u and no second lambda state
-    const bool persist_only = p.schedule == DTV_SCHED_PERSIST;
+    // (a plan that keeps checkpoints recomputes its outer steps with the other kernels in reverse mode)
+    const bool persist_only = p.schedule == DTV_SCHED_PERSIST && !p.save_for_backward;
     pl->buf_bytes = persist_only ? 0 : sizeof(float) * (size_t)(pl->tot_p1 + pl->tot_p2);
     pl->pairs = p.inner == DTV_INNER_CP2 && !persist_only && p.n_inner >= 2 && p.steps_per_launch != 1;
     for (int k = 0; k < 4; ++k) pl->off_buf[k] = take(pl->buf_size(k));
@@ -1186,7 +1187,19 @@ static int solve_impl(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_mask, 
     // to its start after 1, 2 or 3 steps) when there is no host work per step.
     auto run_range = [&](int n0, int n1, int sched, int rows, bool graphs) -> int {
         if (n1 <= n0) return DTV_OK;
-        if (sched == DTV_SCHED_PERSIST) return run_persist(n1 - n0);
+        if (sched == DTV_SCHED_PERSIST) {
+            if (!P.save_for_backward) return run_persist(n1 - n0);
+            // with checkpoints: one launch per segment of ckpt_every outer steps, the state saved before it
+            const int C = P.ckpt_every;
+            for (int m = n0; m < n1;) {
+                const int next = std::min(n1, (m / C + 1) * C);
+                int rc = m % C == 0 ? save_state(m / C, bufs[base]) : DTV_OK;
+                if (rc == DTV_OK) rc = run_persist(next - m);
+                if (rc != DTV_OK) return rc;
+                m = next;
+            }
+            return DTV_OK;
+        }
         int n = n0;
         if (graphs && !host_work && !P.no_graphs && n1 - n0 >= 4) {
             // the buffer state (base, which u buffer is current) after each step

@@ -109,3 +109,26 @@ def test_fused_backward_long_horizon_well_conditioned():
     assert s_f < 5e-5 and s_a < 5e-5  # the conditioning this test relies on
     assert e_f <= 1e-4
     assert e_a <= 1e-4
+
+
+def test_backward_after_persistent_forward_equals_fused_forward():
+    """A plan that keeps checkpoints may run its forward on the persistent
+    schedule (one cooperative launch per checkpoint segment, the state saved
+    between them): the checkpoints, and so the gradients, are bitwise those of
+    the fused forward."""
+    from paper_1901_00682_amd import dtvdd
+    H, W = 256, 384
+    rc, cc = np.arange(0, H + 1, 128), np.arange(0, W + 1, 128)
+    f, ubar = _problem(H, W, 33)
+    res = {}
+    for sch in ("persistent", "fused"):
+        plan = dtvdd.Plan([dtvdd.Image(H, W, rc, cc, 8.0)], n_outer=23, n_inner=5, save_for_backward=True,
+                          ckpt_every=5, schedule=sch)
+        ft = torch.from_numpy(f.ravel()).cuda()
+        st, _ = plan.solve(ft, want_stats=False)
+        gf, ga = plan.backward(ft, torch.from_numpy(ubar.astype(np.float32).ravel()).cuda())
+        torch.cuda.synchronize()
+        assert plan.schedule() == sch
+        res[sch] = (st["u"].cpu().numpy().copy(), gf.cpu().numpy().copy(), ga.cpu().numpy().copy())
+    for a, b in zip(res["persistent"], res["fused"]):
+        assert np.array_equal(a, b)
