@@ -36,8 +36,8 @@ KERNEL_SOURCES = {
     "k_fused_fista_staggered": ["fused.hip", "fused_common.h", "fista_ops.h", "dtvdd_internal.h"],
     "k_fista_step": ["kernels.hip", "fista_ops.h", "dtvdd_internal.h"],
     "k_cp2_step": ["kernels.hip", "cp2_ops.h", "fista_ops.h", "dtvdd_internal.h"],
-    # (an odd n_inner ends with a one-step launch, timed with the two-step ones)
-    "k_cp2_pair": ["cp2_pair.hip", "cp2_pair.h", "kernels.hip", "cp2_ops.h", "fista_ops.h", "dtvdd_internal.h"],
+    # (a one-step launch that ends an outer step is timed with the multi-step ones)
+    "k_cp2_multi": ["cp2_multi.hip", "cp2_multi.h", "kernels.hip", "cp2_ops.h", "fista_ops.h", "dtvdd_internal.h"],
     "k_fused_cp2": ["fused_cp2.hip", "cp2_tile.h", "cp2_ops.h", "fused_common.h", "fista_ops.h", "dtvdd_internal.h"],
     "k_persist_cp2": ["persist_cp2.hip", "cp2_tile.h", "cp2_ops.h", "exchange.h", "fused_common.h", "fista_ops.h",
                       "dtvdd_internal.h"],
@@ -420,7 +420,8 @@ def main():
     ap.add_argument("--schedule", default="auto")
     ap.add_argument("--rows", type=int, default=0, help="streaming strip height (0: the plan picks)")
     ap.add_argument("--steps-per-launch", type=int, default=0,
-                    help="streaming primal-dual schedule: local steps per launch (1 or 2; 0: the plan's default, 2)")
+                    help="streaming primal-dual schedule: the most local steps per launch (1 .. 5; 0: the plan's "
+                         "default)")
     ap.add_argument("--cpu-outer", type=int, default=500, help="outer steps of the oracle sample (0: skip)")
     ap.add_argument("--cpu-outer-single", type=int, default=20, help="outer steps of the one-thread oracle sample")
     ap.add_argument("--no-extra", action="store_true", help="default workload: skip the batched and backward blocks")

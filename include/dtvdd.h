@@ -173,11 +173,13 @@ typedef struct {
                                   only: every subdomain at most 128 x 128 (FISTA), or 128 x 128
                                   or smaller with its short sides on the image boundary (CP2);
                                   no save_for_backward.  0: fixed n_inner steps */
-    int32_t steps_per_launch;  /* streaming schedule of the primal-dual local solver (CP2): local
-                                  steps per launch.  0 or 2: two consecutive steps per launch
-                                  (their intermediate x and u stay in registers; an odd n_inner ends
-                                  with a one-step launch), the same result bitwise as 1; 1: one
-                                  step per launch.  Ignored by the other schedules and by FISTA */
+    int32_t steps_per_launch;  /* streaming schedule of the primal-dual local solver (CP2): the most
+                                  local steps one launch runs, 1 .. 5 (0: the library's default, 5).
+                                  The n_inner steps of an outer step are cut into the fewest
+                                  launches of at most that many steps, as evenly as possible (5
+                                  steps at 3 per launch: 3 + 2); the intermediate x and u of a
+                                  launch stay in registers.  Every value gives the same result
+                                  bitwise.  Ignored by the other schedules and by FISTA */
 } dtv_dd_params;
 
 /* Where image `image` lives in the concatenated buffers (element offsets). */

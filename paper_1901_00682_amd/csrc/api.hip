@@ -14,7 +14,7 @@
 #include <vector>
 
 #include "dtvdd.h"
-#include "cp2_pair.h"
+#include "cp2_multi.h"
 #include "dtvdd_internal.h"
 
 using namespace dtv;
@@ -44,6 +44,51 @@ int hip_fail(hipError_t e, const char *what)
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 int pitch_of(int n) { return (int)align_up((size_t)n, 64); }
+
+// steps per launch of the streaming primal-dual schedule when the parameters leave it open (the
+// most a launch runs: n_inner = 5 in one launch, 10 in two)
+constexpr int kDefaultStepsPerLaunch = kMaxMultiSteps;
+
+// The local steps of one streaming primal-dual outer step cut into launches of at most spl steps,
+// as evenly as the launch count allows, longer launches first (K = 5: spl 2 -> 2 2 1, spl 3 or 4
+// -> 3 2, spl 5 -> 5).
+std::vector<int> cp2_launch_steps(int K, int spl)
+{
+    std::vector<int> v;
+    if (spl <= 1) {
+        v.assign(K, 1);
+        return v;
+    }
+    const int n = (K + spl - 1) / spl;
+    for (int i = 0; i < n; ++i) v.push_back(K / n + (i < K % n ? 1 : 0));
+    return v;
+}
+
+// One launch of that sequence: steps k0 .. k0 + steps - 1, reading x_{k0-1} from edge buffer ia and
+// x_{k0-2} from ib, writing x_{k0+steps-2} to ic (steps >= 2) and x_{k0+steps-1} to id.
+struct Cp2Launch {
+    int k0, steps, ia, ib, ic, id;
+};
+
+// The launches of one outer step over nb edge buffers (4 with one-step launches, 5 otherwise) from
+// x_0 in buffer base: each writes to the lowest buffers that hold neither x_0 (the anchors) nor
+// what it reads.  One-step launches put x_k in the (k - 1) % 3-th buffer other than the base.
+std::vector<Cp2Launch> cp2_stream_plan(int K, int spl, int base, int nb)
+{
+    std::vector<Cp2Launch> v;
+    int a = base, b = base, k = 1;
+    for (int S : cp2_launch_steps(K, spl)) {
+        int fr[2] = {-1, -1}, q = 0;
+        for (int x = 0; x < nb && q < 2; ++x)
+            if (x != base && x != a && x != b) fr[q++] = x;
+        const Cp2Launch l{k, S, a, b, S >= 2 ? fr[0] : -1, S >= 2 ? fr[1] : fr[0]};
+        v.push_back(l);
+        b = S >= 2 ? l.ic : a;
+        a = l.id;
+        k += S;
+    }
+    return v;
+}
 
 struct ImgHost {
     int H, W, ny, nx;
@@ -97,7 +142,9 @@ struct dtv_dd_plan {
     std::vector<ImgDev> h_imgs;
     std::vector<int> h_info;
     std::vector<StreamTile> h_tiles[kRowChoices];  // streaming work lists, strips of 4 << ri rows
-    std::vector<StreamTile> h_ptiles[kRowChoices];  // the same for the two-step primal-dual kernel (kPairCols)
+    // the same for the multi-step primal-dual kernel, by steps per launch S = 2 .. kMaxMultiSteps
+    // (strips of multi_cols(S) columns); only for the S the plan's launches use
+    std::vector<StreamTile> h_mtiles[kMaxMultiSteps - 1][kRowChoices];
     std::vector<SubTile> h_subs;
     std::vector<float> h_beta;  // adaptive stopping: the FISTA momentum table (beta[k], k = 0 .. n_inner)
     std::vector<float> h_cp2tab;  // adaptive stopping: the primal-dual step scalars (FusedCp2Args::tab)
@@ -123,10 +170,10 @@ struct dtv_dd_plan {
     char *run_ws = nullptr;    // workspace of the last solve: the bound one, or the scratch array
     bool ran_persist = false;  // the last solve ran the persistent schedule (its error word is in run_ws)
     size_t buf_bytes = 0;      // bytes of each rotation buffer (0: the plan runs only the persistent schedule)
-    bool pairs = false;        // the streaming primal-dual schedule runs its local steps two per launch
+    int spl = 1;               // the streaming primal-dual schedule runs up to spl local steps per launch
 
     // workspace layout (byte offsets)
-    size_t off_imgs = 0, off_info = 0, off_tiles[kRowChoices] = {0, 0, 0, 0}, off_ptiles[kRowChoices] = {0, 0, 0, 0},
+    size_t off_imgs = 0, off_info = 0, off_tiles[kRowChoices] = {0, 0, 0, 0}, off_mtiles[kMaxMultiSteps - 1][kRowChoices] = {},
            off_subs = 0, off_psubs = 0, off_buf[4] = {0, 0, 0, 0},
            off_u2 = 0,
            off_part = 0, off_dout = 0, off_xch = 0, off_sync = 0, off_lamw = 0, ws_bytes = 0;
@@ -178,11 +225,11 @@ struct dtv_dd_plan {
     const int *d_info() const { return (const int *)(ws + off_info); }
     const StreamTile *d_tiles(int R) const { return (const StreamTile *)(ws + off_tiles[row_index(R)]); }
     int ntiles(int R) const { return (int)h_tiles[row_index(R)].size(); }
-    const StreamTile *d_ptiles(int R) const { return (const StreamTile *)(ws + off_ptiles[row_index(R)]); }
-    int nptiles(int R) const { return (int)h_ptiles[row_index(R)].size(); }
+    const StreamTile *d_mtiles(int S, int R) const { return (const StreamTile *)(ws + off_mtiles[S - 2][row_index(R)]); }
+    int nmtiles(int S, int R) const { return (int)h_mtiles[S - 2][row_index(R)].size(); }
     // rotation buffer k: three always (FISTA: x in two, c' in the third), a fourth for the
-    // two-step primal-dual launches
-    size_t buf_size(int k) const { return k < 3 || pairs ? buf_bytes : 0; }
+    // multi-step primal-dual launches
+    size_t buf_size(int k) const { return k < 3 || spl > 1 ? buf_bytes : 0; }
     float *buf1(int k) const { return (float *)(ws + off_buf[k]); }
     float *buf2(int k) const { return (float *)(ws + off_buf[k]) + tot_p1; }
     float *u2() const { return (float *)(ws + off_u2); }
@@ -362,7 +409,8 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
         return fail(DTV_EINVAL, "rows must be 0, 4, 8, 16 or 32");
     if (p.no_graphs != 0 && p.no_graphs != 1) return fail(DTV_EINVAL, "no_graphs must be 0 or 1");
     if (p.spin_limit < 0) return fail(DTV_EINVAL, "spin_limit must be >= 0");
-    if (p.steps_per_launch < 0 || p.steps_per_launch > 2) return fail(DTV_EINVAL, "steps_per_launch must be 0, 1 or 2");
+    if (p.steps_per_launch < 0 || p.steps_per_launch > kMaxMultiSteps)
+        return fail(DTV_EINVAL, "steps_per_launch must be between 0 and 5");
 
     dtv_dd_plan *pl = new dtv_dd_plan();
     pl->uid = ++g_plan_ids;
@@ -444,10 +492,6 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
         for (int ri = 0; ri < kRowChoices; ++ri)
             for (int i0 = 0; i0 < h.H; i0 += 4 << ri)
                 for (int j0 = 0; j0 < h.W; j0 += kStreamCols) pl->h_tiles[ri].push_back(StreamTile{b, i0, j0, 0});
-        if (p.inner == DTV_INNER_CP2)
-            for (int ri = 0; ri < kRowChoices; ++ri)
-                for (int i0 = 0; i0 < h.H; i0 += 4 << ri)
-                    for (int j0 = 0; j0 < h.W; j0 += kPairCols) pl->h_ptiles[ri].push_back(StreamTile{b, i0, j0, 0});
         for (int r = 0; r < h.ny; ++r)
             for (int c = 0; c < h.nx; ++c)
                 pl->h_subs.push_back(SubTile{b, r, c, h.rcut[r], h.ccut[c], h.rcut[r + 1] - h.rcut[r],
@@ -566,7 +610,6 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
     pl->off_imgs = take(sizeof(ImgDev) * pl->h_imgs.size());
     pl->off_info = take(sizeof(int) * pl->h_info.size());
     for (int ri = 0; ri < kRowChoices; ++ri) pl->off_tiles[ri] = take(sizeof(StreamTile) * pl->h_tiles[ri].size());
-    for (int ri = 0; ri < kRowChoices; ++ri) pl->off_ptiles[ri] = take(sizeof(StreamTile) * pl->h_ptiles[ri].size());
     pl->off_subs = take(sizeof(SubTile) * pl->h_subs.size());
     pl->off_psubs = take(sizeof(SubTile) * std::max<size_t>(1, pl->p_subs.size()));
     // the persistent schedule updates p~, u and lambda in place: a plan that runs only that schedule
@@ -574,7 +617,25 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
     // (a plan that keeps checkpoints recomputes its outer steps with the other kernels in reverse mode)
     const bool persist_only = p.schedule == DTV_SCHED_PERSIST && !p.save_for_backward;
     pl->buf_bytes = persist_only ? 0 : sizeof(float) * (size_t)(pl->tot_p1 + pl->tot_p2);
-    pl->pairs = p.inner == DTV_INNER_CP2 && !persist_only && p.n_inner >= 2 && p.steps_per_launch != 1;
+    pl->spl = p.inner == DTV_INNER_CP2 && !persist_only && p.n_inner >= 2
+                  ? std::min(p.steps_per_launch == 0 ? kDefaultStepsPerLaunch : p.steps_per_launch, p.n_inner)
+                  : 1;
+    if (pl->spl > 1) {
+        // work lists of the multi-step launches an outer step makes
+        for (int S : cp2_launch_steps(p.n_inner, pl->spl)) {
+            if (S < 2 || !pl->h_mtiles[S - 2][0].empty()) continue;
+            for (int b = 0; b < n_images; ++b) {
+                const ImgHost &h = pl->imgs[b];
+                for (int ri = 0; ri < kRowChoices; ++ri)
+                    for (int i0 = 0; i0 < h.H; i0 += 4 << ri)
+                        for (int j0 = 0; j0 < h.W; j0 += multi_cols(S))
+                            pl->h_mtiles[S - 2][ri].push_back(StreamTile{b, i0, j0, 0});
+            }
+        }
+    }
+    for (int S = 2; S <= kMaxMultiSteps; ++S)
+        for (int ri = 0; ri < kRowChoices; ++ri)
+            pl->off_mtiles[S - 2][ri] = take(sizeof(StreamTile) * pl->h_mtiles[S - 2][ri].size());
     for (int k = 0; k < 4; ++k) pl->off_buf[k] = take(pl->buf_size(k));
     pl->off_u2 = take(p.inner == DTV_INNER_CP2 && !persist_only ? sizeof(float) * (size_t)pl->tot_px : 0);
     pl->diag_nblk = diag_blocks_per_image(pl->maxH, pl->maxW);
@@ -696,11 +757,12 @@ extern "C" int dtv_dd_bind_workspace(dtv_dd_plan *pl, void *d_ws, size_t bytes)
         HIP_TRY(hipMemcpy(ws + pl->off_tiles[ri], pl->h_tiles[ri].data(), sizeof(StreamTile) * pl->h_tiles[ri].size(),
                           hipMemcpyHostToDevice),
                 "upload work list");
-    for (int ri = 0; ri < kRowChoices; ++ri)
-        if (!pl->h_ptiles[ri].empty())
-            HIP_TRY(hipMemcpy(ws + pl->off_ptiles[ri], pl->h_ptiles[ri].data(),
-                              sizeof(StreamTile) * pl->h_ptiles[ri].size(), hipMemcpyHostToDevice),
-                    "upload work list");
+    for (int S = 2; S <= kMaxMultiSteps; ++S)
+        for (int ri = 0; ri < kRowChoices; ++ri)
+            if (!pl->h_mtiles[S - 2][ri].empty())
+                HIP_TRY(hipMemcpy(ws + pl->off_mtiles[S - 2][ri], pl->h_mtiles[S - 2][ri].data(),
+                                  sizeof(StreamTile) * pl->h_mtiles[S - 2][ri].size(), hipMemcpyHostToDevice),
+                        "upload work list");
     HIP_TRY(hipMemcpy(ws + pl->off_subs, pl->h_subs.data(), sizeof(SubTile) * pl->h_subs.size(), hipMemcpyHostToDevice),
             "upload subdomain list");
     if (!pl->p_subs.empty())
@@ -823,7 +885,7 @@ struct Timer {
 static std::vector<float> fista_betas(int K);
 
 // next rotation state of the edge buffers after one outer step (see outer_step)
-static int next_base(int sched, bool cp2, int K, int base, bool pairs)
+static int next_base(int sched, bool cp2, int K, int base, int spl)
 {
     if (sched == DTV_SCHED_PERSIST) return base;
     if (sched == DTV_SCHED_FUSED) return base == 0 ? 1 : 0;  // the fused kernels read one buffer and write the other
@@ -833,17 +895,12 @@ static int next_base(int sched, bool cp2, int K, int base, bool pairs)
             if (k != base) rot[q++] = k;
         return rot[K % 3];
     }
-    // primal-dual: x_k in the (k - 1)-th of the buffers other than the base, three of them (four
-    // with two-step launches, which write x_k and x_(k+1) while reading x_(k-1) and x_(k-2))
-    const int nb = pairs ? 5 : 4, ns = nb - 1;
-    int sc[4] = {0, 0, 0, 0}, q = 0;
-    for (int k = 0; k < nb; ++k)
-        if (k != base) sc[q++] = k;
-    return sc[(K - 1) % ns];
+    // primal-dual: the buffer the last launch of the outer step writes x_K to (cp2_stream_plan)
+    return cp2_stream_plan(K, spl, base, spl > 1 ? 5 : 4).back().id;
 }
 
 // launches of one streaming primal-dual outer step (each swaps the two u buffers)
-static int cp2_launches(int K, bool pairs) { return pairs ? K / 2 + (K & 1) : K; }
+static int cp2_launches(int K, int spl) { return (int)cp2_launch_steps(K, spl).size(); }
 
 // Arguments every solve entry point checks before anything is enqueued.
 static int check_solve_args(const dtv_dd_plan *pl, const float *d_f, const uint8_t *d_mask, const float *d_u,
@@ -993,7 +1050,7 @@ static int solve_impl(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_mask, 
                     "lambda update");
         // (a2)+(a3) local solves; the anchor phat is formed on the fly from p~^n and lambda
         if (sched == DTV_SCHED_FUSED && cp2) {
-            const int out = next_base(sched, cp2, K, base, pl->pairs);
+            const int out = next_base(sched, cp2, K, base, pl->spl);
             FusedCp2Args ca = cp2_args();
             ca.out1 = bufs[out].p1;
             ca.out2 = bufs[out].p2;
@@ -1009,7 +1066,7 @@ static int solve_impl(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_mask, 
             base = out;
             lam_cur = lam_other();
         } else if (sched == DTV_SCHED_FUSED) {
-            const int out = next_base(sched, cp2, K, base, pl->pairs);
+            const int out = next_base(sched, cp2, K, base, pl->spl);
             fa.base1 = bufs[base].p1; fa.base2 = bufs[base].p2;
             fa.out1 = bufs[out].p1; fa.out2 = bufs[out].p2;
             fa.lam = lam_cur;
@@ -1048,69 +1105,59 @@ static int solve_impl(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_mask, 
             }
             base = rot[K % 3];
         } else {
-            // x_k in sc[(k - 1) % ns]: the ns buffers other than the base (next_base); each launch
-            // reads x_(k-1) and x_(k-2) and writes x_k (and x_(k+1)) to other buffers
-            const int nb = pl->pairs ? 5 : 4, ns = nb - 1;
-            int sc[4] = {0, 0, 0, 0}, r = 0;
-            for (int k = 0; k < nb; ++k)
-                if (k != base) sc[r++] = k;
-            auto xbuf = [&](int k) { return k <= 0 ? base : sc[(k - 1) % ns]; };
-            int k = 1;
-            for (; pl->pairs && k + 1 <= K; k += 2) {  // steps k and k + 1 in one launch
-                const int it = k - 1;
-                Cp2PairArgs a{};
-                a.imgs = pl->d_imgs(); a.tiles = pl->d_ptiles(rows); a.ntiles = pl->nptiles(rows); a.info = pl->d_info();
-                const int ia = xbuf(k - 1), ib = xbuf(k - 2);
-                a.xa1 = bufs[ia].p1; a.xa2 = bufs[ia].p2; a.xb1 = bufs[ib].p1; a.xb2 = bufs[ib].p2;
-                a.base1 = bufs[base].p1; a.base2 = bufs[base].p2; a.lam = lam_cur; a.f = d_f; a.mask = mask;
+            // launches of up to pl->spl steps (cp2_stream_plan); each reads x_(k-1) and x_(k-2) and
+            // writes its last two iterates (one-step launches: x_k) to buffers other than those and the base
+            const std::vector<Cp2Launch> plan = cp2_stream_plan(K, pl->spl, base, pl->spl > 1 ? 5 : 4);
+            for (const Cp2Launch &l : plan) {
+                const int it = l.k0 - 1;
                 float *u_next = u_cur == d_u ? pl->u2() : d_u;
-                a.u_in = u_cur; a.u_out = u_next;
-                a.outk1 = bufs[xbuf(k)].p1; a.outk2 = bufs[xbuf(k)].p2;
-                a.outn1 = bufs[xbuf(k + 1)].p1; a.outn2 = bufs[xbuf(k + 1)].p2;
-                a.theta_a = it >= 1 ? (float)th[it - 1] : 0.0f;
-                a.sk_a = (float)sk[it]; a.tk_a = (float)tk[it];
-                a.ck_a = cp2_keep(P, tk[it]); a.ca_a = cp2_anchor(P, tk[it]);
-                a.theta_b = (float)th[it];
-                a.sk_b = (float)sk[it + 1]; a.tk_b = (float)tk[it + 1];
-                a.ck_b = cp2_keep(P, tk[it + 1]); a.ca_b = cp2_anchor(P, tk[it + 1]);
-                a.tau = (float)P.tau;
-                a.fidelity = P.fidelity;
-                a.cv_c1 = (float)P.cv_c1;
-                a.cv_c2 = (float)P.cv_c2;
                 int rc = with_host ? tm.begin() : DTV_OK;
                 if (rc != DTV_OK) return rc;
-                HIP_TRY(launch_cp2_pair(a, it >= 1, rows, q, with_host ? tm.e0 : nullptr, with_host ? tm.e1 : nullptr),
-                        "CP2 step pair");
+                if (l.steps >= 2) {  // steps k0 .. k0 + steps - 1 in one launch
+                    Cp2MultiArgs a{};
+                    a.imgs = pl->d_imgs(); a.tiles = pl->d_mtiles(l.steps, rows); a.ntiles = pl->nmtiles(l.steps, rows);
+                    a.info = pl->d_info();
+                    a.xa1 = bufs[l.ia].p1; a.xa2 = bufs[l.ia].p2; a.xb1 = bufs[l.ib].p1; a.xb2 = bufs[l.ib].p2;
+                    a.base1 = bufs[base].p1; a.base2 = bufs[base].p2; a.lam = lam_cur; a.f = d_f; a.mask = mask;
+                    a.u_in = u_cur; a.u_out = u_next;
+                    a.outk1 = bufs[l.ic].p1; a.outk2 = bufs[l.ic].p2;
+                    a.outn1 = bufs[l.id].p1; a.outn2 = bufs[l.id].p2;
+                    for (int L = 0; L < l.steps; ++L) {  // level L runs step k0 + L (index it + L)
+                        a.theta[L] = it + L >= 1 ? (float)th[it + L - 1] : 0.0f;
+                        a.sk[L] = (float)sk[it + L];
+                        a.tk[L] = (float)tk[it + L];
+                        a.ck[L] = cp2_keep(P, tk[it + L]);
+                        a.ca[L] = cp2_anchor(P, tk[it + L]);
+                    }
+                    a.tau = (float)P.tau;
+                    a.fidelity = P.fidelity;
+                    a.cv_c1 = (float)P.cv_c1;
+                    a.cv_c2 = (float)P.cv_c2;
+                    HIP_TRY(launch_cp2_multi(a, it >= 1, rows, l.steps, q, with_host ? tm.e0 : nullptr,
+                                             with_host ? tm.e1 : nullptr),
+                            "CP2 multi-step launch");
+                } else {
+                    Cp2StepArgs a{};
+                    a.imgs = pl->d_imgs(); a.tiles = pl->d_tiles(rows); a.ntiles = pl->ntiles(rows); a.info = pl->d_info();
+                    a.xa1 = bufs[l.ia].p1; a.xa2 = bufs[l.ia].p2; a.xb1 = bufs[l.ib].p1; a.xb2 = bufs[l.ib].p2;
+                    a.base1 = bufs[base].p1; a.base2 = bufs[base].p2; a.lam = lam_cur; a.f = d_f; a.mask = mask;
+                    a.u_in = u_cur; a.u_out = u_next;
+                    a.out1 = bufs[l.id].p1; a.out2 = bufs[l.id].p2;
+                    a.theta_prev = it >= 1 ? (float)th[it - 1] : 0.0f;
+                    a.sk = (float)sk[it]; a.tk = (float)tk[it]; a.tau = (float)P.tau;
+                    a.c_keep = cp2_keep(P, tk[it]);
+                    a.c_anchor = cp2_anchor(P, tk[it]);
+                    a.fidelity = P.fidelity;
+                    a.cv_c1 = (float)P.cv_c1;
+                    a.cv_c2 = (float)P.cv_c2;
+                    HIP_TRY(launch_cp2_step(a, it >= 1, rows, q, with_host ? tm.e0 : nullptr, with_host ? tm.e1 : nullptr),
+                            "CP2 step");
+                }
                 rc = with_host ? tm.end() : DTV_OK;
                 if (rc != DTV_OK) return rc;
                 u_cur = u_next;
             }
-            for (; k <= K; ++k) {
-                const int ia = xbuf(k - 1), ib = xbuf(k - 2), io = xbuf(k);
-                const int it = k - 1;
-                Cp2StepArgs a{};
-                a.imgs = pl->d_imgs(); a.tiles = pl->d_tiles(rows); a.ntiles = pl->ntiles(rows); a.info = pl->d_info();
-                a.xa1 = bufs[ia].p1; a.xa2 = bufs[ia].p2; a.xb1 = bufs[ib].p1; a.xb2 = bufs[ib].p2;
-                a.base1 = bufs[base].p1; a.base2 = bufs[base].p2; a.lam = lam_cur; a.f = d_f; a.mask = mask;
-                float *u_next = u_cur == d_u ? pl->u2() : d_u;
-                a.u_in = u_cur; a.u_out = u_next;
-                a.out1 = bufs[io].p1; a.out2 = bufs[io].p2;
-                a.theta_prev = it >= 1 ? (float)th[it - 1] : 0.0f;
-                a.sk = (float)sk[it]; a.tk = (float)tk[it]; a.tau = (float)P.tau;
-                a.c_keep = cp2_keep(P, tk[it]);
-                a.c_anchor = cp2_anchor(P, tk[it]);
-                a.fidelity = P.fidelity;
-                a.cv_c1 = (float)P.cv_c1;
-                a.cv_c2 = (float)P.cv_c2;
-                int rc = with_host ? tm.begin() : DTV_OK;
-                if (rc != DTV_OK) return rc;
-                HIP_TRY(launch_cp2_step(a, it >= 1, rows, q, with_host ? tm.e0 : nullptr, with_host ? tm.e1 : nullptr),
-                        "CP2 step");
-                rc = with_host ? tm.end() : DTV_OK;
-                if (rc != DTV_OK) return rc;
-                u_cur = u_next;
-            }
-            base = xbuf(K);
+            base = plan.back().id;
         }
         const bool last = n == P.n_outer - 1;
         if (with_host && P.diag_every > 0 && ((n + 1) % P.diag_every == 0 || last)) {
@@ -1209,8 +1256,8 @@ static int solve_impl(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_mask, 
             bool uf = u_cur != d_u, lp = lam_cur != d_lambda;
             for (int i = 0; i < 8; ++i) {
                 seq.push_back(state(b, uf, lp));
-                b = next_base(sched, cp2, K, b, pl->pairs);
-                if (cp2 && sched != DTV_SCHED_FUSED && (cp2_launches(K, pl->pairs) & 1)) uf = !uf;
+                b = next_base(sched, cp2, K, b, pl->spl);
+                if (cp2 && sched != DTV_SCHED_FUSED && (cp2_launches(K, pl->spl) & 1)) uf = !uf;
                 if (sched == DTV_SCHED_FUSED) lp = !lp;
             }
             int start = -1, period = 0;
@@ -1677,7 +1724,7 @@ extern "C" int dtv_dd_kernel_time(const dtv_dd_plan *pl, double *avg_ms, int64_t
                                : mixed ? "k_fused_fista_mixed"
                                : pl->stagger_blocks > 0 ? "k_fused_fista_staggered"
                                                         : "k_fused_fista")
-                        : (cp2 ? (pl->pairs ? "k_cp2_pair" : "k_cp2_step") : "k_fista_step");
+                        : (cp2 ? (pl->spl > 1 ? "k_cp2_multi" : "k_cp2_step") : "k_fista_step");
     if (bytes_per_launch) {
         // Algorithmic HBM bytes of one timed launch (E = edge dofs of the torn
         // p~, N = pixels, 4 bytes each), averaged over the launches of an outer step.
@@ -1688,8 +1735,8 @@ extern "C" int dtv_dd_kernel_time(const dtv_dd_plan *pl, double *avg_ms, int64_t
         //   streaming FISTA step k >= 3: read x_{k-1}, x_{k-2}, c', write x_k       4 (4E)
         //   CP2 step 1: read x_0, u, f (+ mask bytes), write x_1, u                 4 (2E + 3N) + mask
         //   CP2 step k >= 2: read x_{k-1}, x_{k-2}, anchor base, u, f (+ mask), write 4 (4E + 3N) + mask
-        //   CP2 two-step launch (k, k + 1): read x_{k-1}, x_{k-2} (k >= 2), anchor base, u, f (+ mask),
-        //     write x_k, x_{k+1}, u                                 4 (5E + 3N) + mask (k = 1: 4 (3E + 3N) + mask)
+        //   CP2 launch of steps k .. k + S - 1 (S >= 2): read x_{k-1}, x_{k-2} (k >= 2), anchor base, u, f
+        //     (+ mask), write x_{k+S-2}, x_{k+S-1}, u               4 (5E + 3N) + mask (k = 1: 4 (3E + 3N) + mask)
         //   (the streaming CP2 figure is the average over the launches of an outer step)
         double E = 0.0, N = 0.0;
         for (const ImgHost &h : pl->imgs) {
@@ -1710,10 +1757,14 @@ extern "C" int dtv_dd_kernel_time(const dtv_dd_plan *pl, double *avg_ms, int64_t
             *bytes_per_launch = 4.0 * (2 * E + 3 * N) + mb;
         } else if (fused) {
             *bytes_per_launch = 4.0 * (2 * E + N);
-        } else if (cp2 && pl->pairs) {
+        } else if (cp2 && pl->spl > 1) {
             int k = 1, nl = 0;
-            for (; k + 1 <= K; k += 2, ++nl) tot += (k == 1 ? 4.0 * (3 * E + 3 * N) : 4.0 * (5 * E + 3 * N)) + mb;
-            for (; k <= K; ++k, ++nl) tot += (k == 1 ? 4.0 * (2 * E + 3 * N) : 4.0 * (4 * E + 3 * N)) + mb;
+            for (int S : cp2_launch_steps(K, pl->spl)) {
+                if (S >= 2) tot += (k == 1 ? 4.0 * (3 * E + 3 * N) : 4.0 * (5 * E + 3 * N)) + mb;
+                else tot += (k == 1 ? 4.0 * (2 * E + 3 * N) : 4.0 * (4 * E + 3 * N)) + mb;
+                k += S;
+                ++nl;
+            }
             *bytes_per_launch = tot / nl;
         } else {
             for (int k = 1; k <= K; ++k) {
@@ -1797,11 +1848,12 @@ static int upload_async(dtv_dd_plan *pl, char *ws, hipStream_t s)
         HIP_TRY(hipMemcpyAsync(ws + pl->off_tiles[ri], pl->h_tiles[ri].data(), sizeof(StreamTile) * pl->h_tiles[ri].size(),
                                hipMemcpyHostToDevice, s),
                 "upload work list");
-    for (int ri = 0; ri < kRowChoices; ++ri)
-        if (!pl->h_ptiles[ri].empty())
-            HIP_TRY(hipMemcpyAsync(ws + pl->off_ptiles[ri], pl->h_ptiles[ri].data(),
-                                   sizeof(StreamTile) * pl->h_ptiles[ri].size(), hipMemcpyHostToDevice, s),
-                    "upload work list");
+    for (int S = 2; S <= kMaxMultiSteps; ++S)
+        for (int ri = 0; ri < kRowChoices; ++ri)
+            if (!pl->h_mtiles[S - 2][ri].empty())
+                HIP_TRY(hipMemcpyAsync(ws + pl->off_mtiles[S - 2][ri], pl->h_mtiles[S - 2][ri].data(),
+                                       sizeof(StreamTile) * pl->h_mtiles[S - 2][ri].size(), hipMemcpyHostToDevice, s),
+                        "upload work list");
     HIP_TRY(hipMemcpyAsync(ws + pl->off_subs, pl->h_subs.data(), sizeof(SubTile) * pl->h_subs.size(),
                            hipMemcpyHostToDevice, s),
             "upload subdomain list");

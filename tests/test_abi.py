@@ -100,6 +100,8 @@ def test_valid_setup_and_layout():
     (dict(inner_tol=1e-3, H=300, W=300, rc=(0, 150, 300), cc=(0, 150, 300)), "at most 128"),
     (dict(inner_tol=1e-3, n_inner=100001), "cap"),
     (dict(spin_limit=-1), "spin_limit"),
+    (dict(inner=1, steps_per_launch=6), "steps_per_launch"),
+    (dict(inner=1, steps_per_launch=-1), "steps_per_launch"),
 ])
 def test_validation_errors(kw, msg):
     code, h = _setup(**kw)
@@ -113,6 +115,11 @@ def test_validation_errors(kw, msg):
     # the undecomposed problem ignores tau and sigma, and gamma has no 1/tau bound
     dict(full_problem=1, rc=(0, 64), cc=(0, 64), tau=0.0, sigma=0.0),
     dict(full_problem=1, rc=(0, 64), cc=(0, 64), inner=1, fidelity=1, tau=0.0, sigma=0.0, gamma=5.0),
+    # the streaming primal-dual launches: every steps-per-launch value, more than n_inner included
+    dict(inner=1, fidelity=1, has_mask=1, steps_per_launch=5),
+    dict(inner=1, n_inner=7, steps_per_launch=3),
+    dict(inner=1, n_inner=2, steps_per_launch=4),
+    dict(inner=1, n_inner=1, steps_per_launch=2),
 ])
 def test_valid_chan_vese_and_full_problem(kw):
     code, h = _setup(**kw)

@@ -1,10 +1,11 @@
-"""The two-step streaming launch of the local primal-dual solver (cp2_pair.hip:
-steps k and k + 1 of Chambolle-Pock Alg. 2 on the local problems of Sec. 5 in
-one launch) against one-step launches, bitwise: every fidelity, masks, ragged
-and one-pixel subdomains (subdomain boundaries inside a strip, on the strip's
-halo rows and on the waves' halo columns), every strip height, odd and even
-inner counts, images narrower than a wave and one row high; and the TV-L1
-inpainting workload at full size against the oracle."""
+"""The multi-step streaming launch of the local primal-dual solver (cp2_multi.hip:
+steps k .. k + S - 1 of Chambolle-Pock Alg. 2 on the local problems of Sec. 5 in
+one launch, S = 2 .. 5) against one-step launches, bitwise: every fidelity,
+masks, ragged and one-pixel subdomains (subdomain boundaries inside a strip, on
+the strip's halo rows and on the waves' halo columns), every strip height,
+inner counts that cut into launches of every length, images narrower than a
+wave and one row high; and the TV-L1 inpainting workload at full size against
+the oracle."""
 import sys
 
 import numpy as np
@@ -72,62 +73,71 @@ def _solve(f, mask, rc, cc, alpha, spl, **kw):
     return plan, gpu_image_state(plan, state)
 
 
-CASES = [(g, fid, K, R) for g in ("uneven", "thin") for fid in FIDS for K, R in ((2, 4), (5, 8), (6, 16), (7, 32))]
-CASES += [("ragged", "L1_mask", 5, 8), ("ragged", "CV", 3, 16), ("narrow", "L2", 4, 4), ("narrow", "L1_mask", 5, 32),
-          ("row", "L2", 5, 8), ("row", "CV", 2, 4), ("col", "L1_mask", 3, 16), ("col", "L2", 6, 4)]
+# inner counts and the launches the steps-per-launch values 2, 3, 4, 5 cut them into:
+#   K = 2: 2 | 2 | 2 | 2;  K = 5: 2 2 1 | 3 2 | 3 2 | 5;  K = 4: 2 2 | 2 2 | 4 | 4;  K = 9: 2 2 2 2 1 | 3 3 3 | 3 3 3 | 5 4
+CASES = [(g, fid, K, R) for g in ("uneven", "thin") for fid in FIDS for K, R in ((2, 4), (5, 8), (4, 16), (9, 32))]
+CASES += [("ragged", "L1_mask", 5, 8), ("ragged", "CV", 7, 16), ("narrow", "L2", 4, 4), ("narrow", "L1_mask", 5, 32),
+          ("row", "L2", 5, 8), ("row", "CV", 9, 4), ("col", "L1_mask", 5, 16), ("col", "L2", 6, 4)]
 
 
 @pytest.mark.parametrize("geom,fid,K,R", CASES)
-def test_pair_equals_one_step_launches_bitwise(geom, fid, K, R):
+def test_multi_equals_one_step_launches_bitwise(geom, fid, K, R):
     H, W, rc, cc = GEOMS[geom]
     kw = dict(FIDS[fid])
     alpha, masked = kw.pop("alpha"), kw.pop("mask")
     f, mask = _input(H, W, 11 * K + R + 7 * len(geom), masked)
-    _say(f"[cp2 pair] {geom} {H}x{W} {fid} K={K} R={R}")
+    _say(f"[cp2 multi] {geom} {H}x{W} {fid} K={K} R={R}")
     res = {}
-    for spl in (1, 2):
+    for spl in (1, 2, 3, 4, 5):
         plan, res[spl] = _solve(f, mask, rc, cc, alpha, spl, n_outer=4, n_inner=K, rows=R, **kw)
-    for q in res[1]:
-        assert np.array_equal(res[1][q], res[2][q]), q
+    for spl in (2, 3, 4, 5):
+        for q in res[1]:
+            assert np.array_equal(res[1][q], res[spl][q]), (spl, q)
 
 
-def test_pair_kernel_is_timed_and_named():
+def test_multi_kernel_is_timed_and_named():
     H, W, rc, cc = GEOMS["uneven"]
     f, mask = _input(H, W, 3, True)
     kw = dict(FIDS["L1_mask"])
     alpha = kw.pop("alpha")
     kw.pop("mask")
-    plan, _ = _solve(f, mask, rc, cc, alpha, 0, n_outer=3, n_inner=5, rows=8, time_kernels=True, **kw)
+    plan, _ = _solve(f, mask, rc, cc, alpha, 2, n_outer=3, n_inner=5, rows=8, time_kernels=True, **kw)
     kt = plan.kernel_time()
-    assert kt["name"] == "k_cp2_pair"
-    assert kt["launches"] == 3 * 3  # two pairs and one single step per outer step
+    assert kt["name"] == "k_cp2_multi"
+    assert kt["launches"] == 3 * 3  # two two-step launches and one one-step launch per outer step
+    plan5, _ = _solve(f, mask, rc, cc, alpha, 5, n_outer=3, n_inner=5, rows=8, time_kernels=True, **kw)
+    assert plan5.kernel_time()["name"] == "k_cp2_multi"
+    assert plan5.kernel_time()["launches"] == 3
     plan1, _ = _solve(f, mask, rc, cc, alpha, 1, n_outer=3, n_inner=5, rows=8, time_kernels=True, **kw)
     assert plan1.kernel_time()["name"] == "k_cp2_step"
+    assert plan1.kernel_time()["launches"] == 3 * 5
     assert plan1.kernel_time()["bytes_per_launch"] > kt["bytes_per_launch"] * 0.5
 
 
-def test_pair_tvl1_workload_against_the_oracle():
+def test_multi_tvl1_workload_against_the_oracle():
     """TV-L1 + inpainting mask, 2000 x 3000, 13 x 20 uneven subdomains, CP2 x 5,
-    on the two-step launches (the autotuner's strip height): the first 30 outer
-    steps against the FP64 oracle, and bitwise equal to one-step launches."""
+    on launches of 2 + 2 + 1, 3 + 2 and 5 steps (strips of 8 and 16 rows): the
+    first 30 outer steps against the FP64 oracle, and bitwise equal to one-step
+    launches."""
     from paper_1901_00682_amd import dtvdd
     c = synth.config3()
     H, W = c.f.shape
     n_outer = 30
-    _say(f"[cp2 pair] config3 {H}x{W} 13x20 TV-L1+mask {n_outer}x{c.n_inner}")
+    _say(f"[cp2 multi] config3 {H}x{W} 13x20 TV-L1+mask {n_outer}x{c.n_inner}")
     ft = torch.from_numpy(np.ascontiguousarray(c.f, dtype=np.float32).ravel()).cuda()
     mt = torch.from_numpy(np.ascontiguousarray(c.mask, dtype=np.uint8).ravel()).cuda()
     res = {}
-    for spl in (2, 1):
+    for spl, R in ((5, 16), (3, 8), (2, 8), (1, 8)):
         plan = dtvdd.Plan([dtvdd.Image(H, W, c.row_cuts, c.col_cuts, c.alpha)], has_mask=True, fidelity="L1",
-                          inner="CP2", n_outer=n_outer, n_inner=c.n_inner, schedule="stream", rows=8,
+                          inner="CP2", n_outer=n_outer, n_inner=c.n_inner, schedule="stream", rows=R,
                           steps_per_launch=spl)
         state, _ = plan.solve(ft, mt)
         torch.cuda.synchronize()
         res[spl] = gpu_image_state(plan, state)
-    for q in res[1]:
-        assert np.array_equal(res[1][q], res[2][q]), q
+    for spl in (2, 3, 5):
+        for q in res[1]:
+            assert np.array_equal(res[1][q], res[spl][q]), (spl, q)
     o = oracle_for(c.f, c.alpha, c.row_cuts, c.col_cuts, fidelity="L1", inner="CP2", mask=c.mask, n_inner=c.n_inner)
     o.run(n_outer)
-    errs = compare(res[2], o)
+    errs = compare(res[5], o)
     _say(f"  errors {errs}")
