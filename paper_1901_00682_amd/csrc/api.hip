@@ -620,6 +620,11 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
     pl->spl = p.inner == DTV_INNER_CP2 && !persist_only && p.n_inner >= 2
                   ? std::min(p.steps_per_launch == 0 ? kDefaultStepsPerLaunch : p.steps_per_launch, p.n_inner)
                   : 1;
+    // the multi-step kernel addresses a row by 32-bit byte offsets (at most 4 (W + nx) along a row
+    // and 4 nx H in the vertical multipliers); an image beyond that runs one step per launch, which
+    // gives the same result
+    for (const ImgHost &h : pl->imgs)
+        if (4.0 * std::max((double)h.W + h.nx, (double)h.nx * h.H) >= 2147483648.0) pl->spl = 1;
     if (pl->spl > 1) {
         // work lists of the multi-step launches an outer step makes
         for (int S : cp2_launch_steps(p.n_inner, pl->spl)) {

@@ -127,6 +127,30 @@ def test_valid_chan_vese_and_full_problem(kw):
     dtvdd.lib().dtv_dd_destroy(h)
 
 
+def _kernel_name(h):
+    name = ctypes.c_char_p()
+    assert dtvdd.lib().dtv_dd_kernel_time(h, None, None, ctypes.byref(name), None) == 0
+    return name.value.decode()
+
+
+def test_multi_step_launches_fall_back_beyond_32_bit_row_offsets():
+    """The multi-step primal-dual kernel addresses rows by 32-bit byte offsets;
+    an image whose vertical multipliers span 2 GiB (nx H >= 2^29) runs one step
+    per launch instead (the same result), a small one the multi-step kernel."""
+    L = dtvdd.lib()
+    H, W = 1 << 20, 1024
+    code, h = _setup(H=H, W=W, rc=(0, H), cc=tuple(range(0, W + 1, 2)), inner=1, steps_per_launch=5)
+    assert code == 0
+    assert _kernel_name(h) == "k_cp2_step"
+    L.dtv_dd_destroy(h)
+    code, h = _setup(inner=1, steps_per_launch=5)
+    assert code == 0 and _kernel_name(h) == "k_cp2_multi"
+    L.dtv_dd_destroy(h)
+    code, h = _setup(inner=1, steps_per_launch=1)
+    assert code == 0 and _kernel_name(h) == "k_cp2_step"
+    L.dtv_dd_destroy(h)
+
+
 def test_inner_counts_before_any_solve_are_zero():
     L = dtvdd.lib()
     for kw in (dict(), dict(inner_tol=1e-3, n_inner=500)):
