@@ -35,6 +35,9 @@ KERNEL_SOURCES = {
     "k_fused_fista": ["fused.hip", "fused_common.h", "fista_ops.h", "dtvdd_internal.h"],
     "k_fused_fista_staggered": ["fused.hip", "fused_common.h", "fista_ops.h", "dtvdd_internal.h"],
     "k_fista_step": ["kernels.hip", "fista_ops.h", "dtvdd_internal.h"],
+    # (a one-step launch that ends an outer step is timed with the multi-step ones)
+    "k_fista_multi": ["fista_multi.hip", "fista_multi.h", "cp2_multi.h", "kernels.hip", "fista_ops.h",
+                      "dtvdd_internal.h"],
     "k_cp2_step": ["kernels.hip", "cp2_ops.h", "fista_ops.h", "dtvdd_internal.h"],
     # (a one-step launch that ends an outer step is timed with the multi-step ones)
     "k_cp2_multi": ["cp2_multi.hip", "cp2_multi.h", "kernels.hip", "cp2_ops.h", "fista_ops.h", "dtvdd_internal.h"],
@@ -420,8 +423,7 @@ def main():
     ap.add_argument("--schedule", default="auto")
     ap.add_argument("--rows", type=int, default=0, help="streaming strip height (0: the plan picks)")
     ap.add_argument("--steps-per-launch", type=int, default=0,
-                    help="streaming primal-dual schedule: the most local steps per launch (1 .. 5; 0: the plan's "
-                         "default)")
+                    help="streaming schedule: the most local steps per launch (1 .. 5; 0: the plan's default)")
     ap.add_argument("--cpu-outer", type=int, default=500, help="outer steps of the oracle sample (0: skip)")
     ap.add_argument("--cpu-outer-single", type=int, default=20, help="outer steps of the one-thread oracle sample")
     ap.add_argument("--no-extra", action="store_true", help="default workload: skip the batched and backward blocks")

@@ -94,7 +94,9 @@ extern "C" {
                                 schedules round identically, so the result does not depend on
                                 the choice); with too few outer steps, or with time_kernels, a
                                 fixed rule picks: persistent, else fused, else streaming */
-#define DTV_SCHED_STREAM 1   /* one launch per inner step over all subdomains */
+#define DTV_SCHED_STREAM 1   /* launches of up to steps_per_launch inner steps over all
+                                subdomains, any size (rows swept, each step one row behind
+                                the step before it) */
 #define DTV_SCHED_FUSED 2    /* one workgroup per subdomain runs all inner steps on chip
                                 (FISTA: subdomains up to 128 x 128; CP2: 128 x 128, or smaller
                                 with the short sides on the image boundary) */
@@ -173,13 +175,14 @@ typedef struct {
                                   only: every subdomain at most 128 x 128 (FISTA), or 128 x 128
                                   or smaller with its short sides on the image boundary (CP2);
                                   no save_for_backward.  0: fixed n_inner steps */
-    int32_t steps_per_launch;  /* streaming schedule of the primal-dual local solver (CP2): the most
-                                  local steps one launch runs, 1 .. 5 (0: the library's default, 5).
-                                  The n_inner steps of an outer step are cut into the fewest
-                                  launches of at most that many steps, as evenly as possible (5
-                                  steps at 3 per launch: 3 + 2); the intermediate x and u of a
-                                  launch stay in registers.  Every value gives the same result
-                                  bitwise.  Ignored by the other schedules and by FISTA */
+    int32_t steps_per_launch;  /* streaming schedule (both local solvers): the most local steps one
+                                  launch runs, 1 .. 5 (0: the library's default, 5).  The n_inner
+                                  steps of an outer step are cut into the fewest launches of at
+                                  most that many steps, as evenly as possible (5 steps at 3 per
+                                  launch: 3 + 2); the intermediate iterates of a launch stay in
+                                  registers.  Every value gives the same result bitwise.  Ignored
+                                  by the other schedules; the reverse pass's recomputation runs one
+                                  step per launch */
 } dtv_dd_params;
 
 /* Where image `image` lives in the concatenated buffers (element offsets). */

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(BUILD, "libdtvdd.so")
-SOURCES = ["api.hip", "kernels.hip", "fused.hip", "fused_cp2.hip", "persist.hip", "persist_cp2.hip", "kernels_bwd.hip", "fused_bwd.hip", "cp2_multi.hip"]
+SOURCES = ["api.hip", "kernels.hip", "fused.hip", "fused_cp2.hip", "persist.hip", "persist_cp2.hip", "kernels_bwd.hip", "fused_bwd.hip", "cp2_multi.hip", "fista_multi.hip"]
 ARCH = "gfx950"
 
 

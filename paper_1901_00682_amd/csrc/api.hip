@@ -15,6 +15,7 @@
 
 #include "dtvdd.h"
 #include "cp2_multi.h"
+#include "fista_multi.h"
 #include "dtvdd_internal.h"
 
 using namespace dtv;
@@ -82,6 +83,32 @@ std::vector<Cp2Launch> cp2_stream_plan(int K, int spl, int base, int nb)
         for (int x = 0; x < nb && q < 2; ++x)
             if (x != base && x != a && x != b) fr[q++] = x;
         const Cp2Launch l{k, S, a, b, S >= 2 ? fr[0] : -1, S >= 2 ? fr[1] : fr[0]};
+        v.push_back(l);
+        b = S >= 2 ? l.ic : a;
+        a = l.id;
+        k += S;
+    }
+    return v;
+}
+
+// The launches of one streaming FISTA outer step (lengths as cp2_launch_steps) over the x buffers
+// 0, 1, 2 and 4 (buffer 3 holds c'): each writes to the lowest of them that holds none of its
+// inputs.  x_0 is read only by the first launch, which forms c' from it, so its buffer is free
+// afterwards; the last launch writes x_K alone (the next outer step restarts from it, without
+// momentum), the others also x_{k+S-2} (ic; -1 where it is not written).
+std::vector<Cp2Launch> fista_stream_plan(int K, int spl, int base)
+{
+    static const int X[4] = {0, 1, 2, 4};
+    std::vector<Cp2Launch> v;
+    const std::vector<int> steps = cp2_launch_steps(K, spl);
+    int a = base, b = base, k = 1;
+    for (size_t n = 0; n < steps.size(); ++n) {
+        const int S = steps[n];
+        const bool prev = S >= 2 && n + 1 < steps.size();
+        int fr[2] = {-1, -1}, q = 0;
+        for (int x : X)
+            if (q < 2 && x != a && x != b) fr[q++] = x;
+        const Cp2Launch l{k, S, a, b, prev ? fr[0] : -1, prev ? fr[1] : fr[0]};
         v.push_back(l);
         b = S >= 2 ? l.ic : a;
         a = l.id;
@@ -617,7 +644,7 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
     // (a plan that keeps checkpoints recomputes its outer steps with the other kernels in reverse mode)
     const bool persist_only = p.schedule == DTV_SCHED_PERSIST && !p.save_for_backward;
     pl->buf_bytes = persist_only ? 0 : sizeof(float) * (size_t)(pl->tot_p1 + pl->tot_p2);
-    pl->spl = p.inner == DTV_INNER_CP2 && !persist_only && p.n_inner >= 2
+    pl->spl = !persist_only && p.n_inner >= 2
                   ? std::min(p.steps_per_launch == 0 ? kDefaultStepsPerLaunch : p.steps_per_launch, p.n_inner)
                   : 1;
     // the multi-step kernel addresses a row by 32-bit byte offsets (at most 4 (W + nx) along a row
@@ -895,6 +922,7 @@ static int next_base(int sched, bool cp2, int K, int base, int spl)
     if (sched == DTV_SCHED_PERSIST) return base;
     if (sched == DTV_SCHED_FUSED) return base == 0 ? 1 : 0;  // the fused kernels read one buffer and write the other
     if (!cp2) {
+        if (spl > 1) return fista_stream_plan(K, spl, base).back().id;
         int rot[3] = {base, 0, 0}, q = 1;
         for (int k = 0; k < 3; ++k)
             if (k != base) rot[q++] = k;
@@ -1086,6 +1114,46 @@ static int solve_impl(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_mask, 
             if (rc != DTV_OK) return rc;
             base = out;
             lam_cur = lam_other();
+        } else if (!cp2 && pl->spl > 1) {
+            // launches of up to pl->spl steps (fista_stream_plan); c' in workspace buffer 3, formed
+            // by the first launch and stored when launches follow it
+            const std::vector<Cp2Launch> plan = fista_stream_plan(K, pl->spl, base);
+            for (const Cp2Launch &l : plan) {
+                const int mode = l.k0 == 1 ? kFistaFirst : (l.k0 == 2 ? kFistaPlain : kFistaMomentum);
+                int rc = with_host ? tm.begin() : DTV_OK;
+                if (rc != DTV_OK) return rc;
+                if (l.steps >= 2) {  // steps k0 .. k0 + steps - 1 in one launch
+                    FistaMultiArgs a{};
+                    a.imgs = pl->d_imgs(); a.tiles = pl->d_mtiles(l.steps, rows); a.ntiles = pl->nmtiles(l.steps, rows);
+                    a.info = pl->d_info();
+                    a.xa1 = bufs[l.ia].p1; a.xa2 = bufs[l.ia].p2; a.xb1 = bufs[l.ib].p1; a.xb2 = bufs[l.ib].p2;
+                    a.lam = lam_cur; a.f = d_f;
+                    a.c1 = bufs[3].p1; a.c2 = bufs[3].p2;
+                    const int ik = l.ic >= 0 ? l.ic : l.id;  // (not written when ic < 0)
+                    a.outk1 = bufs[ik].p1; a.outk2 = bufs[ik].p2;
+                    a.outn1 = bufs[l.id].p1; a.outn2 = bufs[l.id].p2;
+                    for (int L = 0; L < l.steps; ++L) a.beta[L] = beta[l.k0 + L];
+                    a.tau = (float)P.tau; a.inv_tau = (float)pl->inv_tau;
+                    a.store_c = l.k0 == 1 && plan.size() > 1;
+                    a.store_prev = l.ic >= 0;
+                    HIP_TRY(launch_fista_multi(a, mode, rows, l.steps, q, with_host ? tm.e0 : nullptr,
+                                               with_host ? tm.e1 : nullptr),
+                            "FISTA multi-step launch");
+                } else {
+                    FistaStepArgs a{};
+                    a.imgs = pl->d_imgs(); a.tiles = pl->d_tiles(rows); a.ntiles = pl->ntiles(rows); a.info = pl->d_info();
+                    a.xa1 = bufs[l.ia].p1; a.xa2 = bufs[l.ia].p2; a.xb1 = bufs[l.ib].p1; a.xb2 = bufs[l.ib].p2;
+                    a.lam = lam_cur; a.f = d_f;
+                    a.c1 = bufs[3].p1; a.c2 = bufs[3].p2;
+                    a.out1 = bufs[l.id].p1; a.out2 = bufs[l.id].p2;
+                    a.beta = beta[l.k0]; a.tau = (float)P.tau; a.inv_tau = (float)pl->inv_tau;
+                    HIP_TRY(launch_fista_step(a, mode, rows, q, with_host ? tm.e0 : nullptr, with_host ? tm.e1 : nullptr),
+                            "FISTA step");
+                }
+                rc = with_host ? tm.end() : DTV_OK;
+                if (rc != DTV_OK) return rc;
+            }
+            base = plan.back().id;
         } else if (!cp2) {
             // x_k lives in rot[k % 3]; c' in workspace buffer 3
             int rot[3] = {base, 0, 0}, r = 1;
@@ -1729,7 +1797,8 @@ extern "C" int dtv_dd_kernel_time(const dtv_dd_plan *pl, double *avg_ms, int64_t
                                : mixed ? "k_fused_fista_mixed"
                                : pl->stagger_blocks > 0 ? "k_fused_fista_staggered"
                                                         : "k_fused_fista")
-                        : (cp2 ? (pl->spl > 1 ? "k_cp2_multi" : "k_cp2_step") : "k_fista_step");
+                        : (cp2 ? (pl->spl > 1 ? "k_cp2_multi" : "k_cp2_step")
+                               : (pl->spl > 1 ? "k_fista_multi" : "k_fista_step"));
     if (bytes_per_launch) {
         // Algorithmic HBM bytes of one timed launch (E = edge dofs of the torn
         // p~, N = pixels, 4 bytes each), averaged over the launches of an outer step.
@@ -1742,7 +1811,10 @@ extern "C" int dtv_dd_kernel_time(const dtv_dd_plan *pl, double *avg_ms, int64_t
         //   CP2 step k >= 2: read x_{k-1}, x_{k-2}, anchor base, u, f (+ mask), write 4 (4E + 3N) + mask
         //   CP2 launch of steps k .. k + S - 1 (S >= 2): read x_{k-1}, x_{k-2} (k >= 2), anchor base, u, f
         //     (+ mask), write x_{k+S-2}, x_{k+S-1}, u               4 (5E + 3N) + mask (k = 1: 4 (3E + 3N) + mask)
-        //   (the streaming CP2 figure is the average over the launches of an outer step)
+        //   FISTA launch of steps k .. k + S - 1 (S >= 2): read x_{k-1} (k = 1: and f), x_{k-2} (k >= 3),
+        //     c' (k >= 2), write x_{k+S-1}, x_{k+S-2} and c' (k = 1) unless the launch ends the outer
+        //     step: 4 (2E + N) for all K steps in one launch
+        //   (the streaming figures are averages over the launches of an outer step)
         double E = 0.0, N = 0.0;
         for (const ImgHost &h : pl->imgs) {
             E += (double)(h.H + h.ny) * h.W + (double)h.H * (h.W + h.nx);
@@ -1771,6 +1843,20 @@ extern "C" int dtv_dd_kernel_time(const dtv_dd_plan *pl, double *avg_ms, int64_t
                 ++nl;
             }
             *bytes_per_launch = tot / nl;
+        } else if (pl->spl > 1) {
+            const std::vector<Cp2Launch> plan = fista_stream_plan(K, pl->spl, 0);
+            for (const Cp2Launch &l : plan) {
+                double b;
+                if (l.steps == 1) {
+                    b = l.k0 == 1 ? 4.0 * (3 * E + N) : (l.k0 == 2 ? 4.0 * (3 * E) : 4.0 * (4 * E));
+                } else {
+                    const double reads = l.k0 == 1 ? E + N : (l.k0 == 2 ? 2 * E : 3 * E);
+                    const double writes = E + (l.ic >= 0 ? E : 0.0) + (l.k0 == 1 && plan.size() > 1 ? E : 0.0);
+                    b = 4.0 * (reads + writes);
+                }
+                tot += b;
+            }
+            *bytes_per_launch = tot / (double)plan.size();
         } else {
             for (int k = 1; k <= K; ++k) {
                 if (cp2) tot += (k == 1 ? 4.0 * (2 * E + 3 * N) : 4.0 * (4 * E + 3 * N)) + mb;

@@ -149,6 +149,13 @@ def test_multi_step_launches_fall_back_beyond_32_bit_row_offsets():
     code, h = _setup(inner=1, steps_per_launch=1)
     assert code == 0 and _kernel_name(h) == "k_cp2_step"
     L.dtv_dd_destroy(h)
+    # the FISTA streaming schedule (schedule 1) likewise
+    code, h = _setup(schedule=1)
+    assert code == 0 and _kernel_name(h) == "k_fista_multi"
+    L.dtv_dd_destroy(h)
+    code, h = _setup(schedule=1, steps_per_launch=1)
+    assert code == 0 and _kernel_name(h) == "k_fista_step"
+    L.dtv_dd_destroy(h)
 
 
 def test_inner_counts_before_any_solve_are_zero():

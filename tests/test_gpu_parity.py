@@ -273,8 +273,17 @@ def test_nonfinite_input_is_reported():
 
 
 def test_kernel_timing_reports_launches():
+    """Streaming schedule: one timed launch per outer step with the four local
+    steps in one launch (the default), one per local step with one step per
+    launch."""
     c = synth.config1()
     plan, state, _, _, _ = run_gpu(c.f, c.alpha, c.row_cuts, c.col_cuts, n_outer=5, n_inner=4, time_kernels=True,
                                    schedule="stream")
     kt = plan.kernel_time()
+    assert kt["name"] == "k_fista_multi"
+    assert kt["launches"] == 5 and kt["avg_ms"] > 0 and kt["bytes_per_launch"] > 0
+    plan, state, _, _, _ = run_gpu(c.f, c.alpha, c.row_cuts, c.col_cuts, n_outer=5, n_inner=4, time_kernels=True,
+                                   schedule="stream", steps_per_launch=1)
+    kt = plan.kernel_time()
+    assert kt["name"] == "k_fista_step"
     assert kt["launches"] == 20 and kt["avg_ms"] > 0 and kt["bytes_per_launch"] > 0
