@@ -1206,6 +1206,7 @@ static int solve_impl(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_mask, 
                     a.fidelity = P.fidelity;
                     a.cv_c1 = (float)P.cv_c1;
                     a.cv_c2 = (float)P.cv_c2;
+                    a.store_prev = &l != &plan.back();  // the next outer step starts without extrapolation
                     HIP_TRY(launch_cp2_multi(a, it >= 1, rows, l.steps, q, with_host ? tm.e0 : nullptr,
                                              with_host ? tm.e1 : nullptr),
                             "CP2 multi-step launch");
@@ -1810,7 +1811,8 @@ extern "C" int dtv_dd_kernel_time(const dtv_dd_plan *pl, double *avg_ms, int64_t
         //   CP2 step 1: read x_0, u, f (+ mask bytes), write x_1, u                 4 (2E + 3N) + mask
         //   CP2 step k >= 2: read x_{k-1}, x_{k-2}, anchor base, u, f (+ mask), write 4 (4E + 3N) + mask
         //   CP2 launch of steps k .. k + S - 1 (S >= 2): read x_{k-1}, x_{k-2} (k >= 2), anchor base, u, f
-        //     (+ mask), write x_{k+S-2}, x_{k+S-1}, u               4 (5E + 3N) + mask (k = 1: 4 (3E + 3N) + mask)
+        //     (+ mask), write x_{k+S-1}, u and, unless the launch ends the outer step, x_{k+S-2}:
+        //     4 (5E + 3N) + mask (k = 1: 4 (3E + 3N) + mask; all K steps in one launch: 4 (2E + 3N) + mask)
         //   FISTA launch of steps k .. k + S - 1 (S >= 2): read x_{k-1} (k = 1: and f), x_{k-2} (k >= 3),
         //     c' (k >= 2), write x_{k+S-1}, x_{k+S-2} and c' (k = 1) unless the launch ends the outer
         //     step: 4 (2E + N) for all K steps in one launch
@@ -1835,14 +1837,16 @@ extern "C" int dtv_dd_kernel_time(const dtv_dd_plan *pl, double *avg_ms, int64_t
         } else if (fused) {
             *bytes_per_launch = 4.0 * (2 * E + N);
         } else if (cp2 && pl->spl > 1) {
-            int k = 1, nl = 0;
-            for (int S : cp2_launch_steps(K, pl->spl)) {
-                if (S >= 2) tot += (k == 1 ? 4.0 * (3 * E + 3 * N) : 4.0 * (5 * E + 3 * N)) + mb;
-                else tot += (k == 1 ? 4.0 * (2 * E + 3 * N) : 4.0 * (4 * E + 3 * N)) + mb;
+            const std::vector<int> steps = cp2_launch_steps(K, pl->spl);
+            int k = 1;
+            for (size_t n = 0; n < steps.size(); ++n) {
+                const int S = steps[n];
+                const double reads = (k == 1 ? E : 3 * E) + 2 * N;  // x_{k-1} (and x_{k-2}, base), u, f
+                const double writes = E + N + (S >= 2 && n + 1 < steps.size() ? E : 0.0);
+                tot += 4.0 * (reads + writes) + mb;
                 k += S;
-                ++nl;
             }
-            *bytes_per_launch = tot / nl;
+            *bytes_per_launch = tot / (double)steps.size();
         } else if (pl->spl > 1) {
             const std::vector<Cp2Launch> plan = fista_stream_plan(K, pl->spl, 0);
             for (const Cp2Launch &l : plan) {

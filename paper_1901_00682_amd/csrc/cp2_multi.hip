@@ -6,9 +6,11 @@
 // The one-step kernel (kernels.hip) reads x_{k-1}, x_{k-2}, the anchor, u, f
 // and the mask and writes x_k and u_k at every step.  Here the steps of a
 // launch pass their results to each other in registers: per launch the kernel
-// reads that input once and writes x_{k+S-2}, x_{k+S-1} and u_{k+S-1} (the
-// next launch extrapolates from the last two iterates), about 53 bytes per
-// pixel for any S (37 when k = 1) against 45 per step for one-step launches.
+// reads that input once and writes x_{k+S-1}, u_{k+S-1} and, when another
+// launch of the outer step follows (it extrapolates from the last two
+// iterates), x_{k+S-2}: about 53 bytes per pixel for any S, 29 for all five
+// steps of an outer step in one launch, against 45 per step for one-step
+// launches.
 //
 // Work decomposition as in the one-step kernel: a 64-lane wave owns a strip
 // of R rows and 64 consecutive columns.  Level L of the launch runs step
@@ -127,6 +129,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(multi_waves(
     float *__restrict__ kb2 = a.outn2 + im.p2;
     const float tau = a.tau;
     const float cv1 = a.cv_c1, cv2 = a.cv_c2;
+    const bool store_prev = a.store_prev != 0;
 
     auto xbar0 = [&](float x, float xp) -> float {
         if constexpr (EXT) return fmaf(a.theta[0], x - xp, x);
@@ -213,19 +216,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(multi_waves(
             if (outlane && q >= i0 && q < iend) {
                 at_byte(uout + (long long)q * W, uj) = u1;
                 if (q > 0) {
-                    at_byte(ka1 + tp * P1, uj) = m.kt;
+                    if (store_prev) at_byte(ka1 + tp * P1, uj) = m.kt;
                     at_byte(kb1 + tp * P1, uj) = nt;
                 }
                 if (j > 0) {
-                    at_byte(ka2 + q * P2, ul) = m.kl;
+                    if (store_prev) at_byte(ka2 + q * P2, ul) = m.kl;
                     at_byte(kb2 + q * P2, ul) = nl;
                 }
                 if (rlast && q < H - 1) {
-                    at_byte(ka1 + (tp + 1) * P1, uj) = m.kb;
+                    if (store_prev) at_byte(ka1 + (tp + 1) * P1, uj) = m.kb;
                     at_byte(kb1 + (tp + 1) * P1, uj) = nb;
                 }
                 if (clast && j < W - 1) {
-                    at_byte(ka2 + q * P2 + 1, ul) = m.kr;
+                    if (store_prev) at_byte(ka2 + q * P2 + 1, ul) = m.kr;
                     at_byte(kb2 + q * P2 + 1, ul) = nr;
                 }
             }
