@@ -505,6 +505,11 @@ def main():
                     "traffic": measured_traffic(kt["name"], args.workload),
                     "avg_launch_us": avg_ms * 1e3, "bytes_per_launch": kt["bytes_per_launch"],
                     "launches_per_step": kt["launches"]}
+        if kt["name"] in ("k_cp2_multi", "k_fista_multi"):
+            # several local steps per launch: the launch moves a fraction of the one-step bytes and
+            # is limited by instruction issue and latency, not by HBM (the VALU counter passes of
+            # profiles/k_cp2_multi_tvl1.md and profiles/k_fista_multi_rof2048.md: 86 % and 67 % busy)
+            roofline["limiter"] = "vector ALU issue and latency (HBM figure: algorithmic bytes / launch time)"
     if args.calibrate_copy:
         # a plain device copy of known size, for scaling the HBM byte counters
         nbytes = 256 << 20
