@@ -207,7 +207,8 @@ def backward_measure(steps: int, warmup: int, schedule: str = "auto") -> dict:
     backward, each timed with the host clock around the call; then one more
     backward with HIP events around every launch of the reverse kernel and of
     the recording forward (their rooflines: algorithmic bytes over the average
-    launch)."""
+    launch).  Then the same with keep_records (the forward keeps every outer
+    step's records, the backward recomputes nothing)."""
     import torch
 
     from paper_1901_00682_amd import dtvdd, synth
@@ -245,6 +246,7 @@ def backward_measure(steps: int, warmup: int, schedule: str = "auto") -> dict:
     tplan.solve(fl, state=ts, want_stats=False)
     tplan.backward(fl, 2.0 * (ts["u"][: B * H * W] - g.reshape(-1)))
     torch.cuda.synchronize()
+    sched = plan.schedule()
     kern = {}
     for which in (0, 1):
         kt = tplan.backward_kernel_time(which)
@@ -256,6 +258,44 @@ def backward_measure(steps: int, warmup: int, schedule: str = "auto") -> dict:
                     "_rec" if which == 1 else ""), "diff"),
                 "avg_launch_us": kt["avg_ms"] * 1e3, "launches": kt["launches"],
                 "bytes_per_launch": kt["bytes_per_launch"]}
+    for p in (plan, tplan):
+        p.close()
+    del plan, tplan, st, ts
+    # keep_records: the forward keeps the state before every outer step and that step's records
+    # (the recording kernel runs in the forward), so the backward only reverses
+    kr = {}
+    if schedule in ("auto", "fused"):
+        trf, trb = [], []
+        rplan = dtvdd.Plan(imgs, n_outer=n_outer, n_inner=K, save_for_backward=True, keep_records=True, device=dev)
+        sr = rplan.new_state()
+        for it in range(warmup + steps):
+            torch.cuda.synchronize(); t0 = time.perf_counter()
+            rplan.solve(fl, state=sr, want_stats=False)
+            torch.cuda.synchronize(); t1 = time.perf_counter()
+            rplan.backward(fl, 2.0 * (sr["u"][: B * H * W] - g.reshape(-1)))
+            torch.cuda.synchronize(); t2 = time.perf_counter()
+            if it >= warmup:
+                trf.append(t1 - t0); trb.append(t2 - t1)
+        ws_gb = rplan.ws.numel() / 1e9
+        rplan.close()
+        del rplan, sr
+        rplan = dtvdd.Plan(imgs, n_outer=n_outer, n_inner=K, save_for_backward=True, keep_records=True, device=dev,
+                           time_kernels=True)
+        sr = rplan.new_state()
+        rplan.solve(fl, state=sr, want_stats=False)
+        rplan.backward(fl, 2.0 * (sr["u"][: B * H * W] - g.reshape(-1)))
+        torch.cuda.synchronize()
+        rk = {}
+        for key, kt in (("recording_forward", rplan.kernel_time()), ("reverse", rplan.backward_kernel_time(0))):
+            gbs = kt["bytes_per_launch"] / (kt["avg_ms"] * 1e-3) / 1e9
+            rk[key] = {"kernel": kt["name"], "achieved": gbs, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                       "avg_launch_us": kt["avg_ms"] * 1e3, "launches": kt["launches"],
+                       "bytes_per_launch": kt["bytes_per_launch"]}
+        rplan.close()
+        del rplan, sr
+        fr, br = float(np.median(trf)) * 1e3, float(np.median(trb)) * 1e3
+        kr = {"forward_ms": fr, "backward_ms": br, "forward_plus_backward_ms": fr + br,
+              "backward_over_forward": br / (float(np.median(tp)) * 1e3), "workspace_GB": ws_gb, "kernels": rk}
     px = B * H * W
     out = {"workload": f"differentiation: {B} x {H}x{W} ROF, 4x4 subdomains, {n_outer} outer x {K} inner, "
                        "loss |u - g|^2, gradient in f and alpha, checkpoint every 20 outer steps",
@@ -264,9 +304,9 @@ def backward_measure(steps: int, warmup: int, schedule: str = "auto") -> dict:
            "backward_ms": float(np.median(tb)) * 1e3,
            "backward_over_forward": float(np.median(tb)) / float(np.median(tp)),
            "forward_value": px * n_outer * K / float(np.median(tp)), "unit": "pixel-inner-iterations/s",
-           "steps": steps, "schedule": plan.schedule(), "kernels": kern}
-    for p in (plan, plain, tplan):
-        p.close()
+           "forward_plus_backward_ms": (float(np.median(tf)) + float(np.median(tb))) * 1e3,
+           "steps": steps, "schedule": sched, "kernels": kern, "keep_records": kr}
+    plain.close()
     return out
 
 

@@ -183,6 +183,15 @@ typedef struct {
                                   registers.  Every value gives the same result bitwise.  Ignored
                                   by the other schedules; the reverse pass's recomputation runs one
                                   step per launch */
+    int32_t keep_records;      /* 1 (with save_for_backward, the fused or auto schedule and the
+                                  on-chip reverse: every subdomain 128 x 128, n_inner 1 .. 8 or 10):
+                                  the forward solve runs the recording fused kernel at every outer
+                                  step and keeps the state before each outer step and that step's
+                                  records (9 n_inner bytes per pixel), so that dtv_dd_backward runs
+                                  the reverse steps alone, with no recomputation; ckpt_every is then
+                                  not used.  The workspace grows to about n_outer (9 n_inner + 8)
+                                  bytes per pixel.  0: checkpoints every ckpt_every outer steps,
+                                  recomputed by the backward pass */
 } dtv_dd_params;
 
 /* Where image `image` lives in the concatenated buffers (element offsets). */
@@ -263,8 +272,9 @@ int dtv_dd_kernel_time(const dtv_dd_plan *plan, double *avg_ms, int64_t *launche
 /* Average duration (ms) of the reverse mode's kernel launches timed in the last dtv_dd_backward
    of a plan with time_kernels = 1 and the fused reverse (every subdomain 128 x 128): which = 0
    the on-chip reverse steps (k_fused_bwd, one launch per outer step), which = 1 the recording
-   forward (one launch per outer step); their count, the kernel's name and its algorithmic HBM
-   bytes per launch.  Zeros when nothing was timed. */
+   forward (one launch per outer step; none with keep_records, where the forward solve records);
+   their count, the kernel's name and its algorithmic HBM bytes per launch.  Zeros when nothing
+   was timed. */
 int dtv_dd_backward_kernel_time(const dtv_dd_plan *plan, int32_t which, double *avg_ms, int64_t *launches,
                                 const char **name, double *bytes_per_launch);
 

@@ -357,6 +357,10 @@ static std::vector<Choice> candidates(const dtv_dd_plan *pl)
         if (any_of_sched(p.schedule, DTV_SCHED_FUSED)) c.push_back({DTV_SCHED_FUSED, pl->rows});
         return c;
     }
+    if (p.keep_records) {  // only the fused kernel records its steps
+        c.push_back({DTV_SCHED_FUSED, pl->rows});
+        return c;
+    }
     const bool any = p.schedule == DTV_SCHED_AUTO;
     if ((any || p.schedule == DTV_SCHED_PERSIST) && pl->persist_ok) c.push_back({DTV_SCHED_PERSIST, pl->rows});
     if ((any || p.schedule == DTV_SCHED_FUSED) && pl->fused_ok) c.push_back({DTV_SCHED_FUSED, pl->rows});
@@ -438,6 +442,10 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
     if (p.spin_limit < 0) return fail(DTV_EINVAL, "spin_limit must be >= 0");
     if (p.steps_per_launch < 0 || p.steps_per_launch > kMaxMultiSteps)
         return fail(DTV_EINVAL, "steps_per_launch must be between 0 and 5");
+    if (p.keep_records != 0 && p.keep_records != 1) return fail(DTV_EINVAL, "keep_records must be 0 or 1");
+    if (p.keep_records && !p.save_for_backward) return fail(DTV_EINVAL, "keep_records needs save_for_backward");
+    if (p.keep_records && p.schedule != DTV_SCHED_AUTO && p.schedule != DTV_SCHED_FUSED)
+        return fail(DTV_EINVAL, "keep_records runs the fused schedule (auto or fused)");
 
     dtv_dd_plan *pl = new dtv_dd_plan();
     pl->uid = ++g_plan_ids;
@@ -682,16 +690,28 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
     if (p.save_for_backward) {
         const size_t E = (size_t)(pl->tot_p1 + pl->tot_p2);
         pl->state_floats = E + (size_t)pl->tot_lam;
-        const int C = p.ckpt_every;
+        // with keep_records the state before every outer step is a checkpoint (and no segment is
+        // recomputed)
+        const int C = p.keep_records ? 1 : p.ckpt_every;
         pl->nseg = (p.n_outer + C - 1) / C;
         const int segmax = std::min(C, std::max(p.n_outer, 1));
         pl->off_ckpt = take(sizeof(float) * pl->state_floats * (size_t)(pl->nseg + 1));
         // a segment's states before each of its steps and after its last one
-        pl->off_seg = take(sizeof(float) * pl->state_floats * (size_t)(segmax + 1));
+        pl->off_seg = take(p.keep_records ? 0 : sizeof(float) * pl->state_floats * (size_t)(segmax + 1));
         const size_t nsub = pl->h_subs.size();
         pl->fbwd = pl->fused_ok && pl->n_full == (int)nsub && fused_record_supported(p.n_inner) &&
                    fused_bwd_supported(p.n_inner);
-        if (pl->fbwd) {
+        if (p.keep_records && !pl->fbwd) {
+            delete pl;
+            return fail(DTV_EINVAL, "keep_records needs the on-chip reverse: every subdomain 128 x 128 and n_inner "
+                                    "1 .. 8 or 10");
+        }
+        if (p.keep_records) {
+            // the records of every outer step, written by the forward solve
+            pl->rec_step = sizeof(float4) * (size_t)p.n_inner * nsub * kRecGroups * kRecThreads;
+            pl->off_frec = take(pl->rec_step * (size_t)std::max(p.n_outer, 1));
+            pl->off_gsub = take(sizeof(double) * nsub);
+        } else if (pl->fbwd) {
             // the records of a whole segment when they fit the budget (the segment's states are then
             // recomputed by the recording launches themselves), else of one outer step
             pl->rec_step = sizeof(float4) * (size_t)p.n_inner * nsub * kRecGroups * kRecThreads;
@@ -712,6 +732,8 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
     pl->ws_bytes = off;
     if (p.schedule != DTV_SCHED_AUTO)
         pl->schedule = p.schedule;
+    else if (p.keep_records)  // only the fused kernel records its steps
+        pl->schedule = DTV_SCHED_FUSED;
     else
         pl->schedule = pl->persist_ok ? DTV_SCHED_PERSIST : pl->fused_ok ? DTV_SCHED_FUSED : DTV_SCHED_STREAM;
     pl->rows = p.rows ? p.rows : 16;
@@ -1303,11 +1325,57 @@ static int solve_impl(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_mask, 
         return DTV_OK;
     };
 
+    // keep_records: outer steps [n0, n1) with the recording fused kernel.  Step n reads its state
+    // (p~^n and the lambda state) from checkpoint slot n and writes the next one to slot n + 1, its
+    // records to frec(n); the state after step n1 - 1 is then copied to the current buffers.
+    auto run_recorded = [&](int n0, int n1) -> int {
+        const size_t E = pl->edges();
+        if (n0 == 0) {
+            int rc = save_state(0, bufs[base]);
+            if (rc != DTV_OK) return rc;
+        }
+        for (int n = n0; n < n1; ++n) {
+            float *st = pl->ckpt(n), *nx = pl->ckpt(n + 1);
+            FusedArgs ra = fa;
+            ra.base1 = st;
+            ra.base2 = st + pl->tot_p1;
+            ra.lam = st + E;
+            ra.out1 = nx;
+            ra.out2 = nx + pl->tot_p1;
+            ra.lam_out = nx + E;
+            ra.rec = pl->frec(n);
+            int rc = tm.begin();
+            if (rc != DTV_OK) return rc;
+            HIP_TRY(launch_fused_fista(ra, (int)pl->h_subs.size(), pl->n_full, pl->n_framed, s, tm.e0, tm.e1),
+                    "fused FISTA (recording)");
+            rc = tm.end();
+            if (rc != DTV_OK) return rc;
+            if (P.diag_every > 0 && ((n + 1) % P.diag_every == 0 || n == P.n_outer - 1)) {
+                HIP_TRY(launch_u_from_p(pl->d_imgs(), pl->n, pl->maxH, pl->maxW, pl->d_info(), nx, nx + pl->tot_p1,
+                                        d_f, d_u, s),
+                        "u recovery");
+                rc = emit_stats(n + 1, d_u, EdgeBuf{nx, nx + pl->tot_p1});
+                if (rc != DTV_OK) return rc;
+            }
+        }
+        const float *fin = pl->ckpt(n1);
+        HIP_TRY(hipMemcpyAsync(bufs[base].p1, fin, sizeof(float) * (size_t)pl->tot_p1, hipMemcpyDeviceToDevice, s),
+                "state");
+        HIP_TRY(hipMemcpyAsync(bufs[base].p2, fin + pl->tot_p1, sizeof(float) * (size_t)pl->tot_p2,
+                               hipMemcpyDeviceToDevice, s),
+                "state");
+        if (pl->tot_lam > 0)
+            HIP_TRY(hipMemcpyAsync(lam_cur, fin + E, sizeof(float) * (size_t)pl->tot_lam, hipMemcpyDeviceToDevice, s),
+                    "state");
+        return DTV_OK;
+    };
+
     // Outer steps [n0, n1) with one schedule.  The per-step schedules replay a
     // captured cycle of outer steps (the rotation of the edge buffers returns
     // to its start after 1, 2 or 3 steps) when there is no host work per step.
     auto run_range = [&](int n0, int n1, int sched, int rows, bool graphs) -> int {
         if (n1 <= n0) return DTV_OK;
+        if (P.keep_records) return run_recorded(n0, n1);
         if (sched == DTV_SCHED_PERSIST) {
             if (!P.save_for_backward) return run_persist(n1 - n0);
             // with checkpoints: one launch per segment of ckpt_every outer steps, the state saved before it
@@ -1446,7 +1514,8 @@ static int solve_impl(dtv_dd_plan *pl, const float *d_f, const uint8_t *d_mask, 
     }
 
     if (P.save_for_backward) {
-        int rc = save_state(pl->nseg, bufs[base]);
+        // (keep_records: the recording steps wrote the last state to slot n_outer = nseg already)
+        int rc = P.keep_records && P.n_outer > 0 ? DTV_OK : save_state(pl->nseg, bufs[base]);
         if (rc != DTV_OK) return rc;
         pl->saved = true;
         pl->saved_outer = P.n_outer;
@@ -1637,10 +1706,9 @@ static int backward_fused(dtv_dd_plan *pl, const float *d_f, float *d_grad_f, fl
                 rec ? "fused FISTA (recording)" : "fused FISTA");
         return DTV_OK;
     };
-    // the reverse of outer step q of the segment, from its state seg(q), the lambda state after its
-    // multiplier update (lam_next) and its records
-    auto reverse = [&](int q, const float *lam_next, const float4 *rec) -> int {
-        const float *st = pl->seg(q);
+    // the reverse of an outer step from its state st, the lambda state after its multiplier update
+    // (lam_next) and its records
+    auto reverse = [&](const float *st, const float *lam_next, const float4 *rec) -> int {
         ba.x0_1 = st;
         ba.x0_2 = st + pl->tot_p1;
         ba.lam = lam_next;
@@ -1654,7 +1722,12 @@ static int backward_fused(dtv_dd_plan *pl, const float *d_f, float *d_grad_f, fl
                 "interface reverse");
         return DTV_OK;
     };
-    for (int sg = pl->nseg - 1; sg >= 0; --sg) {
+    // keep_records: the forward solve kept every state and every outer step's records
+    for (int n = P.keep_records ? N - 1 : -1; n >= 0; --n) {
+        int rc = reverse(pl->ckpt(n), pl->ckpt(n + 1) + E, pl->frec(n));
+        if (rc != DTV_OK) return rc;
+    }
+    for (int sg = P.keep_records ? -1 : pl->nseg - 1; sg >= 0; --sg) {
         const int n0 = sg * C, n1 = std::min(N, n0 + C), m = n1 - n0;
         HIP_TRY(hipMemcpyAsync(pl->seg(0), pl->ckpt(sg), sizeof(float) * pl->state_floats, hipMemcpyDeviceToDevice, s),
                 "restore checkpoint");
@@ -1665,7 +1738,7 @@ static int backward_fused(dtv_dd_plan *pl, const float *d_f, float *d_grad_f, fl
                 if (rc != DTV_OK) return rc;
             }
             for (int q = m - 1; q >= 0; --q) {
-                int rc = reverse(q, pl->seg(q + 1) + E, pl->frec(q));
+                int rc = reverse(pl->seg(q), pl->seg(q + 1) + E, pl->frec(q));
                 if (rc != DTV_OK) return rc;
             }
             continue;
@@ -1677,7 +1750,7 @@ static int backward_fused(dtv_dd_plan *pl, const float *d_f, float *d_grad_f, fl
         for (int q = m - 1; q >= 0; --q) {  // its outer steps in reverse, each recorded again
             int rc = forward(pl->seg(q), pl->buf1(0), pl->lam1(), pl->frec());
             if (rc != DTV_OK) return rc;
-            rc = reverse(q, pl->lam1(), pl->frec());
+            rc = reverse(pl->seg(q), pl->lam1(), pl->frec());
             if (rc != DTV_OK) return rc;
         }
     }
@@ -1795,6 +1868,7 @@ extern "C" int dtv_dd_kernel_time(const dtv_dd_plan *pl, double *avg_ms, int64_t
     if (name)
         *name = persist ? (cp2 ? "k_persist_cp2" : "k_persist_fista")
                 : fused ? (cp2 ? "k_fused_cp2"
+                               : pl->prm.keep_records ? "k_fused_fista (recording)"
                                : mixed ? "k_fused_fista_mixed"
                                : pl->stagger_blocks > 0 ? "k_fused_fista_staggered"
                                                         : "k_fused_fista")
@@ -1804,6 +1878,7 @@ extern "C" int dtv_dd_kernel_time(const dtv_dd_plan *pl, double *avg_ms, int64_t
         // Algorithmic HBM bytes of one timed launch (E = edge dofs of the torn
         // p~, N = pixels, 4 bytes each), averaged over the launches of an outer step.
         //   fused: read p~^n and f, write p~^(n+1)                                 4 (2E + N)
+        //   fused, recording (keep_records): and write the K step records          4 (2E + N) + 9 K N
         //   fused CP2: read p~^n, u, f (+ mask bytes), write p~^(n+1), u           4 (2E + 3N) + mask
         //   streaming FISTA step 1: read x_0 and f, write c' and x_1                4 (3E + N)
         //   streaming FISTA step 2: read x_1 and c', write x_2                      4 (3E)
@@ -1834,6 +1909,10 @@ extern "C" int dtv_dd_kernel_time(const dtv_dd_plan *pl, double *avg_ms, int64_t
             *bytes_per_launch = 4.0 * (2 * E + N + 6 * lam) + 32.0 * lam * pl->prm.n_outer + (cp2 ? 8.0 * N + mb : 0.0);
         } else if (fused && cp2) {
             *bytes_per_launch = 4.0 * (2 * E + 3 * N) + mb;
+        } else if (fused && pl->prm.keep_records) {
+            // and write the K step records, 9 bytes per pixel each (kRecGroups 16-byte groups per
+            // thread of 16 pixels)
+            *bytes_per_launch = 4.0 * (2 * E + N) + (double)kRecGroups * K * N;
         } else if (fused) {
             *bytes_per_launch = 4.0 * (2 * E + N);
         } else if (cp2 && pl->spl > 1) {

@@ -56,7 +56,7 @@ class Params(ctypes.Structure):
                 ("schedule", ctypes.c_int32), ("time_kernels", ctypes.c_int32), ("rows", ctypes.c_int32),
                 ("no_graphs", ctypes.c_int32), ("cv_c1", ctypes.c_double), ("cv_c2", ctypes.c_double),
                 ("full_problem", ctypes.c_int32), ("spin_limit", ctypes.c_int32), ("inner_tol", ctypes.c_double),
-                ("steps_per_launch", ctypes.c_int32)]
+                ("steps_per_launch", ctypes.c_int32), ("keep_records", ctypes.c_int32)]
 
 
 class Layout(ctypes.Structure):
@@ -149,7 +149,7 @@ class Plan:
                  sigma0=1.0 / 80.0, gamma=None, n_outer=100, n_inner=10, diag_every=0, gap_tol=0.0,
                  warm_start=False, save_for_backward=False, ckpt_every=20, schedule="auto",
                  time_kernels=False, rows=0, graphs=True, c1=0.6, c2=0.1, full_problem=False, inner_tol=0.0,
-                 spin_limit=0, steps_per_launch=0, device=None, bind=True):
+                 spin_limit=0, steps_per_launch=0, keep_records=False, device=None, bind=True):
         import torch
 
         L = lib()
@@ -173,7 +173,7 @@ class Plan:
                              int(diag_every), float(gap_tol), int(warm_start), int(save_for_backward),
                              int(ckpt_every), SCHEDULE[schedule], int(time_kernels), int(rows),
                              int(not graphs), float(c1), float(c2), int(full_problem), int(spin_limit),
-                             float(inner_tol), int(steps_per_launch))
+                             float(inner_tol), int(steps_per_launch), int(keep_records))
         h = ctypes.c_void_p()
         _check(L.dtv_dd_setup(descs, len(self.images), ctypes.byref(self.params), ctypes.byref(h)))
         self.h = h
@@ -372,11 +372,14 @@ def _torch_function():
         """u = solve(f, alpha) with the unrolled Algorithm 1 (FISTA local
         steps); differentiable in f and alpha through the library's reverse
         mode with outer-step checkpoints.  f: [H, W] or [B, H, W] float32 on the
-        GPU; alpha: a scalar or [B] tensor (one weight per image)."""
+        GPU; alpha: a scalar or [B] tensor (one weight per image).  keep_records:
+        the forward solve keeps every outer step's step records instead
+        (about n_outer (9 n_inner + 8) bytes per pixel of device memory), so
+        that the backward pass recomputes nothing."""
 
         @staticmethod
         def forward(ctx, f, alpha, grid=(4, 4), n_outer=200, n_inner=5, ckpt_every=20, tau=50.0, sigma=0.01,
-                    schedule="auto"):
+                    schedule="auto", keep_records=False):
             batched = f.dim() == 3
             fb = f if batched else f.unsqueeze(0)
             B, H, W = fb.shape
@@ -386,7 +389,7 @@ def _torch_function():
             rc, cc = floor_cuts(H, grid[0]), floor_cuts(W, grid[1])
             plan = Plan([Image(H, W, rc, cc, float(al[b])) for b in range(B)], n_outer=n_outer, n_inner=n_inner,
                         save_for_backward=True, ckpt_every=ckpt_every, tau=tau, sigma=sigma, schedule=schedule,
-                        device=f.device)
+                        keep_records=keep_records, device=f.device)
             fl = fb.detach().contiguous().reshape(-1).to(torch.float32)
             state, _ = plan.solve(fl, want_stats=False)
             u = state["u"][: B * H * W].view(B, H, W).clone()
@@ -406,7 +409,7 @@ def _torch_function():
             if ga.numel() != max(1, int(np.prod(ctx.alpha_shape))):
                 ga = ga.sum()   # one alpha shared by the whole batch
             ga = ga.reshape(ctx.alpha_shape).to(ctx.alpha_device)
-            return gf, ga, None, None, None, None, None, None, None
+            return gf, ga, None, None, None, None, None, None, None, None
 
     return DTVDD
 

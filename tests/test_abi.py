@@ -102,6 +102,12 @@ def test_valid_setup_and_layout():
     (dict(spin_limit=-1), "spin_limit"),
     (dict(inner=1, steps_per_launch=6), "steps_per_launch"),
     (dict(inner=1, steps_per_launch=-1), "steps_per_launch"),
+    (dict(keep_records=2), "keep_records must"),
+    (dict(keep_records=1), "keep_records needs save_for_backward"),
+    (dict(keep_records=1, save_for_backward=1, schedule=1), "keep_records runs the fused"),
+    (dict(keep_records=1, save_for_backward=1), "on-chip reverse"),
+    (dict(keep_records=1, save_for_backward=1, H=256, W=256, rc=(0, 128, 256), cc=(0, 128, 256), n_inner=9),
+     "on-chip reverse"),
 ])
 def test_validation_errors(kw, msg):
     code, h = _setup(**kw)
@@ -245,3 +251,27 @@ def test_scratch_size_matches_header():
     text = open(os.path.join(ROOT, "include", "dtvdd.h")).read()
     m = re.search(r"#define DTV_SCRATCH_BYTES \((\d+)u << (\d+)\)", text)
     assert m and int(m.group(1)) << int(m.group(2)) == dtvdd.SCRATCH_BYTES
+
+
+def test_keep_records_workspace_and_schedule():
+    """keep_records: the fused schedule without measuring, the records of every
+    outer step (9 n_inner bytes per pixel) and the state before each in the
+    workspace."""
+    L = dtvdd.lib()
+    big = dict(H=256, W=384, rc=(0, 128, 256), cc=(0, 128, 256, 384), save_for_backward=1, n_outer=30, n_inner=5)
+    code, h0 = _setup(**big)
+    assert code == 0, dtvdd.lib().dtv_last_error().decode()
+    code, h1 = _setup(keep_records=1, **big)
+    assert code == 0, dtvdd.lib().dtv_last_error().decode()
+    n0, n1 = ctypes.c_size_t(), ctypes.c_size_t()
+    assert L.dtv_dd_workspace_bytes(h0, ctypes.byref(n0)) == 0
+    assert L.dtv_dd_workspace_bytes(h1, ctypes.byref(n1)) == 0
+    px = 256 * 384
+    # the checkpointed plan keeps the records of one segment (20 outer steps) at most
+    assert n1.value >= 30 * 9 * 5 * px and n1.value - n0.value >= 10 * 9 * 5 * px
+    sch, rows, src = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    assert L.dtv_dd_choice(h1, ctypes.byref(sch), ctypes.byref(rows), ctypes.byref(src)) == 0
+    assert sch.value == 2 and src.value == 0  # DTV_SCHED_FUSED by the rule
+    assert _kernel_name(h1) == "k_fused_fista (recording)"
+    L.dtv_dd_destroy(h0)
+    L.dtv_dd_destroy(h1)

@@ -24,11 +24,11 @@ def _gpu():
         pytest.skip("no GPU")
 
 
-def gpu_grad(fs, alphas, rc, cc, ubars, n_outer, K, ckpt_every, schedule="auto"):
+def gpu_grad(fs, alphas, rc, cc, ubars, n_outer, K, ckpt_every, schedule="auto", **kw):
     from paper_1901_00682_amd import dtvdd
     H, W = fs[0].shape
     plan = dtvdd.Plan([dtvdd.Image(H, W, rc, cc, a) for a in alphas], n_outer=n_outer, n_inner=K,
-                      save_for_backward=True, ckpt_every=ckpt_every, schedule=schedule)
+                      save_for_backward=True, ckpt_every=ckpt_every, schedule=schedule, **kw)
     f = torch.from_numpy(np.concatenate([x.ravel() for x in fs]).astype(np.float32)).cuda()
     st, _ = plan.solve(f, want_stats=False)
     gu = torch.from_numpy(np.concatenate([x.ravel() for x in ubars]).astype(np.float32)).cuda()

@@ -1,6 +1,8 @@
 """Reverse mode with the fused kernels (every subdomain 128 x 128: a recording
 forward launch and an on-chip reverse launch per outer step) against the FP64
-oracle's reverse pass; independence of the checkpoint spacing and of batching."""
+oracle's reverse pass; independence of the checkpoint spacing and of batching;
+the forward solve that keeps every outer step's records (keep_records) against
+the checkpointed one, bitwise."""
 import sys
 
 import numpy as np
@@ -132,3 +134,58 @@ def test_backward_after_persistent_forward_equals_fused_forward():
         res[sch] = (st["u"].cpu().numpy().copy(), gf.cpu().numpy().copy(), ga.cpu().numpy().copy())
     for a, b in zip(res["persistent"], res["fused"]):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("H,W,alphas,n_outer,K", [
+    (256, 384, [8.0], 23, 5),
+    (256, 256, [4.0, 12.0], 7, 10),
+    (128, 256, [6.0], 5, 1),
+    (128, 128, [3.0], 1, 8),
+])
+def test_keep_records_equals_checkpoints_bitwise(H, W, alphas, n_outer, K):
+    """keep_records: the forward solve runs the recording fused kernel from
+    checkpoint slot n to slot n + 1 and keeps every step's records; the
+    backward pass only reverses.  Same kernels and arithmetic as the
+    checkpointed pass, whose recomputation records the same states: u, the
+    final state and both gradients are bitwise equal."""
+    rc, cc = np.arange(0, H + 1, 128), np.arange(0, W + 1, 128)
+    probs = [_problem(H, W, 90 + b + K) for b in range(len(alphas))]
+    fs, ubars = [p[0] for p in probs], [p[1] for p in probs]
+    _say(f"[keep records] {len(alphas)} x {H}x{W} {n_outer}x{K}")
+    gf0, ga0, _, st0 = gpu_grad(fs, alphas, rc, cc, ubars, n_outer, K, 3)
+    gf1, ga1, plan, st1 = gpu_grad(fs, alphas, rc, cc, ubars, n_outer, K, 3, keep_records=True)
+    assert plan.schedule() == "fused"
+    for q in ("u", "p1", "p2", "lam"):
+        assert torch.equal(st0[q], st1[q]), q
+    assert np.array_equal(gf0, gf1) and np.array_equal(ga0, ga1)
+
+
+def test_keep_records_against_oracle_and_timed():
+    from paper_1901_00682_amd import dtvdd
+    H, W, alpha, n_outer, K = 256, 256, 8.0, 6, 5
+    rc, cc = np.arange(0, H + 1, 128), np.arange(0, W + 1, 128)
+    f, ubar = _problem(H, W, 501)
+    _say(f"[keep records] {H}x{W} {n_outer}x{K} against the oracle, timed")
+    plan = dtvdd.Plan([dtvdd.Image(H, W, rc, cc, alpha)], n_outer=n_outer, n_inner=K, save_for_backward=True,
+                      keep_records=True, time_kernels=True, diag_every=2)
+    ft = torch.from_numpy(f.ravel()).cuda()
+    st, stats = plan.solve(ft)
+    gf, ga = plan.backward(ft, torch.from_numpy(ubar.astype(np.float32).ravel()).cuda())
+    torch.cuda.synchronize()
+    kt = plan.kernel_time()
+    assert kt["name"] == "k_fused_fista (recording)" and kt["launches"] == n_outer
+    assert plan.backward_kernel_time(0)["launches"] == n_outer
+    assert plan.backward_kernel_time(1)["launches"] == 0
+    # the diagnostics follow the same states as a plain solve's
+    ref = dtvdd.Plan([dtvdd.Image(H, W, rc, cc, alpha)], n_outer=n_outer, n_inner=K, schedule="fused", diag_every=2)
+    st_ref, stats_ref = ref.solve(ft)
+    torch.cuda.synchronize()
+    assert torch.equal(st["u"], st_ref["u"])
+    assert np.array_equal(np.asarray(stats), np.asarray(stats_ref))
+    o = oracle.Oracle(oracle.Problem(f.astype(np.float64), alpha, rc, cc, n_inner=K))
+    fbar, abar = o.backward(n_outer, ubar.astype(np.float32).astype(np.float64))
+    e_f = rel_l2(gf.cpu().numpy().astype(np.float64).reshape(H, W), fbar)
+    e_a = abs(float(ga.cpu()[0]) - abar) / abs(abar)
+    _say(f"  dl/df rel L2 {e_f:.2e}   dl/dalpha rel {e_a:.2e}")
+    assert e_f <= 1e-4
+    assert e_a <= 1e-4
