@@ -192,6 +192,17 @@ typedef struct {
                                   not used.  The workspace grows to about n_outer (9 n_inner + 8)
                                   bytes per pixel.  0: checkpoints every ckpt_every outer steps,
                                   recomputed by the backward pass */
+    int32_t reverse_schedule;  /* the reverse steps of dtv_dd_backward on the on-chip reverse (every
+                                  subdomain 128 x 128): DTV_SCHED_AUTO = one cooperative launch per
+                                  range of outer steps whose records are all kept (a checkpoint
+                                  segment's when they fit 4 GiB, the whole solve's with keep_records)
+                                  when every subdomain is resident at once, pbar kept on chip and
+                                  the interface transpose done point to point between the tiles,
+                                  else as DTV_SCHED_FUSED; DTV_SCHED_FUSED = one launch per outer
+                                  step and an interface-transpose launch; DTV_SCHED_PERSIST = the
+                                  cooperative launches or DTV_EINVAL at setup.  Every choice gives
+                                  the same result bitwise.  A wait that gives up (spin_limit) is
+                                  reported by dtv_dd_status */
 } dtv_dd_params;
 
 /* Where image `image` lives in the concatenated buffers (element offsets). */
@@ -242,7 +253,8 @@ int dtv_dd_bind_workspace(dtv_dd_plan *plan, void *d_ws, size_t bytes);
 int dtv_dd_solve(dtv_dd_plan *plan, const float *d_f, const uint8_t *d_mask, float *d_u, float *d_p1,
                  float *d_p2, float *d_lambda, double *h_stats, int32_t *n_rows, void *stream);
 
-/* Outcome of the last solve's persistent launches: a persistent schedule lets a subdomain wait a
+/* Outcome of the last solve's (or, after dtv_dd_backward, the last backward pass's) persistent
+   launches: a persistent schedule lets a subdomain wait a
    bounded number of polls (spin_limit) for each neighbour's interface copies; a wait that gives up
    sets an error word in the workspace that solve used, and the launch ends early.  The solve itself
    does not wait for its launches, so it cannot see that word; this call copies it to the host

@@ -214,6 +214,8 @@ struct dtv_dd_plan {
     size_t off_ckpt = 0, off_seg = 0, off_xrec = 0, off_zrec = 0, off_lam1 = 0, off_xb = 0, off_hb = 0, off_pb = 0,
            off_lb = 0, off_galpha = 0, off_frec = 0, off_gsub = 0;
     bool fbwd = false;        // reverse mode with the fused kernels (every subdomain 128 x 128)
+    bool pbwd = false;        // and the persistent reverse (one cooperative launch per range of outer steps)
+    size_t off_bxch = 0;      // its exchange words
     bool seg_rec = false;     // fused reverse: the step records of a whole checkpoint segment are kept
     size_t rec_step = 0;      // bytes of one outer step's records
     bool adaptive = false;    // inner_tol > 0: the fused kernel stops each local solve by the relative-change rule
@@ -275,6 +277,7 @@ struct dtv_dd_plan {
     // step records of the fused forward: outer step q of the segment (q = 0 without seg_rec)
     float4 *frec(int q = 0) const { return (float4 *)(ws + off_frec + (size_t)q * rec_step); }
     double *gsub() const { return (double *)(ws + off_gsub); }     // per-subdomain alpha partial sums
+    unsigned long long *bxch() const { return (unsigned long long *)(ws + off_bxch); }
     double *dout() const { return (double *)(ws + off_dout); }
     unsigned long long *xch() const { return (unsigned long long *)(ws + off_xch); }
     float *lamw() const { return (float *)(ws + off_lamw); }  // second lambda state (fused schedule)
@@ -446,6 +449,9 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
     if (p.keep_records && !p.save_for_backward) return fail(DTV_EINVAL, "keep_records needs save_for_backward");
     if (p.keep_records && p.schedule != DTV_SCHED_AUTO && p.schedule != DTV_SCHED_FUSED)
         return fail(DTV_EINVAL, "keep_records runs the fused schedule (auto or fused)");
+    if (p.reverse_schedule != DTV_SCHED_AUTO && p.reverse_schedule != DTV_SCHED_FUSED &&
+        p.reverse_schedule != DTV_SCHED_PERSIST)
+        return fail(DTV_EINVAL, "reverse_schedule must be auto, fused or persistent");
 
     dtv_dd_plan *pl = new dtv_dd_plan();
     pl->uid = ++g_plan_ids;
@@ -722,6 +728,19 @@ extern "C" int dtv_dd_setup(const dtv_image_desc *imgs, int32_t n_images, const 
             pl->off_xrec = take(sizeof(float) * E * (size_t)p.n_inner);
             pl->off_zrec = take(sizeof(float) * E * (size_t)p.n_inner);
         }
+        // the persistent reverse takes the ranges whose records are all kept (a checkpoint segment's,
+        // or the whole solve's with keep_records) when every subdomain is resident at once
+        if (pl->fbwd && (p.keep_records || pl->seg_rec) && p.reverse_schedule != DTV_SCHED_FUSED) {
+            int dev = 0;
+            pl->pbwd = hipGetDevice(&dev) == hipSuccess && persist_supported(dev) &&
+                       (int)nsub <= persist_bwd_capacity(dev, p.n_inner);
+        }
+        if (p.reverse_schedule == DTV_SCHED_PERSIST && !pl->pbwd) {
+            delete pl;
+            return fail(DTV_EINVAL, "reverse_schedule persistent needs the on-chip reverse with the records of a "
+                                    "range kept (every subdomain 128 x 128, all resident at once)");
+        }
+        pl->off_bxch = take(pl->pbwd ? sizeof(unsigned long long) * 2 * (size_t)pl->tot_lam : 0);
         pl->off_lam1 = take(sizeof(float) * (size_t)pl->tot_lam);
         pl->off_xb = take(sizeof(float) * E * 3);
         pl->off_hb = take(sizeof(float) * E);
@@ -1722,8 +1741,47 @@ static int backward_fused(dtv_dd_plan *pl, const float *d_f, float *d_grad_f, fl
                 "interface reverse");
         return DTV_OK;
     };
+    // the persistent reverse of outer steps [0, m) of a range: the state before step q at
+    // st0 + q state_floats, its records at rec0 + q rec_step
+    const unsigned spin_limit = P.spin_limit > 0 ? (unsigned)P.spin_limit : kSpinLimitDefault;
+    if (pl->pbwd) {
+        HIP_TRY(launch_fill_zero(pl->sync_words(), 2 * sizeof(unsigned), s), "clear error flag");
+        pl->ran_persist = true;
+        pl->run_ws = pl->ws;
+    }
+    auto reverse_range = [&](const float *st0, const float4 *rec0, int m) -> int {
+        if (m <= 0) return DTV_OK;
+        PersistBwdArgs pa{};
+        pa.b = ba;
+        pa.st = st0;
+        pa.st_stride = (long long)pl->state_floats;
+        pa.p2_off = pl->tot_p1;
+        pa.lam_off = (long long)E;
+        pa.rec = rec0;
+        pa.rec_outer = (long long)(pl->rec_step / sizeof(float4));
+        pa.n_steps = m;
+        pa.sigma = (float)P.sigma;
+        pa.lamb = pl->lb();
+        pa.xch = pl->bxch();
+        pa.xch_stride = pl->tot_lam;
+        pa.err = (int *)pl->sync_words();
+        pa.spin_limit = spin_limit;
+        HIP_TRY(launch_fill_zero(pl->bxch(), sizeof(unsigned long long) * 2 * (size_t)pl->tot_lam, s),
+                "clear exchange");
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        int rc = events(0, &e0, &e1);
+        if (rc != DTV_OK) return rc;
+        if (e0) HIP_TRY(hipEventRecord(e0, s), "event");
+        HIP_TRY(launch_persist_bwd(pa, nsub, s), "persistent reverse");
+        if (e1) HIP_TRY(hipEventRecord(e1, s), "event");
+        return DTV_OK;
+    };
     // keep_records: the forward solve kept every state and every outer step's records
-    for (int n = P.keep_records ? N - 1 : -1; n >= 0; --n) {
+    if (P.keep_records && pl->pbwd) {
+        int rc = reverse_range(pl->ckpt(0), pl->frec(0), N);
+        if (rc != DTV_OK) return rc;
+    }
+    for (int n = P.keep_records && !pl->pbwd ? N - 1 : -1; n >= 0; --n) {
         int rc = reverse(pl->ckpt(n), pl->ckpt(n + 1) + E, pl->frec(n));
         if (rc != DTV_OK) return rc;
     }
@@ -1736,6 +1794,11 @@ static int backward_fused(dtv_dd_plan *pl, const float *d_f, float *d_grad_f, fl
             for (int q = 0; q < m; ++q) {
                 int rc = forward(pl->seg(q), pl->seg(q + 1), pl->seg(q + 1) + E, pl->frec(q));
                 if (rc != DTV_OK) return rc;
+            }
+            if (pl->pbwd) {
+                int rc = reverse_range(pl->seg(0), pl->frec(0), m);
+                if (rc != DTV_OK) return rc;
+                continue;
             }
             for (int q = m - 1; q >= 0; --q) {
                 int rc = reverse(pl->seg(q), pl->seg(q + 1) + E, pl->frec(q));
@@ -1958,7 +2021,7 @@ extern "C" int dtv_dd_backward_kernel_time(const dtv_dd_plan *pl, int32_t which,
     if (which != 0 && which != 1) return fail(DTV_EINVAL, "which must be 0 (reverse steps) or 1 (recording forward)");
     if (avg_ms) *avg_ms = pl->tb_ms[which];
     if (launches) *launches = pl->tb_count[which];
-    if (name) *name = which == 0 ? "k_fused_bwd" : "k_fused_fista (recording)";
+    if (name) *name = which == 0 ? (pl->pbwd ? "k_persist_bwd" : "k_fused_bwd") : "k_fused_fista (recording)";
     if (bytes_per_launch) {
         // Algorithmic HBM bytes of one launch (E = edge dofs of the torn p~, N = pixels, K = n_inner,
         // 4 bytes each; a step record is kRecGroups 16-byte groups per thread of 16 pixels, R = 9
@@ -1966,6 +2029,7 @@ extern "C" int dtv_dd_backward_kernel_time(const dtv_dd_plan *pl, int32_t which,
         //   reverse steps: read the K records, pbar^(n+1), p~^n, f and fbar; write pbar^n and fbar
         //                                                                           4 (3E + 3N) + R K N
         //   recording forward: read p~^n and f; write p~^(n+1) and the K records     4 (2E + N) + R K N
+        //   (the lambda state and the interface copies are a negligible part)
         double E = 0.0, N = 0.0;
         for (const ImgHost &h : pl->imgs) {
             E += (double)(h.H + h.ny) * h.W + (double)h.H * (h.W + h.nx);
@@ -1974,6 +2038,12 @@ extern "C" int dtv_dd_backward_kernel_time(const dtv_dd_plan *pl, int32_t which,
         const double R = (double)kRecGroups * 16.0 / 16.0;
         const double rec = R * (double)pl->prm.n_inner * N;
         *bytes_per_launch = which == 0 ? 4.0 * (3 * E + 3 * N) + rec : 4.0 * (2 * E + N) + rec;
+        if (which == 0 && pl->pbwd && pl->tb_count[0] > 0) {
+            // the persistent reverse, per launch: read pbar, per outer step the K records, p~^n, f and
+            // fbar, and write fbar, then write pbar                  4 (2E) + steps (4 (E + 3N) + R K N)
+            const double steps = (double)pl->saved_outer / (double)pl->tb_count[0];
+            *bytes_per_launch = 8.0 * E + steps * (4.0 * (E + 3 * N) + rec);
+        }
     }
     return DTV_OK;
 }

@@ -298,9 +298,10 @@ __global__ __launch_bounds__(256) void k_bwd_interface(const ImgDev *imgs, const
         pb = pb2;
     }
     float *L = lamb + im.lam;
-    const float lt = fmaf(-tau, hb[is] - hb[it], L[e]);
-    pb[is] += L[im.nlam + e] + 2.0f * sigma * lt;
-    pb[it] += L[2 * im.nlam + e] - 2.0f * sigma * lt;
+    float lt = L[e], ds, dt;
+    iface_bwd(hb[is], hb[it], tau, sigma, lt, L[im.nlam + e], L[2 * im.nlam + e], ds, dt);
+    pb[is] += ds;
+    pb[it] += dt;
     L[im.nlam + e] = -sigma * lt;
     L[2 * im.nlam + e] = sigma * lt;
     L[e] = lt;

@@ -56,7 +56,8 @@ class Params(ctypes.Structure):
                 ("schedule", ctypes.c_int32), ("time_kernels", ctypes.c_int32), ("rows", ctypes.c_int32),
                 ("no_graphs", ctypes.c_int32), ("cv_c1", ctypes.c_double), ("cv_c2", ctypes.c_double),
                 ("full_problem", ctypes.c_int32), ("spin_limit", ctypes.c_int32), ("inner_tol", ctypes.c_double),
-                ("steps_per_launch", ctypes.c_int32), ("keep_records", ctypes.c_int32)]
+                ("steps_per_launch", ctypes.c_int32), ("keep_records", ctypes.c_int32),
+                ("reverse_schedule", ctypes.c_int32)]
 
 
 class Layout(ctypes.Structure):
@@ -149,7 +150,8 @@ class Plan:
                  sigma0=1.0 / 80.0, gamma=None, n_outer=100, n_inner=10, diag_every=0, gap_tol=0.0,
                  warm_start=False, save_for_backward=False, ckpt_every=20, schedule="auto",
                  time_kernels=False, rows=0, graphs=True, c1=0.6, c2=0.1, full_problem=False, inner_tol=0.0,
-                 spin_limit=0, steps_per_launch=0, keep_records=False, device=None, bind=True):
+                 spin_limit=0, steps_per_launch=0, keep_records=False, reverse_schedule="auto", device=None,
+                 bind=True):
         import torch
 
         L = lib()
@@ -173,7 +175,8 @@ class Plan:
                              int(diag_every), float(gap_tol), int(warm_start), int(save_for_backward),
                              int(ckpt_every), SCHEDULE[schedule], int(time_kernels), int(rows),
                              int(not graphs), float(c1), float(c2), int(full_problem), int(spin_limit),
-                             float(inner_tol), int(steps_per_launch), int(keep_records))
+                             float(inner_tol), int(steps_per_launch), int(keep_records),
+                             SCHEDULE[reverse_schedule])
         h = ctypes.c_void_p()
         _check(L.dtv_dd_setup(descs, len(self.images), ctypes.byref(self.params), ctypes.byref(h)))
         self.h = h
@@ -291,9 +294,10 @@ class Plan:
                                         self._stream(stream)))
         return out.reshape(self.n_images, 4)
 
-    def backward(self, f, grad_u, stream=None):
+    def backward(self, f, grad_u, stream=None, check=True):
         """Reverse mode of the last solve (which must have run with
-        save_for_backward): returns (dl/df, dl/dalpha per image)."""
+        save_for_backward): returns (dl/df, dl/dalpha per image).  check: read
+        the persistent reverse's wait status afterwards (waits for the stream)."""
         import torch
 
         assert f.dtype == torch.float32 and grad_u.dtype == torch.float32
@@ -301,6 +305,8 @@ class Plan:
         grad_alpha = torch.zeros(self.n_images, dtype=torch.float32, device=self.device)
         _check(lib().dtv_dd_backward(self.h, _ptr(f), _ptr(grad_u.contiguous()), _ptr(grad_f), _ptr(grad_alpha),
                                      self._stream(stream)))
+        if check:
+            self.status(stream)
         return grad_f, grad_alpha
 
     def inner_counts(self, stream=None) -> np.ndarray:

@@ -174,7 +174,9 @@ def test_keep_records_against_oracle_and_timed():
     torch.cuda.synchronize()
     kt = plan.kernel_time()
     assert kt["name"] == "k_fused_fista (recording)" and kt["launches"] == n_outer
-    assert plan.backward_kernel_time(0)["launches"] == n_outer
+    # the whole reverse in one persistent launch, no recording launch
+    kb = plan.backward_kernel_time(0)
+    assert kb["name"] == "k_persist_bwd" and kb["launches"] == 1
     assert plan.backward_kernel_time(1)["launches"] == 0
     # the diagnostics follow the same states as a plain solve's
     ref = dtvdd.Plan([dtvdd.Image(H, W, rc, cc, alpha)], n_outer=n_outer, n_inner=K, schedule="fused", diag_every=2)
@@ -189,3 +191,31 @@ def test_keep_records_against_oracle_and_timed():
     _say(f"  dl/df rel L2 {e_f:.2e}   dl/dalpha rel {e_a:.2e}")
     assert e_f <= 1e-4
     assert e_a <= 1e-4
+
+
+@pytest.mark.parametrize("H,W,alphas,n_outer,K,keep,C", [
+    (256, 384, [8.0], 23, 5, False, 5),
+    (256, 384, [8.0], 23, 5, True, 20),
+    (128, 128, [3.0], 7, 1, True, 20),
+    (384, 256, [4.0, 12.0], 6, 10, False, 4),
+    (256, 256, [6.0, 7.0, 8.0], 9, 2, True, 20),
+    (384, 384, [5.0], 11, 3, False, 20),
+])
+def test_persistent_reverse_equals_per_step_bitwise(H, W, alphas, n_outer, K, keep, C):
+    """The persistent reverse (one cooperative launch per checkpoint segment, or
+    per solve with keep_records; pbar on chip between outer steps, the interface
+    transpose point to point) against one reverse launch and one interface
+    launch per outer step: both gradients bitwise equal, single tiles, interior
+    tiles with four interfaces and batches included."""
+    rc, cc = np.arange(0, H + 1, 128), np.arange(0, W + 1, 128)
+    probs = [_problem(H, W, 300 + b + K + n_outer) for b in range(len(alphas))]
+    fs, ubars = [p[0] for p in probs], [p[1] for p in probs]
+    _say(f"[persistent reverse] {len(alphas)} x {H}x{W} {n_outer}x{K} keep_records {keep} ckpt {C}")
+    gf0, ga0, p0, _ = gpu_grad(fs, alphas, rc, cc, ubars, n_outer, K, C, keep_records=keep,
+                               reverse_schedule="fused", time_kernels=True)
+    gf1, ga1, p1, _ = gpu_grad(fs, alphas, rc, cc, ubars, n_outer, K, C, keep_records=keep,
+                               reverse_schedule="persistent", time_kernels=True)
+    k0, k1 = p0.backward_kernel_time(0), p1.backward_kernel_time(0)
+    assert k0["name"] == "k_fused_bwd" and k0["launches"] == n_outer
+    assert k1["name"] == "k_persist_bwd" and k1["launches"] == (1 if keep else -(-n_outer // C))
+    assert np.array_equal(gf0, gf1) and np.array_equal(ga0, ga1)

@@ -59,7 +59,7 @@ def test_batched_64_images_full_size():
         _say(f"  errors {errs}")
 
 
-def _full_diff(n_outer):
+def _full_diff(n_outer, **kw):
     from paper_1901_00682_amd import dtvdd
     cases = synth.config5(n_outer=n_outer)
     B = len(cases)
@@ -67,7 +67,7 @@ def _full_diff(n_outer):
     K = cases[0].n_inner
     imgs = [dtvdd.Image(H, W, c.row_cuts, c.col_cuts, c.alpha) for c in cases]
     ubar = np.random.default_rng(55).standard_normal((B, H, W)).astype(np.float32)
-    plan = dtvdd.Plan(imgs, n_outer=n_outer, n_inner=K, save_for_backward=True, ckpt_every=20)
+    plan = dtvdd.Plan(imgs, n_outer=n_outer, n_inner=K, save_for_backward=True, ckpt_every=20, **kw)
     f = torch.from_numpy(np.stack([c.f for c in cases]).ravel()).cuda()
     st, _ = plan.solve(f, want_stats=False)
     gf, ga = plan.backward(f, torch.from_numpy(ubar.ravel()).cuda())
@@ -129,3 +129,23 @@ def test_differentiation_full_size_within_conditioning():
     assert s_f > 1e-3  # the conditioning this test relies on is present
     assert e_f <= 3 * s_f
     assert e_a <= 3 * s_a
+
+
+def test_differentiation_full_size_reverse_schedules_bitwise():
+    """The differentiation workload as benchmarked (16 x 512^2, 200 x 5): the
+    checkpointed backward with one reverse launch per outer step, with one
+    persistent launch per checkpoint segment, and keep_records with one
+    persistent launch for the whole solve give bitwise equal gradients."""
+    import gc
+    res = []
+    for kw in (dict(reverse_schedule="fused"), dict(reverse_schedule="persistent"),
+               dict(keep_records=True, reverse_schedule="persistent")):
+        _say(f"[full size, 200 outer] {kw}")
+        _, _, gf, ga, plan, _ = _full_diff(200, **kw)
+        res.append((gf, ga))
+        plan.close()
+        del plan
+        gc.collect()
+        torch.cuda.empty_cache()
+    for gf, ga in res[1:]:
+        assert np.array_equal(gf, res[0][0]) and np.array_equal(ga, res[0][1])
