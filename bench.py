@@ -44,7 +44,8 @@ KERNEL_SOURCES = {
     "k_fused_cp2": ["fused_cp2.hip", "cp2_tile.h", "cp2_ops.h", "fused_common.h", "fista_ops.h", "dtvdd_internal.h"],
     "k_persist_cp2": ["persist_cp2.hip", "cp2_tile.h", "cp2_ops.h", "exchange.h", "fused_common.h", "fista_ops.h",
                       "dtvdd_internal.h"],
-    "k_fused_bwd": ["fused_bwd.hip", "fused_common.h", "fista_ops.h", "dtvdd_internal.h"],
+    "k_fused_bwd": ["fused_bwd.hip", "bwd.h", "exchange.h", "fused_common.h", "fista_ops.h", "dtvdd_internal.h"],
+    "k_persist_bwd": ["fused_bwd.hip", "bwd.h", "exchange.h", "fused_common.h", "fista_ops.h", "dtvdd_internal.h"],
     "k_fused_fista_rec": ["fused.hip", "fused_common.h", "fista_ops.h", "dtvdd_internal.h"],
 }
 
@@ -288,9 +289,14 @@ def backward_measure(steps: int, warmup: int, schedule: str = "auto") -> dict:
         rk = {}
         for key, kt in (("recording_forward", rplan.kernel_time()), ("reverse", rplan.backward_kernel_time(0))):
             gbs = kt["bytes_per_launch"] / (kt["avg_ms"] * 1e-3) / 1e9
-            rk[key] = {"kernel": kt["name"], "achieved": gbs, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+            rk[key] = {"bound": "hbm", "kernel": kt["name"], "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": gbs / HBM_PEAK_GBS,
+                       "traffic": measured_traffic(kt["name"].split()[0] + ("_rec" if key == "recording_forward"
+                                                                            else ""), "diff_kr"),
                        "avg_launch_us": kt["avg_ms"] * 1e3, "launches": kt["launches"],
                        "bytes_per_launch": kt["bytes_per_launch"]}
+            if key == "reverse":  # one launch reverses every outer step of the solve
+                rk[key]["per_outer_step_us"] = kt["avg_ms"] * 1e3 * kt["launches"] / n_outer
         rplan.close()
         del rplan, sr
         fr, br = float(np.median(trf)) * 1e3, float(np.median(trb)) * 1e3
@@ -310,9 +316,26 @@ def backward_measure(steps: int, warmup: int, schedule: str = "auto") -> dict:
     return out
 
 
+def copy_calibration(dev):
+    """A plain 256 MiB device copy, four times: what the HBM byte counters read
+    for it scales them (run with --calibrate-copy under the counter passes)."""
+    import torch
+
+    nbytes = 256 << 20
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).uniform_()
+    dst = torch.empty_like(src)
+    for _ in range(4):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+
+
 def run_diff(args):
     """Forward and reverse mode of 16 unrolled 512 x 512 ROF solves."""
+    import torch
+
     b = backward_measure(args.steps, args.warmup, args.schedule)
+    if args.calibrate_copy:
+        copy_calibration(torch.device("cuda:0"))
     return {
         "metric": METRIC, "value": b["forward_value"], "unit": "pixel-inner-iterations/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -551,13 +574,7 @@ def main():
             # profiles/k_cp2_multi_tvl1.md and profiles/k_fista_multi_rof2048.md: 86 % and 67 % busy)
             roofline["limiter"] = "vector ALU issue and latency (HBM figure: algorithmic bytes / launch time)"
     if args.calibrate_copy:
-        # a plain device copy of known size, for scaling the HBM byte counters
-        nbytes = 256 << 20
-        src = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).uniform_()
-        dst = torch.empty_like(src)
-        for _ in range(4):
-            dst.copy_(src)
-        torch.cuda.synchronize()
+        copy_calibration(dev)
     out = {
         "metric": METRIC,
         "value": px_it,

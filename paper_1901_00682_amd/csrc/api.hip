@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "dtvdd.h"
+#include "bwd.h"
 #include "cp2_multi.h"
 #include "fista_multi.h"
 #include "dtvdd_internal.h"

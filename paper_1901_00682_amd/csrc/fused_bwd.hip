@@ -19,6 +19,7 @@
 // l columns 2 l and 2 l + 1, the two adjoint slots in VGPRs, the right
 // boundary column in LDS, one exchange row per strip for zbar and one for
 // div zbar; each step has two workgroup barriers.
+#include "bwd.h"
 #include "exchange.h"
 #include "fused_common.h"
 

@@ -9,6 +9,7 @@
 // zbar = xbar * 1{|z| < 1}.  Gradients accumulate in FP32 edge and pixel
 // arrays; the alpha derivative accumulates in FP64 per work item and is
 // reduced in a fixed order.
+#include "bwd.h"
 #include "dtvdd_internal.h"
 #include "fista_ops.h"
 
