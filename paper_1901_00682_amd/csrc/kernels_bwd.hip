@@ -318,42 +318,62 @@ hipError_t launch_bwd_interface(const ImgDev *imgs, int nimg, int max_nlam, cons
     return hipGetLastError();
 }
 
-// alphabar per image: the per-tile partial sums added in tile order
-__global__ void k_alpha_reduce(const StreamTile *tiles, int ntiles, const double *galpha, float *out)
+// alphabar per image from the per-tile (and per-subdomain) partial sums: one workgroup per
+// image, each thread adds every 256th partial in order, then a fixed tree over the threads -- the
+// same order in every run
+constexpr int kReduceThreads = 256;
+
+__device__ __forceinline__ float tree_sum(double *part, double acc)
 {
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kReduceThreads / 2; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    return (float)part[0];
+}
+
+__global__ __launch_bounds__(kReduceThreads) void k_alpha_reduce(const StreamTile *tiles, int ntiles,
+                                                                 const double *galpha, float *out)
+{
+    __shared__ double part[kReduceThreads];
     const int img = blockIdx.x;
-    if (threadIdx.x != 0) return;
     double acc = 0.0;
-    for (int t = 0; t < ntiles; ++t)
+    for (int t = threadIdx.x; t < ntiles; t += kReduceThreads)
         if (tiles[t].img == img) acc += galpha[t];
-    out[img] = (float)acc;
+    const float v = tree_sum(part, acc);
+    if (threadIdx.x == 0) out[img] = v;
 }
 
 hipError_t launch_alpha_reduce(const StreamTile *tiles, int ntiles, int nimg, const double *galpha, float *out,
                                hipStream_t s)
 {
-    hipLaunchKernelGGL(k_alpha_reduce, dim3(nimg), dim3(64), 0, s, tiles, ntiles, galpha, out);
+    hipLaunchKernelGGL(k_alpha_reduce, dim3(nimg), dim3(kReduceThreads), 0, s, tiles, ntiles, galpha, out);
     return hipGetLastError();
 }
 
 // the same with the per-subdomain partial sums of the fused reverse steps added
-__global__ void k_alpha_reduce2(const StreamTile *tiles, int ntiles, const double *galpha, const SubTile *subs,
-                                int nsub, const double *gsub, float *out)
+__global__ __launch_bounds__(kReduceThreads) void k_alpha_reduce2(const StreamTile *tiles, int ntiles,
+                                                                  const double *galpha, const SubTile *subs,
+                                                                  int nsub, const double *gsub, float *out)
 {
+    __shared__ double part[kReduceThreads];
     const int img = blockIdx.x;
-    if (threadIdx.x != 0) return;
     double acc = 0.0;
-    for (int t = 0; t < ntiles; ++t)
+    for (int t = threadIdx.x; t < ntiles; t += kReduceThreads)
         if (tiles[t].img == img) acc += galpha[t];
-    for (int t = 0; t < nsub; ++t)
+    for (int t = threadIdx.x; t < nsub; t += kReduceThreads)
         if (subs[t].img == img) acc += gsub[t];
-    out[img] = (float)acc;
+    const float v = tree_sum(part, acc);
+    if (threadIdx.x == 0) out[img] = v;
 }
 
 hipError_t launch_alpha_reduce2(const StreamTile *tiles, int ntiles, const double *galpha, const SubTile *subs,
                                 int nsub, const double *gsub, int nimg, float *out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_alpha_reduce2, dim3(nimg), dim3(64), 0, s, tiles, ntiles, galpha, subs, nsub, gsub, out);
+    hipLaunchKernelGGL(k_alpha_reduce2, dim3(nimg), dim3(kReduceThreads), 0, s, tiles, ntiles, galpha, subs, nsub,
+                       gsub, out);
     return hipGetLastError();
 }
 
