@@ -219,3 +219,37 @@ def test_persistent_reverse_equals_per_step_bitwise(H, W, alphas, n_outer, K, ke
     assert k0["name"] == "k_fused_bwd" and k0["launches"] == n_outer
     assert k1["name"] == "k_persist_bwd" and k1["launches"] == (1 if keep else -(-n_outer // C))
     assert np.array_equal(gf0, gf1) and np.array_equal(ga0, ga1)
+
+
+def test_persistent_reverse_timeout_is_reported():
+    """The persistent reverse's waits for a neighbour's interface word are
+    bounded; a poll limit of 1, forced from the host, makes a wait give up
+    unless the word is already there.  The backward then either completes and
+    equals the normal one, or dtv_dd_status reports the timeout (every tile
+    leaves its loop, so the launch drains); a normal backward afterwards is
+    unaffected.  keep_records: the forward makes no persistent launch."""
+    from paper_1901_00682_amd import dtvdd
+    H, W = 384, 384
+    rc, cc = np.arange(0, H + 1, 128), np.arange(0, W + 1, 128)
+    f, ubar = _problem(H, W, 61)
+    ft = torch.from_numpy(f.ravel()).cuda()
+    gu = torch.from_numpy(ubar.astype(np.float32).ravel()).cuda()
+    kw = dict(n_outer=12, n_inner=5, save_for_backward=True, keep_records=True, reverse_schedule="persistent")
+
+    def grads(**extra):
+        plan = dtvdd.Plan([dtvdd.Image(H, W, rc, cc, 8.0)], **kw, **extra)
+        plan.solve(ft, want_stats=False)
+        gf, ga = plan.backward(ft, gu)
+        torch.cuda.synchronize()
+        return gf.clone(), ga.clone()
+
+    ref = grads()
+    try:
+        got = grads(spin_limit=1)
+        assert torch.equal(ref[0], got[0]) and torch.equal(ref[1], got[1])
+        _say("  spin limit 1: every word was there in time")
+    except dtvdd.DtvError as e:
+        assert e.code == dtvdd.DTV_EHIP and "timed out" in str(e)
+        _say(f"  spin limit 1: {e}")
+    again = grads()
+    assert torch.equal(ref[0], again[0]) and torch.equal(ref[1], again[1])
