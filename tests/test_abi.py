@@ -108,6 +108,9 @@ def test_valid_setup_and_layout():
     (dict(keep_records=1, save_for_backward=1), "on-chip reverse"),
     (dict(keep_records=1, save_for_backward=1, H=256, W=256, rc=(0, 128, 256), cc=(0, 128, 256), n_inner=9),
      "on-chip reverse"),
+    (dict(reverse_schedule=1), "reverse_schedule must"),
+    (dict(reverse_schedule=9), "reverse_schedule must"),
+    (dict(save_for_backward=1, reverse_schedule=3), "reverse_schedule persistent needs"),
 ])
 def test_validation_errors(kw, msg):
     code, h = _setup(**kw)
