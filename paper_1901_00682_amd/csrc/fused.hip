@@ -387,6 +387,12 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, int t, FusedLds &
     };
     float *q1_tile = o1 + row1 * P1 + tl.ca;
     float *q2_tile = o2 + (long long)tl.ra * P2 + col2;
+    // the recording kernel: the row bases are uniform and the thread's column enters as one 32-bit
+    // byte offset, formed here (a column offset kept from the prologue stays live through the
+    // recorded steps, in scratch); the other kernels address the row plus the column
+    unsigned jo4 = 0;
+    if constexpr (REC) jo4 = (unsigned)opaque(ja) * 4u;
+    auto at = [jo4, ja](float *row) { return REC ? (float *)((char *)row + jo4) : row + ja; };
 #pragma unroll
     for (int r = 0; r < kR; ++r) {
         const int il = il0 + r;
@@ -394,28 +400,28 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, int t, FusedLds &
             float *q1 = q1_tile + (long long)il * P1;
             float *q2 = q2_tile + (long long)il * P2;
             if (c.actb) {
-                st2(q1 + ja, A.e1a[r], A.e1b[r]);
-                st2(q2 + ja, A.e2a[r], A.e2b[r]);
+                st2(at(q1), A.e1a[r], A.e1b[r]);
+                st2(at(q2), A.e2a[r], A.e2b[r]);
             } else if (c.acta) {
-                q1[ja] = A.e1a[r];
-                if (l2b) st2(q2 + ja, A.e2a[r], A.e2b[r]);
-                else q2[ja] = A.e2a[r];
+                *at(q1) = A.e1a[r];
+                if (l2b) st2(at(q2), A.e2a[r], A.e2b[r]);
+                else *at(q2) = A.e2a[r];
             } else if (l2a) {
-                q2[ja] = A.e2a[r];
+                *at(q2) = A.e2a[r];
             }
             // the right boundary edge: a framed tile narrower than 128 holds it in column w with
             // masks, and has it on the image boundary without
             if ((c.lastcol_a || c.lastcol_b) && (!FR || w == kFusedMax)) q2[w] = S.rx[rx_slot][il];
         } else if (FR == 2 && il == h) {  // the bottom edges of a framed tile lower than 128
             float *q1 = q1_tile + (long long)il * P1;
-            if (c.actb) st2(q1 + ja, A.e1a[r], A.e1b[r]);
-            else if (c.acta) q1[ja] = A.e1a[r];
+            if (c.actb) st2(at(q1), A.e1a[r], A.e1b[r]);
+            else if (c.acta) *at(q1) = A.e1a[r];
         }
     }
     if (c.has_bottom && (!FR || h == kFusedMax)) {
         float *qb = q1_tile + (long long)h * P1;
-        if (c.actb) st2(qb + ja, A.ba, A.bb);
-        else if (c.acta) qb[ja] = A.ba;
+        if (c.actb) st2(at(qb), A.ba, A.bb);
+        else if (c.acta) *at(qb) = A.ba;
     }
 }
 
